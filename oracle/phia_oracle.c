@@ -1,0 +1,387 @@
+/*
+ * PHIA CPU oracle -- TEST INFRASTRUCTURE ONLY (see phia_oracle.h).
+ *
+ * Build: gcc -O2 -std=c11 -ffp-contract=off -fopenmp -shared -fPIC.
+ * No fast-math: every float operation below is one IEEE binary32 operation
+ * with round-to-nearest-even, and every fused multiply-add is an explicit
+ * fmaf, so the results are fixed by the specification and not by the compiler.
+ *
+ * Paper passages followed (Wang et al., arXiv 2407.10205):
+ *   Eq. 2          Ising energy over i<j pairs plus local fields.
+ *   Eq. 6          quasi-gradient I_i = sum_j J_ij sgn(x_j) + h_i.
+ *   Eq. 5, Eq. 8   dv/dt = beta * d sgn(x)/dx * I - x with the tanh surrogate
+ *                  d/dx tanh(gamma x) = gamma (1 - tanh^2(gamma x)).
+ *   App. A, A3     x drawn from g(x), the standard normal density.
+ *   App. A, A7     x <- x + eps v, then v <- v - eps grad_x H at the new x.
+ *   Sec. 2.1       spins read out as s = sgn(x).
+ *   App. B, Tab. 3 state 5: keep the best configuration found so far.
+ */
+#include "phia_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x64-10: two 64x64->128 multiplies per round, Weyl key bumps.  */
+/* ------------------------------------------------------------------ */
+static const uint64_t PHILOX_M0 = 0xD2E7470EE14C6C93ULL;
+static const uint64_t PHILOX_M1 = 0xCA5A826395121157ULL;
+static const uint64_t PHILOX_W0 = 0x9E3779B97F4A7C15ULL;
+static const uint64_t PHILOX_W1 = 0xBB67AE8584CAA73BULL;
+
+void oracle_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4])
+{
+    uint64_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint64_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        unsigned __int128 p0 = (unsigned __int128)PHILOX_M0 * c0;
+        unsigned __int128 p1 = (unsigned __int128)PHILOX_M1 * c2;
+        uint64_t hi0 = (uint64_t)(p0 >> 64), lo0 = (uint64_t)p0;
+        uint64_t hi1 = (uint64_t)(p1 >> 64), lo1 = (uint64_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* ------------------------------------------------------------------ */
+/* Elementary functions, FP32, written from their power series.        */
+/* ------------------------------------------------------------------ */
+static float f_from_bits(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
+static uint32_t bits_from_f(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
+
+/* ln 2 split so that LN2_HI is the float nearest ln 2 and LN2_LO the float
+ * nearest the remainder ln 2 - LN2_HI. */
+#define O_LN2_HI  0.693147182464599609375f
+#define O_LN2_LO  (-1.9046542999577e-09f)
+#define O_LOG2E   1.44269504088896340736f
+#define O_SQRT2   1.41421356237309504880f
+#define O_TWO_PI  6.28318530717958647692f
+
+/* e^y, y <= 0.  Reduction y = k ln2 + r, |r| <= ln2/2 (Cody-Waite with the
+ * split constant), then the degree-7 Taylor polynomial of e^r in Horner form,
+ * then an exact scaling by 2^k.  Below -80 the value is taken as 0. */
+float oracle_exp_nonpos(float y)
+{
+    if (!(y >= -80.0f)) return 0.0f;
+    float kf = rintf(y * O_LOG2E);
+    float r = fmaf(-kf, O_LN2_HI, y);
+    r = fmaf(-kf, O_LN2_LO, r);
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    int k = (int)kf;                              /* in [-116, 0] */
+    float scale = f_from_bits((uint32_t)(k + 127) << 23);
+    return p * scale;
+}
+
+/* ln u for a normal u in (0, 1).  u = m 2^e with m folded into
+ * (sqrt(1/2), sqrt(2)], t = (m-1)/(m+1), ln m = 2 atanh t =
+ * 2t (1 + t^2/3 + t^4/5 + t^6/7 + t^8/9), ln u = e ln2 + ln m. */
+float oracle_ln_unit(float u)
+{
+    uint32_t b = bits_from_f(u);
+    int e = (int)((b >> 23) & 0xffu) - 127;
+    float m = f_from_bits((b & 0x007fffffu) | 0x3f800000u);
+    if (m > O_SQRT2) {
+        m = m * 0.5f;
+        e += 1;
+    }
+    float t = (m - 1.0f) / (m + 1.0f);
+    float t2 = t * t;
+    float P = fmaf(t2, 1.0f / 9.0f, 1.0f / 7.0f);
+    P = fmaf(P, t2, 1.0f / 5.0f);
+    P = fmaf(P, t2, 1.0f / 3.0f);
+    float tt = t + t;
+    float lnm = fmaf(tt * t2, P, tt);
+    float ef = (float)e;
+    return fmaf(ef, O_LN2_HI, fmaf(ef, O_LN2_LO, lnm));
+}
+
+/* cos and sin of 2 pi u for u in (0, 1).  k = rint(4u), r = u - k/4 in
+ * [-1/8, 1/8] (exact), theta = 2 pi r in [-pi/4, pi/4]; Taylor series of sin
+ * to theta^9 and cos to theta^10, then a rotation by k quarter turns. */
+void oracle_sincos_2pi(float u, float* c, float* s)
+{
+    float kf = rintf(4.0f * u);
+    float r = fmaf(kf, -0.25f, u);
+    float th = r * O_TWO_PI;
+    float t2 = th * th;
+    float sp = fmaf(t2, 1.0f / 362880.0f, -(1.0f / 5040.0f));
+    sp = fmaf(sp, t2, 1.0f / 120.0f);
+    sp = fmaf(sp, t2, -(1.0f / 6.0f));
+    float sn = fmaf(th * t2, sp, th);
+    float cp = fmaf(t2, -(1.0f / 3628800.0f), 1.0f / 40320.0f);
+    cp = fmaf(cp, t2, -(1.0f / 720.0f));
+    cp = fmaf(cp, t2, 1.0f / 24.0f);
+    cp = fmaf(cp, t2, -0.5f);
+    float cs = fmaf(t2, cp, 1.0f);
+    switch (((int)kf) & 3) {
+    case 0: *c = cs;  *s = sn;  break;
+    case 1: *c = -sn; *s = cs;  break;
+    case 2: *c = -cs; *s = -sn; break;
+    default: *c = sn; *s = -cs; break;
+    }
+}
+
+/* sech^2(u) = 1 - tanh^2(u) = 4t / (1+t)^2 with t = e^{-2|u|}. */
+float oracle_sech2(float u)
+{
+    float a = fabsf(u);
+    float t = oracle_exp_nonpos(-(a + a));
+    float q = 1.0f + t;
+    return (4.0f * t) / (q * q);
+}
+
+float oracle_uniform(uint32_t w)
+{
+    return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
+}
+
+/* Counter-based standard normal draw number i of stream (seed, tag, r, round):
+ * Philox4x64-10 with key (seed, 0) and counter (i/8, round, r, tag); the four
+ * 64-bit outputs give eight 32-bit words (low half first); draw i uses word
+ * pair p = (i mod 8)/2 in a Box-Muller transform, cosine branch for even i. */
+float oracle_gauss(uint64_t seed, uint32_t tag, uint64_t r, uint64_t round, uint64_t i)
+{
+    uint64_t ctr[4] = { i >> 3, round, r, (uint64_t)tag };
+    uint64_t key[2] = { seed, 0 };
+    uint64_t out[4];
+    oracle_philox4x64_10(ctr, key, out);
+    unsigned p = (unsigned)((i & 7u) >> 1);
+    uint32_t wa = (uint32_t)out[p];
+    uint32_t wb = (uint32_t)(out[p] >> 32);
+    float ua = oracle_uniform(wa);
+    float ub = oracle_uniform(wb);
+    float rho = sqrtf(-2.0f * oracle_ln_unit(ua));
+    float c, s;
+    oracle_sincos_2pi(ub, &c, &s);
+    return (i & 1u) ? rho * s : rho * c;
+}
+
+/* ------------------------------------------------------------------ */
+/* Energies and fields                                                 */
+/* ------------------------------------------------------------------ */
+int64_t oracle_energy(int N, const int32_t* J, const int32_t* h, const int8_t* s)
+{
+    int64_t e = 0;
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j)
+            e -= (int64_t)J[(int64_t)i * N + j] * s[i] * s[j];
+    for (int i = 0; i < N; ++i)
+        e -= (int64_t)h[i] * s[i];
+    return e;
+}
+
+void oracle_local_field(int N, const int32_t* J, const int32_t* h, const int8_t* s, int32_t* I)
+{
+    for (int i = 0; i < N; ++i) {
+        int64_t acc = h[i];
+        for (int j = 0; j < N; ++j)
+            acc += (int64_t)J[(int64_t)i * N + j] * s[j];
+        I[i] = (int32_t)acc;
+    }
+}
+
+double oracle_energy_f64(int N, const double* J, const double* h, const int8_t* s)
+{
+    double e = 0.0;
+    for (int i = 0; i < N; ++i)
+        for (int j = i + 1; j < N; ++j)
+            e -= J[(int64_t)i * N + j] * (double)(s[i] * s[j]);
+    for (int i = 0; i < N; ++i)
+        e -= h[i] * (double)s[i];
+    return e;
+}
+
+int64_t oracle_bruteforce(int N, const int32_t* J, const int32_t* h, int8_t* s_best)
+{
+    if (N < 1 || N > 24) return INT64_MAX;
+    int8_t* s = (int8_t*)malloc((size_t)N);
+    int64_t best = INT64_MAX;
+    uint64_t count = 1ull << N;
+    for (uint64_t m = 0; m < count; ++m) {
+        for (int i = 0; i < N; ++i) s[i] = ((m >> i) & 1u) ? -1 : 1;
+        int64_t e = oracle_energy(N, J, h, s);
+        if (e < best) {
+            best = e;
+            if (s_best) memcpy(s_best, s, (size_t)N);
+        }
+    }
+    free(s);
+    return best;
+}
+
+/* ------------------------------------------------------------------ */
+/* Packing onto the fixed-point grid                                   */
+/* ------------------------------------------------------------------ */
+static int on_grid(double v, int f)
+{
+    double t = ldexp(v, f);
+    return t == nearbyint(t);
+}
+
+int oracle_pack(int N, const double* J, const double* h, int frac_bits, int quantize,
+                int32_t* J_int, int32_t* h_int, int* f_out)
+{
+    if (N < 1 || !J || frac_bits > 15) return -1;
+    for (int i = 0; i < N; ++i) {
+        if (J[(int64_t)i * N + i] != 0.0) return -3;
+        for (int j = 0; j < N; ++j) {
+            double a = J[(int64_t)i * N + j];
+            if (!isfinite(a)) return -1;
+            if (a != J[(int64_t)j * N + i]) return -2;
+        }
+    }
+    if (h)
+        for (int i = 0; i < N; ++i)
+            if (!isfinite(h[i])) return -1;
+    int f = frac_bits;
+    if (f < 0) {
+        for (f = 0; f <= 15; ++f) {
+            int ok = 1;
+            for (int64_t t = 0; ok && t < (int64_t)N * N; ++t) ok = on_grid(J[t], f);
+            for (int i = 0; ok && h && i < N; ++i) ok = on_grid(h[i], f);
+            if (ok) break;
+        }
+        if (f > 15) {
+            if (!quantize) return -4;
+            f = 15;
+        }
+    }
+    for (int64_t t = 0; t < (int64_t)N * N; ++t) {
+        double a = ldexp(J[t], f);
+        double q = nearbyint(a);
+        if (!quantize && q != a) return -4;
+        if (fabs(q) > 2147483647.0) return -4;
+        J_int[t] = (int32_t)q;
+    }
+    for (int i = 0; i < N; ++i) {
+        double a = h ? ldexp(h[i], f) : 0.0;
+        double q = nearbyint(a);
+        if (!quantize && q != a) return -4;
+        if (fabs(q) > 2147483647.0) return -4;
+        h_int[i] = (int32_t)q;
+    }
+    if (f_out) *f_out = f;
+    return 0;
+}
+
+void oracle_beta_linear(float b0, float b1, int64_t T, float* out)
+{
+    for (int64_t k = 0; k < T; ++k) {
+        double b = (double)b0;
+        if (T > 1) b = (double)b0 + (((double)b1 - (double)b0) * (double)k) / (double)(T - 1);
+        out[k] = (float)b;
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* The sweep                                                           */
+/* ------------------------------------------------------------------ */
+enum { TAG_X = 0, TAG_V = 1 };
+
+static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
+                       int64_t rr, int64_t k0, int64_t k1, const float* betas,
+                       float eps, float gamma, int64_t L, uint64_t seed, int init,
+                       float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                       int64_t* Etrace, int8_t* s, int32_t* I)
+{
+    if (init) {
+        /* App. A, A3: x ~ g(x), the standard normal. */
+        for (int i = 0; i < N; ++i) x[i] = oracle_gauss(seed, TAG_X, (uint64_t)rr, 0, (uint64_t)i);
+        for (int i = 0; i < N; ++i) v[i] = 0.0f;
+        *bestE = INT64_MAX;
+        *bestStep = -1;
+        memset(bestS, 0, (size_t)N);
+    }
+    for (int64_t k = k0; k < k1; ++k) {
+        /* Momentum drawn afresh at the start of every round of L steps. */
+        if (k % L == 0)
+            for (int i = 0; i < N; ++i)
+                v[i] = oracle_gauss(seed, TAG_V, (uint64_t)rr, (uint64_t)(k / L), (uint64_t)i);
+        /* A7, first line: drift with the current momentum. */
+        for (int i = 0; i < N; ++i) x[i] = fmaf(eps, v[i], x[i]);
+        /* Spin readout s = sgn x, with sgn(+0) = sgn(-0) = +1. */
+        for (int i = 0; i < N; ++i) s[i] = (x[i] >= 0.0f) ? 1 : -1;
+        /* Eq. 6: quasi-gradient. */
+        oracle_local_field(N, J, h, s, I);
+        /* Eq. 2 through the field: sum_i s_i (I_i + h_i) = 2 sum_{i<j} J s s + 2 sum h s. */
+        int64_t two_e = 0;
+        for (int i = 0; i < N; ++i) two_e += (int64_t)s[i] * ((int64_t)I[i] + h[i]);
+        int64_t E = -(two_e / 2);
+        if (Etrace) Etrace[k - k0] = E;
+        /* Table 3, state 5: best-so-far, strict improvement keeps the earliest. */
+        if (E < *bestE) {
+            *bestE = E;
+            *bestStep = k;
+            memcpy(bestS, s, (size_t)N);
+        }
+        /* A7, second line, with Eq. 5 and Eq. 8:
+         * v <- v + eps (beta gamma sech^2(gamma x) sigma I - x). */
+        float c = (betas[k] * gamma) * sigma;
+        for (int i = 0; i < N; ++i) {
+            float d = oracle_sech2(gamma * x[i]);
+            float p = c * d;
+            float g = fmaf(p, (float)I[i], -x[i]);
+            v[i] = fmaf(eps, g, v[i]);
+        }
+    }
+}
+
+int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
+                  int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
+                  float eps, float gamma, int64_t L, uint64_t seed, int init,
+                  float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                  int64_t* Etrace, int threads)
+{
+    if (N < 1 || R < 0 || k0 < 0 || k1 < k0 || L < 1 || frac_bits < 0 || frac_bits > 30) return -1;
+    if (init && k0 != 0) return -1;
+    float sigma = ldexpf(1.0f, -frac_bits);
+    if (threads < 1) threads = 1;
+    int fail = 0;
+#ifdef _OPENMP
+#pragma omp parallel num_threads(threads)
+#endif
+    {
+        int8_t* s = (int8_t*)malloc((size_t)N);
+        int32_t* I = (int32_t*)malloc(sizeof(int32_t) * (size_t)N);
+        if (!s || !I) fail = 1;
+#ifdef _OPENMP
+#pragma omp for schedule(dynamic, 1)
+#endif
+        for (int r = 0; r < R; ++r) {
+            if (!s || !I) continue;
+            anneal_one(N, J, h, sigma, r0 + r, k0, k1, betas, eps, gamma, L, seed, init,
+                       x + (int64_t)r * N, v + (int64_t)r * N, bestE + r,
+                       bestS + (int64_t)r * N, bestStep + r,
+                       Etrace ? Etrace + (int64_t)r * (k1 - k0) : NULL, s, I);
+        }
+        free(s);
+        free(I);
+    }
+    return fail ? -1 : 0;
+}
+
+int oracle_argmin(int R, const int64_t* bestE)
+{
+    int best = -1;
+    for (int r = 0; r < R; ++r)
+        if (best < 0 || bestE[r] < bestE[best]) best = r;
+    return best;
+}

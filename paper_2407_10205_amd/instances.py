@@ -1,0 +1,103 @@
+"""Seeded synthetic Ising instances.
+
+This module only draws inputs (couplings J, local fields h) with the
+coefficient distributions of the problem families the paper benchmarks
+(Table 2); it holds none of the annealer's arithmetic.  Every generator uses
+``numpy.random.Generator(numpy.random.Philox(seed))`` so that the same seed
+gives the same instance on every machine.
+
+Conventions: J is a dense symmetric float64 [N, N] array with a zero
+diagonal, h a float64 [N] array; the Ising energy is
+E(s) = -sum_{i<j} J_ij s_i s_j - sum_i h_i s_i (Eq. 2).
+"""
+import numpy as np
+
+
+def rng(seed):
+    return np.random.Generator(np.random.Philox(int(seed)))
+
+
+def _sym(U):
+    """Mirror the strict upper triangle of U into a symmetric matrix."""
+    T = np.triu(U, 1)
+    return T + T.T
+
+
+def sk_pm1(N, seed):
+    """Sherrington-Kirkpatrick spin glass, J_ij uniform in {-1, +1}, h = 0
+    (the sk_ising family of Table 2)."""
+    g = rng(seed)
+    U = g.integers(0, 2, size=(N, N)).astype(np.float64) * 2.0 - 1.0
+    return _sym(U), np.zeros(N)
+
+
+def er_maxcut(N, p, seed, signed=False):
+    """Max-cut on an Erdos-Renyi graph G(N, p) as an Ising problem.
+
+    Edge weights w_ij = +1 (or uniform +-1 when signed); maximising the cut
+    sum_{i<j} w_ij (1 - s_i s_j)/2 is minimising E with J_ij = -w_ij, h = 0,
+    and cut = (W - E)/2 with W = sum of the weights (maxcut_dense family).
+    """
+    g = rng(seed)
+    A = (g.random((N, N)) < p).astype(np.float64)
+    if signed:
+        A *= g.integers(0, 2, size=(N, N)) * 2.0 - 1.0
+    W = _sym(A)
+    return -W, np.zeros(N)
+
+
+def sk_gauss_fixed(N, seed, frac_bits=5, bits=8):
+    """SK with Gaussian couplings quantised to a signed fixed-point grid.
+
+    J_int = clamp(rint(2^f z), -(2^(bits-1)), 2^(bits-1)-1) with z ~ N(0, 1)
+    and J = J_int 2^-f; h_int uniform on [-2^f, 2^f] so h lies in [-1, 1]
+    on the same grid (the spin_model family with fractional coefficients).
+    """
+    g = rng(seed)
+    sc = float(2 ** frac_bits)
+    lo, hi = -(2 ** (bits - 1)), 2 ** (bits - 1) - 1
+    Z = g.standard_normal((N, N))
+    Ji = np.clip(np.rint(Z * sc), lo, hi)
+    hi_ = g.integers(-int(sc), int(sc) + 1, size=N).astype(np.float64)
+    return _sym(Ji) / sc, hi_ / sc
+
+
+def regular3_pm1(N, seed, with_field=True):
+    """Random 3-regular graph (pairing model with restarts), J = +-1 on its
+    edges, h uniform in {-1, 0, 1} (the maxcut_d3 family with signs).
+    N must be even."""
+    if N % 2:
+        raise ValueError("a 3-regular graph needs an even number of vertices")
+    g = rng(seed)
+    while True:
+        stubs = np.repeat(np.arange(N), 3)
+        g.shuffle(stubs)
+        a, b = stubs[0::2], stubs[1::2]
+        if np.any(a == b):
+            continue
+        lo, hi = np.minimum(a, b), np.maximum(a, b)
+        if len(set(zip(lo.tolist(), hi.tolist()))) != len(lo):
+            continue
+        break
+    J = np.zeros((N, N))
+    sgn = g.integers(0, 2, size=lo.shape[0]) * 2.0 - 1.0
+    J[lo, hi] = sgn
+    J[hi, lo] = sgn
+    h = g.integers(-1, 2, size=N).astype(np.float64) if with_field else np.zeros(N)
+    return J, h
+
+
+def uniform_fixed(N, seed, frac_bits=8, with_field=True):
+    """Couplings and fields uniform on [-1, 1] rounded to the 2^-f grid
+    (the spin_model family of Table 2)."""
+    g = rng(seed)
+    sc = float(2 ** frac_bits)
+    U = np.rint(g.uniform(-1.0, 1.0, size=(N, N)) * sc) / sc
+    h = np.rint(g.uniform(-1.0, 1.0, size=N) * sc) / sc if with_field else np.zeros(N)
+    return _sym(U), h
+
+
+def random_field_pm1(N, seed):
+    """Integer fields in {-1, 0, 1} drawn independently (used to add h to an
+    integer coupling family)."""
+    return rng(seed).integers(-1, 2, size=N).astype(np.float64)
