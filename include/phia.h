@@ -1,0 +1,177 @@
+/*
+ * phia.h -- C ABI of the MI355X (gfx950) library for the data-parallel sweep
+ * of the Parallel Hamiltonian Monte Carlo Ising Annealer (PHIA; Wang et al.,
+ * "Parallel Ising Annealer via Gradient-based Hamiltonian Monte Carlo").
+ *
+ * Problem (Sec. 2.1, Eq. 2): minimise E(s) = -sum_{i<j} J_ij s_i s_j -
+ * sum_i h_i s_i over s in {-1,+1}^N, with real couplings J_ij = J_ji and
+ * fields h_i held in fixed point (Sec. 2.2): every value is an integer multiple
+ * of sigma = 2^-f.  The library runs R independent replicas of the sweep
+ * (Eq. 5-8, App. A A7) and keeps each replica's best configuration
+ * (App. B, Table 3, state 5).
+ *
+ * Conventions for every entry point:
+ *  - Plain pointers; arrays named "host" are caller-owned host memory and are
+ *    only read (inputs) or written (outputs) during the call.  The library
+ *    copies inputs at create time and owns all device memory of a problem
+ *    until phia_destroy.
+ *  - Matrices are dense row-major; spin arrays are int8 with values +1 / -1.
+ *  - Energies in "units" are exact integers in units of sigma = 2^-frac_bits.
+ *  - Every function returns PHIA_OK (0) or a negative phia_status; on error
+ *    phia_last_error() gives a message (thread-local, valid until the next
+ *    call on the same thread).  No C++ exception crosses this boundary.
+ *  - A device fault or a timed-out group barrier poisons the handle: later
+ *    calls return PHIA_EDEVICE.
+ *  - One host thread at a time per problem handle.
+ */
+#ifndef PHIA_H
+#define PHIA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct phia_problem phia_problem;
+
+typedef enum {
+    PHIA_OK = 0,
+    PHIA_EINVAL = -1,   /* bad argument (null pointer, size out of range)            */
+    PHIA_ENOTSYM = -2,  /* J is not symmetric                                        */
+    PHIA_EDIAG = -3,    /* J has a nonzero diagonal entry                            */
+    PHIA_ERANGE = -4,   /* value off the 2^-f grid (quantize = 0) or too large       */
+    PHIA_ENOMEM = -5,   /* device or host allocation failed                          */
+    PHIA_EDEVICE = -6,  /* HIP error, device fault or group-barrier timeout          */
+    PHIA_ESTATE = -7    /* call out of order (e.g. phia_best before any anneal)      */
+} phia_status;
+
+/* Arithmetic used for the quasi-gradient J.s (Eq. 6).  Every path computes the
+ * same exact integer field, so results are identical across paths. */
+typedef enum {
+    PHIA_PATH_AUTO = 0,     /* I8 if |J| <= 127 units, else BF16HILO, else FP32      */
+    PHIA_PATH_FP32 = 1,     /* FP32 couplings, VALU dot products (plain sweep)       */
+    PHIA_PATH_I8 = 2,       /* int8 couplings, int8 MFMA with int32 accumulation     */
+    PHIA_PATH_BF16HILO = 3  /* J = 256 hi + lo, two BF16 MFMA planes, FP32 accumulate */
+} phia_path;
+
+typedef struct {
+    int32_t frac_bits;  /* f in [0, 15]; -1 picks the smallest f that holds J, h exactly */
+    int32_t quantize;   /* 0: reject off-grid values; 1: round half to even onto the grid */
+    int32_t path;       /* phia_path                                                     */
+    int32_t device;     /* HIP device ordinal                                            */
+    void* stream;       /* hipStream_t for all work of this problem; NULL = null stream  */
+} phia_options;
+
+/* Annealing schedule.  The inverse temperature of step k is betas[k] when
+ * betas != NULL (host array of `steps` floats), else the linear table
+ * beta_k = float(b0 + ((b1 - b0) * k) / (steps - 1)) evaluated in double.
+ * eps is the integrator step of A7, gamma the surrogate slope of Eq. 7-8,
+ * refresh_L the number of steps between momentum draws (v ~ N(0, I) at every
+ * k with k mod refresh_L == 0, k = 0 included). */
+typedef struct {
+    float beta0, beta1;
+    const float* betas;
+    float eps, gamma;
+    int64_t refresh_L;
+} phia_schedule;
+
+typedef struct {
+    int32_t N, Np;          /* spins and padded spins (multiple of 64)               */
+    int32_t path;           /* resolved phia_path                                    */
+    int32_t frac_bits;      /* f                                                     */
+    int32_t exact;          /* 1 if the couplings were on the grid (no rounding)     */
+    int32_t group;          /* workgroups that share one replica block's J (>= 1)    */
+    int32_t replicas;       /* R of the current anneal (0 if none)                   */
+    int32_t rows_per_block; /* replicas per workgroup block                          */
+    int64_t steps;          /* T of the current anneal                               */
+    int64_t step;           /* next step to run                                      */
+    int64_t max_abs_J;      /* max |J| in units                                      */
+    size_t device_bytes;    /* device memory held by the problem                     */
+} phia_info;
+
+/* Create a problem from real couplings.  J: host, N*N doubles, row-major,
+ * symmetric with a zero diagonal (the i<j sum of Eq. 2 read as a full
+ * symmetric matrix).  h: host, N doubles, or NULL for h = 0.  N in
+ * [1, 16384].  opt may be NULL (frac_bits = -1, quantize = 0, AUTO, device 0,
+ * null stream).  On success *out owns device copies of J and h. */
+phia_status phia_create(const double* J, const double* h, int32_t N,
+                        const phia_options* opt, phia_problem** out);
+
+/* Run a whole anneal: phia_anneal_start, phia_anneal_run(steps) and a
+ * synchronisation.  replicas in [1, 1<<20], steps >= 1, seed keys the
+ * counter-based Gaussian stream (Philox4x64-10); replica r always draws the
+ * same numbers for the same seed, whatever else runs. */
+phia_status phia_anneal(phia_problem* p, int32_t replicas, int64_t steps,
+                        const phia_schedule* schedule, uint64_t seed);
+
+/* Allocate replica state and draw x ~ N(0, I) (App. A, A3) for step 0.
+ * Enqueued on the problem's stream; returns without waiting. */
+phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps,
+                              const phia_schedule* schedule, uint64_t seed);
+
+/* Enqueue steps [current, k_end) (k_end <= steps).  Returns without waiting;
+ * splitting a run into several calls gives bit-identical results. */
+phia_status phia_anneal_run(phia_problem* p, int64_t k_end);
+
+/* Wait for the problem's stream and report a device error or barrier timeout. */
+phia_status phia_sync(phia_problem* p);
+
+/* Best configuration over all replicas (lowest energy, lowest replica on
+ * ties).  energy: host double = sigma * E_units (exact), or, when the input
+ * was rounded onto the grid, the FP64 energy of that configuration against
+ * the original couplings.  spins: host int8[N] or NULL.  Synchronises. */
+phia_status phia_best(phia_problem* p, double* energy, int8_t* spins);
+
+/* Exact best energy in units of 2^-frac_bits, and the replica that found it. */
+phia_status phia_best_exact(phia_problem* p, int64_t* energy_units, int32_t* frac_bits,
+                            int32_t* replica);
+
+/* FP64 energy (Eq. 2) of the best configuration against the couplings given
+ * to phia_create, computed on the device in FP64. */
+phia_status phia_best_f64(phia_problem* p, double* energy);
+
+/* Per-replica records: E: host int64[R] (units), S: host int8[R*N] or NULL,
+ * step: host int64[R] (first step reaching the record) or NULL. */
+phia_status phia_replica_best(phia_problem* p, int64_t* E, int8_t* S, int64_t* step);
+
+/* Continuous state: x, v: host float[R*N] or NULL; k: host int64 or NULL
+ * (the next step to run). */
+phia_status phia_get_state(phia_problem* p, float* x, float* v, int64_t* k);
+
+/* Overwrite the continuous state of the current anneal (x, v: host
+ * float[R*N]) and set the next step to k (0 <= k <= steps).  Records are
+ * kept.  Used to resume from saved state and by invariance tests. */
+phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int64_t k);
+
+phia_status phia_get_info(const phia_problem* p, phia_info* out);
+
+/* Record the energy of every step of the next anneal (test and diagnostic
+ * hook).  Call before phia_anneal_start; costs R*steps*8 bytes of device
+ * memory.  phia_get_trace copies the energies, host int64[R*steps] in units
+ * (row r holds E_0 .. E_{steps-1} of replica r; steps not yet run read 0). */
+phia_status phia_set_trace(phia_problem* p, int32_t enable);
+phia_status phia_get_trace(phia_problem* p, int64_t* E);
+
+/* Self-check of the device's elementary functions (diagnostic hook).
+ * kind 0: e^x for x <= 0; 1: ln u, u in (0,1); 2: cos and sin of 2 pi u
+ * (out holds 2n floats, cos first); 3: sech^2; 4: Gaussian draws with
+ * in64 = {seed, then n quadruples (tag, replica, round, index)}.
+ * in: host float[n] (kinds 0-3), out: host float[n] (2n for kind 2). */
+phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64, float* out, int64_t n,
+                            int32_t device);
+
+/* Release all device memory of p.  NULL is accepted. */
+void phia_destroy(phia_problem* p);
+
+/* Message of the last error on this thread ("" if none). */
+const char* phia_last_error(void);
+
+/* Library version string. */
+const char* phia_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PHIA_H */

@@ -1,0 +1,37 @@
+"""Build libphia.so (HIP kernels + host runtime + C ABI) for gfx950 with hipcc."""
+import os
+import subprocess
+import sys
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(PKG)
+CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(ROOT, "include")
+LIB = os.path.join(PKG, "libphia.so")
+
+SOURCES = ["phia_kernels.hip", "phia_runtime.cpp"]
+
+# -ffp-contract=off: no implicit fused multiply-adds (the sweep's op sequence
+# is fixed and every fma is explicit).  Correctly rounded FP32 division and
+# square root (HIP's default, stated).  Packed FP32 instructions disabled.
+HIPFLAGS = [
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "-ffp-contract=off", "-fhip-fp32-correctly-rounded-divide-sqrt",
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall", "-Wno-unused-function",
+]
+
+
+def build(verbose=False):
+    srcs = [os.path.join(CSRC, s) for s in SOURCES]
+    out = LIB + ".tmp"
+    cmd = ["hipcc", *HIPFLAGS, "-I", INCLUDE, "-I", CSRC, *srcs, "-o", out]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(out, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    build(verbose=True)

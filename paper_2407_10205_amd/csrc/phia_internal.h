@@ -1,0 +1,72 @@
+// Internal interface between the host runtime and the HIP kernels of the PHIA
+// sweep.  Not part of the public ABI (include/phia.h).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace phia {
+
+constexpr int kWaves = 4;            // waves per workgroup in the MFMA sweep
+constexpr int kThreads = 64 * kWaves;
+constexpr int kCbw = 4;              // max 16-column blocks per wave (MFMA sweep)
+constexpr int kFp32Rows = 4;         // replicas per workgroup in the FP32 sweep
+constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
+constexpr uint32_t kSpinLimit = 1u << 21;  // bounded polls per group barrier
+
+enum Path : int { kPathAuto = 0, kPathFp32 = 1, kPathI8 = 2, kPathBf16 = 3 };
+
+// Arguments of one sweep launch.  Device pointers unless noted.
+struct SweepArgs {
+    int32_t N, Np;              // spins, padded spins (multiple of 64)
+    const int32_t* h;           // [Np] fields in sigma units, zero padded
+    const void* J;              // packed couplings, layout depends on the path
+    const float* ctab;          // [T] c_k = (beta_k * gamma) * sigma
+    float eps, gamma;
+    int64_t L;                  // momentum refresh period
+    uint64_t seed;
+    int64_t k0, k1;             // steps [k0, k1) of this launch
+    int32_t R;                  // replicas of the problem
+    int64_t r_base;             // stream replica index of replica 0
+    float* x;                   // [R][Np]
+    float* v;                   // [R][Np]
+    int64_t* bestE;             // [R]
+    int8_t* bestS;              // [R][Np]
+    int64_t* bestStep;          // [R]
+    int64_t* etrace;            // [R][T] energy of every step, or null
+    int64_t T;                  // total steps (row length of etrace)
+    // MFMA sweep geometry
+    int32_t G;                  // workgroups per replica block (column split)
+    int32_t ncb;                // Np / 16
+    int32_t rows;               // replicas per block (16 * MT)
+    int32_t nblocks;            // ceil(R / rows)
+    int32_t ngroups;            // concurrently running groups
+    int32_t xcd_map;            // 1: group members share blockIdx % 8
+    int32_t j_lds;              // 1: J slice resident in LDS, 0: read from global
+    // group exchange (G > 1)
+    int8_t* xbuf;               // [2][ngroups][rows][Np] spins
+    int64_t* pbuf;              // [2][ngroups][G][rows] partial energies
+    uint32_t* flags;            // [ngroups][G] barrier sequence numbers
+    uint32_t seq_base;          // sequence number before this launch
+    int32_t* err;               // device error word (1 = barrier timeout)
+};
+
+// Layout of packed couplings.
+//  FP32: float [Np][Np] row-major.
+//  I8:   fragment-major int8: [Np/16 col blocks][Np/64 k blocks][64 lanes][16],
+//        lane l holds J[cb*16 + l%16][kb*64 + 16*(l/16) + t], t < 16.
+//  BF16: [Np/16][Np/32 k chunks][2 planes hi, lo][64 lanes][8 bf16],
+//        lane l holds plane[cb*16 + l%16][kc*32 + 8*(l/16) + t], t < 8,
+//        with J = 256 hi + lo, lo in [-128, 127].
+
+hipError_t launch_init(const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st);
+hipError_t launch_sweep_mfma(int path, int mt, const SweepArgs& a, size_t lds_bytes, hipStream_t st);
+size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a);
+hipError_t launch_argmin(const int64_t* bestE, int32_t R, int64_t* out2, hipStream_t st);
+hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const int8_t* s,
+                             double* out, hipStream_t st);
+hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,
+                             hipStream_t st);
+int max_coresident_mfma(int path, int mt, size_t lds_bytes);
+
+}  // namespace phia

@@ -1,0 +1,823 @@
+// HIP kernels of the PHIA sweep for gfx950 (MI355X).
+//
+// One step k of the sweep, for every replica r and spin i at once
+// (Wang et al., Sec. 2.1 Eq. 5-8 and App. A A7):
+//   if k mod L == 0: v_i ~ N(0, 1)                      (momentum refresh)
+//   x_i <- x_i + eps v_i ;  s_i = sgn x_i, sgn(0) = +1   (drift, readout)
+//   I_i = sum_j J_ij s_j + h_i                            (Eq. 6, exact int32)
+//   E   = -(sum_i s_i (I_i + h_i)) / 2                    (Eq. 2, exact int64)
+//   best-so-far record of (E, s)                          (App. B, Table 3)
+//   v_i <- v_i + eps (c_k sech^2(gamma x_i) I_i - x_i),   c_k = beta_k gamma sigma
+//
+// Kernels:
+//   k_init         x ~ N(0, I) (App. A, A3), records reset.
+//   k_sweep_fp32   plain sweep: FP32 couplings, VALU dot products, one
+//                  workgroup owns kFp32Rows replicas for the whole launch.
+//   k_sweep_mfma   J.s on matrix cores: int8 x int8 -> int32
+//                  (v_mfma_i32_16x16x64_i8) or two BF16 planes J = 256 hi + lo
+//                  with FP32 accumulation (v_mfma_f32_16x16x32_bf16).  A
+//                  workgroup owns 16*MT replicas and a slice of the columns;
+//                  its J slice stays in LDS for the whole launch.  When J is too
+//                  large for one CU, G workgroups split the columns and swap
+//                  the new spins of their slices through global memory once
+//                  per step (bounded flag barrier, partial energies ride along
+//                  one step late).  x, v and the accumulators stay in VGPRs in
+//                  the MFMA output layout, so the kick is fused with J.s.
+//   k_argmin       lowest best energy over replicas (lowest index on ties).
+//   k_energy_f64   FP64 Eq. 2 energy of one configuration.
+#include <stdint.h>
+
+#include "phia_devmath.h"
+#include "phia_internal.h"
+
+namespace phia {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+
+// ------------------------------------------------------------------ init --
+__global__ void __launch_bounds__(256) k_init(SweepArgs a)
+{
+    const int64_t total = static_cast<int64_t>(a.R) * a.Np;
+    for (int64_t idx = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; idx < total;
+         idx += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        const int64_t r = idx / a.Np;
+        const int i = static_cast<int>(idx - r * a.Np);
+        a.x[idx] = (i < a.N) ? dev_gauss(a.seed, kTagX, a.r_base + r, 0, i) : 0.0f;
+        a.v[idx] = 0.0f;
+        a.bestS[idx] = 0;
+        if (i == 0) {
+            a.bestE[r] = INT64_MAX;
+            a.bestStep[r] = -1;
+        }
+    }
+}
+
+hipError_t launch_init(const SweepArgs& a, hipStream_t st)
+{
+    const int64_t total = static_cast<int64_t>(a.R) * a.Np;
+    int64_t blocks = (total + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------- shared helpers --
+// Momentum draws happen once every L steps; a real call keeps the unrolled
+// sweep loops from holding many Philox states live at once.
+__device__ __attribute__((noinline)) float gauss_v(uint64_t seed, uint64_t replica, uint64_t round, int i)
+{
+    return dev_gauss(seed, kTagV, replica, round, static_cast<uint64_t>(i));
+}
+
+__device__ __forceinline__ float kick(float x, float v, int I, float ck, float eps, float gamma)
+{
+    const float d = dev_sech2(gamma * x);
+    const float p = ck * d;
+    const float g = __builtin_fmaf(p, static_cast<float>(I), -x);
+    return __builtin_fmaf(eps, g, v);
+}
+
+__device__ __forceinline__ int wave_sum16(int v)
+{
+    // sum over the 16 lanes that share lane / 16
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    return v;
+}
+
+__device__ __forceinline__ int wave_sum64(int v)
+{
+    v = wave_sum16(v);
+    v += __shfl_xor(v, 16, 64);
+    v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// --------------------------------------------------------- FP32 sweep --
+// Thread t owns columns i = t + 256 c (c < CPT) of kFp32Rows replicas.
+template <int CPT>
+__global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
+{
+    constexpr int RB = kFp32Rows;
+    extern __shared__ __align__(16) float sS[];  // [RB][Np] spins as +-1.0f
+    __shared__ int64_t sPart[RB][4];
+    __shared__ int64_t sBest[RB];
+    __shared__ int sImp[RB];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int Np = a.Np, N = a.N;
+    const int64_t rb0 = static_cast<int64_t>(blockIdx.x) * RB;
+    const float* __restrict__ J = static_cast<const float*>(a.J);
+
+    float x[RB][CPT], v[RB][CPT];
+    int hc[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int i = tid + 256 * c;
+        hc[c] = (i < Np) ? a.h[i] : 0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool ok = (rb0 + r < a.R) && (i < Np);
+            x[r][c] = ok ? a.x[(rb0 + r) * Np + i] : 0.0f;
+            v[r][c] = ok ? a.v[(rb0 + r) * Np + i] : 0.0f;
+        }
+    }
+    int64_t bstep = -1;
+    if (tid < RB) {
+        const bool ok = rb0 + tid < a.R;
+        sBest[tid] = ok ? a.bestE[rb0 + tid] : INT64_MAX;
+        bstep = ok ? a.bestStep[rb0 + tid] : -1;
+    }
+    __syncthreads();
+
+    for (int64_t k = a.k0; k < a.k1; ++k) {
+        if (k % a.L == 0) {
+            const uint64_t rnd = static_cast<uint64_t>(k / a.L);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + 256 * c;
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    v[r][c] = (i < N && rb0 + r < a.R) ? gauss_v(a.seed, a.r_base + rb0 + r, rnd, i) : 0.0f;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + 256 * c;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                x[r][c] = __builtin_fmaf(a.eps, v[r][c], x[r][c]);
+                if (i < Np) sS[r * Np + i] = (x[r][c] >= 0.0f) ? 1.0f : -1.0f;
+            }
+        }
+        __syncthreads();
+
+        float acc[RB][CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r][c] = 0.0f;
+        for (int j = 0; j < N; ++j) {
+            float sj[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) sj[r] = sS[r * Np + j];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + 256 * c;
+                if (i < Np) {
+                    const float jv = J[static_cast<int64_t>(j) * Np + i];
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv, sj[r], acc[r][c]);
+                }
+            }
+        }
+
+        int I[RB][CPT];
+        int part[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            part[r] = 0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + 256 * c;
+                I[r][c] = static_cast<int>(acc[r][c]) + hc[c];
+                const int s = (x[r][c] >= 0.0f) ? 1 : -1;
+                if (i < N) part[r] += s * (I[r][c] + hc[c]);
+            }
+            const int ws = wave_sum64(part[r]);
+            if (lane == 0) sPart[r][wave] = ws;
+        }
+        __syncthreads();
+        if (tid < RB) {
+            const int64_t tot = sPart[tid][0] + sPart[tid][1] + sPart[tid][2] + sPart[tid][3];
+            const int64_t E = -(tot / 2);
+            const bool ok = rb0 + tid < a.R;
+            if (ok && a.etrace) a.etrace[(rb0 + tid) * a.T + k] = E;
+            const int imp = ok && (E < sBest[tid]);
+            if (imp) {
+                sBest[tid] = E;
+                bstep = k;
+            }
+            sImp[tid] = imp;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (sImp[r]) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int i = tid + 256 * c;
+                    if (i < N) a.bestS[(rb0 + r) * Np + i] = (x[r][c] >= 0.0f) ? 1 : -1;
+                }
+            }
+        }
+        const float ck = a.ctab[k];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int r = 0; r < RB; ++r) v[r][c] = kick(x[r][c], v[r][c], I[r][c], ck, a.eps, a.gamma);
+    }
+
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int i = tid + 256 * c;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (rb0 + r < a.R && i < Np) {
+                a.x[(rb0 + r) * Np + i] = x[r][c];
+                a.v[(rb0 + r) * Np + i] = v[r][c];
+            }
+        }
+    }
+    if (tid < RB && rb0 + tid < a.R) {
+        a.bestE[rb0 + tid] = sBest[tid];
+        a.bestStep[rb0 + tid] = bstep;
+    }
+}
+
+hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st)
+{
+    const int cpt = (a.Np + 255) / 256;
+    const unsigned blocks = static_cast<unsigned>((a.R + kFp32Rows - 1) / kFp32Rows);
+    const size_t lds = sizeof(float) * static_cast<size_t>(kFp32Rows) * a.Np;
+    if (cpt <= 1)
+        hipLaunchKernelGGL(k_sweep_fp32<1>, dim3(blocks), dim3(256), lds, st, a);
+    else if (cpt <= 2)
+        hipLaunchKernelGGL(k_sweep_fp32<2>, dim3(blocks), dim3(256), lds, st, a);
+    else if (cpt <= 4)
+        hipLaunchKernelGGL(k_sweep_fp32<4>, dim3(blocks), dim3(256), lds, st, a);
+    else if (cpt <= 8)
+        hipLaunchKernelGGL(k_sweep_fp32<8>, dim3(blocks), dim3(256), lds, st, a);
+    else if (cpt <= 16)
+        hipLaunchKernelGGL(k_sweep_fp32<16>, dim3(blocks), dim3(256), lds, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+// --------------------------------------------------------- MFMA sweep --
+// LDS carve-up of one workgroup, shared with the host launch code.
+struct LdsPlan {
+    uint32_t j_off, s_off, s_bytes, p_off, e_off, b_off, k_off, misc_off, total;
+};
+
+__host__ __device__ inline uint32_t esz_of(int path) { return path == kPathI8 ? 1u : 2u; }
+__host__ __device__ inline uint32_t cb_bytes(int path, int Np)
+{
+    return static_cast<uint32_t>(Np) * 16u * (path == kPathI8 ? 1u : 4u);
+}
+
+__host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_max, int j_lds)
+{
+    LdsPlan p;
+    const uint32_t rows = 16u * mt;
+    p.j_off = 0;
+    p.s_off = j_lds ? static_cast<uint32_t>(cbs_max) * cb_bytes(path, Np) : 0u;
+    p.s_bytes = rows * (static_cast<uint32_t>(Np) * esz_of(path) + 16u);
+    p.p_off = p.s_off + 2u * p.s_bytes;
+    p.e_off = p.p_off + 3u * rows * 8u;
+    p.b_off = p.e_off + rows * 8u;       // [2][RB] best energies (parity buffers)
+    p.k_off = p.b_off + 2u * rows * 8u;  // [RB] step of the best energy
+    p.misc_off = p.k_off + rows * 8u;
+    p.total = p.misc_off + 16u;
+    return p;
+}
+
+__device__ __forceinline__ bool seq_reached(uint32_t f, uint32_t target)
+{
+    return static_cast<int32_t>(f - target) >= 0;
+}
+
+template <int PATH, int MT, bool GROUP>
+__global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
+{
+    constexpr int RB = 16 * MT;
+    constexpr int ESZ = (PATH == kPathI8) ? 1 : 2;
+    constexpr int NE = MT * kCbw * 4;  // owned elements per lane
+    static_assert(NE <= 64, "previous-sign mask holds 64 elements");
+    extern __shared__ __align__(16) unsigned char lds[];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int Np = a.Np, N = a.N;
+
+    int group = blockIdx.x, member = 0;
+    const int G = GROUP ? a.G : 1;
+    if (GROUP) {
+        if (a.xcd_map) {
+            const int w = blockIdx.x, pos = w >> 3;
+            member = pos % G;
+            group = (pos / G) * 8 + (w & 7);
+        } else {
+            member = blockIdx.x % G;
+            group = blockIdx.x / G;
+        }
+    }
+    const int cb0 = member * a.ncb / G;
+    const int cb1 = (member + 1) * a.ncb / G;
+    const int cbs = cb1 - cb0;
+    const int cbs_max = (a.ncb + G - 1) / G;
+    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, a.j_lds);
+    const uint32_t srow = static_cast<uint32_t>(Np) * ESZ + 16u;  // S row stride, bytes
+    const uint32_t cbb = cb_bytes(PATH, Np);
+    unsigned char* sJ = lds + P.j_off;
+    int64_t* sP = reinterpret_cast<int64_t*>(lds + P.p_off);   // [3][RB]
+    int64_t* sE = reinterpret_cast<int64_t*>(lds + P.e_off);   // [RB]
+    int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);   // [2][RB]
+    int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);   // [RB]
+    int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
+
+    const unsigned char* Jg = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0) * cbb;
+    if (a.j_lds) {
+        const uint32_t nvec = static_cast<uint32_t>(cbs) * cbb / 16u;
+        const uint4* src = reinterpret_cast<const uint4*>(Jg);
+        uint4* dst = reinterpret_cast<uint4*>(sJ);
+        for (uint32_t q = tid; q < nvec; q += kThreads) dst[q] = src[q];
+    }
+    if (tid == 0) *sAbort = 0;
+    const unsigned char* Jsrc = a.j_lds ? sJ : Jg;
+
+    int col[kCbw], hreg[kCbw];
+    bool cval[kCbw];
+#pragma unroll
+    for (int cw = 0; cw < kCbw; ++cw) {
+        const int c = wave + kWaves * cw;
+        cval[cw] = c < cbs;
+        col[cw] = (cb0 + c) * 16 + lr;
+        hreg[cw] = (cval[cw] && col[cw] < Np) ? a.h[col[cw]] : 0;
+    }
+    const int nkb = Np / 64;
+    const float eps = a.eps, gamma = a.gamma;
+    const uint32_t seq_stride = static_cast<uint32_t>(a.k1 - a.k0 + 1);
+    int iter = 0;
+
+    for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
+        const int64_t rb0 = static_cast<int64_t>(blk) * RB;
+        float x[MT][kCbw][4], v[MT][kCbw][4];
+        bool rval[MT][4];
+        for (int q = tid; q < RB; q += kThreads) {
+            const bool ok = rb0 + q < a.R;
+            sB[q] = sB[RB + q] = ok ? a.bestE[rb0 + q] : INT64_MAX;
+            sK[q] = ok ? a.bestStep[rb0 + q] : -1;
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+                rval[mt][j] = gr < a.R;
+#pragma unroll
+                for (int cw = 0; cw < kCbw; ++cw) {
+                    const bool ok = rval[mt][j] && cval[cw];
+                    x[mt][cw][j] = ok ? a.x[gr * Np + col[cw]] : 0.0f;
+                    v[mt][cw][j] = ok ? a.v[gr * Np + col[cw]] : 0.0f;
+                }
+            }
+        for (int q = tid; q < 3 * RB; q += kThreads) sP[q] = 0;
+        __syncthreads();
+
+        uint64_t pm = 0;  // signs of step k-1, bit (mt*kCbw + cw)*4 + j
+        bool aborted = false;
+        for (int64_t k = a.k0; k <= a.k1; ++k) {
+            const bool last = (k == a.k1);  // closing pass: records of step k1-1 only
+            const int par = static_cast<int>(k & 1);
+            unsigned char* S = lds + P.s_off + par * P.s_bytes;
+            if (!last) {
+                pm = 0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (x[mt][cw][j] >= 0.0f) pm |= 1ull << ((mt * kCbw + cw) * 4 + j);
+                if (k % a.L == 0) {
+                    const uint64_t rnd = static_cast<uint64_t>(k / a.L);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+#pragma unroll
+                            for (int cw = 0; cw < kCbw; ++cw) {
+                                const bool ok = cval[cw] && rval[mt][j] && col[cw] < N;
+                                v[mt][cw][j] = ok ? gauss_v(a.seed, a.r_base + rb0 + mt * 16 + 4 * lg + j,
+                                                            rnd, col[cw])
+                                                  : 0.0f;
+                            }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw) {
+                        if (!cval[cw]) continue;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            x[mt][cw][j] = __builtin_fmaf(eps, v[mt][cw][j], x[mt][cw][j]);
+                            const int row = mt * 16 + 4 * lg + j;
+                            const bool pos = x[mt][cw][j] >= 0.0f;
+                            if (ESZ == 1)
+                                S[row * srow + col[cw]] = pos ? 1 : 0xff;
+                            else
+                                reinterpret_cast<uint16_t*>(S + row * srow)[col[cw]] = pos ? 0x3f80 : 0xbf80;
+                        }
+                    }
+            } else {
+                pm = 0;
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            if (x[mt][cw][j] >= 0.0f) pm |= 1ull << ((mt * kCbw + cw) * 4 + j);
+            }
+
+            if (GROUP) {
+                __syncthreads();
+                const uint32_t seq = a.seq_base + static_cast<uint32_t>(iter) * seq_stride +
+                                     static_cast<uint32_t>(k - a.k0) + 1u;
+                const size_t gslot = static_cast<size_t>(par) * a.ngroups + group;
+                unsigned char* X = reinterpret_cast<unsigned char*>(a.xbuf) +
+                                   gslot * RB * static_cast<size_t>(Np) * ESZ;
+                if (!last) {
+                    const uint32_t own = static_cast<uint32_t>(cbs) * 16u * ESZ;  // bytes per row
+                    const uint32_t per_row = own / 16u;
+                    const uint32_t nvec = RB * per_row;
+                    for (uint32_t q = tid; q < nvec; q += kThreads) {
+                        const uint32_t row = q / per_row, cc = q - row * per_row;
+                        const uint32_t off = static_cast<uint32_t>(cb0) * 16u * ESZ + cc * 16u;
+                        *reinterpret_cast<uint4*>(X + static_cast<size_t>(row) * Np * ESZ + off) =
+                            *reinterpret_cast<const uint4*>(S + row * srow + off);
+                    }
+                }
+                if (k > a.k0 && tid < RB)
+                    a.pbuf[(gslot * G + member) * RB + tid] = sP[((k - 1) % 3) * RB + tid];
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                __syncthreads();
+                uint32_t* flags = a.flags + static_cast<size_t>(group) * G;
+                if (tid == 0) __hip_atomic_store(flags + member, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                for (int m = tid; m < G; m += kThreads) {
+                    uint32_t polls = 0;
+                    while (!seq_reached(__hip_atomic_load(flags + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                                        seq)) {
+                        ++polls;
+                        if (polls > kSpinLimit ||
+                            ((polls & 255u) == 0 &&
+                             __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+                            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            *sAbort = 1;
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
+                    }
+                }
+                __syncthreads();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                if (*sAbort) {
+                    aborted = true;
+                    break;
+                }
+                if (!last) {
+                    const uint32_t per_row = static_cast<uint32_t>(Np) * ESZ / 16u;
+                    const uint32_t nvec = RB * per_row;
+                    for (uint32_t q = tid; q < nvec; q += kThreads) {
+                        const uint32_t row = q / per_row, cc = q - row * per_row;
+                        *reinterpret_cast<uint4*>(S + row * srow + cc * 16u) =
+                            *reinterpret_cast<const uint4*>(X + static_cast<size_t>(row) * Np * ESZ + cc * 16u);
+                    }
+                }
+                if (k > a.k0 && tid < RB) {
+                    int64_t t = 0;
+                    for (int m = 0; m < G; ++m) t += a.pbuf[(gslot * G + m) * RB + tid];
+                    sE[tid] = t;
+                }
+                __syncthreads();
+            } else {
+                __syncthreads();
+            }
+
+            // Records of step k-1 (App. B, Table 3, state 5).
+            // Every lane holding a row takes the same decision from the
+            // previous record (parity buffer par^1); lane 0 of the row group
+            // in wave 0 writes the new record into buffer par.
+            if (k > a.k0) {
+                const int64_t* tot = GROUP ? sE : sP + ((k - 1) % 3) * RB;
+                const int64_t* prev = sB + (par ^ 1) * RB;
+                int64_t* next = sB + par * RB;
+                const bool writer = (wave == 0 && lr == 0);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int row = mt * 16 + 4 * lg + j;
+                        const int64_t E = -(tot[row] / 2);
+                        const int64_t B = prev[row];
+                        const bool imp = E < B;
+                        if (writer) {
+                            next[row] = imp ? E : B;
+                            if (imp) sK[row] = k - 1;
+                        }
+                        if (!rval[mt][j]) continue;
+                        if (a.etrace && member == 0 && writer)
+                            a.etrace[(rb0 + row) * a.T + (k - 1)] = E;
+                        if (imp) {
+#pragma unroll
+                            for (int cw = 0; cw < kCbw; ++cw)
+                                if (cval[cw] && col[cw] < N)
+                                    a.bestS[(rb0 + row) * Np + col[cw]] =
+                                        ((pm >> ((mt * kCbw + cw) * 4 + j)) & 1u) ? 1 : -1;
+                        }
+                    }
+            }
+            if (last) break;
+            if (tid < RB) sP[((k + 1) % 3) * RB + tid] = 0;
+
+            // Quasi-gradient on matrix cores.
+            int I[MT][kCbw][4];
+            if (PATH == kPathI8) {
+                v4i acc[MT][kCbw];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw) acc[mt][cw] = v4i{0, 0, 0, 0};
+                for (int kb = 0; kb < nkb; ++kb) {
+                    v4i A[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        A[mt] = *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + kb * 64 + 16 * lg);
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw) {
+                        if (!cval[cw]) continue;
+                        const int c = wave + kWaves * cw;
+                        const v4i B = *reinterpret_cast<const v4i*>(
+                            Jsrc + (static_cast<size_t>(c) * nkb + kb) * 1024 + lane * 16);
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+                            acc[mt][cw] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B, acc[mt][cw], 0, 0, 0);
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) I[mt][cw][j] = acc[mt][cw][j] + hreg[cw];
+            } else {
+                v4f ahi[MT][kCbw], alo[MT][kCbw];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw) {
+                        ahi[mt][cw] = v4f{0.f, 0.f, 0.f, 0.f};
+                        alo[mt][cw] = v4f{0.f, 0.f, 0.f, 0.f};
+                    }
+                const int nkc = Np / 32;
+                for (int kc = 0; kc < nkc; ++kc) {
+                    v8bf A[MT];
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+                        A[mt] = __builtin_bit_cast(
+                            v8bf, *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + kc * 64 + 16 * lg));
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw) {
+                        if (!cval[cw]) continue;
+                        const int c = wave + kWaves * cw;
+                        const unsigned char* base = Jsrc + ((static_cast<size_t>(c) * nkc + kc) * 2) * 1024;
+                        const v8bf Bh = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i*>(base + lane * 16));
+                        const v8bf Bl =
+                            __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i*>(base + 1024 + lane * 16));
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt) {
+                            ahi[mt][cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bh, ahi[mt][cw], 0, 0, 0);
+                            alo[mt][cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bl, alo[mt][cw], 0, 0, 0);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            I[mt][cw][j] = 256 * static_cast<int>(ahi[mt][cw][j]) +
+                                           static_cast<int>(alo[mt][cw][j]) + hreg[cw];
+            }
+
+            // Partial energies of step k and the kick.
+            const float ck = a.ctab[k];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    int part = 0;
+#pragma unroll
+                    for (int cw = 0; cw < kCbw; ++cw) {
+                        if (!cval[cw]) continue;
+                        const int s = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
+                        if (col[cw] < N) part += s * (I[mt][cw][j] + hreg[cw]);
+                        v[mt][cw][j] = kick(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j], ck, eps, gamma);
+                    }
+                    part = wave_sum16(part);
+                    if (lr == 0)
+                        atomicAdd(reinterpret_cast<unsigned long long*>(sP + (k % 3) * RB + mt * 16 + 4 * lg + j),
+                                  static_cast<unsigned long long>(static_cast<int64_t>(part)));
+                }
+        }
+        if (aborted) return;
+
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                if (!rval[mt][j]) continue;
+                const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+#pragma unroll
+                for (int cw = 0; cw < kCbw; ++cw)
+                    if (cval[cw]) {
+                        a.x[gr * Np + col[cw]] = x[mt][cw][j];
+                        a.v[gr * Np + col[cw]] = v[mt][cw][j];
+                    }
+            }
+        __syncthreads();
+        if (member == 0) {
+            // Final records sit in the buffer written by the closing pass (k1).
+            const int64_t* fin = sB + (a.k1 & 1) * RB;
+            for (int q = tid; q < RB; q += kThreads)
+                if (rb0 + q < a.R) {
+                    a.bestE[rb0 + q] = fin[q];
+                    a.bestStep[rb0 + q] = sK[q];
+                }
+        }
+        __syncthreads();
+    }
+}
+
+size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)
+{
+    const int cbs_max = (a.ncb + a.G - 1) / a.G;
+    return lds_plan(path, mt, a.Np, cbs_max, a.j_lds).total;
+}
+
+template <int PATH, int MT, bool GROUP>
+static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    const unsigned grid = static_cast<unsigned>(GROUP ? a.ngroups * a.G : a.nblocks);
+    auto kern = k_sweep_mfma<PATH, MT, GROUP>;
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    if (GROUP) {
+        SweepArgs copy = a;
+        void* args[] = {&copy};
+        e = hipLaunchCooperativeKernel(reinterpret_cast<const void*>(kern), dim3(grid), dim3(kThreads), args,
+                                       static_cast<unsigned>(lds), st);
+        if (e != hipSuccess) return e;
+    } else {
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kThreads), lds, st, a);
+    }
+    return hipGetLastError();
+}
+
+template <int PATH, int MT>
+static hipError_t launch_mfma_g(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    return a.G > 1 ? launch_mfma_t<PATH, MT, true>(a, lds, st) : launch_mfma_t<PATH, MT, false>(a, lds, st);
+}
+
+hipError_t launch_sweep_mfma(int path, int mt, const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    if (path == kPathI8) {
+        if (mt == 1) return launch_mfma_g<kPathI8, 1>(a, lds, st);
+        if (mt == 2) return launch_mfma_g<kPathI8, 2>(a, lds, st);
+    } else if (path == kPathBf16) {
+        if (mt == 1) return launch_mfma_g<kPathBf16, 1>(a, lds, st);
+        if (mt == 2) return launch_mfma_g<kPathBf16, 2>(a, lds, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+int max_coresident_mfma(int path, int mt, size_t lds)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const void* f = nullptr;
+    if (path == kPathI8)
+        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, true>)
+                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 2, true>);
+    else
+        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, true>)
+                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 2, true>);
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;
+    return per * cus;
+}
+
+// ---------------------------------------------------------------- argmin --
+__global__ void __launch_bounds__(256) k_argmin(const int64_t* bestE, int32_t R, int64_t* out)
+{
+    __shared__ int64_t sE[256];
+    __shared__ int64_t sR[256];
+    int64_t e = INT64_MAX, r = -1;
+    for (int i = threadIdx.x; i < R; i += 256) {
+        const int64_t v = bestE[i];
+        if (r < 0 || v < e) {
+            e = v;
+            r = i;
+        }
+    }
+    sE[threadIdx.x] = e;
+    sR[threadIdx.x] = r;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            const int64_t e2 = sE[threadIdx.x + w], r2 = sR[threadIdx.x + w];
+            const int64_t e1 = sE[threadIdx.x], r1 = sR[threadIdx.x];
+            const bool take = r2 >= 0 && (r1 < 0 || e2 < e1 || (e2 == e1 && r2 < r1));
+            if (take) {
+                sE[threadIdx.x] = e2;
+                sR[threadIdx.x] = r2;
+            }
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = sE[0];
+        out[1] = sR[0];
+    }
+}
+
+hipError_t launch_argmin(const int64_t* bestE, int32_t R, int64_t* out2, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_argmin, dim3(1), dim3(256), 0, st, bestE, R, out2);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------ FP64 energy --
+__global__ void __launch_bounds__(256) k_energy_f64(const double* J, const double* h, int32_t N, const int8_t* s,
+                                                    double* out)
+{
+    __shared__ double sred[256];
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < N; i += 256) {
+        const double si = s[i];
+        double row = 0.0;
+        for (int j = i + 1; j < N; ++j) row += J[static_cast<int64_t>(i) * N + j] * s[j];
+        acc += si * row + (h ? h[i] * si : 0.0);
+    }
+    sred[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) sred[threadIdx.x] += sred[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = -sred[0];
+}
+
+hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const int8_t* s, double* out,
+                             hipStream_t st)
+{
+    hipLaunchKernelGGL(k_energy_f64, dim3(1), dim3(256), 0, st, J, h, N, s, out);
+    return hipGetLastError();
+}
+
+// ----------------------------------------------------- fmath self-check --
+__global__ void __launch_bounds__(256) k_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out,
+                                                    int64_t n)
+{
+    for (int64_t q = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; q < n;
+         q += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+        if (kind == 0) {
+            out[q] = dev_exp_nonpos(in[q]);
+        } else if (kind == 1) {
+            out[q] = dev_ln_unit(in[q]);
+        } else if (kind == 2) {
+            float c, s;
+            dev_sincos_2pi(in[q], c, s);
+            out[2 * q] = c;
+            out[2 * q + 1] = s;
+        } else if (kind == 3) {
+            out[q] = dev_sech2(in[q]);
+        } else {
+            out[q] = dev_gauss(in64[0], static_cast<uint32_t>(in64[1 + 4 * q]), in64[2 + 4 * q], in64[3 + 4 * q],
+                               in64[4 + 4 * q]);
+        }
+    }
+}
+
+hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n, hipStream_t st)
+{
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fmath_eval, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, kind, in, in64, out, n);
+    return hipGetLastError();
+}
+
+}  // namespace phia

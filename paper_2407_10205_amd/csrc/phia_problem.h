@@ -1,0 +1,66 @@
+// The opaque problem handle of include/phia.h (host-side bookkeeping).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "phia.h"
+#include "phia_internal.h"
+
+namespace phia {
+
+// Launch geometry of the MFMA sweep (see k_sweep_mfma).
+struct Geometry {
+    bool ok = false;
+    int mt = 1;        // 16-replica row tiles per workgroup
+    int G = 1;         // workgroups splitting the columns of one replica block
+    int j_lds = 1;     // J slice resident in LDS
+    int rows = 16;     // replicas per block
+    int nblocks = 0;   // replica blocks
+    int ngroups = 0;   // groups running concurrently
+    int xcd_map = 0;   // group members share blockIdx % 8 (one XCD)
+    size_t lds = 0;    // dynamic LDS bytes per workgroup
+};
+
+phia_status fail(phia_status st, const char* fmt, ...);
+phia_status hip_fail(struct ::phia_problem* p, hipError_t e, const char* what);
+void clear_error();
+
+}  // namespace phia
+
+struct phia_problem {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    int N = 0, Np = 0, path = 0, f = 0;
+    bool exact = true;
+    int64_t maxabsJ = 0;
+    bool poisoned = false;
+    // instance
+    void* dJ = nullptr;
+    int32_t* dh = nullptr;
+    double* dJ64 = nullptr;
+    double* dh64 = nullptr;
+    int32_t* derr = nullptr;
+    int64_t* dscratch = nullptr;
+    size_t base_bytes = 0;
+    // anneal
+    bool started = false, has_run = false, trace = false;
+    int32_t R = 0;
+    int64_t T = 0, k = 0, L = 1;
+    float eps = 0.f, gamma = 0.f;
+    uint64_t seed = 0;
+    float* dctab = nullptr;
+    float* dx = nullptr;
+    float* dv = nullptr;
+    int64_t* dbestE = nullptr;
+    int8_t* dbestS = nullptr;
+    int64_t* dbestStep = nullptr;
+    int64_t* detrace = nullptr;
+    int8_t* dxbuf = nullptr;
+    int64_t* dpbuf = nullptr;
+    uint32_t* dflags = nullptr;
+    uint32_t seq = 0;
+    int32_t best_r = -1;
+    size_t state_bytes = 0;
+    phia::Geometry geo;
+};

@@ -1,0 +1,766 @@
+// Host runtime of the PHIA library: validation and fixed-point packing of the
+// instance, choice of the J.s arithmetic and of the kernel geometry, device
+// memory, schedule tables, launches and error reporting behind the C ABI of
+// include/phia.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "phia.h"
+#include "phia_internal.h"
+#include "phia_problem.h"
+
+using namespace phia;
+
+namespace phia {
+
+static thread_local std::string g_err;
+
+phia_status fail(phia_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+phia_status hip_fail(phia_problem* p, hipError_t e, const char* what)
+{
+    if (p) p->poisoned = true;
+    return fail(PHIA_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+void clear_error() { g_err.clear(); }
+
+template <class T>
+static void dfree(T*& ptr)
+{
+    if (ptr) (void)hipFree(ptr);
+    ptr = nullptr;
+}
+
+static hipError_t dalloc(void** ptr, size_t bytes, size_t* counter)
+{
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 16);
+    if (e == hipSuccess && counter) *counter += bytes;
+    return e;
+}
+
+// ------------------------------------------------------------- packing --
+// Grid check: v * 2^f is an integer.
+static bool on_grid(double v, int f)
+{
+    const double t = std::ldexp(v, f);
+    return t == std::nearbyint(t);
+}
+
+phia_status pack_instance(const double* J, const double* h, int N, int frac_bits, int quantize,
+                          std::vector<int32_t>& Ji, std::vector<int32_t>& hi, int& f_out, bool& exact)
+{
+    const int64_t NN = static_cast<int64_t>(N) * N;
+    for (int i = 0; i < N; ++i) {
+        if (J[static_cast<int64_t>(i) * N + i] != 0.0) return fail(PHIA_EDIAG, "J[%d][%d] != 0", i, i);
+        for (int j = 0; j < N; ++j) {
+            const double a = J[static_cast<int64_t>(i) * N + j];
+            if (!std::isfinite(a)) return fail(PHIA_EINVAL, "J[%d][%d] is not finite", i, j);
+            if (a != J[static_cast<int64_t>(j) * N + i]) return fail(PHIA_ENOTSYM, "J[%d][%d] != J[%d][%d]", i, j, j, i);
+        }
+    }
+    if (h)
+        for (int i = 0; i < N; ++i)
+            if (!std::isfinite(h[i])) return fail(PHIA_EINVAL, "h[%d] is not finite", i);
+    int f = frac_bits;
+    if (f > 15) return fail(PHIA_EINVAL, "frac_bits must be in [-1, 15]");
+    if (f < 0) {
+        for (f = 0; f <= 15; ++f) {
+            bool ok = true;
+            for (int64_t t = 0; ok && t < NN; ++t) ok = on_grid(J[t], f);
+            for (int i = 0; ok && h && i < N; ++i) ok = on_grid(h[i], f);
+            if (ok) break;
+        }
+        if (f > 15) {
+            if (!quantize) return fail(PHIA_ERANGE, "couplings are not on any grid 2^-f with f <= 15");
+            f = 15;
+        }
+    }
+    exact = true;
+    Ji.assign(static_cast<size_t>(NN), 0);
+    hi.assign(static_cast<size_t>(N), 0);
+    for (int64_t t = 0; t < NN; ++t) {
+        const double a = std::ldexp(J[t], f), q = std::nearbyint(a);
+        if (q != a) {
+            if (!quantize) return fail(PHIA_ERANGE, "J entry %lld is off the 2^-%d grid", (long long)t, f);
+            exact = false;
+        }
+        if (std::fabs(q) >= 1073741824.0) return fail(PHIA_ERANGE, "J entry %lld out of range", (long long)t);
+        Ji[static_cast<size_t>(t)] = static_cast<int32_t>(q);
+    }
+    for (int i = 0; i < N; ++i) {
+        const double a = h ? std::ldexp(h[i], f) : 0.0, q = std::nearbyint(a);
+        if (q != a) {
+            if (!quantize) return fail(PHIA_ERANGE, "h[%d] is off the 2^-%d grid", i, f);
+            exact = false;
+        }
+        if (std::fabs(q) >= 1073741824.0) return fail(PHIA_ERANGE, "h[%d] out of range", i);
+        hi[static_cast<size_t>(i)] = static_cast<int32_t>(q);
+    }
+    f_out = f;
+    return PHIA_OK;
+}
+
+// I8 fragment-major: [Np/16][Np/64][64 lanes][16 bytes].
+static void pack_i8(const std::vector<int32_t>& Ji, int N, int Np, std::vector<int8_t>& out)
+{
+    const int ncb = Np / 16, nkb = Np / 64;
+    out.assign(static_cast<size_t>(Np) * Np, 0);
+    for (int cb = 0; cb < ncb; ++cb)
+        for (int kb = 0; kb < nkb; ++kb)
+            for (int l = 0; l < 64; ++l) {
+                const int i = cb * 16 + (l & 15);
+                int8_t* dst = &out[((static_cast<size_t>(cb) * nkb + kb) * 64 + l) * 16];
+                for (int t = 0; t < 16; ++t) {
+                    const int j = kb * 64 + 16 * (l >> 4) + t;
+                    dst[t] = (i < N && j < N) ? static_cast<int8_t>(Ji[static_cast<size_t>(i) * N + j]) : 0;
+                }
+            }
+}
+
+static uint16_t bf16_of_int(int v)
+{
+    // |v| <= 256: exact in bfloat16 (8 significant bits).
+    const float f = static_cast<float>(v);
+    uint32_t b;
+    std::memcpy(&b, &f, 4);
+    return static_cast<uint16_t>(b >> 16);
+}
+
+// BF16 hi/lo fragment-major: [Np/16][Np/32][2][64 lanes][8 bf16].
+static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector<uint16_t>& out)
+{
+    const int ncb = Np / 16, nkc = Np / 32;
+    out.assign(static_cast<size_t>(Np) * Np * 2, 0);
+    for (int cb = 0; cb < ncb; ++cb)
+        for (int kc = 0; kc < nkc; ++kc)
+            for (int pl = 0; pl < 2; ++pl)
+                for (int l = 0; l < 64; ++l) {
+                    const int i = cb * 16 + (l & 15);
+                    uint16_t* dst = &out[(((static_cast<size_t>(cb) * nkc + kc) * 2 + pl) * 64 + l) * 8];
+                    for (int t = 0; t < 8; ++t) {
+                        const int j = kc * 32 + 8 * (l >> 4) + t;
+                        const int v = (i < N && j < N) ? Ji[static_cast<size_t>(i) * N + j] : 0;
+                        const int lo = ((v + 128) & 255) - 128;
+                        const int hi = (v - lo) / 256;
+                        dst[t] = bf16_of_int(pl == 0 ? hi : lo);
+                    }
+                }
+}
+
+// ------------------------------------------------------- kernel geometry --
+static void choose_mfma_geometry(phia_problem* p, int R)
+{
+    const int Np = p->Np, ncb = Np / 16;
+    int dev_cus = 256;
+    (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, p->dev);
+    const int gmin = (ncb + kWaves * kCbw - 1) / (kWaves * kCbw);
+    SweepArgs a{};
+    a.Np = Np;
+    a.ncb = ncb;
+    for (int pass = 0; pass < 2; ++pass) {          // pass 0: J in LDS, pass 1: J from global
+        for (int mt : {2, 1}) {
+            const int rows = 16 * mt;
+            const int nblocks = (R + rows - 1) / rows;
+            for (int G = gmin; G <= ncb; ++G) {
+                a.G = G;
+                a.j_lds = pass == 0;
+                const size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
+                if (lds > static_cast<size_t>(kLdsMax)) {
+                    if (pass == 1) break;  // S alone does not fit; more columns per member won't help
+                    continue;
+                }
+                int ngroups = nblocks;
+                if (G > 1) {
+                    const int maxwg = max_coresident_mfma(p->path, mt, lds);
+                    if (maxwg < G) break;
+                    ngroups = std::min(nblocks, maxwg / G);
+                    if (ngroups >= 8) ngroups -= ngroups % 8;
+                }
+                p->geo.mt = mt;
+                p->geo.G = G;
+                p->geo.j_lds = a.j_lds;
+                p->geo.rows = rows;
+                p->geo.nblocks = nblocks;
+                p->geo.ngroups = ngroups;
+                p->geo.xcd_map = (G > 1 && ngroups % 8 == 0) ? 1 : 0;
+                p->geo.lds = lds;
+                p->geo.ok = true;
+                (void)dev_cus;
+                return;
+            }
+        }
+    }
+    p->geo.ok = false;
+}
+
+static void free_state(phia_problem* p)
+{
+    dfree(p->dx);
+    dfree(p->dv);
+    dfree(p->dbestE);
+    dfree(p->dbestS);
+    dfree(p->dbestStep);
+    dfree(p->dctab);
+    dfree(p->detrace);
+    dfree(p->dxbuf);
+    dfree(p->dpbuf);
+    dfree(p->dflags);
+    p->state_bytes = 0;
+    p->R = 0;
+    p->T = 0;
+    p->k = 0;
+}
+
+SweepArgs sweep_args(const phia_problem* p)
+{
+    SweepArgs a{};
+    a.N = p->N;
+    a.Np = p->Np;
+    a.h = p->dh;
+    a.J = p->dJ;
+    a.ctab = p->dctab;
+    a.eps = p->eps;
+    a.gamma = p->gamma;
+    a.L = p->L;
+    a.seed = p->seed;
+    a.R = p->R;
+    a.r_base = 0;
+    a.x = p->dx;
+    a.v = p->dv;
+    a.bestE = p->dbestE;
+    a.bestS = p->dbestS;
+    a.bestStep = p->dbestStep;
+    a.etrace = p->detrace;
+    a.T = p->T;
+    a.G = p->geo.G;
+    a.ncb = p->Np / 16;
+    a.rows = p->geo.rows;
+    a.nblocks = p->geo.nblocks;
+    a.ngroups = p->geo.ngroups;
+    a.xcd_map = p->geo.xcd_map;
+    a.j_lds = p->geo.j_lds;
+    a.xbuf = p->dxbuf;
+    a.pbuf = p->dpbuf;
+    a.flags = p->dflags;
+    a.seq_base = p->seq;
+    a.err = p->derr;
+    return a;
+}
+
+phia_status check_usable(const phia_problem* p)
+{
+    if (!p) return fail(PHIA_EINVAL, "null problem");
+    if (p->poisoned) return fail(PHIA_EDEVICE, "problem handle is poisoned by an earlier device error");
+    return PHIA_OK;
+}
+
+}  // namespace phia
+
+// =================================================================== ABI ==
+extern "C" {
+
+const char* phia_last_error(void) { return g_err.c_str(); }
+
+const char* phia_version(void) { return "phia-mi355x 0.1 (gfx950)"; }
+
+phia_status phia_create(const double* J, const double* h, int32_t N, const phia_options* opt, phia_problem** out)
+{
+    clear_error();
+    if (!out) return fail(PHIA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!J) return fail(PHIA_EINVAL, "J is null");
+    if (N < 1 || N > 16384) return fail(PHIA_EINVAL, "N = %d outside [1, 16384]", N);
+    phia_options o{-1, 0, PHIA_PATH_AUTO, 0, nullptr};
+    if (opt) o = *opt;
+    if (o.path < PHIA_PATH_AUTO || o.path > PHIA_PATH_BF16HILO) return fail(PHIA_EINVAL, "unknown path %d", o.path);
+
+    std::vector<int32_t> Ji, hi;
+    int f = 0;
+    bool exact = true;
+    phia_status st = pack_instance(J, h, N, o.frac_bits, o.quantize, Ji, hi, f, exact);
+    if (st != PHIA_OK) return st;
+
+    int64_t maxJ = 0, minJ = 0, maxrow = 0;
+    for (int i = 0; i < N; ++i) {
+        int64_t row = std::llabs(hi[i]);
+        for (int j = 0; j < N; ++j) {
+            const int64_t v = Ji[static_cast<size_t>(i) * N + j];
+            maxJ = std::max(maxJ, v);
+            minJ = std::min(minJ, v);
+            row += std::llabs(v);
+        }
+        maxrow = std::max(maxrow, row);
+    }
+    const int64_t maxabs = std::max(maxJ, -minJ);
+    if (maxrow >= (int64_t(1) << 31)) return fail(PHIA_ERANGE, "sum_j |J_ij| + |h_i| does not fit int32");
+    int path = o.path;
+    const bool i8_ok = maxJ <= 127 && minJ >= -128;
+    const bool bf_ok = maxabs <= 32767;
+    const bool f32_ok = maxrow < (int64_t(1) << 24);
+    if (path == PHIA_PATH_AUTO) path = i8_ok ? PHIA_PATH_I8 : bf_ok ? PHIA_PATH_BF16HILO : PHIA_PATH_FP32;
+    if (path == PHIA_PATH_I8 && !i8_ok) return fail(PHIA_ERANGE, "couplings outside int8 for the I8 path");
+    if (path == PHIA_PATH_BF16HILO && !bf_ok) return fail(PHIA_ERANGE, "couplings outside 16 bits for BF16HILO");
+    if (path == PHIA_PATH_FP32 && !f32_ok) return fail(PHIA_ERANGE, "row sums exceed 2^24 for the FP32 path");
+
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PHIA_EDEVICE, "no HIP device");
+    if (o.device < 0 || o.device >= ndev) return fail(PHIA_EINVAL, "device %d not present", o.device);
+    hipError_t e = hipSetDevice(o.device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+
+    phia_problem* p = new (std::nothrow) phia_problem();
+    if (!p) return fail(PHIA_ENOMEM, "host allocation failed");
+    p->dev = o.device;
+    p->st = static_cast<hipStream_t>(o.stream);
+    p->N = N;
+    p->Np = (N + 63) / 64 * 64;
+    p->path = path;
+    p->f = f;
+    p->exact = exact;
+    p->maxabsJ = maxabs;
+    const int Np = p->Np;
+
+    std::vector<int32_t> hpad(static_cast<size_t>(Np), 0);
+    std::copy(hi.begin(), hi.end(), hpad.begin());
+    size_t jbytes = 0;
+    std::vector<float> jf;
+    std::vector<int8_t> j8;
+    std::vector<uint16_t> jb;
+    const void* jsrc = nullptr;
+    if (path == PHIA_PATH_FP32) {
+        jf.assign(static_cast<size_t>(Np) * Np, 0.0f);
+        for (int i = 0; i < N; ++i)
+            for (int j = 0; j < N; ++j)
+                jf[static_cast<size_t>(i) * Np + j] = static_cast<float>(Ji[static_cast<size_t>(i) * N + j]);
+        jbytes = jf.size() * sizeof(float);
+        jsrc = jf.data();
+    } else if (path == PHIA_PATH_I8) {
+        pack_i8(Ji, N, Np, j8);
+        jbytes = j8.size();
+        jsrc = j8.data();
+    } else {
+        pack_bf16(Ji, N, Np, jb);
+        jbytes = jb.size() * sizeof(uint16_t);
+        jsrc = jb.data();
+    }
+    size_t* cnt = &p->base_bytes;
+    if ((e = dalloc(reinterpret_cast<void**>(&p->dJ), jbytes, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dh), sizeof(int32_t) * Np, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dJ64), sizeof(double) * N * static_cast<size_t>(N), cnt)) !=
+            hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dh64), sizeof(double) * N, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->derr), sizeof(int32_t) * 4, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dscratch), 64, cnt)) != hipSuccess) {
+        phia_destroy(p);
+        return fail(PHIA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    std::vector<double> h64(static_cast<size_t>(N), 0.0);
+    if (h) std::copy(h, h + N, h64.begin());
+    if ((e = hipMemcpy(p->dJ, jsrc, jbytes, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->dh, hpad.data(), sizeof(int32_t) * Np, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->dJ64, J, sizeof(double) * N * static_cast<size_t>(N), hipMemcpyHostToDevice)) !=
+            hipSuccess ||
+        (e = hipMemcpy(p->dh64, h64.data(), sizeof(double) * N, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemset(p->derr, 0, sizeof(int32_t) * 4)) != hipSuccess) {
+        phia_destroy(p);
+        return fail(PHIA_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    }
+    *out = p;
+    return PHIA_OK;
+}
+
+void phia_destroy(phia_problem* p)
+{
+    if (!p) return;
+    (void)hipSetDevice(p->dev);
+    if (!p->poisoned && p->st) (void)hipStreamSynchronize(p->st);
+    if (!p->poisoned && !p->st) (void)hipDeviceSynchronize();
+    free_state(p);
+    dfree(p->dJ);
+    dfree(p->dh);
+    dfree(p->dJ64);
+    dfree(p->dh64);
+    dfree(p->derr);
+    dfree(p->dscratch);
+    delete p;
+}
+
+phia_status phia_set_trace(phia_problem* p, int32_t enable)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    p->trace = enable != 0;
+    return PHIA_OK;
+}
+
+phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s,
+                              uint64_t seed)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!s) return fail(PHIA_EINVAL, "schedule is null");
+    if (replicas < 1 || replicas > (1 << 20)) return fail(PHIA_EINVAL, "replicas = %d outside [1, 2^20]", replicas);
+    if (steps < 1 || steps > (int64_t(1) << 31)) return fail(PHIA_EINVAL, "steps = %lld out of range", (long long)steps);
+    if (s->refresh_L < 1) return fail(PHIA_EINVAL, "refresh_L must be >= 1");
+    if (!std::isfinite(s->eps) || !std::isfinite(s->gamma)) return fail(PHIA_EINVAL, "eps and gamma must be finite");
+    hipError_t e = hipSetDevice(p->dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
+    e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
+    free_state(p);
+
+    // Inverse-temperature table and the kick factors c_k = (beta_k * gamma) * sigma.
+    std::vector<float> ctab(static_cast<size_t>(steps));
+    const float sigma = std::ldexp(1.0f, -p->f);
+    for (int64_t k = 0; k < steps; ++k) {
+        float b;
+        if (s->betas) {
+            b = s->betas[k];
+        } else {
+            double d = static_cast<double>(s->beta0);
+            if (steps > 1)
+                d = static_cast<double>(s->beta0) +
+                    ((static_cast<double>(s->beta1) - static_cast<double>(s->beta0)) * static_cast<double>(k)) /
+                        static_cast<double>(steps - 1);
+            b = static_cast<float>(d);
+        }
+        ctab[static_cast<size_t>(k)] = (b * s->gamma) * sigma;
+    }
+    p->R = replicas;
+    p->T = steps;
+    p->k = 0;
+    p->eps = s->eps;
+    p->gamma = s->gamma;
+    p->L = s->refresh_L;
+    p->seed = seed;
+    p->has_run = false;
+
+    const size_t RN = static_cast<size_t>(replicas) * p->Np;
+    size_t* cnt = &p->state_bytes;
+    if ((e = dalloc(reinterpret_cast<void**>(&p->dx), RN * sizeof(float), cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dv), RN * sizeof(float), cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dbestS), RN, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dbestE), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dbestStep), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dctab), sizeof(float) * steps, cnt)) != hipSuccess) {
+        free_state(p);
+        return fail(PHIA_ENOMEM, "state allocation failed: %s", hipGetErrorString(e));
+    }
+    if (p->trace) {
+        if ((e = dalloc(reinterpret_cast<void**>(&p->detrace), sizeof(int64_t) * replicas * steps, cnt)) !=
+            hipSuccess) {
+            free_state(p);
+            return fail(PHIA_ENOMEM, "trace allocation failed");
+        }
+        (void)hipMemsetAsync(p->detrace, 0, sizeof(int64_t) * replicas * steps, p->st);
+    }
+    if ((e = hipMemcpyAsync(p->dctab, ctab.data(), sizeof(float) * steps, hipMemcpyHostToDevice, p->st)) !=
+        hipSuccess) {
+        free_state(p);
+        return hip_fail(p, e, "upload of the schedule");
+    }
+    // ctab is a pageable host vector; make the copy complete before it goes out of scope.
+    if ((e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize()) != hipSuccess)
+        return hip_fail(p, e, "schedule upload");
+
+    p->geo = Geometry{};
+    if (p->path == PHIA_PATH_FP32) {
+        p->geo.ok = true;
+        p->geo.G = 1;
+        p->geo.rows = kFp32Rows;
+        p->geo.nblocks = (replicas + kFp32Rows - 1) / kFp32Rows;
+        p->geo.ngroups = p->geo.nblocks;
+    } else {
+        choose_mfma_geometry(p, replicas);
+        if (!p->geo.ok) {
+            free_state(p);
+            return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
+        }
+        if (p->geo.G > 1) {
+            const size_t esz = p->path == PHIA_PATH_I8 ? 1 : 2;
+            const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * p->Np * esz;
+            const size_t pb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * sizeof(int64_t);
+            const size_t fb = static_cast<size_t>(p->geo.ngroups) * p->geo.G * sizeof(uint32_t);
+            if ((e = dalloc(reinterpret_cast<void**>(&p->dxbuf), xb, cnt)) != hipSuccess ||
+                (e = dalloc(reinterpret_cast<void**>(&p->dpbuf), pb, cnt)) != hipSuccess ||
+                (e = dalloc(reinterpret_cast<void**>(&p->dflags), fb, cnt)) != hipSuccess) {
+                free_state(p);
+                return fail(PHIA_ENOMEM, "exchange buffer allocation failed");
+            }
+            if ((e = hipMemsetAsync(p->dflags, 0, fb, p->st)) != hipSuccess) return hip_fail(p, e, "flag reset");
+            p->seq = 0;
+        }
+    }
+    SweepArgs a = sweep_args(p);
+    if ((e = launch_init(a, p->st)) != hipSuccess) return hip_fail(p, e, "init kernel launch");
+    p->started = true;
+    return PHIA_OK;
+}
+
+phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!p->started) return fail(PHIA_ESTATE, "phia_anneal_start has not been called");
+    if (k_end < p->k || k_end > p->T) return fail(PHIA_EINVAL, "k_end = %lld outside [%lld, %lld]", (long long)k_end,
+                                                  (long long)p->k, (long long)p->T);
+    if (k_end == p->k) return PHIA_OK;
+    hipError_t e = hipSetDevice(p->dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
+    SweepArgs a = sweep_args(p);
+    a.k0 = p->k;
+    a.k1 = k_end;
+    if (p->path == PHIA_PATH_FP32) {
+        e = launch_sweep_fp32(a, p->st);
+    } else {
+        e = launch_sweep_mfma(p->path, p->geo.mt, a, p->geo.lds, p->st);
+        if (p->geo.G > 1) {
+            const int iters = (p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups;
+            p->seq += static_cast<uint32_t>(iters) * static_cast<uint32_t>(k_end - p->k + 1);
+        }
+    }
+    if (e != hipSuccess) return hip_fail(p, e, "sweep launch");
+    p->k = k_end;
+    p->has_run = true;
+    return PHIA_OK;
+}
+
+phia_status phia_sync(phia_problem* p)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    hipError_t e = hipSetDevice(p->dev);
+    if (e == hipSuccess) e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(p, e, "synchronise");
+    int32_t err = 0;
+    e = hipMemcpy(&err, p->derr, sizeof err, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(p, e, "read device error word");
+    if (err) {
+        p->poisoned = true;
+        return fail(PHIA_EDEVICE, "a workgroup-group barrier timed out (device error word %d)", err);
+    }
+    return PHIA_OK;
+}
+
+phia_status phia_anneal(phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s, uint64_t seed)
+{
+    phia_status st = phia_anneal_start(p, replicas, steps, s, seed);
+    if (st != PHIA_OK) return st;
+    st = phia_anneal_run(p, steps);
+    if (st != PHIA_OK) return st;
+    return phia_sync(p);
+}
+
+static phia_status need_results(phia_problem* p)
+{
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!p->started || !p->has_run) return fail(PHIA_ESTATE, "no anneal steps have run");
+    return phia_sync(p);
+}
+
+phia_status phia_best_exact(phia_problem* p, int64_t* energy_units, int32_t* frac_bits, int32_t* replica)
+{
+    clear_error();
+    phia_status st = need_results(p);
+    if (st != PHIA_OK) return st;
+    hipError_t e = launch_argmin(p->dbestE, p->R, p->dscratch, p->st);
+    if (e != hipSuccess) return hip_fail(p, e, "argmin launch");
+    int64_t res[2];
+    if ((e = hipMemcpyAsync(res, p->dscratch, sizeof res, hipMemcpyDeviceToHost, p->st)) != hipSuccess ||
+        (e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize()) != hipSuccess)
+        return hip_fail(p, e, "argmin readback");
+    if (energy_units) *energy_units = res[0];
+    if (frac_bits) *frac_bits = p->f;
+    if (replica) *replica = static_cast<int32_t>(res[1]);
+    p->best_r = static_cast<int32_t>(res[1]);
+    return PHIA_OK;
+}
+
+phia_status phia_best_f64(phia_problem* p, double* energy)
+{
+    clear_error();
+    if (!energy) return fail(PHIA_EINVAL, "energy is null");
+    int64_t E;
+    int32_t f, r;
+    phia_status st = phia_best_exact(p, &E, &f, &r);
+    if (st != PHIA_OK) return st;
+    double* dout = reinterpret_cast<double*>(p->dscratch) + 4;
+    hipError_t e = launch_energy_f64(p->dJ64, p->dh64, p->N, p->dbestS + static_cast<size_t>(r) * p->Np, dout, p->st);
+    if (e != hipSuccess) return hip_fail(p, e, "FP64 energy launch");
+    if ((e = hipMemcpyAsync(energy, dout, sizeof(double), hipMemcpyDeviceToHost, p->st)) != hipSuccess ||
+        (e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize()) != hipSuccess)
+        return hip_fail(p, e, "FP64 energy readback");
+    return PHIA_OK;
+}
+
+phia_status phia_best(phia_problem* p, double* energy, int8_t* spins)
+{
+    clear_error();
+    int64_t E;
+    int32_t f, r;
+    phia_status st = phia_best_exact(p, &E, &f, &r);
+    if (st != PHIA_OK) return st;
+    if (energy) {
+        if (p->exact) {
+            *energy = std::ldexp(static_cast<double>(E), -f);
+        } else {
+            st = phia_best_f64(p, energy);
+            if (st != PHIA_OK) return st;
+        }
+    }
+    if (spins) {
+        hipError_t e = hipMemcpy(spins, p->dbestS + static_cast<size_t>(r) * p->Np, static_cast<size_t>(p->N),
+                                 hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(p, e, "best spins readback");
+    }
+    return PHIA_OK;
+}
+
+phia_status phia_replica_best(phia_problem* p, int64_t* E, int8_t* S, int64_t* step)
+{
+    clear_error();
+    phia_status st = need_results(p);
+    if (st != PHIA_OK) return st;
+    hipError_t e;
+    if (E && (e = hipMemcpy(E, p->dbestE, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(p, e, "records readback");
+    if (step && (e = hipMemcpy(step, p->dbestStep, sizeof(int64_t) * p->R, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(p, e, "records readback");
+    if (S) {
+        if ((e = hipMemcpy2D(S, static_cast<size_t>(p->N), p->dbestS, static_cast<size_t>(p->Np),
+                             static_cast<size_t>(p->N), static_cast<size_t>(p->R), hipMemcpyDeviceToHost)) !=
+            hipSuccess)
+            return hip_fail(p, e, "records readback");
+    }
+    return PHIA_OK;
+}
+
+phia_status phia_get_trace(phia_problem* p, int64_t* E)
+{
+    clear_error();
+    phia_status st = need_results(p);
+    if (st != PHIA_OK) return st;
+    if (!p->detrace) return fail(PHIA_ESTATE, "tracing was not enabled before phia_anneal_start");
+    if (!E) return fail(PHIA_EINVAL, "E is null");
+    hipError_t e = hipMemcpy(E, p->detrace, sizeof(int64_t) * p->R * p->T, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(p, e, "trace readback");
+    return PHIA_OK;
+}
+
+phia_status phia_get_state(phia_problem* p, float* x, float* v, int64_t* k)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!p->started) return fail(PHIA_ESTATE, "no anneal started");
+    st = phia_sync(p);
+    if (st != PHIA_OK) return st;
+    const size_t pitch = sizeof(float) * p->Np, w = sizeof(float) * p->N;
+    hipError_t e;
+    if (x && (e = hipMemcpy2D(x, w, p->dx, pitch, w, static_cast<size_t>(p->R), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(p, e, "state readback");
+    if (v && (e = hipMemcpy2D(v, w, p->dv, pitch, w, static_cast<size_t>(p->R), hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(p, e, "state readback");
+    if (k) *k = p->k;
+    return PHIA_OK;
+}
+
+phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int64_t k)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!p->started) return fail(PHIA_ESTATE, "no anneal started");
+    if (!x || !v) return fail(PHIA_EINVAL, "x and v are required");
+    if (k < 0 || k > p->T) return fail(PHIA_EINVAL, "k outside [0, steps]");
+    st = phia_sync(p);
+    if (st != PHIA_OK) return st;
+    const size_t pitch = sizeof(float) * p->Np, w = sizeof(float) * p->N;
+    hipError_t e;
+    if ((e = hipMemcpy2D(p->dx, pitch, x, w, w, static_cast<size_t>(p->R), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy2D(p->dv, pitch, v, w, w, static_cast<size_t>(p->R), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(p, e, "state upload");
+    p->k = k;
+    return PHIA_OK;
+}
+
+phia_status phia_get_info(const phia_problem* p, phia_info* out)
+{
+    clear_error();
+    if (!p || !out) return fail(PHIA_EINVAL, "null argument");
+    out->N = p->N;
+    out->Np = p->Np;
+    out->path = p->path;
+    out->frac_bits = p->f;
+    out->exact = p->exact ? 1 : 0;
+    out->group = p->geo.G;
+    out->replicas = p->R;
+    out->rows_per_block = p->geo.rows;
+    out->steps = p->T;
+    out->step = p->k;
+    out->max_abs_J = p->maxabsJ;
+    out->device_bytes = p->base_bytes + p->state_bytes;
+    return PHIA_OK;
+}
+
+phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64, float* out, int64_t n,
+                            int32_t device)
+{
+    clear_error();
+    if (kind < 0 || kind > 4 || n < 0 || !out) return fail(PHIA_EINVAL, "bad argument");
+    if (n == 0) return PHIA_OK;
+    if (kind < 4 && !in) return fail(PHIA_EINVAL, "in is null");
+    if (kind == 4 && !in64) return fail(PHIA_EINVAL, "in64 is null");
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    const size_t nout = static_cast<size_t>(n) * (kind == 2 ? 2 : 1);
+    float *din = nullptr, *dout = nullptr;
+    uint64_t* d64 = nullptr;
+    phia_status st = PHIA_OK;
+    if ((e = hipMalloc(&dout, nout * sizeof(float))) != hipSuccess) return fail(PHIA_ENOMEM, "allocation failed");
+    if (kind < 4) {
+        if ((e = hipMalloc(&din, static_cast<size_t>(n) * sizeof(float))) != hipSuccess ||
+            (e = hipMemcpy(din, in, static_cast<size_t>(n) * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
+            st = hip_fail(nullptr, e, "fmath upload");
+    } else {
+        const size_t m = 1 + 4 * static_cast<size_t>(n);
+        if ((e = hipMalloc(&d64, m * sizeof(uint64_t))) != hipSuccess ||
+            (e = hipMemcpy(d64, in64, m * sizeof(uint64_t), hipMemcpyHostToDevice)) != hipSuccess)
+            st = hip_fail(nullptr, e, "fmath upload");
+    }
+    if (st == PHIA_OK) {
+        if ((e = launch_fmath_eval(kind, din, d64, dout, n, nullptr)) != hipSuccess ||
+            (e = hipDeviceSynchronize()) != hipSuccess ||
+            (e = hipMemcpy(out, dout, nout * sizeof(float), hipMemcpyDeviceToHost)) != hipSuccess)
+            st = hip_fail(nullptr, e, "fmath kernel");
+    }
+    dfree(din);
+    dfree(dout);
+    dfree(d64);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,248 @@
+"""Python binding of libphia.so (include/phia.h): argument marshalling only.
+
+Every step of the sweep runs in the HIP kernels of the shared library.  If
+the library is missing this module raises at import; there is no CPU
+fallback.  torch is imported first so that the process holds a single HIP
+runtime (torch's), which the library then shares; torch supplies streams and
+events for timing.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+try:  # one HIP runtime per process: load torch's before the library's
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover - torch is part of the image
+    torch = None
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libphia.so")
+
+PATHS = {"auto": 0, "fp32": 1, "i8": 2, "bf16hilo": 3}
+PATH_NAMES = {v: k for k, v in PATHS.items()}
+STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG", -4: "PHIA_ERANGE",
+          -5: "PHIA_ENOMEM", -6: "PHIA_EDEVICE", -7: "PHIA_ESTATE"}
+
+# Every symbol declared in include/phia.h.
+EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
+           "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_get_state",
+           "phia_set_state", "phia_get_info", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
+           "phia_destroy", "phia_last_error", "phia_version")
+
+
+class PhiaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Options(C.Structure):
+    _fields_ = [("frac_bits", C.c_int32), ("quantize", C.c_int32), ("path", C.c_int32),
+                ("device", C.c_int32), ("stream", C.c_void_p)]
+
+
+class Schedule(C.Structure):
+    _fields_ = [("beta0", C.c_float), ("beta1", C.c_float), ("betas", C.c_void_p),
+                ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64)]
+
+
+class Info(C.Structure):
+    _fields_ = [("N", C.c_int32), ("Np", C.c_int32), ("path", C.c_int32), ("frac_bits", C.c_int32),
+                ("exact", C.c_int32), ("group", C.c_int32), ("replicas", C.c_int32),
+                ("rows_per_block", C.c_int32), ("steps", C.c_int64), ("step", C.c_int64),
+                ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t)]
+
+
+def _declare(lib):
+    P, I32, I64, U64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+    sig = {
+        "phia_create": [P, P, I32, P, P],
+        "phia_anneal": [P, I32, I64, P, U64],
+        "phia_anneal_start": [P, I32, I64, P, U64],
+        "phia_anneal_run": [P, I64],
+        "phia_sync": [P],
+        "phia_best": [P, P, P],
+        "phia_best_exact": [P, P, P, P],
+        "phia_best_f64": [P, P],
+        "phia_replica_best": [P, P, P, P],
+        "phia_get_state": [P, P, P, P],
+        "phia_set_state": [P, P, P, I64],
+        "phia_get_info": [P, P],
+        "phia_set_trace": [P, I32],
+        "phia_get_trace": [P, P],
+        "phia_eval_fmath": [I32, P, P, P, I64, I32],
+    }
+    for name, args in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = C.c_int
+    lib.phia_destroy.argtypes = [P]
+    lib.phia_destroy.restype = None
+    lib.phia_last_error.restype = C.c_char_p
+    lib.phia_version.restype = C.c_char_p
+
+
+_lib = None
+
+
+def lib():
+    """Load libphia.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2407_10205_amd.build.build()")
+        handle = C.CDLL(LIB_PATH)
+        _declare(handle)
+        _lib = handle
+    return _lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise PhiaError(rc, lib().phia_last_error().decode(errors="replace"))
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50):
+    """Build a Schedule; keeps a reference to the betas array on the object."""
+    s = Schedule()
+    s.eps = eps
+    s.gamma = gamma
+    s.refresh_L = int(refresh_L)
+    if betas is not None:
+        b = np.ascontiguousarray(betas, dtype=np.float32)
+        if b.shape[0] < steps:
+            raise ValueError("betas shorter than steps")
+        s.betas = b.ctypes.data
+        s._keep = b
+        s.beta0 = float(b[0])
+        s.beta1 = float(b[-1])
+    else:
+        s.beta0 = beta0
+        s.beta1 = beta1
+        s.betas = None
+    return s
+
+
+class Problem:
+    """One Ising instance on the device (phia_problem)."""
+
+    def __init__(self, J, h=None, frac_bits=-1, quantize=False, path="auto", device=0, stream=None):
+        J = np.ascontiguousarray(J, dtype=np.float64)
+        if J.ndim != 2 or J.shape[0] != J.shape[1]:
+            raise ValueError("J must be square")
+        self.N = J.shape[0]
+        hh = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
+        o = Options(frac_bits, 1 if quantize else 0, PATHS[path] if isinstance(path, str) else int(path),
+                    device, C.c_void_p(stream) if stream else None)
+        p = C.c_void_p()
+        _check(lib().phia_create(_ptr(J), _ptr(hh), self.N, C.byref(o), C.byref(p)))
+        self._p = p
+        self._sched = None
+        self.R = 0
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_p", None):
+            lib().phia_destroy(self._p)
+            self._p = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- anneal
+    def set_trace(self, enable=True):
+        _check(lib().phia_set_trace(self._p, 1 if enable else 0))
+
+    def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L)
+        _check(lib().phia_anneal_start(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
+        self.R = int(replicas)
+
+    def run(self, k_end):
+        _check(lib().phia_anneal_run(self._p, int(k_end)))
+
+    def sync(self):
+        _check(lib().phia_sync(self._p))
+
+    def anneal(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L)
+        _check(lib().phia_anneal(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
+        self.R = int(replicas)
+
+    # -- results
+    def best(self):
+        e = C.c_double()
+        s = np.zeros(self.N, np.int8)
+        _check(lib().phia_best(self._p, C.byref(e), _ptr(s)))
+        return e.value, s
+
+    def best_exact(self):
+        e, f, r = C.c_int64(), C.c_int32(), C.c_int32()
+        _check(lib().phia_best_exact(self._p, C.byref(e), C.byref(f), C.byref(r)))
+        return e.value, f.value, r.value
+
+    def best_f64(self):
+        e = C.c_double()
+        _check(lib().phia_best_f64(self._p, C.byref(e)))
+        return e.value
+
+    def replica_best(self):
+        E = np.zeros(self.R, np.int64)
+        S = np.zeros((self.R, self.N), np.int8)
+        K = np.zeros(self.R, np.int64)
+        _check(lib().phia_replica_best(self._p, _ptr(E), _ptr(S), _ptr(K)))
+        return E, S, K
+
+    def trace(self, steps):
+        E = np.zeros((self.R, steps), np.int64)
+        _check(lib().phia_get_trace(self._p, _ptr(E)))
+        return E
+
+    def get_state(self):
+        x = np.zeros((self.R, self.N), np.float32)
+        v = np.zeros((self.R, self.N), np.float32)
+        k = C.c_int64()
+        _check(lib().phia_get_state(self._p, _ptr(x), _ptr(v), C.byref(k)))
+        return x, v, k.value
+
+    def set_state(self, x, v, k):
+        x = np.ascontiguousarray(x, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(lib().phia_set_state(self._p, _ptr(x), _ptr(v), int(k)))
+
+    def info(self):
+        i = Info()
+        _check(lib().phia_get_info(self._p, C.byref(i)))
+        d = {f: getattr(i, f) for f, _ in Info._fields_}
+        d["path_name"] = PATH_NAMES.get(d["path"], "?")
+        return d
+
+
+def eval_fmath(kind, values=None, quads=None, seed=0, device=0):
+    """Evaluate the device's elementary functions (self-check hook)."""
+    if kind == 4:
+        q = np.ascontiguousarray(quads, dtype=np.uint64).reshape(-1, 4)
+        n = q.shape[0]
+        in64 = np.concatenate([np.array([seed], np.uint64), q.reshape(-1)])
+        out = np.zeros(n, np.float32)
+        _check(lib().phia_eval_fmath(4, None, _ptr(in64), _ptr(out), n, device))
+        return out
+    vals = np.ascontiguousarray(values, dtype=np.float32)
+    n = vals.shape[0]
+    out = np.zeros(2 * n if kind == 2 else n, np.float32)
+    _check(lib().phia_eval_fmath(kind, _ptr(vals), None, _ptr(out), n, device))
+    return out.reshape(n, 2) if kind == 2 else out

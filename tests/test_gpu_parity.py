@@ -1,0 +1,205 @@
+"""GPU parity of the HIP sweep against the CPU oracle, through the C ABI.
+
+Every quantity is compared exactly: the sweep is a fixed sequence of IEEE
+binary32 operations and exact integer arithmetic, so x, v, spins, energies,
+records and record steps must be bit-identical (which is tighter than the
+1e-5 relative bound required of FP32 trajectories).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2407_10205_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2407_10205_amd import phia
+    phia.lib()
+    return phia
+
+
+def int_units(J, h, f):
+    return (np.rint(J * 2**f).astype(np.int32), np.rint(h * 2**f).astype(np.int32))
+
+
+def run_both(P, O, J, h, f, path, R, T, eps, gamma, b0, b1, L, seed, trace=True, sample=None):
+    """Run device and oracle on the same instance; returns (dev dict, oracle Run)."""
+    say(f"case N={J.shape[0]} R={R} T={T} path={path} f={f} seed={seed}")
+    prob = P.Problem(J, h, frac_bits=f, path=path)
+    if trace:
+        prob.set_trace(True)
+    prob.anneal(R, T, eps, gamma, beta0=b0, beta1=b1, refresh_L=L, seed=seed)
+    E, S, K = prob.replica_best()
+    x, v, k = prob.get_state()
+    dev = dict(E=E, S=S, K=K, x=x, v=v, k=k, info=prob.info(),
+               trace=prob.trace(T) if trace else None, best=prob.best(), best_exact=prob.best_exact())
+    prob.close()
+    Ji, hi = int_units(J, h, f)
+    betas = O.beta_linear(b0, b1, T)
+    rows = range(R) if sample is None else sample
+    runs = {}
+    for r in rows:
+        runs[r] = O.anneal(Ji, hi, f, 1, betas, eps, gamma, L, seed, r0=r, trace=trace, threads=1)
+    return dev, runs
+
+
+def assert_parity(dev, runs):
+    for r, o in runs.items():
+        assert np.array_equal(dev["x"][r].view(np.uint32), o.x[0].view(np.uint32)), f"x replica {r}"
+        assert np.array_equal(dev["v"][r].view(np.uint32), o.v[0].view(np.uint32)), f"v replica {r}"
+        assert dev["E"][r] == o.bestE[0], f"bestE replica {r}"
+        assert dev["K"][r] == o.bestStep[0], f"bestStep replica {r}"
+        assert np.array_equal(dev["S"][r], o.bestS[0]), f"bestS replica {r}"
+        if dev["trace"] is not None:
+            assert np.array_equal(dev["trace"][r], o.Etrace[0]), f"energy trace replica {r}"
+
+
+# ------------------------------------------------------------ fmath ----
+def test_fmath_bit_exact(P, O):
+    rs = np.random.default_rng(0)
+    ys = np.concatenate([np.linspace(-80, 0, 20001), -rs.exponential(3.0, 20000), [0.0, -81.0, -80.0]])
+    ys = ys.astype(np.float32)
+    got = P.eval_fmath(0, ys)
+    ref = np.array([O.exp_nonpos(y) for y in ys], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    us = ((2 * rs.integers(0, 2**23, 30000) + 1) / 2**24).astype(np.float32)
+    got = P.eval_fmath(1, us)
+    ref = np.array([O.ln_unit(u) for u in us], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    got = P.eval_fmath(2, us)
+    ref = np.array([O.sincos_2pi(u) for u in us], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    xs = np.concatenate([rs.normal(0, 3, 30000), [0.0, -0.0, 40.0, 41.0]]).astype(np.float32)
+    got = P.eval_fmath(3, xs)
+    ref = np.array([O.sech2(x) for x in xs], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    quads = np.stack([rs.integers(0, 2, 20000), rs.integers(0, 2**40, 20000),
+                      rs.integers(0, 2**20, 20000), rs.integers(0, 2**16, 20000)], axis=1).astype(np.uint64)
+    got = P.eval_fmath(4, quads=quads, seed=0xABCDEF)
+    ref = np.array([O.gauss(0xABCDEF, int(t), int(r), int(k), int(i)) for t, r, k, i in quads], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+
+
+# ------------------------------------------------------- small cases ----
+@pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo"])
+def test_c1_sk16_parity(P, O, path):
+    """SK N=16, J uniform +-1, h=0, 64 replicas x 1000 steps, linear beta."""
+    J, h = inst.sk_pm1(16, 0)
+    dev, runs = run_both(P, O, J, h, 0, path, 64, 1000, 0.2, 1.0, 0.1, 3.0, 50, 1234)
+    assert dev["info"]["path_name"] == path
+    assert_parity(dev, runs)
+    Eg, _ = O.bruteforce(J.astype(np.int32), h.astype(np.int32))
+    e, s = dev["best"]
+    assert e == Eg
+    assert O.energy(J.astype(np.int32), h.astype(np.int32), s) == Eg
+
+
+@pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo"])
+def test_ragged_fixed_point_parity(P, O, path):
+    """Ragged N (not a multiple of 16 or 64), ragged R, fractional couplings
+    and fields on the 2^-5 grid, momentum refresh period not dividing T."""
+    J, h = inst.sk_gauss_fixed(77, 3, frac_bits=5, bits=8)
+    dev, runs = run_both(P, O, J, h, 5, path, 37, 301, 0.15, 1.5, 0.05, 2.0, 37, 99)
+    assert_parity(dev, runs)
+
+
+def test_bf16_hilo_sixteen_bit_couplings(P, O):
+    """16-bit couplings (sigma = 2^-12): the hi plane is not zero."""
+    J, h = inst.sk_gauss_fixed(50, 8, frac_bits=12, bits=16)
+    assert np.abs(J * 4096).max() > 255
+    dev, runs = run_both(P, O, J, h, 12, "bf16hilo", 20, 200, 0.2, 1.0, 0.001, 0.02, 25, 5)
+    assert dev["info"]["path_name"] == "bf16hilo"
+    assert_parity(dev, runs)
+
+
+def test_single_spin_and_tiny(P, O):
+    J = np.zeros((1, 1))
+    h = np.array([0.75])
+    dev, runs = run_both(P, O, J, h, 2, "i8", 5, 50, 0.2, 1.0, 0.1, 3.0, 7, 3)
+    assert_parity(dev, runs)
+    J, h = inst.sk_pm1(3, 1)
+    dev, runs = run_both(P, O, J, h, 0, "fp32", 3, 20, 0.2, 1.0, 0.1, 3.0, 1, 3)
+    assert_parity(dev, runs)
+
+
+# ------------------------------------------------ resume and state ----
+@pytest.mark.parametrize("path", ["fp32", "i8"])
+def test_chunked_run_is_bit_identical(P, O, path):
+    J, h = inst.sk_gauss_fixed(40, 2, frac_bits=4)
+    a = P.Problem(J, h, path=path)
+    a.anneal(20, 400, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=30, seed=17)
+    ref = a.replica_best(), a.get_state()
+    b = P.Problem(J, h, path=path)
+    b.start(20, 400, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=30, seed=17)
+    for k in (1, 7, 100, 101, 399, 400):
+        b.run(k)
+    b.sync()
+    got = b.replica_best(), b.get_state()
+    for u, w in zip(ref[0], got[0]):
+        assert np.array_equal(u, w)
+    assert np.array_equal(ref[1][0], got[1][0]) and np.array_equal(ref[1][1], got[1][1])
+    a.close()
+    b.close()
+
+
+def test_set_state_continues_like_oracle(P, O):
+    """Explicit (x, v) at step k: the device continues exactly as the oracle."""
+    J, h = inst.sk_gauss_fixed(33, 4, frac_bits=3)
+    Ji, hi = int_units(J, h, 3)
+    T, R = 200, 6
+    p = P.Problem(J, h, path="i8")
+    p.start(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=1000, seed=1)
+    rs = np.random.default_rng(7)
+    x0 = rs.standard_normal((R, 33)).astype(np.float32)
+    v0 = rs.standard_normal((R, 33)).astype(np.float32)
+    p.set_state(x0, v0, 5)
+    p.run(T)
+    x, v, _ = p.get_state()
+    run = O.Run(33, R)
+    run.x[:] = x0
+    run.v[:] = v0
+    run.bestE[:] = np.iinfo(np.int64).max
+    run.bestStep[:] = -1
+    O.anneal(Ji, hi, 3, R, O.beta_linear(0.1, 3.0, T), 0.2, 1.0, 1000, 1, k0=5, k1=T, run=run)
+    assert np.array_equal(x, run.x) and np.array_equal(v, run.v)
+    E, S, K = p.replica_best()
+    assert np.array_equal(E, run.bestE) and np.array_equal(K, run.bestStep)
+    p.close()
+
+
+def test_best_energy_f64_against_original_couplings(P, O):
+    """Rounded input: phia_best reports the FP64 energy of the best state
+    against the original real couplings."""
+    rs = np.random.default_rng(2)
+    N = 30
+    U = rs.uniform(-1, 1, (N, N))
+    J = np.triu(U, 1) + np.triu(U, 1).T
+    h = rs.uniform(-1, 1, N)
+    p = P.Problem(J, h, frac_bits=6, quantize=True, path="i8")
+    assert p.info()["exact"] == 0
+    p.anneal(16, 300, 0.2, 1.0, beta0=0.5, beta1=20.0, refresh_L=50, seed=3)
+    e, s = p.best()
+    assert abs(e - O.energy_f64(J, h, s)) <= 1e-12 * max(1.0, abs(e))
+    p.close()
+
+
+# ------------------------------------------- workgroup-group path ----
+def test_group_split_parity_sampled(P, O):
+    """Max-cut on G(800, 0.06), int8 J too large for one CU's LDS: the
+    columns are split over a group of workgroups.  Full replica count of the
+    benchmark workload shape (1024); sampled replicas against the oracle."""
+    J, h = inst.er_maxcut(800, 0.06, 0)
+    sample = [0, 1, 31, 32, 500, 1023]
+    dev, runs = run_both(P, O, J, h, 0, "i8", 1024, 120, 0.2, 1.0, 0.02, 0.6, 40, 11, sample=sample)
+    say("geometry", dev["info"])
+    assert dev["info"]["group"] > 1
+    assert_parity(dev, runs)
