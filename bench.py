@@ -1,0 +1,194 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the PHIA sweep on one MI355X.
+
+Workload (default): max-cut on a synthetic Erdos-Renyi graph G(800, 0.06)
+with unit weights (J = -1 on edges, h = 0, int8 couplings), 1024 replicas x
+10^4 HMC steps, linear inverse-temperature schedule, int8 MFMA quasi-gradient.
+One benchmark step is one complete anneal of that workload: draw of the
+initial positions, 10^4 sweep steps over all replicas (momentum refresh,
+drift, readout, J.s + h, exact energy, records, kick), and the final argmin.
+
+Prints one JSON line: spin-updates/s over the timed steps, the sweep
+kernel's roofline position (HIP events on the library's stream), time to
+target at 99% success (Eq. 9) against the best energy of a 10x longer run,
+and the CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import math
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and unit counts (per GPU).
+CUS, CLOCK_HZ = 256, 2.4e9
+VALU_OPS_PEAK = CUS * 64 * CLOCK_HZ          # 64 FP32/INT32 lanes per CU per clock
+INT8_MFMA_PEAK = 5.0e15                      # dense int8 ops/s
+BF16_MFMA_PEAK = 2.5e15
+# Arithmetic operations of one spin-update in the sweep specification (TANH
+# mode): drift 1, readout 1, field add 1, energy term 3, kick 27 (gamma x,
+# 2|u|, e^y 17, sech^2 assembly 3 with the division counted once, c*d,
+# int->float, two fma).  The 16-column MFMA output is exactly the field.
+OPS_PER_SPIN_UPDATE = 33
+
+WORKLOADS = {
+    # name: (generator, kwargs, R, T, schedule)
+    "maxcut800": dict(gen="er_maxcut", args=dict(N=800, p=0.06, seed=0), R=1024, T=10000,
+                      sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
+                      desc="maxcut ER G(800,0.06) w=+1 (J=-1), h=0, 1024 replicas x 1e4 steps"),
+    "sk16": dict(gen="sk_pm1", args=dict(N=16, seed=0), R=64, T=1000,
+                 sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=50),
+                 desc="SK N=16 J=+-1, h=0, 64 replicas x 1000 steps"),
+    "sk2000": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=5, bits=8), R=512, T=20000,
+                   sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
+                   desc="SK N=2000 J~N(0,1) 8-bit fixed point (2^-5), h in [-1,1], 512 replicas x 2e4 steps"),
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def make_instance(w):
+    from paper_2407_10205_amd import instances as inst
+    return getattr(inst, w["gen"])(**w["args"])
+
+
+def cpu_baseline(J, h, w, budget_s):
+    """Time the oracle on a bounded replica/step sample of the workload."""
+    import numpy as np
+    from oracle import oracle as O
+    f = 0
+    while not np.all(np.rint(J * 2**f) == J * 2**f) or not np.all(np.rint(h * 2**f) == h * 2**f):
+        f += 1
+    Ji = np.rint(J * 2**f).astype(np.int32)
+    hi = np.rint(h * 2**f).astype(np.int32)
+    N, T = J.shape[0], w["T"]
+    s = w["sched"]
+    betas = O.beta_linear(s["beta0"], s["beta1"], T)
+    threads = max(1, min(16, os.cpu_count() or 1))
+    # calibrate one replica on a few steps, then size the sample to the budget
+    t = time.perf_counter()
+    O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1)
+    per_step = (time.perf_counter() - t) / 20
+    R = threads
+    steps = int(max(20, min(T, budget_s / max(per_step, 1e-9))))
+    t = time.perf_counter()
+    O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads)
+    dt = time.perf_counter() - t
+    return {"value": R * N * steps / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"replicas 0..{R - 1}, steps 0..{steps - 1} of the same schedule, "
+                      f"{dt:.1f} s on {platform.processor() or platform.machine()}"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5, help="timed complete anneals")
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="maxcut800", choices=sorted(WORKLOADS))
+    ap.add_argument("--path", default="i8", choices=["i8", "bf16hilo", "fp32", "auto"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-tts", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); replicas are independent, "
+              "so a multi-GPU run would shard them with no per-step exchange -- not built here.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2407_10205_amd import phia
+
+    w = WORKLOADS[args.workload]
+    J, h = make_instance(w)
+    N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]
+    stream = torch.cuda.Stream()
+    prob = phia.Problem(J, h, path=args.path, stream=stream.cuda_stream)
+    info = None
+
+    def one(seed, events=None):
+        prob.start(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"], refresh_L=s["refresh_L"],
+                   seed=seed)
+        if events is not None:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            prob.run(T)
+            e1.record(stream)
+            events.append((e0, e1))
+        else:
+            prob.run(T)
+        return prob.best_exact()
+
+    for i in range(args.warmup):
+        one(900 + i)
+    info = prob.info()
+    torch.cuda.synchronize()
+    events, bests = [], []
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        bests.append(one(1000 + i, events))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    E_runs = []
+    # per-replica records of the last timed run, for the success estimate
+    E_last, _, _ = prob.replica_best()
+    wall = t1 - t0
+    ms_step = 1000 * wall / args.steps
+    su = float(R) * N * T * args.steps
+    value = su / wall
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    su_launch = float(R) * N * T
+    achieved = su_launch * OPS_PER_SPIN_UPDATE / (kern_ms / 1000)
+    Np = info["Np"]
+    mfma_ops = 2.0 * Np * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
+    mfma_peak = INT8_MFMA_PEAK if info["path_name"] == "i8" else BF16_MFMA_PEAK * 0.5
+    roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_OPS_PEAK, "unit": "ops/s",
+                "frac": achieved / VALU_OPS_PEAK, "traffic": None,
+                "kernel": "k_sweep_mfma" if info["path_name"] != "fp32" else "k_sweep_fp32",
+                "kernel_ms": kern_ms, "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
+                "mfma_executed_ops_per_s": mfma_ops / (kern_ms / 1000),
+                "mfma_frac_of_peak": (mfma_ops / (kern_ms / 1000)) / mfma_peak}
+
+    extra = {}
+    if not args.no_tts:
+        # target: best energy of one run 10x longer (untimed), Eq. 9 with P per launch
+        ref = phia.Problem(J, h, path=args.path, stream=stream.cuda_stream)
+        ref.anneal(R, 10 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
+                   refresh_L=s["refresh_L"], seed=4242)
+        target = ref.best_exact()[0]
+        ref.close()
+        p_hat = float(np.mean(E_last <= target))
+        P = 1.0 - (1.0 - p_hat) ** R if p_hat > 0 else 0.0
+        t_run = ms_step / 1000
+        if P >= 0.99:
+            tts = t_run
+        elif P <= 0:
+            tts = float("inf")
+        else:
+            tts = t_run * math.log(0.01) / math.log(1.0 - P)
+        extra = {"tts99_s": tts, "target_energy": int(target), "replica_success": p_hat,
+                 "best_energy_per_run": [int(b[0]) for b in bests]}
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(J, h, w, args.cpu_seconds)
+    out = {
+        "metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i8" if info["path_name"] == "i8" else info["path_name"],
+        "data": "synthetic",
+        "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
+                   "schedule": s, "group": info["group"], "rows_per_block": info["rows_per_block"]},
+        "roofline": roofline, "cpu_baseline": cpu, **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -11,7 +11,8 @@ constexpr int kThreads = 64 * kWaves;
 constexpr int kCbw = 4;              // max 16-column blocks per wave (MFMA sweep)
 constexpr int kFp32Rows = 4;         // replicas per workgroup in the FP32 sweep
 constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
-constexpr uint32_t kSpinLimit = 1u << 21;  // bounded polls per group barrier
+constexpr uint32_t kSpinLimit = 1u << 21;  // bounded polls per exchange word
+constexpr int kGatherWords = 8;      // exchange words in flight per thread
 
 enum Path : int { kPathAuto = 0, kPathFp32 = 1, kPathI8 = 2, kPathBf16 = 3 };
 
@@ -43,10 +44,9 @@ struct SweepArgs {
     int32_t xcd_map;            // 1: group members share blockIdx % 8
     int32_t j_lds;              // 1: J slice resident in LDS, 0: read from global
     // group exchange (G > 1)
-    int8_t* xbuf;               // [2][ngroups][rows][Np] spins
-    int64_t* pbuf;              // [2][ngroups][G][rows] partial energies
-    uint32_t* flags;            // [ngroups][G] barrier sequence numbers
-    uint32_t seq_base;          // sequence number before this launch
+    uint64_t* xbits;            // [2][ngroups][rows][Np/16] (seq << 32) | 16 sign bits
+    uint64_t* pbuf;             // [2][ngroups][G][rows][2] (seq << 32) | 32-bit half of a partial energy
+    uint32_t seq_base;          // sequence number before this launch (tags start at seq_base + 1)
     int32_t* err;               // device error word (1 = barrier timeout)
 };
 

@@ -162,18 +162,38 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
         for (int c = 0; c < CPT; ++c)
 #pragma unroll
             for (int r = 0; r < RB; ++r) acc[r][c] = 0.0f;
-        for (int j = 0; j < N; ++j) {
+        // Eight rows of J in flight per thread before their multiply-adds.
+        int j = 0;
+        for (; j + 8 <= N; j += 8) {
+            float jv[8][CPT];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int i = tid + 256 * c;
+                    jv[u][c] = (i < Np) ? J[static_cast<int64_t>(j + u) * Np + i] : 0.0f;
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                float sj[RB];
+#pragma unroll
+                for (int r = 0; r < RB; ++r) sj[r] = sS[r * Np + j + u];
+#pragma unroll
+                for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                    for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv[u][c], sj[r], acc[r][c]);
+            }
+        }
+        for (; j < N; ++j) {
             float sj[RB];
 #pragma unroll
             for (int r = 0; r < RB; ++r) sj[r] = sS[r * Np + j];
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
                 const int i = tid + 256 * c;
-                if (i < Np) {
-                    const float jv = J[static_cast<int64_t>(j) * Np + i];
+                const float jv = (i < Np) ? J[static_cast<int64_t>(j) * Np + i] : 0.0f;
 #pragma unroll
-                    for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv, sj[r], acc[r][c]);
-                }
+                for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv, sj[r], acc[r][c]);
             }
         }
 
@@ -281,16 +301,32 @@ __host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_ma
     p.s_bytes = rows * (static_cast<uint32_t>(Np) * esz_of(path) + 16u);
     p.p_off = p.s_off + 2u * p.s_bytes;
     p.e_off = p.p_off + 3u * rows * 8u;
-    p.b_off = p.e_off + rows * 8u;       // [2][RB] best energies (parity buffers)
+    p.b_off = p.e_off + 2u * rows * 8u;  // [2][RB] best energies (parity buffers)
     p.k_off = p.b_off + 2u * rows * 8u;  // [RB] step of the best energy
     p.misc_off = p.k_off + rows * 8u;
     p.total = p.misc_off + 16u;
     return p;
 }
 
-__device__ __forceinline__ bool seq_reached(uint32_t f, uint32_t target)
+// Poll a tagged exchange word until its upper 32 bits equal seq.  Gives up
+// after kSpinLimit polls (or when another workgroup has already given up),
+// raising the device error word and the workgroup's abort flag; the caller
+// then leaves the sweep, so every wave of the grid terminates.
+__device__ __forceinline__ uint64_t await_tag(const uint64_t* p, uint32_t seq, int32_t* err, int* abort_flag)
 {
-    return static_cast<int32_t>(f - target) >= 0;
+    uint32_t polls = 0;
+    for (;;) {
+        const uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (static_cast<uint32_t>(w >> 32) == seq) return w;
+        ++polls;
+        if (polls > kSpinLimit ||
+            ((polls & 255u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            *abort_flag = 1;
+            return w;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
 }
 
 template <int PATH, int MT, bool GROUP>
@@ -327,7 +363,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
     const uint32_t cbb = cb_bytes(PATH, Np);
     unsigned char* sJ = lds + P.j_off;
     int64_t* sP = reinterpret_cast<int64_t*>(lds + P.p_off);   // [3][RB]
-    int64_t* sE = reinterpret_cast<int64_t*>(lds + P.e_off);   // [RB]
+    int64_t* sE = reinterpret_cast<int64_t*>(lds + P.e_off);   // [2][RB] member-summed partials
     int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);   // [2][RB]
     int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);   // [RB]
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
@@ -418,6 +454,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
                             x[mt][cw][j] = __builtin_fmaf(eps, v[mt][cw][j], x[mt][cw][j]);
+                            if (GROUP) continue;  // spins reach S through the exchange
                             const int row = mt * 16 + 4 * lg + j;
                             const bool pos = x[mt][cw][j] >= 0.0f;
                             if (ESZ == 1)
@@ -438,65 +475,105 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
             }
 
             if (GROUP) {
-                __syncthreads();
+                // Exchange through agent-coherent relaxed 64-bit atomics (sc1
+                // accesses, no L2 write-back or invalidate).  Every word carries
+                // the 32-bit sequence number of the step it belongs to, so a
+                // reader polls the data itself: one publish and one gather per
+                // step, and a stale or torn value can never be taken as current.
                 const uint32_t seq = a.seq_base + static_cast<uint32_t>(iter) * seq_stride +
                                      static_cast<uint32_t>(k - a.k0) + 1u;
+                const uint64_t tag = static_cast<uint64_t>(seq) << 32;
                 const size_t gslot = static_cast<size_t>(par) * a.ngroups + group;
-                unsigned char* X = reinterpret_cast<unsigned char*>(a.xbuf) +
-                                   gslot * RB * static_cast<size_t>(Np) * ESZ;
+                uint64_t* X = a.xbits + gslot * RB * static_cast<size_t>(a.ncb);
+                uint64_t* Pb = a.pbuf + gslot * static_cast<size_t>(G) * RB * 2;
                 if (!last) {
-                    const uint32_t own = static_cast<uint32_t>(cbs) * 16u * ESZ;  // bytes per row
-                    const uint32_t per_row = own / 16u;
-                    const uint32_t nvec = RB * per_row;
-                    for (uint32_t q = tid; q < nvec; q += kThreads) {
-                        const uint32_t row = q / per_row, cc = q - row * per_row;
-                        const uint32_t off = static_cast<uint32_t>(cb0) * 16u * ESZ + cc * 16u;
-                        *reinterpret_cast<uint4*>(X + static_cast<size_t>(row) * Np * ESZ + off) =
-                            *reinterpret_cast<const uint4*>(S + row * srow + off);
-                    }
-                }
-                if (k > a.k0 && tid < RB)
-                    a.pbuf[(gslot * G + member) * RB + tid] = sP[((k - 1) % 3) * RB + tid];
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                __syncthreads();
-                uint32_t* flags = a.flags + static_cast<size_t>(group) * G;
-                if (tid == 0) __hip_atomic_store(flags + member, seq, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                for (int m = tid; m < G; m += kThreads) {
-                    uint32_t polls = 0;
-                    while (!seq_reached(__hip_atomic_load(flags + m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
-                                        seq)) {
-                        ++polls;
-                        if (polls > kSpinLimit ||
-                            ((polls & 255u) == 0 &&
-                             __hip_atomic_load(a.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
-                            __hip_atomic_store(a.err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                            *sAbort = 1;
-                            break;
+                    // One 16-bit sign word per (replica, 16-column block); bit t
+                    // set means spin cb*16 + t is +1.
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int cw = 0; cw < kCbw; ++cw) {
+                            if (!cval[cw]) continue;  // uniform in the wave
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const uint64_t b = __ballot(x[mt][cw][j] >= 0.0f);
+                                if (lr == 0) {
+                                    const uint64_t w = (b >> (16 * lg)) & 0xffffu;
+                                    const int row = mt * 16 + 4 * lg + j;
+                                    __hip_atomic_store(X + row * a.ncb + cb0 + wave + kWaves * cw, tag | w,
+                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                                }
+                            }
                         }
-                        __builtin_amdgcn_s_sleep(1);
+                }
+                if (tid < RB) sE[par * RB + tid] = 0;  // last read two steps ago
+                __syncthreads();  // sP of step k-1 complete, sE[par] cleared
+                if (k > a.k0 && tid < RB) {
+                    const uint64_t e = static_cast<uint64_t>(sP[((k - 1) % 3) * RB + tid]);
+                    uint64_t* dst = Pb + (static_cast<size_t>(member) * RB + tid) * 2;
+                    __hip_atomic_store(dst, tag | (e & 0xffffffffu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(dst + 1, tag | (e >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                }
+                // Gather: every sign word of the block (own columns included)
+                // into S, and the members' partial energies of step k-1 into
+                // sE[par].  Each thread issues all of its loads before looking
+                // at any of them, so the gather costs one memory round trip.
+                const int nw = last ? 0 : RB * a.ncb;
+                for (int base = 0; base < nw; base += kThreads * kGatherWords) {
+                    uint64_t wv[kGatherWords];
+#pragma unroll
+                    for (int u = 0; u < kGatherWords; ++u) {
+                        const int q = base + u * kThreads + tid;
+                        wv[u] = (q < nw) ? __hip_atomic_load(X + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) : tag;
+                    }
+#pragma unroll
+                    for (int u = 0; u < kGatherWords; ++u) {
+                        const int q = base + u * kThreads + tid;
+                        if (q >= nw) continue;
+                        uint64_t w = wv[u];
+                        if (static_cast<uint32_t>(w >> 32) != seq) w = await_tag(X + q, seq, a.err, sAbort);
+                        const int row = q / a.ncb, cb = q - row * a.ncb;
+                        if (ESZ == 1) {
+                            uint32_t d[4];
+#pragma unroll
+                            for (int t = 0; t < 4; ++t) {
+                                const uint32_t n = static_cast<uint32_t>(w >> (4 * t)) & 0xfu;
+                                const uint32_t m = (n * 0x00204081u) & 0x01010101u;  // bit i -> byte i
+                                d[t] = 0xffffffffu - 0xfeu * m;                      // 0x01 or 0xff per byte
+                            }
+                            *reinterpret_cast<uint4*>(S + row * srow + cb * 16) = uint4{d[0], d[1], d[2], d[3]};
+                        } else {
+                            uint32_t d[8];
+#pragma unroll
+                            for (int t = 0; t < 8; ++t) {
+                                const uint32_t n = static_cast<uint32_t>(w >> (2 * t)) & 3u;
+                                const uint32_t m = (n & 1u) | ((n & 2u) << 15);      // bit i -> half i
+                                d[t] = 0xbf80bf80u - 0x8000u * m;                    // bf16 +1 / -1
+                            }
+                            uint4* dst = reinterpret_cast<uint4*>(S + row * srow + cb * 32);
+                            dst[0] = uint4{d[0], d[1], d[2], d[3]};
+                            dst[1] = uint4{d[4], d[5], d[6], d[7]};
+                        }
+                    }
+                }
+                if (k > a.k0) {
+                    const int np = G * RB;
+                    for (int q = tid; q < np; q += kThreads) {
+                        const uint64_t* src = Pb + static_cast<size_t>(q) * 2;
+                        uint64_t lo = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        uint64_t hi = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                        if (static_cast<uint32_t>(lo >> 32) != seq) lo = await_tag(src, seq, a.err, sAbort);
+                        if (static_cast<uint32_t>(hi >> 32) != seq) hi = await_tag(src + 1, seq, a.err, sAbort);
+                        const uint64_t e = (lo & 0xffffffffu) | ((hi & 0xffffffffu) << 32);
+                        atomicAdd(reinterpret_cast<unsigned long long*>(sE + par * RB + (q % RB)),
+                                  static_cast<unsigned long long>(e));
                     }
                 }
                 __syncthreads();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 if (*sAbort) {
                     aborted = true;
                     break;
                 }
-                if (!last) {
-                    const uint32_t per_row = static_cast<uint32_t>(Np) * ESZ / 16u;
-                    const uint32_t nvec = RB * per_row;
-                    for (uint32_t q = tid; q < nvec; q += kThreads) {
-                        const uint32_t row = q / per_row, cc = q - row * per_row;
-                        *reinterpret_cast<uint4*>(S + row * srow + cc * 16u) =
-                            *reinterpret_cast<const uint4*>(X + static_cast<size_t>(row) * Np * ESZ + cc * 16u);
-                    }
-                }
-                if (k > a.k0 && tid < RB) {
-                    int64_t t = 0;
-                    for (int m = 0; m < G; ++m) t += a.pbuf[(gslot * G + m) * RB + tid];
-                    sE[tid] = t;
-                }
-                __syncthreads();
             } else {
                 __syncthreads();
             }
@@ -506,7 +583,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
             // previous record (parity buffer par^1); lane 0 of the row group
             // in wave 0 writes the new record into buffer par.
             if (k > a.k0) {
-                const int64_t* tot = GROUP ? sE : sP + ((k - 1) % 3) * RB;
+                const int64_t* tot = GROUP ? sE + par * RB : sP + ((k - 1) % 3) * RB;
                 const int64_t* prev = sB + (par ^ 1) * RB;
                 int64_t* next = sB + par * RB;
                 const bool writer = (wave == 0 && lr == 0);

@@ -56,9 +56,8 @@ struct phia_problem {
     int8_t* dbestS = nullptr;
     int64_t* dbestStep = nullptr;
     int64_t* detrace = nullptr;
-    int8_t* dxbuf = nullptr;
-    int64_t* dpbuf = nullptr;
-    uint32_t* dflags = nullptr;
+    uint64_t* dxbits = nullptr;
+    uint64_t* dpbuf = nullptr;
     uint32_t seq = 0;
     int32_t best_r = -1;
     size_t state_bytes = 0;

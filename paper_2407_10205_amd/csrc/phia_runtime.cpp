@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -166,20 +167,26 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 }
 
 // ------------------------------------------------------- kernel geometry --
+// Geometry of the MFMA sweep: prefer J resident in LDS, 32 replicas per
+// block, and the fewest workgroups per block that fit.  PHIA_GEOMETRY="mt,G,jlds"
+// restricts the search to one candidate (tuning experiments).
 static void choose_mfma_geometry(phia_problem* p, int R)
 {
     const int Np = p->Np, ncb = Np / 16;
-    int dev_cus = 256;
-    (void)hipDeviceGetAttribute(&dev_cus, hipDeviceAttributeMultiprocessorCount, p->dev);
     const int gmin = (ncb + kWaves * kCbw - 1) / (kWaves * kCbw);
+    int f_mt = 0, f_G = 0, f_j = -1;
+    if (const char* env = std::getenv("PHIA_GEOMETRY")) std::sscanf(env, "%d,%d,%d", &f_mt, &f_G, &f_j);
     SweepArgs a{};
     a.Np = Np;
     a.ncb = ncb;
     for (int pass = 0; pass < 2; ++pass) {          // pass 0: J in LDS, pass 1: J from global
+        if (f_j >= 0 && pass != (f_j ? 0 : 1)) continue;
         for (int mt : {2, 1}) {
+            if (f_mt && mt != f_mt) continue;
             const int rows = 16 * mt;
             const int nblocks = (R + rows - 1) / rows;
             for (int G = gmin; G <= ncb; ++G) {
+                if (f_G && G != f_G) continue;
                 a.G = G;
                 a.j_lds = pass == 0;
                 const size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
@@ -203,7 +210,6 @@ static void choose_mfma_geometry(phia_problem* p, int R)
                 p->geo.xcd_map = (G > 1 && ngroups % 8 == 0) ? 1 : 0;
                 p->geo.lds = lds;
                 p->geo.ok = true;
-                (void)dev_cus;
                 return;
             }
         }
@@ -220,9 +226,8 @@ static void free_state(phia_problem* p)
     dfree(p->dbestStep);
     dfree(p->dctab);
     dfree(p->detrace);
-    dfree(p->dxbuf);
+    dfree(p->dxbits);
     dfree(p->dpbuf);
-    dfree(p->dflags);
     p->state_bytes = 0;
     p->R = 0;
     p->T = 0;
@@ -257,9 +262,8 @@ SweepArgs sweep_args(const phia_problem* p)
     a.ngroups = p->geo.ngroups;
     a.xcd_map = p->geo.xcd_map;
     a.j_lds = p->geo.j_lds;
-    a.xbuf = p->dxbuf;
+    a.xbits = p->dxbits;
     a.pbuf = p->dpbuf;
-    a.flags = p->dflags;
     a.seq_base = p->seq;
     a.err = p->derr;
     return a;
@@ -427,7 +431,10 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
     e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
-    free_state(p);
+    // Same shape as the previous anneal: keep the device buffers (the group
+    // barrier sequence continues from its last value).
+    const bool reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr);
+    if (!reuse) free_state(p);
 
     // Inverse-temperature table and the kick factors c_k = (beta_k * gamma) * sigma.
     std::vector<float> ctab(static_cast<size_t>(steps));
@@ -457,23 +464,23 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
 
     const size_t RN = static_cast<size_t>(replicas) * p->Np;
     size_t* cnt = &p->state_bytes;
-    if ((e = dalloc(reinterpret_cast<void**>(&p->dx), RN * sizeof(float), cnt)) != hipSuccess ||
+    if (!reuse && ((e = dalloc(reinterpret_cast<void**>(&p->dx), RN * sizeof(float), cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dv), RN * sizeof(float), cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dbestS), RN, cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dbestE), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dbestStep), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dctab), sizeof(float) * steps, cnt)) != hipSuccess) {
+        (e = dalloc(reinterpret_cast<void**>(&p->dctab), sizeof(float) * steps, cnt)) != hipSuccess)) {
         free_state(p);
         return fail(PHIA_ENOMEM, "state allocation failed: %s", hipGetErrorString(e));
     }
-    if (p->trace) {
+    if (p->trace && !reuse) {
         if ((e = dalloc(reinterpret_cast<void**>(&p->detrace), sizeof(int64_t) * replicas * steps, cnt)) !=
             hipSuccess) {
             free_state(p);
             return fail(PHIA_ENOMEM, "trace allocation failed");
         }
-        (void)hipMemsetAsync(p->detrace, 0, sizeof(int64_t) * replicas * steps, p->st);
     }
+    if (p->trace) (void)hipMemsetAsync(p->detrace, 0, sizeof(int64_t) * replicas * steps, p->st);
     if ((e = hipMemcpyAsync(p->dctab, ctab.data(), sizeof(float) * steps, hipMemcpyHostToDevice, p->st)) !=
         hipSuccess) {
         free_state(p);
@@ -483,6 +490,12 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     if ((e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize()) != hipSuccess)
         return hip_fail(p, e, "schedule upload");
 
+    if (reuse) {
+        SweepArgs a = sweep_args(p);
+        if ((e = launch_init(a, p->st)) != hipSuccess) return hip_fail(p, e, "init kernel launch");
+        p->started = true;
+        return PHIA_OK;
+    }
     p->geo = Geometry{};
     if (p->path == PHIA_PATH_FP32) {
         p->geo.ok = true;
@@ -497,17 +510,17 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
             return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
         }
         if (p->geo.G > 1) {
-            const size_t esz = p->path == PHIA_PATH_I8 ? 1 : 2;
-            const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * p->Np * esz;
-            const size_t pb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * sizeof(int64_t);
-            const size_t fb = static_cast<size_t>(p->geo.ngroups) * p->geo.G * sizeof(uint32_t);
-            if ((e = dalloc(reinterpret_cast<void**>(&p->dxbuf), xb, cnt)) != hipSuccess ||
-                (e = dalloc(reinterpret_cast<void**>(&p->dpbuf), pb, cnt)) != hipSuccess ||
-                (e = dalloc(reinterpret_cast<void**>(&p->dflags), fb, cnt)) != hipSuccess) {
+            // Tagged exchange words start at zero; tags start at 1.
+            const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * (p->Np / 16) * sizeof(uint64_t);
+            const size_t pb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * 2 * sizeof(uint64_t);
+            if ((e = dalloc(reinterpret_cast<void**>(&p->dxbits), xb, cnt)) != hipSuccess ||
+                (e = dalloc(reinterpret_cast<void**>(&p->dpbuf), pb, cnt)) != hipSuccess) {
                 free_state(p);
                 return fail(PHIA_ENOMEM, "exchange buffer allocation failed");
             }
-            if ((e = hipMemsetAsync(p->dflags, 0, fb, p->st)) != hipSuccess) return hip_fail(p, e, "flag reset");
+            if ((e = hipMemsetAsync(p->dxbits, 0, xb, p->st)) != hipSuccess ||
+                (e = hipMemsetAsync(p->dpbuf, 0, pb, p->st)) != hipSuccess)
+                return hip_fail(p, e, "exchange buffer reset");
             p->seq = 0;
         }
     }
