@@ -95,6 +95,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
+    ap.add_argument("--no-tune", action="store_true", help="skip the geometry autotuner")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); replicas are independent, "
@@ -111,6 +112,7 @@ def main():
     N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]
     stream = torch.cuda.Stream()
     prob = phia.Problem(J, h, path=args.path, stream=stream.cuda_stream)
+    tuned_us = prob.autotune(R, 200) if not args.no_tune else None
     info = None
 
     def one(seed, events=None):
@@ -160,6 +162,8 @@ def main():
     if not args.no_tts:
         # target: best energy of one run 10x longer (untimed), Eq. 9 with P per launch
         ref = phia.Problem(J, h, path=args.path, stream=stream.cuda_stream)
+        if not args.no_tune:
+            ref.autotune(R, 100)
         ref.anneal(R, 10 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
                    refresh_L=s["refresh_L"], seed=4242)
         target = ref.best_exact()[0]
@@ -184,7 +188,8 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "i8" if info["path_name"] == "i8" else info["path_name"],
         "data": "synthetic",
         "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
-                   "schedule": s, "group": info["group"], "rows_per_block": info["rows_per_block"]},
+                   "schedule": s, "group": info["group"], "rows_per_block": info["rows_per_block"],
+                   "j_in_lds": info["j_in_lds"], "autotune_us_per_step": tuned_us},
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }
     print(json.dumps(out), flush=True)

@@ -85,6 +85,7 @@ typedef struct {
     int32_t group;          /* workgroups that share one replica block's J (>= 1)    */
     int32_t replicas;       /* R of the current anneal (0 if none)                   */
     int32_t rows_per_block; /* replicas per workgroup block                          */
+    int32_t j_in_lds;       /* 1: each workgroup's coupling slice resides in LDS     */
     int64_t steps;          /* T of the current anneal                               */
     int64_t step;           /* next step to run                                      */
     int64_t max_abs_J;      /* max |J| in units                                      */
@@ -146,6 +147,19 @@ phia_status phia_get_state(phia_problem* p, float* x, float* v, int64_t* k);
 phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int64_t k);
 
 phia_status phia_get_info(const phia_problem* p, phia_info* out);
+
+/* Autotuner of the launch geometry of the matrix-core sweep (replicas per
+ * workgroup block, workgroups sharing one block's columns, coupling slice in
+ * LDS or streamed): every feasible geometry for `replicas` replicas runs
+ * probe_steps steps (in [10, 100000]) on this problem, timed with HIP events
+ * on its stream, and the fastest is kept for later anneals with the same
+ * replica count.  Ends any anneal in progress (state is released).  When
+ * the environment variable PHIA_TUNE_CACHE names a file, the winner is
+ * appended to it and problems of the same path, padded size and replica
+ * count created later use it without timing.  best_us: host double, time per
+ * step of the winner in microseconds, or NULL.  The FP32 path has one
+ * geometry and returns at once (best_us = 0). */
+phia_status phia_autotune(phia_problem* p, int32_t replicas, int64_t probe_steps, double* best_us);
 
 /* Record the energy of every step of the next anneal (test and diagnostic
  * hook).  Call before phia_anneal_start; costs R*steps*8 bytes of device

@@ -6,9 +6,9 @@
 
 namespace phia {
 
-constexpr int kWaves = 4;            // waves per workgroup in the MFMA sweep
+constexpr int kWaves = 8;            // waves per workgroup in the MFMA sweep
 constexpr int kThreads = 64 * kWaves;
-constexpr int kCbw = 4;              // max 16-column blocks per wave (MFMA sweep)
+constexpr int kCbw = 2;              // max 16-column blocks per wave (MFMA sweep)
 constexpr int kFp32Rows = 4;         // replicas per workgroup in the FP32 sweep
 constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
 constexpr uint32_t kSpinLimit = 1u << 21;  // bounded polls per exchange word

@@ -329,13 +329,151 @@ __device__ __forceinline__ uint64_t await_tag(const uint64_t* p, uint32_t seq, i
     }
 }
 
-template <int PATH, int MT, bool GROUP>
+// Unpack one 16-bit sign word (bit t set: spin +1) into 16 int8 or 16 bf16
+// spins of an S row.
+template <int ESZ>
+__device__ __forceinline__ void unpack_signs(uint32_t w, unsigned char* dst)
+{
+    if (ESZ == 1) {
+        uint32_t d[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const uint32_t n = (w >> (4 * t)) & 0xfu;
+            const uint32_t m = (n * 0x00204081u) & 0x01010101u;  // bit i -> byte i
+            d[t] = 0xffffffffu - 0xfeu * m;                      // 0x01 or 0xff per byte
+        }
+        *reinterpret_cast<uint4*>(dst) = uint4{d[0], d[1], d[2], d[3]};
+    } else {
+        uint32_t d[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const uint32_t n = (w >> (2 * t)) & 3u;
+            const uint32_t m = (n & 1u) | ((n & 2u) << 15);      // bit i -> half i
+            d[t] = 0xbf80bf80u - 0x8000u * m;                    // bf16 +1 / -1
+        }
+        uint4* q = reinterpret_cast<uint4*>(dst);
+        q[0] = uint4{d[0], d[1], d[2], d[3]};
+        q[1] = uint4{d[4], d[5], d[6], d[7]};
+    }
+}
+
+// Quasi-gradient of one wave: NCW column blocks (16 columns each) for the MT
+// row tiles of the block, I = S . J^T + h on matrix cores.  Jw points at the
+// wave's first column block; the next one is kWaves blocks further.  The
+// operands of k-block kb+1 are loaded while the products of kb issue.
+template <int PATH, int MT, int NCW>
+__device__ __forceinline__ void quasi_gradient(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
+                                               size_t cw_stride, int Np, int lane, int lr, int lg,
+                                               const int (&hreg)[kCbw], int (&I)[MT][kCbw][4])
+{
+    if (PATH == kPathI8) {
+        const int nkb = Np / 64;
+        v4i acc[MT][NCW];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw) acc[mt][cw] = v4i{0, 0, 0, 0};
+        v4i An[MT], Bn[NCW];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            An[mt] = *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + 16 * lg);
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) Bn[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + lane * 16);
+        for (int kb = 0; kb < nkb; ++kb) {
+            v4i A[MT], B[NCW];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) A[mt] = An[mt];
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw) B[cw] = Bn[cw];
+            if (kb + 1 < nkb) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    An[mt] = *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + (kb + 1) * 64 + 16 * lg);
+#pragma unroll
+                for (int cw = 0; cw < NCW; ++cw)
+                    Bn[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + (kb + 1) * 1024 + lane * 16);
+            }
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    acc[mt][cw] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B[cw], acc[mt][cw], 0, 0, 0);
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) I[mt][cw][j] = acc[mt][cw][j] + hreg[cw];
+    } else {
+        const int nkc = Np / 32;
+        v4f ahi[MT][NCW], alo[MT][NCW];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw) {
+                ahi[mt][cw] = v4f{0.f, 0.f, 0.f, 0.f};
+                alo[mt][cw] = v4f{0.f, 0.f, 0.f, 0.f};
+            }
+        v4i An[MT], Hn[NCW], Ln[NCW];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+            An[mt] = *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + 16 * lg);
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) {
+            Hn[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + lane * 16);
+            Ln[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + 1024 + lane * 16);
+        }
+        for (int kc = 0; kc < nkc; ++kc) {
+            v4i A[MT], H[NCW], Lo[NCW];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) A[mt] = An[mt];
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw) {
+                H[cw] = Hn[cw];
+                Lo[cw] = Ln[cw];
+            }
+            if (kc + 1 < nkc) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    An[mt] = *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + (kc + 1) * 64 + 16 * lg);
+#pragma unroll
+                for (int cw = 0; cw < NCW; ++cw) {
+                    const unsigned char* b = Jw + cw * cw_stride + static_cast<size_t>(kc + 1) * 2048 + lane * 16;
+                    Hn[cw] = *reinterpret_cast<const v4i*>(b);
+                    Ln[cw] = *reinterpret_cast<const v4i*>(b + 1024);
+                }
+            }
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw) {
+                const v8bf Bh = __builtin_bit_cast(v8bf, H[cw]);
+                const v8bf Bl = __builtin_bit_cast(v8bf, Lo[cw]);
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt) {
+                    const v8bf Am = __builtin_bit_cast(v8bf, A[mt]);
+                    ahi[mt][cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am, Bh, ahi[mt][cw], 0, 0, 0);
+                    alo[mt][cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Am, Bl, alo[mt][cw], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int cw = 0; cw < NCW; ++cw)
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    I[mt][cw][j] = 256 * static_cast<int>(ahi[mt][cw][j]) + static_cast<int>(alo[mt][cw][j]) + hreg[cw];
+    }
+}
+
+template <int PATH, int MT, bool GROUP, bool JLDS, bool TRACE>
 __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 {
     constexpr int RB = 16 * MT;
     constexpr int ESZ = (PATH == kPathI8) ? 1 : 2;
     constexpr int NE = MT * kCbw * 4;  // owned elements per lane
-    static_assert(NE <= 64, "previous-sign mask holds 64 elements");
+    static_assert(NE <= 32, "previous-sign mask holds 32 elements");
+    static_assert(kWaves * NE * 8 <= 16 * MT * 80, "ballot staging fits in one S buffer");
     extern __shared__ __align__(16) unsigned char lds[];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -358,25 +496,26 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
     const int cb1 = (member + 1) * a.ncb / G;
     const int cbs = cb1 - cb0;
     const int cbs_max = (a.ncb + G - 1) / G;
-    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, a.j_lds);
+    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, JLDS ? 1 : 0);
     const uint32_t srow = static_cast<uint32_t>(Np) * ESZ + 16u;  // S row stride, bytes
     const uint32_t cbb = cb_bytes(PATH, Np);
     unsigned char* sJ = lds + P.j_off;
-    int64_t* sP = reinterpret_cast<int64_t*>(lds + P.p_off);   // [3][RB]
+    int64_t* sP = reinterpret_cast<int64_t*>(lds + P.p_off);   // [3][RB] partial energies
     int64_t* sE = reinterpret_cast<int64_t*>(lds + P.e_off);   // [2][RB] member-summed partials
-    int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);   // [2][RB]
-    int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);   // [RB]
+    int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);   // [2][RB] best energies
+    int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);   // [RB] step of the best
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
 
     const unsigned char* Jg = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0) * cbb;
-    if (a.j_lds) {
+    if (JLDS) {
         const uint32_t nvec = static_cast<uint32_t>(cbs) * cbb / 16u;
         const uint4* src = reinterpret_cast<const uint4*>(Jg);
         uint4* dst = reinterpret_cast<uint4*>(sJ);
         for (uint32_t q = tid; q < nvec; q += kThreads) dst[q] = src[q];
     }
     if (tid == 0) *sAbort = 0;
-    const unsigned char* Jsrc = a.j_lds ? sJ : Jg;
+    // column blocks of this wave: c = wave + kWaves * cw for cw < ncw
+    const int ncw = wave < cbs ? min(kCbw, (cbs - wave + kWaves - 1) / kWaves) : 0;
 
     int col[kCbw], hreg[kCbw];
     bool cval[kCbw];
@@ -389,7 +528,10 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
     }
     const int nkb = Np / 64;
     const float eps = a.eps, gamma = a.gamma;
-    const uint32_t seq_stride = static_cast<uint32_t>(a.k1 - a.k0 + 1);
+    const int nsteps = static_cast<int>(a.k1 - a.k0);
+    const uint32_t seq_stride = static_cast<uint32_t>(nsteps + 1);
+    // first momentum refresh at or after k0
+    const int64_t ref0 = a.k0 + (a.L - a.k0 % a.L) % a.L;
     int iter = 0;
 
     for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
@@ -414,37 +556,64 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                     v[mt][cw][j] = ok ? a.v[gr * Np + col[cw]] : 0.0f;
                 }
             }
+        // Best configuration of the owned elements as sign bits (bit set:
+        // spin +1), same bit layout as pm; written back once per launch.
+        uint32_t bestbits = 0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int cw = 0; cw < kCbw; ++cw) {
+                    const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+                    if (rval[mt][j] && cval[cw] && col[cw] < N && a.bestS[gr * Np + col[cw]] > 0)
+                        bestbits |= 1u << ((mt * kCbw + cw) * 4 + j);
+                }
         for (int q = tid; q < 3 * RB; q += kThreads) sP[q] = 0;
         __syncthreads();
 
-        uint64_t pm = 0;  // signs of step k-1, bit (mt*kCbw + cw)*4 + j
+        uint32_t pm = 0;  // signs of step k-1, bit (mt*kCbw + cw)*4 + j
         bool aborted = false;
-        for (int64_t k = a.k0; k <= a.k1; ++k) {
-            const bool last = (k == a.k1);  // closing pass: records of step k1-1 only
+        int64_t next_ref = ref0;
+        uint64_t round = static_cast<uint64_t>(ref0 / a.L);
+        int r3 = static_cast<int>(a.k0 % 3);  // k mod 3
+        for (int s = 0; s <= nsteps; ++s) {
+            const int64_t k = a.k0 + s;
+            const bool last = (s == nsteps);  // closing pass: records of step k1-1 only
             const int par = static_cast<int>(k & 1);
+            const int r3p = (r3 == 0) ? 2 : r3 - 1, r3n = (r3 == 2) ? 0 : r3 + 1;
             unsigned char* S = lds + P.s_off + par * P.s_bytes;
+            pm = 0;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int cw = 0; cw < kCbw; ++cw)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (x[mt][cw][j] >= 0.0f) pm |= 1u << ((mt * kCbw + cw) * 4 + j);
             if (!last) {
-                pm = 0;
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            if (x[mt][cw][j] >= 0.0f) pm |= 1ull << ((mt * kCbw + cw) * 4 + j);
-                if (k % a.L == 0) {
-                    const uint64_t rnd = static_cast<uint64_t>(k / a.L);
+                if (k == next_ref) {
+                    // Momentum refresh: one Gaussian per owned element, drawn in
+                    // a rolled loop (one inlined generator) and moved into the
+                    // register-resident v afterwards.
+                    float vn[NE];
+#pragma unroll 1
+                    for (int e = 0; e < NE; ++e) {
+                        const int mt = e / (kCbw * 4), cw = (e >> 2) % kCbw, j = e & 3;
+                        const int c = wave + kWaves * cw;
+                        const int cl = (cb0 + c) * 16 + lr;
+                        const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+                        const bool ok = c < cbs && gr < a.R && cl < N;
+                        vn[e] = ok ? dev_gauss(a.seed, kTagV, a.r_base + gr, round, cl) : 0.0f;
+                    }
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                        for (int j = 0; j < 4; ++j)
+                        for (int cw = 0; cw < kCbw; ++cw)
 #pragma unroll
-                            for (int cw = 0; cw < kCbw; ++cw) {
-                                const bool ok = cval[cw] && rval[mt][j] && col[cw] < N;
-                                v[mt][cw][j] = ok ? gauss_v(a.seed, a.r_base + rb0 + mt * 16 + 4 * lg + j,
-                                                            rnd, col[cw])
-                                                  : 0.0f;
-                            }
+                            for (int j = 0; j < 4; ++j) v[mt][cw][j] = vn[(mt * kCbw + cw) * 4 + j];
+                    next_ref += a.L;
+                    ++round;
                 }
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
@@ -463,15 +632,6 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                                 reinterpret_cast<uint16_t*>(S + row * srow)[col[cw]] = pos ? 0x3f80 : 0xbf80;
                         }
                     }
-            } else {
-                pm = 0;
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            if (x[mt][cw][j] >= 0.0f) pm |= 1ull << ((mt * kCbw + cw) * 4 + j);
             }
 
             if (GROUP) {
@@ -479,45 +639,56 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                 // accesses, no L2 write-back or invalidate).  Every word carries
                 // the 32-bit sequence number of the step it belongs to, so a
                 // reader polls the data itself: one publish and one gather per
-                // step, and a stale or torn value can never be taken as current.
+                // step, and a stale value is never taken as current.
                 const uint32_t seq = a.seq_base + static_cast<uint32_t>(iter) * seq_stride +
-                                     static_cast<uint32_t>(k - a.k0) + 1u;
+                                     static_cast<uint32_t>(s) + 1u;
                 const uint64_t tag = static_cast<uint64_t>(seq) << 32;
                 const size_t gslot = static_cast<size_t>(par) * a.ngroups + group;
                 uint64_t* X = a.xbits + gslot * RB * static_cast<size_t>(a.ncb);
                 uint64_t* Pb = a.pbuf + gslot * static_cast<size_t>(G) * RB * 2;
                 if (!last) {
-                    // One 16-bit sign word per (replica, 16-column block); bit t
-                    // set means spin cb*16 + t is +1.
+                    // One 16-bit sign word per (replica, 16-column block): the
+                    // wave's MT*kCbw*4 ballots go through LDS so that each lane
+                    // stores one word with a single unbranched instruction.  The
+                    // staging area is the start of S[par], which the gather
+                    // below overwrites only after the next workgroup barrier.
+                    uint64_t* sW = reinterpret_cast<uint64_t*>(S) + wave * (MT * kCbw * 4);
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                        for (int cw = 0; cw < kCbw; ++cw) {
-                            if (!cval[cw]) continue;  // uniform in the wave
+                        for (int cw = 0; cw < kCbw; ++cw)
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
                                 const uint64_t b = __ballot(x[mt][cw][j] >= 0.0f);
-                                if (lr == 0) {
-                                    const uint64_t w = (b >> (16 * lg)) & 0xffffu;
-                                    const int row = mt * 16 + 4 * lg + j;
-                                    __hip_atomic_store(X + row * a.ncb + cb0 + wave + kWaves * cw, tag | w,
-                                                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                                }
+                                if (lane == 0) sW[(mt * kCbw + cw) * 4 + j] = b;
                             }
-                        }
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    // lane -> (ballot bi = lane / 4, row group g = lane % 4)
+                    constexpr int NW = MT * kCbw * 4 * 4;
+                    if (lane < NW) {
+                        const int bi = lane >> 2, g = lane & 3;
+                        const int mt = bi / (kCbw * 4), cw = (bi >> 2) % kCbw, j = bi & 3;
+                        const int c = wave + kWaves * cw;
+                        const uint64_t w = (sW[bi] >> (16 * g)) & 0xffffu;
+                        const int row = mt * 16 + 4 * g + j;
+                        if (c < cbs)
+                            __hip_atomic_store(X + row * a.ncb + cb0 + c, tag | w, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+                    }
                 }
                 if (tid < RB) sE[par * RB + tid] = 0;  // last read two steps ago
                 __syncthreads();  // sP of step k-1 complete, sE[par] cleared
-                if (k > a.k0 && tid < RB) {
-                    const uint64_t e = static_cast<uint64_t>(sP[((k - 1) % 3) * RB + tid]);
+                if (s > 0 && tid < RB) {
+                    const uint64_t e = static_cast<uint64_t>(sP[r3p * RB + tid]);
                     uint64_t* dst = Pb + (static_cast<size_t>(member) * RB + tid) * 2;
                     __hip_atomic_store(dst, tag | (e & 0xffffffffu), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                     __hip_atomic_store(dst + 1, tag | (e >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 }
-                // Gather: every sign word of the block (own columns included)
+                // Gather every sign word of the block (own columns included)
                 // into S, and the members' partial energies of step k-1 into
-                // sE[par].  Each thread issues all of its loads before looking
-                // at any of them, so the gather costs one memory round trip.
+                // sE[par].  All of a thread's loads are issued before any is
+                // inspected: one memory round trip.
                 const int nw = last ? 0 : RB * a.ncb;
                 for (int base = 0; base < nw; base += kThreads * kGatherWords) {
                     uint64_t wv[kGatherWords];
@@ -533,30 +704,10 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                         uint64_t w = wv[u];
                         if (static_cast<uint32_t>(w >> 32) != seq) w = await_tag(X + q, seq, a.err, sAbort);
                         const int row = q / a.ncb, cb = q - row * a.ncb;
-                        if (ESZ == 1) {
-                            uint32_t d[4];
-#pragma unroll
-                            for (int t = 0; t < 4; ++t) {
-                                const uint32_t n = static_cast<uint32_t>(w >> (4 * t)) & 0xfu;
-                                const uint32_t m = (n * 0x00204081u) & 0x01010101u;  // bit i -> byte i
-                                d[t] = 0xffffffffu - 0xfeu * m;                      // 0x01 or 0xff per byte
-                            }
-                            *reinterpret_cast<uint4*>(S + row * srow + cb * 16) = uint4{d[0], d[1], d[2], d[3]};
-                        } else {
-                            uint32_t d[8];
-#pragma unroll
-                            for (int t = 0; t < 8; ++t) {
-                                const uint32_t n = static_cast<uint32_t>(w >> (2 * t)) & 3u;
-                                const uint32_t m = (n & 1u) | ((n & 2u) << 15);      // bit i -> half i
-                                d[t] = 0xbf80bf80u - 0x8000u * m;                    // bf16 +1 / -1
-                            }
-                            uint4* dst = reinterpret_cast<uint4*>(S + row * srow + cb * 32);
-                            dst[0] = uint4{d[0], d[1], d[2], d[3]};
-                            dst[1] = uint4{d[4], d[5], d[6], d[7]};
-                        }
+                        unpack_signs<ESZ>(static_cast<uint32_t>(w) & 0xffffu, S + row * srow + cb * 16 * ESZ);
                     }
                 }
-                if (k > a.k0) {
+                if (s > 0) {
                     const int np = G * RB;
                     for (int q = tid; q < np; q += kThreads) {
                         const uint64_t* src = Pb + static_cast<size_t>(q) * 2;
@@ -578,12 +729,12 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                 __syncthreads();
             }
 
-            // Records of step k-1 (App. B, Table 3, state 5).
-            // Every lane holding a row takes the same decision from the
-            // previous record (parity buffer par^1); lane 0 of the row group
-            // in wave 0 writes the new record into buffer par.
-            if (k > a.k0) {
-                const int64_t* tot = GROUP ? sE + par * RB : sP + ((k - 1) % 3) * RB;
+            // Records of step k-1 (App. B, Table 3, state 5).  Every lane that
+            // holds a row takes the same decision from the previous record
+            // (parity buffer par^1); lane 0 of each row group in wave 0 writes
+            // the new record into buffer par.
+            if (s > 0) {
+                const int64_t* tot = GROUP ? sE + par * RB : sP + r3p * RB;
                 const int64_t* prev = sB + (par ^ 1) * RB;
                 int64_t* next = sB + par * RB;
                 const bool writer = (wave == 0 && lr == 0);
@@ -599,94 +750,32 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                             next[row] = imp ? E : B;
                             if (imp) sK[row] = k - 1;
                         }
-                        if (!rval[mt][j]) continue;
-                        if (a.etrace && member == 0 && writer)
+                        if (TRACE && member == 0 && writer && rval[mt][j])
                             a.etrace[(rb0 + row) * a.T + (k - 1)] = E;
-                        if (imp) {
+                        // replace this row's bits of the record by the signs of step k-1
+                        uint32_t rowmask = 0;
 #pragma unroll
-                            for (int cw = 0; cw < kCbw; ++cw)
-                                if (cval[cw] && col[cw] < N)
-                                    a.bestS[(rb0 + row) * Np + col[cw]] =
-                                        ((pm >> ((mt * kCbw + cw) * 4 + j)) & 1u) ? 1 : -1;
-                        }
+                        for (int cw = 0; cw < kCbw; ++cw) rowmask |= 1u << ((mt * kCbw + cw) * 4 + j);
+                        if (imp) bestbits = (bestbits & ~rowmask) | (pm & rowmask);
                     }
             }
             if (last) break;
-            if (tid < RB) sP[((k + 1) % 3) * RB + tid] = 0;
+            if (tid < RB) sP[r3n * RB + tid] = 0;
+            const float ck = a.ctab[k];
 
-            // Quasi-gradient on matrix cores.
-            int I[MT][kCbw][4];
-            if (PATH == kPathI8) {
-                v4i acc[MT][kCbw];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw) acc[mt][cw] = v4i{0, 0, 0, 0};
-                for (int kb = 0; kb < nkb; ++kb) {
-                    v4i A[MT];
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        A[mt] = *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + kb * 64 + 16 * lg);
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw) {
-                        if (!cval[cw]) continue;
-                        const int c = wave + kWaves * cw;
-                        const v4i B = *reinterpret_cast<const v4i*>(
-                            Jsrc + (static_cast<size_t>(c) * nkb + kb) * 1024 + lane * 16);
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt)
-                            acc[mt][cw] = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[mt], B, acc[mt][cw], 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) I[mt][cw][j] = acc[mt][cw][j] + hreg[cw];
-            } else {
-                v4f ahi[MT][kCbw], alo[MT][kCbw];
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw) {
-                        ahi[mt][cw] = v4f{0.f, 0.f, 0.f, 0.f};
-                        alo[mt][cw] = v4f{0.f, 0.f, 0.f, 0.f};
-                    }
-                const int nkc = Np / 32;
-                for (int kc = 0; kc < nkc; ++kc) {
-                    v8bf A[MT];
-#pragma unroll
-                    for (int mt = 0; mt < MT; ++mt)
-                        A[mt] = __builtin_bit_cast(
-                            v8bf, *reinterpret_cast<const v4i*>(S + (mt * 16 + lr) * srow + kc * 64 + 16 * lg));
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw) {
-                        if (!cval[cw]) continue;
-                        const int c = wave + kWaves * cw;
-                        const unsigned char* base = Jsrc + ((static_cast<size_t>(c) * nkc + kc) * 2) * 1024;
-                        const v8bf Bh = __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i*>(base + lane * 16));
-                        const v8bf Bl =
-                            __builtin_bit_cast(v8bf, *reinterpret_cast<const v4i*>(base + 1024 + lane * 16));
-#pragma unroll
-                        for (int mt = 0; mt < MT; ++mt) {
-                            ahi[mt][cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bh, ahi[mt][cw], 0, 0, 0);
-                            alo[mt][cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], Bl, alo[mt][cw], 0, 0, 0);
-                        }
-                    }
-                }
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw)
-#pragma unroll
-                        for (int j = 0; j < 4; ++j)
-                            I[mt][cw][j] = 256 * static_cast<int>(ahi[mt][cw][j]) +
-                                           static_cast<int>(alo[mt][cw][j]) + hreg[cw];
+            // Quasi-gradient on matrix cores (columns of this wave only).
+            int I[MT][kCbw][4] = {};
+            {
+                const unsigned char* Jw = (JLDS ? static_cast<const unsigned char*>(sJ) : Jg) +
+                                          static_cast<size_t>(wave) * cbb;
+                const size_t cws = static_cast<size_t>(kWaves) * cbb;
+                if (ncw >= 2)
+                    quasi_gradient<PATH, MT, (kCbw >= 2 ? 2 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+                else if (ncw == 1)
+                    quasi_gradient<PATH, MT, 1>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
             }
 
             // Partial energies of step k and the kick.
-            const float ck = a.ctab[k];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -695,15 +784,16 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 #pragma unroll
                     for (int cw = 0; cw < kCbw; ++cw) {
                         if (!cval[cw]) continue;
-                        const int s = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
-                        if (col[cw] < N) part += s * (I[mt][cw][j] + hreg[cw]);
+                        const int sg = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
+                        if (col[cw] < N) part += sg * (I[mt][cw][j] + hreg[cw]);
                         v[mt][cw][j] = kick(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j], ck, eps, gamma);
                     }
                     part = wave_sum16(part);
                     if (lr == 0)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(sP + (k % 3) * RB + mt * 16 + 4 * lg + j),
+                        atomicAdd(reinterpret_cast<unsigned long long*>(sP + r3 * RB + mt * 16 + 4 * lg + j),
                                   static_cast<unsigned long long>(static_cast<int64_t>(part)));
                 }
+            r3 = r3n;
         }
         if (aborted) return;
 
@@ -718,6 +808,8 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                     if (cval[cw]) {
                         a.x[gr * Np + col[cw]] = x[mt][cw][j];
                         a.v[gr * Np + col[cw]] = v[mt][cw][j];
+                        if (col[cw] < N)
+                            a.bestS[gr * Np + col[cw]] = ((bestbits >> ((mt * kCbw + cw) * 4 + j)) & 1u) ? 1 : -1;
                     }
             }
         __syncthreads();
@@ -740,11 +832,11 @@ size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)
     return lds_plan(path, mt, a.Np, cbs_max, a.j_lds).total;
 }
 
-template <int PATH, int MT, bool GROUP>
+template <int PATH, int MT, bool GROUP, bool JLDS, bool TRACE>
 static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
 {
     const unsigned grid = static_cast<unsigned>(GROUP ? a.ngroups * a.G : a.nblocks);
-    auto kern = k_sweep_mfma<PATH, MT, GROUP>;
+    auto kern = k_sweep_mfma<PATH, MT, GROUP, JLDS, TRACE>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -760,10 +852,24 @@ static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int PATH, int MT, bool GROUP, bool JLDS>
+static hipError_t launch_mfma_tr(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    return a.etrace ? launch_mfma_t<PATH, MT, GROUP, JLDS, true>(a, lds, st)
+                    : launch_mfma_t<PATH, MT, GROUP, JLDS, false>(a, lds, st);
+}
+
+template <int PATH, int MT, bool GROUP>
+static hipError_t launch_mfma_j(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    return a.j_lds ? launch_mfma_tr<PATH, MT, GROUP, true>(a, lds, st)
+                   : launch_mfma_tr<PATH, MT, GROUP, false>(a, lds, st);
+}
+
 template <int PATH, int MT>
 static hipError_t launch_mfma_g(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    return a.G > 1 ? launch_mfma_t<PATH, MT, true>(a, lds, st) : launch_mfma_t<PATH, MT, false>(a, lds, st);
+    return a.G > 1 ? launch_mfma_j<PATH, MT, true>(a, lds, st) : launch_mfma_j<PATH, MT, false>(a, lds, st);
 }
 
 hipError_t launch_sweep_mfma(int path, int mt, const SweepArgs& a, size_t lds, hipStream_t st)
@@ -783,13 +889,15 @@ int max_coresident_mfma(int path, int mt, size_t lds)
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    // Occupancy is set by LDS and registers; the group variants of each shape
+    // have the largest register footprint.
     const void* f = nullptr;
     if (path == kPathI8)
-        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, true>)
-                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 2, true>);
+        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, true, true, true>)
+                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 2, true, true, true>);
     else
-        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, true>)
-                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 2, true>);
+        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, true, true, true>)
+                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 2, true, true, true>);
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;

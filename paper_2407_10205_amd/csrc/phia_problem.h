@@ -62,4 +62,6 @@ struct phia_problem {
     int32_t best_r = -1;
     size_t state_bytes = 0;
     phia::Geometry geo;
+    phia::Geometry tuned;  // autotuned geometry for tuned_R replicas
+    int32_t tuned_R = 0;
 };

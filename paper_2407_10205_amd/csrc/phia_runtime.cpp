@@ -167,54 +167,130 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 }
 
 // ------------------------------------------------------- kernel geometry --
-// Geometry of the MFMA sweep: prefer J resident in LDS, 32 replicas per
-// block, and the fewest workgroups per block that fit.  PHIA_GEOMETRY="mt,G,jlds"
-// restricts the search to one candidate (tuning experiments).
-static void choose_mfma_geometry(phia_problem* p, int R)
+// ------------------------------------------------------- tuning cache --
+// One line per tuned shape: "phia-tune path Np R mt G jlds us_per_step".
+static const char* tune_cache_path() { return std::getenv("PHIA_TUNE_CACHE"); }
+
+static bool make_geometry(phia_problem* p, int R, int mt, int G, int j_lds, Geometry& g);
+
+static bool lookup_tune_cache(phia_problem* p, int R)
+{
+    const char* path = tune_cache_path();
+    if (!path) return false;
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    char tag[32];
+    int pa, np, r, mt, G, jl;
+    double us;
+    bool found = false;
+    Geometry g;
+    while (std::fscanf(f, "%31s %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &mt, &G, &jl, &us) == 8) {
+        if (std::strcmp(tag, "phia-tune") == 0 && pa == p->path && np == p->Np && r == R &&
+            make_geometry(p, R, mt, G, jl, g)) {
+            p->geo = g;
+            found = true;
+        }
+    }
+    std::fclose(f);
+    return found;
+}
+
+static void append_tune_cache(const phia_problem* p, int R, const Geometry& g, double us)
+{
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;
+    std::fprintf(f, "phia-tune %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.mt, g.G, g.j_lds, us);
+    std::fclose(f);
+}
+
+// Complete a candidate launch geometry (mt row tiles per block, G workgroups
+// per block, J slice in LDS or not) for R replicas; false if it does not fit
+// this device (LDS, columns per workgroup, co-residency of a group).
+static bool make_geometry(phia_problem* p, int R, int mt, int G, int j_lds, Geometry& g)
 {
     const int Np = p->Np, ncb = Np / 16;
-    const int gmin = (ncb + kWaves * kCbw - 1) / (kWaves * kCbw);
-    int f_mt = 0, f_G = 0, f_j = -1;
-    if (const char* env = std::getenv("PHIA_GEOMETRY")) std::sscanf(env, "%d,%d,%d", &f_mt, &f_G, &f_j);
+    if (mt < 1 || mt > 2 || G < 1 || G > ncb) return false;
+    const int cbs_max = (ncb + G - 1) / G;
+    if (cbs_max > kWaves * kCbw) return false;
     SweepArgs a{};
     a.Np = Np;
     a.ncb = ncb;
-    for (int pass = 0; pass < 2; ++pass) {          // pass 0: J in LDS, pass 1: J from global
-        if (f_j >= 0 && pass != (f_j ? 0 : 1)) continue;
-        for (int mt : {2, 1}) {
-            if (f_mt && mt != f_mt) continue;
-            const int rows = 16 * mt;
-            const int nblocks = (R + rows - 1) / rows;
-            for (int G = gmin; G <= ncb; ++G) {
-                if (f_G && G != f_G) continue;
-                a.G = G;
-                a.j_lds = pass == 0;
-                const size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
-                if (lds > static_cast<size_t>(kLdsMax)) {
-                    if (pass == 1) break;  // S alone does not fit; more columns per member won't help
-                    continue;
-                }
-                int ngroups = nblocks;
-                if (G > 1) {
-                    const int maxwg = max_coresident_mfma(p->path, mt, lds);
-                    if (maxwg < G) break;
-                    ngroups = std::min(nblocks, maxwg / G);
-                    if (ngroups >= 8) ngroups -= ngroups % 8;
-                }
-                p->geo.mt = mt;
-                p->geo.G = G;
-                p->geo.j_lds = a.j_lds;
-                p->geo.rows = rows;
-                p->geo.nblocks = nblocks;
-                p->geo.ngroups = ngroups;
-                p->geo.xcd_map = (G > 1 && ngroups % 8 == 0) ? 1 : 0;
-                p->geo.lds = lds;
-                p->geo.ok = true;
-                return;
+    a.G = G;
+    a.j_lds = j_lds;
+    const size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
+    if (lds > static_cast<size_t>(kLdsMax)) return false;
+    const int rows = 16 * mt, nblocks = (R + rows - 1) / rows;
+    int ngroups = nblocks;
+    if (G > 1) {
+        const int maxwg = max_coresident_mfma(p->path, mt, lds);
+        if (maxwg < G) return false;
+        ngroups = std::min(nblocks, maxwg / G);
+        if (ngroups >= 8) ngroups -= ngroups % 8;
+    }
+    g = Geometry{};
+    g.ok = true;
+    g.mt = mt;
+    g.G = G;
+    g.j_lds = j_lds;
+    g.rows = rows;
+    g.nblocks = nblocks;
+    g.ngroups = ngroups;
+    g.xcd_map = (G > 1 && ngroups % 8 == 0) ? 1 : 0;
+    g.lds = lds;
+    return true;
+}
+
+// Every feasible geometry for R replicas (group sizes up to 64 workgroups).
+static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
+{
+    std::vector<Geometry> out;
+    const int ncb = p->Np / 16;
+    int last_cbs = -1;
+    for (int G = 1; G <= std::min(ncb, 64); ++G) {
+        const int cbs_max = (ncb + G - 1) / G;
+        if (cbs_max == last_cbs) continue;  // same slice width as a smaller group
+        last_cbs = cbs_max;
+        for (int mt : {1, 2})
+            for (int jl : {1, 0}) {
+                Geometry g;
+                if (make_geometry(p, R, mt, G, jl, g)) out.push_back(g);
             }
+    }
+    return out;
+}
+
+// Default geometry without tuning: fewest passes over the replica blocks,
+// then the fewest owned elements per workgroup, then J in LDS.
+// PHIA_GEOMETRY="mt,G,jlds" forces one candidate (tuning experiments).
+static void choose_mfma_geometry(phia_problem* p, int R)
+{
+    p->geo.ok = false;
+    int f_mt = 0, f_G = 0, f_j = -1;
+    if (const char* env = std::getenv("PHIA_GEOMETRY")) {
+        if (std::sscanf(env, "%d,%d,%d", &f_mt, &f_G, &f_j) == 3) {
+            Geometry g;
+            if (make_geometry(p, R, f_mt, f_G, f_j, g)) p->geo = g;
+            return;
         }
     }
-    p->geo.ok = false;
+    if (p->tuned.ok && p->tuned_R == R) {
+        p->geo = p->tuned;
+        return;
+    }
+    if (lookup_tune_cache(p, R)) return;
+    double best = 0;
+    for (const Geometry& g : candidate_geometries(p, R)) {
+        const int iters = (g.nblocks + g.ngroups - 1) / g.ngroups;
+        const int cbs_max = (p->Np / 16 + g.G - 1) / g.G;
+        const double elems = static_cast<double>(g.rows) * cbs_max * 16;
+        const double cost = iters * 1e9 + elems * 2 + (g.j_lds ? 0 : 1);
+        if (!p->geo.ok || cost < best) {
+            p->geo = g;
+            best = cost;
+        }
+    }
 }
 
 static void free_state(phia_problem* p)
@@ -720,6 +796,77 @@ phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int6
     return PHIA_OK;
 }
 
+phia_status phia_autotune(phia_problem* p, int32_t replicas, int64_t probe_steps, double* best_us)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (replicas < 1 || replicas > (1 << 20)) return fail(PHIA_EINVAL, "replicas = %d outside [1, 2^20]", replicas);
+    if (probe_steps < 10 || probe_steps > 100000) return fail(PHIA_EINVAL, "probe_steps outside [10, 100000]");
+    if (best_us) *best_us = 0.0;
+    if (p->path == PHIA_PATH_FP32) return PHIA_OK;  // one launch shape only
+    std::vector<Geometry> cands = candidate_geometries(p, replicas);
+    if (cands.empty()) return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
+    // Candidates that need more passes over the replica blocks than twice
+    // the best one cannot win; skip them.
+    int min_iters = 1 << 30;
+    for (const Geometry& g : cands) min_iters = std::min(min_iters, (g.nblocks + g.ngroups - 1) / g.ngroups);
+    hipError_t e = hipSetDevice(p->dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if ((e = hipEventCreate(&e0)) != hipSuccess || (e = hipEventCreate(&e1)) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return hip_fail(p, e, "event creation");
+    }
+    const phia_schedule sched{0.1f, 3.0f, nullptr, 0.2f, 1.0f, 25};
+    const int64_t warm = 8;
+    const bool trace = p->trace;
+    p->trace = false;
+    Geometry best{};
+    double best_step_us = 0.0;
+    for (const Geometry& g : cands) {
+        if ((g.nblocks + g.ngroups - 1) / g.ngroups > 2 * min_iters) continue;
+        free_state(p);
+        p->tuned = g;
+        p->tuned_R = replicas;
+        st = phia_anneal_start(p, replicas, warm + probe_steps, &sched, 1);
+        if (st == PHIA_OK) st = phia_anneal_run(p, warm);
+        if (st != PHIA_OK) break;
+        if ((e = hipEventRecord(e0, p->st)) != hipSuccess) {
+            st = hip_fail(p, e, "event record");
+            break;
+        }
+        st = phia_anneal_run(p, warm + probe_steps);
+        if (st != PHIA_OK) break;
+        if ((e = hipEventRecord(e1, p->st)) != hipSuccess || (e = hipEventSynchronize(e1)) != hipSuccess) {
+            st = hip_fail(p, e, "event timing");
+            break;
+        }
+        st = phia_sync(p);
+        if (st != PHIA_OK) break;
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        const double us = 1000.0 * ms / static_cast<double>(probe_steps);
+        if (!best.ok || us < best_step_us) {
+            best = g;
+            best_step_us = us;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    free_state(p);
+    p->trace = trace;
+    p->started = false;
+    p->has_run = false;
+    p->tuned = best;
+    p->tuned_R = best.ok ? replicas : 0;
+    if (st != PHIA_OK) return st;
+    if (!best.ok) return fail(PHIA_ERANGE, "no geometry could be timed");
+    append_tune_cache(p, replicas, best, best_step_us);
+    if (best_us) *best_us = best_step_us;
+    return PHIA_OK;
+}
+
 phia_status phia_get_info(const phia_problem* p, phia_info* out)
 {
     clear_error();
@@ -732,6 +879,7 @@ phia_status phia_get_info(const phia_problem* p, phia_info* out)
     out->group = p->geo.G;
     out->replicas = p->R;
     out->rows_per_block = p->geo.rows;
+    out->j_in_lds = p->geo.j_lds;
     out->steps = p->T;
     out->step = p->k;
     out->max_abs_J = p->maxabsJ;

@@ -27,7 +27,7 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
 # Every symbol declared in include/phia.h.
 EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_get_state",
-           "phia_set_state", "phia_get_info", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
+           "phia_set_state", "phia_get_info", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
            "phia_destroy", "phia_last_error", "phia_version")
 
 
@@ -50,7 +50,7 @@ class Schedule(C.Structure):
 class Info(C.Structure):
     _fields_ = [("N", C.c_int32), ("Np", C.c_int32), ("path", C.c_int32), ("frac_bits", C.c_int32),
                 ("exact", C.c_int32), ("group", C.c_int32), ("replicas", C.c_int32),
-                ("rows_per_block", C.c_int32), ("steps", C.c_int64), ("step", C.c_int64),
+                ("rows_per_block", C.c_int32), ("j_in_lds", C.c_int32), ("steps", C.c_int64), ("step", C.c_int64),
                 ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t)]
 
 
@@ -69,6 +69,7 @@ def _declare(lib):
         "phia_get_state": [P, P, P, P],
         "phia_set_state": [P, P, P, I64],
         "phia_get_info": [P, P],
+        "phia_autotune": [P, I32, I64, P],
         "phia_set_trace": [P, I32],
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
@@ -223,6 +224,12 @@ class Problem:
         x = np.ascontiguousarray(x, dtype=np.float32)
         v = np.ascontiguousarray(v, dtype=np.float32)
         _check(lib().phia_set_state(self._p, _ptr(x), _ptr(v), int(k)))
+
+    def autotune(self, replicas, probe_steps=200):
+        """Time every feasible sweep geometry and keep the fastest (us/step)."""
+        us = C.c_double()
+        _check(lib().phia_autotune(self._p, int(replicas), int(probe_steps), C.byref(us)))
+        return us.value
 
     def info(self):
         i = Info()

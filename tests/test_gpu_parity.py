@@ -203,3 +203,56 @@ def test_group_split_parity_sampled(P, O):
     say("geometry", dev["info"])
     assert dev["info"]["group"] > 1
     assert_parity(dev, runs)
+
+
+def test_every_geometry_gives_identical_results(P, O):
+    """Race check across tilings: every feasible launch geometry (replicas
+    per block, workgroups per block, J in LDS or streamed) reproduces the
+    same bit-exact run, which also matches the oracle on sampled replicas."""
+    import os
+    J, h = inst.sk_gauss_fixed(300, 21, frac_bits=5, bits=8)
+    R, T = 70, 90
+    ref = None
+    ran = 0
+    Ji, hi = int_units(J, h, 5)
+    betas = O.beta_linear(0.05, 1.0, T)
+    for mt in (1, 2):
+        for G in (1, 2, 3, 5, 7, 10, 20):
+            for jl in (1, 0):
+                os.environ["PHIA_GEOMETRY"] = f"{mt},{G},{jl}"
+                try:
+                    p = P.Problem(J, h, path="i8")
+                    try:
+                        p.anneal(R, T, 0.2, 1.0, beta0=0.05, beta1=1.0, refresh_L=20, seed=8)
+                    except P.PhiaError as e:
+                        assert e.code == -4, str(e)  # geometry does not fit: skipped
+                        continue
+                    say("geometry", mt, G, jl, p.info())
+                    got = p.replica_best() + p.get_state()[:2]
+                    p.close()
+                finally:
+                    del os.environ["PHIA_GEOMETRY"]
+                ran += 1
+                if ref is None:
+                    ref = got
+                    for r in (0, 69):
+                        o = O.anneal(Ji, hi, 5, 1, betas, 0.2, 1.0, 20, 8, r0=r)
+                        assert got[0][r] == o.bestE[0] and np.array_equal(got[3][r], o.x[0])
+                else:
+                    for u, w in zip(ref, got):
+                        assert np.array_equal(u, w), (mt, G, jl)
+    assert ran >= 6
+
+
+def test_autotune_keeps_results(P, O):
+    J, h = inst.er_maxcut(400, 0.05, 2)
+    p = P.Problem(J, h, path="i8")
+    us = p.autotune(96, 40)
+    assert us > 0
+    p.anneal(96, 150, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=25, seed=4)
+    E, S, K = p.replica_best()
+    say("tuned", p.info(), us)
+    Ji, hi = int_units(J, h, 0)
+    o = O.anneal(Ji, hi, 0, 1, O.beta_linear(0.1, 3.0, 150), 0.2, 1.0, 25, 4, r0=95)
+    assert E[95] == o.bestE[0] and np.array_equal(S[95], o.bestS[0])
+    p.close()
