@@ -14,6 +14,9 @@ target at 99% success (Eq. 9) against the best energy of a 10x longer run,
 and the CPU oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import csv
+import glob
+import hashlib
 import json
 import math
 import os
@@ -49,8 +52,82 @@ WORKLOADS = {
 }
 
 
+KERNEL_SRC = os.path.join(ROOT, "paper_2407_10205_amd", "csrc", "phia_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_mfma_maxcut800_traffic.json")
+COPY_BYTES = 256 << 20  # plain device copy used to calibrate the byte counters
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_sha():
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def recorded_traffic(workload, geometry):
+    """HBM bytes per sweep launch from the committed counter summary, or None
+    when the kernel source or the launch geometry changed since it was taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload or t.get("geometry") != geometry:
+        return None
+    return t.get("bytes_per_launch")
+
+
+def calibrate_copy():
+    """A plain device copy of COPY_BYTES (reads and writes that many bytes)."""
+    import torch
+    a = torch.ones(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+
+
+def _rows(pattern):
+    out = []
+    for path in glob.glob(pattern, recursive=True):
+        with open(path, newline="") as f:
+            out.extend(csv.DictReader(f))
+    return out
+
+
+def summarize_profiles(root, workload):
+    """Turn rocprofv3 outputs under root (stats/, fetch/, write/) into the
+    traffic summary: per-dispatch FETCH_SIZE and WRITE_SIZE of the sweep
+    kernel, each scaled by the same counter on the calibration copy."""
+    stats = _rows(os.path.join(root, "stats", "**", "*kernel_stats.csv"))
+    res = {"workload": workload, "kernel_sha": kernel_sha(), "copy_bytes": COPY_BYTES}
+    sweeps = [row for row in stats if "k_sweep" in row.get("Name", "")]
+    if sweeps:
+        top = max(sweeps, key=lambda r: float(r.get("TotalDurationNs", 0)))
+        res["kernel_stats"] = {k: top[k] for k in ("Name", "Calls", "AverageNs", "MinNs", "MaxNs", "Percentage")
+                               if k in top}
+    counters = {}
+    for which in ("fetch", "write"):
+        rows = _rows(os.path.join(root, which, "**", "*counter_collection.csv"))
+        sweep, copy = [], []
+        for row in rows:
+            name = row.get("Kernel_Name", row.get("Kernel-Name", ""))
+            val = float(row.get("Counter_Value", row.get("Counter-Value", "nan")))
+            if "k_sweep" in name:
+                sweep.append(val)
+            elif "copy" in name.lower() or "elementwise" in name.lower():
+                copy.append(val)
+        if sweep and copy:
+            kib_per_byte = max(copy) / COPY_BYTES  # counter units per byte moved by the copy
+            counters[which] = {"sweep_counter_per_dispatch": sum(sweep) / len(sweep),
+                               "copy_counter_per_dispatch": max(copy),
+                               "bytes_per_launch": (sum(sweep) / len(sweep)) / kib_per_byte}
+    res["counters"] = counters
+    if "fetch" in counters and "write" in counters:
+        res["bytes_per_launch"] = counters["fetch"]["bytes_per_launch"] + counters["write"]["bytes_per_launch"]
+    return res
 
 
 def make_instance(w):
@@ -96,7 +173,20 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
     ap.add_argument("--no-tune", action="store_true", help="skip the geometry autotuner")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (byte-counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="summarise rocprofv3 outputs in DIR/{stats,fetch,write} and exit")
+    ap.add_argument("--geometry-out", metavar="FILE", help="write the launch geometry used to FILE")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        res = summarize_profiles(args.summarize_profiles, WORKLOADS[args.workload]["desc"])
+        geo = os.path.join(args.summarize_profiles, "geometry.json")
+        if os.path.exists(geo):
+            with open(geo) as f:
+                res["geometry"] = json.load(f)
+        print(json.dumps(res, indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); replicas are independent, "
               "so a multi-GPU run would shard them with no per-step exchange -- not built here.",
@@ -130,7 +220,6 @@ def main():
 
     for i in range(args.warmup):
         one(900 + i)
-    info = prob.info()
     torch.cuda.synchronize()
     events, bests = [], []
     t0 = time.perf_counter()
@@ -138,7 +227,7 @@ def main():
         bests.append(one(1000 + i, events))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    E_runs = []
+    info = prob.info()  # geometry of the timed runs
     # per-replica records of the last timed run, for the success estimate
     E_last, _, _ = prob.replica_best()
     wall = t1 - t0
@@ -151,8 +240,12 @@ def main():
     Np = info["Np"]
     mfma_ops = 2.0 * Np * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
     mfma_peak = INT8_MFMA_PEAK if info["path_name"] == "i8" else BF16_MFMA_PEAK * 0.5
+    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds")}
+    if args.geometry_out:
+        with open(args.geometry_out, "w") as f:
+            json.dump(geometry, f)
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_OPS_PEAK, "unit": "ops/s",
-                "frac": achieved / VALU_OPS_PEAK, "traffic": None,
+                "frac": achieved / VALU_OPS_PEAK, "traffic": recorded_traffic(w["desc"], geometry),
                 "kernel": "k_sweep_mfma" if info["path_name"] != "fp32" else "k_sweep_fp32",
                 "kernel_ms": kern_ms, "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
                 "mfma_executed_ops_per_s": mfma_ops / (kern_ms / 1000),
@@ -179,6 +272,8 @@ def main():
             tts = t_run * math.log(0.01) / math.log(1.0 - P)
         extra = {"tts99_s": tts, "target_energy": int(target), "replica_success": p_hat,
                  "best_energy_per_run": [int(b[0]) for b in bests]}
+    if args.calibrate_copy:
+        calibrate_copy()
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(J, h, w, args.cpu_seconds)

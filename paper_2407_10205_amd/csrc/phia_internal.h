@@ -8,7 +8,7 @@ namespace phia {
 
 constexpr int kWaves = 8;            // waves per workgroup in the MFMA sweep
 constexpr int kThreads = 64 * kWaves;
-constexpr int kCbw = 2;              // max 16-column blocks per wave (MFMA sweep)
+constexpr int kCbwMax = 2;           // max 16-column blocks per wave (MFMA sweep)
 constexpr int kFp32Rows = 4;         // replicas per workgroup in the FP32 sweep
 constexpr int kLdsMax = 160 * 1024;  // LDS bytes per workgroup on gfx950
 constexpr uint32_t kSpinLimit = 1u << 21;  // bounded polls per exchange word
@@ -60,13 +60,13 @@ struct SweepArgs {
 
 hipError_t launch_init(const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st);
-hipError_t launch_sweep_mfma(int path, int mt, const SweepArgs& a, size_t lds_bytes, hipStream_t st);
+hipError_t launch_sweep_mfma(int path, int mt, int cbw, const SweepArgs& a, size_t lds_bytes, hipStream_t st);
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a);
 hipError_t launch_argmin(const int64_t* bestE, int32_t R, int64_t* out2, hipStream_t st);
 hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const int8_t* s,
                              double* out, hipStream_t st);
 hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                              hipStream_t st);
-int max_coresident_mfma(int path, int mt, size_t lds_bytes);
+int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, size_t lds_bytes);
 
 }  // namespace phia

@@ -361,10 +361,10 @@ __device__ __forceinline__ void unpack_signs(uint32_t w, unsigned char* dst)
 // row tiles of the block, I = S . J^T + h on matrix cores.  Jw points at the
 // wave's first column block; the next one is kWaves blocks further.  The
 // operands of k-block kb+1 are loaded while the products of kb issue.
-template <int PATH, int MT, int NCW>
+template <int PATH, int MT, int CBW, int NCW>
 __device__ __forceinline__ void quasi_gradient(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
                                                size_t cw_stride, int Np, int lane, int lr, int lg,
-                                               const int (&hreg)[kCbw], int (&I)[MT][kCbw][4])
+                                               const int (&hreg)[CBW], int (&I)[MT][CBW][4])
 {
     if (PATH == kPathI8) {
         const int nkb = Np / 64;
@@ -466,12 +466,15 @@ __device__ __forceinline__ void quasi_gradient(const unsigned char* S, uint32_t 
     }
 }
 
-template <int PATH, int MT, bool GROUP, bool JLDS, bool TRACE>
-__global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
+// One column block and one row tile per wave: registers are capped at 128 so two
+// workgroups share a CU and hide each other's exchange latency.
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CBW == 1 && MT == 1 ? 4 : 2)))
+k_sweep_mfma(SweepArgs a)
 {
     constexpr int RB = 16 * MT;
     constexpr int ESZ = (PATH == kPathI8) ? 1 : 2;
-    constexpr int NE = MT * kCbw * 4;  // owned elements per lane
+    constexpr int NE = MT * CBW * 4;  // owned elements per lane
     static_assert(NE <= 32, "previous-sign mask holds 32 elements");
     static_assert(kWaves * NE * 8 <= 16 * MT * 80, "ballot staging fits in one S buffer");
     extern __shared__ __align__(16) unsigned char lds[];
@@ -515,12 +518,12 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
     }
     if (tid == 0) *sAbort = 0;
     // column blocks of this wave: c = wave + kWaves * cw for cw < ncw
-    const int ncw = wave < cbs ? min(kCbw, (cbs - wave + kWaves - 1) / kWaves) : 0;
+    const int ncw = wave < cbs ? min(CBW, (cbs - wave + kWaves - 1) / kWaves) : 0;
 
-    int col[kCbw], hreg[kCbw];
-    bool cval[kCbw];
+    int col[CBW], hreg[CBW];
+    bool cval[CBW];
 #pragma unroll
-    for (int cw = 0; cw < kCbw; ++cw) {
+    for (int cw = 0; cw < CBW; ++cw) {
         const int c = wave + kWaves * cw;
         cval[cw] = c < cbs;
         col[cw] = (cb0 + c) * 16 + lr;
@@ -536,7 +539,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 
     for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
         const int64_t rb0 = static_cast<int64_t>(blk) * RB;
-        float x[MT][kCbw][4], v[MT][kCbw][4];
+        float x[MT][CBW][4], v[MT][CBW][4];
         bool rval[MT][4];
         for (int q = tid; q < RB; q += kThreads) {
             const bool ok = rb0 + q < a.R;
@@ -550,7 +553,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                 const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
                 rval[mt][j] = gr < a.R;
 #pragma unroll
-                for (int cw = 0; cw < kCbw; ++cw) {
+                for (int cw = 0; cw < CBW; ++cw) {
                     const bool ok = rval[mt][j] && cval[cw];
                     x[mt][cw][j] = ok ? a.x[gr * Np + col[cw]] : 0.0f;
                     v[mt][cw][j] = ok ? a.v[gr * Np + col[cw]] : 0.0f;
@@ -564,15 +567,15 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 #pragma unroll
             for (int j = 0; j < 4; ++j)
 #pragma unroll
-                for (int cw = 0; cw < kCbw; ++cw) {
+                for (int cw = 0; cw < CBW; ++cw) {
                     const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
                     if (rval[mt][j] && cval[cw] && col[cw] < N && a.bestS[gr * Np + col[cw]] > 0)
-                        bestbits |= 1u << ((mt * kCbw + cw) * 4 + j);
+                        bestbits |= 1u << ((mt * CBW + cw) * 4 + j);
                 }
         for (int q = tid; q < 3 * RB; q += kThreads) sP[q] = 0;
         __syncthreads();
 
-        uint32_t pm = 0;  // signs of step k-1, bit (mt*kCbw + cw)*4 + j
+        uint32_t pm = 0;  // signs of step k-1, bit (mt*CBW + cw)*4 + j
         bool aborted = false;
         int64_t next_ref = ref0;
         uint64_t round = static_cast<uint64_t>(ref0 / a.L);
@@ -587,10 +590,10 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int cw = 0; cw < kCbw; ++cw)
+                for (int cw = 0; cw < CBW; ++cw)
 #pragma unroll
                     for (int j = 0; j < 4; ++j)
-                        if (x[mt][cw][j] >= 0.0f) pm |= 1u << ((mt * kCbw + cw) * 4 + j);
+                        if (x[mt][cw][j] >= 0.0f) pm |= 1u << ((mt * CBW + cw) * 4 + j);
             if (!last) {
                 if (k == next_ref) {
                     // Momentum refresh: one Gaussian per owned element, drawn in
@@ -599,7 +602,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                     float vn[NE];
 #pragma unroll 1
                     for (int e = 0; e < NE; ++e) {
-                        const int mt = e / (kCbw * 4), cw = (e >> 2) % kCbw, j = e & 3;
+                        const int mt = e / (CBW * 4), cw = (e >> 2) % CBW, j = e & 3;
                         const int c = wave + kWaves * cw;
                         const int cl = (cb0 + c) * 16 + lr;
                         const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
@@ -609,16 +612,16 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                        for (int cw = 0; cw < kCbw; ++cw)
+                        for (int cw = 0; cw < CBW; ++cw)
 #pragma unroll
-                            for (int j = 0; j < 4; ++j) v[mt][cw][j] = vn[(mt * kCbw + cw) * 4 + j];
+                            for (int j = 0; j < 4; ++j) v[mt][cw][j] = vn[(mt * CBW + cw) * 4 + j];
                     next_ref += a.L;
                     ++round;
                 }
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw) {
+                    for (int cw = 0; cw < CBW; ++cw) {
                         if (!cval[cw]) continue;
 #pragma unroll
                         for (int j = 0; j < 4; ++j) {
@@ -648,27 +651,27 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                 uint64_t* Pb = a.pbuf + gslot * static_cast<size_t>(G) * RB * 2;
                 if (!last) {
                     // One 16-bit sign word per (replica, 16-column block): the
-                    // wave's MT*kCbw*4 ballots go through LDS so that each lane
+                    // wave's MT*CBW*4 ballots go through LDS so that each lane
                     // stores one word with a single unbranched instruction.  The
                     // staging area is the start of S[par], which the gather
                     // below overwrites only after the next workgroup barrier.
-                    uint64_t* sW = reinterpret_cast<uint64_t*>(S) + wave * (MT * kCbw * 4);
+                    uint64_t* sW = reinterpret_cast<uint64_t*>(S) + wave * (MT * CBW * 4);
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                        for (int cw = 0; cw < kCbw; ++cw)
+                        for (int cw = 0; cw < CBW; ++cw)
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
                                 const uint64_t b = __ballot(x[mt][cw][j] >= 0.0f);
-                                if (lane == 0) sW[(mt * kCbw + cw) * 4 + j] = b;
+                                if (lane == 0) sW[(mt * CBW + cw) * 4 + j] = b;
                             }
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     // lane -> (ballot bi = lane / 4, row group g = lane % 4)
-                    constexpr int NW = MT * kCbw * 4 * 4;
+                    constexpr int NW = MT * CBW * 4 * 4;
                     if (lane < NW) {
                         const int bi = lane >> 2, g = lane & 3;
-                        const int mt = bi / (kCbw * 4), cw = (bi >> 2) % kCbw, j = bi & 3;
+                        const int mt = bi / (CBW * 4), cw = (bi >> 2) % CBW, j = bi & 3;
                         const int c = wave + kWaves * cw;
                         const uint64_t w = (sW[bi] >> (16 * g)) & 0xffffu;
                         const int row = mt * 16 + 4 * g + j;
@@ -755,7 +758,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                         // replace this row's bits of the record by the signs of step k-1
                         uint32_t rowmask = 0;
 #pragma unroll
-                        for (int cw = 0; cw < kCbw; ++cw) rowmask |= 1u << ((mt * kCbw + cw) * 4 + j);
+                        for (int cw = 0; cw < CBW; ++cw) rowmask |= 1u << ((mt * CBW + cw) * 4 + j);
                         if (imp) bestbits = (bestbits & ~rowmask) | (pm & rowmask);
                     }
             }
@@ -764,15 +767,15 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
             const float ck = a.ctab[k];
 
             // Quasi-gradient on matrix cores (columns of this wave only).
-            int I[MT][kCbw][4] = {};
+            int I[MT][CBW][4] = {};
             {
                 const unsigned char* Jw = (JLDS ? static_cast<const unsigned char*>(sJ) : Jg) +
                                           static_cast<size_t>(wave) * cbb;
                 const size_t cws = static_cast<size_t>(kWaves) * cbb;
                 if (ncw >= 2)
-                    quasi_gradient<PATH, MT, (kCbw >= 2 ? 2 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+                    quasi_gradient<PATH, MT, CBW, (CBW >= 2 ? 2 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
                 else if (ncw == 1)
-                    quasi_gradient<PATH, MT, 1>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+                    quasi_gradient<PATH, MT, CBW, 1>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
             }
 
             // Partial energies of step k and the kick.
@@ -782,7 +785,7 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                 for (int j = 0; j < 4; ++j) {
                     int part = 0;
 #pragma unroll
-                    for (int cw = 0; cw < kCbw; ++cw) {
+                    for (int cw = 0; cw < CBW; ++cw) {
                         if (!cval[cw]) continue;
                         const int sg = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
                         if (col[cw] < N) part += sg * (I[mt][cw][j] + hreg[cw]);
@@ -804,12 +807,12 @@ __global__ void __launch_bounds__(kThreads, 1) k_sweep_mfma(SweepArgs a)
                 if (!rval[mt][j]) continue;
                 const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
 #pragma unroll
-                for (int cw = 0; cw < kCbw; ++cw)
+                for (int cw = 0; cw < CBW; ++cw)
                     if (cval[cw]) {
                         a.x[gr * Np + col[cw]] = x[mt][cw][j];
                         a.v[gr * Np + col[cw]] = v[mt][cw][j];
                         if (col[cw] < N)
-                            a.bestS[gr * Np + col[cw]] = ((bestbits >> ((mt * kCbw + cw) * 4 + j)) & 1u) ? 1 : -1;
+                            a.bestS[gr * Np + col[cw]] = ((bestbits >> ((mt * CBW + cw) * 4 + j)) & 1u) ? 1 : -1;
                     }
             }
         __syncthreads();
@@ -832,11 +835,11 @@ size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)
     return lds_plan(path, mt, a.Np, cbs_max, a.j_lds).total;
 }
 
-template <int PATH, int MT, bool GROUP, bool JLDS, bool TRACE>
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE>
 static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
 {
     const unsigned grid = static_cast<unsigned>(GROUP ? a.ngroups * a.G : a.nblocks);
-    auto kern = k_sweep_mfma<PATH, MT, GROUP, JLDS, TRACE>;
+    auto kern = k_sweep_mfma<PATH, MT, CBW, GROUP, JLDS, TRACE>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -852,52 +855,69 @@ static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int PATH, int MT, bool GROUP, bool JLDS>
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS>
 static hipError_t launch_mfma_tr(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    return a.etrace ? launch_mfma_t<PATH, MT, GROUP, JLDS, true>(a, lds, st)
-                    : launch_mfma_t<PATH, MT, GROUP, JLDS, false>(a, lds, st);
+    return a.etrace ? launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, true>(a, lds, st)
+                    : launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, false>(a, lds, st);
 }
 
-template <int PATH, int MT, bool GROUP>
+template <int PATH, int MT, int CBW, bool GROUP>
 static hipError_t launch_mfma_j(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    return a.j_lds ? launch_mfma_tr<PATH, MT, GROUP, true>(a, lds, st)
-                   : launch_mfma_tr<PATH, MT, GROUP, false>(a, lds, st);
+    return a.j_lds ? launch_mfma_tr<PATH, MT, CBW, GROUP, true>(a, lds, st)
+                   : launch_mfma_tr<PATH, MT, CBW, GROUP, false>(a, lds, st);
 }
 
-template <int PATH, int MT>
+template <int PATH, int MT, int CBW>
 static hipError_t launch_mfma_g(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    return a.G > 1 ? launch_mfma_j<PATH, MT, true>(a, lds, st) : launch_mfma_j<PATH, MT, false>(a, lds, st);
+    return a.G > 1 ? launch_mfma_j<PATH, MT, CBW, true>(a, lds, st) : launch_mfma_j<PATH, MT, CBW, false>(a, lds, st);
 }
 
-hipError_t launch_sweep_mfma(int path, int mt, const SweepArgs& a, size_t lds, hipStream_t st)
+template <int PATH>
+static hipError_t launch_mfma_p(int mt, int cbw, const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    if (path == kPathI8) {
-        if (mt == 1) return launch_mfma_g<kPathI8, 1>(a, lds, st);
-        if (mt == 2) return launch_mfma_g<kPathI8, 2>(a, lds, st);
-    } else if (path == kPathBf16) {
-        if (mt == 1) return launch_mfma_g<kPathBf16, 1>(a, lds, st);
-        if (mt == 2) return launch_mfma_g<kPathBf16, 2>(a, lds, st);
-    }
+    if (mt == 1 && cbw == 1) return launch_mfma_g<PATH, 1, 1>(a, lds, st);
+    if (mt == 1 && cbw == 2) return launch_mfma_g<PATH, 1, 2>(a, lds, st);
+    if (mt == 2 && cbw == 1) return launch_mfma_g<PATH, 2, 1>(a, lds, st);
+    if (mt == 2 && cbw == 2) return launch_mfma_g<PATH, 2, 2>(a, lds, st);
     return hipErrorInvalidValue;
 }
 
-int max_coresident_mfma(int path, int mt, size_t lds)
+hipError_t launch_sweep_mfma(int path, int mt, int cbw, const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    if (path == kPathI8) return launch_mfma_p<kPathI8>(mt, cbw, a, lds, st);
+    if (path == kPathBf16) return launch_mfma_p<kPathBf16>(mt, cbw, a, lds, st);
+    return hipErrorInvalidValue;
+}
+
+template <int PATH, int MT, int CBW>
+static const void* group_kernel(int jlds, int trace)
+{
+    if (jlds)
+        return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, true, true>)
+                     : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, true, false>);
+    return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, true>)
+                 : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false>);
+}
+
+template <int PATH>
+static const void* group_kernel_p(int mt, int cbw, int jlds, int trace)
+{
+    return mt == 1 ? (cbw == 1 ? group_kernel<PATH, 1, 1>(jlds, trace) : group_kernel<PATH, 1, 2>(jlds, trace))
+                   : (cbw == 1 ? group_kernel<PATH, 2, 1>(jlds, trace) : group_kernel<PATH, 2, 2>(jlds, trace));
+}
+
+// Workgroups of the group sweep variant (mt, cbw, jlds, trace) that can be
+// resident on the device at once.
+int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, size_t lds)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    // Occupancy is set by LDS and registers; the group variants of each shape
-    // have the largest register footprint.
-    const void* f = nullptr;
-    if (path == kPathI8)
-        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, true, true, true>)
-                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 2, true, true, true>);
-    else
-        f = mt == 1 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, true, true, true>)
-                    : reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 2, true, true, true>);
+    const void* f = path == kPathI8 ? group_kernel_p<kPathI8>(mt, cbw, jlds, trace)
+                                    : group_kernel_p<kPathBf16>(mt, cbw, jlds, trace);
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;

@@ -13,6 +13,7 @@ namespace phia {
 struct Geometry {
     bool ok = false;
     int mt = 1;        // 16-replica row tiles per workgroup
+    int cbw = 2;       // max 16-column blocks per wave
     int G = 1;         // workgroups splitting the columns of one replica block
     int j_lds = 1;     // J slice resident in LDS
     int rows = 16;     // replicas per block

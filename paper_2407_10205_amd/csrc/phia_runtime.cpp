@@ -168,10 +168,10 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 
 // ------------------------------------------------------- kernel geometry --
 // ------------------------------------------------------- tuning cache --
-// One line per tuned shape: "phia-tune path Np R mt G jlds us_per_step".
+// One line per tuned shape: "phia-tune2 path Np R mt cbw G jlds us_per_step".
 static const char* tune_cache_path() { return std::getenv("PHIA_TUNE_CACHE"); }
 
-static bool make_geometry(phia_problem* p, int R, int mt, int G, int j_lds, Geometry& g);
+static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g);
 
 static bool lookup_tune_cache(phia_problem* p, int R)
 {
@@ -180,13 +180,13 @@ static bool lookup_tune_cache(phia_problem* p, int R)
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char tag[32];
-    int pa, np, r, mt, G, jl;
+    int pa, np, r, mt, cbw, G, jl;
     double us;
     bool found = false;
     Geometry g;
-    while (std::fscanf(f, "%31s %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &mt, &G, &jl, &us) == 8) {
-        if (std::strcmp(tag, "phia-tune") == 0 && pa == p->path && np == p->Np && r == R &&
-            make_geometry(p, R, mt, G, jl, g)) {
+    while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &mt, &cbw, &G, &jl, &us) == 9) {
+        if (std::strcmp(tag, "phia-tune2") == 0 && pa == p->path && np == p->Np && r == R &&
+            make_geometry(p, R, mt, cbw, G, jl, g)) {
             p->geo = g;
             found = true;
         }
@@ -201,19 +201,19 @@ static void append_tune_cache(const phia_problem* p, int R, const Geometry& g, d
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "phia-tune %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.mt, g.G, g.j_lds, us);
+    std::fprintf(f, "phia-tune2 %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.mt, g.cbw, g.G, g.j_lds, us);
     std::fclose(f);
 }
 
 // Complete a candidate launch geometry (mt row tiles per block, G workgroups
 // per block, J slice in LDS or not) for R replicas; false if it does not fit
 // this device (LDS, columns per workgroup, co-residency of a group).
-static bool make_geometry(phia_problem* p, int R, int mt, int G, int j_lds, Geometry& g)
+static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g)
 {
     const int Np = p->Np, ncb = Np / 16;
-    if (mt < 1 || mt > 2 || G < 1 || G > ncb) return false;
+    if (mt < 1 || mt > 2 || cbw < 1 || cbw > kCbwMax || G < 1 || G > ncb) return false;
     const int cbs_max = (ncb + G - 1) / G;
-    if (cbs_max > kWaves * kCbw) return false;
+    if (cbs_max > kWaves * cbw) return false;
     SweepArgs a{};
     a.Np = Np;
     a.ncb = ncb;
@@ -224,7 +224,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int G, int j_lds, Geom
     const int rows = 16 * mt, nblocks = (R + rows - 1) / rows;
     int ngroups = nblocks;
     if (G > 1) {
-        const int maxwg = max_coresident_mfma(p->path, mt, lds);
+        const int maxwg = max_coresident_mfma(p->path, mt, cbw, j_lds, p->trace ? 1 : 0, lds);
         if (maxwg < G) return false;
         ngroups = std::min(nblocks, maxwg / G);
         if (ngroups >= 8) ngroups -= ngroups % 8;
@@ -232,6 +232,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int G, int j_lds, Geom
     g = Geometry{};
     g.ok = true;
     g.mt = mt;
+    g.cbw = cbw;
     g.G = G;
     g.j_lds = j_lds;
     g.rows = rows;
@@ -253,10 +254,11 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
         if (cbs_max == last_cbs) continue;  // same slice width as a smaller group
         last_cbs = cbs_max;
         for (int mt : {1, 2})
-            for (int jl : {1, 0}) {
-                Geometry g;
-                if (make_geometry(p, R, mt, G, jl, g)) out.push_back(g);
-            }
+            for (int cbw = 1; cbw <= kCbwMax; ++cbw)
+                for (int jl : {1, 0}) {
+                    Geometry g;
+                    if (make_geometry(p, R, mt, cbw, G, jl, g)) out.push_back(g);
+                }
     }
     return out;
 }
@@ -267,11 +269,11 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
 static void choose_mfma_geometry(phia_problem* p, int R)
 {
     p->geo.ok = false;
-    int f_mt = 0, f_G = 0, f_j = -1;
+    int f_mt = 0, f_G = 0, f_j = -1, f_c = kCbwMax;
     if (const char* env = std::getenv("PHIA_GEOMETRY")) {
-        if (std::sscanf(env, "%d,%d,%d", &f_mt, &f_G, &f_j) == 3) {
+        if (std::sscanf(env, "%d,%d,%d,%d", &f_mt, &f_G, &f_j, &f_c) >= 3) {
             Geometry g;
-            if (make_geometry(p, R, f_mt, f_G, f_j, g)) p->geo = g;
+            if (make_geometry(p, R, f_mt, f_c, f_G, f_j, g)) p->geo = g;
             return;
         }
     }
@@ -623,7 +625,7 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
     if (p->path == PHIA_PATH_FP32) {
         e = launch_sweep_fp32(a, p->st);
     } else {
-        e = launch_sweep_mfma(p->path, p->geo.mt, a, p->geo.lds, p->st);
+        e = launch_sweep_mfma(p->path, p->geo.mt, p->geo.cbw, a, p->geo.lds, p->st);
         if (p->geo.G > 1) {
             const int iters = (p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups;
             p->seq += static_cast<uint32_t>(iters) * static_cast<uint32_t>(k_end - p->k + 1);
@@ -860,6 +862,7 @@ phia_status phia_autotune(phia_problem* p, int32_t replicas, int64_t probe_steps
     p->has_run = false;
     p->tuned = best;
     p->tuned_R = best.ok ? replicas : 0;
+    p->geo = best;
     if (st != PHIA_OK) return st;
     if (!best.ok) return fail(PHIA_ERANGE, "no geometry could be timed");
     append_tune_cache(p, replicas, best, best_step_us);
