@@ -46,6 +46,10 @@ WORKLOADS = {
     "sk16": dict(gen="sk_pm1", args=dict(N=16, seed=0), R=64, T=1000,
                  sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=50),
                  desc="SK N=16 J=+-1, h=0, 64 replicas x 1000 steps"),
+    "batch4096": dict(gen="batch", args=dict(count=4096, nmin=32, nmax=512, seed=0), R=32, T=5000,
+                      sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
+                      desc="batch of 4096 instances, N uniform in [32,512], even ids SK +-1 (h=0), odd ids random "
+                           "3-regular +-1 with h in {-1,0,1}; 32 replicas x 5000 steps each, one graph launch"),
     "sk2000": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=5, bits=8), R=512, T=20000,
                    sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
                    desc="SK N=2000 J~N(0,1) 8-bit fixed point (2^-5), h in [-1,1], 512 replicas x 2e4 steps"),
@@ -135,6 +139,64 @@ def make_instance(w):
     return getattr(inst, w["gen"])(**w["args"])
 
 
+def make_batch(count, nmin, nmax, seed):
+    """Instances of the batch workload (sizes drawn from one seeded stream)."""
+    import numpy as np
+    from paper_2407_10205_amd import instances as inst
+    g = inst.rng(seed)
+    sizes = g.integers(nmin, nmax + 1, size=count)
+    out = []
+    for i, n in enumerate(sizes):
+        n = int(n)
+        if i % 2 == 0:
+            out.append(inst.sk_pm1(n, 10_000 + i))
+        else:
+            out.append(inst.regular3_pm1(n + (n % 2), 10_000 + i))
+    return out
+
+
+def run_batch_bench(args, w):
+    """Throughput of the batched sweep: one step = the whole batch."""
+    import numpy as np
+    import torch
+    from paper_2407_10205_amd import phia
+    t = time.perf_counter()
+    insts = make_batch(**w["args"])
+    log(f"generated {len(insts)} instances in {time.perf_counter() - t:.1f} s")
+    stream = torch.cuda.Stream()
+    probs = [phia.Problem(J, h, path="i8", stream=stream.cuda_stream) for J, h in insts]
+    n = len(probs)
+    R, T, s = w["R"], w["T"], w["sched"]
+    reps, steps = [R] * n, [T] * n
+    scheds = [s] * n
+    su = float(sum(p.N for p in probs)) * R * T
+
+    def one(seed0):
+        phia.batch_run(probs, reps, steps, scheds, [seed0 + i for i in range(n)])
+
+    for i in range(args.warmup):
+        one(900_000 * (i + 1))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        one(1_000_000 * (i + 1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    value = su * args.steps / wall
+    best = [p.best_exact()[0] for p in probs[:4]]
+    out = {"metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": 1000 * wall / args.steps, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "config": {"workload": w["desc"], "instances": n, "replicas": R, "hmc_steps": T, "path": "i8",
+                      "schedule": s, "spin_updates_per_step": su},
+           "roofline": {"bound": "alu", "achieved": su * OPS_PER_SPIN_UPDATE / (wall / args.steps),
+                        "peak": VALU_OPS_PEAK, "unit": "ops/s",
+                        "frac": su * OPS_PER_SPIN_UPDATE / (wall / args.steps) / VALU_OPS_PEAK, "traffic": None,
+                        "kernel": "k_sweep_mfma (batch)"},
+           "cpu_baseline": None, "best_energy_first4": [int(b) for b in best]}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(J, h, w, budget_s):
     """Time the oracle on a bounded replica/step sample of the workload."""
     import numpy as np
@@ -198,6 +260,9 @@ def main():
     from paper_2407_10205_amd import phia
 
     w = WORKLOADS[args.workload]
+    if w["gen"] == "batch":
+        run_batch_bench(args, w)
+        return
     J, h = make_instance(w)
     N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]
     stream = torch.cuda.Stream()

@@ -176,6 +176,19 @@ phia_status phia_get_trace(phia_problem* p, int64_t* E);
 phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                             int32_t device);
 
+/* Anneal `count` problems of uneven size together: one captured HIP graph
+ * (an init kernel and one sweep kernel per bucket of similar instances)
+ * runs every problem's whole anneal.  Problem i uses replicas[i], steps[i],
+ * scheds[i] and seeds[i] (host arrays of count entries) exactly as
+ * phia_anneal would, with bit-identical results; afterwards phia_best,
+ * phia_replica_best and phia_get_state read each problem as usual.  All
+ * problems must be on one device, use the I8 or BF16HILO path, have N <= 512
+ * and appear once.  The work runs on problem 0's stream (a private stream if
+ * that is the null stream) and the call returns when it has finished.
+ * Energy traces are not recorded in batches. */
+phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,
+                           const int64_t* steps, const phia_schedule* scheds, const uint64_t* seeds);
+
 /* Release all device memory of p.  NULL is accepted. */
 void phia_destroy(phia_problem* p);
 

@@ -1,0 +1,198 @@
+// Batched sweep: many instances of uneven size annealed by one captured
+// HIP graph.  Every instance is split into 16-replica work items; one
+// workgroup runs one item for all of its steps with all of its columns (no
+// exchange between workgroups), its coupling slice in LDS when it fits and
+// streamed from L2 otherwise.  Items are grouped into buckets by (path,
+// column blocks per wave, J placement), each bucket sorted largest first so
+// that the dispatcher balances the tail; the init kernel and the bucket
+// kernels are captured into one graph and launched once.  Results are
+// bit-identical to annealing each instance alone: the Gaussian stream is
+// keyed by (seed, replica) and the sweep's arithmetic does not depend on the
+// launch geometry.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <map>
+#include <tuple>
+#include <vector>
+
+#include "phia.h"
+#include "phia_internal.h"
+#include "phia_problem.h"
+
+using namespace phia;
+
+namespace {
+
+struct Bucket {
+    int path = 0, cbw = 2, jl = 1;
+    size_t lds = 0;
+    std::vector<SweepArgs> items;
+};
+
+}  // namespace
+
+extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,
+                                      const int64_t* steps, const phia_schedule* scheds, const uint64_t* seeds)
+{
+    clear_error();
+    if (!probs || !replicas || !steps || !scheds || !seeds) return fail(PHIA_EINVAL, "null argument");
+    if (count < 1 || count > (1 << 22)) return fail(PHIA_EINVAL, "count = %d out of range", count);
+    const int dev = probs[0] ? probs[0]->dev : 0;
+    for (int i = 0; i < count; ++i) {
+        phia_problem* p = probs[i];
+        phia_status st = check_usable(p);
+        if (st != PHIA_OK) return st;
+        if (p->dev != dev) return fail(PHIA_EINVAL, "problem %d is on another device", i);
+        if (p->path == PHIA_PATH_FP32) return fail(PHIA_EINVAL, "problem %d uses the FP32 path; batches run I8/BF16HILO", i);
+        if (p->Np > kBatchMaxNp) return fail(PHIA_ERANGE, "problem %d: N = %d exceeds %d for batches", i, p->N, kBatchMaxNp);
+        if ((st = check_schedule(replicas[i], steps[i], &scheds[i])) != PHIA_OK) return st;
+        if (steps[i] >= (int64_t(1) << 31)) return fail(PHIA_EINVAL, "problem %d: too many steps", i);
+    }
+    {
+        std::vector<const phia_problem*> sorted(probs, probs + count);
+        std::sort(sorted.begin(), sorted.end());
+        if (std::adjacent_find(sorted.begin(), sorted.end()) != sorted.end())
+            return fail(PHIA_EINVAL, "a problem appears twice in the batch");
+    }
+    hipError_t e = hipSetDevice(dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(nullptr, e, "synchronise");
+
+    // Stream capture needs a stream other than the null stream.
+    hipStream_t st = probs[0]->st;
+    bool own_stream = false;
+    if (!st) {
+        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+            return hip_fail(nullptr, e, "stream creation");
+        own_stream = true;
+    }
+    std::vector<hipStream_t> saved(static_cast<size_t>(count));
+    for (int i = 0; i < count; ++i) {
+        saved[i] = probs[i]->st;
+        probs[i]->st = st;
+    }
+    auto restore = [&]() {
+        for (int i = 0; i < count; ++i) probs[i]->st = saved[i];
+        if (own_stream) (void)hipStreamDestroy(st);
+    };
+
+    // Replica state and schedules (host tables stay alive until the final sync).
+    std::vector<std::vector<float>> ctabs(static_cast<size_t>(count));
+    std::vector<SweepArgs> init_tab(static_cast<size_t>(count));
+    std::map<std::tuple<int, int, int>, Bucket> buckets;
+    phia_status st_ = PHIA_OK;
+    for (int i = 0; i < count && st_ == PHIA_OK; ++i) {
+        phia_problem* p = probs[i];
+        kick_factors(p, steps[i], &scheds[i], ctabs[i]);
+        bool reuse = false;
+        st_ = setup_state(p, replicas[i], steps[i], &scheds[i], seeds[i], ctabs[i], reuse, false);
+        if (st_ != PHIA_OK) break;
+        p->geo = Geometry{};
+        p->geo.ok = true;
+        p->geo.mt = 1;
+        p->geo.G = 1;
+        p->geo.rows = 16;
+        p->geo.nblocks = (replicas[i] + 15) / 16;
+        p->geo.ngroups = p->geo.nblocks;
+        const int ncb = p->Np / 16;
+        const int cbw = ncb <= kWaves * 2 ? 2 : 4;
+        const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
+        p->geo.cbw = cbw;
+        p->geo.j_lds = jl;
+        SweepArgs a = sweep_args(p);
+        a.k0 = 0;
+        a.k1 = steps[i];
+        a.etrace = nullptr;
+        a.G = 1;
+        a.ncb = ncb;
+        a.rows = 16;
+        a.j_lds = jl;
+        init_tab[static_cast<size_t>(i)] = a;
+        Bucket& b = buckets[std::make_tuple(p->path, cbw, jl)];
+        b.path = p->path;
+        b.cbw = cbw;
+        b.jl = jl;
+        b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl));
+        for (int blk = 0; blk < p->geo.nblocks; ++blk) {
+            SweepArgs it = a;
+            it.block = blk;
+            it.nblocks = blk + 1;
+            it.ngroups = 1;
+            b.items.push_back(it);
+        }
+    }
+    if (st_ != PHIA_OK) {
+        restore();
+        return st_;
+    }
+    // Largest instances first: the dispatcher then fills the tail with small ones.
+    size_t total_items = 0;
+    for (auto& kv : buckets) {
+        std::stable_sort(kv.second.items.begin(), kv.second.items.end(),
+                         [](const SweepArgs& x, const SweepArgs& y) { return x.Np > y.Np; });
+        total_items += kv.second.items.size();
+    }
+    // One device table: the init entries, then every bucket's items.
+    std::vector<SweepArgs> host_tab(init_tab);
+    std::vector<size_t> offs;
+    for (auto& kv : buckets) {
+        offs.push_back(host_tab.size());
+        host_tab.insert(host_tab.end(), kv.second.items.begin(), kv.second.items.end());
+    }
+    SweepArgs* dtab = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipMalloc(&dtab, sizeof(SweepArgs) * host_tab.size())) != hipSuccess) {
+        restore();
+        return fail(PHIA_ENOMEM, "work table allocation failed");
+    }
+    auto cleanup = [&]() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipFree(dtab);
+        restore();
+    };
+    if ((e = hipMemcpyAsync(dtab, host_tab.data(), sizeof(SweepArgs) * host_tab.size(), hipMemcpyHostToDevice,
+                            st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        cleanup();
+        return hip_fail(nullptr, e, "work table upload");
+    }
+    for (auto& kv : buckets)
+        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.lds)) != hipSuccess) {
+            cleanup();
+            return hip_fail(nullptr, e, "kernel attributes");
+        }
+    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
+        cleanup();
+        return hip_fail(nullptr, e, "graph capture");
+    }
+    hipError_t le = launch_init_batch(dtab, count, st);
+    size_t bi = 0;
+    for (auto& kv : buckets) {
+        if (le == hipSuccess)
+            le = launch_sweep_batch(kv.second.path, kv.second.cbw, dtab + offs[bi],
+                                    static_cast<int>(kv.second.items.size()), kv.second.lds, st);
+        ++bi;
+    }
+    e = hipStreamEndCapture(st, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        cleanup();
+        return hip_fail(nullptr, le != hipSuccess ? le : e, "graph capture of the batch");
+    }
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess ||
+        (e = hipGraphLaunch(exec, st)) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess) {
+        for (int i = 0; i < count; ++i) probs[i]->poisoned = true;
+        cleanup();
+        return hip_fail(nullptr, e, "batch graph");
+    }
+    cleanup();
+    for (int i = 0; i < count; ++i) {
+        probs[i]->k = steps[i];
+        probs[i]->started = true;
+        probs[i]->has_run = true;
+    }
+    (void)total_items;
+    return PHIA_OK;
+}

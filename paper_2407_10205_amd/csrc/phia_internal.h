@@ -48,6 +48,9 @@ struct SweepArgs {
     uint64_t* pbuf;             // [2][ngroups][G][rows][2] (seq << 32) | 32-bit half of a partial energy
     uint32_t seq_base;          // sequence number before this launch (tags start at seq_base + 1)
     int32_t* err;               // device error word (1 = barrier timeout)
+    // batch mode: the launch argument points at one entry per workgroup
+    const SweepArgs* table;     // work items (device), or null
+    int32_t block;              // replica block of this work item
 };
 
 // Layout of packed couplings.
@@ -68,5 +71,11 @@ hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const 
 hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                              hipStream_t st);
 int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, size_t lds_bytes);
+// batch mode: 16-replica work items, one workgroup each, up to 512 columns
+constexpr int kBatchMaxNp = kWaves * 4 * 16;
+hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st);
+size_t sweep_batch_lds_bytes(int path, int Np, int j_lds);
+hipError_t prepare_sweep_batch(int path, int cbw, size_t lds_bytes);
+hipError_t launch_sweep_batch(int path, int cbw, const SweepArgs* dtable, int nitems, size_t lds_bytes, hipStream_t st);
 
 }  // namespace phia

@@ -466,12 +466,33 @@ __device__ __forceinline__ void quasi_gradient(const unsigned char* S, uint32_t 
     }
 }
 
+// Dispatch on the wave's column-block count (uniform in the wave).
+template <int PATH, int MT, int CBW>
+__device__ __forceinline__ void quasi_gradient_w(int ncw, const unsigned char* S, uint32_t srow,
+                                                 const unsigned char* Jw, size_t cws, int Np, int lane, int lr,
+                                                 int lg, const int (&hreg)[CBW], int (&I)[MT][CBW][4])
+{
+    if (CBW >= 4 && ncw >= 4)
+        quasi_gradient<PATH, MT, CBW, (CBW >= 4 ? 4 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+    else if (CBW >= 3 && ncw == 3)
+        quasi_gradient<PATH, MT, CBW, (CBW >= 3 ? 3 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+    else if (CBW >= 2 && ncw == 2)
+        quasi_gradient<PATH, MT, CBW, (CBW >= 2 ? 2 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+    else if (ncw >= 1)
+        quasi_gradient<PATH, MT, CBW, 1>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+}
+
 // One column block and one row tile per wave: registers are capped at 128 so two
 // workgroups share a CU and hide each other's exchange latency.
-template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE>
+// BATCH: each workgroup runs one work item of a table (one replica block of
+// one instance, all of its columns), with the J placement chosen per item.
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BATCH = false>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CBW == 1 && MT == 1 ? 4 : 2)))
-k_sweep_mfma(SweepArgs a)
+k_sweep_mfma(SweepArgs args)
 {
+    static_assert(!(BATCH && GROUP), "batch items run on one workgroup each");
+    const SweepArgs a = BATCH ? args.table[blockIdx.x] : args;
+    const bool jl = BATCH ? (a.j_lds != 0) : JLDS;
     constexpr int RB = 16 * MT;
     constexpr int ESZ = (PATH == kPathI8) ? 1 : 2;
     constexpr int NE = MT * CBW * 4;  // owned elements per lane
@@ -483,7 +504,7 @@ k_sweep_mfma(SweepArgs a)
     const int lr = lane & 15, lg = lane >> 4;
     const int Np = a.Np, N = a.N;
 
-    int group = blockIdx.x, member = 0;
+    int group = BATCH ? a.block : static_cast<int>(blockIdx.x), member = 0;
     const int G = GROUP ? a.G : 1;
     if (GROUP) {
         if (a.xcd_map) {
@@ -499,7 +520,7 @@ k_sweep_mfma(SweepArgs a)
     const int cb1 = (member + 1) * a.ncb / G;
     const int cbs = cb1 - cb0;
     const int cbs_max = (a.ncb + G - 1) / G;
-    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, JLDS ? 1 : 0);
+    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, jl ? 1 : 0);
     const uint32_t srow = static_cast<uint32_t>(Np) * ESZ + 16u;  // S row stride, bytes
     const uint32_t cbb = cb_bytes(PATH, Np);
     unsigned char* sJ = lds + P.j_off;
@@ -510,7 +531,7 @@ k_sweep_mfma(SweepArgs a)
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
 
     const unsigned char* Jg = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0) * cbb;
-    if (JLDS) {
+    if (jl) {
         const uint32_t nvec = static_cast<uint32_t>(cbs) * cbb / 16u;
         const uint4* src = reinterpret_cast<const uint4*>(Jg);
         uint4* dst = reinterpret_cast<uint4*>(sJ);
@@ -769,13 +790,13 @@ k_sweep_mfma(SweepArgs a)
             // Quasi-gradient on matrix cores (columns of this wave only).
             int I[MT][CBW][4] = {};
             {
-                const unsigned char* Jw = (JLDS ? static_cast<const unsigned char*>(sJ) : Jg) +
-                                          static_cast<size_t>(wave) * cbb;
                 const size_t cws = static_cast<size_t>(kWaves) * cbb;
-                if (ncw >= 2)
-                    quasi_gradient<PATH, MT, CBW, (CBW >= 2 ? 2 : 1)>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
-                else if (ncw == 1)
-                    quasi_gradient<PATH, MT, CBW, 1>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
+                if (jl)
+                    quasi_gradient_w<PATH, MT, CBW>(ncw, S, srow, sJ + static_cast<size_t>(wave) * cbb, cws, Np, lane,
+                                                    lr, lg, hreg, I);
+                else
+                    quasi_gradient_w<PATH, MT, CBW>(ncw, S, srow, Jg + static_cast<size_t>(wave) * cbb, cws, Np, lane,
+                                                    lr, lg, hreg, I);
             }
 
             // Partial energies of step k and the kick.
@@ -827,6 +848,67 @@ k_sweep_mfma(SweepArgs a)
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------------------------ batching --
+// One workgroup per instance: x ~ N(0, I), v = 0, records reset.
+__global__ void __launch_bounds__(256) k_init_batch(const SweepArgs* table)
+{
+    const SweepArgs& a = table[blockIdx.x];
+    const int64_t total = static_cast<int64_t>(a.R) * a.Np;
+    for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
+        const int64_t r = idx / a.Np;
+        const int i = static_cast<int>(idx - r * a.Np);
+        a.x[idx] = (i < a.N) ? dev_gauss(a.seed, kTagX, a.r_base + r, 0, i) : 0.0f;
+        a.v[idx] = 0.0f;
+        a.bestS[idx] = 0;
+        if (i == 0) {
+            a.bestE[r] = INT64_MAX;
+            a.bestStep[r] = -1;
+        }
+    }
+}
+
+hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init_batch, dim3(static_cast<unsigned>(count)), dim3(256), 0, st, dtable);
+    return hipGetLastError();
+}
+
+size_t sweep_batch_lds_bytes(int path, int Np, int j_lds)
+{
+    return lds_plan(path, 1, Np, Np / 16, j_lds).total;
+}
+
+hipError_t prepare_sweep_batch(int path, int cbw, size_t lds)
+{
+    const void* f = nullptr;
+    if (path == kPathI8)
+        f = cbw == 2 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, 2, false, false, false, true>)
+                     : reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, 4, false, false, false, true>);
+    else
+        f = cbw == 2 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, 2, false, false, false, true>)
+                     : reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, 4, false, false, false, true>);
+    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+}
+
+// Items of one bucket: same path and column-block width; table entries
+// describe one 16-replica block each.
+hipError_t launch_sweep_batch(int path, int cbw, const SweepArgs* dtable, int nitems, size_t lds, hipStream_t st)
+{
+    SweepArgs a{};
+    a.table = dtable;
+    const dim3 grid(static_cast<unsigned>(nitems)), block(kThreads);
+    if (path == kPathI8) {
+        if (cbw == 2) hipLaunchKernelGGL((k_sweep_mfma<kPathI8, 1, 2, false, false, false, true>), grid, block, lds, st, a);
+        else hipLaunchKernelGGL((k_sweep_mfma<kPathI8, 1, 4, false, false, false, true>), grid, block, lds, st, a);
+    } else {
+        if (cbw == 2)
+            hipLaunchKernelGGL((k_sweep_mfma<kPathBf16, 1, 2, false, false, false, true>), grid, block, lds, st, a);
+        else
+            hipLaunchKernelGGL((k_sweep_mfma<kPathBf16, 1, 4, false, false, false, true>), grid, block, lds, st, a);
+    }
+    return hipGetLastError();
 }
 
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)

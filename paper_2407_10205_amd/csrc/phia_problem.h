@@ -29,6 +29,19 @@ void clear_error();
 
 }  // namespace phia
 
+#include <vector>
+
+namespace phia {
+phia_status check_usable(const ::phia_problem* p);
+phia_status check_schedule(int32_t replicas, int64_t steps, const phia_schedule* s);
+void kick_factors(const ::phia_problem* p, int64_t steps, const phia_schedule* s, std::vector<float>& ctab);
+phia_status setup_state(::phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s, uint64_t seed,
+                        const std::vector<float>& ctab, bool& reuse, bool sync_first);
+void free_state(::phia_problem* p);
+SweepArgs sweep_args(const ::phia_problem* p);
+}  // namespace phia
+
+struct phia_problem;
 struct phia_problem {
     int dev = 0;
     hipStream_t st = nullptr;

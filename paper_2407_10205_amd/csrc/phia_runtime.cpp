@@ -295,7 +295,7 @@ static void choose_mfma_geometry(phia_problem* p, int R)
     }
 }
 
-static void free_state(phia_problem* p)
+void free_state(phia_problem* p)
 {
     dfree(p->dx);
     dfree(p->dv);
@@ -494,28 +494,26 @@ phia_status phia_set_trace(phia_problem* p, int32_t enable)
     return PHIA_OK;
 }
 
-phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s,
-                              uint64_t seed)
+}  // extern "C"
+
+namespace phia {
+
+phia_status check_schedule(int32_t replicas, int64_t steps, const phia_schedule* s)
 {
-    clear_error();
-    phia_status st = check_usable(p);
-    if (st != PHIA_OK) return st;
     if (!s) return fail(PHIA_EINVAL, "schedule is null");
     if (replicas < 1 || replicas > (1 << 20)) return fail(PHIA_EINVAL, "replicas = %d outside [1, 2^20]", replicas);
     if (steps < 1 || steps > (int64_t(1) << 31)) return fail(PHIA_EINVAL, "steps = %lld out of range", (long long)steps);
     if (s->refresh_L < 1) return fail(PHIA_EINVAL, "refresh_L must be >= 1");
     if (!std::isfinite(s->eps) || !std::isfinite(s->gamma)) return fail(PHIA_EINVAL, "eps and gamma must be finite");
-    hipError_t e = hipSetDevice(p->dev);
-    if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
-    e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
-    if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
-    // Same shape as the previous anneal: keep the device buffers (the group
-    // barrier sequence continues from its last value).
-    const bool reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr);
-    if (!reuse) free_state(p);
+    return PHIA_OK;
+}
 
-    // Inverse-temperature table and the kick factors c_k = (beta_k * gamma) * sigma.
-    std::vector<float> ctab(static_cast<size_t>(steps));
+// Kick factors c_k = (beta_k * gamma) * sigma of a schedule, with the linear
+// inverse-temperature table beta_k = float(b0 + ((b1 - b0) k) / (T - 1))
+// evaluated in double when no explicit table is given.
+void kick_factors(const phia_problem* p, int64_t steps, const phia_schedule* s, std::vector<float>& ctab)
+{
+    ctab.resize(static_cast<size_t>(steps));
     const float sigma = std::ldexp(1.0f, -p->f);
     for (int64_t k = 0; k < steps; ++k) {
         float b;
@@ -531,6 +529,22 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
         }
         ctab[static_cast<size_t>(k)] = (b * s->gamma) * sigma;
     }
+}
+
+// Replica state and schedule of a new anneal (device buffers kept when the
+// shape is unchanged).  The kick factors are copied asynchronously from
+// `ctab`, which must stay alive until the stream has passed the copy.
+phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s, uint64_t seed,
+                        const std::vector<float>& ctab, bool& reuse, bool sync_first)
+{
+    hipError_t e = hipSetDevice(p->dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
+    if (sync_first) {
+        e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
+    }
+    reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr);
+    if (!reuse) free_state(p);
     p->R = replicas;
     p->T = steps;
     p->k = 0;
@@ -539,15 +553,15 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     p->L = s->refresh_L;
     p->seed = seed;
     p->has_run = false;
-
+    p->started = false;
     const size_t RN = static_cast<size_t>(replicas) * p->Np;
     size_t* cnt = &p->state_bytes;
     if (!reuse && ((e = dalloc(reinterpret_cast<void**>(&p->dx), RN * sizeof(float), cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dv), RN * sizeof(float), cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dbestS), RN, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dbestE), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dbestStep), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dctab), sizeof(float) * steps, cnt)) != hipSuccess)) {
+                   (e = dalloc(reinterpret_cast<void**>(&p->dv), RN * sizeof(float), cnt)) != hipSuccess ||
+                   (e = dalloc(reinterpret_cast<void**>(&p->dbestS), RN, cnt)) != hipSuccess ||
+                   (e = dalloc(reinterpret_cast<void**>(&p->dbestE), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
+                   (e = dalloc(reinterpret_cast<void**>(&p->dbestStep), sizeof(int64_t) * replicas, cnt)) != hipSuccess ||
+                   (e = dalloc(reinterpret_cast<void**>(&p->dctab), sizeof(float) * steps, cnt)) != hipSuccess)) {
         free_state(p);
         return fail(PHIA_ENOMEM, "state allocation failed: %s", hipGetErrorString(e));
     }
@@ -564,10 +578,28 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
         free_state(p);
         return hip_fail(p, e, "upload of the schedule");
     }
-    // ctab is a pageable host vector; make the copy complete before it goes out of scope.
-    if ((e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize()) != hipSuccess)
-        return hip_fail(p, e, "schedule upload");
+    return PHIA_OK;
+}
 
+}  // namespace phia
+
+extern "C" {
+
+phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s,
+                              uint64_t seed)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if ((st = check_schedule(replicas, steps, s)) != PHIA_OK) return st;
+    std::vector<float> ctab;
+    kick_factors(p, steps, s, ctab);
+    bool reuse = false;
+    if ((st = setup_state(p, replicas, steps, s, seed, ctab, reuse, true)) != PHIA_OK) return st;
+    // ctab is a pageable host vector; make the copy complete before it goes out of scope.
+    hipError_t e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(p, e, "schedule upload");
+    size_t* cnt = &p->state_bytes;
     if (reuse) {
         SweepArgs a = sweep_args(p);
         if ((e = launch_init(a, p->st)) != hipSuccess) return hip_fail(p, e, "init kernel launch");

@@ -28,7 +28,7 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
 EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_get_state",
            "phia_set_state", "phia_get_info", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
-           "phia_destroy", "phia_last_error", "phia_version")
+           "phia_batch_run", "phia_destroy", "phia_last_error", "phia_version")
 
 
 class PhiaError(RuntimeError):
@@ -73,6 +73,7 @@ def _declare(lib):
         "phia_set_trace": [P, I32],
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
+        "phia_batch_run": [P, I32, P, P, P, P],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -237,6 +238,29 @@ class Problem:
         d = {f: getattr(i, f) for f, _ in Info._fields_}
         d["path_name"] = PATH_NAMES.get(d["path"], "?")
         return d
+
+
+def batch_run(problems, replicas, steps, schedules, seeds):
+    """Anneal several problems in one graph launch (phia_batch_run).
+
+    schedules: list of dicts with eps, gamma, beta0, beta1 (or betas), refresh_L.
+    """
+    n = len(problems)
+    arr = (C.c_void_p * n)(*[p._p for p in problems])
+    reps = np.ascontiguousarray(replicas, dtype=np.int32)
+    stp = np.ascontiguousarray(steps, dtype=np.int64)
+    sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+    scheds = (Schedule * n)()
+    keep = []
+    for i, sc in enumerate(schedules):
+        one = make_schedule(int(stp[i]), sc["eps"], sc["gamma"], sc.get("beta0"), sc.get("beta1"),
+                            sc.get("betas"), sc.get("refresh_L", 50))
+        keep.append(one)
+        C.memmove(C.byref(scheds, i * C.sizeof(Schedule)), C.byref(one), C.sizeof(Schedule))
+    _check(lib().phia_batch_run(arr, n, _ptr(reps), _ptr(stp), C.cast(scheds, C.c_void_p), _ptr(sd)))
+    for p, r in zip(problems, reps):
+        p.R = int(r)
+    del keep
 
 
 def eval_fmath(kind, values=None, quads=None, seed=0, device=0):

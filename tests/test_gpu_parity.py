@@ -256,3 +256,51 @@ def test_autotune_keeps_results(P, O):
     o = O.anneal(Ji, hi, 0, 1, O.beta_linear(0.1, 3.0, 150), 0.2, 1.0, 25, 4, r0=95)
     assert E[95] == o.bestE[0] and np.array_equal(S[95], o.bestS[0])
     p.close()
+
+
+def test_batch_matches_single_runs_and_oracle(P, O):
+    """Uneven-N batch (int8 and BF16 hi/lo, J in LDS and streamed, ragged
+    replica counts, per-instance schedules and seeds) is bit-identical to
+    annealing every instance alone, and to the oracle on sampled replicas."""
+    specs = [
+        ("sk", 17, "i8", 16, 120, 1), ("reg3", 64, "i8", 37, 90, 2), ("sk", 100, "bf16hilo", 32, 75, 3),
+        ("fixed", 250, "i8", 20, 60, 4), ("reg3", 302, "i8", 33, 50, 5), ("sk", 400, "i8", 16, 40, 6),
+        ("fixed", 512, "i8", 18, 30, 7), ("sk", 33, "bf16hilo", 5, 100, 8), ("fixed16", 130, "bf16hilo", 17, 40, 9),
+    ]
+    inst_list, probs, reps, steps, scheds, seeds = [], [], [], [], [], []
+    for kind, N, path, R, T, seed in specs:
+        if kind == "sk":
+            J, h = inst.sk_pm1(N, seed)
+        elif kind == "reg3":
+            J, h = inst.regular3_pm1(N, seed)
+        elif kind == "fixed":
+            J, h = inst.sk_gauss_fixed(N, seed, frac_bits=5, bits=8)
+        else:
+            J, h = inst.sk_gauss_fixed(N, seed, frac_bits=12, bits=16)
+        sc = dict(eps=0.2, gamma=1.0, beta0=0.05 * seed, beta1=1.0 + seed, refresh_L=10 + seed)
+        inst_list.append((J, h))
+        probs.append(P.Problem(J, h, path=path))
+        reps.append(R)
+        steps.append(T)
+        scheds.append(sc)
+        seeds.append(100 + seed)
+    say("batch of", len(probs))
+    P.batch_run(probs, reps, steps, scheds, seeds)
+    for i, p in enumerate(probs):
+        got = p.replica_best() + p.get_state()[:2]
+        J, h = inst_list[i]
+        q = P.Problem(J, h, path=specs[i][2])
+        sc = scheds[i]
+        q.anneal(reps[i], steps[i], sc["eps"], sc["gamma"], beta0=sc["beta0"], beta1=sc["beta1"],
+                 refresh_L=sc["refresh_L"], seed=seeds[i])
+        ref = q.replica_best() + q.get_state()[:2]
+        for u, w in zip(ref, got):
+            assert np.array_equal(u, w), specs[i]
+        if i in (1, 4, 6):
+            f = 5 if specs[i][0] == "fixed" else 0
+            Ji, hi = int_units(J, h, f)
+            o = O.anneal(Ji, hi, f, 1, O.beta_linear(sc["beta0"], sc["beta1"], steps[i]), sc["eps"], sc["gamma"],
+                         sc["refresh_L"], seeds[i], r0=reps[i] - 1)
+            assert got[0][-1] == o.bestE[0] and np.array_equal(got[3][-1], o.x[0]), specs[i]
+        q.close()
+        p.close()
