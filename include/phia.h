@@ -189,6 +189,65 @@ phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64,
 phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,
                            const int64_t* steps, const phia_schedule* scheds, const uint64_t* seeds);
 
+/* ---------------------------------------------------------------- serving --
+ * A server anneals submitted problems with continuous batching on one GPU.
+ * Requests are admitted in arrival order when a slot is free and their
+ * estimated device footprint (couplings plus replica state) fits within
+ * hbm_budget bytes next to the running ones; a request that can never fit
+ * fails.  Each scheduling round advances every running request by
+ * chunk_steps steps (instances with N <= 512 together in one batched launch,
+ * larger ones each in a column-split launch), then checks every request: it
+ * retires when its best energy reaches target_energy_units (units of
+ * 2^-frac_bits of its problem) or after max_steps steps.  Requests stop only
+ * at chunk boundaries, so a request's result is the same alone and in any
+ * mix.  A submitted problem belongs to the server until its request has
+ * finished: the caller must not use or destroy it before that.  All server
+ * functions are thread-safe. */
+typedef struct phia_server phia_server;
+
+enum {
+    PHIA_REQ_QUEUED = 0,
+    PHIA_REQ_RUNNING = 1,
+    PHIA_REQ_DONE = 2,
+    PHIA_REQ_CANCELLED = 3,
+    PHIA_REQ_FAILED = -1
+};
+
+typedef struct {
+    int32_t state;         /* PHIA_REQ_*                                                */
+    int32_t success;       /* 1: the best energy reached the target                     */
+    int32_t frac_bits;     /* f of the problem                                          */
+    int32_t replica;       /* replica holding the best state (-1 before any step)       */
+    int64_t energy_units;  /* best energy in units of 2^-f (INT64_MAX before any step)  */
+    int64_t steps_used;    /* steps run                                                 */
+    double t_arrive;       /* seconds since server creation: submission                 */
+    double t_admit;        /* admission (-1 while queued)                               */
+    double t_done;         /* retirement (-1 while unfinished)                          */
+} phia_result;
+
+/* hbm_budget > 0 bytes, max_slots in [1, 65536], chunk_steps >= 1. */
+phia_status phia_server_create(size_t hbm_budget, int32_t max_slots, int32_t chunk_steps, int32_t device,
+                               phia_server** out);
+/* Queue a request; *ticket identifies it.  The schedule (and an explicit
+ * beta table, which is copied) has max_steps entries. */
+phia_status phia_server_submit(phia_server* s, phia_problem* p, int32_t replicas, int64_t max_steps,
+                               int64_t target_energy_units, const phia_schedule* schedule, uint64_t seed,
+                               uint64_t* ticket);
+/* Device bytes a request of `replicas` x `max_steps` on p is charged against
+ * the server's budget (couplings, replica state, schedule, exchange). */
+phia_status phia_server_footprint(const phia_problem* p, int32_t replicas, int64_t max_steps, size_t* bytes);
+/* Current state and result of a request (never blocks). */
+phia_status phia_server_poll(phia_server* s, uint64_t ticket, phia_result* out);
+/* Block until the request has finished (timeout_s < 0: no limit); returns
+ * PHIA_ESTATE with the current state on timeout. */
+phia_status phia_server_wait(phia_server* s, uint64_t ticket, double timeout_s, phia_result* out);
+/* Best state of a finished request: host int8[N] of its problem. */
+phia_status phia_server_spins(phia_server* s, uint64_t ticket, int8_t* spins);
+/* Cancel a queued request, or stop a running one at the end of the round. */
+phia_status phia_server_cancel(phia_server* s, uint64_t ticket);
+/* Cancel what is queued, stop what runs, release the server (not the problems). */
+void phia_server_destroy(phia_server* s);
+
 /* Release all device memory of p.  NULL is accepted. */
 void phia_destroy(phia_problem* p);
 

@@ -30,7 +30,87 @@ struct Bucket {
     std::vector<SweepArgs> items;
 };
 
+// Work items of steps [p->k, k_end) of problem p, added to its bucket.
+void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int>, Bucket>& buckets)
+{
+    const int ncb = p->Np / 16;
+    const int cbw = ncb <= kWaves * 2 ? 2 : 4;
+    const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
+    const int nblocks = (p->R + 15) / 16;
+    SweepArgs a = sweep_args(p);
+    a.k0 = p->k;
+    a.k1 = k_end;
+    a.etrace = nullptr;
+    a.G = 1;
+    a.ncb = ncb;
+    a.rows = 16;
+    a.j_lds = jl;
+    Bucket& b = buckets[std::make_tuple(p->path, cbw, jl)];
+    b.path = p->path;
+    b.cbw = cbw;
+    b.jl = jl;
+    b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl));
+    for (int blk = 0; blk < nblocks; ++blk) {
+        SweepArgs it = a;
+        it.block = blk;
+        it.nblocks = blk + 1;
+        it.ngroups = 1;
+        b.items.push_back(it);
+    }
+}
+
 }  // namespace
+
+namespace phia {
+
+// Enqueue steps [k, k_end[i]) of every problem as batch work items on st
+// (problems already started, Np <= kBatchMaxNp, matrix-core paths).  The
+// device table `dtab` (capacity `cap` entries, grown as needed) must not be
+// in use by earlier launches; the caller synchronises between rounds.
+phia_status launch_batch_chunk(phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
+                               SweepArgs*& dtab, size_t& cap)
+{
+    std::map<std::tuple<int, int, int>, Bucket> buckets;
+    for (int i = 0; i < count; ++i)
+        if (k_end[i] > probs[i]->k) add_items(probs[i], k_end[i], buckets);
+    std::vector<SweepArgs> tab;
+    std::vector<size_t> offs;
+    for (auto& kv : buckets) {
+        std::stable_sort(kv.second.items.begin(), kv.second.items.end(),
+                         [](const SweepArgs& x, const SweepArgs& y) { return x.Np > y.Np; });
+        offs.push_back(tab.size());
+        tab.insert(tab.end(), kv.second.items.begin(), kv.second.items.end());
+    }
+    if (tab.empty()) return PHIA_OK;
+    hipError_t e;
+    if (tab.size() > cap) {
+        if (dtab) (void)hipFree(dtab);
+        dtab = nullptr;
+        cap = 0;
+        if ((e = hipMalloc(&dtab, sizeof(SweepArgs) * tab.size() * 2)) != hipSuccess)
+            return fail(PHIA_ENOMEM, "work table allocation failed");
+        cap = tab.size() * 2;
+    }
+    // pageable source: the copy completes before hipMemcpy returns
+    if ((e = hipMemcpy(dtab, tab.data(), sizeof(SweepArgs) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+        return hip_fail(nullptr, e, "work table upload");
+    size_t bi = 0;
+    for (auto& kv : buckets) {
+        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.lds)) != hipSuccess ||
+            (e = launch_sweep_batch(kv.second.path, kv.second.cbw, dtab + offs[bi],
+                                    static_cast<int>(kv.second.items.size()), kv.second.lds, st)) != hipSuccess)
+            return hip_fail(nullptr, e, "batch chunk launch");
+        ++bi;
+    }
+    for (int i = 0; i < count; ++i)
+        if (k_end[i] > probs[i]->k) {
+            probs[i]->k = k_end[i];
+            probs[i]->has_run = true;
+        }
+    return PHIA_OK;
+}
+
+}  // namespace phia
 
 extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,
                                       const int64_t* steps, const phia_schedule* scheds, const uint64_t* seeds)

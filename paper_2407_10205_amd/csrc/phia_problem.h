@@ -39,6 +39,8 @@ phia_status setup_state(::phia_problem* p, int32_t replicas, int64_t steps, cons
                         const std::vector<float>& ctab, bool& reuse, bool sync_first);
 void free_state(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
+phia_status launch_batch_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
+                               SweepArgs*& dtab, size_t& cap);
 }  // namespace phia
 
 struct phia_problem;

@@ -1,0 +1,411 @@
+// Serving loop: continuous batching of annealing requests on one GPU.
+//
+// Requests queue in arrival order.  A request is admitted when a slot is
+// free and its estimated device footprint (couplings plus replica state)
+// fits the memory budget next to the requests already running; its replica
+// state then stays resident until it retires.  The service thread runs
+// scheduling rounds: each round advances every running request by one chunk
+// of steps -- all running instances with N <= 512 in one batched launch
+// (16-replica work items), larger ones each in their own column-split
+// launch, all on one stream -- then reads every request's best energy with
+// one synchronisation.  A request retires when its best energy reaches its
+// target or its step budget is used up; its result (energy, replica, steps,
+// best state, timestamps) is kept for the caller and its device state is
+// released, which may admit waiting requests at the next round.  Requests
+// stop only at chunk boundaries, so a request's result is the same alone and
+// in any mix.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <tuple>
+#include <unordered_map>
+#include <vector>
+
+#include "phia.h"
+#include "phia_internal.h"
+#include "phia_problem.h"
+
+using namespace phia;
+
+namespace {
+
+struct Request {
+    uint64_t ticket = 0;
+    phia_problem* p = nullptr;
+    int32_t R = 0;
+    int64_t max_steps = 0;
+    int64_t target = 0;
+    phia_schedule sched{};
+    std::vector<float> betas;  // copy of an explicit table
+    uint64_t seed = 0;
+    size_t footprint = 0;
+    hipStream_t saved_stream = nullptr;
+    phia_result res{};
+    std::vector<int8_t> spins;
+    std::atomic<bool> cancel{false};
+    bool started = false;   // service thread only
+    bool failed = false;    // service thread only
+    int64_t energy = INT64_MAX;  // service thread only: best energy of the last round
+    int32_t replica = -1;        // service thread only
+};
+
+}  // namespace
+
+struct phia_server {
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Request*> pending;
+    std::vector<Request*> running;
+    std::unordered_map<uint64_t, Request*> all;
+    size_t budget = 0, in_use = 0;
+    int max_slots = 1;
+    int64_t chunk = 1000;
+    int dev = 0;
+    hipStream_t st = nullptr;
+    int64_t* host_res = nullptr;  // pinned: [2 * max_slots] (energy, replica)
+    SweepArgs* dtab = nullptr;
+    size_t dtab_cap = 0;
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::thread worker;
+    std::chrono::steady_clock::time_point t0;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+};
+
+namespace {
+
+size_t footprint(const phia_problem* p, int32_t R, int64_t T)
+{
+    const size_t RN = static_cast<size_t>(R) * p->Np;
+    return p->base_bytes + RN * 9 + static_cast<size_t>(R) * 16 + static_cast<size_t>(T) * 4 +
+           2 * RN / 16 * 8 * 2 + 65536;
+}
+
+void finish(phia_server* s, Request* r, int32_t state)
+{
+    r->res.state = state;
+    r->res.t_done = s->now();
+    r->res.steps_used = r->p->k;
+    if (r->started) free_state(r->p);
+    r->p->st = r->saved_stream;
+    r->p->started = false;
+    r->p->has_run = false;
+    s->in_use -= r->footprint;
+}
+
+// One scheduling round over the running requests (service thread only).
+void round_once(phia_server* s, std::vector<Request*>& run)
+{
+    const int n = static_cast<int>(run.size());
+    std::vector<phia_problem*> small;
+    std::vector<int64_t> small_end;
+    hipError_t e = hipSuccess;
+    for (Request* r : run) {
+        phia_problem* p = r->p;
+        const int64_t k_end = std::min(p->k + s->chunk, p->T);
+        if (p->Np <= kBatchMaxNp && p->path != PHIA_PATH_FP32) {
+            small.push_back(p);
+            small_end.push_back(k_end);
+        } else if (k_end > p->k) {
+            if (phia_anneal_run(p, k_end) != PHIA_OK) r->failed = true;
+        }
+    }
+    if (!small.empty() && launch_batch_chunk(small.data(), static_cast<int>(small.size()), small_end.data(), s->st,
+                                             s->dtab, s->dtab_cap) != PHIA_OK)
+        for (Request* r : run)
+            if (r->p->Np <= kBatchMaxNp) r->failed = true;
+    for (int i = 0; i < n; ++i) {
+        phia_problem* p = run[i]->p;
+        if ((e = launch_argmin(p->dbestE, p->R, p->dscratch, s->st)) != hipSuccess ||
+            (e = hipMemcpyAsync(s->host_res + 2 * i, p->dscratch, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
+                                s->st)) != hipSuccess)
+            run[i]->failed = true;
+    }
+    if ((e = hipStreamSynchronize(s->st)) != hipSuccess) {
+        for (Request* r : run) {
+            r->failed = true;
+            r->p->poisoned = true;
+        }
+        return;
+    }
+    for (int i = 0; i < n; ++i) {
+        Request* r = run[i];
+        if (r->failed) continue;
+        int32_t err = 0;
+        if (r->p->geo.G > 1 && hipMemcpy(&err, r->p->derr, sizeof err, hipMemcpyDeviceToHost) == hipSuccess && err) {
+            r->failed = true;
+            r->p->poisoned = true;
+            continue;
+        }
+        r->energy = s->host_res[2 * i];
+        r->replica = static_cast<int32_t>(s->host_res[2 * i + 1]);
+    }
+}
+
+void service(phia_server* s)
+{
+    (void)hipSetDevice(s->dev);
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        // Admission in arrival order, within the slot count and the budget.
+        std::vector<Request*> admitted;
+        while (!s->pending.empty() && static_cast<int>(s->running.size()) < s->max_slots) {
+            Request* r = s->pending.front();
+            if (r->cancel) {
+                s->pending.pop_front();
+                r->res.state = PHIA_REQ_CANCELLED;
+                r->res.t_done = s->now();
+                continue;
+            }
+            if (s->in_use + r->footprint > s->budget) {
+                if (s->running.empty()) {  // can never fit
+                    s->pending.pop_front();
+                    r->res.state = PHIA_REQ_FAILED;
+                    r->res.t_done = s->now();
+                    continue;
+                }
+                break;
+            }
+            s->pending.pop_front();
+            s->in_use += r->footprint;
+            r->res.state = PHIA_REQ_RUNNING;
+            r->res.t_admit = s->now();
+            s->running.push_back(r);
+            admitted.push_back(r);
+        }
+        s->cv_done.notify_all();
+        if (s->running.empty()) {
+            if (s->stop) break;
+            s->cv_work.wait(lk);
+            continue;
+        }
+        std::vector<Request*> run = s->running;
+        lk.unlock();
+        for (Request* r : admitted) {
+            r->saved_stream = r->p->st;
+            r->p->st = s->st;
+            if (phia_anneal_start(r->p, r->R, r->max_steps, &r->sched, r->seed) != PHIA_OK)
+                r->failed = true;
+            else
+                r->started = true;
+        }
+        std::vector<Request*> live;
+        for (Request* r : run)
+            if (!r->failed) live.push_back(r);
+        round_once(s, live);
+        // Retire finished requests (their best state is copied out first).
+        std::vector<std::tuple<Request*, int32_t, bool>> done;
+        for (Request* r : run) {
+            if (r->failed) {
+                done.push_back({r, PHIA_REQ_FAILED, false});
+                continue;
+            }
+            const bool hit = r->energy <= r->target;
+            const bool cancel = r->cancel.load();
+            if (hit || r->p->k >= r->p->T || cancel) {
+                if (r->p->has_run && r->replica >= 0) {
+                    r->spins.resize(static_cast<size_t>(r->p->N));
+                    (void)hipMemcpy(r->spins.data(), r->p->dbestS + static_cast<size_t>(r->replica) * r->p->Np,
+                                    static_cast<size_t>(r->p->N), hipMemcpyDeviceToHost);
+                }
+                done.push_back({r, cancel && !hit ? PHIA_REQ_CANCELLED : PHIA_REQ_DONE, hit});
+            }
+        }
+        lk.lock();
+        for (Request* r : run) {
+            r->res.energy_units = r->energy;
+            r->res.replica = r->replica;
+            r->res.steps_used = r->p->k;
+        }
+        for (auto& d : done) {
+            Request* r = std::get<0>(d);
+            r->res.success = std::get<2>(d) ? 1 : 0;
+            finish(s, r, std::get<1>(d));
+            s->running.erase(std::find(s->running.begin(), s->running.end(), r));
+        }
+        if (!done.empty()) s->cv_done.notify_all();
+    }
+    s->cv_done.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+phia_status phia_server_create(size_t hbm_budget, int32_t max_slots, int32_t chunk_steps, int32_t device,
+                               phia_server** out)
+{
+    clear_error();
+    if (!out) return fail(PHIA_EINVAL, "out is null");
+    *out = nullptr;
+    if (hbm_budget == 0 || max_slots < 1 || max_slots > 65536 || chunk_steps < 1)
+        return fail(PHIA_EINVAL, "bad server parameters");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+        return fail(PHIA_EINVAL, "device %d not present", device);
+    hipError_t e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    phia_server* s = new (std::nothrow) phia_server();
+    if (!s) return fail(PHIA_ENOMEM, "host allocation failed");
+    s->budget = hbm_budget;
+    s->max_slots = max_slots;
+    s->chunk = chunk_steps;
+    s->dev = device;
+    s->t0 = std::chrono::steady_clock::now();
+    if ((e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipHostMalloc(reinterpret_cast<void**>(&s->host_res), sizeof(int64_t) * 2 * max_slots)) !=
+            hipSuccess) {
+        if (s->st) (void)hipStreamDestroy(s->st);
+        delete s;
+        return hip_fail(nullptr, e, "server resources");
+    }
+    s->worker = std::thread(service, s);
+    *out = s;
+    return PHIA_OK;
+}
+
+phia_status phia_server_submit(phia_server* s, phia_problem* p, int32_t replicas, int64_t max_steps,
+                               int64_t target_energy_units, const phia_schedule* sched, uint64_t seed,
+                               uint64_t* ticket)
+{
+    clear_error();
+    if (!s || !ticket) return fail(PHIA_EINVAL, "null argument");
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if ((st = check_schedule(replicas, max_steps, sched)) != PHIA_OK) return st;
+    if (p->dev != s->dev) return fail(PHIA_EINVAL, "problem is on another device");
+    Request* r = new (std::nothrow) Request();
+    if (!r) return fail(PHIA_ENOMEM, "host allocation failed");
+    r->p = p;
+    r->R = replicas;
+    r->max_steps = max_steps;
+    r->target = target_energy_units;
+    r->sched = *sched;
+    if (sched->betas) {
+        r->betas.assign(sched->betas, sched->betas + max_steps);
+        r->sched.betas = r->betas.data();
+    }
+    r->seed = seed;
+    r->footprint = footprint(p, replicas, max_steps);
+    r->res.state = PHIA_REQ_QUEUED;
+    r->res.energy_units = INT64_MAX;
+    r->res.frac_bits = p->f;
+    r->res.replica = -1;
+    r->res.t_admit = -1.0;
+    r->res.t_done = -1.0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto& kv : s->all)
+            if (kv.second->p == p && (kv.second->res.state == PHIA_REQ_QUEUED ||
+                                      kv.second->res.state == PHIA_REQ_RUNNING)) {
+                delete r;
+                return fail(PHIA_EINVAL, "problem already has an unfinished request");
+            }
+        r->ticket = s->next_ticket++;
+        r->res.t_arrive = s->now();
+        s->all[r->ticket] = r;
+        s->pending.push_back(r);
+        *ticket = r->ticket;
+    }
+    s->cv_work.notify_one();
+    return PHIA_OK;
+}
+
+phia_status phia_server_footprint(const phia_problem* p, int32_t replicas, int64_t max_steps, size_t* bytes)
+{
+    clear_error();
+    if (!p || !bytes || replicas < 1 || max_steps < 1) return fail(PHIA_EINVAL, "bad argument");
+    *bytes = footprint(p, replicas, max_steps);
+    return PHIA_OK;
+}
+
+phia_status phia_server_poll(phia_server* s, uint64_t ticket, phia_result* out)
+{
+    clear_error();
+    if (!s || !out) return fail(PHIA_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(PHIA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    *out = it->second->res;
+    return PHIA_OK;
+}
+
+phia_status phia_server_wait(phia_server* s, uint64_t ticket, double timeout_s, phia_result* out)
+{
+    clear_error();
+    if (!s || !out) return fail(PHIA_EINVAL, "null argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(PHIA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second;
+    auto finished = [&] { return r->res.state != PHIA_REQ_QUEUED && r->res.state != PHIA_REQ_RUNNING; };
+    if (timeout_s < 0)
+        s->cv_done.wait(lk, finished);
+    else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), finished)) {
+        *out = r->res;
+        return fail(PHIA_ESTATE, "request %llu not finished within the timeout", (unsigned long long)ticket);
+    }
+    *out = r->res;
+    return PHIA_OK;
+}
+
+phia_status phia_server_spins(phia_server* s, uint64_t ticket, int8_t* spins)
+{
+    clear_error();
+    if (!s || !spins) return fail(PHIA_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->all.find(ticket);
+    if (it == s->all.end()) return fail(PHIA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    const Request* r = it->second;
+    if (r->res.state != PHIA_REQ_DONE && r->res.state != PHIA_REQ_CANCELLED) return fail(PHIA_ESTATE, "not done");
+    if (r->spins.empty()) return fail(PHIA_ESTATE, "no steps ran");
+    std::memcpy(spins, r->spins.data(), r->spins.size());
+    return PHIA_OK;
+}
+
+phia_status phia_server_cancel(phia_server* s, uint64_t ticket)
+{
+    clear_error();
+    if (!s) return fail(PHIA_EINVAL, "null argument");
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->all.find(ticket);
+        if (it == s->all.end()) return fail(PHIA_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+        it->second->cancel = true;
+    }
+    s->cv_work.notify_one();
+    return PHIA_OK;
+}
+
+void phia_server_destroy(phia_server* s)
+{
+    if (!s) return;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (Request* r : s->pending) r->cancel = true;
+        for (Request* r : s->running) r->cancel = true;
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->worker.joinable()) s->worker.join();
+    (void)hipSetDevice(s->dev);
+    for (auto& kv : s->all) delete kv.second;
+    if (s->dtab) (void)hipFree(s->dtab);
+    if (s->host_res) (void)hipHostFree(s->host_res);
+    if (s->st) (void)hipStreamDestroy(s->st);
+    delete s;
+}
+
+}  // extern "C"

@@ -101,3 +101,70 @@ def random_field_pm1(N, seed):
     """Integer fields in {-1, 0, 1} drawn independently (used to add h to an
     integer coupling family)."""
     return rng(seed).integers(-1, 2, size=N).astype(np.float64)
+
+
+def planted_loops(N, seed, alpha=0.4, dense=False, min_len=4):
+    """Planted-solution instance from frustrated loops (Hen et al., PRA 92,
+    042325, 2015), in the convention E = -sum_{i<j} J_ij s_i s_j.
+
+    Loops are cycles cut out of random walks (no immediate backtracking) on a
+    base graph -- a random 3-regular graph (sparse) or the complete graph
+    (dense).  Each loop adds +1 to the couplings of its edges except one
+    random edge, which gets -1: with all spins +1 the loop satisfies every
+    bond but one, which is the best any configuration can do on a frustrated
+    cycle, so the sum over loops is minimised by s = +1 with energy
+    -sum_loops (len - 2).  A random gauge t (J_ij -> t_i t_j J_ij) hides the
+    solution: the planted state is t with the same energy.
+
+    Returns (J, h, E_planted, t) with h = 0 and integer couplings.
+    """
+    g = rng(seed)
+    if dense:
+        def step(u, prev):
+            while True:
+                w = int(g.integers(0, N))
+                if w != u and w != prev:
+                    return w
+    else:
+        M = N + (N % 2)
+        base, _ = regular3_pm1(M, int(g.integers(0, 2**31)), with_field=False)
+        nbrs = [np.nonzero(base[i])[0][np.nonzero(base[i])[0] < N] for i in range(N)]
+
+        def step(u, prev):
+            cand = [int(w) for w in nbrs[u] if w != prev]
+            if not cand:
+                cand = [int(w) for w in nbrs[u]]
+            return cand[int(g.integers(0, len(cand)))]
+    J = np.zeros((N, N))
+    E = 0
+    loops = 0
+    target = max(1, int(round(alpha * N)))
+    tries = 0
+    while loops < target and tries < 100 * target:
+        tries += 1
+        start = int(g.integers(0, N))
+        path, pos, prev = [start], {start: 0}, -1
+        u = start
+        for _ in range(4 * N):
+            w = step(u, prev)
+            if w in pos:
+                cyc = path[pos[w]:]
+                break
+            pos[w] = len(path)
+            path.append(w)
+            prev, u = u, w
+        else:
+            continue
+        if len(cyc) < min_len:
+            continue
+        edges = [(cyc[i], cyc[(i + 1) % len(cyc)]) for i in range(len(cyc))]
+        bad = int(g.integers(0, len(edges)))
+        for e_i, (a, b) in enumerate(edges):
+            v = -1.0 if e_i == bad else 1.0
+            J[a, b] += v
+            J[b, a] += v
+        E -= len(cyc) - 2
+        loops += 1
+    t = g.integers(0, 2, size=N) * 2.0 - 1.0
+    J = J * np.outer(t, t)
+    return J, np.zeros(N), int(E), t.astype(np.int8)

@@ -28,7 +28,11 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
 EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_get_state",
            "phia_set_state", "phia_get_info", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
-           "phia_batch_run", "phia_destroy", "phia_last_error", "phia_version")
+           "phia_batch_run", "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
+           "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
+           "phia_destroy", "phia_last_error", "phia_version")
+
+REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, -1
 
 
 class PhiaError(RuntimeError):
@@ -45,6 +49,15 @@ class Options(C.Structure):
 class Schedule(C.Structure):
     _fields_ = [("beta0", C.c_float), ("beta1", C.c_float), ("betas", C.c_void_p),
                 ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64)]
+
+
+class Result(C.Structure):
+    _fields_ = [("state", C.c_int32), ("success", C.c_int32), ("frac_bits", C.c_int32), ("replica", C.c_int32),
+                ("energy_units", C.c_int64), ("steps_used", C.c_int64), ("t_arrive", C.c_double),
+                ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
 
 
 class Info(C.Structure):
@@ -74,6 +87,13 @@ def _declare(lib):
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
         "phia_batch_run": [P, I32, P, P, P, P],
+        "phia_server_create": [C.c_size_t, I32, I32, I32, P],
+        "phia_server_submit": [P, P, I32, I64, I64, P, U64, P],
+        "phia_server_poll": [P, U64, P],
+        "phia_server_footprint": [P, I32, I64, P],
+        "phia_server_wait": [P, U64, C.c_double, P],
+        "phia_server_spins": [P, U64, P],
+        "phia_server_cancel": [P, U64],
     }
     for name, args in sig.items():
         f = getattr(lib, name)
@@ -81,6 +101,8 @@ def _declare(lib):
         f.restype = C.c_int
     lib.phia_destroy.argtypes = [P]
     lib.phia_destroy.restype = None
+    lib.phia_server_destroy.argtypes = [P]
+    lib.phia_server_destroy.restype = None
     lib.phia_last_error.restype = C.c_char_p
     lib.phia_version.restype = C.c_char_p
 
@@ -261,6 +283,68 @@ def batch_run(problems, replicas, steps, schedules, seeds):
     for p, r in zip(problems, reps):
         p.R = int(r)
     del keep
+
+
+def server_footprint(problem, replicas, max_steps):
+    b = C.c_size_t()
+    _check(lib().phia_server_footprint(problem._p, int(replicas), int(max_steps), C.byref(b)))
+    return b.value
+
+
+class Server:
+    """Continuous-batching annealing server (phia_server)."""
+
+    def __init__(self, hbm_budget, max_slots=64, chunk_steps=1000, device=0):
+        s = C.c_void_p()
+        _check(lib().phia_server_create(int(hbm_budget), int(max_slots), int(chunk_steps), int(device),
+                                        C.byref(s)))
+        self._s = s
+        self._keep = {}
+
+    def submit(self, problem, replicas, max_steps, target, eps, gamma, beta0=None, beta1=None, betas=None,
+               refresh_L=50, seed=0):
+        sch = make_schedule(max_steps, eps, gamma, beta0, beta1, betas, refresh_L)
+        t = C.c_uint64()
+        _check(lib().phia_server_submit(self._s, problem._p, int(replicas), int(max_steps), int(target),
+                                        C.byref(sch), int(seed), C.byref(t)))
+        self._keep[t.value] = (problem, sch)
+        return t.value
+
+    def poll(self, ticket):
+        r = Result()
+        _check(lib().phia_server_poll(self._s, int(ticket), C.byref(r)))
+        return r.as_dict()
+
+    def wait(self, ticket, timeout=-1.0):
+        r = Result()
+        _check(lib().phia_server_wait(self._s, int(ticket), float(timeout), C.byref(r)))
+        return r.as_dict()
+
+    def spins(self, ticket):
+        p = self._keep[ticket][0]
+        out = np.zeros(p.N, np.int8)
+        _check(lib().phia_server_spins(self._s, int(ticket), _ptr(out)))
+        return out
+
+    def cancel(self, ticket):
+        _check(lib().phia_server_cancel(self._s, int(ticket)))
+
+    def close(self):
+        if getattr(self, "_s", None):
+            lib().phia_server_destroy(self._s)
+            self._s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def eval_fmath(kind, values=None, quads=None, seed=0, device=0):

@@ -304,3 +304,88 @@ def test_batch_matches_single_runs_and_oracle(P, O):
             assert got[0][-1] == o.bestE[0] and np.array_equal(got[3][-1], o.x[0]), specs[i]
         q.close()
         p.close()
+
+
+def _serve_specs():
+    out = []
+    for i, (N, dense, R, T) in enumerate([(40, False, 32, 900), (120, True, 16, 1200), (300, False, 20, 700),
+                                          (600, False, 32, 500), (90, True, 64, 400)]):
+        J, h, E, t = inst.planted_loops(N, 50 + i, alpha=0.4, dense=dense)
+        out.append((J, h, E, R, T, 77 + i))
+    return out
+
+
+def _serve(P, specs, max_slots, budget=1 << 36, chunk=100):
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    srv = P.Server(budget, max_slots=max_slots, chunk_steps=chunk)
+    probs, tickets = [], []
+    for J, h, E, R, T, seed in specs:
+        p = P.Problem(J, h, path="i8")
+        probs.append(p)
+        tickets.append(srv.submit(p, R, T, E, seed=seed, **sched))
+    res = [srv.wait(t, 120.0) for t in tickets]
+    spins = [srv.spins(t) for t in tickets]
+    srv.close()
+    for p in probs:
+        p.close()
+    return res, spins
+
+
+def test_server_result_same_alone_and_in_mix(P, O):
+    """Continuous batching: every request gives the same result (energy,
+    replica, steps used, success, best state) alone and in a mix of batched
+    small instances and a column-split large one."""
+    specs = _serve_specs()
+    alone = [_serve(P, [sp], 1) for sp in specs]
+    mix, mix_spins = _serve(P, specs, 8)
+    for i, ((res1, sp1), r2, s2) in enumerate(zip(alone, mix, mix_spins)):
+        r1 = res1[0]
+        say("request", i, r1, r2)
+        assert r1["state"] == P.REQ_DONE and r2["state"] == P.REQ_DONE
+        for key in ("success", "energy_units", "replica", "steps_used"):
+            assert r1[key] == r2[key], (i, key)
+        assert np.array_equal(sp1[0], s2)
+        J, h, E = specs[i][0], specs[i][1], specs[i][2]
+        assert O.energy(J.astype(np.int32), h.astype(np.int32), s2) == r2["energy_units"]
+        assert r2["energy_units"] >= E
+        assert r2["success"] == (r2["energy_units"] <= E)
+    # a request that ran its whole budget equals a plain anneal of that many steps
+    J, h, E, R, T, seed = specs[3]
+    if mix[3]["steps_used"] == T:
+        p = P.Problem(J, h, path="i8")
+        p.anneal(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=25, seed=seed)
+        assert p.best_exact()[0] == mix[3]["energy_units"]
+        p.close()
+
+
+def test_server_budget_forces_queueing_and_cancel(P, O):
+    specs = []
+    for i in range(3):
+        J, h, E, t = inst.planted_loops(100, 200 + i, alpha=0.4)
+        specs.append((J, h, E, 16, 300, 5 + i))
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    probs = [P.Problem(J, h, path="i8") for J, h, E, R, T, s in specs]
+    # budget below any two footprints: requests run one after another
+    fps = [P.server_footprint(p, R, T) for p, (J, h, E, R, T, s) in zip(probs, specs)]
+    assert max(fps) < min(fps) * 2
+    srv = P.Server(int(max(fps) * 1.2), max_slots=8, chunk_steps=100)
+    tickets = [srv.submit(p, R, T, -10**9, seed=s, **sched) for p, (J, h, E, R, T, s) in zip(probs, specs)]
+    res = [srv.wait(t, 120.0) for t in tickets]
+    for a, b in zip(res, res[1:]):
+        assert b["t_admit"] >= a["t_done"]
+    assert all(r["state"] == P.REQ_DONE and r["success"] == 0 for r in res)
+    srv.close()
+    # cancel a long running request; the other one is unaffected
+    srv = P.Server(1 << 36, max_slots=8, chunk_steps=50)
+    t_long = srv.submit(probs[0], 32, 200000, -10**9, seed=1, **sched)
+    t_short = srv.submit(probs[1], 16, 300, -10**9, seed=2, **sched)
+    r_short = srv.wait(t_short, 60.0)
+    srv.cancel(t_long)
+    r_long = srv.wait(t_long, 60.0)
+    assert r_long["state"] == P.REQ_CANCELLED and r_long["steps_used"] < 200000
+    srv.close()
+    ref = _serve(P, [(specs[1][0], specs[1][1], -10**9, 16, 300, 2)], 1, chunk=50)[0][0]
+    assert r_short["state"] == P.REQ_DONE
+    assert ref["energy_units"] == r_short["energy_units"] and ref["steps_used"] == r_short["steps_used"]
+    for p in probs:
+        p.close()

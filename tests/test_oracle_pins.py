@@ -345,3 +345,16 @@ def test_negation_symmetry_without_field(O):
     a, b = runs[0][0], runs[1][0]
     assert np.array_equal(a.x, -b.x) and np.array_equal(a.v, -b.v)
     assert np.array_equal(a.Etrace, b.Etrace)
+
+
+@pytest.mark.parametrize("dense", [False, True])
+def test_planted_loops_energy_is_the_ground_state(O, dense):
+    """Frustrated-loop planting: the gauge state t has the planted energy and
+    exhaustive search finds nothing lower (N = 14)."""
+    for seed in range(3):
+        J, h, E, t = inst.planted_loops(14, seed, alpha=0.6, dense=dense)
+        Ji = J.astype(np.int32)
+        assert np.array_equal(J, J.T) and np.all(np.diag(J) == 0)
+        assert O.energy(Ji, h.astype(np.int32), t) == E
+        Eg, _ = O.bruteforce(Ji, h.astype(np.int32))
+        assert Eg == E
