@@ -50,6 +50,11 @@ WORKLOADS = {
                       sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
                       desc="batch of 4096 instances, N uniform in [32,512], even ids SK +-1 (h=0), odd ids random "
                            "3-regular +-1 with h in {-1,0,1}; 32 replicas x 5000 steps each, one graph launch"),
+    "serve": dict(gen="serve", args=dict(rate=200.0, nmin=100, nmax=4000, seed=0), R=64, T=20000,
+                  sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
+                  desc="serving: Poisson arrivals at 200 req/s, planted frustrated-loop instances, N log-uniform "
+                       "in [100,4000], half dense / half sparse, half integer / half fixed point (2^-4); 64 replicas, "
+                       "stop at the planted energy or 2e4 steps"),
     "sk2000": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=5, bits=8), R=512, T=20000,
                    sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
                    desc="SK N=2000 J~N(0,1) 8-bit fixed point (2^-5), h in [-1,1], 512 replicas x 2e4 steps"),
@@ -155,6 +160,62 @@ def make_batch(count, nmin, nmax, seed):
     return out
 
 
+def make_requests(count, rate, nmin, nmax, seed):
+    """Arrival times and planted instances of the serving workload."""
+    import numpy as np
+    from paper_2407_10205_amd import instances as inst
+    g = inst.rng(seed)
+    gaps = g.exponential(1.0 / rate, size=count)
+    sizes = np.rint(np.exp(g.uniform(np.log(nmin), np.log(nmax), size=count))).astype(int)
+    reqs = []
+    for i in range(count):
+        dense = i % 2 == 1
+        fixed = (i // 2) % 2 == 1
+        J, h, E, t = inst.planted_loops(int(sizes[i]), 20_000 + i, alpha=0.4, dense=dense)
+        f = 0
+        if fixed:  # the same instance held in fixed point: J / 16 on the 2^-4 grid
+            J, f = J / 16.0, 4
+        reqs.append(dict(arrive=float(np.cumsum(gaps)[i]), J=J, h=h, target=E, frac_bits=f, N=int(sizes[i]),
+                         dense=dense))
+    return reqs
+
+
+def run_serve_bench(args, w):
+    """Latency and throughput of the continuous-batching server."""
+    import numpy as np
+    from paper_2407_10205_amd import phia
+    t = time.perf_counter()
+    reqs = make_requests(args.requests, **w["args"])
+    probs = [phia.Problem(r["J"], r["h"], frac_bits=r["frac_bits"], path="i8") for r in reqs]
+    log(f"prepared {len(reqs)} requests in {time.perf_counter() - t:.1f} s")
+    R, T, s = w["R"], w["T"], w["sched"]
+    srv = phia.Server(200 << 30, max_slots=args.slots, chunk_steps=args.chunk)
+    tickets = []
+    t0 = time.perf_counter()
+    for r, p in zip(reqs, probs):
+        delay = r["arrive"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        tickets.append(srv.submit(p, R, T, r["target"], seed=17, **s))
+    res = [srv.wait(tk) for tk in tickets]
+    srv.close()
+    lat = np.array([x["t_done"] - x["t_arrive"] for x in res])
+    su = float(sum(R * r["N"] * x["steps_used"] for r, x in zip(reqs, res)))
+    span = max(x["t_done"] for x in res) - min(x["t_arrive"] for x in res)
+    ok = np.array([x["success"] for x in res], bool)
+    out = {"metric": "spin-updates/s", "value": su / span, "unit": "spin-updates/s", "n_gpus": 1,
+           "steps": len(reqs), "warmup": 0, "ms_per_step": 1000 * span / len(reqs), "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "config": {"workload": w["desc"], "requests": len(reqs), "replicas": R, "max_steps": T,
+                      "slots": args.slots, "chunk_steps": args.chunk, "offered_rate_per_s": w["args"]["rate"]},
+           "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
+           "latency_p50_success_s": float(np.percentile(lat[ok], 50)) if ok.any() else None,
+           "latency_p99_success_s": float(np.percentile(lat[ok], 99)) if ok.any() else None,
+           "success_rate": float(ok.mean()), "mean_steps_used": float(np.mean([x["steps_used"] for x in res])),
+           "roofline": None, "cpu_baseline": None}
+    print(json.dumps(out), flush=True)
+
+
 def run_batch_bench(args, w):
     """Throughput of the batched sweep: one step = the whole batch."""
     import numpy as np
@@ -240,6 +301,9 @@ def main():
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise rocprofv3 outputs in DIR/{stats,fetch,write} and exit")
     ap.add_argument("--geometry-out", metavar="FILE", help="write the launch geometry used to FILE")
+    ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
+    ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
+    ap.add_argument("--chunk", type=int, default=500, help="serving workload: steps per scheduling round")
     args = ap.parse_args()
     if args.summarize_profiles:
         res = summarize_profiles(args.summarize_profiles, WORKLOADS[args.workload]["desc"])
@@ -262,6 +326,9 @@ def main():
     w = WORKLOADS[args.workload]
     if w["gen"] == "batch":
         run_batch_bench(args, w)
+        return
+    if w["gen"] == "serve":
+        run_serve_bench(args, w)
         return
     J, h = make_instance(w)
     N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]
