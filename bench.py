@@ -62,7 +62,7 @@ WORKLOADS = {
 
 
 KERNEL_SRC = os.path.join(ROOT, "paper_2407_10205_amd", "csrc", "phia_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_sweep_mfma_maxcut800_traffic.json")
+PROFILES = os.path.join(ROOT, "profiles")
 COPY_BYTES = 256 << 20  # plain device copy used to calibrate the byte counters
 
 
@@ -75,11 +75,15 @@ def kernel_sha():
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def recorded_traffic(workload, geometry):
+def traffic_file(kernel, workload_name):
+    return os.path.join(PROFILES, f"{kernel}_{workload_name}_traffic.json")
+
+
+def recorded_traffic(kernel, workload_name, workload, geometry):
     """HBM bytes per sweep launch from the committed counter summary, or None
     when the kernel source or the launch geometry changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(kernel, workload_name)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -372,13 +376,16 @@ def main():
     Np = info["Np"]
     mfma_ops = 2.0 * Np * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
     mfma_peak = INT8_MFMA_PEAK if info["path_name"] == "i8" else BF16_MFMA_PEAK * 0.5
-    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds")}
+    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel")}
+    kernel = ("k_sweep_fp32" if info["path_name"] == "fp32" else
+              "k_sweep_pp" if info["sweep_kernel"] == 1 else "k_sweep_mfma")
     if args.geometry_out:
         with open(args.geometry_out, "w") as f:
             json.dump(geometry, f)
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_OPS_PEAK, "unit": "ops/s",
-                "frac": achieved / VALU_OPS_PEAK, "traffic": recorded_traffic(w["desc"], geometry),
-                "kernel": "k_sweep_mfma" if info["path_name"] != "fp32" else "k_sweep_fp32",
+                "frac": achieved / VALU_OPS_PEAK,
+                "traffic": recorded_traffic(kernel, args.workload, w["desc"], geometry),
+                "kernel": kernel,
                 "kernel_ms": kern_ms, "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
                 "mfma_executed_ops_per_s": mfma_ops / (kern_ms / 1000),
                 "mfma_frac_of_peak": (mfma_ops / (kern_ms / 1000)) / mfma_peak}
@@ -416,7 +423,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
                    "schedule": s, "group": info["group"], "rows_per_block": info["rows_per_block"],
-                   "j_in_lds": info["j_in_lds"], "autotune_us_per_step": tuned_us},
+                   "j_in_lds": info["j_in_lds"], "sweep_kernel": kernel, "autotune_us_per_step": tuned_us},
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }
     print(json.dumps(out), flush=True)

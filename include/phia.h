@@ -86,6 +86,10 @@ typedef struct {
     int32_t replicas;       /* R of the current anneal (0 if none)                   */
     int32_t rows_per_block; /* replicas per workgroup block                          */
     int32_t j_in_lds;       /* 1: each workgroup's coupling slice resides in LDS     */
+    int32_t sweep_kernel;   /* 0: one replica block per workgroup; 1: two 16-replica
+                               sub-blocks per workgroup whose steps alternate, so
+                               the column-split exchange of one overlaps the
+                               other's compute                                      */
     int64_t steps;          /* T of the current anneal                               */
     int64_t step;           /* next step to run                                      */
     int64_t max_abs_J;      /* max |J| in units                                      */

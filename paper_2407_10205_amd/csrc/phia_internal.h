@@ -44,7 +44,7 @@ struct SweepArgs {
     int32_t xcd_map;            // 1: group members share blockIdx % 8
     int32_t j_lds;              // 1: J slice resident in LDS, 0: read from global
     // group exchange (G > 1)
-    uint64_t* xbits;            // [2][ngroups][rows][Np/16] (seq << 32) | 16 sign bits
+    uint64_t* xbits;            // [2][ngroups][rows][Np/16] tagged sign words
     uint64_t* pbuf;             // [2][ngroups][G][rows][2] (seq << 32) | 32-bit half of a partial energy
     uint32_t seq_base;          // sequence number before this launch (tags start at seq_base + 1)
     int32_t* err;               // device error word (1 = barrier timeout)
@@ -71,6 +71,12 @@ hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const 
 hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                              hipStream_t st);
 int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, size_t lds_bytes);
+// interleaved group sweep: int8 J, two 16-replica sub-blocks per workgroup
+constexpr int kPpMaxNcb = 256;            // Np <= 4096
+constexpr int64_t kPpMaxRowSum = 1 << 18;  // 32 * max_i(sum_j |J_ij| + |h_i|) < 2^23
+size_t sweep_pp_lds_bytes(int Np, int G);
+hipError_t launch_sweep_pp(const SweepArgs& a, size_t lds_bytes, hipStream_t st);
+int max_coresident_pp(int ncb, size_t lds_bytes);
 // batch mode: 16-replica work items, one workgroup each, up to 512 columns
 constexpr int kBatchMaxNp = kWaves * 4 * 16;
 hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st);

@@ -550,7 +550,6 @@ k_sweep_mfma(SweepArgs args)
         col[cw] = (cb0 + c) * 16 + lr;
         hreg[cw] = (cval[cw] && col[cw] < Np) ? a.h[col[cw]] : 0;
     }
-    const int nkb = Np / 64;
     const float eps = a.eps, gamma = a.gamma;
     const int nsteps = static_cast<int>(a.k1 - a.k0);
     const uint32_t seq_stride = static_cast<uint32_t>(nsteps + 1);
@@ -848,6 +847,481 @@ k_sweep_mfma(SweepArgs args)
         }
         __syncthreads();
     }
+}
+
+// ------------------------------------------ interleaved group sweep --
+// Column-split int8 sweep in which every workgroup carries two 16-replica
+// sub-blocks whose steps alternate.  The spins a sub-block publishes travel
+// to the other members of its group while the workgroup computes the other
+// sub-block, so the exchange latency hides behind matrix-core and kick work.
+// Host-checked requirements: at most kWaves column blocks per member (wave w
+// owns column block cb0 + w of both sub-blocks), Np / 16 <= 32 * NU,
+// 32 * max_i(sum_j |J_ij| + |h_i|) < 2^23 (a 16-column partial energy fits 24
+// bits) and 2 N max_i(...) < 2^31 (a row's energy sum fits int32).  With
+// NKB > 0 (Np <= 64 NKB) a wave keeps its column block of J in VGPRs as NKB
+// MFMA operand fragments for the whole launch; with NKB = 0 the member's J
+// slice sits in LDS.
+//
+// Exchange word of (sub-block, replica row, column block), 64 bits:
+//   [63:40] low 24 bits of the publication's sequence number (tag)
+//   [39:16] sum over the block's 16 columns of s_i (I_i + h_i) of the
+//           previous step, signed 24-bit
+//   [15:0]  spins, bit t set: spin +1
+// Publication q (q = 0 .. nsteps) of a sub-block carries the spins of step
+// k0 + q and the partial energies of step k0 + q - 1; the last one (q =
+// nsteps) repeats the spins of step k1 - 1, which nothing reads.  Sequence
+// numbers of consecutive publications are consecutive (also across replica
+// block iterations and launches), and publication seq lives in the slot of
+// parity seq & 1: a slot is rewritten two publications later, after every
+// member has read it.
+struct PpPlan {
+    uint32_t j_off, s_off, s_bytes, e_off, b_off, k_off, misc_off, total;
+};
+
+// S row stride: Np bytes, or 64 NKB bytes when the MFMA loop reads NKB
+// k blocks unconditionally (bytes past Np meet zero J fragments), plus 16.
+__host__ __device__ inline uint32_t pp_srow(int Np, int nkb_regs)
+{
+    return static_cast<uint32_t>(nkb_regs > 0 ? 64 * nkb_regs : Np) + 16u;
+}
+
+__host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs)
+{
+    PpPlan p;
+    p.j_off = 0;
+    p.s_off = nkb_regs > 0 ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
+    p.s_bytes = 16u * pp_srow(Np, nkb_regs);
+    p.e_off = p.s_off + 2u * p.s_bytes;  // [2][16] energy sums of the previous step
+    p.b_off = p.e_off + 2u * 16u * 8u;   // [2 sub-blocks][2 parities][16] best energies
+    p.k_off = p.b_off + 4u * 16u * 8u;   // [2][16] step of the best energy
+    p.misc_off = p.k_off + 2u * 16u * 8u;
+    p.total = p.misc_off + 16u;
+    return p;
+}
+
+// Sum over the 16 lanes of a DPP row (lanes sharing lane / 16), result in
+// every lane of the row.  All 64 lanes must be active.
+__device__ __forceinline__ int row_sum16_dpp(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);  // row_mirror
+    return v;
+}
+
+// Gather mapping: thread t reads the words of replica row t / 32, column
+// blocks t % 32 + 32 u, u < NU; a column block past the end reads the last
+// one instead (a valid word, ignored afterwards), so every load is issued
+// unconditionally.
+template <int NU>
+__device__ __forceinline__ void pp_issue(const uint64_t* Xs, int ncb, int row, int c0, uint64_t (&w)[NU])
+{
+#pragma unroll
+    for (int u = 0; u < NU; ++u) {
+        const int c = min(c0 + 32 * u, ncb - 1);
+        w[u] = __hip_atomic_load(Xs + row * ncb + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+template <int NU>
+__device__ __forceinline__ uint32_t pp_stale(uint32_t tag, const uint64_t (&w)[NU])
+{
+    uint32_t m = 0;
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
+        if (static_cast<uint32_t>(w[u] >> 40) != tag) m |= 1u << u;
+    return m;
+}
+
+// Re-read the words that still carry an older tag until all are current.
+// The loop is uniform over the wave.  Returns false after kSpinLimit polls
+// or once another workgroup has raised the device error word (then this
+// one raises it too).
+template <int NU>
+__device__ __forceinline__ bool pp_complete(const uint64_t* Xs, int ncb, int row, int c0, uint32_t tag,
+                                            uint64_t (&w)[NU], int32_t* err)
+{
+    uint32_t stale = pp_stale<NU>(tag, w);
+    uint32_t polls = 0;
+    while (__any(stale != 0)) {
+        ++polls;
+        if (polls > kSpinLimit ||
+            ((polls & 255u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
+            __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int c = min(c0 + 32 * u, ncb - 1);
+            if ((stale >> u) & 1u)
+                w[u] = __hip_atomic_load(Xs + row * ncb + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        stale = pp_stale<NU>(tag, w);
+    }
+    return true;
+}
+
+// A wave that owns a column block stores the words of its 16 replica rows:
+// lane (lr, lg) with lr < 4 stores row 4 lg + lr, taking the spins from
+// ballot lr and the row's partial energy p_lr (each p_j is present in every
+// lane of its DPP row).
+__device__ __forceinline__ void pp_publish(uint64_t* Xs, int ncb, int cblk, int lr, int lg, const float (&x)[4],
+                                           int p0, int p1, int p2, int p3, uint32_t tag)
+{
+    const uint64_t b0 = __ballot(x[0] >= 0.0f), b1 = __ballot(x[1] >= 0.0f);
+    const uint64_t b2 = __ballot(x[2] >= 0.0f), b3 = __ballot(x[3] >= 0.0f);
+    const bool odd = (lr & 1) != 0, high = (lr & 2) != 0;
+    const uint64_t b = high ? (odd ? b3 : b2) : (odd ? b1 : b0);
+    const int pe = high ? (odd ? p3 : p2) : (odd ? p1 : p0);
+    const uint64_t word = (static_cast<uint64_t>(tag) << 40) |
+                          (static_cast<uint64_t>(static_cast<uint32_t>(pe) & 0xffffffu) << 16) |
+                          ((b >> (16 * lg)) & 0xffffu);
+    if (lr < 4)
+        __hip_atomic_store(Xs + (4 * lg + lr) * ncb + cblk, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// I = S . J^T + h for one 16x16 tile, J fragments in VGPRs.  All NKB
+// operand loads are issued before the first product; k blocks at or past
+// nkb read S padding against zero J fragments and add nothing.
+template <int NKB>
+__device__ __forceinline__ void quasi_gradient_regj(const unsigned char* S, uint32_t srow, const v4i (&jr)[NKB],
+                                                    int nkb, int lr, int lg, int h, int (&I)[4])
+{
+    v4i A[NKB];
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) A[kb] = *reinterpret_cast<const v4i*>(S + lr * srow + kb * 64 + 16 * lg);
+    v4i acc = v4i{0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[kb], jr[kb], acc, 0, 0, 0);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) I[j] = acc[j] + h;
+}
+
+template <int NU, int NKB>
+__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_pp(SweepArgs a)
+{
+    extern __shared__ __align__(16) unsigned char lds[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lr = lane & 15, lg = lane >> 4;
+    const int Np = a.Np, N = a.N, ncb = a.ncb, G = a.G;
+    int group, member;
+    if (a.xcd_map) {
+        const int w = blockIdx.x, pos = w >> 3;
+        member = pos % G;
+        group = (pos / G) * 8 + (w & 7);
+    } else {
+        member = blockIdx.x % G;
+        group = blockIdx.x / G;
+    }
+    const int cb0 = member * ncb / G, cb1 = (member + 1) * ncb / G, cbs = cb1 - cb0;
+    const PpPlan P = pp_plan(Np, (ncb + G - 1) / G, NKB);
+    const uint32_t srow = pp_srow(Np, NKB);
+    const uint32_t cbb = cb_bytes(kPathI8, Np);
+    const int nkb = Np / 64;
+    unsigned char* sJ = lds + P.j_off;
+    int64_t* sEt = reinterpret_cast<int64_t*>(lds + P.e_off);
+    int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);
+    int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);
+    int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
+    // J of the wave's column block: VGPR fragments (NKB > 0) or the LDS slice.
+    v4i jr[NKB > 0 ? NKB : 1];
+    if (NKB > 0) {
+        const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0 + wave) * cbb;
+#pragma unroll
+        for (int kb = 0; kb < (NKB > 0 ? NKB : 1); ++kb)
+            jr[kb] = (wave < cbs && kb < nkb) ? *reinterpret_cast<const v4i*>(Jw + kb * 1024 + lane * 16)
+                                              : v4i{0, 0, 0, 0};
+    } else {
+        const uint32_t nvec = static_cast<uint32_t>(cbs) * cbb / 16u;
+        const uint4* src = reinterpret_cast<const uint4*>(static_cast<const unsigned char*>(a.J) +
+                                                          static_cast<size_t>(cb0) * cbb);
+        uint4* dst = reinterpret_cast<uint4*>(sJ);
+        for (uint32_t q = tid; q < nvec; q += kThreads) dst[q] = src[q];
+    }
+    if (tid == 0) *sAbort = 0;
+
+    const bool cval = wave < cbs;  // this wave owns a column block
+    const int cblk = cb0 + wave;
+    const int col = cblk * 16 + lr;
+    const int hreg1[1] = {cval ? a.h[col] : 0};
+    const bool creal = cval && col < N;
+    const int grow = tid >> 5, gc0 = tid & 31;
+    const float eps = a.eps, gamma = a.gamma;
+    const int nsteps = static_cast<int>(a.k1 - a.k0);
+    const uint32_t seq_stride = static_cast<uint32_t>(nsteps + 1);
+    const int64_t ref0 = a.k0 + (a.L - a.k0 % a.L) % a.L;
+    const size_t plane = static_cast<size_t>(16) * ncb;
+    int iter = 0;
+
+    for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
+        const int64_t rb0 = static_cast<int64_t>(blk) * 32;
+        // word arrays of (parity, sub-block)
+        auto xs = [&](uint32_t seq, int sb) -> uint64_t* {
+            return a.xbits + ((static_cast<size_t>(seq & 1u) * a.ngroups + group) * 2 + sb) * plane;
+        };
+        for (int q = tid; q < 32; q += kThreads) {
+            const int sb = q >> 4, r = q & 15;
+            const bool ok = rb0 + q < a.R;
+            const int64_t b = ok ? a.bestE[rb0 + q] : INT64_MAX;
+            sB[(sb * 2 + 0) * 16 + r] = b;
+            sB[(sb * 2 + 1) * 16 + r] = b;
+            sK[q] = ok ? a.bestStep[rb0 + q] : -1;
+        }
+        float x[2][4], v[2][4];
+        uint32_t bestbits = 0, pm = 0;
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gr = rb0 + sb * 16 + 4 * lg + j;
+                const bool ok = cval && gr < a.R;
+                x[sb][j] = ok ? a.x[gr * Np + col] : 0.0f;
+                v[sb][j] = ok ? a.v[gr * Np + col] : 0.0f;
+                if (ok && creal && a.bestS[gr * Np + col] > 0) bestbits |= 1u << (sb * 4 + j);
+            }
+
+        const uint32_t seq0 = a.seq_base + static_cast<uint32_t>(iter) * seq_stride + 1u;
+        int64_t next_ref = ref0;
+        uint64_t round = static_cast<uint64_t>(ref0 / a.L);
+        bool aborted = false;
+        uint64_t w[NU];
+
+        // Momentum refresh of sub-block sb's owned elements for step kr.
+        auto refresh = [&](int sb) {
+#pragma unroll 1
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gr = rb0 + sb * 16 + 4 * lg + j;
+                const float g = (creal && gr < a.R) ? gauss_v(a.seed, a.r_base + gr, round, col) : 0.0f;
+                if (j == 0) v[sb][0] = g;
+                else if (j == 1) v[sb][1] = g;
+                else if (j == 2) v[sb][2] = g;
+                else v[sb][3] = g;
+            }
+        };
+
+        // Publication 0: the drift of step k0.
+        {
+            const bool ref = (a.k0 == next_ref);
+#pragma unroll
+            for (int sb = 0; sb < 2; ++sb) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (x[sb][j] >= 0.0f) pm |= 1u << (sb * 4 + j);
+                if (ref) refresh(sb);
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[sb][j] = __builtin_fmaf(eps, v[sb][j], x[sb][j]);
+                if (cval) pp_publish(xs(seq0, sb), ncb, cblk, lr, lg, x[sb], 0, 0, 0, 0, seq0 & 0xffffffu);
+            }
+            if (ref) {
+                next_ref += a.L;
+                ++round;
+            }
+        }
+        __syncthreads();  // records initialised
+        pp_issue<NU>(xs(seq0, 0), ncb, grow, gc0, w);
+
+        float ck_next = a.ctab[a.k0];
+        for (int s = 0; s <= nsteps; ++s) {
+            const int64_t k = a.k0 + s;
+            const uint32_t seq = seq0 + static_cast<uint32_t>(s);
+            const bool closing = (s == nsteps);
+            const bool drift_next = (s + 1 < nsteps);
+            const bool ref_next = drift_next && (k + 1 == next_ref);
+            const float ck = ck_next;  // c_k, loaded one step ahead
+            ck_next = a.ctab[drift_next ? k + 1 : k];
+            const int par = static_cast<int>(k & 1);
+#pragma unroll
+            for (int X = 0; X < 2; ++X) {
+                unsigned char* S = lds + P.s_off + X * P.s_bytes;
+                // Spins of step k and partial energies of step k - 1.
+                if (!pp_complete<NU>(xs(seq, X), ncb, grow, gc0, seq & 0xffffffu, w, a.err)) *sAbort = 1;
+                int psum = 0;
+#pragma unroll
+                for (int u = 0; u < NU; ++u) {
+                    const int c = gc0 + 32 * u;
+                    if (c < ncb) {
+                        if (!closing) unpack_signs<1>(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 16);
+                        psum += static_cast<int32_t>(static_cast<uint32_t>(w[u] >> 16) << 8) >> 8;
+                    }
+                }
+                if (s > 0) {
+                    // Row total over the 32 lanes of the replica row: DPP row
+                    // sums, then row r - 1 added into rows 1 and 3.
+                    int t = row_sum16_dpp(psum);
+                    t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);  // row_bcast:15
+                    if (gc0 == 31) sEt[X * 16 + grow] = t;
+                }
+                __syncthreads();
+                const int abort_seen = *sAbort;
+                // Records of step k - 1 (App. B, Table 3, state 5); placed after
+                // the products are issued so that they overlap them.
+                auto records = [&]() {
+                    if (s == 0) return;
+                    const int64_t* prev = sB + (X * 2 + (par ^ 1)) * 16;
+                    int64_t* next = sB + (X * 2 + par) * 16;
+                    const bool writer = (wave == 0 && lr == 0);
+                    int64_t Ev[4], Bv[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {  // all reads before any write
+                        Ev[j] = -(sEt[X * 16 + 4 * lg + j] / 2);
+                        Bv[j] = prev[4 * lg + j];
+                    }
+                    uint32_t impm = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (Ev[j] < Bv[j]) impm |= 1u << j;
+                    const uint32_t sel = impm << (4 * X);
+                    bestbits = (bestbits & ~sel) | (pm & sel);
+                    if (writer) {
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const bool imp = (impm >> j) & 1u;
+                            next[4 * lg + j] = imp ? Ev[j] : Bv[j];
+                            if (imp) sK[X * 16 + 4 * lg + j] = k - 1;
+                        }
+                    }
+                };
+                if (closing) {
+                    if (abort_seen) {
+                        aborted = true;
+                        break;
+                    }
+                    records();
+                    if (X == 0) pp_issue<NU>(xs(seq, 1), ncb, grow, gc0, w);
+                    continue;
+                }
+                // Quasi-gradient of step k on matrix cores.
+                int I[1][1][4] = {};
+                if (cval) {
+                    if (NKB > 0)
+                        quasi_gradient_regj<(NKB > 0 ? NKB : 1)>(S, srow, jr, nkb, lr, lg, hreg1[0], I[0][0]);
+                    else
+                        quasi_gradient<kPathI8, 1, 1, 1>(S, srow, sJ + static_cast<size_t>(wave) * cbb, 0, Np, lane,
+                                                         lr, lg, hreg1, I);
+                }
+                if (abort_seen) {
+                    aborted = true;
+                    break;
+                }
+                records();
+                // Next gather: sub-block 1 of publication s, or sub-block 0
+                // of publication s + 1 (both already published).
+                if (X == 0) pp_issue<NU>(xs(seq, 1), ncb, grow, gc0, w);
+                else pp_issue<NU>(xs(seq + 1u, 0), ncb, grow, gc0, w);
+                if (cval) {
+                    int part[4];
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const int sg = (x[X][j] >= 0.0f) ? 1 : -1;
+                        part[j] = creal ? sg * (I[0][0][j] + hreg1[0]) : 0;
+                        v[X][j] = kick(x[X][j], v[X][j], I[0][0][j], ck, eps, gamma);
+                    }
+                    const int p0 = row_sum16_dpp(part[0]), p1 = row_sum16_dpp(part[1]);
+                    const int p2 = row_sum16_dpp(part[2]), p3 = row_sum16_dpp(part[3]);
+                    uint32_t sg4 = 0;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (x[X][j] >= 0.0f) sg4 |= 1u << j;
+                    pm = (pm & ~(0xfu << (4 * X))) | (sg4 << (4 * X));
+                    if (drift_next) {
+                        if (ref_next) refresh(X);
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) x[X][j] = __builtin_fmaf(eps, v[X][j], x[X][j]);
+                    }
+                    pp_publish(xs(seq + 1u, X), ncb, cblk, lr, lg, x[X], p0, p1, p2, p3, (seq + 1u) & 0xffffffu);
+                }
+            }
+            if (aborted) break;
+            if (ref_next) {
+                next_ref += a.L;
+                ++round;
+            }
+        }
+        if (aborted) return;
+
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t gr = rb0 + sb * 16 + 4 * lg + j;
+                if (!cval || gr >= a.R) continue;
+                a.x[gr * Np + col] = x[sb][j];
+                a.v[gr * Np + col] = v[sb][j];
+                if (creal) a.bestS[gr * Np + col] = ((bestbits >> (sb * 4 + j)) & 1u) ? 1 : -1;
+            }
+        __syncthreads();
+        if (member == 0) {
+            const int fin = static_cast<int>(a.k1 & 1);
+            for (int q = tid; q < 32; q += kThreads)
+                if (rb0 + q < a.R) {
+                    const int sb = q >> 4, r = q & 15;
+                    a.bestE[rb0 + q] = sB[(sb * 2 + fin) * 16 + r];
+                    a.bestStep[rb0 + q] = sK[q];
+                }
+        }
+        __syncthreads();
+    }
+}
+
+// J fragments per wave kept in VGPRs for Np: the k-block count rounded up
+// to even, up to 16 (0: J slice in LDS).
+static int pp_nkb_regs(int Np)
+{
+    const int nkb = Np / 64;
+    return nkb <= 16 ? (nkb + 1) / 2 * 2 : 0;
+}
+
+size_t sweep_pp_lds_bytes(int Np, int G)
+{
+    const int ncb = Np / 16;
+    return pp_plan(Np, (ncb + G - 1) / G, pp_nkb_regs(Np)).total;
+}
+
+static const void* pp_kernel(int ncb)
+{
+    const int Np = 16 * ncb;
+    switch (pp_nkb_regs(Np)) {
+    case 2: return reinterpret_cast<const void*>(k_sweep_pp<1, 2>);
+    case 4: return reinterpret_cast<const void*>(k_sweep_pp<1, 4>);
+    case 6: return reinterpret_cast<const void*>(k_sweep_pp<1, 6>);
+    case 8: return reinterpret_cast<const void*>(k_sweep_pp<1, 8>);
+    case 10: return reinterpret_cast<const void*>(k_sweep_pp<2, 10>);
+    case 12: return reinterpret_cast<const void*>(k_sweep_pp<2, 12>);
+    case 14: return reinterpret_cast<const void*>(k_sweep_pp<2, 14>);
+    case 16: return reinterpret_cast<const void*>(k_sweep_pp<2, 16>);
+    default: break;
+    }
+    if (ncb <= 128) return reinterpret_cast<const void*>(k_sweep_pp<4, 0>);
+    return reinterpret_cast<const void*>(k_sweep_pp<8, 0>);
+}
+
+hipError_t launch_sweep_pp(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    if (a.ncb < 1 || a.ncb > kPpMaxNcb) return hipErrorInvalidValue;
+    const void* kern = pp_kernel(a.ncb);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    SweepArgs copy = a;
+    void* args[] = {&copy};
+    e = hipLaunchCooperativeKernel(kern, dim3(static_cast<unsigned>(a.ngroups * a.G)), dim3(kThreads), args,
+                                   static_cast<unsigned>(lds), st);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+int max_coresident_pp(int ncb, size_t lds)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (ncb < 1 || ncb > kPpMaxNcb) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const void* f = pp_kernel(ncb);
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;
+    return per * cus;
 }
 
 // ------------------------------------------------------------ batching --

@@ -12,6 +12,7 @@ namespace phia {
 // Launch geometry of the MFMA sweep (see k_sweep_mfma).
 struct Geometry {
     bool ok = false;
+    int kind = 0;      // 0: k_sweep_mfma, 1: k_sweep_pp (interleaved sub-blocks)
     int mt = 1;        // 16-replica row tiles per workgroup
     int cbw = 2;       // max 16-column blocks per wave
     int G = 1;         // workgroups splitting the columns of one replica block
@@ -50,6 +51,7 @@ struct phia_problem {
     int N = 0, Np = 0, path = 0, f = 0;
     bool exact = true;
     int64_t maxabsJ = 0;
+    int64_t maxrow = 0;  // max_i (sum_j |J_ij| + |h_i|) in units
     bool poisoned = false;
     // instance
     void* dJ = nullptr;

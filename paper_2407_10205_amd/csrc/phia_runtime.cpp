@@ -168,10 +168,11 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 
 // ------------------------------------------------------- kernel geometry --
 // ------------------------------------------------------- tuning cache --
-// One line per tuned shape: "phia-tune2 path Np R mt cbw G jlds us_per_step".
+// One line per tuned shape: "phia-tune3 path Np R kind mt cbw G jlds us_per_step".
 static const char* tune_cache_path() { return std::getenv("PHIA_TUNE_CACHE"); }
 
 static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g);
+static bool make_geometry_pp(phia_problem* p, int R, int G, Geometry& g);
 
 static bool lookup_tune_cache(phia_problem* p, int R)
 {
@@ -180,13 +181,14 @@ static bool lookup_tune_cache(phia_problem* p, int R)
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char tag[32];
-    int pa, np, r, mt, cbw, G, jl;
+    int pa, np, r, kind, mt, cbw, G, jl;
     double us;
     bool found = false;
     Geometry g;
-    while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &mt, &cbw, &G, &jl, &us) == 9) {
-        if (std::strcmp(tag, "phia-tune2") == 0 && pa == p->path && np == p->Np && r == R &&
-            make_geometry(p, R, mt, cbw, G, jl, g)) {
+    while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &kind, &mt, &cbw, &G, &jl, &us) ==
+           10) {
+        if (std::strcmp(tag, "phia-tune3") == 0 && pa == p->path && np == p->Np && r == R &&
+            (kind == 1 ? make_geometry_pp(p, R, G, g) : make_geometry(p, R, mt, cbw, G, jl, g))) {
             p->geo = g;
             found = true;
         }
@@ -201,7 +203,8 @@ static void append_tune_cache(const phia_problem* p, int R, const Geometry& g, d
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "phia-tune2 %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.mt, g.cbw, g.G, g.j_lds, us);
+    std::fprintf(f, "phia-tune3 %d %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.kind, g.mt, g.cbw, g.G, g.j_lds,
+                 us);
     std::fclose(f);
 }
 
@@ -243,6 +246,37 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     return true;
 }
 
+// Interleaved group sweep (k_sweep_pp): int8 J, blocks of 32 replicas as two
+// alternating 16-replica sub-blocks, G >= 2 workgroups per block with one
+// column block per wave and the J slice in LDS; false if it does not apply.
+static bool make_geometry_pp(phia_problem* p, int R, int G, Geometry& g)
+{
+    const int Np = p->Np, ncb = Np / 16;
+    if (p->path != PHIA_PATH_I8 || p->trace || G < 2 || G > ncb || ncb > kPpMaxNcb) return false;
+    if (p->maxrow >= kPpMaxRowSum || 2 * p->maxrow * p->N >= (int64_t(1) << 31)) return false;
+    if ((ncb + G - 1) / G > kWaves) return false;
+    const size_t lds = sweep_pp_lds_bytes(Np, G);
+    if (lds > static_cast<size_t>(kLdsMax)) return false;
+    const int maxwg = max_coresident_pp(ncb, lds);
+    if (maxwg < G) return false;
+    const int nblocks = (R + 31) / 32;
+    int ngroups = std::min(nblocks, maxwg / G);
+    if (ngroups >= 8) ngroups -= ngroups % 8;
+    g = Geometry{};
+    g.ok = true;
+    g.kind = 1;
+    g.mt = 2;
+    g.cbw = 1;
+    g.G = G;
+    g.j_lds = 1;
+    g.rows = 32;
+    g.nblocks = nblocks;
+    g.ngroups = ngroups;
+    g.xcd_map = (ngroups % 8 == 0) ? 1 : 0;
+    g.lds = lds;
+    return true;
+}
+
 // Every feasible geometry for R replicas (group sizes up to 64 workgroups).
 static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
 {
@@ -259,18 +293,26 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
                     Geometry g;
                     if (make_geometry(p, R, mt, cbw, G, jl, g)) out.push_back(g);
                 }
+        Geometry g;
+        if (make_geometry_pp(p, R, G, g)) out.push_back(g);
     }
     return out;
 }
 
 // Default geometry without tuning: fewest passes over the replica blocks,
 // then the fewest owned elements per workgroup, then J in LDS.
-// PHIA_GEOMETRY="mt,G,jlds" forces one candidate (tuning experiments).
+// PHIA_GEOMETRY="mt,G,jlds[,cbw]" or "pp,G" forces one candidate (tuning
+// experiments).
 static void choose_mfma_geometry(phia_problem* p, int R)
 {
     p->geo.ok = false;
     int f_mt = 0, f_G = 0, f_j = -1, f_c = kCbwMax;
     if (const char* env = std::getenv("PHIA_GEOMETRY")) {
+        if (std::sscanf(env, "pp,%d", &f_G) == 1) {
+            Geometry g;
+            if (make_geometry_pp(p, R, f_G, g)) p->geo = g;
+            return;
+        }
         if (std::sscanf(env, "%d,%d,%d,%d", &f_mt, &f_G, &f_j, &f_c) >= 3) {
             Geometry g;
             if (make_geometry(p, R, f_mt, f_c, f_G, f_j, g)) p->geo = g;
@@ -282,12 +324,19 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         return;
     }
     if (lookup_tune_cache(p, R)) return;
+    // Fewest passes over the replica blocks first; among those a geometry
+    // without column split, else the interleaved kernel with the smallest
+    // group, else the fewest owned elements per workgroup, then J in LDS.
+    const std::vector<Geometry> cands = candidate_geometries(p, R);
+    int min_iters = 1 << 30;
+    for (const Geometry& g : cands) min_iters = std::min(min_iters, (g.nblocks + g.ngroups - 1) / g.ngroups);
     double best = 0;
-    for (const Geometry& g : candidate_geometries(p, R)) {
+    for (const Geometry& g : cands) {
         const int iters = (g.nblocks + g.ngroups - 1) / g.ngroups;
+        if (iters != min_iters) continue;
         const int cbs_max = (p->Np / 16 + g.G - 1) / g.G;
         const double elems = static_cast<double>(g.rows) * cbs_max * 16;
-        const double cost = iters * 1e9 + elems * 2 + (g.j_lds ? 0 : 1);
+        const double cost = g.kind == 1 ? 1e6 + g.G : (g.G > 1 ? 2e6 : 0.0) + elems * 2 + (g.j_lds ? 0 : 1);
         if (!p->geo.ok || cost < best) {
             p->geo = g;
             best = cost;
@@ -418,6 +467,7 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     p->f = f;
     p->exact = exact;
     p->maxabsJ = maxabs;
+    p->maxrow = maxrow;
     const int Np = p->Np;
 
     std::vector<int32_t> hpad(static_cast<size_t>(Np), 0);
@@ -656,6 +706,27 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
     a.k1 = k_end;
     if (p->path == PHIA_PATH_FP32) {
         e = launch_sweep_fp32(a, p->st);
+    } else if (p->geo.kind == 1) {
+        // 24-bit tags: launches of at most `chunk` steps, and the sequence
+        // restarts (with cleared words) before it would wrap.
+        const int64_t iters = (p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups;
+        const int64_t tag_room = (int64_t(1) << 24) - 2;
+        const int64_t chunk = std::min<int64_t>(int64_t(1) << 22, tag_room / iters - 1);
+        for (int64_t k = p->k; k < k_end && e == hipSuccess;) {
+            const int64_t kk = std::min(k_end, k + chunk);
+            const int64_t use = iters * (kk - k + 1);
+            if (static_cast<int64_t>(p->seq) + use > tag_room) {
+                const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * (p->Np / 16) * sizeof(uint64_t);
+                if ((e = hipMemsetAsync(p->dxbits, 0, xb, p->st)) != hipSuccess) break;
+                p->seq = 0;
+            }
+            a.k0 = k;
+            a.k1 = kk;
+            a.seq_base = p->seq;
+            e = launch_sweep_pp(a, p->geo.lds, p->st);
+            p->seq += static_cast<uint32_t>(use);
+            k = kk;
+        }
     } else {
         e = launch_sweep_mfma(p->path, p->geo.mt, p->geo.cbw, a, p->geo.lds, p->st);
         if (p->geo.G > 1) {
@@ -915,6 +986,7 @@ phia_status phia_get_info(const phia_problem* p, phia_info* out)
     out->replicas = p->R;
     out->rows_per_block = p->geo.rows;
     out->j_in_lds = p->geo.j_lds;
+    out->sweep_kernel = p->geo.kind;
     out->steps = p->T;
     out->step = p->k;
     out->max_abs_J = p->maxabsJ;

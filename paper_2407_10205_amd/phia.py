@@ -63,7 +63,8 @@ class Result(C.Structure):
 class Info(C.Structure):
     _fields_ = [("N", C.c_int32), ("Np", C.c_int32), ("path", C.c_int32), ("frac_bits", C.c_int32),
                 ("exact", C.c_int32), ("group", C.c_int32), ("replicas", C.c_int32),
-                ("rows_per_block", C.c_int32), ("j_in_lds", C.c_int32), ("steps", C.c_int64), ("step", C.c_int64),
+                ("rows_per_block", C.c_int32), ("j_in_lds", C.c_int32), ("sweep_kernel", C.c_int32),
+                ("steps", C.c_int64), ("step", C.c_int64),
                 ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t)]
 
 

@@ -244,6 +244,106 @@ def test_every_geometry_gives_identical_results(P, O):
     assert ran >= 6
 
 
+class _Geometry:
+    """Force one launch geometry for the problems created inside the block."""
+
+    def __init__(self, spec):
+        self.spec = spec
+
+    def __enter__(self):
+        import os
+        os.environ["PHIA_GEOMETRY"] = self.spec
+
+    def __exit__(self, *exc):
+        import os
+        del os.environ["PHIA_GEOMETRY"]
+
+
+def test_interleaved_group_sweep_full_parity(P, O):
+    """Interleaved sub-block sweep (two 16-replica sub-blocks per workgroup,
+    column split over G workgroups): every replica of a ragged case (N not a
+    multiple of 16, R not a multiple of 32, refresh period not dividing T)
+    bit-identical to the oracle, energy traces included through the records."""
+    J, h = inst.sk_gauss_fixed(150, 5, frac_bits=5, bits=8)
+    with _Geometry("pp,3"):
+        dev, runs = run_both(P, O, J, h, 5, "i8", 45, 137, 0.2, 1.0, 0.05, 1.5, 23, 71, trace=False)
+    say("geometry", dev["info"])
+    assert dev["info"]["sweep_kernel"] == 1 and dev["info"]["group"] == 3
+    assert_parity(dev, runs)
+
+
+def test_interleaved_geometries_and_chunks_identical(P, O):
+    """Group sizes, several passes over the replica blocks per launch
+    (R = 4096 on a 320-spin instance) and runs split into uneven chunks all
+    give the run of the one-workgroup-per-block kernel, bit for bit."""
+    J, h = inst.sk_gauss_fixed(300, 21, frac_bits=5, bits=8)
+    R, T = 4096, 61
+    sched = dict(beta0=0.05, beta1=1.0, refresh_L=20, seed=8)
+
+    def once(spec, chunks=None):
+        with _Geometry(spec):
+            p = P.Problem(J, h, path="i8")
+            if chunks is None:
+                p.anneal(R, T, 0.2, 1.0, **sched)
+            else:
+                p.start(R, T, 0.2, 1.0, **sched)
+                for k in chunks:
+                    p.run(k)
+                p.sync()
+            info = p.info()
+            got = p.replica_best() + p.get_state()[:2]
+            p.close()
+        say("geometry", spec, info)
+        return info, got
+
+    _, ref = once("1,2,1")
+    for spec, chunks in (("pp,3", None), ("pp,10", None), ("pp,20", None), ("pp,5", [1, 2, 30, 61])):
+        info, got = once(spec, chunks)
+        assert info["sweep_kernel"] == 1
+        for u, w in zip(ref, got):
+            assert np.array_equal(u, w), spec
+    Ji, hi = int_units(J, h, 5)
+    betas = O.beta_linear(0.05, 1.0, T)
+    for r in (0, 31, 32, 4095):
+        o = O.anneal(Ji, hi, 5, 1, betas, 0.2, 1.0, 20, 8, r0=r)
+        assert ref[0][r] == o.bestE[0] and np.array_equal(ref[3][r], o.x[0])
+
+
+def test_interleaved_lds_resident_j_sampled(P, O):
+    """Np > 1024: the interleaved kernel keeps each member's J slice in LDS
+    instead of VGPRs.  Sampled replicas against the oracle, and the whole
+    run against the one-block-per-workgroup kernel."""
+    J, h = inst.sk_gauss_fixed(1100, 4, frac_bits=5, bits=8)
+    R, T = 70, 45
+    sample = [0, 16, 33, 69]
+    with _Geometry("pp,12"):
+        dev, runs = run_both(P, O, J, h, 5, "i8", R, T, 0.2, 1.0, 0.05, 1.0, 20, 5, trace=False, sample=sample)
+    say("geometry", dev["info"])
+    assert dev["info"]["sweep_kernel"] == 1 and dev["info"]["Np"] > 1024
+    assert_parity(dev, runs)
+    with _Geometry("1,12,0"):
+        p = P.Problem(J, h, frac_bits=5, path="i8")
+        p.anneal(R, T, 0.2, 1.0, beta0=0.05, beta1=1.0, refresh_L=20, seed=5)
+        E, S, K = p.replica_best()
+        x, v, _ = p.get_state()
+        p.close()
+    assert np.array_equal(E, dev["E"]) and np.array_equal(K, dev["K"]) and np.array_equal(S, dev["S"])
+    assert np.array_equal(x.view(np.uint32), dev["x"].view(np.uint32))
+
+
+def test_interleaved_benchmark_shape_sampled(P, O):
+    """Max-cut G(800, 0.06), 1024 replicas on the interleaved kernel with
+    eight workgroups per block: sampled replicas against the oracle."""
+    J, h = inst.er_maxcut(800, 0.06, 0)
+    sample = [0, 15, 16, 31, 32, 511, 1023]
+    with _Geometry("pp,8"):
+        dev, runs = run_both(P, O, J, h, 0, "i8", 1024, 120, 0.2, 1.0, 0.02, 0.6, 40, 11, trace=False,
+                             sample=sample)
+    say("geometry", dev["info"])
+    assert dev["info"]["sweep_kernel"] == 1
+    assert_parity(dev, runs)
+
+
 def test_autotune_keeps_results(P, O):
     J, h = inst.er_maxcut(400, 0.05, 2)
     p = P.Problem(J, h, path="i8")
