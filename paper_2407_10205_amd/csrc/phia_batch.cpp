@@ -38,6 +38,7 @@ void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int
     const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
     const int nblocks = (p->R + 15) / 16;
     SweepArgs a = sweep_args(p);
+    a.J = p->dJ;  // int8 fragments (the batch kernel's operands)
     a.k0 = p->k;
     a.k1 = k_end;
     a.etrace = nullptr;
@@ -181,6 +182,7 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         p->geo.cbw = cbw;
         p->geo.j_lds = jl;
         SweepArgs a = sweep_args(p);
+        a.J = p->dJ;
         a.k0 = 0;
         a.k1 = steps[i];
         a.etrace = nullptr;

@@ -885,12 +885,21 @@ __host__ __device__ inline uint32_t pp_srow(int Np, int nkb_regs)
     return static_cast<uint32_t>(nkb_regs > 0 ? 64 * nkb_regs : Np) + 16u;
 }
 
-__host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs)
+// FP4 operands: NKB blocks of 128 k positions, 64 bytes of spins each.
+__host__ __device__ inline uint32_t pp_srow_fp4(int nkb_regs) { return 64u * nkb_regs + 16u; }
+
+// LDS of the interleaved sweep.  int8 operands: J slice in LDS unless
+// nkb_regs > 0 (VGPR fragments).  FP4 operands: J slice always in LDS,
+// nkb_regs blocks of 1 KiB per column block (zero past the packed ones).
+__host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, bool fp4 = false)
 {
     PpPlan p;
     p.j_off = 0;
-    p.s_off = nkb_regs > 0 ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
-    p.s_bytes = 16u * pp_srow(Np, nkb_regs);
+    if (fp4)
+        p.s_off = static_cast<uint32_t>(cbs_max) * static_cast<uint32_t>(nkb_regs) * 1024u;
+    else
+        p.s_off = nkb_regs > 0 ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
+    p.s_bytes = 16u * (fp4 ? pp_srow_fp4(nkb_regs) : pp_srow(Np, nkb_regs));
     p.e_off = p.s_off + 2u * p.s_bytes;  // [2][16] energy sums of the previous step
     p.b_off = p.e_off + 2u * 16u * 8u;   // [2 sub-blocks][2 parities][16] best energies
     p.k_off = p.b_off + 4u * 16u * 8u;   // [2][16] step of the best energy
@@ -982,28 +991,98 @@ __device__ __forceinline__ void pp_publish(uint64_t* Xs, int ncb, int cblk, int 
         __hip_atomic_store(Xs + (4 * lg + lr) * ncb + cblk, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// I = S . J^T + h for one 16x16 tile, J fragments in VGPRs.  All NKB
-// operand loads are issued before the first product; k blocks at or past
-// nkb read S padding against zero J fragments and add nothing.
+// I = S . J^T + h for one 16x16 tile, J fragments in VGPRs.  The S
+// operands of kPpDepth k blocks are in flight ahead of the products; k blocks
+// at or past nkb read S padding against zero J fragments and add nothing.
+constexpr int kPpDepth = 4;
+
 template <int NKB>
 __device__ __forceinline__ void quasi_gradient_regj(const unsigned char* S, uint32_t srow, const v4i (&jr)[NKB],
                                                     int nkb, int lr, int lg, int h, int (&I)[4])
 {
-    v4i A[NKB];
+    (void)nkb;
+    const unsigned char* row = S + lr * srow + 16 * lg;
+    v4i A[kPpDepth];
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) A[kb] = *reinterpret_cast<const v4i*>(S + lr * srow + kb * 64 + 16 * lg);
+    for (int d = 0; d < kPpDepth && d < NKB; ++d) A[d] = *reinterpret_cast<const v4i*>(row + d * 64);
     v4i acc = v4i{0, 0, 0, 0};
 #pragma unroll
-    for (int kb = 0; kb < NKB; ++kb) acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(A[kb], jr[kb], acc, 0, 0, 0);
+    for (int kb = 0; kb < NKB; ++kb) {
+        const v4i cur = A[kb % kPpDepth];
+        if (kb + kPpDepth < NKB) A[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur, jr[kb], acc, 0, 0, 0);
+    }
 #pragma unroll
     for (int j = 0; j < 4; ++j) I[j] = acc[j] + h;
 }
 
-template <int NU, int NKB>
-__global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2))) k_sweep_pp(SweepArgs a)
+// Expand one 16-bit sign word into 16 FP4 (E2M1) spins, +1.0 = 0x2 and
+// -1.0 = 0xA, 8 bytes: within each byte of spin bits the nibbles hold spins
+// 0 4 1 5 2 6 3 7 (the packed J uses the same order along k).
+__device__ __forceinline__ void unpack_signs_fp4(uint32_t w, unsigned char* dst)
 {
+    uint32_t d[2];
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+        const uint32_t b = (w >> (8 * t)) & 0xffu;
+        const uint32_t lo = ((b & 0xfu) * 0x00204081u) & 0x01010101u;  // bit i -> bit 8 i
+        const uint32_t hi = ((b >> 4) * 0x00204081u) & 0x01010101u;
+        d[t] = 0xaaaaaaaau - 8u * (lo | (hi << 4));
+    }
+    *reinterpret_cast<uint2*>(dst) = uint2{d[0], d[1]};
+}
+
+typedef int v8i __attribute__((ext_vector_type(8)));
+
+// I = S . J^T + h for one 16x16 tile with FP4 operands and FP32
+// accumulation (v_mfma_scale_f32_16x16x128_f8f6f4, scales 1.0): every
+// product and partial sum is an integer below 2^24, so the result is exact.
+// Jw: the wave's column block of the LDS J slice, NKB blocks of 1 KiB.
+template <int NKB>
+__device__ __forceinline__ void quasi_gradient_fp4(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
+                                                   int lane, int lr, int lg, int h, int (&I)[4])
+{
+    const unsigned char* row = S + lr * srow + 16 * lg;
+    const unsigned char* jl = Jw + lane * 16;
+    v4i A[kPpDepth], B[kPpDepth];
+#pragma unroll
+    for (int d = 0; d < kPpDepth && d < NKB; ++d) {
+        A[d] = *reinterpret_cast<const v4i*>(row + d * 64);
+        B[d] = *reinterpret_cast<const v4i*>(jl + d * 1024);
+    }
+    v4f acc = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int kb = 0; kb < NKB; ++kb) {
+        const v4i ca = A[kb % kPpDepth], cb = B[kb % kPpDepth];
+        if (kb + kPpDepth < NKB) {
+            A[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
+            B[kb % kPpDepth] = *reinterpret_cast<const v4i*>(jl + (kb + kPpDepth) * 1024);
+        }
+        const v8i a8 = v8i{ca[0], ca[1], ca[2], ca[3], 0, 0, 0, 0};
+        const v8i b8 = v8i{cb[0], cb[1], cb[2], cb[3], 0, 0, 0, 0};
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc, 4, 4, 0, 127, 0, 127);
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) I[j] = static_cast<int>(acc[j]) + h;
+}
+
+// Sixteen waves: team 0 (waves 0-7) owns sub-block 0, team 1 (waves 8-15)
+// sub-block 1; wave w of a team owns column block cb0 + w.  Each team
+// alternates between gathering its sub-block's spins (and the previous
+// step's partial energies) and computing one step of it; the teams are one
+// phase apart, so in every phase one team computes while the other waits
+// for the exchange, and a workgroup barrier closes each phase.
+constexpr int kPpWaves = 16;
+constexpr int kPpThreads = 64 * kPpWaves;
+
+template <int NU, int NKB, bool FP4 = false>
+__global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sweep_pp(SweepArgs a)
+{
+    static_assert(!FP4 || NKB > 0, "FP4 operands need the unrolled k loop");
+    constexpr bool JREG = NKB > 0 && !FP4;  // int8 J fragments in VGPRs
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int team = wave >> 3, tw = wave & 7, tt = tid & 511;
     const int lr = lane & 15, lg = lane >> 4;
     const int Np = a.Np, N = a.N, ncb = a.ncb, G = a.G;
     int group, member;
@@ -1016,38 +1095,52 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
         group = blockIdx.x / G;
     }
     const int cb0 = member * ncb / G, cb1 = (member + 1) * ncb / G, cbs = cb1 - cb0;
-    const PpPlan P = pp_plan(Np, (ncb + G - 1) / G, NKB);
-    const uint32_t srow = pp_srow(Np, NKB);
-    const uint32_t cbb = cb_bytes(kPathI8, Np);
-    const int nkb = Np / 64;
+    const PpPlan P = pp_plan(Np, (ncb + G - 1) / G, NKB, FP4);
+    const uint32_t srow = FP4 ? pp_srow_fp4(NKB) : pp_srow(Np, NKB);
+    const int nkb = FP4 ? (Np + 127) / 128 : Np / 64;  // packed k blocks
+    const uint32_t cbb = FP4 ? static_cast<uint32_t>(nkb) * 1024u : cb_bytes(kPathI8, Np);
     unsigned char* sJ = lds + P.j_off;
-    int64_t* sEt = reinterpret_cast<int64_t*>(lds + P.e_off);
-    int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);
-    int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);
+    unsigned char* S = lds + P.s_off + team * P.s_bytes;
+    int64_t* sEt = reinterpret_cast<int64_t*>(lds + P.e_off) + team * 16;
+    int64_t* sBall = reinterpret_cast<int64_t*>(lds + P.b_off);
+    int64_t* sB = sBall + team * 32;  // [parity][16]
+    int64_t* sKall = reinterpret_cast<int64_t*>(lds + P.k_off);
+    int64_t* sK = sKall + team * 16;
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
-    // J of the wave's column block: VGPR fragments (NKB > 0) or the LDS slice.
-    v4i jr[NKB > 0 ? NKB : 1];
-    if (NKB > 0) {
-        const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0 + wave) * cbb;
+    const bool cval = tw < cbs;  // this wave owns a column block
+    const int cblk = cb0 + tw;
+    const int col = cblk * 16 + lr;
+    // J of the wave's column block: VGPR fragments, or the member's slice in
+    // LDS (FP4: NKB blocks per column block, zero past the packed ones).
+    v4i jr[JREG ? NKB : 1];
+    if (JREG) {
+        const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb;
 #pragma unroll
-        for (int kb = 0; kb < (NKB > 0 ? NKB : 1); ++kb)
-            jr[kb] = (wave < cbs && kb < nkb) ? *reinterpret_cast<const v4i*>(Jw + kb * 1024 + lane * 16)
-                                              : v4i{0, 0, 0, 0};
+        for (int kb = 0; kb < (JREG ? NKB : 1); ++kb)
+            jr[kb] = (cval && kb < nkb) ? *reinterpret_cast<const v4i*>(Jw + kb * 1024 + lane * 16)
+                                        : v4i{0, 0, 0, 0};
+    } else if (FP4) {
+        const uint32_t per_cb = static_cast<uint32_t>(NKB) * 64u;  // 16-byte vectors per column block
+        const uint4* src = reinterpret_cast<const uint4*>(a.J);
+        uint4* dst = reinterpret_cast<uint4*>(sJ);
+        for (uint32_t q = tid; q < static_cast<uint32_t>(cbs) * per_cb; q += kPpThreads) {
+            const uint32_t c = q / per_cb, kb = (q % per_cb) / 64u, l = q % 64u;
+            dst[q] = kb < static_cast<uint32_t>(nkb)
+                         ? src[(static_cast<size_t>(cb0 + c) * nkb + kb) * 64u + l]
+                         : uint4{0u, 0u, 0u, 0u};
+        }
     } else {
         const uint32_t nvec = static_cast<uint32_t>(cbs) * cbb / 16u;
         const uint4* src = reinterpret_cast<const uint4*>(static_cast<const unsigned char*>(a.J) +
                                                           static_cast<size_t>(cb0) * cbb);
         uint4* dst = reinterpret_cast<uint4*>(sJ);
-        for (uint32_t q = tid; q < nvec; q += kThreads) dst[q] = src[q];
+        for (uint32_t q = tid; q < nvec; q += kPpThreads) dst[q] = src[q];
     }
     if (tid == 0) *sAbort = 0;
 
-    const bool cval = wave < cbs;  // this wave owns a column block
-    const int cblk = cb0 + wave;
-    const int col = cblk * 16 + lr;
     const int hreg1[1] = {cval ? a.h[col] : 0};
     const bool creal = cval && col < N;
-    const int grow = tid >> 5, gc0 = tid & 31;
+    const int grow = tt >> 5, gc0 = tt & 31;
     const float eps = a.eps, gamma = a.gamma;
     const int nsteps = static_cast<int>(a.k1 - a.k0);
     const uint32_t seq_stride = static_cast<uint32_t>(nsteps + 1);
@@ -1057,208 +1150,204 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 
     for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
         const int64_t rb0 = static_cast<int64_t>(blk) * 32;
-        // word arrays of (parity, sub-block)
-        auto xs = [&](uint32_t seq, int sb) -> uint64_t* {
-            return a.xbits + ((static_cast<size_t>(seq & 1u) * a.ngroups + group) * 2 + sb) * plane;
+        const int64_t tb0 = rb0 + team * 16;  // first replica of this team's sub-block
+        // word array of this team's sub-block for publication seq
+        auto xs = [&](uint32_t seq) -> uint64_t* {
+            return a.xbits + ((static_cast<size_t>(seq & 1u) * a.ngroups + group) * 2 + team) * plane;
         };
-        for (int q = tid; q < 32; q += kThreads) {
+        for (int q = tid; q < 32; q += kPpThreads) {
             const int sb = q >> 4, r = q & 15;
             const bool ok = rb0 + q < a.R;
             const int64_t b = ok ? a.bestE[rb0 + q] : INT64_MAX;
-            sB[(sb * 2 + 0) * 16 + r] = b;
-            sB[(sb * 2 + 1) * 16 + r] = b;
-            sK[q] = ok ? a.bestStep[rb0 + q] : -1;
+            sBall[(sb * 2 + 0) * 16 + r] = b;
+            sBall[(sb * 2 + 1) * 16 + r] = b;
+            sKall[q] = ok ? a.bestStep[rb0 + q] : -1;
         }
-        float x[2][4], v[2][4];
+        float x[4], v[4];
         uint32_t bestbits = 0, pm = 0;
 #pragma unroll
-        for (int sb = 0; sb < 2; ++sb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t gr = rb0 + sb * 16 + 4 * lg + j;
-                const bool ok = cval && gr < a.R;
-                x[sb][j] = ok ? a.x[gr * Np + col] : 0.0f;
-                v[sb][j] = ok ? a.v[gr * Np + col] : 0.0f;
-                if (ok && creal && a.bestS[gr * Np + col] > 0) bestbits |= 1u << (sb * 4 + j);
-            }
+        for (int j = 0; j < 4; ++j) {
+            const int64_t gr = tb0 + 4 * lg + j;
+            const bool ok = cval && gr < a.R;
+            x[j] = ok ? a.x[gr * Np + col] : 0.0f;
+            v[j] = ok ? a.v[gr * Np + col] : 0.0f;
+            if (ok && creal && a.bestS[gr * Np + col] > 0) bestbits |= 1u << j;
+        }
 
         const uint32_t seq0 = a.seq_base + static_cast<uint32_t>(iter) * seq_stride + 1u;
         int64_t next_ref = ref0;
         uint64_t round = static_cast<uint64_t>(ref0 / a.L);
-        bool aborted = false;
         uint64_t w[NU];
 
-        // Momentum refresh of sub-block sb's owned elements for step kr.
-        auto refresh = [&](int sb) {
+        // Momentum refresh of the owned elements (draws of `round`).
+        auto refresh = [&]() {
 #pragma unroll 1
             for (int j = 0; j < 4; ++j) {
-                const int64_t gr = rb0 + sb * 16 + 4 * lg + j;
+                const int64_t gr = tb0 + 4 * lg + j;
                 const float g = (creal && gr < a.R) ? gauss_v(a.seed, a.r_base + gr, round, col) : 0.0f;
-                if (j == 0) v[sb][0] = g;
-                else if (j == 1) v[sb][1] = g;
-                else if (j == 2) v[sb][2] = g;
-                else v[sb][3] = g;
+                if (j == 0) v[0] = g;
+                else if (j == 1) v[1] = g;
+                else if (j == 2) v[2] = g;
+                else v[3] = g;
             }
+        };
+        auto signs4 = [&]() {
+            uint32_t m = 0;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+                if (x[j] >= 0.0f) m |= 1u << j;
+            return m;
+        };
+
+        // Publication q: spins of step k0 + q and partial energies of step
+        // k0 + q - 1 of this team's sub-block; read into S (q < nsteps) and
+        // the row energy sums (q > 0).  Returns false when the wait gave up.
+        auto gather = [&](int q) {
+            const uint32_t seq = seq0 + static_cast<uint32_t>(q);
+            pp_issue<NU>(xs(seq), ncb, grow, gc0, w);
+            const bool ok = pp_complete<NU>(xs(seq), ncb, grow, gc0, seq & 0xffffffu, w, a.err);
+            int psum = 0;
+#pragma unroll
+            for (int u = 0; u < NU; ++u) {
+                const int c = gc0 + 32 * u;
+                if (c < ncb) {
+                    if (q < nsteps) {
+                        if (FP4)
+                            unpack_signs_fp4(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 8);
+                        else
+                            unpack_signs<1>(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 16);
+                    }
+                    psum += static_cast<int32_t>(static_cast<uint32_t>(w[u] >> 16) << 8) >> 8;
+                }
+            }
+            if (q > 0) {
+                // Row total over the 32 lanes of the replica row: DPP row
+                // sums, then row r - 1 added into rows 1 and 3.
+                int t = row_sum16_dpp(psum);
+                t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);  // row_bcast:15
+                if (gc0 == 31) sEt[grow] = t;
+            }
+            return ok;
+        };
+
+        // Records of step k0 + s - 1, then (s < nsteps) step k0 + s and its
+        // publication s + 1.
+        auto compute = [&](int s) {
+            const int64_t k = a.k0 + s;
+            const bool closing = (s == nsteps);
+            const float ck = closing ? 0.0f : a.ctab[k];
+            int I[1][1][4] = {};
+            if (!closing && cval) {
+                if (FP4)
+                    quasi_gradient_fp4<(NKB > 0 ? NKB : 1)>(S, srow, sJ + static_cast<size_t>(tw) * NKB * 1024u,
+                                                            lane, lr, lg, hreg1[0], I[0][0]);
+                else if (JREG)
+                    quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, nkb, lr, lg, hreg1[0], I[0][0]);
+                else
+                    quasi_gradient<kPathI8, 1, 1, 1>(S, srow, sJ + static_cast<size_t>(tw) * cbb, 0, Np, lane, lr,
+                                                     lg, hreg1, I);
+            }
+            if (s > 0) {  // App. B, Table 3, state 5
+                const int par = static_cast<int>(k & 1);
+                const int64_t* prev = sB + (par ^ 1) * 16;
+                int64_t* next = sB + par * 16;
+                int64_t Ev[4], Bv[4];
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {  // all reads before any write
+                    Ev[j] = -(sEt[4 * lg + j] / 2);
+                    Bv[j] = prev[4 * lg + j];
+                }
+                uint32_t impm = 0;
+#pragma unroll
+                for (int j = 0; j < 4; ++j)
+                    if (Ev[j] < Bv[j]) impm |= 1u << j;
+                bestbits = (bestbits & ~impm) | (pm & impm);
+                if (tw == 0 && lr == 0) {
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {
+                        const bool imp = (impm >> j) & 1u;
+                        next[4 * lg + j] = imp ? Ev[j] : Bv[j];
+                        if (imp) sK[4 * lg + j] = k - 1;
+                    }
+                }
+            }
+            if (closing || !cval) return;
+            int part[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int sg = (x[j] >= 0.0f) ? 1 : -1;
+                part[j] = creal ? sg * (I[0][0][j] + hreg1[0]) : 0;
+                v[j] = kick(x[j], v[j], I[0][0][j], ck, eps, gamma);
+            }
+            const int p0 = row_sum16_dpp(part[0]), p1 = row_sum16_dpp(part[1]);
+            const int p2 = row_sum16_dpp(part[2]), p3 = row_sum16_dpp(part[3]);
+            pm = signs4();
+            if (s + 1 < nsteps) {
+                if (k + 1 == next_ref) refresh();
+#pragma unroll
+                for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(eps, v[j], x[j]);
+            }
+            const uint32_t seq = seq0 + static_cast<uint32_t>(s) + 1u;
+            pp_publish(xs(seq), ncb, cblk, lr, lg, x, p0, p1, p2, p3, seq & 0xffffffu);
         };
 
         // Publication 0: the drift of step k0.
         {
-            const bool ref = (a.k0 == next_ref);
-#pragma unroll
-            for (int sb = 0; sb < 2; ++sb) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (x[sb][j] >= 0.0f) pm |= 1u << (sb * 4 + j);
-                if (ref) refresh(sb);
-#pragma unroll
-                for (int j = 0; j < 4; ++j) x[sb][j] = __builtin_fmaf(eps, v[sb][j], x[sb][j]);
-                if (cval) pp_publish(xs(seq0, sb), ncb, cblk, lr, lg, x[sb], 0, 0, 0, 0, seq0 & 0xffffffu);
-            }
-            if (ref) {
+            pm = signs4();
+            if (a.k0 == next_ref) {
+                refresh();
                 next_ref += a.L;
                 ++round;
             }
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(eps, v[j], x[j]);
+            if (cval) pp_publish(xs(seq0), ncb, cblk, lr, lg, x, 0, 0, 0, 0, seq0 & 0xffffffu);
         }
         __syncthreads();  // records initialised
-        pp_issue<NU>(xs(seq0, 0), ncb, grow, gc0, w);
-
-        float ck_next = a.ctab[a.k0];
-        for (int s = 0; s <= nsteps; ++s) {
-            const int64_t k = a.k0 + s;
-            const uint32_t seq = seq0 + static_cast<uint32_t>(s);
-            const bool closing = (s == nsteps);
-            const bool drift_next = (s + 1 < nsteps);
-            const bool ref_next = drift_next && (k + 1 == next_ref);
-            const float ck = ck_next;  // c_k, loaded one step ahead
-            ck_next = a.ctab[drift_next ? k + 1 : k];
-            const int par = static_cast<int>(k & 1);
-#pragma unroll
-            for (int X = 0; X < 2; ++X) {
-                unsigned char* S = lds + P.s_off + X * P.s_bytes;
-                // Spins of step k and partial energies of step k - 1.
-                if (!pp_complete<NU>(xs(seq, X), ncb, grow, gc0, seq & 0xffffffu, w, a.err)) *sAbort = 1;
-                int psum = 0;
-#pragma unroll
-                for (int u = 0; u < NU; ++u) {
-                    const int c = gc0 + 32 * u;
-                    if (c < ncb) {
-                        if (!closing) unpack_signs<1>(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 16);
-                        psum += static_cast<int32_t>(static_cast<uint32_t>(w[u] >> 16) << 8) >> 8;
-                    }
-                }
-                if (s > 0) {
-                    // Row total over the 32 lanes of the replica row: DPP row
-                    // sums, then row r - 1 added into rows 1 and 3.
-                    int t = row_sum16_dpp(psum);
-                    t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);  // row_bcast:15
-                    if (gc0 == 31) sEt[X * 16 + grow] = t;
-                }
-                __syncthreads();
-                const int abort_seen = *sAbort;
-                // Records of step k - 1 (App. B, Table 3, state 5); placed after
-                // the products are issued so that they overlap them.
-                auto records = [&]() {
-                    if (s == 0) return;
-                    const int64_t* prev = sB + (X * 2 + (par ^ 1)) * 16;
-                    int64_t* next = sB + (X * 2 + par) * 16;
-                    const bool writer = (wave == 0 && lr == 0);
-                    int64_t Ev[4], Bv[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {  // all reads before any write
-                        Ev[j] = -(sEt[X * 16 + 4 * lg + j] / 2);
-                        Bv[j] = prev[4 * lg + j];
-                    }
-                    uint32_t impm = 0;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (Ev[j] < Bv[j]) impm |= 1u << j;
-                    const uint32_t sel = impm << (4 * X);
-                    bestbits = (bestbits & ~sel) | (pm & sel);
-                    if (writer) {
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) {
-                            const bool imp = (impm >> j) & 1u;
-                            next[4 * lg + j] = imp ? Ev[j] : Bv[j];
-                            if (imp) sK[X * 16 + 4 * lg + j] = k - 1;
-                        }
-                    }
-                };
-                if (closing) {
-                    if (abort_seen) {
-                        aborted = true;
-                        break;
-                    }
-                    records();
-                    if (X == 0) pp_issue<NU>(xs(seq, 1), ncb, grow, gc0, w);
-                    continue;
-                }
-                // Quasi-gradient of step k on matrix cores.
-                int I[1][1][4] = {};
-                if (cval) {
-                    if (NKB > 0)
-                        quasi_gradient_regj<(NKB > 0 ? NKB : 1)>(S, srow, jr, nkb, lr, lg, hreg1[0], I[0][0]);
-                    else
-                        quasi_gradient<kPathI8, 1, 1, 1>(S, srow, sJ + static_cast<size_t>(wave) * cbb, 0, Np, lane,
-                                                         lr, lg, hreg1, I);
-                }
-                if (abort_seen) {
-                    aborted = true;
-                    break;
-                }
-                records();
-                // Next gather: sub-block 1 of publication s, or sub-block 0
-                // of publication s + 1 (both already published).
-                if (X == 0) pp_issue<NU>(xs(seq, 1), ncb, grow, gc0, w);
-                else pp_issue<NU>(xs(seq + 1u, 0), ncb, grow, gc0, w);
-                if (cval) {
-                    int part[4];
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int sg = (x[X][j] >= 0.0f) ? 1 : -1;
-                        part[j] = creal ? sg * (I[0][0][j] + hreg1[0]) : 0;
-                        v[X][j] = kick(x[X][j], v[X][j], I[0][0][j], ck, eps, gamma);
-                    }
-                    const int p0 = row_sum16_dpp(part[0]), p1 = row_sum16_dpp(part[1]);
-                    const int p2 = row_sum16_dpp(part[2]), p3 = row_sum16_dpp(part[3]);
-                    uint32_t sg4 = 0;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (x[X][j] >= 0.0f) sg4 |= 1u << j;
-                    pm = (pm & ~(0xfu << (4 * X))) | (sg4 << (4 * X));
-                    if (drift_next) {
-                        if (ref_next) refresh(X);
-#pragma unroll
-                        for (int j = 0; j < 4; ++j) x[X][j] = __builtin_fmaf(eps, v[X][j], x[X][j]);
-                    }
-                    pp_publish(xs(seq + 1u, X), ncb, cblk, lr, lg, x[X], p0, p1, p2, p3, (seq + 1u) & 0xffffffu);
-                }
+        if (team == 0 && !gather(0)) *sAbort = 1;
+        __syncthreads();
+        // Phase ph: team ph % 2 computes, the other team gathers.
+        bool aborted = false;
+        int abort_seen = 0;
+        const int nphase = 2 * nsteps + 2;
+        for (int ph = 0; ph < nphase; ++ph) {
+            if (abort_seen) {
+                aborted = true;
+                break;
             }
-            if (aborted) break;
-            if (ref_next) {
-                next_ref += a.L;
-                ++round;
+            const int abort_flag = *sAbort;  // consumed one phase later
+            if (team == (ph & 1)) {
+                const int s = (ph - team) >> 1;
+                compute(s);
+                if (s + 1 < nsteps && a.k0 + s + 1 == next_ref) {
+                    next_ref += a.L;
+                    ++round;
+                }
+            } else {
+                const int q = (team == 0) ? (ph + 1) >> 1 : ph >> 1;
+                if (q <= nsteps && !gather(q)) *sAbort = 1;
             }
+            __syncthreads();
+            abort_seen = abort_flag;
         }
         if (aborted) return;
 
 #pragma unroll
-        for (int sb = 0; sb < 2; ++sb)
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int64_t gr = rb0 + sb * 16 + 4 * lg + j;
-                if (!cval || gr >= a.R) continue;
-                a.x[gr * Np + col] = x[sb][j];
-                a.v[gr * Np + col] = v[sb][j];
-                if (creal) a.bestS[gr * Np + col] = ((bestbits >> (sb * 4 + j)) & 1u) ? 1 : -1;
-            }
+        for (int j = 0; j < 4; ++j) {
+            const int64_t gr = tb0 + 4 * lg + j;
+            if (!cval || gr >= a.R) continue;
+            a.x[gr * Np + col] = x[j];
+            a.v[gr * Np + col] = v[j];
+            if (creal) a.bestS[gr * Np + col] = ((bestbits >> j) & 1u) ? 1 : -1;
+        }
         __syncthreads();
         if (member == 0) {
             const int fin = static_cast<int>(a.k1 & 1);
-            for (int q = tid; q < 32; q += kThreads)
+            for (int q = tid; q < 32; q += kPpThreads)
                 if (rb0 + q < a.R) {
                     const int sb = q >> 4, r = q & 15;
-                    a.bestE[rb0 + q] = sB[(sb * 2 + fin) * 16 + r];
-                    a.bestStep[rb0 + q] = sK[q];
+                    a.bestE[rb0 + q] = sBall[(sb * 2 + fin) * 16 + r];
+                    a.bestStep[rb0 + q] = sKall[q];
                 }
         }
         __syncthreads();
@@ -1266,61 +1355,78 @@ __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(2
 }
 
 // J fragments per wave kept in VGPRs for Np: the k-block count rounded up
-// to even, up to 16 (0: J slice in LDS).
+// to even, up to 4 (sixteen waves leave 128 registers per lane); 0: J slice
+// in LDS.
 static int pp_nkb_regs(int Np)
 {
     const int nkb = Np / 64;
-    return nkb <= 16 ? (nkb + 1) / 2 * 2 : 0;
+    return nkb <= 4 ? (nkb + 1) / 2 * 2 : 0;
 }
 
-size_t sweep_pp_lds_bytes(int Np, int G)
+// FP4 k blocks (128 wide) of the unrolled product: ceil(Np / 128) rounded up
+// to even, up to 8 (Np <= 1024).
+static int pp_nkb4(int Np)
+{
+    const int nkb = (Np + 127) / 128;
+    return nkb <= 8 ? (nkb + 1) / 2 * 2 : 0;
+}
+
+size_t sweep_pp_lds_bytes(int Np, int G, int fp4)
 {
     const int ncb = Np / 16;
+    if (fp4) return pp_plan(Np, (ncb + G - 1) / G, pp_nkb4(Np), true).total;
     return pp_plan(Np, (ncb + G - 1) / G, pp_nkb_regs(Np)).total;
 }
 
-static const void* pp_kernel(int ncb)
+static const void* pp_kernel(int ncb, int fp4)
 {
     const int Np = 16 * ncb;
+    if (fp4) {
+        switch (pp_nkb4(Np)) {
+        case 2: return reinterpret_cast<const void*>(k_sweep_pp<1, 2, true>);
+        case 4: return reinterpret_cast<const void*>(k_sweep_pp<1, 4, true>);
+        case 6: return reinterpret_cast<const void*>(k_sweep_pp<2, 6, true>);
+        case 8: return reinterpret_cast<const void*>(k_sweep_pp<2, 8, true>);
+        default: return nullptr;
+        }
+    }
     switch (pp_nkb_regs(Np)) {
     case 2: return reinterpret_cast<const void*>(k_sweep_pp<1, 2>);
     case 4: return reinterpret_cast<const void*>(k_sweep_pp<1, 4>);
-    case 6: return reinterpret_cast<const void*>(k_sweep_pp<1, 6>);
-    case 8: return reinterpret_cast<const void*>(k_sweep_pp<1, 8>);
-    case 10: return reinterpret_cast<const void*>(k_sweep_pp<2, 10>);
-    case 12: return reinterpret_cast<const void*>(k_sweep_pp<2, 12>);
-    case 14: return reinterpret_cast<const void*>(k_sweep_pp<2, 14>);
-    case 16: return reinterpret_cast<const void*>(k_sweep_pp<2, 16>);
     default: break;
     }
+    if (ncb <= 32) return reinterpret_cast<const void*>(k_sweep_pp<1, 0>);
+    if (ncb <= 64) return reinterpret_cast<const void*>(k_sweep_pp<2, 0>);
     if (ncb <= 128) return reinterpret_cast<const void*>(k_sweep_pp<4, 0>);
     return reinterpret_cast<const void*>(k_sweep_pp<8, 0>);
 }
 
-hipError_t launch_sweep_pp(const SweepArgs& a, size_t lds, hipStream_t st)
+hipError_t launch_sweep_pp(const SweepArgs& a, int fp4, size_t lds, hipStream_t st)
 {
     if (a.ncb < 1 || a.ncb > kPpMaxNcb) return hipErrorInvalidValue;
-    const void* kern = pp_kernel(a.ncb);
+    const void* kern = pp_kernel(a.ncb, fp4);
+    if (!kern) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
     SweepArgs copy = a;
     void* args[] = {&copy};
-    e = hipLaunchCooperativeKernel(kern, dim3(static_cast<unsigned>(a.ngroups * a.G)), dim3(kThreads), args,
+    e = hipLaunchCooperativeKernel(kern, dim3(static_cast<unsigned>(a.ngroups * a.G)), dim3(kPpThreads), args,
                                    static_cast<unsigned>(lds), st);
     if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
-int max_coresident_pp(int ncb, size_t lds)
+int max_coresident_pp(int ncb, int fp4, size_t lds)
 {
     int dev = 0, cus = 0, per = 0;
     if (ncb < 1 || ncb > kPpMaxNcb) return 0;
+    if (!pp_kernel(ncb, fp4)) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* f = pp_kernel(ncb);
+    const void* f = pp_kernel(ncb, fp4);
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kPpThreads, lds) != hipSuccess) return 0;
     return per * cus;
 }
 

@@ -12,7 +12,7 @@ namespace phia {
 // Launch geometry of the MFMA sweep (see k_sweep_mfma).
 struct Geometry {
     bool ok = false;
-    int kind = 0;      // 0: k_sweep_mfma, 1: k_sweep_pp (interleaved sub-blocks)
+    int kind = 0;      // 0: k_sweep_mfma; k_sweep_pp (interleaved sub-blocks) with 1: int8, 2: FP4 operands
     int mt = 1;        // 16-replica row tiles per workgroup
     int cbw = 2;       // max 16-column blocks per wave
     int G = 1;         // workgroups splitting the columns of one replica block
@@ -55,6 +55,7 @@ struct phia_problem {
     bool poisoned = false;
     // instance
     void* dJ = nullptr;
+    void* dJ4 = nullptr;  // FP4 operand copy of J (interleaved sweep), or null
     int32_t* dh = nullptr;
     double* dJ64 = nullptr;
     double* dh64 = nullptr;

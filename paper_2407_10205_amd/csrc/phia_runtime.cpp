@@ -119,6 +119,41 @@ phia_status pack_instance(const double* J, const double* h, int N, int frac_bits
     return PHIA_OK;
 }
 
+// FP4 (E2M1) code of an integer coupling, or -1 if it has none: the
+// representable integers are 0, +-1, +-2, +-3, +-4, +-6.
+static int fp4_code(int v)
+{
+    const int a = v < 0 ? -v : v;
+    static const int mag[7] = {0, 2, 4, 5, 6, -1, 7};  // |v| = 0, 1, 2, 3, 4, 5, 6
+    if (a > 6 || mag[a] < 0) return -1;
+    return (v < 0 && a != 0 ? 8 : 0) | mag[a];
+}
+
+// FP4 fragment-major: [Np/16 col blocks][nkb4][64 lanes][16 bytes] with
+// nkb4 = ceil(Np / 128).  Lane l holds column cb*16 + l%16 and the 32 k
+// positions 128 kb + 32 (l/16) + t, element t in nibble t (low nibble first).
+// Within each group of 8 k positions the spins are ordered 0 4 1 5 2 6 3 7,
+// the order in which the sweep expands a byte of spin bits.
+static void pack_fp4(const std::vector<int32_t>& Ji, int N, int Np, std::vector<uint8_t>& out)
+{
+    static const int perm[8] = {0, 4, 1, 5, 2, 6, 3, 7};
+    const int ncb = Np / 16, nkb4 = (Np + 127) / 128;
+    out.assign(static_cast<size_t>(ncb) * nkb4 * 64 * 16, 0);
+    for (int cb = 0; cb < ncb; ++cb)
+        for (int kb = 0; kb < nkb4; ++kb)
+            for (int l = 0; l < 64; ++l) {
+                const int i = cb * 16 + (l & 15);
+                uint8_t* dst = &out[((static_cast<size_t>(cb) * nkb4 + kb) * 64 + l) * 16];
+                for (int t = 0; t < 32; ++t) {
+                    const int kpos = kb * 128 + 32 * (l >> 4) + t;
+                    const int j = 8 * (kpos / 8) + perm[kpos % 8];
+                    const int v = (i < N && j < N) ? Ji[static_cast<size_t>(i) * N + j] : 0;
+                    const int c = fp4_code(v);
+                    dst[t >> 1] |= static_cast<uint8_t>((c & 15) << (4 * (t & 1)));
+                }
+            }
+}
+
 // I8 fragment-major: [Np/16][Np/64][64 lanes][16 bytes].
 static void pack_i8(const std::vector<int32_t>& Ji, int N, int Np, std::vector<int8_t>& out)
 {
@@ -172,7 +207,7 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 static const char* tune_cache_path() { return std::getenv("PHIA_TUNE_CACHE"); }
 
 static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g);
-static bool make_geometry_pp(phia_problem* p, int R, int G, Geometry& g);
+static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g);
 
 static bool lookup_tune_cache(phia_problem* p, int R)
 {
@@ -188,7 +223,7 @@ static bool lookup_tune_cache(phia_problem* p, int R)
     while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &kind, &mt, &cbw, &G, &jl, &us) ==
            10) {
         if (std::strcmp(tag, "phia-tune3") == 0 && pa == p->path && np == p->Np && r == R &&
-            (kind == 1 ? make_geometry_pp(p, R, G, g) : make_geometry(p, R, mt, cbw, G, jl, g))) {
+            (kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g) : make_geometry(p, R, mt, cbw, G, jl, g))) {
             p->geo = g;
             found = true;
         }
@@ -246,25 +281,27 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     return true;
 }
 
-// Interleaved group sweep (k_sweep_pp): int8 J, blocks of 32 replicas as two
-// alternating 16-replica sub-blocks, G >= 2 workgroups per block with one
-// column block per wave and the J slice in LDS; false if it does not apply.
-static bool make_geometry_pp(phia_problem* p, int R, int G, Geometry& g)
+// Interleaved group sweep (k_sweep_pp): int8 path, blocks of 32 replicas as
+// two 16-replica sub-blocks on two wave teams, G >= 2 workgroups per block
+// with one column block per wave; MFMA operands int8 or (fp4 = 1, couplings
+// that are all FP4 integers) FP4.  False if it does not apply.
+static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g)
 {
     const int Np = p->Np, ncb = Np / 16;
     if (p->path != PHIA_PATH_I8 || p->trace || G < 2 || G > ncb || ncb > kPpMaxNcb) return false;
+    if (fp4 && !p->dJ4) return false;
     if (p->maxrow >= kPpMaxRowSum || 2 * p->maxrow * p->N >= (int64_t(1) << 31)) return false;
     if ((ncb + G - 1) / G > kWaves) return false;
-    const size_t lds = sweep_pp_lds_bytes(Np, G);
+    const size_t lds = sweep_pp_lds_bytes(Np, G, fp4);
     if (lds > static_cast<size_t>(kLdsMax)) return false;
-    const int maxwg = max_coresident_pp(ncb, lds);
+    const int maxwg = max_coresident_pp(ncb, fp4, lds);
     if (maxwg < G) return false;
     const int nblocks = (R + 31) / 32;
     int ngroups = std::min(nblocks, maxwg / G);
     if (ngroups >= 8) ngroups -= ngroups % 8;
     g = Geometry{};
     g.ok = true;
-    g.kind = 1;
+    g.kind = fp4 ? 2 : 1;
     g.mt = 2;
     g.cbw = 1;
     g.G = G;
@@ -293,8 +330,10 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
                     Geometry g;
                     if (make_geometry(p, R, mt, cbw, G, jl, g)) out.push_back(g);
                 }
-        Geometry g;
-        if (make_geometry_pp(p, R, G, g)) out.push_back(g);
+        for (int fp4 : {0, 1}) {
+            Geometry g;
+            if (make_geometry_pp(p, R, G, fp4, g)) out.push_back(g);
+        }
     }
     return out;
 }
@@ -308,9 +347,9 @@ static void choose_mfma_geometry(phia_problem* p, int R)
     p->geo.ok = false;
     int f_mt = 0, f_G = 0, f_j = -1, f_c = kCbwMax;
     if (const char* env = std::getenv("PHIA_GEOMETRY")) {
-        if (std::sscanf(env, "pp,%d", &f_G) == 1) {
+        if (std::sscanf(env, "pp,%d", &f_G) == 1 || std::sscanf(env, "pp4,%d", &f_G) == 1) {
             Geometry g;
-            if (make_geometry_pp(p, R, f_G, g)) p->geo = g;
+            if (make_geometry_pp(p, R, f_G, std::strncmp(env, "pp4", 3) == 0, g)) p->geo = g;
             return;
         }
         if (std::sscanf(env, "%d,%d,%d,%d", &f_mt, &f_G, &f_j, &f_c) >= 3) {
@@ -336,7 +375,8 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         if (iters != min_iters) continue;
         const int cbs_max = (p->Np / 16 + g.G - 1) / g.G;
         const double elems = static_cast<double>(g.rows) * cbs_max * 16;
-        const double cost = g.kind == 1 ? 1e6 + g.G : (g.G > 1 ? 2e6 : 0.0) + elems * 2 + (g.j_lds ? 0 : 1);
+        const double cost = g.kind >= 1 ? 1e6 + 2 * g.G - (g.kind == 2 ? 1 : 0)
+                                        : (g.G > 1 ? 2e6 : 0.0) + elems * 2 + (g.j_lds ? 0 : 1);
         if (!p->geo.ok || cost < best) {
             p->geo = g;
             best = cost;
@@ -367,7 +407,7 @@ SweepArgs sweep_args(const phia_problem* p)
     a.N = p->N;
     a.Np = p->Np;
     a.h = p->dh;
-    a.J = p->dJ;
+    a.J = p->geo.kind == 2 ? p->dJ4 : p->dJ;
     a.ctab = p->dctab;
     a.eps = p->eps;
     a.gamma = p->gamma;
@@ -475,6 +515,7 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     size_t jbytes = 0;
     std::vector<float> jf;
     std::vector<int8_t> j8;
+    std::vector<uint8_t> j4;
     std::vector<uint16_t> jb;
     const void* jsrc = nullptr;
     if (path == PHIA_PATH_FP32) {
@@ -488,6 +529,11 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
         pack_i8(Ji, N, Np, j8);
         jbytes = j8.size();
         jsrc = j8.data();
+        // Couplings that are all FP4 integers also get the FP4 operand copy
+        // of the interleaved sweep (Np <= 1024: J fragments in VGPRs).
+        bool fp4_ok = Np <= 1024;
+        for (size_t t = 0; fp4_ok && t < Ji.size(); ++t) fp4_ok = fp4_code(Ji[t]) >= 0;
+        if (fp4_ok) pack_fp4(Ji, N, Np, j4);
     } else {
         pack_bf16(Ji, N, Np, jb);
         jbytes = jb.size() * sizeof(uint16_t);
@@ -500,9 +546,14 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
             hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dh64), sizeof(double) * N, cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->derr), sizeof(int32_t) * 4, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dscratch), 64, cnt)) != hipSuccess) {
+        (e = dalloc(reinterpret_cast<void**>(&p->dscratch), 64, cnt)) != hipSuccess ||
+        (!j4.empty() && (e = dalloc(reinterpret_cast<void**>(&p->dJ4), j4.size(), cnt)) != hipSuccess)) {
         phia_destroy(p);
         return fail(PHIA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
+    }
+    if (!j4.empty() && (e = hipMemcpy(p->dJ4, j4.data(), j4.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+        phia_destroy(p);
+        return fail(PHIA_EDEVICE, "upload failed: %s", hipGetErrorString(e));
     }
     std::vector<double> h64(static_cast<size_t>(N), 0.0);
     if (h) std::copy(h, h + N, h64.begin());
@@ -527,6 +578,7 @@ void phia_destroy(phia_problem* p)
     if (!p->poisoned && !p->st) (void)hipDeviceSynchronize();
     free_state(p);
     dfree(p->dJ);
+    dfree(p->dJ4);
     dfree(p->dh);
     dfree(p->dJ64);
     dfree(p->dh64);
@@ -706,7 +758,7 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
     a.k1 = k_end;
     if (p->path == PHIA_PATH_FP32) {
         e = launch_sweep_fp32(a, p->st);
-    } else if (p->geo.kind == 1) {
+    } else if (p->geo.kind >= 1) {
         // 24-bit tags: launches of at most `chunk` steps, and the sequence
         // restarts (with cleared words) before it would wrap.
         const int64_t iters = (p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups;
@@ -723,7 +775,7 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
             a.k0 = k;
             a.k1 = kk;
             a.seq_base = p->seq;
-            e = launch_sweep_pp(a, p->geo.lds, p->st);
+            e = launch_sweep_pp(a, p->geo.kind == 2, p->geo.lds, p->st);
             p->seq += static_cast<uint32_t>(use);
             k = kk;
         }

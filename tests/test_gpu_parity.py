@@ -331,17 +331,56 @@ def test_interleaved_lds_resident_j_sampled(P, O):
     assert np.array_equal(x.view(np.uint32), dev["x"].view(np.uint32))
 
 
+def test_interleaved_fp4_operands(P, O):
+    """Couplings whose integer codes are all FP4 values (0, +-1, +-2, +-3,
+    +-4, +-6) run the interleaved kernel with FP4 MFMA operands: full parity
+    with the oracle on a ragged case that uses every code, and bit-identical
+    to the int8-operand kernel; a code outside the set leaves the FP4 variant
+    unavailable."""
+    rs = np.random.default_rng(12)
+    N = 230
+    codes = np.array([0, 1, -1, 2, -2, 3, -3, 4, -4, 6, -6])
+    U = rs.choice(codes, size=(N, N)).astype(np.float64)
+    J = np.triu(U, 1) + np.triu(U, 1).T
+    h = rs.integers(-3, 4, N).astype(np.float64)
+    R, T = 45, 97
+    with _Geometry("pp4,3"):
+        dev, runs = run_both(P, O, J, h, 0, "i8", R, T, 0.2, 1.0, 0.02, 0.5, 19, 23, trace=False)
+    say("geometry", dev["info"])
+    assert dev["info"]["sweep_kernel"] == 2
+    assert_parity(dev, runs)
+    with _Geometry("pp,3"):
+        p = P.Problem(J, h, path="i8")
+        p.anneal(R, T, 0.2, 1.0, beta0=0.02, beta1=0.5, refresh_L=19, seed=23)
+        assert p.info()["sweep_kernel"] == 1
+        E, S, K = p.replica_best()
+        x, v, _ = p.get_state()
+        p.close()
+    assert np.array_equal(E, dev["E"]) and np.array_equal(K, dev["K"]) and np.array_equal(S, dev["S"])
+    assert np.array_equal(x.view(np.uint32), dev["x"].view(np.uint32))
+    assert np.array_equal(v.view(np.uint32), dev["v"].view(np.uint32))
+    J5 = J.copy()
+    J5[0, 1] = J5[1, 0] = 5.0
+    with _Geometry("pp4,3"):
+        p = P.Problem(J5, h, path="i8")
+        with pytest.raises(P.PhiaError) as e:
+            p.anneal(R, T, 0.2, 1.0, beta0=0.02, beta1=0.5, refresh_L=19, seed=23)
+        assert e.value.code == -4
+        p.close()
+
+
 def test_interleaved_benchmark_shape_sampled(P, O):
     """Max-cut G(800, 0.06), 1024 replicas on the interleaved kernel with
     eight workgroups per block: sampled replicas against the oracle."""
     J, h = inst.er_maxcut(800, 0.06, 0)
     sample = [0, 15, 16, 31, 32, 511, 1023]
-    with _Geometry("pp,8"):
-        dev, runs = run_both(P, O, J, h, 0, "i8", 1024, 120, 0.2, 1.0, 0.02, 0.6, 40, 11, trace=False,
-                             sample=sample)
-    say("geometry", dev["info"])
-    assert dev["info"]["sweep_kernel"] == 1
-    assert_parity(dev, runs)
+    for spec, kind in (("pp,8", 1), ("pp4,7", 2)):
+        with _Geometry(spec):
+            dev, runs = run_both(P, O, J, h, 0, "i8", 1024, 120, 0.2, 1.0, 0.02, 0.6, 40, 11, trace=False,
+                                 sample=sample)
+        say("geometry", dev["info"])
+        assert dev["info"]["sweep_kernel"] == kind
+        assert_parity(dev, runs)
 
 
 def test_autotune_keeps_results(P, O):
