@@ -32,6 +32,7 @@ CUS, CLOCK_HZ = 256, 2.4e9
 VALU_OPS_PEAK = CUS * 64 * CLOCK_HZ          # 64 FP32/INT32 lanes per CU per clock
 INT8_MFMA_PEAK = 5.0e15                      # dense int8 ops/s
 BF16_MFMA_PEAK = 2.5e15
+FP4_MFMA_PEAK = 10.1e15
 # Arithmetic operations of one spin-update in the sweep specification (TANH
 # mode): drift 1, readout 1, field add 1, energy term 3, kick 27 (gamma x,
 # 2|u|, e^y 17, sech^2 assembly 3 with the division counted once, c*d,
@@ -375,10 +376,15 @@ def main():
     achieved = su_launch * OPS_PER_SPIN_UPDATE / (kern_ms / 1000)
     Np = info["Np"]
     mfma_ops = 2.0 * Np * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
-    mfma_peak = INT8_MFMA_PEAK if info["path_name"] == "i8" else BF16_MFMA_PEAK * 0.5
+    fp4_ops = info["sweep_kernel"] == 2  # interleaved sweep with FP4 MFMA operands
+    if fp4_ops:
+        Nk = math.ceil(Np / 128) * 128  # FP4 products run over 128-wide k blocks
+        mfma_ops = 2.0 * Nk * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
+    mfma_peak = (FP4_MFMA_PEAK if fp4_ops else INT8_MFMA_PEAK if info["path_name"] == "i8"
+                 else BF16_MFMA_PEAK * 0.5)
     geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel")}
     kernel = ("k_sweep_fp32" if info["path_name"] == "fp32" else
-              "k_sweep_pp" if info["sweep_kernel"] == 1 else "k_sweep_mfma")
+              "k_sweep_pp" if info["sweep_kernel"] >= 1 else "k_sweep_mfma")
     if args.geometry_out:
         with open(args.geometry_out, "w") as f:
             json.dump(geometry, f)
@@ -419,7 +425,8 @@ def main():
     out = {
         "metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "i8" if info["path_name"] == "i8" else info["path_name"],
+        "scaling": "weak", "vs_baseline": None,
+        "dtype": "fp4" if info["sweep_kernel"] == 2 else info["path_name"],
         "data": "synthetic",
         "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
                    "schedule": s, "group": info["group"], "rows_per_block": info["rows_per_block"],
