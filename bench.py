@@ -56,6 +56,12 @@ WORKLOADS = {
                   desc="serving: Poisson arrivals at 200 req/s, planted frustrated-loop instances, N log-uniform "
                        "in [100,4000], half dense / half sparse, half integer / half fixed point (2^-4); 64 replicas, "
                        "stop at the planted energy or 2e4 steps"),
+    "tts_sweep": dict(gen="tts_sweep", args=dict(sizes=(8, 16, 32, 64, 128, 256, 512, 1024), seed=0), R=256,
+                      T=1000, sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
+                      desc="time to target versus N for the Table 2 families (maxcut_dense, maxcut_d3, sk_bool, "
+                           "sk_ising, sk_uniform, spin_model; fractional ones on the 2^-6 grid); 256 replicas x "
+                           "max(1000, 10 N) steps per run; target: exhaustive ground state for N <= 20, else the "
+                           "best energy of a 20x longer run"),
     "sk2000": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=5, bits=8), R=512, T=20000,
                    sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
                    desc="SK N=2000 J~N(0,1) 8-bit fixed point (2^-5), h in [-1,1], 512 replicas x 2e4 steps"),
@@ -263,6 +269,85 @@ def run_batch_bench(args, w):
     print(json.dumps(out), flush=True)
 
 
+def tts99(t_run, p_hat, R):
+    """Eq. 9 with the success probability of one launch of R replicas."""
+    P = 1.0 - (1.0 - p_hat) ** R if p_hat > 0 else 0.0
+    if P >= 0.99:
+        return t_run
+    if P <= 0:
+        return float("inf")
+    return t_run * math.log(0.01) / math.log(1.0 - P)
+
+
+def ground_energy_exhaustive(Ji, hi):
+    """Minimum over all 2^N spin states of Eq. 2 in integer units (N <= 20),
+    enumerated in chunks with numpy."""
+    import numpy as np
+    N = Ji.shape[0]
+    J64, h64 = Ji.astype(np.int64), hi.astype(np.int64)
+    best = None
+    chunk = 1 << min(N, 14)
+    bits = np.arange(N, dtype=np.int64)
+    for start in range(0, 1 << N, chunk):
+        idx = np.arange(start, min(start + chunk, 1 << N), dtype=np.int64)
+        S = 1 - 2 * ((idx[:, None] >> bits[None, :]) & 1)       # rows of +-1
+        E2 = -(np.einsum("ri,ij,rj->r", S, J64, S)) - 2 * (S @ h64)  # 2 E (i<j sum counted twice)
+        m = int(E2.min()) // 2
+        best = m if best is None else min(best, m)
+    return best
+
+
+def run_tts_sweep(args, w):
+    """Time to target of one anneal (R replicas in parallel) for each Table 2
+    family and size.  One JSON line with every point."""
+    import numpy as np
+    import torch
+    from paper_2407_10205_amd import instances as inst, phia
+
+    R, s = w["R"], w["sched"]
+    stream = torch.cuda.Stream()
+    points = []
+    t_all = time.perf_counter()
+    for fam in inst.TABLE2_FAMILIES:
+        for n in w["args"]["sizes"]:
+            N = n + (n % 2 if fam == "maxcut_d3" else 0)
+            T = max(w["T"], 10 * N)
+            J, h = inst.table2_family(fam, N, w["args"]["seed"] + n)
+            prob = phia.Problem(J, h, stream=stream.cuda_stream)
+            f = prob.info()["frac_bits"]
+            if N <= 20:
+                Ji = np.rint(J * 2 ** f).astype(np.int32)
+                hi = np.rint(h * 2 ** f).astype(np.int32)
+                target, how = ground_energy_exhaustive(Ji, hi), "exhaustive"
+            else:
+                prob.anneal(R, 20 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
+                            refresh_L=s["refresh_L"], seed=777)
+                target, how = int(prob.best_exact()[0]), "best of a 20x longer run"
+            prob.anneal(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"], refresh_L=s["refresh_L"],
+                        seed=1)  # warm-up
+            torch.cuda.synchronize()
+            reps, succ = 3, []
+            t0 = time.perf_counter()
+            for i in range(reps):
+                prob.anneal(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
+                            refresh_L=s["refresh_L"], seed=100 + i)
+                E, _, _ = prob.replica_best()
+                succ.append(float(np.mean(E <= target)))
+            t_run = (time.perf_counter() - t0) / reps
+            info = prob.info()
+            prob.close()
+            p_hat = float(np.mean(succ))
+            pt = {"family": fam, "N": N, "steps": T, "path": info["path_name"], "frac_bits": f, "sweep_kernel": info["sweep_kernel"],
+                  "group": info["group"], "target_units": target, "target": how, "replica_success": p_hat,
+                  "t_run_s": t_run, "tts99_s": tts99(t_run, p_hat, R)}
+            points.append(pt)
+            log(json.dumps(pt))
+    out = {"metric": "tts99_s", "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
+           "config": {"workload": w["desc"], "replicas": R, "schedule": s},
+           "points": points, "wall_s": time.perf_counter() - t_all}
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(J, h, w, budget_s):
     """Time the oracle on a bounded replica/step sample of the workload."""
     import numpy as np
@@ -334,6 +419,9 @@ def main():
         return
     if w["gen"] == "serve":
         run_serve_bench(args, w)
+        return
+    if w["gen"] == "tts_sweep":
+        run_tts_sweep(args, w)
         return
     J, h = make_instance(w)
     N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]

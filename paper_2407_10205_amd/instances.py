@@ -97,6 +97,42 @@ def uniform_fixed(N, seed, frac_bits=8, with_field=True):
     return _sym(U), h
 
 
+def regular3_graph(N, seed):
+    """Adjacency matrix of a random 3-regular graph (pairing model with
+    restarts; N even)."""
+    J, _ = regular3_pm1(N, seed, with_field=False)
+    return np.abs(J)
+
+
+# Table 2 families.  The table lists the problem's coefficients; as for the
+# max-cut rows (graph weights w, Ising couplings J = -w), every family enters
+# Eq. 2 with couplings -w, so that all of them are frustrated.
+def table2_family(name, N, seed, frac_bits=6):
+    """Instance of a Table 2 family of size N: (J, h) on the 2^-frac_bits
+    grid (fractional families are rounded onto it)."""
+    g = rng(seed)
+    if name == "maxcut_dense":          # unweighted max-cut on G(N, 1/2)
+        return er_maxcut(N, 0.5, seed)
+    if name == "maxcut_d3":             # unweighted max-cut on a cubic graph
+        return -regular3_graph(N, seed), np.zeros(N)
+    if name == "sk_bool":               # w_ij in {0, 1}, iid fair coin
+        W = g.integers(0, 2, size=(N, N)).astype(np.float64)
+        return -_sym(W), np.zeros(N)
+    if name == "sk_ising":              # w_ij in {-1, +1}
+        return sk_pm1(N, seed)
+    if name == "sk_uniform":            # w_ij = 0 or U(0, 1), each with probability 1/2
+        sc = float(2 ** frac_bits)
+        W = np.where(g.random((N, N)) < 0.5, 0.0, np.rint(g.random((N, N)) * sc) / sc)
+        return -_sym(W), np.zeros(N)
+    if name == "spin_model":            # w_ij, h_i uniform on [-1, 1]
+        J, h = uniform_fixed(N, seed, frac_bits=frac_bits)
+        return -J, h
+    raise ValueError(f"unknown family {name}")
+
+
+TABLE2_FAMILIES = ("maxcut_dense", "maxcut_d3", "sk_bool", "sk_ising", "sk_uniform", "spin_model")
+
+
 def random_field_pm1(N, seed):
     """Integer fields in {-1, 0, 1} drawn independently (used to add h to an
     integer coupling family)."""

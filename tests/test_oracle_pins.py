@@ -358,3 +358,4 @@ def test_planted_loops_energy_is_the_ground_state(O, dense):
         assert O.energy(Ji, h.astype(np.int32), t) == E
         Eg, _ = O.bruteforce(Ji, h.astype(np.int32))
         assert Eg == E
+
