@@ -32,6 +32,8 @@ def _load():
     lib.oracle_sincos_2pi.argtypes = [C.c_float, P, P]
     lib.oracle_sech2.argtypes = [C.c_float]
     lib.oracle_sech2.restype = C.c_float
+    lib.oracle_poly2.argtypes = [C.c_float]
+    lib.oracle_poly2.restype = C.c_float
     lib.oracle_uniform.argtypes = [C.c_uint32]
     lib.oracle_uniform.restype = C.c_float
     lib.oracle_gauss.argtypes = [C.c_uint64, C.c_uint32, C.c_uint64, C.c_uint64, C.c_uint64]
@@ -48,7 +50,7 @@ def _load():
     lib.oracle_beta_linear.argtypes = [C.c_float, C.c_float, C.c_int64, P]
     lib.oracle_anneal.argtypes = [C.c_int, P, P, C.c_int, C.c_int, C.c_int64, C.c_int64,
                                   C.c_int64, P, C.c_float, C.c_float, C.c_int64, C.c_uint64,
-                                  C.c_int, P, P, P, P, P, P, C.c_int]
+                                  C.c_int, C.c_int, P, P, P, P, P, P, C.c_int]
     lib.oracle_anneal.restype = C.c_int
     lib.oracle_argmin.argtypes = [C.c_int, P]
     lib.oracle_argmin.restype = C.c_int
@@ -85,6 +87,10 @@ def sincos_2pi(u):
 
 def sech2(u):
     return np.float32(_load().oracle_sech2(float(u)))
+
+
+def poly2(u):
+    return np.float32(_load().oracle_poly2(float(u)))
 
 
 def uniform(w):
@@ -161,11 +167,12 @@ class Run:
 
 
 def anneal(J, h, frac_bits, R, betas, eps, gamma, L, seed, k0=0, k1=None, r0=0,
-           run=None, trace=False, threads=1):
+           run=None, trace=False, threads=1, deriv="tanh"):
     """Run steps k0 <= k < k1 (default: all of betas) of the sweep.
 
     With run=None a fresh anneal starts (k0 must be 0); otherwise the given
-    Run is continued in place.  Returns the Run.
+    Run is continued in place.  deriv: "tanh" (Eq. 8) or "poly2" (the
+    quadratic of the POLY2 mode).  Returns the Run.
     """
     N, J, h = _ij(J, h)
     betas = np.ascontiguousarray(betas, dtype=np.float32)
@@ -177,6 +184,7 @@ def anneal(J, h, frac_bits, R, betas, eps, gamma, L, seed, k0=0, k1=None, r0=0,
     run.Etrace = np.zeros((R, k1 - k0), np.int64) if trace else None
     rc = _load().oracle_anneal(N, _p(J), _p(h), frac_bits, R, r0, k0, k1, _p(betas),
                                float(eps), float(gamma), int(L), int(seed), int(init),
+                               {"tanh": 0, "poly2": 1}[deriv],
                                _p(run.x), _p(run.v), _p(run.bestE), _p(run.bestS),
                                _p(run.bestStep), _p(run.Etrace), int(threads))
     if rc != 0:

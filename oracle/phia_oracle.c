@@ -157,6 +157,18 @@ float oracle_sech2(float u)
     return (4.0f * t) * (y * y);
 }
 
+/* POLY2 derivative mode: the FPGA replaces Eq. 8's sech^2 by a quadratic
+ * polynomial (Sec. 2.3; its coefficients are not given).  Reading: the
+ * truncated parabola d(u) = max(0, 1 - u^2 / 2.25), which equals sech^2 at 0
+ * and has the same integral over the real line (4 * 1.5 / 3 = 2).  Op order:
+ * t = u*u; q = fma(-t, 4/9, 1); d = q > 0 ? q : 0. */
+float oracle_poly2(float u)
+{
+    float t = u * u;
+    float q = fmaf(-t, 4.0f / 9.0f, 1.0f);
+    return q > 0.0f ? q : 0.0f;
+}
+
 float oracle_uniform(uint32_t w)
 {
     return (float)(2u * (w >> 9) + 1u) * 0x1p-24f;
@@ -307,7 +319,7 @@ enum { TAG_X = 0, TAG_V = 1 };
 
 static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
                        int64_t rr, int64_t k0, int64_t k1, const float* betas,
-                       float eps, float gamma, int64_t L, uint64_t seed, int init,
+                       float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
                        float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                        int64_t* Etrace, int8_t* s, int32_t* I)
 {
@@ -342,10 +354,11 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
             memcpy(bestS, s, (size_t)N);
         }
         /* A7, second line, with Eq. 5 and Eq. 8:
-         * v <- v + eps (beta gamma sech^2(gamma x) sigma I - x). */
+         * v <- v + eps (beta gamma sech^2(gamma x) sigma I - x)
+         * (POLY2 mode: the quadratic in place of sech^2). */
         float c = (betas[k] * gamma) * sigma;
         for (int i = 0; i < N; ++i) {
-            float d = oracle_sech2(gamma * x[i]);
+            float d = deriv ? oracle_poly2(gamma * x[i]) : oracle_sech2(gamma * x[i]);
             float p = c * d;
             float g = fmaf(p, (float)I[i], -x[i]);
             v[i] = fmaf(eps, g, v[i]);
@@ -355,11 +368,12 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
 
 int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
                   int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
-                  float eps, float gamma, int64_t L, uint64_t seed, int init,
+                  float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
                   float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                   int64_t* Etrace, int threads)
 {
     if (N < 1 || R < 0 || k0 < 0 || k1 < k0 || L < 1 || frac_bits < 0 || frac_bits > 30) return -1;
+    if (deriv != 0 && deriv != 1) return -1;
     if (init && k0 != 0) return -1;
     float sigma = ldexpf(1.0f, -frac_bits);
     if (threads < 1) threads = 1;
@@ -376,7 +390,7 @@ int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
 #endif
         for (int r = 0; r < R; ++r) {
             if (!s || !I) continue;
-            anneal_one(N, J, h, sigma, r0 + r, k0, k1, betas, eps, gamma, L, seed, init,
+            anneal_one(N, J, h, sigma, r0 + r, k0, k1, betas, eps, gamma, L, seed, init, deriv,
                        x + (int64_t)r * N, v + (int64_t)r * N, bestE + r,
                        bestS + (int64_t)r * N, bestStep + r,
                        Etrace ? Etrace + (int64_t)r * (k1 - k0) : NULL, s, I);

@@ -29,6 +29,7 @@ float oracle_exp_nonpos(float y);            /* e^y for y <= 0, 0 below -80     
 float oracle_ln_unit(float u);               /* ln u for normal u in (0, 1)           */
 void  oracle_sincos_2pi(float u, float* c, float* s); /* cos, sin of 2*pi*u, u in (0,1) */
 float oracle_sech2(float u);                 /* 1 - tanh^2(u), the Eq. 8 factor      */
+float oracle_poly2(float u);                 /* max(0, 1 - u^2/2.25), POLY2 mode     */
 float oracle_uniform(uint32_t w);            /* (2*(w>>9)+1) * 2^-24                  */
 float oracle_gauss(uint64_t seed, uint32_t tag, uint64_t r, uint64_t round, uint64_t i);
 
@@ -59,10 +60,11 @@ void oracle_beta_linear(float b0, float b1, int64_t T, float* out);
  * betas has at least k1 entries (indexed by absolute step k).
  * Etrace (optional) receives E_k for every replica and step: [R][k1-k0].
  * threads: OpenMP threads over replicas (<= 0 means 1).
+ * deriv: 0 TANH (sech^2 of Eq. 8), 1 POLY2 (oracle_poly2 in its place).
  * Returns 0, or -1 on a bad argument. */
 int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
                   int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
-                  float eps, float gamma, int64_t L, uint64_t seed, int init,
+                  float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
                   float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                   int64_t* Etrace, int threads);
 

@@ -359,3 +359,74 @@ def test_planted_loops_energy_is_the_ground_state(O, dense):
         Eg, _ = O.bruteforce(Ji, h.astype(np.int32))
         assert Eg == E
 
+
+
+# ------------------------------------------------------------ POLY2 ----
+def test_poly2_closed_form(O):
+    """POLY2 mode: d(u) = max(0, 1 - u^2 / 2.25), the truncated parabola with
+    d(0) = sech^2(0) = 1 and the same integral over the line (2)."""
+    us = np.concatenate([np.linspace(-2.0, 2.0, 4001), [0.0, -0.0, 1.5, -1.5, 40.0]]).astype(np.float32)
+    got = np.array([O.poly2(u) for u in us], np.float64)
+    ref = np.maximum(0.0, 1.0 - us.astype(np.float64) ** 2 / 2.25)
+    assert np.max(np.abs(got - ref)) <= 3 * 2.0 ** -24
+    assert O.poly2(0.0) == 1.0 and O.poly2(1.5) == 0.0 and O.poly2(-1.5) == 0.0 and O.poly2(2.0) == 0.0
+    assert all(O.poly2(u) == O.poly2(-u) for u in us)
+    du = 1e-4
+    grid = np.arange(-1.6, 1.6 + du / 2, du, dtype=np.float64)
+    vals = np.array([O.poly2(np.float32(u)) for u in grid], np.float64)
+    integral = du * (vals.sum() - 0.5 * (vals[0] + vals[-1]))
+    assert abs(integral - 2.0) < 1e-3
+
+
+def test_poly2_decoupled_spins_conserve_energy(O):
+    """J = 0, h != 0, constant beta, POLY2 mode: the kick is the gradient of
+    U(x) = -beta sigma h Q(gamma x) + x^2/2 with Q(u) = u - u^3/6.75 on
+    |u| <= 1.5 (and +-1 beyond; Q' is the quadratic), so A7 keeps
+    H = U + v^2/2 within O(eps)."""
+    N, R = 4, 2
+    h = np.array([4, -8, 2, 12], np.int32)          # sigma = 1/4
+    J = np.zeros((N, N), np.int32)
+    beta, gamma, eps = 1.5, 2.0, 0.01
+    T = 3000
+    betas = np.full(T, beta, np.float32)
+
+    def Q(u):
+        c = np.clip(u, -1.5, 1.5)
+        return c - c ** 3 / 6.75
+
+    def Hs(x, v):
+        return -beta * (h / 4.0) * Q(gamma * x) + 0.5 * x * x + 0.5 * v * v
+
+    run = O.Run(N, R)
+    rs = np.random.default_rng(2)
+    run.x[:] = rs.standard_normal((R, N)).astype(np.float32)
+    run.v[:] = rs.standard_normal((R, N)).astype(np.float32)
+    run.bestE[:] = np.iinfo(np.int64).max
+    H0 = Hs(run.x.astype(np.float64), run.v.astype(np.float64))
+    worst = 0.0
+    for k in range(1, T, 100):
+        O.anneal(J, h, 2, R, betas, eps, gamma, 10**9, 0, k0=k, k1=min(k + 100, T), run=run, deriv="poly2")
+        worst = max(worst, np.max(np.abs(Hs(run.x.astype(np.float64), run.v.astype(np.float64)) - H0)))
+    assert worst < 40 * eps
+
+
+def test_poly2_mode_only_changes_the_kick_factor(O):
+    """With beta = 0 the derivative factor is multiplied by zero, so both
+    modes run bit-identically; with beta > 0 they differ."""
+    J, h = _c1()
+    zero = np.zeros(300, np.float32)
+    a = O.anneal(J, h, 0, 4, zero, 0.2, 1.0, 50, 7)
+    b = O.anneal(J, h, 0, 4, zero, 0.2, 1.0, 50, 7, deriv="poly2")
+    assert np.array_equal(a.x.view(np.uint32), b.x.view(np.uint32))
+    betas = O.beta_linear(0.1, 3.0, 300)
+    a = O.anneal(J, h, 0, 4, betas, 0.2, 1.0, 50, 7)
+    b = O.anneal(J, h, 0, 4, betas, 0.2, 1.0, 50, 7, deriv="poly2")
+    assert not np.array_equal(a.x, b.x)
+
+
+def test_poly2_c1_reaches_bruteforce_ground_state(O):
+    J, h = _c1()
+    Eg, _ = O.bruteforce(J, h)
+    betas = O.beta_linear(0.1, 3.0, 1000)
+    run = O.anneal(J, h, 0, 64, betas, 0.2, 1.0, 50, 1234, deriv="poly2", threads=4)
+    assert run.bestE.min() == Eg
