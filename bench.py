@@ -38,6 +38,9 @@ FP4_MFMA_PEAK = 10.1e15
 # 2|u|, e^y 17, sech^2 assembly 3 with the division counted once, c*d,
 # int->float, two fma).  The 16-column MFMA output is exactly the field.
 OPS_PER_SPIN_UPDATE = 33
+# POLY2 mode: the kick is gamma x, u*u, one fma, max, c*d, int->float and two
+# fma (8 instead of 27).
+OPS_PER_SPIN_UPDATE_POLY2 = 14
 
 WORKLOADS = {
     # name: (generator, kwargs, R, T, schedule)
@@ -348,7 +351,7 @@ def run_tts_sweep(args, w):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(J, h, w, budget_s):
+def cpu_baseline(J, h, w, budget_s, deriv="tanh"):
     """Time the oracle on a bounded replica/step sample of the workload."""
     import numpy as np
     from oracle import oracle as O
@@ -363,12 +366,12 @@ def cpu_baseline(J, h, w, budget_s):
     threads = max(1, min(16, os.cpu_count() or 1))
     # calibrate one replica on a few steps, then size the sample to the budget
     t = time.perf_counter()
-    O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1)
+    O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1, deriv=deriv)
     per_step = (time.perf_counter() - t) / 20
     R = threads
     steps = int(max(20, min(T, budget_s / max(per_step, 1e-9))))
     t = time.perf_counter()
-    O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads)
+    O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads, deriv=deriv)
     dt = time.perf_counter() - t
     return {"value": R * N * steps / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"replicas 0..{R - 1}, steps 0..{steps - 1} of the same schedule, "
@@ -391,6 +394,8 @@ def main():
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise rocprofv3 outputs in DIR/{stats,fetch,write} and exit")
     ap.add_argument("--geometry-out", metavar="FILE", help="write the launch geometry used to FILE")
+    ap.add_argument("--deriv", default="tanh", choices=["tanh", "poly2"],
+                    help="derivative factor of the kick: sech^2 (Eq. 8) or the FPGA's quadratic (POLY2 mode)")
     ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
     ap.add_argument("--chunk", type=int, default=500, help="serving workload: steps per scheduling round")
@@ -432,7 +437,7 @@ def main():
 
     def one(seed, events=None):
         prob.start(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"], refresh_L=s["refresh_L"],
-                   seed=seed)
+                   seed=seed, deriv=args.deriv)
         if events is not None:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -461,7 +466,8 @@ def main():
     value = su / wall
     kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     su_launch = float(R) * N * T
-    achieved = su_launch * OPS_PER_SPIN_UPDATE / (kern_ms / 1000)
+    ops_su = OPS_PER_SPIN_UPDATE_POLY2 if args.deriv == "poly2" else OPS_PER_SPIN_UPDATE
+    achieved = su_launch * ops_su / (kern_ms / 1000)
     Np = info["Np"]
     mfma_ops = 2.0 * Np * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
     fp4_ops = info["sweep_kernel"] == 2  # interleaved sweep with FP4 MFMA operands
@@ -480,7 +486,7 @@ def main():
                 "frac": achieved / VALU_OPS_PEAK,
                 "traffic": recorded_traffic(kernel, args.workload, w["desc"], geometry),
                 "kernel": kernel,
-                "kernel_ms": kern_ms, "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
+                "kernel_ms": kern_ms, "ops_per_spin_update": ops_su,
                 "mfma_executed_ops_per_s": mfma_ops / (kern_ms / 1000),
                 "mfma_frac_of_peak": (mfma_ops / (kern_ms / 1000)) / mfma_peak}
 
@@ -491,7 +497,7 @@ def main():
         if not args.no_tune:
             ref.autotune(R, 100)
         ref.anneal(R, 10 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
-                   refresh_L=s["refresh_L"], seed=4242)
+                   refresh_L=s["refresh_L"], seed=4242, deriv=args.deriv)
         target = ref.best_exact()[0]
         ref.close()
         p_hat = float(np.mean(E_last <= target))
@@ -509,7 +515,7 @@ def main():
         calibrate_copy()
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(J, h, w, args.cpu_seconds)
+        cpu = cpu_baseline(J, h, w, args.cpu_seconds, args.deriv)
     out = {
         "metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -517,7 +523,7 @@ def main():
         "dtype": "fp4" if info["sweep_kernel"] == 2 else info["path_name"],
         "data": "synthetic",
         "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
-                   "schedule": s, "group": info["group"], "rows_per_block": info["rows_per_block"],
+                   "schedule": dict(s, deriv=args.deriv), "group": info["group"], "rows_per_block": info["rows_per_block"],
                    "j_in_lds": info["j_in_lds"], "sweep_kernel": kernel, "autotune_us_per_step": tuned_us},
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }

@@ -69,12 +69,19 @@ typedef struct {
  * beta_k = float(b0 + ((b1 - b0) * k) / (steps - 1)) evaluated in double.
  * eps is the integrator step of A7, gamma the surrogate slope of Eq. 7-8,
  * refresh_L the number of steps between momentum draws (v ~ N(0, I) at every
- * k with k mod refresh_L == 0, k = 0 included). */
+ * k with k mod refresh_L == 0, k = 0 included).  deriv_mode picks the factor
+ * of the kick: PHIA_DERIV_TANH, the sech^2(gamma x) of Eq. 8, or
+ * PHIA_DERIV_POLY2, the quadratic polynomial that the FPGA uses in its place
+ * (Sec. 2.3; coefficients not given there, here max(0, 1 - u^2 / 2.25):
+ * equal to sech^2 at 0 and of equal area). */
+typedef enum { PHIA_DERIV_TANH = 0, PHIA_DERIV_POLY2 = 1 } phia_deriv;
+
 typedef struct {
     float beta0, beta1;
     const float* betas;
     float eps, gamma;
     int64_t refresh_L;
+    int32_t deriv_mode;     /* phia_deriv; 0 = TANH                                    */
 } phia_schedule;
 
 typedef struct {
@@ -175,8 +182,9 @@ phia_status phia_get_trace(phia_problem* p, int64_t* E);
 /* Self-check of the device's elementary functions (diagnostic hook).
  * kind 0: e^x for x <= 0; 1: ln u, u in (0,1); 2: cos and sin of 2 pi u
  * (out holds 2n floats, cos first); 3: sech^2; 4: Gaussian draws with
- * in64 = {seed, then n quadruples (tag, replica, round, index)}.
- * in: host float[n] (kinds 0-3), out: host float[n] (2n for kind 2). */
+ * in64 = {seed, then n quadruples (tag, replica, round, index)}; 5: the
+ * POLY2 quadratic.  in: host float[n] (kinds 0-3, 5), out: host float[n]
+ * (2n for kind 2). */
 phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                             int32_t device);
 

@@ -114,6 +114,15 @@ PHIA_DEV float dev_sech2(float u)
     return (4.0f * t) * (y * y);
 }
 
+// POLY2 mode: max(0, 1 - u^2 / 2.25) in place of sech^2 (t = u*u,
+// q = fma(-t, 4/9, 1), d = q > 0 ? q : 0).
+PHIA_DEV float dev_poly2(float u)
+{
+    const float t = u * u;
+    const float q = __builtin_fmaf(-t, 4.0f / 9.0f, 1.0f);
+    return q > 0.0f ? q : 0.0f;
+}
+
 PHIA_DEV float dev_uniform(uint32_t w)
 {
     return static_cast<float>(2u * (w >> 9) + 1u) * 0x1p-24f;

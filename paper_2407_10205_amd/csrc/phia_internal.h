@@ -23,6 +23,7 @@ struct SweepArgs {
     const void* J;              // packed couplings, layout depends on the path
     const float* ctab;          // [T] c_k = (beta_k * gamma) * sigma
     float eps, gamma;
+    int32_t deriv;              // 0: sech^2 (Eq. 8), 1: POLY2 quadratic
     int64_t L;                  // momentum refresh period
     uint64_t seed;
     int64_t k0, k1;             // steps [k0, k1) of this launch

@@ -72,9 +72,10 @@ __device__ __attribute__((noinline)) float gauss_v(uint64_t seed, uint64_t repli
     return dev_gauss(seed, kTagV, replica, round, static_cast<uint64_t>(i));
 }
 
-__device__ __forceinline__ float kick(float x, float v, int I, float ck, float eps, float gamma)
+__device__ __forceinline__ float kick(float x, float v, int I, float ck, float eps, float gamma, int deriv)
 {
-    const float d = dev_sech2(gamma * x);
+    const float u = gamma * x;
+    const float d = deriv ? dev_poly2(u) : dev_sech2(u);
     const float p = ck * d;
     const float g = __builtin_fmaf(p, static_cast<float>(I), -x);
     return __builtin_fmaf(eps, g, v);
@@ -240,7 +241,7 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
 #pragma unroll
-            for (int r = 0; r < RB; ++r) v[r][c] = kick(x[r][c], v[r][c], I[r][c], ck, a.eps, a.gamma);
+            for (int r = 0; r < RB; ++r) v[r][c] = kick(x[r][c], v[r][c], I[r][c], ck, a.eps, a.gamma, a.deriv);
     }
 
 #pragma unroll
@@ -809,7 +810,7 @@ k_sweep_mfma(SweepArgs args)
                         if (!cval[cw]) continue;
                         const int sg = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
                         if (col[cw] < N) part += sg * (I[mt][cw][j] + hreg[cw]);
-                        v[mt][cw][j] = kick(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j], ck, eps, gamma);
+                        v[mt][cw][j] = kick(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j], ck, eps, gamma, a.deriv);
                     }
                     part = wave_sum16(part);
                     if (lr == 0)
@@ -1277,7 +1278,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             for (int j = 0; j < 4; ++j) {
                 const int sg = (x[j] >= 0.0f) ? 1 : -1;
                 part[j] = creal ? sg * (I[0][0][j] + hreg1[0]) : 0;
-                v[j] = kick(x[j], v[j], I[0][0][j], ck, eps, gamma);
+                v[j] = kick(x[j], v[j], I[0][0][j], ck, eps, gamma, a.deriv);
             }
             const int p0 = row_sum16_dpp(part[0]), p1 = row_sum16_dpp(part[1]);
             const int p2 = row_sum16_dpp(part[2]), p3 = row_sum16_dpp(part[3]);
@@ -1671,6 +1672,8 @@ __global__ void __launch_bounds__(256) k_fmath_eval(int kind, const float* in, c
             out[2 * q + 1] = s;
         } else if (kind == 3) {
             out[q] = dev_sech2(in[q]);
+        } else if (kind == 5) {
+            out[q] = dev_poly2(in[q]);
         } else {
             out[q] = dev_gauss(in64[0], static_cast<uint32_t>(in64[1 + 4 * q]), in64[2 + 4 * q], in64[3 + 4 * q],
                                in64[4 + 4 * q]);

@@ -67,6 +67,7 @@ struct phia_problem {
     int32_t R = 0;
     int64_t T = 0, k = 0, L = 1;
     float eps = 0.f, gamma = 0.f;
+    int deriv = 0;  // phia_deriv of the current anneal
     uint64_t seed = 0;
     float* dctab = nullptr;
     float* dx = nullptr;

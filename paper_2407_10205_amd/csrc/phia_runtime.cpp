@@ -412,6 +412,7 @@ SweepArgs sweep_args(const phia_problem* p)
     a.eps = p->eps;
     a.gamma = p->gamma;
     a.L = p->L;
+    a.deriv = p->deriv;
     a.seed = p->seed;
     a.R = p->R;
     a.r_base = 0;
@@ -606,6 +607,8 @@ phia_status check_schedule(int32_t replicas, int64_t steps, const phia_schedule*
     if (replicas < 1 || replicas > (1 << 20)) return fail(PHIA_EINVAL, "replicas = %d outside [1, 2^20]", replicas);
     if (steps < 1 || steps > (int64_t(1) << 31)) return fail(PHIA_EINVAL, "steps = %lld out of range", (long long)steps);
     if (s->refresh_L < 1) return fail(PHIA_EINVAL, "refresh_L must be >= 1");
+    if (s->deriv_mode != PHIA_DERIV_TANH && s->deriv_mode != PHIA_DERIV_POLY2)
+        return fail(PHIA_EINVAL, "deriv_mode = %d is neither TANH nor POLY2", s->deriv_mode);
     if (!std::isfinite(s->eps) || !std::isfinite(s->gamma)) return fail(PHIA_EINVAL, "eps and gamma must be finite");
     return PHIA_OK;
 }
@@ -653,6 +656,7 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
     p->eps = s->eps;
     p->gamma = s->gamma;
     p->L = s->refresh_L;
+    p->deriv = s->deriv_mode;
     p->seed = seed;
     p->has_run = false;
     p->started = false;
@@ -1051,9 +1055,9 @@ phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64,
                             int32_t device)
 {
     clear_error();
-    if (kind < 0 || kind > 4 || n < 0 || !out) return fail(PHIA_EINVAL, "bad argument");
+    if (kind < 0 || kind > 5 || n < 0 || !out) return fail(PHIA_EINVAL, "bad argument");
     if (n == 0) return PHIA_OK;
-    if (kind < 4 && !in) return fail(PHIA_EINVAL, "in is null");
+    if (kind != 4 && !in) return fail(PHIA_EINVAL, "in is null");
     if (kind == 4 && !in64) return fail(PHIA_EINVAL, "in64 is null");
     hipError_t e = hipSetDevice(device);
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
@@ -1062,7 +1066,7 @@ phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64,
     uint64_t* d64 = nullptr;
     phia_status st = PHIA_OK;
     if ((e = hipMalloc(&dout, nout * sizeof(float))) != hipSuccess) return fail(PHIA_ENOMEM, "allocation failed");
-    if (kind < 4) {
+    if (kind != 4) {
         if ((e = hipMalloc(&din, static_cast<size_t>(n) * sizeof(float))) != hipSuccess ||
             (e = hipMemcpy(din, in, static_cast<size_t>(n) * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess)
             st = hip_fail(nullptr, e, "fmath upload");

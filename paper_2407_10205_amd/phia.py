@@ -48,7 +48,10 @@ class Options(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("beta0", C.c_float), ("beta1", C.c_float), ("betas", C.c_void_p),
-                ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64)]
+                ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64), ("deriv_mode", C.c_int32)]
+
+
+DERIV = {"tanh": 0, "poly2": 1}
 
 
 class Result(C.Structure):
@@ -132,12 +135,14 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50):
-    """Build a Schedule; keeps a reference to the betas array on the object."""
+def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, deriv="tanh"):
+    """Build a Schedule; keeps a reference to the betas array on the object.
+    deriv: "tanh" (Eq. 8) or "poly2" (the FPGA's quadratic)."""
     s = Schedule()
     s.eps = eps
     s.gamma = gamma
     s.refresh_L = int(refresh_L)
+    s.deriv_mode = DERIV[deriv] if isinstance(deriv, str) else int(deriv)
     if betas is not None:
         b = np.ascontiguousarray(betas, dtype=np.float32)
         if b.shape[0] < steps:
@@ -192,8 +197,9 @@ class Problem:
     def set_trace(self, enable=True):
         _check(lib().phia_set_trace(self._p, 1 if enable else 0))
 
-    def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0):
-        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L)
+    def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
+              deriv="tanh"):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv)
         _check(lib().phia_anneal_start(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
 
@@ -203,8 +209,9 @@ class Problem:
     def sync(self):
         _check(lib().phia_sync(self._p))
 
-    def anneal(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0):
-        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L)
+    def anneal(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
+               deriv="tanh"):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv)
         _check(lib().phia_anneal(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
 
@@ -277,7 +284,7 @@ def batch_run(problems, replicas, steps, schedules, seeds):
     keep = []
     for i, sc in enumerate(schedules):
         one = make_schedule(int(stp[i]), sc["eps"], sc["gamma"], sc.get("beta0"), sc.get("beta1"),
-                            sc.get("betas"), sc.get("refresh_L", 50))
+                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"))
         keep.append(one)
         C.memmove(C.byref(scheds, i * C.sizeof(Schedule)), C.byref(one), C.sizeof(Schedule))
     _check(lib().phia_batch_run(arr, n, _ptr(reps), _ptr(stp), C.cast(scheds, C.c_void_p), _ptr(sd)))
@@ -303,8 +310,8 @@ class Server:
         self._keep = {}
 
     def submit(self, problem, replicas, max_steps, target, eps, gamma, beta0=None, beta1=None, betas=None,
-               refresh_L=50, seed=0):
-        sch = make_schedule(max_steps, eps, gamma, beta0, beta1, betas, refresh_L)
+               refresh_L=50, seed=0, deriv="tanh"):
+        sch = make_schedule(max_steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv)
         t = C.c_uint64()
         _check(lib().phia_server_submit(self._s, problem._p, int(replicas), int(max_steps), int(target),
                                         C.byref(sch), int(seed), C.byref(t)))

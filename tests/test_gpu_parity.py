@@ -31,13 +31,13 @@ def int_units(J, h, f):
     return (np.rint(J * 2**f).astype(np.int32), np.rint(h * 2**f).astype(np.int32))
 
 
-def run_both(P, O, J, h, f, path, R, T, eps, gamma, b0, b1, L, seed, trace=True, sample=None):
+def run_both(P, O, J, h, f, path, R, T, eps, gamma, b0, b1, L, seed, trace=True, sample=None, deriv="tanh"):
     """Run device and oracle on the same instance; returns (dev dict, oracle Run)."""
-    say(f"case N={J.shape[0]} R={R} T={T} path={path} f={f} seed={seed}")
+    say(f"case N={J.shape[0]} R={R} T={T} path={path} f={f} seed={seed} deriv={deriv}")
     prob = P.Problem(J, h, frac_bits=f, path=path)
     if trace:
         prob.set_trace(True)
-    prob.anneal(R, T, eps, gamma, beta0=b0, beta1=b1, refresh_L=L, seed=seed)
+    prob.anneal(R, T, eps, gamma, beta0=b0, beta1=b1, refresh_L=L, seed=seed, deriv=deriv)
     E, S, K = prob.replica_best()
     x, v, k = prob.get_state()
     dev = dict(E=E, S=S, K=K, x=x, v=v, k=k, info=prob.info(),
@@ -48,7 +48,7 @@ def run_both(P, O, J, h, f, path, R, T, eps, gamma, b0, b1, L, seed, trace=True,
     rows = range(R) if sample is None else sample
     runs = {}
     for r in rows:
-        runs[r] = O.anneal(Ji, hi, f, 1, betas, eps, gamma, L, seed, r0=r, trace=trace, threads=1)
+        runs[r] = O.anneal(Ji, hi, f, 1, betas, eps, gamma, L, seed, r0=r, trace=trace, threads=1, deriv=deriv)
     return dev, runs
 
 
@@ -82,6 +82,10 @@ def test_fmath_bit_exact(P, O):
     got = P.eval_fmath(3, xs)
     ref = np.array([O.sech2(x) for x in xs], np.float32)
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
+    xs = np.concatenate([rs.normal(0, 1, 30000), [0.0, -0.0, 1.5, -1.5, 40.0]]).astype(np.float32)
+    got = P.eval_fmath(5, xs)
+    ref = np.array([O.poly2(x) for x in xs], np.float32)
+    assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
     quads = np.stack([rs.integers(0, 2, 20000), rs.integers(0, 2**40, 20000),
                       rs.integers(0, 2**20, 20000), rs.integers(0, 2**16, 20000)], axis=1).astype(np.uint64)
     got = P.eval_fmath(4, quads=quads, seed=0xABCDEF)
@@ -109,6 +113,15 @@ def test_ragged_fixed_point_parity(P, O, path):
     and fields on the 2^-5 grid, momentum refresh period not dividing T."""
     J, h = inst.sk_gauss_fixed(77, 3, frac_bits=5, bits=8)
     dev, runs = run_both(P, O, J, h, 5, path, 37, 301, 0.15, 1.5, 0.05, 2.0, 37, 99)
+    assert_parity(dev, runs)
+
+
+@pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo"])
+def test_poly2_mode_parity(P, O, path):
+    """POLY2 derivative mode (quadratic in place of sech^2) on the ragged
+    fixed-point case: every replica bit-identical to the oracle."""
+    J, h = inst.sk_gauss_fixed(77, 3, frac_bits=5, bits=8)
+    dev, runs = run_both(P, O, J, h, 5, path, 37, 301, 0.15, 1.5, 0.05, 2.0, 37, 99, deriv="poly2")
     assert_parity(dev, runs)
 
 
@@ -374,10 +387,10 @@ def test_interleaved_benchmark_shape_sampled(P, O):
     eight workgroups per block: sampled replicas against the oracle."""
     J, h = inst.er_maxcut(800, 0.06, 0)
     sample = [0, 15, 16, 31, 32, 511, 1023]
-    for spec, kind in (("pp,8", 1), ("pp4,7", 2)):
+    for spec, kind, deriv in (("pp,8", 1, "tanh"), ("pp4,7", 2, "tanh"), ("pp4,7", 2, "poly2")):
         with _Geometry(spec):
             dev, runs = run_both(P, O, J, h, 0, "i8", 1024, 120, 0.2, 1.0, 0.02, 0.6, 40, 11, trace=False,
-                                 sample=sample)
+                                 sample=sample, deriv=deriv)
         say("geometry", dev["info"])
         assert dev["info"]["sweep_kernel"] == kind
         assert_parity(dev, runs)
@@ -416,7 +429,8 @@ def test_batch_matches_single_runs_and_oracle(P, O):
             J, h = inst.sk_gauss_fixed(N, seed, frac_bits=5, bits=8)
         else:
             J, h = inst.sk_gauss_fixed(N, seed, frac_bits=12, bits=16)
-        sc = dict(eps=0.2, gamma=1.0, beta0=0.05 * seed, beta1=1.0 + seed, refresh_L=10 + seed)
+        sc = dict(eps=0.2, gamma=1.0, beta0=0.05 * seed, beta1=1.0 + seed, refresh_L=10 + seed,
+                  deriv="poly2" if seed % 2 else "tanh")
         inst_list.append((J, h))
         probs.append(P.Problem(J, h, path=path))
         reps.append(R)
@@ -431,7 +445,7 @@ def test_batch_matches_single_runs_and_oracle(P, O):
         q = P.Problem(J, h, path=specs[i][2])
         sc = scheds[i]
         q.anneal(reps[i], steps[i], sc["eps"], sc["gamma"], beta0=sc["beta0"], beta1=sc["beta1"],
-                 refresh_L=sc["refresh_L"], seed=seeds[i])
+                 refresh_L=sc["refresh_L"], seed=seeds[i], deriv=sc["deriv"])
         ref = q.replica_best() + q.get_state()[:2]
         for u, w in zip(ref, got):
             assert np.array_equal(u, w), specs[i]
@@ -439,7 +453,7 @@ def test_batch_matches_single_runs_and_oracle(P, O):
             f = 5 if specs[i][0] == "fixed" else 0
             Ji, hi = int_units(J, h, f)
             o = O.anneal(Ji, hi, f, 1, O.beta_linear(sc["beta0"], sc["beta1"], steps[i]), sc["eps"], sc["gamma"],
-                         sc["refresh_L"], seeds[i], r0=reps[i] - 1)
+                         sc["refresh_L"], seeds[i], r0=reps[i] - 1, deriv=sc["deriv"])
             assert got[0][-1] == o.bestE[0] and np.array_equal(got[3][-1], o.x[0]), specs[i]
         q.close()
         p.close()
