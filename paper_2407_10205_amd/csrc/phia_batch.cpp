@@ -111,6 +111,103 @@ phia_status launch_batch_chunk(phia_problem* const* probs, int count, const int6
     return PHIA_OK;
 }
 
+// Steps [p->k, k_end[i]) of column-split problems (k_sweep_mfma geometry with
+// G > 1), several problems per cooperative launch: one table entry per
+// workgroup, all of a problem's workgroups in one launch, launches packed up
+// to the co-resident workgroup count.  Problems that cannot share a launch
+// run alone.
+phia_status launch_group_chunk(phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
+                               SweepArgs*& dtab, size_t& cap)
+{
+    struct Launch {
+        int path, mt, cbw;
+        size_t lds;
+        std::vector<int> members;  // problem indices
+        int nwg;
+    };
+    std::map<std::tuple<int, int, int>, std::vector<int>> by_kernel;
+    for (int i = 0; i < count; ++i) {
+        const phia_problem* p = probs[i];
+        if (k_end[i] <= p->k) continue;
+        if (p->geo.kind != 0 || p->geo.G < 2) return fail(PHIA_EINVAL, "problem %d is not a column-split sweep", i);
+        by_kernel[std::make_tuple(p->path, p->geo.mt, p->geo.cbw)].push_back(i);
+    }
+    std::vector<Launch> launches;
+    std::vector<int> alone;
+    for (auto& kv : by_kernel) {
+        size_t lds = 0;
+        for (int i : kv.second) lds = std::max(lds, probs[i]->geo.lds);
+        const int maxwg = max_coresident_group_table(std::get<0>(kv.first), std::get<1>(kv.first),
+                                                     std::get<2>(kv.first), lds);
+        Launch cur{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), lds, {}, 0};
+        for (int i : kv.second) {
+            const int w = probs[i]->geo.ngroups * probs[i]->geo.G;
+            if (w > maxwg) {
+                alone.push_back(i);
+                continue;
+            }
+            if (cur.nwg + w > maxwg) {
+                launches.push_back(cur);
+                cur.members.clear();
+                cur.nwg = 0;
+            }
+            cur.members.push_back(i);
+            cur.nwg += w;
+        }
+        if (!cur.members.empty()) launches.push_back(cur);
+    }
+    std::vector<SweepArgs> tab;
+    std::vector<size_t> offs;
+    for (const Launch& L : launches) {
+        offs.push_back(tab.size());
+        for (int i : L.members) {
+            phia_problem* p = probs[i];
+            SweepArgs a = sweep_args(p);
+            a.k0 = p->k;
+            a.k1 = k_end[i];
+            a.etrace = nullptr;
+            a.xcd_map = 0;
+            for (int g = 0; g < p->geo.ngroups; ++g)
+                for (int m = 0; m < p->geo.G; ++m) {
+                    SweepArgs it = a;
+                    it.block = g;
+                    it.member = m;
+                    tab.push_back(it);
+                }
+        }
+    }
+    hipError_t e;
+    if (!tab.empty()) {
+        if (tab.size() > cap) {
+            if (dtab) (void)hipFree(dtab);
+            dtab = nullptr;
+            cap = 0;
+            if ((e = hipMalloc(&dtab, sizeof(SweepArgs) * tab.size() * 2)) != hipSuccess)
+                return fail(PHIA_ENOMEM, "work table allocation failed");
+            cap = tab.size() * 2;
+        }
+        if ((e = hipMemcpy(dtab, tab.data(), sizeof(SweepArgs) * tab.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(nullptr, e, "work table upload");
+    }
+    for (size_t li = 0; li < launches.size(); ++li) {
+        const Launch& L = launches[li];
+        if ((e = launch_sweep_group_table(L.path, L.mt, L.cbw, dtab + offs[li], L.nwg, L.lds, st)) != hipSuccess)
+            return hip_fail(nullptr, e, "group table launch");
+        for (int i : L.members) {
+            phia_problem* p = probs[i];
+            const int iters = (p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups;
+            p->seq += static_cast<uint32_t>(iters) * static_cast<uint32_t>(k_end[i] - p->k + 1);
+            p->k = k_end[i];
+            p->has_run = true;
+        }
+    }
+    for (int i : alone) {
+        phia_status s2 = phia_anneal_run(probs[i], k_end[i]);
+        if (s2 != PHIA_OK) return s2;
+    }
+    return PHIA_OK;
+}
+
 }  // namespace phia
 
 extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,

@@ -51,7 +51,8 @@ struct SweepArgs {
     int32_t* err;               // device error word (1 = barrier timeout)
     // batch mode: the launch argument points at one entry per workgroup
     const SweepArgs* table;     // work items (device), or null
-    int32_t block;              // replica block of this work item
+    int32_t block;              // replica block (group) of this work item
+    int32_t member;             // group member of this work item (table launches of the group sweep)
 };
 
 // Layout of packed couplings.
@@ -84,5 +85,11 @@ hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st)
 size_t sweep_batch_lds_bytes(int path, int Np, int j_lds);
 hipError_t prepare_sweep_batch(int path, int cbw, size_t lds_bytes);
 hipError_t launch_sweep_batch(int path, int cbw, const SweepArgs* dtable, int nitems, size_t lds_bytes, hipStream_t st);
+// column-split sweeps of several problems in one cooperative launch: one
+// table entry per workgroup (problem, group, member); all of one problem's
+// workgroups in the same launch
+hipError_t launch_sweep_group_table(int path, int mt, int cbw, const SweepArgs* dtable, int nwg, size_t lds_bytes,
+                                    hipStream_t st);
+int max_coresident_group_table(int path, int mt, int cbw, size_t lds_bytes);
 
 }  // namespace phia

@@ -485,13 +485,14 @@ __device__ __forceinline__ void quasi_gradient_w(int ncw, const unsigned char* S
 
 // One column block and one row tile per wave: registers are capped at 128 so two
 // workgroups share a CU and hide each other's exchange latency.
-// BATCH: each workgroup runs one work item of a table (one replica block of
-// one instance, all of its columns), with the J placement chosen per item.
+// BATCH: each workgroup runs one work item of a table, with the J placement
+// chosen per item: one replica block of one instance and all of its columns,
+// or (with GROUP) one member of one group of a column-split instance, so that
+// one cooperative launch carries several instances.
 template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BATCH = false>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CBW == 1 && MT == 1 ? 4 : 2)))
 k_sweep_mfma(SweepArgs args)
 {
-    static_assert(!(BATCH && GROUP), "batch items run on one workgroup each");
     const SweepArgs a = BATCH ? args.table[blockIdx.x] : args;
     const bool jl = BATCH ? (a.j_lds != 0) : JLDS;
     constexpr int RB = 16 * MT;
@@ -507,7 +508,9 @@ k_sweep_mfma(SweepArgs args)
 
     int group = BATCH ? a.block : static_cast<int>(blockIdx.x), member = 0;
     const int G = GROUP ? a.G : 1;
-    if (GROUP) {
+    if (GROUP && BATCH) {
+        member = a.member;
+    } else if (GROUP) {
         if (a.xcd_map) {
             const int w = blockIdx.x, pos = w >> 3;
             member = pos % G;
@@ -1490,6 +1493,51 @@ hipError_t launch_sweep_batch(int path, int cbw, const SweepArgs* dtable, int ni
             hipLaunchKernelGGL((k_sweep_mfma<kPathBf16, 1, 4, false, false, false, true>), grid, block, lds, st, a);
     }
     return hipGetLastError();
+}
+
+template <int PATH, int MT, int CBW>
+static const void* group_table_kernel()
+{
+    return reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, true>);
+}
+
+static const void* group_table_kernel(int path, int mt, int cbw)
+{
+    if (path == kPathI8) {
+        if (mt == 1) return cbw == 1 ? group_table_kernel<kPathI8, 1, 1>() : group_table_kernel<kPathI8, 1, 2>();
+        return cbw == 1 ? group_table_kernel<kPathI8, 2, 1>() : group_table_kernel<kPathI8, 2, 2>();
+    }
+    if (mt == 1) return cbw == 1 ? group_table_kernel<kPathBf16, 1, 1>() : group_table_kernel<kPathBf16, 1, 2>();
+    return cbw == 1 ? group_table_kernel<kPathBf16, 2, 1>() : group_table_kernel<kPathBf16, 2, 2>();
+}
+
+hipError_t launch_sweep_group_table(int path, int mt, int cbw, const SweepArgs* dtable, int nwg, size_t lds,
+                                    hipStream_t st)
+{
+    if (mt < 1 || mt > 2 || cbw < 1 || cbw > 2 || nwg < 1) return hipErrorInvalidValue;
+    const void* kern = group_table_kernel(path, mt, cbw);
+    hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    if (e != hipSuccess) return e;
+    SweepArgs a{};
+    a.table = dtable;
+    void* args[] = {&a};
+    e = hipLaunchCooperativeKernel(kern, dim3(static_cast<unsigned>(nwg)), dim3(kThreads), args,
+                                   static_cast<unsigned>(lds), st);
+    if (e != hipSuccess) return e;
+    return hipGetLastError();
+}
+
+int max_coresident_group_table(int path, int mt, int cbw, size_t lds)
+{
+    int dev = 0, cus = 0, per = 0;
+    if (mt < 1 || mt > 2 || cbw < 1 || cbw > 2) return 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+    const void* f = group_table_kernel(path, mt, cbw);
+    if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
+        return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;
+    return per * cus;
 }
 
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)

@@ -42,6 +42,8 @@ void free_state(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
 phia_status launch_batch_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
                                SweepArgs*& dtab, size_t& cap);
+phia_status launch_group_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
+                               SweepArgs*& dtab, size_t& cap);
 }  // namespace phia
 
 struct phia_problem;
@@ -64,6 +66,7 @@ struct phia_problem {
     size_t base_bytes = 0;
     // anneal
     bool started = false, has_run = false, trace = false;
+    bool one_block_kernel = false;  // restrict geometries to k_sweep_mfma (server table launches)
     int32_t R = 0;
     int64_t T = 0, k = 0, L = 1;
     float eps = 0.f, gamma = 0.f;

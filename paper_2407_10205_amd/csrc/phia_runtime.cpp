@@ -288,7 +288,8 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
 static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g)
 {
     const int Np = p->Np, ncb = Np / 16;
-    if (p->path != PHIA_PATH_I8 || p->trace || G < 2 || G > ncb || ncb > kPpMaxNcb) return false;
+    if (p->path != PHIA_PATH_I8 || p->trace || p->one_block_kernel || G < 2 || G > ncb || ncb > kPpMaxNcb)
+        return false;
     if (fp4 && !p->dJ4) return false;
     if (p->maxrow >= kPpMaxRowSum || 2 * p->maxrow * p->N >= (int64_t(1) << 31)) return false;
     if ((ncb + G - 1) / G > kWaves) return false;
@@ -375,8 +376,10 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         if (iters != min_iters) continue;
         const int cbs_max = (p->Np / 16 + g.G - 1) / g.G;
         const double elems = static_cast<double>(g.rows) * cbs_max * 16;
-        const double cost = g.kind >= 1 ? 1e6 + 2 * g.G - (g.kind == 2 ? 1 : 0)
-                                        : (g.G > 1 ? 2e6 : 0.0) + elems * 2 + (g.j_lds ? 0 : 1);
+        double cost = g.kind >= 1 ? 1e6 + 2 * g.G - (g.kind == 2 ? 1 : 0)
+                                  : (g.G > 1 ? 2e6 : 0.0) + elems * 2 + (g.j_lds ? 0 : 1);
+        // Served requests share cooperative launches: the fewest workgroups.
+        if (p->one_block_kernel) cost = static_cast<double>(g.nblocks) * g.G * 4 + (g.j_lds ? 0 : 1) + g.mt;
         if (!p->geo.ok || cost < best) {
             p->geo = g;
             best = cost;

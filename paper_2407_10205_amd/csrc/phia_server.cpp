@@ -71,8 +71,10 @@ struct phia_server {
     int dev = 0;
     hipStream_t st = nullptr;
     int64_t* host_res = nullptr;  // pinned: [2 * max_slots] (energy, replica)
-    SweepArgs* dtab = nullptr;
+    SweepArgs* dtab = nullptr;  // work table of the batched small instances
     size_t dtab_cap = 0;
+    SweepArgs* gtab = nullptr;  // work table of the column-split instances
+    size_t gtab_cap = 0;
     uint64_t next_ticket = 1;
     bool stop = false;
     std::thread worker;
@@ -100,6 +102,7 @@ void finish(phia_server* s, Request* r, int32_t state)
     r->res.steps_used = r->p->k;
     if (r->started) free_state(r->p);
     r->p->st = r->saved_stream;
+    r->p->one_block_kernel = false;
     r->p->started = false;
     r->p->has_run = false;
     s->in_use -= r->footprint;
@@ -109,8 +112,8 @@ void finish(phia_server* s, Request* r, int32_t state)
 void round_once(phia_server* s, std::vector<Request*>& run)
 {
     const int n = static_cast<int>(run.size());
-    std::vector<phia_problem*> small;
-    std::vector<int64_t> small_end;
+    std::vector<phia_problem*> small, split;
+    std::vector<int64_t> small_end, split_end;
     hipError_t e = hipSuccess;
     for (Request* r : run) {
         phia_problem* p = r->p;
@@ -118,6 +121,9 @@ void round_once(phia_server* s, std::vector<Request*>& run)
         if (p->Np <= kBatchMaxNp && p->path != PHIA_PATH_FP32) {
             small.push_back(p);
             small_end.push_back(k_end);
+        } else if (p->path != PHIA_PATH_FP32 && p->geo.kind == 0 && p->geo.G > 1) {
+            split.push_back(p);
+            split_end.push_back(k_end);
         } else if (k_end > p->k) {
             if (phia_anneal_run(p, k_end) != PHIA_OK) r->failed = true;
         }
@@ -126,6 +132,11 @@ void round_once(phia_server* s, std::vector<Request*>& run)
                                              s->dtab, s->dtab_cap) != PHIA_OK)
         for (Request* r : run)
             if (r->p->Np <= kBatchMaxNp) r->failed = true;
+    // Column-split instances: several per cooperative launch.
+    if (!split.empty() && launch_group_chunk(split.data(), static_cast<int>(split.size()), split_end.data(), s->st,
+                                             s->gtab, s->gtab_cap) != PHIA_OK)
+        for (Request* r : run)
+            if (std::find(split.begin(), split.end(), r->p) != split.end()) r->failed = true;
     for (int i = 0; i < n; ++i) {
         phia_problem* p = run[i]->p;
         if ((e = launch_argmin(p->dbestE, p->R, p->dscratch, s->st)) != hipSuccess ||
@@ -196,6 +207,7 @@ void service(phia_server* s)
         for (Request* r : admitted) {
             r->saved_stream = r->p->st;
             r->p->st = s->st;
+            r->p->one_block_kernel = true;  // geometries that the table launches carry
             if (phia_anneal_start(r->p, r->R, r->max_steps, &r->sched, r->seed) != PHIA_OK)
                 r->failed = true;
             else
@@ -403,6 +415,7 @@ void phia_server_destroy(phia_server* s)
     (void)hipSetDevice(s->dev);
     for (auto& kv : s->all) delete kv.second;
     if (s->dtab) (void)hipFree(s->dtab);
+    if (s->gtab) (void)hipFree(s->gtab);
     if (s->host_res) (void)hipHostFree(s->host_res);
     if (s->st) (void)hipStreamDestroy(s->st);
     delete s;

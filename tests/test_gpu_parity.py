@@ -511,6 +511,34 @@ def test_server_result_same_alone_and_in_mix(P, O):
         p.close()
 
 
+def test_server_column_split_requests_share_launches(P, O):
+    """Large requests (column-split geometries) of several sizes and replica
+    counts run together, several per cooperative launch; with an unreachable
+    target each runs its whole budget and must equal a plain anneal of that
+    many steps (best energy, replica, best state), and the oracle on a
+    sampled replica."""
+    specs = []
+    for i, (N, R, T) in enumerate([(600, 32, 300), (777, 48, 250), (1000, 16, 200), (700, 64, 260)]):
+        J, h, E, t = inst.planted_loops(N, 90 + i, alpha=0.4, dense=(i % 2 == 1))
+        specs.append((J, h, -(1 << 60), R, T, 300 + i))
+    res, spins = _serve(P, specs, 8, chunk=90)
+    for i, (J, h, _, R, T, seed) in enumerate(specs):
+        r = res[i]
+        say("request", i, r)
+        assert r["state"] == P.REQ_DONE and r["steps_used"] == T and not r["success"]
+        p = P.Problem(J, h, path="i8")
+        p.anneal(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=25, seed=seed)
+        E, S, K = p.replica_best()
+        info = p.info()
+        p.close()
+        say("plain", info)
+        assert r["energy_units"] == E.min() and r["replica"] == int(np.argmin(E))
+        assert np.array_equal(spins[i], S[r["replica"]])
+        Ji, hi = int_units(J, h, 0)
+        o = O.anneal(Ji, hi, 0, 1, O.beta_linear(0.1, 3.0, T), 0.2, 1.0, 25, seed, r0=R - 1)
+        assert E[R - 1] == o.bestE[0]
+
+
 def test_server_budget_forces_queueing_and_cancel(P, O):
     specs = []
     for i in range(3):
