@@ -40,9 +40,14 @@ constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kSqrt2 = 1.41421356237309504880f;
 constexpr float kTwoPi = 6.28318530717958647692f;
 
+// Branch-free: the polynomial is evaluated for every y and the result is
+// replaced by 0 below -80 (or for NaN), so that several elements of a lane
+// interleave without divergent branches; the values are those of the early
+// return.
 PHIA_DEV float dev_exp_nonpos(float y)
 {
-    if (!(y >= -80.0f)) return 0.0f;
+    const bool in_range = (y >= -80.0f);
+    y = in_range ? y : 0.0f;
     const float k = __builtin_rintf(y * kLog2e);
     float r = __builtin_fmaf(-k, kLn2Hi, y);
     r = __builtin_fmaf(-k, kLn2Lo, r);
@@ -55,7 +60,8 @@ PHIA_DEV float dev_exp_nonpos(float y)
     p = __builtin_fmaf(p, r, 1.0f);
     p = __builtin_fmaf(p, r, 1.0f);
     const int ki = static_cast<int>(k);
-    return p * bits_to_f(static_cast<uint32_t>(ki + 127) << 23);
+    const float e = p * bits_to_f(static_cast<uint32_t>(ki + 127) << 23);
+    return in_range ? e : 0.0f;
 }
 
 PHIA_DEV float dev_ln_unit(float u)

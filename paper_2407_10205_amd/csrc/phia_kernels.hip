@@ -27,6 +27,8 @@
 //   k_energy_f64   FP64 Eq. 2 energy of one configuration.
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "phia_devmath.h"
 #include "phia_internal.h"
 
@@ -70,6 +72,19 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t st)
 __device__ __attribute__((noinline)) float gauss_v(uint64_t seed, uint64_t replica, uint64_t round, int i)
 {
     return dev_gauss(seed, kTagV, replica, round, static_cast<uint64_t>(i));
+}
+
+// DERIV 0: sech^2 (Eq. 8); 1: the POLY2 quadratic.  Callers branch on the
+// (uniform) mode outside their element loops so that the elements of a lane
+// interleave.
+template <int DERIV>
+__device__ __forceinline__ float kick_t(float x, float v, int I, float ck, float eps, float gamma)
+{
+    const float u = gamma * x;
+    const float d = DERIV ? dev_poly2(u) : dev_sech2(u);
+    const float p = ck * d;
+    const float g = __builtin_fmaf(p, static_cast<float>(I), -x);
+    return __builtin_fmaf(eps, g, v);
 }
 
 __device__ __forceinline__ float kick(float x, float v, int I, float ck, float eps, float gamma, int deriv)
@@ -802,7 +817,24 @@ k_sweep_mfma(SweepArgs args)
                                                     lr, lg, hreg, I);
             }
 
-            // Partial energies of step k and the kick.
+            // The kick of the owned elements (mode branch outside the loops),
+            // then the partial energies of step k.
+            auto kick_all = [&](auto mode) {
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int cw = 0; cw < CBW; ++cw) {
+                        if (!cval[cw]) continue;
+#pragma unroll
+                        for (int j = 0; j < 4; ++j)
+                            v[mt][cw][j] = kick_t<decltype(mode)::value>(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j],
+                                                                        ck, eps, gamma);
+                    }
+            };
+            if (a.deriv)
+                kick_all(std::integral_constant<int, 1>{});
+            else
+                kick_all(std::integral_constant<int, 0>{});
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -813,7 +845,6 @@ k_sweep_mfma(SweepArgs args)
                         if (!cval[cw]) continue;
                         const int sg = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
                         if (col[cw] < N) part += sg * (I[mt][cw][j] + hreg[cw]);
-                        v[mt][cw][j] = kick(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j], ck, eps, gamma, a.deriv);
                     }
                     part = wave_sum16(part);
                     if (lr == 0)
@@ -1281,7 +1312,13 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             for (int j = 0; j < 4; ++j) {
                 const int sg = (x[j] >= 0.0f) ? 1 : -1;
                 part[j] = creal ? sg * (I[0][0][j] + hreg1[0]) : 0;
-                v[j] = kick(x[j], v[j], I[0][0][j], ck, eps, gamma, a.deriv);
+            }
+            if (a.deriv) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = kick_t<1>(x[j], v[j], I[0][0][j], ck, eps, gamma);
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) v[j] = kick_t<0>(x[j], v[j], I[0][0][j], ck, eps, gamma);
             }
             const int p0 = row_sum16_dpp(part[0]), p1 = row_sum16_dpp(part[1]);
             const int p2 = row_sum16_dpp(part[2]), p3 = row_sum16_dpp(part[3]);
