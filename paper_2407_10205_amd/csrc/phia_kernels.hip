@@ -1237,8 +1237,10 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         // Publication q: spins of step k0 + q and partial energies of step
         // k0 + q - 1 of this team's sub-block; read into S (q < nsteps) and
         // the row energy sums (q > 0).  Returns false when the wait gave up.
+        float ck_next = 0.0f;  // c_k of the next compute phase, loaded with its gather
         auto gather = [&](int q) {
             const uint32_t seq = seq0 + static_cast<uint32_t>(q);
+            if (q < nsteps) ck_next = a.ctab[a.k0 + q];
             pp_issue<NU>(xs(seq), ncb, grow, gc0, w);
             const bool ok = pp_complete<NU>(xs(seq), ncb, grow, gc0, seq & 0xffffffu, w, a.err);
             int psum = 0;
@@ -1270,7 +1272,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         auto compute = [&](int s) {
             const int64_t k = a.k0 + s;
             const bool closing = (s == nsteps);
-            const float ck = closing ? 0.0f : a.ctab[k];
+            const float ck = ck_next;
             int I[1][1][4] = {};
             if (!closing && cval) {
                 if (FP4)
