@@ -12,7 +12,14 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-TAG_X, TAG_V = 0, 1
+TAG_X, TAG_V, TAG_MH = 0, 1, 2
+
+
+class _MhC(C.Structure):
+    _fields_ = [("enable", C.c_int32), ("up", C.c_float), ("down", C.c_float),
+                ("x0", C.c_void_p), ("Estart", C.c_void_p), ("Qstart", C.c_void_p),
+                ("Elast", C.c_void_p), ("lam", C.c_void_p), ("acc", C.c_void_p),
+                ("dec", C.c_void_p), ("trace", C.c_void_p)]
 
 
 def _load():
@@ -52,6 +59,8 @@ def _load():
                                   C.c_int64, P, C.c_float, C.c_float, C.c_int64, C.c_uint64,
                                   C.c_int, C.c_int, P, P, P, P, P, P, C.c_int]
     lib.oracle_anneal.restype = C.c_int
+    lib.oracle_anneal_mh.argtypes = lib.oracle_anneal.argtypes + [C.POINTER(_MhC)]
+    lib.oracle_anneal_mh.restype = C.c_int
     lib.oracle_argmin.argtypes = [C.c_int, P]
     lib.oracle_argmin.restype = C.c_int
     _lib = lib
@@ -164,15 +173,27 @@ class Run:
         self.bestS = np.zeros((R, N), np.int8)
         self.bestStep = np.zeros(R, np.int64)
         self.Etrace = None
+        # accept/reject state (used when the anneal runs with mh=...)
+        self.x0 = np.zeros((R, N), np.float32)
+        self.Estart = np.zeros(R, np.int64)
+        self.Qstart = np.zeros(R, np.int64)
+        self.Elast = np.zeros(R, np.int64)
+        self.lam = np.ones(R, np.float32)
+        self.acc = np.zeros(R, np.int32)
+        self.dec = np.zeros(R, np.int32)
+        self.mhtrace = None
 
 
 def anneal(J, h, frac_bits, R, betas, eps, gamma, L, seed, k0=0, k1=None, r0=0,
-           run=None, trace=False, threads=1, deriv="tanh"):
+           run=None, trace=False, threads=1, deriv="tanh", mh=None):
     """Run steps k0 <= k < k1 (default: all of betas) of the sweep.
 
     With run=None a fresh anneal starts (k0 must be 0); otherwise the given
     Run is continued in place.  deriv: "tanh" (Eq. 8) or "poly2" (the
-    quadratic of the POLY2 mode).  Returns the Run.
+    quadratic of the POLY2 mode).  mh: None, or (up, down) to accept or reject
+    every trajectory of L steps and scale beta by up / down after each
+    outcome (trace=True also records the outcomes in run.mhtrace).  Returns
+    the Run.
     """
     N, J, h = _ij(J, h)
     betas = np.ascontiguousarray(betas, dtype=np.float32)
@@ -182,11 +203,21 @@ def anneal(J, h, frac_bits, R, betas, eps, gamma, L, seed, k0=0, k1=None, r0=0,
     if init:
         run = Run(N, R)
     run.Etrace = np.zeros((R, k1 - k0), np.int64) if trace else None
-    rc = _load().oracle_anneal(N, _p(J), _p(h), frac_bits, R, r0, k0, k1, _p(betas),
-                               float(eps), float(gamma), int(L), int(seed), int(init),
-                               {"tanh": 0, "poly2": 1}[deriv],
-                               _p(run.x), _p(run.v), _p(run.bestE), _p(run.bestS),
-                               _p(run.bestStep), _p(run.Etrace), int(threads))
+    args = (N, _p(J), _p(h), frac_bits, R, r0, k0, k1, _p(betas),
+            float(eps), float(gamma), int(L), int(seed), int(init),
+            {"tanh": 0, "poly2": 1}[deriv],
+            _p(run.x), _p(run.v), _p(run.bestE), _p(run.bestS),
+            _p(run.bestStep), _p(run.Etrace), int(threads))
+    if mh is None:
+        rc = _load().oracle_anneal(*args)
+    else:
+        L = int(L)
+        kd0 = L if k0 < L else k0 + (L - k0 % L) % L
+        nd = (k1 - 1 - kd0) // L + 1 if k1 > kd0 else 0
+        run.mhtrace = np.zeros((R, nd), np.int8) if trace else None
+        st = _MhC(1, float(mh[0]), float(mh[1]), _p(run.x0), _p(run.Estart), _p(run.Qstart),
+                  _p(run.Elast), _p(run.lam), _p(run.acc), _p(run.dec), _p(run.mhtrace))
+        rc = _load().oracle_anneal_mh(*args, C.byref(st))
     if rc != 0:
         raise ValueError("oracle_anneal rejected its arguments")
     return run

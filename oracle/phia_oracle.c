@@ -315,13 +315,77 @@ void oracle_beta_linear(float b0, float b1, int64_t T, float* out)
 /* ------------------------------------------------------------------ */
 /* The sweep                                                           */
 /* ------------------------------------------------------------------ */
-enum { TAG_X = 0, TAG_V = 1 };
+enum { TAG_X = 0, TAG_V = 1, TAG_MH = 2 };
+
+/* State of the accept/reject step of one replica (App. A, Table 3 state 4). */
+typedef struct {
+    int enable;
+    float up, down;   /* factors of lam after an accepted / a rejected trajectory */
+    float* x0;        /* [N] x at the start of the current trajectory              */
+    int64_t* Estart;  /* energy of sgn x0, INT64_MIN before the first one is known */
+    int64_t* Qstart;  /* quantised x.x + v.v at the start of the trajectory        */
+    float* lam;       /* multiplier of beta                                        */
+    int32_t* acc;     /* accepted trajectories                                     */
+    int32_t* dec;     /* decided trajectories                                      */
+    int8_t* trace;    /* optional: outcome of trajectory m (1 accept, 0 reject,
+                         -1 taken without a decision), indexed m - m_first         */
+    int64_t m_first;
+} mh_ctx;
+
+/* x_i^2 + v_i^2 on the grid 2^-24, capped at 2^46 grid units (2^22), as int64:
+ * the squares are exact in double, their sum rounds once. */
+static int64_t kinetic_units(float x, float v)
+{
+    double t = ((double)x * (double)x + (double)v * (double)v) * 0x1p24;
+    return (t < 0x1p46) ? (int64_t)nearbyint(t) : ((int64_t)1 << 46);
+}
+
+static int64_t kinetic_sum(int N, const float* x, const float* v)
+{
+    int64_t q = 0;
+    for (int i = 0; i < N; ++i) q += kinetic_units(x[i], v[i]);
+    return q;
+}
+
+/* End of trajectory m = k/L - 1 at the start of step k (k a positive multiple
+ * of L): accept its end point (x, v) with probability min(1, exp(-dH)), where
+ * H(x, v) = beta E(sgn x) + x.x/2 + v.v/2 (App. A) with the beta of the
+ * trajectory's last step times lam; otherwise return x to the trajectory's
+ * start.  The first trajectory starts from the initial draw, whose energy is
+ * never evaluated: it is taken without a decision.  lam is then multiplied by
+ * up or down (Table 3, state 4), clamped to [2^-10, 2^10]. */
+static void metropolis(const mh_ctx* m, int N, float sigma, int64_t rr, int64_t k, int64_t L,
+                       const float* betas, uint64_t seed, int64_t Eend, float* x, const float* v)
+{
+    const int64_t traj = k / L - 1;
+    int8_t outcome = -1;
+    if (*m->Estart != INT64_MIN) {
+        const double beta = (double)betas[k - 1] * (double)*m->lam;
+        const double dE = (double)(Eend - *m->Estart);
+        const double dQ = (double)(kinetic_sum(N, x, v) - *m->Qstart) * 0x1p-25;
+        const double dH = fma(beta * (double)sigma, dE, dQ);
+        uint64_t ctr[4] = {0, (uint64_t)traj, (uint64_t)rr, TAG_MH}, key[2] = {seed, 0}, out[4];
+        oracle_philox4x64_10(ctr, key, out);
+        const float lnu = oracle_ln_unit(oracle_uniform((uint32_t)out[0]));
+        outcome = ((double)lnu < -dH) ? 1 : 0;
+        float lam = *m->lam * (outcome ? m->up : m->down);
+        lam = fminf(fmaxf(lam, 0x1p-10f), 0x1p10f);
+        *m->lam = lam;
+        *m->acc += outcome;
+        *m->dec += 1;
+    }
+    if (outcome == 0)
+        memcpy(x, m->x0, sizeof(float) * (size_t)N);
+    else
+        *m->Estart = Eend;
+    if (m->trace && traj >= m->m_first) m->trace[traj - m->m_first] = outcome;
+}
 
 static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
                        int64_t rr, int64_t k0, int64_t k1, const float* betas,
                        float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
                        float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
-                       int64_t* Etrace, int8_t* s, int32_t* I)
+                       int64_t* Etrace, int8_t* s, int32_t* I, const mh_ctx* mh, int64_t* Elast)
 {
     if (init) {
         /* App. A, A3: x ~ g(x), the standard normal. */
@@ -330,12 +394,27 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
         *bestE = INT64_MAX;
         *bestStep = -1;
         memset(bestS, 0, (size_t)N);
+        if (mh) {
+            *mh->Estart = INT64_MIN;
+            *mh->Qstart = 0;
+            *mh->lam = 1.0f;
+            *mh->acc = 0;
+            *mh->dec = 0;
+            memcpy(mh->x0, x, sizeof(float) * (size_t)N);
+        }
     }
     for (int64_t k = k0; k < k1; ++k) {
-        /* Momentum drawn afresh at the start of every round of L steps. */
-        if (k % L == 0)
+        if (k % L == 0) {
+            /* Accept/reject of the trajectory that ended with step k - 1. */
+            if (mh && k > 0) metropolis(mh, N, sigma, rr, k, L, betas, seed, *Elast, x, v);
+            /* Momentum drawn afresh at the start of every round of L steps. */
             for (int i = 0; i < N; ++i)
                 v[i] = oracle_gauss(seed, TAG_V, (uint64_t)rr, (uint64_t)(k / L), (uint64_t)i);
+            if (mh) {
+                memcpy(mh->x0, x, sizeof(float) * (size_t)N);
+                *mh->Qstart = kinetic_sum(N, x, v);
+            }
+        }
         /* A7, first line: drift with the current momentum. */
         for (int i = 0; i < N; ++i) x[i] = fmaf(eps, v[i], x[i]);
         /* Spin readout s = sgn x, with sgn(+0) = sgn(-0) = +1. */
@@ -346,6 +425,7 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
         int64_t two_e = 0;
         for (int i = 0; i < N; ++i) two_e += (int64_t)s[i] * ((int64_t)I[i] + h[i]);
         int64_t E = -(two_e / 2);
+        *Elast = E;
         if (Etrace) Etrace[k - k0] = E;
         /* Table 3, state 5: best-so-far, strict improvement keeps the earliest. */
         if (E < *bestE) {
@@ -357,6 +437,7 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
          * v <- v + eps (beta gamma sech^2(gamma x) sigma I - x)
          * (POLY2 mode: the quadratic in place of sech^2). */
         float c = (betas[k] * gamma) * sigma;
+        if (mh) c = c * *mh->lam;
         for (int i = 0; i < N; ++i) {
             float d = deriv ? oracle_poly2(gamma * x[i]) : oracle_sech2(gamma * x[i]);
             float p = c * d;
@@ -366,17 +447,25 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
     }
 }
 
-int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
-                  int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
-                  float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
-                  float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
-                  int64_t* Etrace, int threads)
+int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
+                     int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
+                     float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
+                     float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                     int64_t* Etrace, int threads, const oracle_mh* mh)
 {
     if (N < 1 || R < 0 || k0 < 0 || k1 < k0 || L < 1 || frac_bits < 0 || frac_bits > 30) return -1;
     if (deriv != 0 && deriv != 1) return -1;
     if (init && k0 != 0) return -1;
+    if (mh && !mh->enable) mh = NULL;
+    if (mh && (!mh->x0 || !mh->Estart || !mh->Qstart || !mh->Elast || !mh->lam || !mh->acc || !mh->dec))
+        return -1;
+    if (mh && !(mh->up > 0.0f && mh->down > 0.0f)) return -1;
     float sigma = ldexpf(1.0f, -frac_bits);
     if (threads < 1) threads = 1;
+    /* decisions at k in [max(k0, L), k1) with k % L == 0, trajectories k/L - 1 */
+    const int64_t kd0 = (k0 < L ? L : k0 + (L - k0 % L) % L);
+    const int64_t m_first = kd0 / L - 1;
+    const int64_t nd = (k1 > kd0) ? (k1 - 1 - kd0) / L + 1 : 0;
     int fail = 0;
 #ifdef _OPENMP
 #pragma omp parallel num_threads(threads)
@@ -390,15 +479,43 @@ int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
 #endif
         for (int r = 0; r < R; ++r) {
             if (!s || !I) continue;
+            int64_t elast_local = 0;
+            int64_t* Elast = &elast_local;
+            mh_ctx ctx, *pc = NULL;
+            if (mh) {
+                ctx.enable = 1;
+                ctx.up = mh->up;
+                ctx.down = mh->down;
+                ctx.x0 = mh->x0 + (int64_t)r * N;
+                ctx.Estart = mh->Estart + r;
+                ctx.Qstart = mh->Qstart + r;
+                ctx.lam = mh->lam + r;
+                ctx.acc = mh->acc + r;
+                ctx.dec = mh->dec + r;
+                ctx.trace = mh->trace ? mh->trace + (int64_t)r * nd : NULL;
+                ctx.m_first = m_first;
+                Elast = mh->Elast + r;
+                pc = &ctx;
+            }
             anneal_one(N, J, h, sigma, r0 + r, k0, k1, betas, eps, gamma, L, seed, init, deriv,
                        x + (int64_t)r * N, v + (int64_t)r * N, bestE + r,
                        bestS + (int64_t)r * N, bestStep + r,
-                       Etrace ? Etrace + (int64_t)r * (k1 - k0) : NULL, s, I);
+                       Etrace ? Etrace + (int64_t)r * (k1 - k0) : NULL, s, I, pc, Elast);
         }
         free(s);
         free(I);
     }
     return fail ? -1 : 0;
+}
+
+int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
+                  int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
+                  float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
+                  float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                  int64_t* Etrace, int threads)
+{
+    return oracle_anneal_mh(N, J, h, frac_bits, R, r0, k0, k1, betas, eps, gamma, L, seed, init, deriv,
+                            x, v, bestE, bestS, bestStep, Etrace, threads, NULL);
 }
 
 int oracle_argmin(int R, const int64_t* bestE)

@@ -68,6 +68,31 @@ int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
                   float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                   int64_t* Etrace, int threads);
 
+/* Accept/reject step at the end of every trajectory of L steps (App. A,
+ * Table 3 state 4), with a multiplier lam of beta driven by its outcomes.
+ * Arrays are per replica ([R], x0 [R][N]) and carry the state from one call to
+ * the next; init = 1 resets them.  trace (optional) receives the outcome of
+ * every trajectory decided in this call, [R][number of multiples of L in
+ * [max(k0, L), k1)]: 1 accepted, 0 rejected, -1 taken without a decision. */
+typedef struct {
+    int32_t enable;
+    float up, down;   /* lam *= up after an acceptance, *= down after a rejection */
+    float* x0;
+    int64_t* Estart;
+    int64_t* Qstart;
+    int64_t* Elast;   /* energy of the last step run                               */
+    float* lam;
+    int32_t* acc;
+    int32_t* dec;
+    int8_t* trace;
+} oracle_mh;
+
+int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
+                     int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
+                     float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
+                     float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                     int64_t* Etrace, int threads, const oracle_mh* mh);
+
 /* Lowest best energy over R replicas; ties take the lowest replica index. */
 int oracle_argmin(int R, const int64_t* bestE);
 

@@ -430,3 +430,142 @@ def test_poly2_c1_reaches_bruteforce_ground_state(O):
     betas = O.beta_linear(0.1, 3.0, 1000)
     run = O.anneal(J, h, 0, 64, betas, 0.2, 1.0, 50, 1234, deriv="poly2", threads=4)
     assert run.bestE.min() == Eg
+
+
+# ------------------------------------------------ accept/reject (state 4) -----
+def _mh_rate_closed_form(eps, L, N, n=400000, seed=11):
+    """Acceptance probability of the first decided trajectory for J = h = 0,
+    by FP64 Monte Carlo over the closed-form map [[1, eps], [-eps, 1 - eps^2]]^L:
+    the first trajectory carries (x0, v0) to its end, the second starts there with
+    a fresh v1, and H = (x.x + v.v) / 2 (no coupling term)."""
+    rs = np.random.default_rng(seed)
+    M = np.linalg.matrix_power(np.array([[1.0, eps], [-eps, 1.0 - eps * eps]]), L)
+    x0, v0, v1 = (rs.standard_normal((n, N)) for _ in range(3))
+    xs = M[0, 0] * x0 + M[0, 1] * v0
+    xe = M[0, 0] * xs + M[0, 1] * v1
+    ve = M[1, 0] * xs + M[1, 1] * v1
+    dH = 0.5 * ((xe * xe + ve * ve).sum(1) - (xs * xs + v1 * v1).sum(1))
+    return float(np.minimum(1.0, np.exp(-dH)).mean())
+
+
+@pytest.mark.parametrize("eps,L,N", [(1.2, 2, 1), (1.2, 3, 2)])
+def test_mh_acceptance_rate_harmonic(O, eps, L, N):
+    """With no couplings H is the kinetic-plus-quadratic term alone; the
+    fraction of replicas that accept their first decided trajectory matches the
+    closed-form expectation (a sign error gives ~0.93, a dropped 1/2 ~0.84 or
+    ~0.50, a doubled one ~0.64 or ~0.29)."""
+    R = 20000
+    J = np.zeros((N, N), np.int32)
+    betas = np.full(2 * L + 1, 1.0, np.float32)
+    run = O.anneal(J, None, 0, R, betas, eps, 1.0, L, 31, mh=(1.0, 1.0), trace=True, threads=4)
+    assert run.mhtrace.shape == (R, 2)
+    assert np.all(run.mhtrace[:, 0] == -1)
+    rate = float(np.mean(run.mhtrace[:, 1] == 1))
+    p = _mh_rate_closed_form(eps, L, N)
+    sd = math.sqrt(p * (1 - p) / R)
+    assert abs(rate - p) < 5 * sd + 0.003, (rate, p)
+    assert np.array_equal(run.acc, (run.mhtrace[:, 1] == 1).astype(np.int32))
+    assert np.all(run.dec == 1)
+
+
+def test_mh_large_beta_accepts_exactly_the_energy_drops(O):
+    """beta large in H while gamma is tiny (the kick scales with beta gamma):
+    beta sigma dE dominates dH, so a trajectory whose end energy differs from
+    its start is accepted iff the energy fell; rejected ends restore the start."""
+    J, h = inst.sk_pm1(12, 3)
+    J, h = J.astype(np.int32), h.astype(np.int32)
+    L = 5
+    betas = np.full(600, 1e4, np.float32)
+    run = O.anneal(J, h, 0, 16, betas, 0.2, 1e-6, L, 3, mh=(1.0, 1.0), trace=True)
+    E, tr = run.Etrace, run.mhtrace
+    checked = rejected = 0
+    for r in range(16):
+        Es = None
+        for m in range(tr.shape[1]):
+            Ee = E[r, (m + 1) * L - 1]
+            if tr[r, m] == -1:
+                assert m == 0
+                Es = Ee
+                continue
+            if Ee != Es:
+                assert (tr[r, m] == 1) == (Ee < Es)
+                checked += 1
+            rejected += tr[r, m] == 0
+            if tr[r, m] == 1:
+                Es = Ee
+    assert checked > 1000 and rejected > 1000
+
+
+def test_mh_reject_restores_the_trajectory_start(O):
+    J, h = _c1()
+    L = 6
+    betas = O.beta_linear(2.0, 3.0, 2 * L + 1)
+    run = O.anneal(J, h, 0, 32, betas, 0.4, 1.0, L, 17, k1=L, mh=(1.0, 1.0))
+    xA, EA = run.x.copy(), run.Elast.copy()
+    O.anneal(J, h, 0, 32, betas, 0.4, 1.0, L, 17, k0=L, k1=2 * L, run=run, mh=(1.0, 1.0))
+    xB, EB = run.x.copy(), run.Elast.copy()
+    assert np.array_equal(run.x0, xA)   # snapshot at the start of trajectory 1
+    O.anneal(J, h, 0, 32, betas, 0.4, 1.0, L, 17, k0=2 * L, k1=2 * L + 1, run=run,
+             mh=(1.0, 1.0), trace=True)
+    acc = run.mhtrace[:, 0] == 1
+    assert 0 < acc.sum() < 32
+    for r in range(32):
+        assert np.array_equal(run.x0[r], xB[r] if acc[r] else xA[r])
+        assert run.Estart[r] == (EB[r] if acc[r] else EA[r])
+
+
+def test_mh_all_accepted_equals_plain_sweep(O):
+    """Small steps and short trajectories: every trajectory is accepted, and the
+    run is bit-identical to the sweep without the accept/reject step."""
+    J, h = inst.sk_pm1(8, 3)
+    J, h = J.astype(np.int32), h.astype(np.int32)
+    betas = np.full(400, 0.001, np.float32)
+    a = O.anneal(J, h, 0, 8, betas, 0.01, 1.0, 4, 3, mh=(1.0, 1.0), trace=True)
+    b = O.anneal(J, h, 0, 8, betas, 0.01, 1.0, 4, 3, trace=True)
+    assert np.all(a.acc == a.dec) and a.dec.sum() == 8 * 98
+    for f in ("x", "v", "bestE", "bestS", "Etrace"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert np.count_nonzero(np.diff(b.Etrace, axis=1)) > 50
+
+
+def test_mh_lambda_multiplies_beta(O):
+    """up = down = 2 doubles lam after every decision, which must equal a run
+    with lam fixed and beta doubled per trajectory (powers of two are exact):
+    lam enters the kick and H exactly as a factor of beta."""
+    J, h = inst.sk_pm1(12, 4)
+    J, h = J.astype(np.int32), h.astype(np.int32)
+    L, T = 25, 275
+    betas = O.beta_linear(0.1, 1.0, T)
+    a = O.anneal(J, h, 0, 8, betas, 0.2, 1.0, L, 9, mh=(2.0, 2.0), trace=True)
+    scale = np.array([2.0 ** max(0, k // L - 1) for k in range(T)], np.float32)
+    b = O.anneal(J, h, 0, 8, betas * scale, 0.2, 1.0, L, 9, mh=(1.0, 1.0), trace=True)
+    assert np.all(a.lam == 2.0 ** 9) and np.all(b.lam == 1.0)
+    for f in ("x", "v", "bestE", "Etrace", "mhtrace", "acc"):
+        assert np.array_equal(getattr(a, f), getattr(b, f)), f
+    assert 0 < a.acc.sum() < a.dec.sum()
+
+
+def test_mh_lambda_follows_outcomes(O):
+    J, h = _c1()
+    betas = O.beta_linear(0.5, 3.0, 400)
+    run = O.anneal(J, h, 0, 8, betas, 0.3, 1.0, 40, 5, mh=(2.0, 0.5))
+    expo = 2 * run.acc.astype(np.int64) - run.dec
+    assert np.all(np.abs(expo) <= 10)
+    assert np.array_equal(run.lam, (2.0 ** expo).astype(np.float32))
+    assert np.all(run.dec == 8)  # decisions at k = 80, ..., 360 (k = 40 takes the first)
+
+
+def test_mh_power_of_two_scaling_and_resume(O):
+    Jf, hf = inst.sk_gauss_fixed(24, 3, frac_bits=4)
+    J = np.rint(Jf * 16).astype(np.int32)
+    h = np.rint(hf * 16).astype(np.int32)
+    betas = O.beta_linear(0.5, 3.0, 300)
+    a = O.anneal(J, h, 4, 4, betas, 0.3, 1.0, 20, 8, mh=(1.25, 0.8), trace=True)
+    b = O.anneal(J * 8, h * 8, 7, 4, betas, 0.3, 1.0, 20, 8, mh=(1.25, 0.8), trace=True)
+    assert np.array_equal(a.x, b.x) and np.array_equal(a.mhtrace, b.mhtrace)
+    assert np.array_equal(a.lam, b.lam) and 0 < a.acc.sum() < a.dec.sum()
+    c = O.anneal(J, h, 4, 4, betas, 0.3, 1.0, 20, 8, k1=40, mh=(1.25, 0.8))
+    for k0, k1 in ((40, 137), (137, 300)):
+        O.anneal(J, h, 4, 4, betas, 0.3, 1.0, 20, 8, k0=k0, k1=k1, run=c, mh=(1.25, 0.8))
+    for f in ("x", "v", "bestE", "bestS", "lam", "acc", "dec"):
+        assert np.array_equal(getattr(a, f), getattr(c, f)), f
