@@ -76,12 +76,28 @@ typedef struct {
  * equal to sech^2 at 0 and of equal area). */
 typedef enum { PHIA_DERIV_TANH = 0, PHIA_DERIV_POLY2 = 1 } phia_deriv;
 
+/* metropolis = 1 adds the accept/reject step of App. A (H(x, v) = beta E(sgn x)
+ * + x.x/2 + v.v/2) and Table 3 state 4 (acceptance and temperature): at every
+ * k > 0 with k mod refresh_L == 0 the trajectory of steps [k - refresh_L, k)
+ * is accepted with probability min(1, exp(-dH)), else x returns to its start
+ * (the first trajectory, which starts at the initial draw, is taken as it is).
+ * dH uses the beta of the trajectory's last step times a per-replica
+ * multiplier lam (starts at 1), with x.x + v.v on the grid 2^-24 (each term
+ * capped at 2^22) and the uniform of counter (0, trajectory, replica, 2) of
+ * the Gaussian stream's generator.  After every decision lam is multiplied by
+ * mh_up (accepted) or mh_down (rejected) and clamped to [2^-10, 2^10]; lam
+ * scales beta in the kick as well (c_k lam).  mh_up = mh_down = 1 keeps the
+ * schedule fixed.  metropolis = 0 ignores mh_up and mh_down.  Metropolis runs
+ * use the one-block-per-workgroup sweep (never the interleaved one). */
 typedef struct {
     float beta0, beta1;
     const float* betas;
     float eps, gamma;
     int64_t refresh_L;
     int32_t deriv_mode;     /* phia_deriv; 0 = TANH                                    */
+    int32_t metropolis;     /* 0: no accept/reject step; 1: accept or reject every
+                               trajectory of refresh_L steps                          */
+    float mh_up, mh_down;   /* > 0, finite: factors of the beta multiplier            */
 } phia_schedule;
 
 typedef struct {
@@ -152,9 +168,17 @@ phia_status phia_replica_best(phia_problem* p, int64_t* E, int8_t* S, int64_t* s
  * (the next step to run). */
 phia_status phia_get_state(phia_problem* p, float* x, float* v, int64_t* k);
 
+/* Accept/reject statistics of a metropolis anneal (App. A, Table 3 state 4),
+ * per replica, each a host array of R or NULL: trajectories accepted,
+ * trajectories decided (the first one is never decided), and the current beta
+ * multiplier.  PHIA_ESTATE if the anneal runs without the step. */
+phia_status phia_replica_mh(phia_problem* p, int32_t* accepted, int32_t* decided, float* lam);
+
 /* Overwrite the continuous state of the current anneal (x, v: host
  * float[R*N]) and set the next step to k (0 <= k <= steps).  Records are
- * kept.  Used to resume from saved state and by invariance tests. */
+ * kept.  The accept/reject state restarts as after the initial draw (start
+ * energy unknown, lam = 1, counts 0).  Used to resume from saved state and by
+ * invariance tests. */
 phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int64_t k);
 
 phia_status phia_get_info(const phia_problem* p, phia_info* out);

@@ -25,17 +25,17 @@ using namespace phia;
 namespace {
 
 struct Bucket {
-    int path = 0, cbw = 2, jl = 1;
+    int path = 0, cbw = 2, jl = 1, mh = 0;
     size_t lds = 0;
     std::vector<SweepArgs> items;
 };
 
 // Work items of steps [p->k, k_end) of problem p, added to its bucket.
-void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int>, Bucket>& buckets)
+void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int, int>, Bucket>& buckets)
 {
     const int ncb = p->Np / 16;
     const int cbw = ncb <= kWaves * 2 ? 2 : 4;
-    const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
+    const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1, p->mh) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
     const int nblocks = (p->R + 15) / 16;
     SweepArgs a = sweep_args(p);
     a.J = p->dJ;  // int8 fragments (the batch kernel's operands)
@@ -46,11 +46,12 @@ void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int
     a.ncb = ncb;
     a.rows = 16;
     a.j_lds = jl;
-    Bucket& b = buckets[std::make_tuple(p->path, cbw, jl)];
+    Bucket& b = buckets[std::make_tuple(p->path, cbw, jl, p->mh)];
     b.path = p->path;
     b.cbw = cbw;
     b.jl = jl;
-    b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl));
+    b.mh = p->mh;
+    b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl, p->mh));
     for (int blk = 0; blk < nblocks; ++blk) {
         SweepArgs it = a;
         it.block = blk;
@@ -71,7 +72,7 @@ namespace phia {
 phia_status launch_batch_chunk(phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
                                SweepArgs*& dtab, size_t& cap)
 {
-    std::map<std::tuple<int, int, int>, Bucket> buckets;
+    std::map<std::tuple<int, int, int, int>, Bucket> buckets;
     for (int i = 0; i < count; ++i)
         if (k_end[i] > probs[i]->k) add_items(probs[i], k_end[i], buckets);
     std::vector<SweepArgs> tab;
@@ -97,8 +98,8 @@ phia_status launch_batch_chunk(phia_problem* const* probs, int count, const int6
         return hip_fail(nullptr, e, "work table upload");
     size_t bi = 0;
     for (auto& kv : buckets) {
-        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.lds)) != hipSuccess ||
-            (e = launch_sweep_batch(kv.second.path, kv.second.cbw, dtab + offs[bi],
+        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, kv.second.lds)) != hipSuccess ||
+            (e = launch_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, dtab + offs[bi],
                                     static_cast<int>(kv.second.items.size()), kv.second.lds, st)) != hipSuccess)
             return hip_fail(nullptr, e, "batch chunk launch");
         ++bi;
@@ -120,17 +121,17 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
                                SweepArgs*& dtab, size_t& cap)
 {
     struct Launch {
-        int path, mt, cbw;
+        int path, mt, cbw, mh;
         size_t lds;
         std::vector<int> members;  // problem indices
         int nwg;
     };
-    std::map<std::tuple<int, int, int>, std::vector<int>> by_kernel;
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by_kernel;
     for (int i = 0; i < count; ++i) {
         const phia_problem* p = probs[i];
         if (k_end[i] <= p->k) continue;
         if (p->geo.kind != 0 || p->geo.G < 2) return fail(PHIA_EINVAL, "problem %d is not a column-split sweep", i);
-        by_kernel[std::make_tuple(p->path, p->geo.mt, p->geo.cbw)].push_back(i);
+        by_kernel[std::make_tuple(p->path, p->geo.mt, p->geo.cbw, p->mh)].push_back(i);
     }
     std::vector<Launch> launches;
     std::vector<int> alone;
@@ -138,8 +139,9 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
         size_t lds = 0;
         for (int i : kv.second) lds = std::max(lds, probs[i]->geo.lds);
         const int maxwg = max_coresident_group_table(std::get<0>(kv.first), std::get<1>(kv.first),
-                                                     std::get<2>(kv.first), lds);
-        Launch cur{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), lds, {}, 0};
+                                                     std::get<2>(kv.first), std::get<3>(kv.first), lds);
+        Launch cur{std::get<0>(kv.first), std::get<1>(kv.first), std::get<2>(kv.first), std::get<3>(kv.first), lds,
+                   {}, 0};
         for (int i : kv.second) {
             const int w = probs[i]->geo.ngroups * probs[i]->geo.G;
             if (w > maxwg) {
@@ -191,7 +193,8 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
     }
     for (size_t li = 0; li < launches.size(); ++li) {
         const Launch& L = launches[li];
-        if ((e = launch_sweep_group_table(L.path, L.mt, L.cbw, dtab + offs[li], L.nwg, L.lds, st)) != hipSuccess)
+        if ((e = launch_sweep_group_table(L.path, L.mt, L.cbw, L.mh, dtab + offs[li], L.nwg, L.lds, st)) !=
+            hipSuccess)
             return hip_fail(nullptr, e, "group table launch");
         for (int i : L.members) {
             phia_problem* p = probs[i];
@@ -258,7 +261,7 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
     // Replica state and schedules (host tables stay alive until the final sync).
     std::vector<std::vector<float>> ctabs(static_cast<size_t>(count));
     std::vector<SweepArgs> init_tab(static_cast<size_t>(count));
-    std::map<std::tuple<int, int, int>, Bucket> buckets;
+    std::map<std::tuple<int, int, int, int>, Bucket> buckets;
     phia_status st_ = PHIA_OK;
     for (int i = 0; i < count && st_ == PHIA_OK; ++i) {
         phia_problem* p = probs[i];
@@ -275,9 +278,10 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         p->geo.ngroups = p->geo.nblocks;
         const int ncb = p->Np / 16;
         const int cbw = ncb <= kWaves * 2 ? 2 : 4;
-        const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
+        const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1, p->mh) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
         p->geo.cbw = cbw;
         p->geo.j_lds = jl;
+        if ((st_ = setup_mh_geometry(p)) != PHIA_OK) break;
         SweepArgs a = sweep_args(p);
         a.J = p->dJ;
         a.k0 = 0;
@@ -288,11 +292,12 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         a.rows = 16;
         a.j_lds = jl;
         init_tab[static_cast<size_t>(i)] = a;
-        Bucket& b = buckets[std::make_tuple(p->path, cbw, jl)];
+        Bucket& b = buckets[std::make_tuple(p->path, cbw, jl, p->mh)];
         b.path = p->path;
         b.cbw = cbw;
         b.jl = jl;
-        b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl));
+        b.mh = p->mh;
+        b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl, p->mh));
         for (int blk = 0; blk < p->geo.nblocks; ++blk) {
             SweepArgs it = a;
             it.block = blk;
@@ -339,7 +344,7 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         return hip_fail(nullptr, e, "work table upload");
     }
     for (auto& kv : buckets)
-        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.lds)) != hipSuccess) {
+        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, kv.second.lds)) != hipSuccess) {
             cleanup();
             return hip_fail(nullptr, e, "kernel attributes");
         }
@@ -351,7 +356,7 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
     size_t bi = 0;
     for (auto& kv : buckets) {
         if (le == hipSuccess)
-            le = launch_sweep_batch(kv.second.path, kv.second.cbw, dtab + offs[bi],
+            le = launch_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, dtab + offs[bi],
                                     static_cast<int>(kv.second.items.size()), kv.second.lds, st);
         ++bi;
     }

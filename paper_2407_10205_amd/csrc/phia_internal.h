@@ -49,6 +49,18 @@ struct SweepArgs {
     uint64_t* pbuf;             // [2][ngroups][G][rows][2] (seq << 32) | 32-bit half of a partial energy
     uint32_t seq_base;          // sequence number before this launch (tags start at seq_base + 1)
     int32_t* err;               // device error word (1 = barrier timeout)
+    // accept/reject at the end of every trajectory of L steps (mh != 0)
+    int32_t mh;
+    float mh_up, mh_down;       // beta multiplier factors after an acceptance / a rejection
+    float sigma;                // 2^-f
+    const float* btab;          // [T] beta_k
+    float* x0;                  // [R][Np] x at the start of the current trajectory
+    int64_t* mhE;               // [R][2] energy at the trajectory start (INT64_MIN: not known),
+                                //        energy of the last step run
+    int64_t* mhQ;               // [R][G] kinetic units of a member's columns at the trajectory start
+    float* lam;                 // [R] beta multiplier
+    int32_t* mhc;               // [R][2] accepted, decided trajectories
+    uint64_t* mhbuf;            // [2][ngroups][G][rows][4] tagged 32-bit halves of (energy, kinetic) partials
     // batch mode: the launch argument points at one entry per workgroup
     const SweepArgs* table;     // work items (device), or null
     int32_t block;              // replica block (group) of this work item
@@ -72,7 +84,7 @@ hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const 
                              double* out, hipStream_t st);
 hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                              hipStream_t st);
-int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, size_t lds_bytes);
+int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, size_t lds_bytes);
 // interleaved group sweep: int8 J, two 16-replica sub-blocks per workgroup
 constexpr int kPpMaxNcb = 256;            // Np <= 4096
 constexpr int64_t kPpMaxRowSum = 1 << 18;  // 32 * max_i(sum_j |J_ij| + |h_i|) < 2^23
@@ -82,14 +94,16 @@ int max_coresident_pp(int ncb, int fp4, size_t lds_bytes);
 // batch mode: 16-replica work items, one workgroup each, up to 512 columns
 constexpr int kBatchMaxNp = kWaves * 4 * 16;
 hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st);
-size_t sweep_batch_lds_bytes(int path, int Np, int j_lds);
-hipError_t prepare_sweep_batch(int path, int cbw, size_t lds_bytes);
-hipError_t launch_sweep_batch(int path, int cbw, const SweepArgs* dtable, int nitems, size_t lds_bytes, hipStream_t st);
+size_t sweep_batch_lds_bytes(int path, int Np, int j_lds, int mh);
+hipError_t prepare_sweep_batch(int path, int cbw, int mh, size_t lds_bytes);
+hipError_t launch_sweep_batch(int path, int cbw, int mh, const SweepArgs* dtable, int nitems, size_t lds_bytes,
+                              hipStream_t st);
 // column-split sweeps of several problems in one cooperative launch: one
 // table entry per workgroup (problem, group, member); all of one problem's
 // workgroups in the same launch
-hipError_t launch_sweep_group_table(int path, int mt, int cbw, const SweepArgs* dtable, int nwg, size_t lds_bytes,
-                                    hipStream_t st);
-int max_coresident_group_table(int path, int mt, int cbw, size_t lds_bytes);
+// (accept/reject runs: mt = 1, cbw = 2 only)
+hipError_t launch_sweep_group_table(int path, int mt, int cbw, int mh, const SweepArgs* dtable, int nwg,
+                                    size_t lds_bytes, hipStream_t st);
+int max_coresident_group_table(int path, int mt, int cbw, int mh, size_t lds_bytes);
 
 }  // namespace phia

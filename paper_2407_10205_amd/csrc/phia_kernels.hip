@@ -52,6 +52,15 @@ __global__ void __launch_bounds__(256) k_init(SweepArgs a)
         if (i == 0) {
             a.bestE[r] = INT64_MAX;
             a.bestStep[r] = -1;
+            if (a.mh) {
+                a.mhE[r * 2] = INT64_MIN;
+                a.mhE[r * 2 + 1] = 0;
+                a.lam[r] = 1.0f;
+                a.mhc[r * 2] = 0;
+                a.mhc[r * 2 + 1] = 0;
+                const int G = a.G > 1 ? a.G : 1;
+                for (int g = 0; g < G; ++g) a.mhQ[r * G + g] = 0;
+            }
         }
     }
 }
@@ -67,6 +76,57 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t st)
 }
 
 // ------------------------------------------------------- shared helpers --
+// Accept/reject at the end of every trajectory of L steps (App. A: H(x, v) =
+// beta E(sgn x) + x.x/2 + v.v/2; Table 3, state 4: acceptance and temperature).
+constexpr uint32_t kTagMH = 2;
+
+// x^2 + v^2 on the grid 2^-24, capped at 2^46 grid units: the squares are exact
+// in double and their sum rounds once, so sums over a replica are exact int64
+// and independent of the order of summation.
+__device__ __forceinline__ long long kin_units(float x, float v)
+{
+    const double t = (static_cast<double>(x) * static_cast<double>(x) +
+                      static_cast<double>(v) * static_cast<double>(v)) * 0x1p24;
+    return t < 0x1p46 ? static_cast<long long>(__builtin_rint(t)) : (1ll << 46);
+}
+
+// Outcome of trajectory `traj` of stream replica rs: 1 accepted, 0 rejected,
+// -1 taken without a decision (start energy Es not known: the first
+// trajectory starts from the initial draw).  Ee: energy at its end, dq: change
+// of the kinetic units over all columns, beta: inverse temperature of its last
+// step, lam: the replica's beta multiplier.  Accept iff ln u < -dH with
+// dH = beta lam sigma (Ee - Es) + dq 2^-25 in double and u the first uniform
+// of the stream's accept/reject counter (0, traj, rs, tag 2).
+__device__ __forceinline__ int mh_outcome(uint64_t seed, uint64_t rs, int64_t traj, int64_t Es, int64_t Ee,
+                                          int64_t dq, float beta, float lam, float sigma)
+{
+    if (Es == INT64_MIN) return -1;
+    const double bl = static_cast<double>(beta) * static_cast<double>(lam);
+    const double dE = static_cast<double>(Ee - Es);
+    const double dQ = static_cast<double>(dq) * 0x1p-25;
+    const double dH = __builtin_fma(bl * static_cast<double>(sigma), dE, dQ);
+    const u64x4 o = dev_philox(0, static_cast<uint64_t>(traj), rs, kTagMH, seed, 0);
+    const float lnu = dev_ln_unit(dev_uniform(static_cast<uint32_t>(o.w[0])));
+    return (static_cast<double>(lnu) < -dH) ? 1 : 0;
+}
+
+// beta multiplier after an outcome, clamped to [2^-10, 2^10].
+__device__ __forceinline__ float mh_lambda(float lam, int outcome, float up, float down)
+{
+    if (outcome < 0) return lam;
+    const float l = lam * (outcome ? up : down);
+    return fminf(fmaxf(l, 0x1p-10f), 0x1p10f);
+}
+
+__device__ __forceinline__ long long wave_sum16_i64(long long v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
+    return v;
+}
+
 // Momentum draws happen once every L steps; a real call keeps the unrolled
 // sweep loops from holding many Philox states live at once.
 __device__ __attribute__((noinline)) float gauss_v(uint64_t seed, uint64_t replica, uint64_t round, int i)
@@ -116,7 +176,7 @@ __device__ __forceinline__ int wave_sum64(int v)
 
 // --------------------------------------------------------- FP32 sweep --
 // Thread t owns columns i = t + 256 c (c < CPT) of kFp32Rows replicas.
-template <int CPT>
+template <int CPT, bool MH>
 __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
 {
     constexpr int RB = kFp32Rows;
@@ -124,6 +184,12 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
     __shared__ int64_t sPart[RB][4];
     __shared__ int64_t sBest[RB];
     __shared__ int sImp[RB];
+    // accept/reject bookkeeping (used only when a.mh)
+    __shared__ int64_t mEs[RB], mQ0[RB], mEl[RB];
+    __shared__ long long mPart[RB][4];
+    __shared__ float mLam[RB];
+    __shared__ int mOut[RB], mAcc[RB], mDec[RB];
+    constexpr bool mh = MH;
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int Np = a.Np, N = a.N;
@@ -148,11 +214,70 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
         const bool ok = rb0 + tid < a.R;
         sBest[tid] = ok ? a.bestE[rb0 + tid] : INT64_MAX;
         bstep = ok ? a.bestStep[rb0 + tid] : -1;
+        if (mh) {
+            const int64_t gq = rb0 + tid;
+            mEs[tid] = ok ? a.mhE[gq * 2] : INT64_MIN;
+            mEl[tid] = ok ? a.mhE[gq * 2 + 1] : 0;
+            mQ0[tid] = ok ? a.mhQ[gq] : 0;
+            mLam[tid] = ok ? a.lam[gq] : 1.0f;
+            mAcc[tid] = ok ? a.mhc[gq * 2] : 0;
+            mDec[tid] = ok ? a.mhc[gq * 2 + 1] : 0;
+        }
     }
     __syncthreads();
+    float lamr[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) lamr[r] = mh ? mLam[r] : 1.0f;
+    // kinetic units of this thread's elements of row r, summed into mPart[r][wave]
+    auto kin_rows = [&]() {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            long long q = 0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) q += kin_units(x[r][c], v[r][c]);
+            q = wave_sum16_i64(q);
+            q += __shfl_xor(q, 16, 64);
+            q += __shfl_xor(q, 32, 64);
+            if (lane == 0) mPart[r][wave] = q;
+        }
+    };
 
     for (int64_t k = a.k0; k < a.k1; ++k) {
         if (k % a.L == 0) {
+            if (mh && k > 0) {
+                // End of trajectory k / L - 1 (energy of step k - 1 in mEl): one
+                // decision per replica; a rejected end point returns x to the
+                // trajectory's start.
+                kin_rows();
+                __syncthreads();
+                if (tid < RB) {
+                    const int64_t gq = rb0 + tid;
+                    int out = 1;
+                    if (gq < a.R) {
+                        const int64_t qe = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
+                        out = mh_outcome(a.seed, static_cast<uint64_t>(a.r_base + gq), k / a.L - 1, mEs[tid],
+                                         mEl[tid], qe - mQ0[tid], a.btab[k - 1], mLam[tid], a.sigma);
+                        if (out != 0) mEs[tid] = mEl[tid];
+                        mLam[tid] = mh_lambda(mLam[tid], out, a.mh_up, a.mh_down);
+                        if (out >= 0) {
+                            mAcc[tid] += out;
+                            mDec[tid] += 1;
+                        }
+                    }
+                    mOut[tid] = out;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    lamr[r] = mLam[r];
+                    if (mOut[r] == 0 && rb0 + r < a.R)
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c) {
+                            const int i = tid + 256 * c;
+                            if (i < Np) x[r][c] = a.x0[(rb0 + r) * Np + i];
+                        }
+                }
+            }
             const uint64_t rnd = static_cast<uint64_t>(k / a.L);
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
@@ -160,6 +285,18 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
                     v[r][c] = (i < N && rb0 + r < a.R) ? gauss_v(a.seed, a.r_base + rb0 + r, rnd, i) : 0.0f;
+            }
+            if (mh) {
+                // Start of a trajectory: x snapshot and kinetic units (summed
+                // into mQ0 after the next barrier).
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int i = tid + 256 * c;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (rb0 + r < a.R && i < Np) a.x0[(rb0 + r) * Np + i] = x[r][c];
+                }
+                kin_rows();
             }
         }
 #pragma unroll
@@ -232,6 +369,10 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
         if (tid < RB) {
             const int64_t tot = sPart[tid][0] + sPart[tid][1] + sPart[tid][2] + sPart[tid][3];
             const int64_t E = -(tot / 2);
+            if (mh) {
+                mEl[tid] = E;
+                if (k % a.L == 0) mQ0[tid] = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
+            }
             const bool ok = rb0 + tid < a.R;
             if (ok && a.etrace) a.etrace[(rb0 + tid) * a.T + k] = E;
             const int imp = ok && (E < sBest[tid]);
@@ -256,7 +397,8 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
 #pragma unroll
-            for (int r = 0; r < RB; ++r) v[r][c] = kick(x[r][c], v[r][c], I[r][c], ck, a.eps, a.gamma, a.deriv);
+            for (int r = 0; r < RB; ++r)
+                v[r][c] = kick(x[r][c], v[r][c], I[r][c], ck * lamr[r], a.eps, a.gamma, a.deriv);
     }
 
 #pragma unroll
@@ -273,34 +415,55 @@ __global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
     if (tid < RB && rb0 + tid < a.R) {
         a.bestE[rb0 + tid] = sBest[tid];
         a.bestStep[rb0 + tid] = bstep;
+        if (mh) {
+            const int64_t gq = rb0 + tid;
+            a.mhE[gq * 2] = mEs[tid];
+            a.mhE[gq * 2 + 1] = mEl[tid];
+            a.mhQ[gq] = mQ0[tid];
+            a.lam[gq] = mLam[tid];
+            a.mhc[gq * 2] = mAcc[tid];
+            a.mhc[gq * 2 + 1] = mDec[tid];
+        }
     }
 }
 
-hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st)
+template <bool MH>
+static hipError_t launch_fp32_t(const SweepArgs& a, hipStream_t st)
 {
     const int cpt = (a.Np + 255) / 256;
     const unsigned blocks = static_cast<unsigned>((a.R + kFp32Rows - 1) / kFp32Rows);
     const size_t lds = sizeof(float) * static_cast<size_t>(kFp32Rows) * a.Np;
     if (cpt <= 1)
-        hipLaunchKernelGGL(k_sweep_fp32<1>, dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_sweep_fp32<1, MH>), dim3(blocks), dim3(256), lds, st, a);
     else if (cpt <= 2)
-        hipLaunchKernelGGL(k_sweep_fp32<2>, dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_sweep_fp32<2, MH>), dim3(blocks), dim3(256), lds, st, a);
     else if (cpt <= 4)
-        hipLaunchKernelGGL(k_sweep_fp32<4>, dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_sweep_fp32<4, MH>), dim3(blocks), dim3(256), lds, st, a);
     else if (cpt <= 8)
-        hipLaunchKernelGGL(k_sweep_fp32<8>, dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_sweep_fp32<8, MH>), dim3(blocks), dim3(256), lds, st, a);
     else if (cpt <= 16)
-        hipLaunchKernelGGL(k_sweep_fp32<16>, dim3(blocks), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((k_sweep_fp32<16, MH>), dim3(blocks), dim3(256), lds, st, a);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
+hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st)
+{
+    return a.mh ? launch_fp32_t<true>(a, st) : launch_fp32_t<false>(a, st);
+}
+
 // --------------------------------------------------------- MFMA sweep --
 // LDS carve-up of one workgroup, shared with the host launch code.
 struct LdsPlan {
-    uint32_t j_off, s_off, s_bytes, p_off, e_off, b_off, k_off, misc_off, total;
+    uint32_t j_off, s_off, s_bytes, p_off, e_off, b_off, k_off, misc_off, mh_off, total;
 };
+
+// Accept/reject bookkeeping of a replica block in LDS, 56 bytes per replica:
+// int64 [5][rows] (start energy, own kinetic units at the start, own kinetic
+// units at the end, summed energy partials, summed kinetic change), then
+// float [rows] beta multiplier and int32 [3][rows] (outcome, accepted, decided).
+constexpr uint32_t kMhLdsPerRow = 56u;
 
 __host__ __device__ inline uint32_t esz_of(int path) { return path == kPathI8 ? 1u : 2u; }
 __host__ __device__ inline uint32_t cb_bytes(int path, int Np)
@@ -308,7 +471,7 @@ __host__ __device__ inline uint32_t cb_bytes(int path, int Np)
     return static_cast<uint32_t>(Np) * 16u * (path == kPathI8 ? 1u : 4u);
 }
 
-__host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_max, int j_lds)
+__host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_max, int j_lds, int mh = 0)
 {
     LdsPlan p;
     const uint32_t rows = 16u * mt;
@@ -320,7 +483,8 @@ __host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_ma
     p.b_off = p.e_off + 2u * rows * 8u;  // [2][RB] best energies (parity buffers)
     p.k_off = p.b_off + 2u * rows * 8u;  // [RB] step of the best energy
     p.misc_off = p.k_off + rows * 8u;
-    p.total = p.misc_off + 16u;
+    p.mh_off = p.misc_off + 16u;
+    p.total = p.mh_off + (mh ? rows * kMhLdsPerRow : 0u);
     return p;
 }
 
@@ -504,7 +668,7 @@ __device__ __forceinline__ void quasi_gradient_w(int ncw, const unsigned char* S
 // chosen per item: one replica block of one instance and all of its columns,
 // or (with GROUP) one member of one group of a column-split instance, so that
 // one cooperative launch carries several instances.
-template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BATCH = false>
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BATCH = false, bool MH = false>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CBW == 1 && MT == 1 ? 4 : 2)))
 k_sweep_mfma(SweepArgs args)
 {
@@ -539,7 +703,8 @@ k_sweep_mfma(SweepArgs args)
     const int cb1 = (member + 1) * a.ncb / G;
     const int cbs = cb1 - cb0;
     const int cbs_max = (a.ncb + G - 1) / G;
-    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, jl ? 1 : 0);
+    constexpr bool mh = MH;  // accept/reject step (App. A, Table 3 state 4)
+    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, jl ? 1 : 0, mh ? 1 : 0);
     const uint32_t srow = static_cast<uint32_t>(Np) * ESZ + 16u;  // S row stride, bytes
     const uint32_t cbb = cb_bytes(PATH, Np);
     unsigned char* sJ = lds + P.j_off;
@@ -548,6 +713,16 @@ k_sweep_mfma(SweepArgs args)
     int64_t* sB = reinterpret_cast<int64_t*>(lds + P.b_off);   // [2][RB] best energies
     int64_t* sK = reinterpret_cast<int64_t*>(lds + P.k_off);   // [RB] step of the best
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
+    // accept/reject bookkeeping (used only when mh)
+    int64_t* mEs = reinterpret_cast<int64_t*>(lds + P.mh_off);  // energy at the trajectory start
+    int64_t* mQ0 = mEs + RB;      // member's kinetic units at the trajectory start
+    int64_t* mQe = mEs + 2 * RB;  // member's kinetic units at the trajectory end
+    int64_t* mTE = mEs + 3 * RB;  // energy partials of the trajectory's last step, summed
+    int64_t* mTQ = mEs + 4 * RB;  // kinetic change, summed over the group
+    float* mLam = reinterpret_cast<float*>(mEs + 5 * RB);
+    int* mOut = reinterpret_cast<int*>(mLam + RB);
+    int* mAcc = mOut + RB;
+    int* mDec = mAcc + RB;
 
     const unsigned char* Jg = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0) * cbb;
     if (jl) {
@@ -584,6 +759,15 @@ k_sweep_mfma(SweepArgs args)
             const bool ok = rb0 + q < a.R;
             sB[q] = sB[RB + q] = ok ? a.bestE[rb0 + q] : INT64_MAX;
             sK[q] = ok ? a.bestStep[rb0 + q] : -1;
+            if (mh) {
+                const int64_t gq = rb0 + q;
+                mEs[q] = ok ? a.mhE[gq * 2] : INT64_MIN;
+                mQ0[q] = ok ? a.mhQ[gq * G + member] : 0;
+                mQe[q] = mTE[q] = mTQ[q] = 0;
+                mLam[q] = ok ? a.lam[gq] : 1.0f;
+                mAcc[q] = ok ? a.mhc[gq * 2] : 0;
+                mDec[q] = ok ? a.mhc[gq * 2 + 1] : 0;
+            }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -613,6 +797,11 @@ k_sweep_mfma(SweepArgs args)
                 }
         for (int q = tid; q < 3 * RB; q += kThreads) sP[q] = 0;
         __syncthreads();
+        float lamr[MT][4];  // beta multiplier of each held row
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) lamr[mt][j] = mh ? mLam[mt * 16 + 4 * lg + j] : 1.0f;
 
         uint32_t pm = 0;  // signs of step k-1, bit (mt*CBW + cw)*4 + j
         bool aborted = false;
@@ -635,6 +824,106 @@ k_sweep_mfma(SweepArgs args)
                         if (x[mt][cw][j] >= 0.0f) pm |= 1u << ((mt * CBW + cw) * 4 + j);
             if (!last) {
                 if (k == next_ref) {
+                    if (mh && k > 0) {
+                        // End of trajectory k / L - 1: the member's kinetic units
+                        // at its end, then the energy of step k - 1 and the
+                        // kinetic change summed over the group, one decision
+                        // per replica, and a rejected end point returns x to
+                        // the trajectory's start.
+                        __syncthreads();  // partial energies of step k - 1 complete
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                long long q = 0;
+#pragma unroll
+                                for (int cw = 0; cw < CBW; ++cw)
+                                    if (cval[cw]) q += kin_units(x[mt][cw][j], v[mt][cw][j]);
+                                q = wave_sum16_i64(q);
+                                if (lr == 0)
+                                    atomicAdd(reinterpret_cast<unsigned long long*>(mQe + mt * 16 + 4 * lg + j),
+                                              static_cast<unsigned long long>(q));
+                            }
+                        __syncthreads();
+                        if (GROUP) {
+                            const uint32_t mseq = a.seq_base + static_cast<uint32_t>(iter) * seq_stride +
+                                                  static_cast<uint32_t>(s) + 1u;
+                            const uint64_t mtag = static_cast<uint64_t>(mseq) << 32;
+                            const size_t gslot = static_cast<size_t>(par) * a.ngroups + group;
+                            uint64_t* Mb = a.mhbuf + gslot * static_cast<size_t>(G) * RB * 4;
+                            if (tid < RB) {
+                                const uint64_t e = static_cast<uint64_t>(s > 0 ? sP[r3p * RB + tid] : 0);
+                                const uint64_t d = static_cast<uint64_t>(mQe[tid] - mQ0[tid]);
+                                uint64_t* dst = Mb + (static_cast<size_t>(member) * RB + tid) * 4;
+                                __hip_atomic_store(dst, mtag | (e & 0xffffffffu), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_store(dst + 1, mtag | (e >> 32), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_store(dst + 2, mtag | (d & 0xffffffffu), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                                __hip_atomic_store(dst + 3, mtag | (d >> 32), __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_AGENT);
+                            }
+                            for (int q = tid; q < G * RB; q += kThreads) {
+                                const uint64_t* src = Mb + static_cast<size_t>(q) * 4;
+                                uint64_t w[4];
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    w[u] = __hip_atomic_load(src + u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+                                for (int u = 0; u < 4; ++u)
+                                    if (static_cast<uint32_t>(w[u] >> 32) != mseq)
+                                        w[u] = await_tag(src + u, mseq, a.err, sAbort);
+                                const uint64_t e = (w[0] & 0xffffffffu) | ((w[1] & 0xffffffffu) << 32);
+                                const uint64_t d = (w[2] & 0xffffffffu) | ((w[3] & 0xffffffffu) << 32);
+                                atomicAdd(reinterpret_cast<unsigned long long*>(mTE + q % RB),
+                                          static_cast<unsigned long long>(e));
+                                atomicAdd(reinterpret_cast<unsigned long long*>(mTQ + q % RB),
+                                          static_cast<unsigned long long>(d));
+                            }
+                        } else if (tid < RB) {
+                            mTE[tid] = s > 0 ? sP[r3p * RB + tid] : 0;
+                            mTQ[tid] = mQe[tid] - mQ0[tid];
+                        }
+                        __syncthreads();
+                        if (GROUP && *sAbort) {
+                            aborted = true;
+                            break;
+                        }
+                        if (tid < RB) {
+                            const int64_t gq = rb0 + tid;
+                            int out = 1;
+                            if (gq < a.R) {
+                                // energy of step k - 1: summed partials, or stored by
+                                // the previous launch when k is its first step
+                                const int64_t Ee = s > 0 ? -(mTE[tid] / 2) : a.mhE[gq * 2 + 1];
+                                out = mh_outcome(a.seed, static_cast<uint64_t>(a.r_base + gq), k / a.L - 1,
+                                                 mEs[tid], Ee, mTQ[tid], a.btab[k - 1], mLam[tid], a.sigma);
+                                if (out != 0) mEs[tid] = Ee;
+                                mLam[tid] = mh_lambda(mLam[tid], out, a.mh_up, a.mh_down);
+                                if (out >= 0) {
+                                    mAcc[tid] += out;
+                                    mDec[tid] += 1;
+                                }
+                            }
+                            mOut[tid] = out;
+                            mQ0[tid] = mQe[tid] = mTE[tid] = mTQ[tid] = 0;
+                        }
+                        __syncthreads();
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int row = mt * 16 + 4 * lg + j;
+                                lamr[mt][j] = mLam[row];
+                                if (mOut[row] == 0 && rval[mt][j]) {
+                                    const int64_t gr = rb0 + row;
+#pragma unroll
+                                    for (int cw = 0; cw < CBW; ++cw)
+                                        if (cval[cw]) x[mt][cw][j] = a.x0[gr * Np + col[cw]];
+                                }
+                            }
+                    }
                     // Momentum refresh: one Gaussian per owned element, drawn in
                     // a rolled loop (one inlined generator) and moved into the
                     // register-resident v afterwards.
@@ -656,6 +945,27 @@ k_sweep_mfma(SweepArgs args)
                             for (int j = 0; j < 4; ++j) v[mt][cw][j] = vn[(mt * CBW + cw) * 4 + j];
                     next_ref += a.L;
                     ++round;
+                    if (mh) {
+                        // Start of a trajectory: x snapshot and the member's
+                        // kinetic units with the fresh momentum.
+#pragma unroll
+                        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) {
+                                const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+                                long long q = 0;
+#pragma unroll
+                                for (int cw = 0; cw < CBW; ++cw)
+                                    if (cval[cw]) {
+                                        q += kin_units(x[mt][cw][j], v[mt][cw][j]);
+                                        if (rval[mt][j]) a.x0[gr * Np + col[cw]] = x[mt][cw][j];
+                                    }
+                                q = wave_sum16_i64(q);
+                                if (lr == 0)
+                                    atomicAdd(reinterpret_cast<unsigned long long*>(mQ0 + mt * 16 + 4 * lg + j),
+                                              static_cast<unsigned long long>(q));
+                            }
+                    }
                 }
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
@@ -794,6 +1104,7 @@ k_sweep_mfma(SweepArgs args)
                         }
                         if (TRACE && member == 0 && writer && rval[mt][j])
                             a.etrace[(rb0 + row) * a.T + (k - 1)] = E;
+                        if (mh && last && member == 0 && writer && rval[mt][j]) a.mhE[(rb0 + row) * 2 + 1] = E;
                         // replace this row's bits of the record by the signs of step k-1
                         uint32_t rowmask = 0;
 #pragma unroll
@@ -828,7 +1139,7 @@ k_sweep_mfma(SweepArgs args)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
                             v[mt][cw][j] = kick_t<decltype(mode)::value>(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j],
-                                                                        ck, eps, gamma);
+                                                                        ck * lamr[mt][j], eps, gamma);
                     }
             };
             if (a.deriv)
@@ -880,6 +1191,18 @@ k_sweep_mfma(SweepArgs args)
                     a.bestStep[rb0 + q] = sK[q];
                 }
         }
+        if (mh)
+            for (int q = tid; q < RB; q += kThreads) {
+                const int64_t gq = rb0 + q;
+                if (gq >= a.R) continue;
+                a.mhQ[gq * G + member] = mQ0[q];
+                if (member == 0) {
+                    a.mhE[gq * 2] = mEs[q];
+                    a.lam[gq] = mLam[q];
+                    a.mhc[gq * 2] = mAcc[q];
+                    a.mhc[gq * 2 + 1] = mDec[q];
+                }
+            }
         __syncthreads();
     }
 }
@@ -1488,6 +1811,15 @@ __global__ void __launch_bounds__(256) k_init_batch(const SweepArgs* table)
         if (i == 0) {
             a.bestE[r] = INT64_MAX;
             a.bestStep[r] = -1;
+            if (a.mh) {
+                a.mhE[r * 2] = INT64_MIN;
+                a.mhE[r * 2 + 1] = 0;
+                a.lam[r] = 1.0f;
+                a.mhc[r * 2] = 0;
+                a.mhc[r * 2 + 1] = 0;
+                const int G = a.G > 1 ? a.G : 1;
+                for (int g = 0; g < G; ++g) a.mhQ[r * G + g] = 0;
+            }
         }
     }
 }
@@ -1498,63 +1830,67 @@ hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st)
     return hipGetLastError();
 }
 
-size_t sweep_batch_lds_bytes(int path, int Np, int j_lds)
+size_t sweep_batch_lds_bytes(int path, int Np, int j_lds, int mh)
 {
-    return lds_plan(path, 1, Np, Np / 16, j_lds).total;
+    return lds_plan(path, 1, Np, Np / 16, j_lds, mh).total;
 }
 
-hipError_t prepare_sweep_batch(int path, int cbw, size_t lds)
+template <int PATH, int CBW>
+static const void* batch_kernel(bool mh)
 {
-    const void* f = nullptr;
-    if (path == kPathI8)
-        f = cbw == 2 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, 2, false, false, false, true>)
-                     : reinterpret_cast<const void*>(k_sweep_mfma<kPathI8, 1, 4, false, false, false, true>);
-    else
-        f = cbw == 2 ? reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, 2, false, false, false, true>)
-                     : reinterpret_cast<const void*>(k_sweep_mfma<kPathBf16, 1, 4, false, false, false, true>);
-    return hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+    return mh ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, false, false, false, true, true>)
+              : reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, false, false, false, true, false>);
 }
 
-// Items of one bucket: same path and column-block width; table entries
-// describe one 16-replica block each.
-hipError_t launch_sweep_batch(int path, int cbw, const SweepArgs* dtable, int nitems, size_t lds, hipStream_t st)
+static const void* batch_kernel(int path, int cbw, bool mh)
+{
+    if (path == kPathI8) return cbw == 2 ? batch_kernel<kPathI8, 2>(mh) : batch_kernel<kPathI8, 4>(mh);
+    return cbw == 2 ? batch_kernel<kPathBf16, 2>(mh) : batch_kernel<kPathBf16, 4>(mh);
+}
+
+hipError_t prepare_sweep_batch(int path, int cbw, int mh, size_t lds)
+{
+    return hipFuncSetAttribute(batch_kernel(path, cbw, mh != 0), hipFuncAttributeMaxDynamicSharedMemorySize,
+                               static_cast<int>(lds));
+}
+
+// Items of one bucket: same path, column-block width and accept/reject mode;
+// table entries describe one 16-replica block each.
+hipError_t launch_sweep_batch(int path, int cbw, int mh, const SweepArgs* dtable, int nitems, size_t lds,
+                              hipStream_t st)
 {
     SweepArgs a{};
     a.table = dtable;
-    const dim3 grid(static_cast<unsigned>(nitems)), block(kThreads);
-    if (path == kPathI8) {
-        if (cbw == 2) hipLaunchKernelGGL((k_sweep_mfma<kPathI8, 1, 2, false, false, false, true>), grid, block, lds, st, a);
-        else hipLaunchKernelGGL((k_sweep_mfma<kPathI8, 1, 4, false, false, false, true>), grid, block, lds, st, a);
-    } else {
-        if (cbw == 2)
-            hipLaunchKernelGGL((k_sweep_mfma<kPathBf16, 1, 2, false, false, false, true>), grid, block, lds, st, a);
-        else
-            hipLaunchKernelGGL((k_sweep_mfma<kPathBf16, 1, 4, false, false, false, true>), grid, block, lds, st, a);
-    }
-    return hipGetLastError();
+    void* args[] = {&a};
+    return hipLaunchKernel(batch_kernel(path, cbw, mh != 0), dim3(static_cast<unsigned>(nitems)), dim3(kThreads),
+                           args, lds, st);
 }
 
 template <int PATH, int MT, int CBW>
-static const void* group_table_kernel()
+static const void* group_table_kernel(bool mh)
 {
-    return reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, true>);
+    if constexpr (MT == 1 && CBW == 2)
+        if (mh) return reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, true, true>);
+    return mh ? nullptr : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, true>);
 }
 
-static const void* group_table_kernel(int path, int mt, int cbw)
+// Accept/reject runs: MT = 1, CBW = 2 only (null otherwise).
+static const void* group_table_kernel(int path, int mt, int cbw, bool mh)
 {
     if (path == kPathI8) {
-        if (mt == 1) return cbw == 1 ? group_table_kernel<kPathI8, 1, 1>() : group_table_kernel<kPathI8, 1, 2>();
-        return cbw == 1 ? group_table_kernel<kPathI8, 2, 1>() : group_table_kernel<kPathI8, 2, 2>();
+        if (mt == 1) return cbw == 1 ? group_table_kernel<kPathI8, 1, 1>(mh) : group_table_kernel<kPathI8, 1, 2>(mh);
+        return cbw == 1 ? group_table_kernel<kPathI8, 2, 1>(mh) : group_table_kernel<kPathI8, 2, 2>(mh);
     }
-    if (mt == 1) return cbw == 1 ? group_table_kernel<kPathBf16, 1, 1>() : group_table_kernel<kPathBf16, 1, 2>();
-    return cbw == 1 ? group_table_kernel<kPathBf16, 2, 1>() : group_table_kernel<kPathBf16, 2, 2>();
+    if (mt == 1) return cbw == 1 ? group_table_kernel<kPathBf16, 1, 1>(mh) : group_table_kernel<kPathBf16, 1, 2>(mh);
+    return cbw == 1 ? group_table_kernel<kPathBf16, 2, 1>(mh) : group_table_kernel<kPathBf16, 2, 2>(mh);
 }
 
-hipError_t launch_sweep_group_table(int path, int mt, int cbw, const SweepArgs* dtable, int nwg, size_t lds,
+hipError_t launch_sweep_group_table(int path, int mt, int cbw, int mh, const SweepArgs* dtable, int nwg, size_t lds,
                                     hipStream_t st)
 {
     if (mt < 1 || mt > 2 || cbw < 1 || cbw > 2 || nwg < 1) return hipErrorInvalidValue;
-    const void* kern = group_table_kernel(path, mt, cbw);
+    const void* kern = group_table_kernel(path, mt, cbw, mh != 0);
+    if (!kern) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
     SweepArgs a{};
@@ -1566,13 +1902,14 @@ hipError_t launch_sweep_group_table(int path, int mt, int cbw, const SweepArgs* 
     return hipGetLastError();
 }
 
-int max_coresident_group_table(int path, int mt, int cbw, size_t lds)
+int max_coresident_group_table(int path, int mt, int cbw, int mh, size_t lds)
 {
     int dev = 0, cus = 0, per = 0;
     if (mt < 1 || mt > 2 || cbw < 1 || cbw > 2) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* f = group_table_kernel(path, mt, cbw);
+    const void* f = group_table_kernel(path, mt, cbw, mh != 0);
+    if (!f) return 0;
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;
@@ -1582,14 +1919,14 @@ int max_coresident_group_table(int path, int mt, int cbw, size_t lds)
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)
 {
     const int cbs_max = (a.ncb + a.G - 1) / a.G;
-    return lds_plan(path, mt, a.Np, cbs_max, a.j_lds).total;
+    return lds_plan(path, mt, a.Np, cbs_max, a.j_lds, a.mh).total;
 }
 
-template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE>
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool MH>
 static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
 {
     const unsigned grid = static_cast<unsigned>(GROUP ? a.ngroups * a.G : a.nblocks);
-    auto kern = k_sweep_mfma<PATH, MT, CBW, GROUP, JLDS, TRACE>;
+    auto kern = k_sweep_mfma<PATH, MT, CBW, GROUP, JLDS, TRACE, false, MH>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -1605,11 +1942,21 @@ static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
     return hipGetLastError();
 }
 
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE>
+static hipError_t launch_mfma_m(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    // accept/reject variants exist for MT = 1, CBW = 2 only
+    if constexpr (MT == 1 && CBW == 2)
+        if (a.mh) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, true>(a, lds, st);
+    if (a.mh) return hipErrorInvalidValue;
+    return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, false>(a, lds, st);
+}
+
 template <int PATH, int MT, int CBW, bool GROUP, bool JLDS>
 static hipError_t launch_mfma_tr(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    return a.etrace ? launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, true>(a, lds, st)
-                    : launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, false>(a, lds, st);
+    return a.etrace ? launch_mfma_m<PATH, MT, CBW, GROUP, JLDS, true>(a, lds, st)
+                    : launch_mfma_m<PATH, MT, CBW, GROUP, JLDS, false>(a, lds, st);
 }
 
 template <int PATH, int MT, int CBW, bool GROUP>
@@ -1642,32 +1989,36 @@ hipError_t launch_sweep_mfma(int path, int mt, int cbw, const SweepArgs& a, size
     return hipErrorInvalidValue;
 }
 
-template <int PATH, int MT, int CBW>
+template <int PATH, int MT, int CBW, bool MH>
 static const void* group_kernel(int jlds, int trace)
 {
     if (jlds)
-        return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, true, true>)
-                     : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, true, false>);
-    return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, true>)
-                 : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false>);
+        return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, true, true, false, MH>)
+                     : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, true, false, false, MH>);
+    return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, true, false, MH>)
+                 : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, false, MH>);
 }
 
 template <int PATH>
-static const void* group_kernel_p(int mt, int cbw, int jlds, int trace)
+static const void* group_kernel_p(int mt, int cbw, int jlds, int trace, int mh)
 {
-    return mt == 1 ? (cbw == 1 ? group_kernel<PATH, 1, 1>(jlds, trace) : group_kernel<PATH, 1, 2>(jlds, trace))
-                   : (cbw == 1 ? group_kernel<PATH, 2, 1>(jlds, trace) : group_kernel<PATH, 2, 2>(jlds, trace));
+    if (mh) return (mt == 1 && cbw == 2) ? group_kernel<PATH, 1, 2, true>(jlds, trace) : nullptr;
+    return mt == 1 ? (cbw == 1 ? group_kernel<PATH, 1, 1, false>(jlds, trace)
+                               : group_kernel<PATH, 1, 2, false>(jlds, trace))
+                   : (cbw == 1 ? group_kernel<PATH, 2, 1, false>(jlds, trace)
+                               : group_kernel<PATH, 2, 2, false>(jlds, trace));
 }
 
-// Workgroups of the group sweep variant (mt, cbw, jlds, trace) that can be
-// resident on the device at once.
-int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, size_t lds)
+// Workgroups of the group sweep variant (mt, cbw, jlds, trace, mh) that can
+// be resident on the device at once (0 if the variant does not exist).
+int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, size_t lds)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* f = path == kPathI8 ? group_kernel_p<kPathI8>(mt, cbw, jlds, trace)
-                                    : group_kernel_p<kPathBf16>(mt, cbw, jlds, trace);
+    const void* f = path == kPathI8 ? group_kernel_p<kPathI8>(mt, cbw, jlds, trace, mh)
+                                    : group_kernel_p<kPathBf16>(mt, cbw, jlds, trace, mh);
+    if (!f) return 0;
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kThreads, lds) != hipSuccess) return 0;

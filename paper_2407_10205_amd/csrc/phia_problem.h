@@ -22,6 +22,7 @@ struct Geometry {
     int ngroups = 0;   // groups running concurrently
     int xcd_map = 0;   // group members share blockIdx % 8 (one XCD)
     size_t lds = 0;    // dynamic LDS bytes per workgroup
+    int mh = 0;        // LDS sized for the accept/reject step
 };
 
 phia_status fail(phia_status st, const char* fmt, ...);
@@ -39,6 +40,7 @@ void kick_factors(const ::phia_problem* p, int64_t steps, const phia_schedule* s
 phia_status setup_state(::phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s, uint64_t seed,
                         const std::vector<float>& ctab, bool& reuse, bool sync_first);
 void free_state(::phia_problem* p);
+phia_status setup_mh_geometry(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
 phia_status launch_batch_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
                                SweepArgs*& dtab, size_t& cap);
@@ -71,6 +73,17 @@ struct phia_problem {
     int64_t T = 0, k = 0, L = 1;
     float eps = 0.f, gamma = 0.f;
     int deriv = 0;  // phia_deriv of the current anneal
+    // accept/reject step of the current anneal
+    int mh = 0;
+    float mh_up = 1.f, mh_down = 1.f;
+    float* dbtab = nullptr;     // [T] beta_k
+    float* dx0 = nullptr;       // [R][Np] x at the trajectory start
+    int64_t* dmhE = nullptr;    // [R][2]
+    int64_t* dmhQ = nullptr;    // [R][max(1, G)]
+    size_t mhQ_cap = 0;         // entries of dmhQ
+    float* dlam = nullptr;      // [R]
+    int32_t* dmhc = nullptr;    // [R][2]
+    uint64_t* dmhbuf = nullptr; // group exchange of the decision's partial sums
     uint64_t seed = 0;
     float* dctab = nullptr;
     float* dx = nullptr;

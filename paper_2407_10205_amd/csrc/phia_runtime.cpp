@@ -250,6 +250,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
 {
     const int Np = p->Np, ncb = Np / 16;
     if (mt < 1 || mt > 2 || cbw < 1 || cbw > kCbwMax || G < 1 || G > ncb) return false;
+    if (p->mh && (mt != 1 || cbw != 2)) return false;  // accept/reject variants: one row tile, two column blocks
     const int cbs_max = (ncb + G - 1) / G;
     if (cbs_max > kWaves * cbw) return false;
     SweepArgs a{};
@@ -257,12 +258,13 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     a.ncb = ncb;
     a.G = G;
     a.j_lds = j_lds;
+    a.mh = p->mh;
     const size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
     if (lds > static_cast<size_t>(kLdsMax)) return false;
     const int rows = 16 * mt, nblocks = (R + rows - 1) / rows;
     int ngroups = nblocks;
     if (G > 1) {
-        const int maxwg = max_coresident_mfma(p->path, mt, cbw, j_lds, p->trace ? 1 : 0, lds);
+        const int maxwg = max_coresident_mfma(p->path, mt, cbw, j_lds, p->trace ? 1 : 0, p->mh, lds);
         if (maxwg < G) return false;
         ngroups = std::min(nblocks, maxwg / G);
         if (ngroups >= 8) ngroups -= ngroups % 8;
@@ -278,6 +280,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     g.ngroups = ngroups;
     g.xcd_map = (G > 1 && ngroups % 8 == 0) ? 1 : 0;
     g.lds = lds;
+    g.mh = p->mh;
     return true;
 }
 
@@ -288,7 +291,8 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
 static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g)
 {
     const int Np = p->Np, ncb = Np / 16;
-    if (p->path != PHIA_PATH_I8 || p->trace || p->one_block_kernel || G < 2 || G > ncb || ncb > kPpMaxNcb)
+    if (p->path != PHIA_PATH_I8 || p->trace || p->one_block_kernel || p->mh || G < 2 || G > ncb ||
+        ncb > kPpMaxNcb)
         return false;
     if (fp4 && !p->dJ4) return false;
     if (p->maxrow >= kPpMaxRowSum || 2 * p->maxrow * p->N >= (int64_t(1) << 31)) return false;
@@ -360,8 +364,17 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         }
     }
     if (p->tuned.ok && p->tuned_R == R) {
-        p->geo = p->tuned;
-        return;
+        if (p->tuned.mh == p->mh) {
+            p->geo = p->tuned;
+            return;
+        }
+        // tuned without (or with) the accept/reject step: same shape, LDS redone
+        Geometry g;
+        if (p->tuned.kind == 0 &&
+            make_geometry(p, R, p->tuned.mt, p->tuned.cbw, p->tuned.G, p->tuned.j_lds, g)) {
+            p->geo = g;
+            return;
+        }
     }
     if (lookup_tune_cache(p, R)) return;
     // Fewest passes over the replica blocks first; among those a geometry
@@ -398,6 +411,14 @@ void free_state(phia_problem* p)
     dfree(p->detrace);
     dfree(p->dxbits);
     dfree(p->dpbuf);
+    dfree(p->dbtab);
+    dfree(p->dx0);
+    dfree(p->dmhE);
+    dfree(p->dmhQ);
+    dfree(p->dlam);
+    dfree(p->dmhc);
+    dfree(p->dmhbuf);
+    p->mhQ_cap = 0;
     p->state_bytes = 0;
     p->R = 0;
     p->T = 0;
@@ -437,6 +458,17 @@ SweepArgs sweep_args(const phia_problem* p)
     a.pbuf = p->dpbuf;
     a.seq_base = p->seq;
     a.err = p->derr;
+    a.mh = p->mh;
+    a.mh_up = p->mh_up;
+    a.mh_down = p->mh_down;
+    a.sigma = std::ldexp(1.0f, -p->f);
+    a.btab = p->dbtab;
+    a.x0 = p->dx0;
+    a.mhE = p->dmhE;
+    a.mhQ = p->dmhQ;
+    a.lam = p->dlam;
+    a.mhc = p->dmhc;
+    a.mhbuf = p->dmhbuf;
     return a;
 }
 
@@ -613,30 +645,57 @@ phia_status check_schedule(int32_t replicas, int64_t steps, const phia_schedule*
     if (s->deriv_mode != PHIA_DERIV_TANH && s->deriv_mode != PHIA_DERIV_POLY2)
         return fail(PHIA_EINVAL, "deriv_mode = %d is neither TANH nor POLY2", s->deriv_mode);
     if (!std::isfinite(s->eps) || !std::isfinite(s->gamma)) return fail(PHIA_EINVAL, "eps and gamma must be finite");
+    if (s->metropolis != 0 && s->metropolis != 1) return fail(PHIA_EINVAL, "metropolis = %d is neither 0 nor 1", s->metropolis);
+    if (s->metropolis && !(std::isfinite(s->mh_up) && std::isfinite(s->mh_down) && s->mh_up > 0.0f && s->mh_down > 0.0f))
+        return fail(PHIA_EINVAL, "mh_up and mh_down must be positive and finite");
     return PHIA_OK;
 }
 
 // Kick factors c_k = (beta_k * gamma) * sigma of a schedule, with the linear
 // inverse-temperature table beta_k = float(b0 + ((b1 - b0) k) / (T - 1))
 // evaluated in double when no explicit table is given.
+static float beta_of(int64_t steps, const phia_schedule* s, int64_t k)
+{
+    if (s->betas) return s->betas[k];
+    double d = static_cast<double>(s->beta0);
+    if (steps > 1)
+        d = static_cast<double>(s->beta0) +
+            ((static_cast<double>(s->beta1) - static_cast<double>(s->beta0)) * static_cast<double>(k)) /
+                static_cast<double>(steps - 1);
+    return static_cast<float>(d);
+}
+
 void kick_factors(const phia_problem* p, int64_t steps, const phia_schedule* s, std::vector<float>& ctab)
 {
     ctab.resize(static_cast<size_t>(steps));
     const float sigma = std::ldexp(1.0f, -p->f);
-    for (int64_t k = 0; k < steps; ++k) {
-        float b;
-        if (s->betas) {
-            b = s->betas[k];
-        } else {
-            double d = static_cast<double>(s->beta0);
-            if (steps > 1)
-                d = static_cast<double>(s->beta0) +
-                    ((static_cast<double>(s->beta1) - static_cast<double>(s->beta0)) * static_cast<double>(k)) /
-                        static_cast<double>(steps - 1);
-            b = static_cast<float>(d);
-        }
-        ctab[static_cast<size_t>(k)] = (b * s->gamma) * sigma;
+    for (int64_t k = 0; k < steps; ++k) ctab[static_cast<size_t>(k)] = (beta_of(steps, s, k) * s->gamma) * sigma;
+}
+
+// Accept/reject buffers that depend on the launch geometry: kinetic units per
+// (replica, group member) and, for column-split groups, the exchange of the
+// decision's partial sums (tags start at 1, the buffer at zero).
+phia_status setup_mh_geometry(phia_problem* p)
+{
+    if (!p->mh) return PHIA_OK;
+    size_t* cnt = &p->state_bytes;
+    hipError_t e;
+    const size_t need = static_cast<size_t>(p->R) * static_cast<size_t>(std::max(1, p->geo.G));
+    if (need > p->mhQ_cap) {
+        dfree(p->dmhQ);
+        p->mhQ_cap = 0;
+        if ((e = dalloc(reinterpret_cast<void**>(&p->dmhQ), need * sizeof(int64_t), cnt)) != hipSuccess)
+            return fail(PHIA_ENOMEM, "accept/reject state allocation failed");
+        p->mhQ_cap = need;
     }
+    dfree(p->dmhbuf);
+    if (p->geo.kind == 0 && p->geo.G > 1) {
+        const size_t mb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * 4 * sizeof(uint64_t);
+        if ((e = dalloc(reinterpret_cast<void**>(&p->dmhbuf), mb, cnt)) != hipSuccess)
+            return fail(PHIA_ENOMEM, "accept/reject exchange allocation failed");
+        if ((e = hipMemsetAsync(p->dmhbuf, 0, mb, p->st)) != hipSuccess) return hip_fail(p, e, "exchange reset");
+    }
+    return PHIA_OK;
 }
 
 // Replica state and schedule of a new anneal (device buffers kept when the
@@ -651,7 +710,8 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
         e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
     }
-    reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr);
+    const int mh = s->metropolis ? 1 : 0;
+    reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr) && p->mh == mh;
     if (!reuse) free_state(p);
     p->R = replicas;
     p->T = steps;
@@ -660,6 +720,9 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
     p->gamma = s->gamma;
     p->L = s->refresh_L;
     p->deriv = s->deriv_mode;
+    p->mh = mh;
+    p->mh_up = mh ? s->mh_up : 1.0f;
+    p->mh_down = mh ? s->mh_down : 1.0f;
     p->seed = seed;
     p->has_run = false;
     p->started = false;
@@ -682,6 +745,25 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
         }
     }
     if (p->trace) (void)hipMemsetAsync(p->detrace, 0, sizeof(int64_t) * replicas * steps, p->st);
+    if (mh) {
+        if (!reuse && ((e = dalloc(reinterpret_cast<void**>(&p->dx0), RN * sizeof(float), cnt)) != hipSuccess ||
+                       (e = dalloc(reinterpret_cast<void**>(&p->dmhE), 2 * sizeof(int64_t) * replicas, cnt)) !=
+                           hipSuccess ||
+                       (e = dalloc(reinterpret_cast<void**>(&p->dlam), sizeof(float) * replicas, cnt)) != hipSuccess ||
+                       (e = dalloc(reinterpret_cast<void**>(&p->dmhc), 2 * sizeof(int32_t) * replicas, cnt)) !=
+                           hipSuccess ||
+                       (e = dalloc(reinterpret_cast<void**>(&p->dbtab), sizeof(float) * steps, cnt)) != hipSuccess)) {
+            free_state(p);
+            return fail(PHIA_ENOMEM, "accept/reject state allocation failed");
+        }
+        std::vector<float> btab(static_cast<size_t>(steps));
+        for (int64_t k = 0; k < steps; ++k) btab[static_cast<size_t>(k)] = beta_of(steps, s, k);
+        // pageable source: the copy completes before hipMemcpy returns
+        if ((e = hipMemcpy(p->dbtab, btab.data(), sizeof(float) * steps, hipMemcpyHostToDevice)) != hipSuccess) {
+            free_state(p);
+            return hip_fail(p, e, "upload of the inverse temperatures");
+        }
+    }
     if ((e = hipMemcpyAsync(p->dctab, ctab.data(), sizeof(float) * steps, hipMemcpyHostToDevice, p->st)) !=
         hipSuccess) {
         free_state(p);
@@ -710,6 +792,7 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     if (e != hipSuccess) return hip_fail(p, e, "schedule upload");
     size_t* cnt = &p->state_bytes;
     if (reuse) {
+        if ((st = setup_mh_geometry(p)) != PHIA_OK) return st;
         SweepArgs a = sweep_args(p);
         if ((e = launch_init(a, p->st)) != hipSuccess) return hip_fail(p, e, "init kernel launch");
         p->started = true;
@@ -742,6 +825,10 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
                 return hip_fail(p, e, "exchange buffer reset");
             p->seq = 0;
         }
+    }
+    if ((st = setup_mh_geometry(p)) != PHIA_OK) {
+        free_state(p);
+        return st;
     }
     SweepArgs a = sweep_args(p);
     if ((e = launch_init(a, p->st)) != hipSuccess) return hip_fail(p, e, "init kernel launch");
@@ -911,6 +998,27 @@ phia_status phia_replica_best(phia_problem* p, int64_t* E, int8_t* S, int64_t* s
     return PHIA_OK;
 }
 
+phia_status phia_replica_mh(phia_problem* p, int32_t* accepted, int32_t* decided, float* lam)
+{
+    clear_error();
+    phia_status st = need_results(p);
+    if (st != PHIA_OK) return st;
+    if (!p->mh) return fail(PHIA_ESTATE, "the current anneal has no accept/reject step");
+    hipError_t e;
+    if (accepted || decided) {
+        std::vector<int32_t> c(2 * static_cast<size_t>(p->R));
+        if ((e = hipMemcpy(c.data(), p->dmhc, sizeof(int32_t) * c.size(), hipMemcpyDeviceToHost)) != hipSuccess)
+            return hip_fail(p, e, "accept/reject readback");
+        for (int32_t r = 0; r < p->R; ++r) {
+            if (accepted) accepted[r] = c[2 * static_cast<size_t>(r)];
+            if (decided) decided[r] = c[2 * static_cast<size_t>(r) + 1];
+        }
+    }
+    if (lam && (e = hipMemcpy(lam, p->dlam, sizeof(float) * p->R, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(p, e, "accept/reject readback");
+    return PHIA_OK;
+}
+
 phia_status phia_get_trace(phia_problem* p, int64_t* E)
 {
     clear_error();
@@ -956,6 +1064,20 @@ phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int6
     if ((e = hipMemcpy2D(p->dx, pitch, x, w, w, static_cast<size_t>(p->R), hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy2D(p->dv, pitch, v, w, w, static_cast<size_t>(p->R), hipMemcpyHostToDevice)) != hipSuccess)
         return hip_fail(p, e, "state upload");
+    if (p->mh) {
+        // the accept/reject state restarts as after the initial draw
+        const size_t R = static_cast<size_t>(p->R);
+        std::vector<int64_t> mE(2 * R, 0);
+        for (size_t r = 0; r < R; ++r) mE[2 * r] = INT64_MIN;
+        const std::vector<float> lam(R, 1.0f);
+        const std::vector<int32_t> c(2 * R, 0);
+        const std::vector<int64_t> q(p->mhQ_cap, 0);
+        if ((e = hipMemcpy(p->dmhE, mE.data(), sizeof(int64_t) * mE.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->dlam, lam.data(), sizeof(float) * R, hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->dmhc, c.data(), sizeof(int32_t) * c.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+            (e = hipMemcpy(p->dmhQ, q.data(), sizeof(int64_t) * q.size(), hipMemcpyHostToDevice)) != hipSuccess)
+            return hip_fail(p, e, "accept/reject state reset");
+    }
     p->k = k;
     return PHIA_OK;
 }

@@ -88,11 +88,14 @@ struct phia_server {
 
 namespace {
 
-size_t footprint(const phia_problem* p, int32_t R, int64_t T)
+size_t footprint(const phia_problem* p, int32_t R, int64_t T, bool mh = false)
 {
     const size_t RN = static_cast<size_t>(R) * p->Np;
-    return p->base_bytes + RN * 9 + static_cast<size_t>(R) * 16 + static_cast<size_t>(T) * 4 +
-           2 * RN / 16 * 8 * 2 + 65536;
+    size_t b = p->base_bytes + RN * 9 + static_cast<size_t>(R) * 16 + static_cast<size_t>(T) * 4 +
+               2 * RN / 16 * 8 * 2 + 65536;
+    // accept/reject: x snapshot, per-replica state, beta table, kinetic units per member
+    if (mh) b += RN * 4 + static_cast<size_t>(R) * 32 + static_cast<size_t>(T) * 4 + RN / 16 * 8 * 2;
+    return b;
 }
 
 void finish(phia_server* s, Request* r, int32_t state)
@@ -310,7 +313,7 @@ phia_status phia_server_submit(phia_server* s, phia_problem* p, int32_t replicas
         r->sched.betas = r->betas.data();
     }
     r->seed = seed;
-    r->footprint = footprint(p, replicas, max_steps);
+    r->footprint = footprint(p, replicas, max_steps, sched->metropolis != 0);
     r->res.state = PHIA_REQ_QUEUED;
     r->res.energy_units = INT64_MAX;
     r->res.frac_bits = p->f;

@@ -26,7 +26,7 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
 
 # Every symbol declared in include/phia.h.
 EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
-           "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_get_state",
+           "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_replica_mh", "phia_get_state",
            "phia_set_state", "phia_get_info", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
            "phia_batch_run", "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
            "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
@@ -48,7 +48,8 @@ class Options(C.Structure):
 
 class Schedule(C.Structure):
     _fields_ = [("beta0", C.c_float), ("beta1", C.c_float), ("betas", C.c_void_p),
-                ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64), ("deriv_mode", C.c_int32)]
+                ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64), ("deriv_mode", C.c_int32),
+                ("metropolis", C.c_int32), ("mh_up", C.c_float), ("mh_down", C.c_float)]
 
 
 DERIV = {"tanh": 0, "poly2": 1}
@@ -83,6 +84,7 @@ def _declare(lib):
         "phia_best_exact": [P, P, P, P],
         "phia_best_f64": [P, P],
         "phia_replica_best": [P, P, P, P],
+        "phia_replica_mh": [P, P, P, P],
         "phia_get_state": [P, P, P, P],
         "phia_set_state": [P, P, P, I64],
         "phia_get_info": [P, P],
@@ -135,14 +137,18 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, deriv="tanh"):
+def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, deriv="tanh", mh=None):
     """Build a Schedule; keeps a reference to the betas array on the object.
-    deriv: "tanh" (Eq. 8) or "poly2" (the FPGA's quadratic)."""
+    deriv: "tanh" (Eq. 8) or "poly2" (the FPGA's quadratic).  mh: None, or
+    (up, down) to accept or reject every trajectory of refresh_L steps and
+    multiply beta by up / down after each outcome ((1, 1): fixed schedule)."""
     s = Schedule()
     s.eps = eps
     s.gamma = gamma
     s.refresh_L = int(refresh_L)
     s.deriv_mode = DERIV[deriv] if isinstance(deriv, str) else int(deriv)
+    s.metropolis = 0 if mh is None else 1
+    s.mh_up, s.mh_down = (1.0, 1.0) if mh is None else (float(mh[0]), float(mh[1]))
     if betas is not None:
         b = np.ascontiguousarray(betas, dtype=np.float32)
         if b.shape[0] < steps:
@@ -198,8 +204,8 @@ class Problem:
         _check(lib().phia_set_trace(self._p, 1 if enable else 0))
 
     def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
-              deriv="tanh"):
-        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv)
+              deriv="tanh", mh=None):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh)
         _check(lib().phia_anneal_start(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
 
@@ -210,8 +216,8 @@ class Problem:
         _check(lib().phia_sync(self._p))
 
     def anneal(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
-               deriv="tanh"):
-        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv)
+               deriv="tanh", mh=None):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh)
         _check(lib().phia_anneal(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
 
@@ -238,6 +244,14 @@ class Problem:
         K = np.zeros(self.R, np.int64)
         _check(lib().phia_replica_best(self._p, _ptr(E), _ptr(S), _ptr(K)))
         return E, S, K
+
+    def replica_mh(self):
+        """Per replica: trajectories accepted, trajectories decided, beta multiplier."""
+        acc = np.zeros(self.R, np.int32)
+        dec = np.zeros(self.R, np.int32)
+        lam = np.zeros(self.R, np.float32)
+        _check(lib().phia_replica_mh(self._p, _ptr(acc), _ptr(dec), _ptr(lam)))
+        return acc, dec, lam
 
     def trace(self, steps):
         E = np.zeros((self.R, steps), np.int64)
@@ -273,7 +287,8 @@ class Problem:
 def batch_run(problems, replicas, steps, schedules, seeds):
     """Anneal several problems in one graph launch (phia_batch_run).
 
-    schedules: list of dicts with eps, gamma, beta0, beta1 (or betas), refresh_L.
+    schedules: list of dicts with eps, gamma, beta0, beta1 (or betas), refresh_L,
+    optionally deriv and mh (see make_schedule).
     """
     n = len(problems)
     arr = (C.c_void_p * n)(*[p._p for p in problems])
@@ -284,7 +299,7 @@ def batch_run(problems, replicas, steps, schedules, seeds):
     keep = []
     for i, sc in enumerate(schedules):
         one = make_schedule(int(stp[i]), sc["eps"], sc["gamma"], sc.get("beta0"), sc.get("beta1"),
-                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"))
+                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"), sc.get("mh"))
         keep.append(one)
         C.memmove(C.byref(scheds, i * C.sizeof(Schedule)), C.byref(one), C.sizeof(Schedule))
     _check(lib().phia_batch_run(arr, n, _ptr(reps), _ptr(stp), C.cast(scheds, C.c_void_p), _ptr(sd)))
@@ -310,8 +325,8 @@ class Server:
         self._keep = {}
 
     def submit(self, problem, replicas, max_steps, target, eps, gamma, beta0=None, beta1=None, betas=None,
-               refresh_L=50, seed=0, deriv="tanh"):
-        sch = make_schedule(max_steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv)
+               refresh_L=50, seed=0, deriv="tanh", mh=None):
+        sch = make_schedule(max_steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh)
         t = C.c_uint64()
         _check(lib().phia_server_submit(self._s, problem._p, int(replicas), int(max_steps), int(target),
                                         C.byref(sch), int(seed), C.byref(t)))
