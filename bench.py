@@ -351,7 +351,7 @@ def run_tts_sweep(args, w):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(J, h, w, budget_s, deriv="tanh"):
+def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
     """Time the oracle on a bounded replica/step sample of the workload."""
     import numpy as np
     from oracle import oracle as O
@@ -366,12 +366,13 @@ def cpu_baseline(J, h, w, budget_s, deriv="tanh"):
     threads = max(1, min(16, os.cpu_count() or 1))
     # calibrate one replica on a few steps, then size the sample to the budget
     t = time.perf_counter()
-    O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1, deriv=deriv)
+    O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1, deriv=deriv, mh=mh)
     per_step = (time.perf_counter() - t) / 20
     R = threads
     steps = int(max(20, min(T, budget_s / max(per_step, 1e-9))))
     t = time.perf_counter()
-    O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads, deriv=deriv)
+    O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads, deriv=deriv,
+             mh=mh)
     dt = time.perf_counter() - t
     return {"value": R * N * steps / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"replicas 0..{R - 1}, steps 0..{steps - 1} of the same schedule, "
@@ -396,6 +397,9 @@ def main():
     ap.add_argument("--geometry-out", metavar="FILE", help="write the launch geometry used to FILE")
     ap.add_argument("--deriv", default="tanh", choices=["tanh", "poly2"],
                     help="derivative factor of the kick: sech^2 (Eq. 8) or the FPGA's quadratic (POLY2 mode)")
+    ap.add_argument("--mh", metavar="UP,DOWN", default=None,
+                    help="accept or reject every trajectory of refresh_L steps (App. A, Table 3 state 4) and "
+                         "multiply beta by UP after an acceptance, DOWN after a rejection (1,1: fixed schedule)")
     ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
     ap.add_argument("--chunk", type=int, default=500, help="serving workload: steps per scheduling round")
@@ -418,6 +422,9 @@ def main():
     import torch
     from paper_2407_10205_amd import phia
 
+    mh = None if args.mh is None else tuple(float(t) for t in args.mh.split(","))
+    if mh is not None and len(mh) != 2:
+        ap.error("--mh takes UP,DOWN")
     w = WORKLOADS[args.workload]
     if w["gen"] == "batch":
         run_batch_bench(args, w)
@@ -437,7 +444,7 @@ def main():
 
     def one(seed, events=None):
         prob.start(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"], refresh_L=s["refresh_L"],
-                   seed=seed, deriv=args.deriv)
+                   seed=seed, deriv=args.deriv, mh=mh)
         if events is not None:
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(stream)
@@ -460,6 +467,11 @@ def main():
     info = prob.info()  # geometry of the timed runs
     # per-replica records of the last timed run, for the success estimate
     E_last, _, _ = prob.replica_best()
+    mh_stats = None
+    if mh is not None:
+        acc, dec, lam = prob.replica_mh()
+        mh_stats = {"accept_rate": float(acc.sum()) / max(1, int(dec.sum())), "decided_per_replica": int(dec[0]),
+                    "beta_multiplier_median": float(np.median(lam))}
     wall = t1 - t0
     ms_step = 1000 * wall / args.steps
     su = float(R) * N * T * args.steps
@@ -497,7 +509,7 @@ def main():
         if not args.no_tune:
             ref.autotune(R, 100)
         ref.anneal(R, 10 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
-                   refresh_L=s["refresh_L"], seed=4242, deriv=args.deriv)
+                   refresh_L=s["refresh_L"], seed=4242, deriv=args.deriv, mh=mh)
         target = ref.best_exact()[0]
         ref.close()
         p_hat = float(np.mean(E_last <= target))
@@ -515,7 +527,7 @@ def main():
         calibrate_copy()
     cpu = None
     if not args.no_cpu:
-        cpu = cpu_baseline(J, h, w, args.cpu_seconds, args.deriv)
+        cpu = cpu_baseline(J, h, w, args.cpu_seconds, args.deriv, mh)
     out = {
         "metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
@@ -523,10 +535,13 @@ def main():
         "dtype": "fp4" if info["sweep_kernel"] == 2 else info["path_name"],
         "data": "synthetic",
         "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
-                   "schedule": dict(s, deriv=args.deriv), "group": info["group"], "rows_per_block": info["rows_per_block"],
+                   "schedule": dict(s, deriv=args.deriv, **({} if mh is None else {"mh_up": mh[0], "mh_down": mh[1]})),
+                   "group": info["group"], "rows_per_block": info["rows_per_block"],
                    "j_in_lds": info["j_in_lds"], "sweep_kernel": kernel, "autotune_us_per_step": tuned_us},
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }
+    if mh_stats is not None:
+        out["metropolis"] = mh_stats
     print(json.dumps(out), flush=True)
 
 
