@@ -259,6 +259,8 @@ def run_batch_bench(args, w):
     wall = time.perf_counter() - t0
     value = su * args.steps / wall
     best = [p.best_exact()[0] for p in probs[:4]]
+    if args.calibrate_copy:
+        calibrate_copy()
     out = {"metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1000 * wall / args.steps, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
@@ -489,6 +491,8 @@ def main():
     mfma_peak = (FP4_MFMA_PEAK if fp4_ops else INT8_MFMA_PEAK if info["path_name"] == "i8"
                  else BF16_MFMA_PEAK * 0.5)
     geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel")}
+    # counter summaries are kept per kernel and per workload variant
+    profile_key = args.workload + ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "")
     kernel = ("k_sweep_fp32" if info["path_name"] == "fp32" else
               "k_sweep_pp" if info["sweep_kernel"] >= 1 else "k_sweep_mfma")
     if args.geometry_out:
@@ -496,7 +500,7 @@ def main():
             json.dump(geometry, f)
     roofline = {"bound": "alu", "achieved": achieved, "peak": VALU_OPS_PEAK, "unit": "ops/s",
                 "frac": achieved / VALU_OPS_PEAK,
-                "traffic": recorded_traffic(kernel, args.workload, w["desc"], geometry),
+                "traffic": recorded_traffic(kernel, profile_key, w["desc"], geometry),
                 "kernel": kernel,
                 "kernel_ms": kern_ms, "ops_per_spin_update": ops_su,
                 "mfma_executed_ops_per_s": mfma_ops / (kern_ms / 1000),
