@@ -1273,22 +1273,19 @@ __device__ __forceinline__ int row_sum16_dpp(int v)
     v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
     v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
     v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
-    v += __builtin_amdgcn_update_dpp(0, v, 0x140, 0xf, 0xf, false);  // row_mirror
+    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true);          // row_mirror (every lane has a source)
     return v;
 }
 
 // Gather mapping: thread t reads the words of replica row t / 32, column
 // blocks t % 32 + 32 u, u < NU; a column block past the end reads the last
 // one instead (a valid word, ignored afterwards), so every load is issued
-// unconditionally.
+// unconditionally.  off[u] is the word's index in the sub-block's array.
 template <int NU>
-__device__ __forceinline__ void pp_issue(const uint64_t* Xs, int ncb, int row, int c0, uint64_t (&w)[NU])
+__device__ __forceinline__ void pp_issue(const uint64_t* Xs, const int (&off)[NU], uint64_t (&w)[NU])
 {
 #pragma unroll
-    for (int u = 0; u < NU; ++u) {
-        const int c = min(c0 + 32 * u, ncb - 1);
-        w[u] = __hip_atomic_load(Xs + row * ncb + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    for (int u = 0; u < NU; ++u) w[u] = __hip_atomic_load(Xs + off[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int NU>
@@ -1306,8 +1303,8 @@ __device__ __forceinline__ uint32_t pp_stale(uint32_t tag, const uint64_t (&w)[N
 // or once another workgroup has raised the device error word (then this
 // one raises it too).
 template <int NU>
-__device__ __forceinline__ bool pp_complete(const uint64_t* Xs, int ncb, int row, int c0, uint32_t tag,
-                                            uint64_t (&w)[NU], int32_t* err)
+__device__ __forceinline__ bool pp_complete(const uint64_t* Xs, const int (&off)[NU], uint32_t tag, uint64_t (&w)[NU],
+                                            int32_t* err)
 {
     uint32_t stale = pp_stale<NU>(tag, w);
     uint32_t polls = 0;
@@ -1320,22 +1317,19 @@ __device__ __forceinline__ bool pp_complete(const uint64_t* Xs, int ncb, int row
         }
         __builtin_amdgcn_s_sleep(1);
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int c = min(c0 + 32 * u, ncb - 1);
-            if ((stale >> u) & 1u)
-                w[u] = __hip_atomic_load(Xs + row * ncb + c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+        for (int u = 0; u < NU; ++u)
+            if ((stale >> u) & 1u) w[u] = __hip_atomic_load(Xs + off[u], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         stale = pp_stale<NU>(tag, w);
     }
     return true;
 }
 
 // A wave that owns a column block stores the words of its 16 replica rows:
-// lane (lr, lg) with lr < 4 stores row 4 lg + lr, taking the spins from
-// ballot lr and the row's partial energy p_lr (each p_j is present in every
-// lane of its DPP row).
-__device__ __forceinline__ void pp_publish(uint64_t* Xs, int ncb, int cblk, int lr, int lg, const float (&x)[4],
-                                           int p0, int p1, int p2, int p3, uint32_t tag)
+// lane (lr, lg) with lr < 4 stores row 4 lg + lr (at dst), taking the spins
+// from ballot lr and the row's partial energy p_lr (each p_j is present in
+// every lane of its DPP row).
+__device__ __forceinline__ void pp_publish(uint64_t* dst, int lr, int lg, const float (&x)[4], int p0, int p1, int p2,
+                                           int p3, uint32_t tag)
 {
     const uint64_t b0 = __ballot(x[0] >= 0.0f), b1 = __ballot(x[1] >= 0.0f);
     const uint64_t b2 = __ballot(x[2] >= 0.0f), b3 = __ballot(x[3] >= 0.0f);
@@ -1345,8 +1339,7 @@ __device__ __forceinline__ void pp_publish(uint64_t* Xs, int ncb, int cblk, int 
     const uint64_t word = (static_cast<uint64_t>(tag) << 40) |
                           (static_cast<uint64_t>(static_cast<uint32_t>(pe) & 0xffffffu) << 16) |
                           ((b >> (16 * lg)) & 0xffffu);
-    if (lr < 4)
-        __hip_atomic_store(Xs + (4 * lg + lr) * ncb + cblk, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lr < 4) __hip_atomic_store(dst, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // I = S . J^T + h for one 16x16 tile, J fragments in VGPRs.  The S
@@ -1377,17 +1370,16 @@ __device__ __forceinline__ void quasi_gradient_regj(const unsigned char* S, uint
 // Expand one 16-bit sign word into 16 FP4 (E2M1) spins, +1.0 = 0x2 and
 // -1.0 = 0xA, 8 bytes: within each byte of spin bits the nibbles hold spins
 // 0 4 1 5 2 6 3 7 (the packed J uses the same order along k).
+__device__ __forceinline__ uint32_t fp4_byte(uint32_t b)
+{
+    const uint32_t lo = ((b & 0xfu) * 0x00204081u) & 0x01010101u;  // bit i -> bit 8 i
+    const uint32_t hi = ((b >> 4) * 0x00204081u) & 0x01010101u;
+    return 0xaaaaaaaau - 8u * (lo | (hi << 4));
+}
+
 __device__ __forceinline__ void unpack_signs_fp4(uint32_t w, unsigned char* dst)
 {
-    uint32_t d[2];
-#pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const uint32_t b = (w >> (8 * t)) & 0xffu;
-        const uint32_t lo = ((b & 0xfu) * 0x00204081u) & 0x01010101u;  // bit i -> bit 8 i
-        const uint32_t hi = ((b >> 4) * 0x00204081u) & 0x01010101u;
-        d[t] = 0xaaaaaaaau - 8u * (lo | (hi << 4));
-    }
-    *reinterpret_cast<uint2*>(dst) = uint2{d[0], d[1]};
+    *reinterpret_cast<uint2*>(dst) = uint2{fp4_byte(w & 0xffu), fp4_byte((w >> 8) & 0xffu)};
 }
 
 typedef int v8i __attribute__((ext_vector_type(8)));
@@ -1459,9 +1451,11 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     const uint32_t cbb = FP4 ? static_cast<uint32_t>(nkb) * 1024u : cb_bytes(kPathI8, Np);
     unsigned char* sJ = lds + P.j_off;
     unsigned char* S = lds + P.s_off + team * P.s_bytes;
-    int64_t* sEt = reinterpret_cast<int64_t*>(lds + P.e_off) + team * 16;
-    int64_t* sBall = reinterpret_cast<int64_t*>(lds + P.b_off);
-    int64_t* sB = sBall + team * 32;  // [parity][16]
+    // Energies in int32: the host admits this kernel only when
+    // 2 N max_i(sum_j |J_ij| + |h_i|) < 2^31, which bounds every row sum.
+    int32_t* sEt = reinterpret_cast<int32_t*>(lds + P.e_off) + team * 16;
+    int32_t* sBall = reinterpret_cast<int32_t*>(lds + P.b_off);
+    int32_t* sB = sBall + team * 32;  // [parity][16]
     int64_t* sKall = reinterpret_cast<int64_t*>(lds + P.k_off);
     int64_t* sK = sKall + team * 16;
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
@@ -1504,6 +1498,10 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     const uint32_t seq_stride = static_cast<uint32_t>(nsteps + 1);
     const int64_t ref0 = a.k0 + (a.L - a.k0 % a.L) % a.L;
     const size_t plane = static_cast<size_t>(16) * ncb;
+    int goff[NU];  // gather: word indices of this thread
+#pragma unroll
+    for (int u = 0; u < NU; ++u) goff[u] = grow * ncb + min(gc0 + 32 * u, ncb - 1);
+    const int poff = (4 * lg + (lr & 3)) * ncb + cblk;  // publication: word of row 4 lg + lr (lanes lr < 4)
     int iter = 0;
 
     for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
@@ -1517,8 +1515,9 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             const int sb = q >> 4, r = q & 15;
             const bool ok = rb0 + q < a.R;
             const int64_t b = ok ? a.bestE[rb0 + q] : INT64_MAX;
-            sBall[(sb * 2 + 0) * 16 + r] = b;
-            sBall[(sb * 2 + 1) * 16 + r] = b;
+            const int32_t b32 = b > INT32_MAX ? INT32_MAX : static_cast<int32_t>(b);  // INT32_MAX: no record yet
+            sBall[(sb * 2 + 0) * 16 + r] = b32;
+            sBall[(sb * 2 + 1) * 16 + r] = b32;
             sKall[q] = ok ? a.bestStep[rb0 + q] : -1;
         }
         float x[4], v[4];
@@ -1564,8 +1563,9 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         auto gather = [&](int q) {
             const uint32_t seq = seq0 + static_cast<uint32_t>(q);
             if (q < nsteps) ck_next = a.ctab[a.k0 + q];
-            pp_issue<NU>(xs(seq), ncb, grow, gc0, w);
-            const bool ok = pp_complete<NU>(xs(seq), ncb, grow, gc0, seq & 0xffffffu, w, a.err);
+            const uint64_t* X = xs(seq);
+            pp_issue<NU>(X, goff, w);
+            const bool ok = pp_complete<NU>(X, goff, seq & 0xffffffu, w, a.err);
             int psum = 0;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {
@@ -1573,7 +1573,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                 if (c < ncb) {
                     if (q < nsteps) {
                         if (FP4)
-                            unpack_signs_fp4(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 8);
+                            unpack_signs_fp4(static_cast<uint32_t>(w[u]), S + grow * srow + c * 8);
                         else
                             unpack_signs<1>(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 16);
                     }
@@ -1609,12 +1609,12 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             }
             if (s > 0) {  // App. B, Table 3, state 5
                 const int par = static_cast<int>(k & 1);
-                const int64_t* prev = sB + (par ^ 1) * 16;
-                int64_t* next = sB + par * 16;
-                int64_t Ev[4], Bv[4];
+                const int32_t* prev = sB + (par ^ 1) * 16;
+                int32_t* next = sB + par * 16;
+                int32_t Ev[4], Bv[4];
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {  // all reads before any write
-                    Ev[j] = -(sEt[4 * lg + j] / 2);
+                    Ev[j] = -(sEt[4 * lg + j] >> 1);  // the sum is even (J symmetric, h counted twice)
                     Bv[j] = prev[4 * lg + j];
                 }
                 uint32_t impm = 0;
@@ -1635,8 +1635,9 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             int part[4];
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int sg = (x[j] >= 0.0f) ? 1 : -1;
-                part[j] = creal ? sg * (I[0][0][j] + hreg1[0]) : 0;
+                // padded columns (col >= N) have zero couplings and field: I + h = 0
+                const int ih = I[0][0][j] + hreg1[0];
+                part[j] = (x[j] >= 0.0f) ? ih : -ih;
             }
             if (a.deriv) {
 #pragma unroll
@@ -1654,7 +1655,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                 for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(eps, v[j], x[j]);
             }
             const uint32_t seq = seq0 + static_cast<uint32_t>(s) + 1u;
-            pp_publish(xs(seq), ncb, cblk, lr, lg, x, p0, p1, p2, p3, seq & 0xffffffu);
+            pp_publish(xs(seq) + poff, lr, lg, x, p0, p1, p2, p3, seq & 0xffffffu);
         };
 
         // Publication 0: the drift of step k0.
@@ -1667,7 +1668,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(eps, v[j], x[j]);
-            if (cval) pp_publish(xs(seq0), ncb, cblk, lr, lg, x, 0, 0, 0, 0, seq0 & 0xffffffu);
+            if (cval) pp_publish(xs(seq0) + poff, lr, lg, x, 0, 0, 0, 0, seq0 & 0xffffffu);
         }
         __syncthreads();  // records initialised
         if (team == 0 && !gather(0)) *sAbort = 1;
@@ -1712,7 +1713,8 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             for (int q = tid; q < 32; q += kPpThreads)
                 if (rb0 + q < a.R) {
                     const int sb = q >> 4, r = q & 15;
-                    a.bestE[rb0 + q] = sBall[(sb * 2 + fin) * 16 + r];
+                    const int32_t e = sBall[(sb * 2 + fin) * 16 + r];
+                    a.bestE[rb0 + q] = e == INT32_MAX ? INT64_MAX : e;
                     a.bestStep[rb0 + q] = sKall[q];
                 }
         }
