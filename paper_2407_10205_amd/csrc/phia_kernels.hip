@@ -1384,13 +1384,15 @@ __device__ __forceinline__ void unpack_signs_fp4(uint32_t w, unsigned char* dst)
 
 typedef int v8i __attribute__((ext_vector_type(8)));
 
-// I = S . J^T + h for one 16x16 tile with FP4 operands and FP32
-// accumulation (v_mfma_scale_f32_16x16x128_f8f6f4, scales 1.0): every
-// product and partial sum is an integer below 2^24, so the result is exact.
+// S . J^T for one 16x16 tile with FP4 operands and FP32 accumulation
+// (v_mfma_scale_f32_16x16x128_f8f6f4, scales 1.0): every product and partial
+// sum is an integer below 2^24, so the result is exact.  Even and odd k
+// blocks go to two accumulators (two independent MFMA chains); the caller
+// converts the sum after other work, while the products run.
 // Jw: the wave's column block of the LDS J slice, NKB blocks of 1 KiB.
 template <int NKB>
-__device__ __forceinline__ void quasi_gradient_fp4(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
-                                                   int lane, int lr, int lg, int h, int (&I)[4])
+__device__ __forceinline__ v4f quasi_gradient_fp4(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
+                                                  int lane, int lr, int lg)
 {
     const unsigned char* row = S + lr * srow + 16 * lg;
     const unsigned char* jl = Jw + lane * 16;
@@ -1400,7 +1402,7 @@ __device__ __forceinline__ void quasi_gradient_fp4(const unsigned char* S, uint3
         A[d] = *reinterpret_cast<const v4i*>(row + d * 64);
         B[d] = *reinterpret_cast<const v4i*>(jl + d * 1024);
     }
-    v4f acc = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+    v4f acc0 = v4f{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
         const v4i ca = A[kb % kPpDepth], cb = B[kb % kPpDepth];
@@ -1410,10 +1412,12 @@ __device__ __forceinline__ void quasi_gradient_fp4(const unsigned char* S, uint3
         }
         const v8i a8 = v8i{ca[0], ca[1], ca[2], ca[3], 0, 0, 0, 0};
         const v8i b8 = v8i{cb[0], cb[1], cb[2], cb[3], 0, 0, 0, 0};
-        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc, 4, 4, 0, 127, 0, 127);
+        if (kb & 1)
+            acc1 = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc1, 4, 4, 0, 127, 0, 127);
+        else
+            acc0 = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a8, b8, acc0, 4, 4, 0, 127, 0, 127);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) I[j] = static_cast<int>(acc[j]) + h;
+    return acc0 + acc1;
 }
 
 // Sixteen waves: team 0 (waves 0-7) owns sub-block 0, team 1 (waves 8-15)
@@ -1597,10 +1601,11 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             const bool closing = (s == nsteps);
             const float ck = ck_next;
             int I[1][1][4] = {};
+            v4f facc = v4f{0.0f, 0.0f, 0.0f, 0.0f};
             if (!closing && cval) {
                 if (FP4)
-                    quasi_gradient_fp4<(NKB > 0 ? NKB : 1)>(S, srow, sJ + static_cast<size_t>(tw) * NKB * 1024u,
-                                                            lane, lr, lg, hreg1[0], I[0][0]);
+                    facc = quasi_gradient_fp4<(NKB > 0 ? NKB : 1)>(S, srow, sJ + static_cast<size_t>(tw) * NKB * 1024u,
+                                                                 lane, lr, lg);
                 else if (JREG)
                     quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, nkb, lr, lg, hreg1[0], I[0][0]);
                 else
@@ -1630,6 +1635,10 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                         if (imp) sK[4 * lg + j] = k - 1;
                     }
                 }
+            }
+            if (FP4 && !closing && cval) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) I[0][0][j] = static_cast<int>(facc[j]) + hreg1[0];
             }
             if (closing || !cval) return;
             int part[4];
