@@ -122,8 +122,11 @@ typedef struct {
 /* Create a problem from real couplings.  J: host, N*N doubles, row-major,
  * symmetric with a zero diagonal (the i<j sum of Eq. 2 read as a full
  * symmetric matrix).  h: host, N doubles, or NULL for h = 0.  N in
- * [1, 16384].  opt may be NULL (frac_bits = -1, quantize = 0, AUTO, device 0,
- * null stream).  On success *out owns device copies of J and h. */
+ * [1, 16384] (else PHIA_EINVAL), and within what the resolved path's sweep
+ * holds (else PHIA_ERANGE): N <= 5056 on I8 (4992 for metropolis
+ * schedules, which then fail at phia_anneal_start), N <= 2496 on BF16HILO,
+ * N <= 4096 on FP32.  opt may be NULL (frac_bits = -1, quantize = 0, AUTO,
+ * device 0, null stream).  On success *out owns device copies of J and h. */
 phia_status phia_create(const double* J, const double* h, int32_t N,
                         const phia_options* opt, phia_problem** out);
 

@@ -526,6 +526,27 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     if (path == PHIA_PATH_I8 && !i8_ok) return fail(PHIA_ERANGE, "couplings outside int8 for the I8 path");
     if (path == PHIA_PATH_BF16HILO && !bf_ok) return fail(PHIA_ERANGE, "couplings outside 16 bits for BF16HILO");
     if (path == PHIA_PATH_FP32 && !f32_ok) return fail(PHIA_ERANGE, "row sums exceed 2^24 for the FP32 path");
+    {
+        // Largest instance each sweep holds: the FP32 sweep keeps up to 16
+        // columns per thread (Np <= 4096); the matrix-core sweeps stage two
+        // spin rows of every replica in LDS, so even the thinnest column
+        // slice needs 32 Np bytes per operand byte there.
+        const int Np = (N + 63) / 64 * 64;
+        bool fits;
+        if (path == PHIA_PATH_FP32) {
+            fits = Np <= 4096;
+        } else {
+            SweepArgs a{};
+            a.Np = Np;
+            a.ncb = Np / 16;
+            a.G = a.ncb;
+            a.j_lds = 0;
+            fits = sweep_mfma_lds_bytes(path, 1, a) <= static_cast<size_t>(kLdsMax);
+        }
+        if (!fits)
+            return fail(PHIA_ERANGE, "N = %d is beyond the %s sweep (N <= 5056 int8, 2496 BF16 hi/lo, 4096 FP32)", N,
+                        path == PHIA_PATH_FP32 ? "FP32" : path == PHIA_PATH_I8 ? "int8" : "BF16 hi/lo");
+    }
 
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(PHIA_EDEVICE, "no HIP device");

@@ -76,3 +76,15 @@ def test_null_and_size_arguments(phia):
     assert L.phia_create(J.ctypes.data_as(C.c_void_p), None, 2, None, None) == -1
     assert L.phia_sync(None) == -1
     L.phia_destroy(None)
+
+
+@pytest.mark.parametrize("path,N", [("i8", 5056), ("bf16hilo", 2496), ("fp32", 4096)])
+def test_size_limits_per_path(phia, path, N):
+    """Each path's largest instance passes the size check (on a machine
+    without a GPU it then fails for want of a device); one spin more is
+    PHIA_ERANGE before any device call."""
+    J = np.zeros((N + 1, N + 1))
+    J[0, 1] = J[1, 0] = 1.0
+    assert _code(phia, J, path=path) == -4
+    code = _code(phia, J[:N, :N].copy(), path=path)
+    assert code != -4

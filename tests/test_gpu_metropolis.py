@@ -230,3 +230,15 @@ def test_mh_server_same_alone_and_in_mix(P, O):
         assert np.array_equal(alone[i][1][0], mix_spins[i])
         J, h = specs[i][0], specs[i][1]
         assert O.energy(J.astype(np.int32), h.astype(np.int32), mix_spins[i]) == r2["energy_units"]
+
+
+def test_mh_largest_int8_instance(P, O):
+    """The accept/reject variant at its largest int8 instance (N = 4992),
+    column-split, every replica against the oracle."""
+    J, h = inst.sk_pm1(4992, 5)
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.5, beta1=2.0, refresh_L=3)
+    say("mh largest N=4992")
+    dev = device_run(P, J, h, 0, "i8", 16, 8, sched, 23, (1.1, 0.9), trace=False)
+    say("geometry", dev["info"])
+    runs = oracle_rows(O, J, h, 0, 8, sched, 23, (1.1, 0.9), range(16), trace=False)
+    assert_parity(dev, runs)

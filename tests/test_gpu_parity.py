@@ -570,3 +570,30 @@ def test_server_budget_forces_queueing_and_cancel(P, O):
     assert ref["energy_units"] == r_short["energy_units"] and ref["steps_used"] == r_short["steps_used"]
     for p in probs:
         p.close()
+
+
+# ------------------------------------------------------ maximum sizes ----
+@pytest.mark.parametrize("path,N,R,T", [("i8", 5056, 17, 6), ("bf16hilo", 2496, 16, 6), ("fp32", 4096, 5, 4)])
+def test_largest_instance_per_path(P, O, path, N, R, T):
+    """The largest N each path holds (int8 5056, BF16 hi/lo 2496, FP32
+    4096), ragged replica count: every replica bit-identical to the oracle."""
+    if path == "bf16hilo":
+        J, h = inst.sk_gauss_fixed(N, 3, frac_bits=12, bits=16)
+        f = 12
+    else:
+        J, h = inst.sk_pm1(N, 3)
+        f = 0
+    say(f"largest {path} N={N}")
+    prob = P.Problem(J, h, frac_bits=f, path=path)
+    prob.anneal(R, T, 0.2, 1.0, beta0=0.5, beta1=2.0, refresh_L=3, seed=21)
+    E, S, K = prob.replica_best()
+    x, v, _ = prob.get_state()
+    info = prob.info()
+    prob.close()
+    say("geometry", info)
+    Ji, hi = int_units(J, h, f)
+    betas = O.beta_linear(0.5, 2.0, T)
+    o = O.anneal(Ji, hi, f, R, betas, 0.2, 1.0, 3, 21, threads=8)
+    assert np.array_equal(x.view(np.uint32), o.x.view(np.uint32))
+    assert np.array_equal(v.view(np.uint32), o.v.view(np.uint32))
+    assert np.array_equal(E, o.bestE) and np.array_equal(K, o.bestStep) and np.array_equal(S, o.bestS)
