@@ -597,3 +597,109 @@ def test_largest_instance_per_path(P, O, path, N, R, T):
     assert np.array_equal(x.view(np.uint32), o.x.view(np.uint32))
     assert np.array_equal(v.view(np.uint32), o.v.view(np.uint32))
     assert np.array_equal(E, o.bestE) and np.array_equal(K, o.bestStep) and np.array_equal(S, o.bestS)
+
+
+# -------------------------------------- the other workloads at full size ----
+@pytest.mark.parametrize("path,geometry", [("i8", None), ("i8", "1,8,0,2"), ("bf16hilo", None)])
+def test_sk2000_full_shape_sampled(P, O, path, geometry):
+    """Dense SK N = 2000 on the 2^-5 grid (8-bit couplings), 512 replicas:
+    the full instance and replica count (short run), in the default launch
+    geometry and in the one the profile measured; sampled replicas against
+    the oracle."""
+    import os
+    J, h = inst.sk_gauss_fixed(2000, 0, frac_bits=5, bits=8)
+    R, T = 512, 120
+    say(f"sk2000 path={path} geometry={geometry}")
+    if geometry:
+        os.environ["PHIA_GEOMETRY"] = geometry
+    try:
+        p = P.Problem(J, h, path=path)
+        p.anneal(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=25, seed=77)
+    finally:
+        os.environ.pop("PHIA_GEOMETRY", None)
+    E, S, K = p.replica_best()
+    x, v, _ = p.get_state()
+    say("geometry", p.info())
+    p.close()
+    Ji, hi = int_units(J, h, 5)
+    betas = O.beta_linear(0.1, 3.0, T)
+    for r in (0, 255, 511):
+        o = O.anneal(Ji, hi, 5, 1, betas, 0.2, 1.0, 25, 77, r0=r)
+        assert np.array_equal(x[r].view(np.uint32), o.x[0].view(np.uint32)), r
+        assert E[r] == o.bestE[0] and K[r] == o.bestStep[0] and np.array_equal(S[r], o.bestS[0]), r
+
+
+def _batch4096():
+    """The 4096-instance batch workload: N uniform in [32, 512], even ids SK
+    +-1, odd ids 3-regular +-1 with h in {-1, 0, 1}."""
+    g = inst.rng(0)
+    sizes = g.integers(32, 513, size=4096)
+    out = []
+    for i, n in enumerate(sizes):
+        n = int(n)
+        out.append(inst.sk_pm1(n, 10_000 + i) if i % 2 == 0 else inst.regular3_pm1(n + (n % 2), 10_000 + i))
+    return out
+
+
+def test_batch_full_size_sampled(P, O):
+    """All 4096 instances in one graph (32 replicas each, short run); sampled
+    instances and replicas against the oracle, and every instance's best
+    state has the energy it reports."""
+    insts = _batch4096()
+    T = 40
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    probs = [P.Problem(J, h, path="i8") for J, h in insts]
+    say("batch of", len(probs))
+    P.batch_run(probs, [32] * len(probs), [T] * len(probs), [sched] * len(probs), list(range(5000, 5000 + len(probs))))
+    betas = O.beta_linear(0.1, 3.0, T)
+    for i in (0, 1, 777, 2048, 4094, 4095):
+        J, h = insts[i]
+        Ji, hi = J.astype(np.int32), h.astype(np.int32)
+        E, S, K = probs[i].replica_best()
+        x, v, _ = probs[i].get_state()
+        for r in (0, 31):
+            o = O.anneal(Ji, hi, 0, 1, betas, 0.2, 1.0, 25, 5000 + i, r0=r)
+            assert E[r] == o.bestE[0] and np.array_equal(x[r].view(np.uint32), o.x[0].view(np.uint32)), (i, r)
+    for i in range(0, len(probs), 97):
+        e, s = probs[i].best()
+        J, h = insts[i]
+        assert O.energy(J.astype(np.int32), h.astype(np.int32), s) == round(e), i
+    for p in probs:
+        p.close()
+
+
+def test_serving_full_stream_energies(P, O):
+    """The serving workload's 60 requests (N log-uniform in [100, 4000], dense
+    and sparse, integer and fixed point): every result's energy is the Eq. 2
+    energy of the state it returns, success means reaching the planted
+    energy, and no result lies below the planted ground state."""
+    import time
+    g = inst.rng(0)
+    n = 60
+    sizes = np.rint(np.exp(g.uniform(np.log(100), np.log(4000), size=n))).astype(int)
+    srv = P.Server(1 << 36, max_slots=64, chunk_steps=500)
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    reqs = []
+    for i in range(n):
+        J, h, E, _ = inst.planted_loops(int(sizes[i]), 20_000 + i, alpha=0.4, dense=(i % 2 == 1))
+        f = 0
+        if (i // 2) % 2 == 1:
+            J, f = J / 16.0, 4
+        p = P.Problem(J, h, frac_bits=f, path="i8")
+        # energies in grid units: the fixed-point copy J / 16 on the 2^-4 grid
+        # has the integer instance's units, so E is the target either way
+        t = srv.submit(p, 64, 20000, E, seed=900 + i, **sched)
+        reqs.append((p, t, J, h, E, f))
+    say("submitted", n)
+    for p, t, J, h, E, f in reqs:
+        r = srv.wait(t, 300.0)
+        assert r["state"] == P.REQ_DONE, r
+        s = srv.spins(t)
+        Ji = np.rint(J * (1 << f)).astype(np.int32)
+        hi = np.rint(h * (1 << f)).astype(np.int32)
+        e = O.energy(Ji, hi, s)
+        assert e == r["energy_units"]
+        assert e >= E and r["success"] == (e <= E)
+    srv.close()
+    for p, *_ in reqs:
+        p.close()
