@@ -490,7 +490,7 @@ def main():
         mfma_ops = 2.0 * Nk * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
     mfma_peak = (FP4_MFMA_PEAK if fp4_ops else INT8_MFMA_PEAK if info["path_name"] == "i8"
                  else BF16_MFMA_PEAK * 0.5)
-    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel")}
+    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel", "group_on_one_xcd")}
     # counter summaries are kept per kernel and per workload variant
     profile_key = args.workload + ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "")
     kernel = ("k_sweep_fp32" if info["path_name"] == "fp32" else
@@ -541,7 +541,8 @@ def main():
         "config": {"workload": w["desc"], "N": N, "replicas": R, "hmc_steps": T, "path": info["path_name"],
                    "schedule": dict(s, deriv=args.deriv, **({} if mh is None else {"mh_up": mh[0], "mh_down": mh[1]})),
                    "group": info["group"], "rows_per_block": info["rows_per_block"],
-                   "j_in_lds": info["j_in_lds"], "sweep_kernel": kernel, "autotune_us_per_step": tuned_us},
+                   "j_in_lds": info["j_in_lds"], "group_on_one_xcd": info["group_on_one_xcd"],
+                   "sweep_kernel": kernel, "autotune_us_per_step": tuned_us},
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }
     if mh_stats is not None:

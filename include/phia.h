@@ -117,6 +117,9 @@ typedef struct {
     int64_t step;           /* next step to run                                      */
     int64_t max_abs_J;      /* max |J| in units                                      */
     size_t device_bytes;    /* device memory held by the problem                     */
+    int32_t group_on_one_xcd; /* 1: a group's workgroups share one XCD; 0: member m of
+                               every group on XCD m mod 8 (each XCD's L2 then holds
+                               only its members' J slices)                           */
 } phia_info;
 
 /* Create a problem from real couplings.  J: host, N*N doubles, row-major,

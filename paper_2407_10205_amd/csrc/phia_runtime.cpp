@@ -203,11 +203,11 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 
 // ------------------------------------------------------- kernel geometry --
 // ------------------------------------------------------- tuning cache --
-// One line per tuned shape: "phia-tune3 path Np R kind mt cbw G jlds us_per_step".
+// One line per tuned shape: "phia-tune4 path Np R kind mt cbw G jlds xcd us_per_step".
 static const char* tune_cache_path() { return std::getenv("PHIA_TUNE_CACHE"); }
 
-static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g);
-static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g);
+static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g, int xcd = -1);
+static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd = -1);
 
 static bool lookup_tune_cache(phia_problem* p, int R)
 {
@@ -216,14 +216,15 @@ static bool lookup_tune_cache(phia_problem* p, int R)
     FILE* f = std::fopen(path, "r");
     if (!f) return false;
     char tag[32];
-    int pa, np, r, kind, mt, cbw, G, jl;
+    int pa, np, r, kind, mt, cbw, G, jl, xcd;
     double us;
     bool found = false;
     Geometry g;
-    while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &kind, &mt, &cbw, &G, &jl, &us) ==
-           10) {
-        if (std::strcmp(tag, "phia-tune3") == 0 && pa == p->path && np == p->Np && r == R &&
-            (kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g) : make_geometry(p, R, mt, cbw, G, jl, g))) {
+    while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &kind, &mt, &cbw, &G, &jl, &xcd,
+                       &us) == 11) {
+        if (std::strcmp(tag, "phia-tune4") == 0 && pa == p->path && np == p->Np && r == R &&
+            (kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g, xcd)
+                       : make_geometry(p, R, mt, cbw, G, jl, g, xcd))) {
             p->geo = g;
             found = true;
         }
@@ -238,15 +239,39 @@ static void append_tune_cache(const phia_problem* p, int R, const Geometry& g, d
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "phia-tune3 %d %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.kind, g.mt, g.cbw, g.G, g.j_lds,
-                 us);
+    std::fprintf(f, "phia-tune4 %d %d %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.kind, g.mt, g.cbw, g.G,
+                 g.j_lds, g.xcd_map, us);
     std::fclose(f);
 }
 
+// Placement of a group's workgroups over the 8 XCDs (round-robin dispatch:
+// workgroup b runs on XCD b mod 8).  xcd_map = 1 puts all members of a group
+// on one XCD; 0 puts member m of every group on XCD m mod 8 (G a multiple of
+// 8), so that each XCD's L2 holds only its members' slices of a J that is
+// streamed every step.  Default: 1, unless J is streamed from L2 and larger
+// than half an XCD's 4 MiB L2.  xcd = 0 or 1 forces a placement; false if
+// it cannot apply.
+static bool pick_xcd(const phia_problem* p, int G, int ngroups, int j_lds, int xcd, int& out)
+{
+    const bool same_ok = G > 1 && ngroups % 8 == 0;
+    if (xcd == 1) {
+        out = 1;
+        return same_ok;
+    }
+    if (xcd == 0) {
+        out = 0;
+        return true;
+    }
+    const double jbytes = static_cast<double>(p->Np) * p->Np * (p->path == PHIA_PATH_I8 ? 1 : 4);
+    out = (same_ok && (j_lds || jbytes <= 2.0 * 1024 * 1024)) ? 1 : 0;
+    return true;
+}
+
 // Complete a candidate launch geometry (mt row tiles per block, G workgroups
-// per block, J slice in LDS or not) for R replicas; false if it does not fit
-// this device (LDS, columns per workgroup, co-residency of a group).
-static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g)
+// per block, J slice in LDS or not, XCD placement) for R replicas; false if it
+// does not fit this device (LDS, columns per workgroup, co-residency of a
+// group).
+static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g, int xcd)
 {
     const int Np = p->Np, ncb = Np / 16;
     if (mt < 1 || mt > 2 || cbw < 1 || cbw > kCbwMax || G < 1 || G > ncb) return false;
@@ -278,7 +303,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     g.rows = rows;
     g.nblocks = nblocks;
     g.ngroups = ngroups;
-    g.xcd_map = (G > 1 && ngroups % 8 == 0) ? 1 : 0;
+    if (!pick_xcd(p, G, ngroups, j_lds, xcd, g.xcd_map)) return false;
     g.lds = lds;
     g.mh = p->mh;
     return true;
@@ -288,7 +313,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
 // two 16-replica sub-blocks on two wave teams, G >= 2 workgroups per block
 // with one column block per wave; MFMA operands int8 or (fp4 = 1, couplings
 // that are all FP4 integers) FP4.  False if it does not apply.
-static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g)
+static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd)
 {
     const int Np = p->Np, ncb = Np / 16;
     if (p->path != PHIA_PATH_I8 || p->trace || p->one_block_kernel || p->mh || G < 2 || G > ncb ||
@@ -314,7 +339,7 @@ static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g
     g.rows = 32;
     g.nblocks = nblocks;
     g.ngroups = ngroups;
-    g.xcd_map = (ngroups % 8 == 0) ? 1 : 0;
+    if (!pick_xcd(p, G, ngroups, 1, xcd, g.xcd_map)) return false;
     g.lds = lds;
     return true;
 }
@@ -332,8 +357,11 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
         for (int mt : {1, 2})
             for (int cbw = 1; cbw <= kCbwMax; ++cbw)
                 for (int jl : {1, 0}) {
-                    Geometry g;
-                    if (make_geometry(p, R, mt, cbw, G, jl, g)) out.push_back(g);
+                    Geometry g, h;
+                    if (!make_geometry(p, R, mt, cbw, G, jl, g)) continue;
+                    out.push_back(g);  // default placement first
+                    // the other placement only matters for a J streamed from L2
+                    if (G > 1 && !jl && make_geometry(p, R, mt, cbw, G, jl, h, 1 - g.xcd_map)) out.push_back(h);
                 }
         for (int fp4 : {0, 1}) {
             Geometry g;
@@ -345,21 +373,22 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
 
 // Default geometry without tuning: fewest passes over the replica blocks,
 // then the fewest owned elements per workgroup, then J in LDS.
-// PHIA_GEOMETRY="mt,G,jlds[,cbw]" or "pp,G" forces one candidate (tuning
-// experiments).
+// PHIA_GEOMETRY="mt,G,jlds[,cbw[,xcd]]" or "pp,G[,xcd]" / "pp4,G[,xcd]" forces
+// one candidate (tuning experiments).
 static void choose_mfma_geometry(phia_problem* p, int R)
 {
     p->geo.ok = false;
     int f_mt = 0, f_G = 0, f_j = -1, f_c = kCbwMax;
     if (const char* env = std::getenv("PHIA_GEOMETRY")) {
-        if (std::sscanf(env, "pp,%d", &f_G) == 1 || std::sscanf(env, "pp4,%d", &f_G) == 1) {
+        int f_x = -1;
+        if (std::sscanf(env, "pp,%d,%d", &f_G, &f_x) >= 1 || std::sscanf(env, "pp4,%d,%d", &f_G, &f_x) >= 1) {
             Geometry g;
-            if (make_geometry_pp(p, R, f_G, std::strncmp(env, "pp4", 3) == 0, g)) p->geo = g;
+            if (make_geometry_pp(p, R, f_G, std::strncmp(env, "pp4", 3) == 0, g, f_x)) p->geo = g;
             return;
         }
-        if (std::sscanf(env, "%d,%d,%d,%d", &f_mt, &f_G, &f_j, &f_c) >= 3) {
+        if (std::sscanf(env, "%d,%d,%d,%d,%d", &f_mt, &f_G, &f_j, &f_c, &f_x) >= 3) {
             Geometry g;
-            if (make_geometry(p, R, f_mt, f_c, f_G, f_j, g)) p->geo = g;
+            if (make_geometry(p, R, f_mt, f_c, f_G, f_j, g, f_x)) p->geo = g;
             return;
         }
     }
@@ -371,7 +400,7 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         // tuned without (or with) the accept/reject step: same shape, LDS redone
         Geometry g;
         if (p->tuned.kind == 0 &&
-            make_geometry(p, R, p->tuned.mt, p->tuned.cbw, p->tuned.G, p->tuned.j_lds, g)) {
+            make_geometry(p, R, p->tuned.mt, p->tuned.cbw, p->tuned.G, p->tuned.j_lds, g, p->tuned.xcd_map)) {
             p->geo = g;
             return;
         }
@@ -1194,6 +1223,7 @@ phia_status phia_get_info(const phia_problem* p, phia_info* out)
     out->step = p->k;
     out->max_abs_J = p->maxabsJ;
     out->device_bytes = p->base_bytes + p->state_bytes;
+    out->group_on_one_xcd = p->geo.G > 1 ? p->geo.xcd_map : 0;
     return PHIA_OK;
 }
 

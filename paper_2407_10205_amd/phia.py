@@ -69,7 +69,7 @@ class Info(C.Structure):
                 ("exact", C.c_int32), ("group", C.c_int32), ("replicas", C.c_int32),
                 ("rows_per_block", C.c_int32), ("j_in_lds", C.c_int32), ("sweep_kernel", C.c_int32),
                 ("steps", C.c_int64), ("step", C.c_int64),
-                ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t)]
+                ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t), ("group_on_one_xcd", C.c_int32)]
 
 
 def _declare(lib):
