@@ -68,6 +68,11 @@ WORKLOADS = {
     "sk2000": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=5, bits=8), R=512, T=20000,
                    sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
                    desc="SK N=2000 J~N(0,1) 8-bit fixed point (2^-5), h in [-1,1], 512 replicas x 2e4 steps"),
+    "sk2000_16bit": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=12, bits=16), R=512, T=20000,
+                         path="bf16hilo",
+                         sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
+                         desc="SK N=2000 J~N(0,1) 16-bit fixed point (2^-12, BF16 hi/lo planes both non-zero), "
+                              "h in [-1,1], 512 replicas x 2e4 steps"),
 }
 
 
@@ -387,7 +392,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed complete anneals")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="maxcut800", choices=sorted(WORKLOADS))
-    ap.add_argument("--path", default="i8", choices=["i8", "bf16hilo", "fp32", "auto"])
+    ap.add_argument("--path", default=None, choices=["i8", "bf16hilo", "fp32", "auto"],
+                    help="coupling path (default: the workload's, int8 unless stated)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-tts", action="store_true")
@@ -439,6 +445,8 @@ def main():
         return
     J, h = make_instance(w)
     N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]
+    if args.path is None:
+        args.path = w.get("path", "i8")
     stream = torch.cuda.Stream()
     prob = phia.Problem(J, h, path=args.path, stream=stream.cuda_stream)
     tuned_us = prob.autotune(R, 200) if not args.no_tune else None
