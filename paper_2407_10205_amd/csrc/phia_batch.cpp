@@ -61,6 +61,38 @@ void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int
     }
 }
 
+// Largest instances first (the dispatcher then fills the tail with small
+// ones), and within every run of 8 instances with the same item count the
+// items interleaved so that the items of one instance sit 8 workgroups apart:
+// under round-robin dispatch over the 8 XCDs they share one XCD and its L2,
+// which then streams that instance's J once for all of its items.
+void order_items(std::vector<SweepArgs>& items)
+{
+    std::stable_sort(items.begin(), items.end(), [](const SweepArgs& x, const SweepArgs& y) { return x.Np > y.Np; });
+    std::vector<std::pair<size_t, size_t>> inst;  // (first item, item count), items of one instance are adjacent
+    for (size_t i = 0; i < items.size();) {
+        size_t j = i + 1;
+        while (j < items.size() && items[j].x == items[i].x) ++j;
+        inst.emplace_back(i, j - i);
+        i = j;
+    }
+    std::vector<SweepArgs> out;
+    out.reserve(items.size());
+    for (size_t c = 0; c < inst.size(); c += 8) {
+        const size_t n = std::min<size_t>(8, inst.size() - c);
+        bool same = n == 8;
+        for (size_t k = 1; same && k < n; ++k) same = inst[c + k].second == inst[c].second;
+        if (same) {
+            for (size_t b = 0; b < inst[c].second; ++b)
+                for (size_t k = 0; k < n; ++k) out.push_back(items[inst[c + k].first + b]);
+        } else {
+            for (size_t k = 0; k < n; ++k)
+                for (size_t b = 0; b < inst[c + k].second; ++b) out.push_back(items[inst[c + k].first + b]);
+        }
+    }
+    items.swap(out);
+}
+
 }  // namespace
 
 namespace phia {
@@ -78,8 +110,7 @@ phia_status launch_batch_chunk(phia_problem* const* probs, int count, const int6
     std::vector<SweepArgs> tab;
     std::vector<size_t> offs;
     for (auto& kv : buckets) {
-        std::stable_sort(kv.second.items.begin(), kv.second.items.end(),
-                         [](const SweepArgs& x, const SweepArgs& y) { return x.Np > y.Np; });
+        order_items(kv.second.items);
         offs.push_back(tab.size());
         tab.insert(tab.end(), kv.second.items.begin(), kv.second.items.end());
     }
@@ -310,11 +341,9 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         restore();
         return st_;
     }
-    // Largest instances first: the dispatcher then fills the tail with small ones.
     size_t total_items = 0;
     for (auto& kv : buckets) {
-        std::stable_sort(kv.second.items.begin(), kv.second.items.end(),
-                         [](const SweepArgs& x, const SweepArgs& y) { return x.Np > y.Np; });
+        order_items(kv.second.items);
         total_items += kv.second.items.size();
     }
     // One device table: the init entries, then every bucket's items.
