@@ -703,3 +703,35 @@ def test_serving_full_stream_energies(P, O):
     srv.close()
     for p, *_ in reqs:
         p.close()
+
+
+def test_xcd_placements_identical(P, O):
+    """Column-split groups with all members on one XCD and with member m of
+    every group on XCD m (J streamed or in LDS): bit-identical runs, which
+    match the oracle on sampled replicas."""
+    import os
+    J, h = inst.sk_gauss_fixed(300, 9, frac_bits=5, bits=8)
+    R, T = 256, 60
+    ref = None
+    for geo in ("1,8,0,2,0", "1,8,0,2,1", "1,8,1,2,0", "1,8,1,2,1", "2,16,0,1,0"):
+        os.environ["PHIA_GEOMETRY"] = geo
+        try:
+            p = P.Problem(J, h, path="i8")
+            p.anneal(R, T, 0.2, 1.0, beta0=0.05, beta1=1.0, refresh_L=20, seed=4)
+        finally:
+            del os.environ["PHIA_GEOMETRY"]
+        info = p.info()
+        say("geometry", geo, info)
+        got = p.replica_best() + p.get_state()[:2]
+        p.close()
+        assert info["group"] in (8, 16)
+        assert info["group_on_one_xcd"] == int(geo[-1])
+        if ref is None:
+            ref = got
+        else:
+            for u, w in zip(ref, got):
+                assert np.array_equal(u, w), geo
+    Ji, hi = int_units(J, h, 5)
+    for r in (0, 255):
+        o = O.anneal(Ji, hi, 5, 1, O.beta_linear(0.05, 1.0, T), 0.2, 1.0, 20, 4, r0=r)
+        assert ref[0][r] == o.bestE[0] and np.array_equal(ref[3][r], o.x[0])
