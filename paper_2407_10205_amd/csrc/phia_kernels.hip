@@ -9,22 +9,37 @@
 //   best-so-far record of (E, s)                          (App. B, Table 3)
 //   v_i <- v_i + eps (c_k sech^2(gamma x_i) I_i - x_i),   c_k = beta_k gamma sigma
 //
+// Optionally, at every k > 0 with k mod L == 0, the trajectory that just
+// ended is accepted or rejected with H(x, v) = beta E + x.x/2 + v.v/2
+// (App. A; App. B, Table 3, state 4), and a per-replica multiplier of beta
+// follows the outcomes.
+//
 // Kernels:
-//   k_init         x ~ N(0, I) (App. A, A3), records reset.
+//   k_init         x ~ N(0, I) (App. A, A3), records and accept/reject
+//                  state reset.
 //   k_sweep_fp32   plain sweep: FP32 couplings, VALU dot products, one
 //                  workgroup owns kFp32Rows replicas for the whole launch.
 //   k_sweep_mfma   J.s on matrix cores: int8 x int8 -> int32
 //                  (v_mfma_i32_16x16x64_i8) or two BF16 planes J = 256 hi + lo
 //                  with FP32 accumulation (v_mfma_f32_16x16x32_bf16).  A
-//                  workgroup owns 16*MT replicas and a slice of the columns;
-//                  its J slice stays in LDS for the whole launch.  When J is too
+//                  workgroup owns 16*MT replicas and a slice of the columns,
+//                  its J slice in LDS or streamed from L2.  When J is too
 //                  large for one CU, G workgroups split the columns and swap
-//                  the new spins of their slices through global memory once
-//                  per step (bounded flag barrier, partial energies ride along
-//                  one step late).  x, v and the accumulators stay in VGPRs in
-//                  the MFMA output layout, so the kick is fused with J.s.
+//                  the new spins of their slices every step through tagged
+//                  64-bit words (bounded polls; partial energies ride along
+//                  one step late).  x, v and the accumulators stay in VGPRs
+//                  in the MFMA output layout, so the kick is fused with J.s.
+//                  Batch mode: one work item (instance, replica block) per
+//                  workgroup from a table; with GROUP, several column-split
+//                  instances in one cooperative launch.  MH: the accept/reject
+//                  step.
+//   k_sweep_pp     the column-split int8 sweep with two 16-replica sub-blocks
+//                  per workgroup on two wave teams one phase apart, so the
+//                  exchange of one sub-block hides behind the compute of the
+//                  other; int8 or FP4 matrix-core operands.
 //   k_argmin       lowest best energy over replicas (lowest index on ties).
 //   k_energy_f64   FP64 Eq. 2 energy of one configuration.
+//   k_fmath_eval   the elementary functions, for bit-exact checks.
 #include <stdint.h>
 
 #include <type_traits>
