@@ -58,7 +58,7 @@ WORKLOADS = {
                   sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
                   desc="serving: Poisson arrivals at 200 req/s, planted frustrated-loop instances, N log-uniform "
                        "in [100,4000], half dense / half sparse, half integer / half fixed point (2^-4); 64 replicas, "
-                       "stop at the planted energy or 2e4 steps"),
+                       "stop at the planted energy or 2e4 steps; beta in units of each instance's grid"),
     "tts_sweep": dict(gen="tts_sweep", args=dict(sizes=(8, 16, 32, 64, 128, 256, 512, 1024), seed=0), R=256,
                       T=1000, sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
                       desc="time to target versus N for the Table 2 families (maxcut_dense, maxcut_d3, sk_bool, "
@@ -215,7 +215,11 @@ def run_serve_bench(args, w):
         delay = r["arrive"] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        tickets.append(srv.submit(p, R, T, r["target"], seed=17, **s))
+        # beta in units of the instance's grid (beta 2^f): the fixed-point copy of
+        # an instance then anneals exactly as the integer one (power-of-two
+        # scaling), so success probabilities are matched across the mix
+        sr = dict(s, beta0=s["beta0"] * 2.0 ** r["frac_bits"], beta1=s["beta1"] * 2.0 ** r["frac_bits"])
+        tickets.append(srv.submit(p, R, T, r["target"], seed=17, **sr))
     res = [srv.wait(tk) for tk in tickets]
     srv.close()
     lat = np.array([x["t_done"] - x["t_arrive"] for x in res])
@@ -410,7 +414,7 @@ def main():
                          "multiply beta by UP after an acceptance, DOWN after a rejection (1,1: fixed schedule)")
     ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
-    ap.add_argument("--chunk", type=int, default=500, help="serving workload: steps per scheduling round")
+    ap.add_argument("--chunk", type=int, default=250, help="serving workload: steps per scheduling round")
     args = ap.parse_args()
     if args.summarize_profiles:
         res = summarize_profiles(args.summarize_profiles, WORKLOADS[args.workload]["desc"])
