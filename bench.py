@@ -412,6 +412,8 @@ def main():
     ap.add_argument("--mh", metavar="UP,DOWN", default=None,
                     help="accept or reject every trajectory of refresh_L steps (App. A, Table 3 state 4) and "
                          "multiply beta by UP after an acceptance, DOWN after a rejection (1,1: fixed schedule)")
+    ap.add_argument("--no-incremental", action="store_true",
+                    help="recompute J.s in full every step (default: flip-incremental update where the sweep has it)")
     ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
     ap.add_argument("--chunk", type=int, default=250, help="serving workload: steps per scheduling round")
@@ -453,6 +455,8 @@ def main():
         args.path = w.get("path", "i8")
     stream = torch.cuda.Stream()
     prob = phia.Problem(J, h, path=args.path, stream=stream.cuda_stream)
+    if args.no_incremental:
+        prob.set_incremental(False)
     tuned_us = prob.autotune(R, 200) if not args.no_tune else None
     info = None
 
@@ -479,6 +483,14 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     info = prob.info()  # geometry of the timed runs
+    inc_stats = None
+    if info["incremental"]:
+        # J.s work of the last timed run: k blocks computed over those of a
+        # full product at every step
+        n_inc, n_full, n_kb = prob.incremental_stats()
+        nkb = info["Np"] // 64
+        inc_stats = {"steps_incremental": n_inc / max(1, n_inc + n_full),
+                     "kblocks_frac": (n_kb + n_full * nkb) / max(1, (n_inc + n_full) * nkb)}
     # per-replica records of the last timed run, for the success estimate
     E_last, _, _ = prob.replica_best()
     mh_stats = None
@@ -500,11 +512,15 @@ def main():
     if fp4_ops:
         Nk = math.ceil(Np / 128) * 128  # FP4 products run over 128-wide k blocks
         mfma_ops = 2.0 * Nk * Np * (math.ceil(R / info["rows_per_block"]) * info["rows_per_block"]) * T
+    if inc_stats is not None:
+        mfma_ops *= inc_stats["kblocks_frac"]
     mfma_peak = (FP4_MFMA_PEAK if fp4_ops else INT8_MFMA_PEAK if info["path_name"] == "i8"
                  else BF16_MFMA_PEAK * 0.5)
-    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel", "group_on_one_xcd")}
+    geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel", "group_on_one_xcd",
+                                     "incremental")}
     # counter summaries are kept per kernel and per workload variant
-    profile_key = args.workload + ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "")
+    profile_key = (args.workload + ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "") +
+                   ("_full" if args.no_incremental else ""))
     kernel = ("k_sweep_fp32" if info["path_name"] == "fp32" else
               "k_sweep_pp" if info["sweep_kernel"] >= 1 else "k_sweep_mfma")
     if args.geometry_out:
@@ -554,11 +570,14 @@ def main():
                    "schedule": dict(s, deriv=args.deriv, **({} if mh is None else {"mh_up": mh[0], "mh_down": mh[1]})),
                    "group": info["group"], "rows_per_block": info["rows_per_block"],
                    "j_in_lds": info["j_in_lds"], "group_on_one_xcd": info["group_on_one_xcd"],
+                   "incremental": info["incremental"],
                    "sweep_kernel": kernel, "autotune_us_per_step": tuned_us},
         "roofline": roofline, "cpu_baseline": cpu, **extra,
     }
     if mh_stats is not None:
         out["metropolis"] = mh_stats
+    if inc_stats is not None:
+        out["incremental"] = inc_stats
     print(json.dumps(out), flush=True)
 
 

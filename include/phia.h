@@ -120,6 +120,8 @@ typedef struct {
     int32_t group_on_one_xcd; /* 1: a group's workgroups share one XCD; 0: member m of
                                every group on XCD m mod 8 (each XCD's L2 then holds
                                only its members' J slices)                           */
+    int32_t incremental;    /* 1: the sweep updates J.s by the flip-incremental
+                               product (see phia_set_incremental)                    */
 } phia_info;
 
 /* Create a problem from real couplings.  J: host, N*N doubles, row-major,
@@ -188,6 +190,33 @@ phia_status phia_replica_mh(phia_problem* p, int32_t* accepted, int32_t* decided
 phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int64_t k);
 
 phia_status phia_get_info(const phia_problem* p, phia_info* out);
+
+/* Flip-incremental quasi-gradient (an execution strategy; not part of the
+ * paper's method).  Between consecutive steps only the spins whose sign
+ * changed alter I = J s + h of Eq. 6: I(k) = I(k-1) + J (s(k) - s(k-1)), with
+ * s(k) - s(k-1) = +-2 on the changed spins and 0 elsewhere.  With on = 1
+ * (the default) the sweep keeps J s in registers and, at every step after
+ * the first of a launch, adds the product over the 16-spin column blocks
+ * that changed in any replica of a 16-replica block, falling back to the
+ * full product when that covers more than 2/3 of it.  Integer arithmetic
+ * makes both identical bit for bit, so results do not depend on the
+ * setting.  It applies where the sweep has such a variant: the I8 path, a
+ * column-split group of one-row-tile blocks with J streamed from L2, no
+ * accept/reject step, an anneal of its own (not a batch or server launch),
+ * N <= 4864 (the LDS holds the bookkeeping);
+ * phia_info.incremental reports whether the current geometry uses it.
+ * on = 0 always computes the full product.  Takes effect at the next
+ * phia_anneal_start or phia_anneal.  PHIA_EINVAL if on is not 0 or 1. */
+phia_status phia_set_incremental(phia_problem* p, int32_t on);
+
+/* Counters of the flip-incremental update since the last phia_anneal_start,
+ * summed over the replica blocks: out[0] steps that took the incremental
+ * product, out[1] steps that computed the full product (every launch's first
+ * step among them), out[2] 64-wide k blocks of the incremental products (a
+ * full product takes Np / 64).  All zero when the geometry has no such
+ * variant.  out: host, 3 int64.  Synchronizes the problem's stream.
+ * PHIA_ESTATE before any phia_anneal_start. */
+phia_status phia_incremental_stats(phia_problem* p, int64_t* out);
 
 /* Autotuner of the launch geometry of the matrix-core sweep (replicas per
  * workgroup block, workgroups sharing one block's columns, coupling slice in

@@ -38,6 +38,7 @@ void add_items(phia_problem* p, int64_t k_end, std::map<std::tuple<int, int, int
     const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1, p->mh) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
     const int nblocks = (p->R + 15) / 16;
     SweepArgs a = sweep_args(p);
+    a.inc = 0;  // table launches carry no flip-incremental variant
     a.J = p->dJ;  // int8 fragments (the batch kernel's operands)
     a.k0 = p->k;
     a.k1 = k_end;
@@ -196,6 +197,7 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
         for (int i : L.members) {
             phia_problem* p = probs[i];
             SweepArgs a = sweep_args(p);
+            a.inc = 0;  // table launches carry no flip-incremental variant
             a.k0 = p->k;
             a.k1 = k_end[i];
             a.etrace = nullptr;
@@ -314,6 +316,7 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         p->geo.j_lds = jl;
         if ((st_ = setup_mh_geometry(p)) != PHIA_OK) break;
         SweepArgs a = sweep_args(p);
+        a.inc = 0;  // table launches carry no flip-incremental variant
         a.J = p->dJ;
         a.k0 = 0;
         a.k1 = steps[i];

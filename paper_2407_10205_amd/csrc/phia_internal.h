@@ -44,6 +44,9 @@ struct SweepArgs {
     int32_t ngroups;            // concurrently running groups
     int32_t xcd_map;            // 1: group members share blockIdx % 8
     int32_t j_lds;              // 1: J slice resident in LDS, 0: read from global
+    int32_t inc;                // 1: flip-incremental field update (int8, column split, J streamed)
+    int64_t* incstat;           // [3] incremental steps, full-product steps, k blocks of the
+                                //     incremental products (member 0 of every group), or null
     // group exchange (G > 1)
     uint64_t* xbits;            // [2][ngroups][rows][Np/16] tagged sign words
     uint64_t* pbuf;             // [2][ngroups][G][rows][2] (seq << 32) | 32-bit half of a partial energy
@@ -84,7 +87,7 @@ hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const 
                              double* out, hipStream_t st);
 hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,
                              hipStream_t st);
-int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, size_t lds_bytes);
+int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, int inc, size_t lds_bytes);
 // interleaved group sweep: int8 J, two 16-replica sub-blocks per workgroup
 constexpr int kPpMaxNcb = 256;            // Np <= 4096
 constexpr int64_t kPpMaxRowSum = 1 << 18;  // 32 * max_i(sum_j |J_ij| + |h_i|) < 2^23

@@ -471,7 +471,7 @@ hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st)
 // --------------------------------------------------------- MFMA sweep --
 // LDS carve-up of one workgroup, shared with the host launch code.
 struct LdsPlan {
-    uint32_t j_off, s_off, s_bytes, p_off, e_off, b_off, k_off, misc_off, mh_off, total;
+    uint32_t j_off, s_off, s_bytes, p_off, e_off, b_off, k_off, misc_off, mh_off, u_off, l_off, total;
 };
 
 // Accept/reject bookkeeping of a replica block in LDS, 56 bytes per replica:
@@ -486,7 +486,17 @@ __host__ __device__ inline uint32_t cb_bytes(int path, int Np)
     return static_cast<uint32_t>(Np) * 16u * (path == kPathI8 ? 1u : 4u);
 }
 
-__host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_max, int j_lds, int mh = 0)
+// inc: LDS of the flip-incremental field update (the changed column blocks
+// as a bit mask [ceil(Np/1024)] uint64 and one list of changed column blocks
+// per wave [kWaves][inc_list_len(Np)] uint16, which also stages that wave's
+// sign ballots).
+__host__ __device__ inline uint32_t inc_list_len(int Np)
+{
+    const uint32_t ncb = static_cast<uint32_t>(Np) / 16u;
+    return ncb > 64u ? ncb : 64u;
+}
+
+__host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_max, int j_lds, int mh = 0, int inc = 0)
 {
     LdsPlan p;
     const uint32_t rows = 16u * mt;
@@ -499,7 +509,10 @@ __host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_ma
     p.k_off = p.b_off + 2u * rows * 8u;  // [RB] step of the best energy
     p.misc_off = p.k_off + rows * 8u;
     p.mh_off = p.misc_off + 16u;
-    p.total = p.mh_off + (mh ? rows * kMhLdsPerRow : 0u);
+    const uint32_t ncb = static_cast<uint32_t>(Np) / 16u;
+    p.u_off = p.mh_off + (mh ? rows * kMhLdsPerRow : 0u);
+    p.l_off = p.u_off + (inc ? ((ncb + 63u) / 64u * 8u + 15u) & ~15u : 0u);
+    p.total = p.l_off + (inc ? (static_cast<uint32_t>(kWaves) * inc_list_len(Np) * 2u + 15u) & ~15u : 0u);
     return p;
 }
 
@@ -677,13 +690,59 @@ __device__ __forceinline__ void quasi_gradient_w(int ncw, const unsigned char* S
         quasi_gradient<PATH, MT, CBW, 1>(S, srow, Jw, cws, Np, lane, lr, lg, hreg, I);
 }
 
+// Flip-incremental field update (int8 path, one row tile): acc += J[:, F] dS_F
+// over the column blocks F listed in `list` (nf entries), where dS = S_new -
+// S_old is -2, 0 or +2 per spin.  The k range of one MFMA holds four listed
+// blocks, one per lane group, and a lane's 16 coupling bytes of a block are
+// contiguous in the fragment-major layout, so the loads stay 16-byte vectors.
+// Integer arithmetic keeps acc equal to the full product J s bit for bit.
+template <int CBW, int NCW>
+__device__ __forceinline__ void quasi_gradient_inc(const unsigned char* Sn, const unsigned char* So, uint32_t srow,
+                                                   const unsigned char* Jw, size_t cw_stride, const uint16_t* list,
+                                                   int nf, int lr, int lg, v4i (&acc)[CBW])
+{
+    const int nvk = (nf + 3) >> 2;
+    auto load = [&](int vk, v4i& d, v4i (&B)[NCW]) {
+        const int e = 4 * vk + lg;
+        const bool ok = e < nf;
+        const int c = ok ? list[e] : 0;
+        const v4i sn = *reinterpret_cast<const v4i*>(Sn + lr * srow + 16 * c);
+        const v4i so = *reinterpret_cast<const v4i*>(So + lr * srow + 16 * c);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            // bytes are 0x01 (+1) or 0xff (-1): 2 s_new per byte where the sign changed
+            const uint32_t n = static_cast<uint32_t>(sn[t]), o = static_cast<uint32_t>(so[t]);
+            d[t] = ok ? static_cast<int>(((n << 1) & 0xfefefefeu) & (n ^ o)) : 0;
+        }
+        const size_t off = static_cast<size_t>(c >> 2) * 1024 + static_cast<size_t>(((c & 3) * 16 + lr) * 16);
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) B[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + off);
+    };
+    if (nvk == 0) return;
+    v4i dn, Bn[NCW];
+    load(0, dn, Bn);
+    for (int vk = 0; vk < nvk; ++vk) {
+        const v4i d = dn;
+        v4i B[NCW];
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) B[cw] = Bn[cw];
+        if (vk + 1 < nvk) load(vk + 1, dn, Bn);
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) acc[cw] = __builtin_amdgcn_mfma_i32_16x16x64_i8(d, B[cw], acc[cw], 0, 0, 0);
+    }
+}
+
 // One column block and one row tile per wave: registers are capped at 128 so two
 // workgroups share a CU and hide each other's exchange latency.
 // BATCH: each workgroup runs one work item of a table, with the J placement
 // chosen per item: one replica block of one instance and all of its columns,
 // or (with GROUP) one member of one group of a column-split instance, so that
 // one cooperative launch carries several instances.
-template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BATCH = false, bool MH = false>
+// INC: the field is kept in registers across steps and updated by the
+// flip-incremental product over the column blocks whose signs changed in any
+// replica of the block, or recomputed in full when too many changed.
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BATCH = false, bool MH = false,
+          bool INC = false>
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CBW == 1 && MT == 1 ? 4 : 2)))
 k_sweep_mfma(SweepArgs args)
 {
@@ -694,6 +753,8 @@ k_sweep_mfma(SweepArgs args)
     constexpr int NE = MT * CBW * 4;  // owned elements per lane
     static_assert(NE <= 32, "previous-sign mask holds 32 elements");
     static_assert(kWaves * NE * 8 <= 16 * MT * 80, "ballot staging fits in one S buffer");
+    static_assert(!INC || (PATH == kPathI8 && MT == 1 && GROUP && !BATCH && !MH),
+                  "flip-incremental variant: int8, one row tile, column split, no accept/reject");
     extern __shared__ __align__(16) unsigned char lds[];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -719,7 +780,7 @@ k_sweep_mfma(SweepArgs args)
     const int cbs = cb1 - cb0;
     const int cbs_max = (a.ncb + G - 1) / G;
     constexpr bool mh = MH;  // accept/reject step (App. A, Table 3 state 4)
-    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, jl ? 1 : 0, mh ? 1 : 0);
+    const LdsPlan P = lds_plan(PATH, MT, Np, cbs_max, jl ? 1 : 0, mh ? 1 : 0, INC ? 1 : 0);
     const uint32_t srow = static_cast<uint32_t>(Np) * ESZ + 16u;  // S row stride, bytes
     const uint32_t cbb = cb_bytes(PATH, Np);
     unsigned char* sJ = lds + P.j_off;
@@ -738,6 +799,10 @@ k_sweep_mfma(SweepArgs args)
     int* mOut = reinterpret_cast<int*>(mLam + RB);
     int* mAcc = mOut + RB;
     int* mDec = mAcc + RB;
+    // flip-incremental bookkeeping (used only when INC)
+    const int ncbk = a.ncb;
+    uint64_t* sM = reinterpret_cast<uint64_t*>(lds + P.u_off);  // bit c: a sign of block c changed
+    uint16_t* sLw = reinterpret_cast<uint16_t*>(lds + P.l_off) + wave * inc_list_len(Np);  // this wave's list
 
     const unsigned char* Jg = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cb0) * cbb;
     if (jl) {
@@ -819,6 +884,11 @@ k_sweep_mfma(SweepArgs args)
             for (int j = 0; j < 4; ++j) lamr[mt][j] = mh ? mLam[mt * 16 + 4 * lg + j] : 1.0f;
 
         uint32_t pm = 0;  // signs of step k-1, bit (mt*CBW + cw)*4 + j
+        v4i accI[CBW];    // INC: J s of the current step (no field), exact
+#pragma unroll
+        for (int cw = 0; cw < CBW; ++cw) accI[cw] = v4i{0, 0, 0, 0};
+        uint32_t n_inc = 0, n_full = 0;  // INC: steps by kind (uniform in the workgroup)
+        uint64_t n_kb = 0;               // INC: k blocks of the incremental products
         bool aborted = false;
         int64_t next_ref = ref0;
         uint64_t round = static_cast<uint64_t>(ref0 / a.L);
@@ -1019,16 +1089,35 @@ k_sweep_mfma(SweepArgs args)
                     // stores one word with a single unbranched instruction.  The
                     // staging area is the start of S[par], which the gather
                     // below overwrites only after the next workgroup barrier.
-                    uint64_t* sW = reinterpret_cast<uint64_t*>(S) + wave * (MT * CBW * 4);
+                    // With INC the previous step's S[par] may still be read by
+                    // another wave's incremental product, so the ballots go
+                    // through this wave's own list area instead.
+                    // With INC every word also carries, in bit 16, whether any
+                    // sign of its column block changed in any replica of the
+                    // block since step k-1 (pm holds those signs).
+                    uint64_t* sW = INC ? reinterpret_cast<uint64_t*>(sLw)
+                                       : reinterpret_cast<uint64_t*>(S) + wave * (MT * CBW * 4);
+                    uint32_t lchg = 0;  // INC: bit cw set when one of this lane's signs of block cw changed
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                         for (int cw = 0; cw < CBW; ++cw)
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
-                                const uint64_t b = __ballot(x[mt][cw][j] >= 0.0f);
+                                const bool pos = x[mt][cw][j] >= 0.0f;
+                                const uint64_t b = __ballot(pos);
                                 if (lane == 0) sW[(mt * CBW + cw) * 4 + j] = b;
+                                if (INC) {
+                                    const uint32_t was = (pm >> ((mt * CBW + cw) * 4 + j)) & 1u;
+                                    lchg |= ((pos ? 1u : 0u) ^ was) << cw;
+                                }
                             }
+                    uint32_t chg = 0;  // INC: bit cw set when column block cw changed in any replica
+                    if (INC) {
+#pragma unroll
+                        for (int cw = 0; cw < CBW; ++cw)
+                            chg |= (__ballot((lchg >> cw) & 1u) != 0 ? 1u : 0u) << cw;
+                    }
                     __builtin_amdgcn_wave_barrier();
                     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     // lane -> (ballot bi = lane / 4, row group g = lane % 4)
@@ -1037,7 +1126,8 @@ k_sweep_mfma(SweepArgs args)
                         const int bi = lane >> 2, g = lane & 3;
                         const int mt = bi / (CBW * 4), cw = (bi >> 2) % CBW, j = bi & 3;
                         const int c = wave + kWaves * cw;
-                        const uint64_t w = (sW[bi] >> (16 * g)) & 0xffffu;
+                        const uint64_t w = ((sW[bi] >> (16 * g)) & 0xffffu) |
+                                           (INC ? static_cast<uint64_t>((chg >> cw) & 1u) << 16 : 0u);
                         const int row = mt * 16 + 4 * g + j;
                         if (c < cbs)
                             __hip_atomic_store(X + row * a.ncb + cb0 + c, tag | w, __ATOMIC_RELAXED,
@@ -1057,6 +1147,7 @@ k_sweep_mfma(SweepArgs args)
                 // sE[par].  All of a thread's loads are issued before any is
                 // inspected: one memory round trip.
                 const int nw = last ? 0 : RB * a.ncb;
+                bool chg_cb = false;  // INC: changed flag of block tid (words q < ncb are row 0's)
                 for (int base = 0; base < nw; base += kThreads * kGatherWords) {
                     uint64_t wv[kGatherWords];
 #pragma unroll
@@ -1072,7 +1163,14 @@ k_sweep_mfma(SweepArgs args)
                         if (static_cast<uint32_t>(w >> 32) != seq) w = await_tag(X + q, seq, a.err, sAbort);
                         const int row = q / a.ncb, cb = q - row * a.ncb;
                         unpack_signs<ESZ>(static_cast<uint32_t>(w) & 0xffffu, S + row * srow + cb * 16 * ESZ);
+                        if (INC && q < a.ncb) chg_cb = ((w >> 16) & 1u) != 0;
                     }
+                }
+                if (INC) {
+                    // words 0 .. ncb-1 (row 0, all blocks) are thread tid's first
+                    // word, so each wave's ballot is 64 blocks of the mask
+                    const uint64_t fb = __ballot(chg_cb);
+                    if (lane == 0 && wave * 64 < ncbk) sM[wave] = fb;
                 }
                 if (s > 0) {
                     const int np = G * RB;
@@ -1133,7 +1231,45 @@ k_sweep_mfma(SweepArgs args)
 
             // Quasi-gradient on matrix cores (columns of this wave only).
             int I[MT][CBW][4] = {};
-            {
+            bool incr = false;
+            if constexpr (INC) {
+                // Column blocks whose signs changed in any replica since step
+                // k-1, compacted in order into this wave's list; the
+                // incremental product runs when it needs at most 2/3 of the
+                // full product's k blocks (one of its k blocks costs about
+                // 1.5 of the full product's: two spin reads and scattered
+                // coupling blocks).
+                if (s > 0) {
+                    int nf = 0;
+                    for (int c0 = 0; c0 < ncbk; c0 += 64) {
+                        const uint64_t b = sM[c0 >> 6];  // bits past the last block are clear
+                        const int pos = nf + static_cast<int>(__builtin_amdgcn_mbcnt_hi(
+                                                 static_cast<uint32_t>(b >> 32),
+                                                 __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(b), 0u)));
+                        if ((b >> lane) & 1u) sLw[pos] = static_cast<uint16_t>(c0 + lane);
+                        nf += __popcll(b);
+                    }
+                    incr = 3 * ((nf + 3) >> 2) <= 2 * (Np / 64);
+                    n_inc += incr ? 1u : 0u;
+                    n_kb += incr ? static_cast<uint64_t>((nf + 3) >> 2) : 0u;
+                    if (incr) {
+                        __builtin_amdgcn_wave_barrier();
+                        __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+                        const unsigned char* So = lds + P.s_off + (par ^ 1) * P.s_bytes;
+                        const unsigned char* Jw = Jg + static_cast<size_t>(wave) * cbb;
+                        const size_t cws = static_cast<size_t>(kWaves) * cbb;
+                        if (CBW >= 2 && ncw >= 2)
+                            quasi_gradient_inc<CBW, (CBW >= 2 ? 2 : 1)>(S, So, srow, Jw, cws, sLw, nf, lr, lg, accI);
+                        else if (ncw >= 1)
+                            quasi_gradient_inc<CBW, 1>(S, So, srow, Jw, cws, sLw, nf, lr, lg, accI);
+#pragma unroll
+                        for (int cw = 0; cw < CBW; ++cw)
+#pragma unroll
+                            for (int j = 0; j < 4; ++j) I[0][cw][j] = accI[cw][j] + hreg[cw];
+                    }
+                }
+            }
+            if (!incr) {
                 const size_t cws = static_cast<size_t>(kWaves) * cbb;
                 if (jl)
                     quasi_gradient_w<PATH, MT, CBW>(ncw, S, srow, sJ + static_cast<size_t>(wave) * cbb, cws, Np, lane,
@@ -1141,6 +1277,13 @@ k_sweep_mfma(SweepArgs args)
                 else
                     quasi_gradient_w<PATH, MT, CBW>(ncw, S, srow, Jg + static_cast<size_t>(wave) * cbb, cws, Np, lane,
                                                     lr, lg, hreg, I);
+                if constexpr (INC) {
+                    ++n_full;
+#pragma unroll
+                    for (int cw = 0; cw < CBW; ++cw)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) accI[cw][j] = I[0][cw][j] - hreg[cw];
+                }
             }
 
             // The kick of the owned elements (mode branch outside the loops),
@@ -1196,6 +1339,11 @@ k_sweep_mfma(SweepArgs args)
                             a.bestS[gr * Np + col[cw]] = ((bestbits >> ((mt * CBW + cw) * 4 + j)) & 1u) ? 1 : -1;
                     }
             }
+        if (INC && member == 0 && tid == 0 && a.incstat) {
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.incstat), static_cast<unsigned long long>(n_inc));
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.incstat + 1), static_cast<unsigned long long>(n_full));
+            atomicAdd(reinterpret_cast<unsigned long long*>(a.incstat + 2), static_cast<unsigned long long>(n_kb));
+        }
         __syncthreads();
         if (member == 0) {
             // Final records sit in the buffer written by the closing pass (k1).
@@ -1945,14 +2093,14 @@ int max_coresident_group_table(int path, int mt, int cbw, int mh, size_t lds)
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a)
 {
     const int cbs_max = (a.ncb + a.G - 1) / a.G;
-    return lds_plan(path, mt, a.Np, cbs_max, a.j_lds, a.mh).total;
+    return lds_plan(path, mt, a.Np, cbs_max, a.j_lds, a.mh, a.inc).total;
 }
 
-template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool MH>
+template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool MH, bool INC = false>
 static hipError_t launch_mfma_t(const SweepArgs& a, size_t lds, hipStream_t st)
 {
     const unsigned grid = static_cast<unsigned>(GROUP ? a.ngroups * a.G : a.nblocks);
-    auto kern = k_sweep_mfma<PATH, MT, CBW, GROUP, JLDS, TRACE, false, MH>;
+    auto kern = k_sweep_mfma<PATH, MT, CBW, GROUP, JLDS, TRACE, false, MH, INC>;
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -1975,6 +2123,10 @@ static hipError_t launch_mfma_m(const SweepArgs& a, size_t lds, hipStream_t st)
     if constexpr (MT == 1 && CBW == 2)
         if (a.mh) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, true>(a, lds, st);
     if (a.mh) return hipErrorInvalidValue;
+    // flip-incremental variants: int8, one row tile, column split, J streamed
+    if constexpr (PATH == kPathI8 && MT == 1 && GROUP && !JLDS)
+        if (a.inc) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, false, true>(a, lds, st);
+    if (a.inc) return hipErrorInvalidValue;
     return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, false>(a, lds, st);
 }
 
@@ -2025,9 +2177,22 @@ static const void* group_kernel(int jlds, int trace)
                  : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, false, MH>);
 }
 
-template <int PATH>
-static const void* group_kernel_p(int mt, int cbw, int jlds, int trace, int mh)
+template <int PATH, int CBW>
+static const void* group_kernel_inc(int trace)
 {
+    if constexpr (PATH == kPathI8)
+        return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, true, false, false, true>)
+                     : reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, false, false, false, true>);
+    return nullptr;
+}
+
+template <int PATH>
+static const void* group_kernel_p(int mt, int cbw, int jlds, int trace, int mh, int inc)
+{
+    if (inc) {
+        if (mh || mt != 1 || jlds) return nullptr;
+        return cbw == 1 ? group_kernel_inc<PATH, 1>(trace) : group_kernel_inc<PATH, 2>(trace);
+    }
     if (mh) return (mt == 1 && cbw == 2) ? group_kernel<PATH, 1, 2, true>(jlds, trace) : nullptr;
     return mt == 1 ? (cbw == 1 ? group_kernel<PATH, 1, 1, false>(jlds, trace)
                                : group_kernel<PATH, 1, 2, false>(jlds, trace))
@@ -2035,15 +2200,15 @@ static const void* group_kernel_p(int mt, int cbw, int jlds, int trace, int mh)
                                : group_kernel<PATH, 2, 2, false>(jlds, trace));
 }
 
-// Workgroups of the group sweep variant (mt, cbw, jlds, trace, mh) that can
-// be resident on the device at once (0 if the variant does not exist).
-int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, size_t lds)
+// Workgroups of the group sweep variant (mt, cbw, jlds, trace, mh, inc) that
+// can be resident on the device at once (0 if the variant does not exist).
+int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, int inc, size_t lds)
 {
     int dev = 0, cus = 0, per = 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* f = path == kPathI8 ? group_kernel_p<kPathI8>(mt, cbw, jlds, trace, mh)
-                                    : group_kernel_p<kPathBf16>(mt, cbw, jlds, trace, mh);
+    const void* f = path == kPathI8 ? group_kernel_p<kPathI8>(mt, cbw, jlds, trace, mh, inc)
+                                    : group_kernel_p<kPathBf16>(mt, cbw, jlds, trace, mh, inc);
     if (!f) return 0;
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;

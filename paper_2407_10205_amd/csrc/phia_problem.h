@@ -23,6 +23,7 @@ struct Geometry {
     int xcd_map = 0;   // group members share blockIdx % 8 (one XCD)
     size_t lds = 0;    // dynamic LDS bytes per workgroup
     int mh = 0;        // LDS sized for the accept/reject step
+    int inc = 0;       // flip-incremental field update
 };
 
 phia_status fail(phia_status st, const char* fmt, ...);
@@ -69,6 +70,9 @@ struct phia_problem {
     // anneal
     bool started = false, has_run = false, trace = false;
     bool one_block_kernel = false;  // restrict geometries to k_sweep_mfma (server table launches)
+    int inc_mode = 1;               // flip-incremental field update where a variant exists
+    int inc_mode_geo = -1;          // inc_mode when the current state and geometry were set up
+    int64_t* dincstat = nullptr;    // [4] flip-incremental step counters of the current anneal
     int32_t R = 0;
     int64_t T = 0, k = 0, L = 1;
     float eps = 0.f, gamma = 0.f;

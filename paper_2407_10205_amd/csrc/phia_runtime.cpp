@@ -284,12 +284,22 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     a.G = G;
     a.j_lds = j_lds;
     a.mh = p->mh;
-    const size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
+    // flip-incremental field update where it has a variant: int8, one row
+    // tile, column split with J streamed, no accept/reject, own launch
+    a.inc = (p->inc_mode && p->path == PHIA_PATH_I8 && mt == 1 && G > 1 && !j_lds && !p->mh &&
+             !p->one_block_kernel && ncb <= 64 * kWaves)
+                ? 1
+                : 0;
+    size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
+    if (a.inc && lds > static_cast<size_t>(kLdsMax)) {
+        a.inc = 0;
+        lds = sweep_mfma_lds_bytes(p->path, mt, a);
+    }
     if (lds > static_cast<size_t>(kLdsMax)) return false;
     const int rows = 16 * mt, nblocks = (R + rows - 1) / rows;
     int ngroups = nblocks;
     if (G > 1) {
-        const int maxwg = max_coresident_mfma(p->path, mt, cbw, j_lds, p->trace ? 1 : 0, p->mh, lds);
+        const int maxwg = max_coresident_mfma(p->path, mt, cbw, j_lds, p->trace ? 1 : 0, p->mh, a.inc, lds);
         if (maxwg < G) return false;
         ngroups = std::min(nblocks, maxwg / G);
         if (ngroups >= 8) ngroups -= ngroups % 8;
@@ -306,6 +316,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     if (!pick_xcd(p, G, ngroups, j_lds, xcd, g.xcd_map)) return false;
     g.lds = lds;
     g.mh = p->mh;
+    g.inc = a.inc;
     return true;
 }
 
@@ -393,11 +404,12 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         }
     }
     if (p->tuned.ok && p->tuned_R == R) {
-        if (p->tuned.mh == p->mh) {
+        if (p->tuned.mh == p->mh && p->tuned.kind != 0) {
             p->geo = p->tuned;
             return;
         }
-        // tuned without (or with) the accept/reject step: same shape, LDS redone
+        // same shape; LDS and variant redone for the current accept/reject
+        // step and flip-incremental setting
         Geometry g;
         if (p->tuned.kind == 0 &&
             make_geometry(p, R, p->tuned.mt, p->tuned.cbw, p->tuned.G, p->tuned.j_lds, g, p->tuned.xcd_map)) {
@@ -483,6 +495,8 @@ SweepArgs sweep_args(const phia_problem* p)
     a.ngroups = p->geo.ngroups;
     a.xcd_map = p->geo.xcd_map;
     a.j_lds = p->geo.j_lds;
+    a.inc = p->geo.inc;
+    a.incstat = p->dincstat;
     a.xbits = p->dxbits;
     a.pbuf = p->dpbuf;
     a.seq_base = p->seq;
@@ -633,6 +647,7 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
         (e = dalloc(reinterpret_cast<void**>(&p->dh64), sizeof(double) * N, cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->derr), sizeof(int32_t) * 4, cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dscratch), 64, cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dincstat), 4 * sizeof(int64_t), cnt)) != hipSuccess ||
         (!j4.empty() && (e = dalloc(reinterpret_cast<void**>(&p->dJ4), j4.size(), cnt)) != hipSuccess)) {
         phia_destroy(p);
         return fail(PHIA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
@@ -670,6 +685,7 @@ void phia_destroy(phia_problem* p)
     dfree(p->dh64);
     dfree(p->derr);
     dfree(p->dscratch);
+    dfree(p->dincstat);
     delete p;
 }
 
@@ -761,8 +777,10 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
         if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
     }
     const int mh = s->metropolis ? 1 : 0;
-    reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr) && p->mh == mh;
+    reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr) && p->mh == mh &&
+            p->inc_mode_geo == p->inc_mode;
     if (!reuse) free_state(p);
+    p->inc_mode_geo = p->inc_mode;
     p->R = replicas;
     p->T = steps;
     p->k = 0;
@@ -840,6 +858,8 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     // ctab is a pageable host vector; make the copy complete before it goes out of scope.
     hipError_t e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(p, e, "schedule upload");
+    if ((e = hipMemsetAsync(p->dincstat, 0, 4 * sizeof(int64_t), p->st)) != hipSuccess)
+        return hip_fail(p, e, "counter reset");
     size_t* cnt = &p->state_bytes;
     if (reuse) {
         if ((st = setup_mh_geometry(p)) != PHIA_OK) return st;
@@ -1218,12 +1238,37 @@ phia_status phia_get_info(const phia_problem* p, phia_info* out)
     out->replicas = p->R;
     out->rows_per_block = p->geo.rows;
     out->j_in_lds = p->geo.j_lds;
+    out->incremental = p->geo.inc;
     out->sweep_kernel = p->geo.kind;
     out->steps = p->T;
     out->step = p->k;
     out->max_abs_J = p->maxabsJ;
     out->device_bytes = p->base_bytes + p->state_bytes;
     out->group_on_one_xcd = p->geo.G > 1 ? p->geo.xcd_map : 0;
+    return PHIA_OK;
+}
+
+phia_status phia_incremental_stats(phia_problem* p, int64_t* out)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!out) return fail(PHIA_EINVAL, "null argument");
+    if (!p->started) return fail(PHIA_ESTATE, "phia_anneal_start has not been called");
+    hipError_t e = hipSetDevice(p->dev);
+    if (e == hipSuccess) e = hipMemcpyAsync(out, p->dincstat, 3 * sizeof(int64_t), hipMemcpyDeviceToHost, p->st);
+    if (e == hipSuccess) e = p->st ? hipStreamSynchronize(p->st) : hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(p, e, "counter read");
+    return PHIA_OK;
+}
+
+phia_status phia_set_incremental(phia_problem* p, int32_t on)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (on != 0 && on != 1) return fail(PHIA_EINVAL, "incremental must be 0 or 1 (got %d)", on);
+    p->inc_mode = on;
     return PHIA_OK;
 }
 

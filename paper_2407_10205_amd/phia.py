@@ -27,7 +27,7 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
 # Every symbol declared in include/phia.h.
 EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_replica_mh", "phia_get_state",
-           "phia_set_state", "phia_get_info", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
+           "phia_set_state", "phia_get_info", "phia_set_incremental", "phia_incremental_stats", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
            "phia_batch_run", "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
            "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
            "phia_destroy", "phia_last_error", "phia_version")
@@ -69,7 +69,8 @@ class Info(C.Structure):
                 ("exact", C.c_int32), ("group", C.c_int32), ("replicas", C.c_int32),
                 ("rows_per_block", C.c_int32), ("j_in_lds", C.c_int32), ("sweep_kernel", C.c_int32),
                 ("steps", C.c_int64), ("step", C.c_int64),
-                ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t), ("group_on_one_xcd", C.c_int32)]
+                ("max_abs_J", C.c_int64), ("device_bytes", C.c_size_t), ("group_on_one_xcd", C.c_int32),
+                ("incremental", C.c_int32)]
 
 
 def _declare(lib):
@@ -90,6 +91,8 @@ def _declare(lib):
         "phia_get_info": [P, P],
         "phia_autotune": [P, I32, I64, P],
         "phia_set_trace": [P, I32],
+        "phia_set_incremental": [P, I32],
+        "phia_incremental_stats": [P, P],
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
         "phia_batch_run": [P, I32, P, P, P, P],
@@ -202,6 +205,17 @@ class Problem:
     # -- anneal
     def set_trace(self, enable=True):
         _check(lib().phia_set_trace(self._p, 1 if enable else 0))
+
+    def set_incremental(self, on=True):
+        """Flip-incremental J.s update where the sweep has it (identical results)."""
+        _check(lib().phia_set_incremental(self._p, 1 if on else 0))
+
+    def incremental_stats(self):
+        """(incremental steps, full-product steps, k blocks of the incremental
+        products) since the anneal started, summed over replica blocks."""
+        out = (C.c_int64 * 3)()
+        _check(lib().phia_incremental_stats(self._p, out))
+        return tuple(int(v) for v in out)
 
     def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
               deriv="tanh", mh=None):

@@ -75,6 +75,9 @@ def test_null_and_size_arguments(phia):
     assert L.phia_create(J.ctypes.data_as(C.c_void_p), None, 20000, None, C.byref(p)) == -1
     assert L.phia_create(J.ctypes.data_as(C.c_void_p), None, 2, None, None) == -1
     assert L.phia_sync(None) == -1
+    assert L.phia_set_incremental(None, 1) == -1
+    out = (C.c_int64 * 3)()
+    assert L.phia_incremental_stats(None, out) == -1
     L.phia_destroy(None)
 
 

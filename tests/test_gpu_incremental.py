@@ -1,0 +1,148 @@
+"""GPU parity of the flip-incremental field update against the full product
+and the CPU oracle, through the C ABI.
+
+Between consecutive steps only the spins whose sign changed alter the field
+I = J s + h of Eq. 6, so I(k) = I(k-1) + J (s(k) - s(k-1)).  The sweep keeps
+J s in int32 registers and adds the product over the 16-spin column blocks
+that changed, or recomputes it in full when too many did.  Both are exact
+integer arithmetic, so every output must be bit-identical with the setting
+on and off, and to the oracle (which recomputes J s every step).
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2407_10205_amd import instances as inst
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def P():
+    from paper_2407_10205_amd import phia
+    phia.lib()
+    return phia
+
+
+def int_units(J, h, f):
+    return (np.rint(J * 2**f).astype(np.int32), np.rint(h * 2**f).astype(np.int32))
+
+
+def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=None):
+    say(f"case N={J.shape[0]} geometry={geometry} inc={inc} R={R} T={T} chunk={chunk} trace={trace}")
+    os.environ["PHIA_GEOMETRY"] = geometry
+    try:
+        p = P.Problem(J, h, frac_bits=f, path="i8")
+        p.set_incremental(inc)
+        if trace:
+            p.set_trace(True)
+        if chunk is None:
+            p.anneal(R, T, 0.2, 1.0, beta0=b0, beta1=b1, refresh_L=L, seed=seed)
+        else:
+            p.start(R, T, 0.2, 1.0, beta0=b0, beta1=b1, refresh_L=L, seed=seed)
+            for k in range(chunk, T + chunk, chunk):
+                p.run(min(k, T))
+            p.sync()
+    finally:
+        del os.environ["PHIA_GEOMETRY"]
+    E, S, K = p.replica_best()
+    x, v, _ = p.get_state()
+    out = dict(E=E, S=S, K=K, x=x, v=v, info=p.info(), stats=p.incremental_stats(),
+               trace=p.trace(T) if trace else None)
+    p.close()
+    say("  info", out["info"]["group"], out["info"]["incremental"], "stats", out["stats"])
+    return out
+
+
+def same(a, b):
+    for key in ("E", "S", "K", "x", "v", "trace"):
+        if a[key] is None:
+            continue
+        u, w = a[key], b[key]
+        if u.dtype.kind == "f":
+            u, w = u.view(np.uint32), w.view(np.uint32)
+        assert np.array_equal(u, w), key
+
+
+def oracle_check(O, dev, J, h, f, T, b0, b1, L, seed, rows, trace=False):
+    Ji, hi = int_units(J, h, f)
+    betas = O.beta_linear(b0, b1, T)
+    for r in rows:
+        o = O.anneal(Ji, hi, f, 1, betas, 0.2, 1.0, L, seed, r0=r, trace=trace)
+        assert np.array_equal(dev["x"][r].view(np.uint32), o.x[0].view(np.uint32)), f"x replica {r}"
+        assert np.array_equal(dev["v"][r].view(np.uint32), o.v[0].view(np.uint32)), f"v replica {r}"
+        assert dev["E"][r] == o.bestE[0] and dev["K"][r] == o.bestStep[0], f"record replica {r}"
+        assert np.array_equal(dev["S"][r], o.bestS[0]), f"bestS replica {r}"
+        if trace:
+            assert np.array_equal(dev["trace"][r], o.Etrace[0]), f"trace replica {r}"
+
+
+@pytest.mark.parametrize("geometry", ["1,8,0,1", "1,8,0,2", "1,4,0,2", "1,2,0,2,0"])
+def test_incremental_equals_full_and_oracle(P, O, geometry):
+    """Ragged N (20 column blocks over the group), ragged R (last block 8 of
+    16 rows), energy traces on; a schedule that ends cold, so that early steps
+    take the full product and late ones the incremental one."""
+    J, h = inst.sk_gauss_fixed(300, 21, frac_bits=5, bits=8)
+    R, T, b0, b1, L, seed = 40, 400, 0.05, 3.0, 25, 17
+    on = run(P, J, h, 5, geometry, True, R, T, b0, b1, L, seed, trace=True)
+    off = run(P, J, h, 5, geometry, False, R, T, b0, b1, L, seed, trace=True)
+    assert on["info"]["incremental"] == 1 and off["info"]["incremental"] == 0
+    n_inc, n_full, n_kb = on["stats"]
+    blocks = (R + 15) // 16
+    assert n_inc + n_full == blocks * T
+    assert n_inc > 0 and n_full >= blocks, "both products must run"
+    assert n_kb < n_inc * (320 // 64), "incremental steps use fewer k blocks than the full product"
+    assert off["stats"] == (0, 0, 0)
+    same(on, off)
+    oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(0, 17, 39), trace=True)
+
+
+def test_incremental_chunked_launches(P, O):
+    """Launch boundaries (every launch starts with the full product) do not
+    change anything."""
+    J, h = inst.sk_gauss_fixed(500, 3, frac_bits=4, bits=8)
+    R, T, b0, b1, L, seed = 64, 300, 0.05, 2.5, 20, 5
+    one = run(P, J, h, 4, "1,8,0,2", True, R, T, b0, b1, L, seed)
+    chunked = run(P, J, h, 4, "1,8,0,2", True, R, T, b0, b1, L, seed, chunk=37)
+    off = run(P, J, h, 4, "1,8,0,2", False, R, T, b0, b1, L, seed, chunk=37)
+    same(one, chunked)
+    same(one, off)
+    n_inc, n_full, _ = chunked["stats"]
+    launches = -(-T // 37)
+    assert n_full >= launches * (R // 16) and n_inc > 0
+    oracle_check(O, one, J, h, 4, T, b0, b1, L, seed, rows=(0, 63))
+
+
+def test_incremental_sk2000_shape(P, O):
+    """The SK N = 2000 shape (32 k blocks of 64) with the group of its
+    workload (8 members, member m of every group on XCD m), sampled against
+    the oracle."""
+    J, h = inst.sk_gauss_fixed(2000, 0, frac_bits=5, bits=8)
+    R, T, b0, b1, L, seed = 32, 600, 0.02, 3.0, 25, 11
+    on = run(P, J, h, 5, "1,8,0,2,0", True, R, T, b0, b1, L, seed)
+    off = run(P, J, h, 5, "1,8,0,2,0", False, R, T, b0, b1, L, seed)
+    same(on, off)
+    n_inc, n_full, n_kb = on["stats"]
+    assert n_inc > 0 and n_kb < n_inc * 32
+    oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(0, 31))
+
+
+def test_incremental_size_limit(P, O):
+    """N = 4864 is the largest int8 instance whose LDS holds the incremental
+    bookkeeping; 64 spins more fall back to the full product."""
+    for N, want in ((4864, 1), (4928, 0)):
+        J, h = inst.sk_gauss_fixed(N, 1, frac_bits=5, bits=8)
+        R, T, b0, b1, L, seed = 16, 40, 0.05, 3.0, 10, 2
+        on = run(P, J, h, 5, "1,32,0,2", True, R, T, b0, b1, L, seed)
+        assert on["info"]["incremental"] == want
+        if want:
+            off = run(P, J, h, 5, "1,32,0,2", False, R, T, b0, b1, L, seed)
+            same(on, off)
+            oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(15,))
