@@ -200,10 +200,10 @@ phia_status phia_get_info(const phia_problem* p, phia_info* out);
  * that changed in any replica of a 16-replica block, falling back to the
  * full product when that covers more than 2/3 of it.  Integer arithmetic
  * makes both identical bit for bit, so results do not depend on the
- * setting.  It applies where the sweep has such a variant: the I8 path, a
- * column-split group of one-row-tile blocks with J streamed from L2, no
- * accept/reject step, an anneal of its own (not a batch or server launch),
- * N <= 4864 (the LDS holds the bookkeeping);
+ * setting.  It applies where the sweep has such a variant: the I8 or
+ * BF16HILO path, a column-split group of one-row-tile blocks with J streamed
+ * from L2, no accept/reject step, an anneal of its own (not a batch or server
+ * launch), and on I8 N <= 4864 (the LDS holds the bookkeeping);
  * phia_info.incremental reports whether the current geometry uses it.
  * on = 0 always computes the full product.  Takes effect at the next
  * phia_anneal_start or phia_anneal.  PHIA_EINVAL if on is not 0 or 1. */

@@ -44,7 +44,7 @@ struct SweepArgs {
     int32_t ngroups;            // concurrently running groups
     int32_t xcd_map;            // 1: group members share blockIdx % 8
     int32_t j_lds;              // 1: J slice resident in LDS, 0: read from global
-    int32_t inc;                // 1: flip-incremental field update (int8, column split, J streamed)
+    int32_t inc;                // 1: flip-incremental field update (column split, J streamed)
     int64_t* incstat;           // [3] incremental steps, full-product steps, k blocks of the
                                 //     incremental products (member 0 of every group), or null
     // group exchange (G > 1)

@@ -732,6 +732,70 @@ __device__ __forceinline__ void quasi_gradient_inc(const unsigned char* Sn, cons
     }
 }
 
+// BF16 hi/lo form of quasi_gradient_inc: a 32-wide k chunk holds two listed
+// column blocks (lane groups 0-1 and 2-3 take their halves); dS = +-2 or 0
+// is exact in bf16, and the hi and lo planes of each incremental step start
+// from zero, so acc += 256 hi + lo stays the exact integer J s.
+template <int CBW, int NCW>
+__device__ __forceinline__ void quasi_gradient_inc_bf16(const unsigned char* Sn, const unsigned char* So,
+                                                        uint32_t srow, const unsigned char* Jw, size_t cw_stride,
+                                                        const uint16_t* list, int nf, int lr, int lg,
+                                                        v4i (&acc)[CBW])
+{
+    const int nvk = (nf + 1) >> 1;
+    const int h = lg & 1;
+    auto load = [&](int vk, v4i& d, v4i (&H)[NCW], v4i (&Lo)[NCW]) {
+        const int e = 2 * vk + (lg >> 1);
+        const bool ok = e < nf;
+        const int c = ok ? list[e] : 0;
+        const v4i sn = *reinterpret_cast<const v4i*>(Sn + lr * srow + 32 * c + 16 * h);
+        const v4i so = *reinterpret_cast<const v4i*>(So + lr * srow + 32 * c + 16 * h);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            // halves are 0x3f80 (+1) or 0xbf80 (-1): +-2 (0x4000 / 0xc000) where the sign changed
+            const uint32_t n = static_cast<uint32_t>(sn[t]), o = static_cast<uint32_t>(so[t]);
+            const uint32_t m = ((n ^ o) >> 15) * 0xffffu;
+            d[t] = ok ? static_cast<int>(((n & 0x80008000u) | 0x40004000u) & m) : 0;
+        }
+        const size_t off = static_cast<size_t>(c >> 1) * 2048 +
+                           static_cast<size_t>(((2 * (c & 1) + h) * 16 + lr) * 16);
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) {
+            H[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + off);
+            Lo[cw] = *reinterpret_cast<const v4i*>(Jw + cw * cw_stride + off + 1024);
+        }
+    };
+    if (nvk == 0) return;
+    v4f ahi[NCW], alo[NCW];
+#pragma unroll
+    for (int cw = 0; cw < NCW; ++cw) {
+        ahi[cw] = v4f{0.f, 0.f, 0.f, 0.f};
+        alo[cw] = v4f{0.f, 0.f, 0.f, 0.f};
+    }
+    v4i dn, Hn[NCW], Ln[NCW];
+    load(0, dn, Hn, Ln);
+    for (int vk = 0; vk < nvk; ++vk) {
+        const v8bf A = __builtin_bit_cast(v8bf, dn);
+        v4i H[NCW], Lo[NCW];
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) {
+            H[cw] = Hn[cw];
+            Lo[cw] = Ln[cw];
+        }
+        if (vk + 1 < nvk) load(vk + 1, dn, Hn, Ln);
+#pragma unroll
+        for (int cw = 0; cw < NCW; ++cw) {
+            ahi[cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(v8bf, H[cw]), ahi[cw], 0, 0, 0);
+            alo[cw] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A, __builtin_bit_cast(v8bf, Lo[cw]), alo[cw], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int cw = 0; cw < NCW; ++cw)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            acc[cw][j] += 256 * static_cast<int>(ahi[cw][j]) + static_cast<int>(alo[cw][j]);
+}
+
 // One column block and one row tile per wave: registers are capped at 128 so two
 // workgroups share a CU and hide each other's exchange latency.
 // BATCH: each workgroup runs one work item of a table, with the J placement
@@ -753,8 +817,8 @@ k_sweep_mfma(SweepArgs args)
     constexpr int NE = MT * CBW * 4;  // owned elements per lane
     static_assert(NE <= 32, "previous-sign mask holds 32 elements");
     static_assert(kWaves * NE * 8 <= 16 * MT * 80, "ballot staging fits in one S buffer");
-    static_assert(!INC || (PATH == kPathI8 && MT == 1 && GROUP && !BATCH && !MH),
-                  "flip-incremental variant: int8, one row tile, column split, no accept/reject");
+    static_assert(!INC || (MT == 1 && GROUP && !BATCH && !MH),
+                  "flip-incremental variant: one row tile, column split, no accept/reject");
     extern __shared__ __align__(16) unsigned char lds[];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -1249,7 +1313,7 @@ k_sweep_mfma(SweepArgs args)
                         if ((b >> lane) & 1u) sLw[pos] = static_cast<uint16_t>(c0 + lane);
                         nf += __popcll(b);
                     }
-                    incr = 3 * ((nf + 3) >> 2) <= 2 * (Np / 64);
+                    incr = 3 * ((nf + 3) >> 2) <= 2 * (Np / 64);  // 64-wide k blocks on both paths
                     n_inc += incr ? 1u : 0u;
                     n_kb += incr ? static_cast<uint64_t>((nf + 3) >> 2) : 0u;
                     if (incr) {
@@ -1258,10 +1322,19 @@ k_sweep_mfma(SweepArgs args)
                         const unsigned char* So = lds + P.s_off + (par ^ 1) * P.s_bytes;
                         const unsigned char* Jw = Jg + static_cast<size_t>(wave) * cbb;
                         const size_t cws = static_cast<size_t>(kWaves) * cbb;
-                        if (CBW >= 2 && ncw >= 2)
-                            quasi_gradient_inc<CBW, (CBW >= 2 ? 2 : 1)>(S, So, srow, Jw, cws, sLw, nf, lr, lg, accI);
-                        else if (ncw >= 1)
-                            quasi_gradient_inc<CBW, 1>(S, So, srow, Jw, cws, sLw, nf, lr, lg, accI);
+                        if (PATH == kPathI8) {
+                            if (CBW >= 2 && ncw >= 2)
+                                quasi_gradient_inc<CBW, (CBW >= 2 ? 2 : 1)>(S, So, srow, Jw, cws, sLw, nf, lr, lg,
+                                                                            accI);
+                            else if (ncw >= 1)
+                                quasi_gradient_inc<CBW, 1>(S, So, srow, Jw, cws, sLw, nf, lr, lg, accI);
+                        } else {
+                            if (CBW >= 2 && ncw >= 2)
+                                quasi_gradient_inc_bf16<CBW, (CBW >= 2 ? 2 : 1)>(S, So, srow, Jw, cws, sLw, nf, lr,
+                                                                                 lg, accI);
+                            else if (ncw >= 1)
+                                quasi_gradient_inc_bf16<CBW, 1>(S, So, srow, Jw, cws, sLw, nf, lr, lg, accI);
+                        }
 #pragma unroll
                         for (int cw = 0; cw < CBW; ++cw)
 #pragma unroll
@@ -2123,8 +2196,8 @@ static hipError_t launch_mfma_m(const SweepArgs& a, size_t lds, hipStream_t st)
     if constexpr (MT == 1 && CBW == 2)
         if (a.mh) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, true>(a, lds, st);
     if (a.mh) return hipErrorInvalidValue;
-    // flip-incremental variants: int8, one row tile, column split, J streamed
-    if constexpr (PATH == kPathI8 && MT == 1 && GROUP && !JLDS)
+    // flip-incremental variants: one row tile, column split, J streamed
+    if constexpr (MT == 1 && GROUP && !JLDS)
         if (a.inc) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, false, true>(a, lds, st);
     if (a.inc) return hipErrorInvalidValue;
     return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, false>(a, lds, st);
@@ -2180,10 +2253,8 @@ static const void* group_kernel(int jlds, int trace)
 template <int PATH, int CBW>
 static const void* group_kernel_inc(int trace)
 {
-    if constexpr (PATH == kPathI8)
-        return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, true, false, false, true>)
-                     : reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, false, false, false, true>);
-    return nullptr;
+    return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, true, false, false, true>)
+                 : reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, false, false, false, true>);
 }
 
 template <int PATH>

@@ -286,7 +286,7 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     a.mh = p->mh;
     // flip-incremental field update where it has a variant: int8, one row
     // tile, column split with J streamed, no accept/reject, own launch
-    a.inc = (p->inc_mode && p->path == PHIA_PATH_I8 && mt == 1 && G > 1 && !j_lds && !p->mh &&
+    a.inc = (p->inc_mode && p->path != PHIA_PATH_FP32 && mt == 1 && G > 1 && !j_lds && !p->mh &&
              !p->one_block_kernel && ncb <= 64 * kWaves)
                 ? 1
                 : 0;

@@ -35,11 +35,11 @@ def int_units(J, h, f):
     return (np.rint(J * 2**f).astype(np.int32), np.rint(h * 2**f).astype(np.int32))
 
 
-def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=None):
-    say(f"case N={J.shape[0]} geometry={geometry} inc={inc} R={R} T={T} chunk={chunk} trace={trace}")
+def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=None, path="i8"):
+    say(f"case N={J.shape[0]} path={path} geometry={geometry} inc={inc} R={R} T={T} chunk={chunk} trace={trace}")
     os.environ["PHIA_GEOMETRY"] = geometry
     try:
-        p = P.Problem(J, h, frac_bits=f, path="i8")
+        p = P.Problem(J, h, frac_bits=f, path=path)
         p.set_incremental(inc)
         if trace:
             p.set_trace(True)
@@ -84,15 +84,22 @@ def oracle_check(O, dev, J, h, f, T, b0, b1, L, seed, rows, trace=False):
             assert np.array_equal(dev["trace"][r], o.Etrace[0]), f"trace replica {r}"
 
 
+PATHS = {"i8": (5, 8), "bf16hilo": (12, 16)}  # path: (frac_bits, coupling bits) of the SK instances
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
 @pytest.mark.parametrize("geometry", ["1,8,0,1", "1,8,0,2", "1,4,0,2", "1,2,0,2,0"])
-def test_incremental_equals_full_and_oracle(P, O, geometry):
+def test_incremental_equals_full_and_oracle(P, O, geometry, path):
     """Ragged N (20 column blocks over the group), ragged R (last block 8 of
     16 rows), energy traces on; a schedule that ends cold, so that early steps
-    take the full product and late ones the incremental one."""
-    J, h = inst.sk_gauss_fixed(300, 21, frac_bits=5, bits=8)
-    R, T, b0, b1, L, seed = 40, 400, 0.05, 3.0, 25, 17
-    on = run(P, J, h, 5, geometry, True, R, T, b0, b1, L, seed, trace=True)
-    off = run(P, J, h, 5, geometry, False, R, T, b0, b1, L, seed, trace=True)
+    take the full product and late ones the incremental one.  BF16 hi/lo with
+    16-bit couplings, both planes non-zero."""
+    f, bits = PATHS[path]
+    J, h = inst.sk_gauss_fixed(300, 21, frac_bits=f, bits=bits)
+    R, T, b0, b1, L, seed = 40, 400, 0.05 * 2.0 ** (f - 5), 3.0 * 2.0 ** (f - 5), 25, 17
+    on = run(P, J, h, f, geometry, True, R, T, b0, b1, L, seed, trace=True, path=path)
+    off = run(P, J, h, f, geometry, False, R, T, b0, b1, L, seed, trace=True, path=path)
+    assert on["info"]["path_name"] == path
     assert on["info"]["incremental"] == 1 and off["info"]["incremental"] == 0
     n_inc, n_full, n_kb = on["stats"]
     blocks = (R + 15) // 16
@@ -101,7 +108,7 @@ def test_incremental_equals_full_and_oracle(P, O, geometry):
     assert n_kb < n_inc * (320 // 64), "incremental steps use fewer k blocks than the full product"
     assert off["stats"] == (0, 0, 0)
     same(on, off)
-    oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(0, 17, 39), trace=True)
+    oracle_check(O, on, J, h, f, T, b0, b1, L, seed, rows=(0, 17, 39), trace=True)
 
 
 def test_incremental_chunked_launches(P, O):
@@ -120,29 +127,37 @@ def test_incremental_chunked_launches(P, O):
     oracle_check(O, one, J, h, 4, T, b0, b1, L, seed, rows=(0, 63))
 
 
-def test_incremental_sk2000_shape(P, O):
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_incremental_sk2000_shape(P, O, path):
     """The SK N = 2000 shape (32 k blocks of 64) with the group of its
-    workload (8 members, member m of every group on XCD m), sampled against
-    the oracle."""
-    J, h = inst.sk_gauss_fixed(2000, 0, frac_bits=5, bits=8)
-    R, T, b0, b1, L, seed = 32, 600, 0.02, 3.0, 25, 11
-    on = run(P, J, h, 5, "1,8,0,2,0", True, R, T, b0, b1, L, seed)
-    off = run(P, J, h, 5, "1,8,0,2,0", False, R, T, b0, b1, L, seed)
+    workloads (8 members, member m of every group on XCD m), 8- and 16-bit
+    couplings, sampled against the oracle."""
+    f, bits = PATHS[path]
+    J, h = inst.sk_gauss_fixed(2000, 0, frac_bits=f, bits=bits)
+    R, T, b0, b1, L, seed = 32, 600, 0.02 * 2.0 ** (f - 5), 3.0 * 2.0 ** (f - 5), 25, 11
+    on = run(P, J, h, f, "1,8,0,2,0", True, R, T, b0, b1, L, seed, path=path)
+    off = run(P, J, h, f, "1,8,0,2,0", False, R, T, b0, b1, L, seed, path=path)
     same(on, off)
     n_inc, n_full, n_kb = on["stats"]
-    assert n_inc > 0 and n_kb < n_inc * 32
-    oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(0, 31))
+    assert on["info"]["incremental"] == 1 and n_inc > 0 and n_kb < n_inc * 32
+    oracle_check(O, on, J, h, f, T, b0, b1, L, seed, rows=(0, 31))
 
 
-def test_incremental_size_limit(P, O):
-    """N = 4864 is the largest int8 instance whose LDS holds the incremental
-    bookkeeping; 64 spins more fall back to the full product."""
-    for N, want in ((4864, 1), (4928, 0)):
-        J, h = inst.sk_gauss_fixed(N, 1, frac_bits=5, bits=8)
-        R, T, b0, b1, L, seed = 16, 40, 0.05, 3.0, 10, 2
-        on = run(P, J, h, 5, "1,32,0,2", True, R, T, b0, b1, L, seed)
+@pytest.mark.parametrize("path,N_max,N_off", [("i8", 4864, 4928), ("bf16hilo", 2496, None)])
+def test_incremental_size_limit(P, O, path, N_max, N_off):
+    """The largest instance whose LDS holds the incremental bookkeeping: int8
+    N = 4864 (64 spins more fall back to the full product), BF16 hi/lo up to
+    its path limit 2496."""
+    f, bits = PATHS[path]
+    for N, want in ((N_max, 1), (N_off, 0)):
+        if N is None:
+            continue
+        J, h = inst.sk_gauss_fixed(N, 1, frac_bits=f, bits=bits)
+        R, T, b0, b1, L, seed = 16, 40, 0.05 * 2.0 ** (f - 5), 3.0 * 2.0 ** (f - 5), 10, 2
+        geo = "1,32,0,2" if path == "i8" else "1,16,0,2"
+        on = run(P, J, h, f, geo, True, R, T, b0, b1, L, seed, path=path)
         assert on["info"]["incremental"] == want
         if want:
-            off = run(P, J, h, 5, "1,32,0,2", False, R, T, b0, b1, L, seed)
+            off = run(P, J, h, f, geo, False, R, T, b0, b1, L, seed, path=path)
             same(on, off)
-            oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(15,))
+            oracle_check(O, on, J, h, f, T, b0, b1, L, seed, rows=(15,))
