@@ -32,7 +32,9 @@
 //                  Batch mode: one work item (instance, replica block) per
 //                  workgroup from a table; with GROUP, several column-split
 //                  instances in one cooperative launch.  MH: the accept/reject
-//                  step.
+//                  step.  INC (column split, J streamed): J.s kept across
+//                  steps and updated over the column blocks whose signs
+//                  changed, I(k) = I(k-1) + J (s(k) - s(k-1)), exact.
 //   k_sweep_pp     the column-split int8 sweep with two 16-replica sub-blocks
 //                  per workgroup on two wave teams one phase apart, so the
 //                  exchange of one sub-block hides behind the compute of the

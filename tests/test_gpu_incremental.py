@@ -161,3 +161,18 @@ def test_incremental_size_limit(P, O, path, N_max, N_off):
             off = run(P, J, h, f, geo, False, R, T, b0, b1, L, seed, path=path)
             same(on, off)
             oracle_check(O, on, J, h, f, T, b0, b1, L, seed, rows=(15,))
+
+
+def test_incremental_several_blocks_per_group(P, O):
+    """More replica blocks than concurrent groups (G = 64 leaves room for 4
+    groups on 256 CUs, 80 replicas make 5 blocks): a group's second block
+    starts from a full product again."""
+    J, h = inst.sk_gauss_fixed(1024, 7, frac_bits=5, bits=8)
+    R, T, b0, b1, L, seed = 80, 200, 0.05, 3.0, 25, 9
+    on = run(P, J, h, 5, "1,64,0,2", True, R, T, b0, b1, L, seed)
+    off = run(P, J, h, 5, "1,64,0,2", False, R, T, b0, b1, L, seed)
+    assert on["info"]["group"] == 64 and on["info"]["incremental"] == 1
+    same(on, off)
+    n_inc, n_full, _ = on["stats"]
+    assert n_inc + n_full == (R // 16) * T and n_inc > 0
+    oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(0, 64, 79))
