@@ -194,19 +194,21 @@ phia_status phia_get_info(const phia_problem* p, phia_info* out);
 /* Flip-incremental quasi-gradient (an execution strategy; not part of the
  * paper's method).  Between consecutive steps only the spins whose sign
  * changed alter I = J s + h of Eq. 6: I(k) = I(k-1) + J (s(k) - s(k-1)), with
- * s(k) - s(k-1) = +-2 on the changed spins and 0 elsewhere.  With on = 1
- * (the default) the sweep keeps J s in registers and, at every step after
- * the first of a launch, adds the product over the 16-spin column blocks
- * that changed in any replica of a 16-replica block, falling back to the
- * full product when that covers more than 2/3 of it.  Integer arithmetic
- * makes both identical bit for bit, so results do not depend on the
- * setting.  It applies where the sweep has such a variant: the I8 or
- * BF16HILO path, a column-split group of one-row-tile blocks with J streamed
- * from L2, no accept/reject step, an anneal of its own (not a batch or server
- * launch), and on I8 N <= 4864 (the LDS holds the bookkeeping);
- * phia_info.incremental reports whether the current geometry uses it.
- * on = 0 always computes the full product.  Takes effect at the next
- * phia_anneal_start or phia_anneal.  PHIA_EINVAL if on is not 0 or 1. */
+ * s(k) - s(k-1) = +-2 on the changed spins and 0 elsewhere.  With it on, the
+ * sweep keeps J s in registers and, at every step after the first of a
+ * launch, adds the product over the 16-spin column blocks that changed in
+ * any replica of a 16-replica block, falling back to the full product when
+ * that covers more than 2/3 of it.  Integer arithmetic makes both identical
+ * bit for bit, so results do not depend on the setting.  It applies where
+ * the sweep has such a variant: the I8 or BF16HILO path, a column-split
+ * group of one-row-tile blocks with J streamed from L2, an anneal of its own
+ * (not a batch or server launch), and on I8 N <= 4864 (the LDS holds the
+ * bookkeeping); phia_info.incremental reports whether the current geometry
+ * uses it.  on = 1: wherever it applies.  on = -1 (the default): likewise,
+ * except with the accept/reject step, whose rejections return whole replicas
+ * to their trajectory start, so that few steps qualify.  on = 0: always the
+ * full product.  Takes effect at the next phia_anneal_start or phia_anneal.
+ * PHIA_EINVAL if on is not -1, 0 or 1. */
 phia_status phia_set_incremental(phia_problem* p, int32_t on);
 
 /* Counters of the flip-incremental update since the last phia_anneal_start,

@@ -819,8 +819,7 @@ k_sweep_mfma(SweepArgs args)
     constexpr int NE = MT * CBW * 4;  // owned elements per lane
     static_assert(NE <= 32, "previous-sign mask holds 32 elements");
     static_assert(kWaves * NE * 8 <= 16 * MT * 80, "ballot staging fits in one S buffer");
-    static_assert(!INC || (MT == 1 && GROUP && !BATCH && !MH),
-                  "flip-incremental variant: one row tile, column split, no accept/reject");
+    static_assert(!INC || (MT == 1 && GROUP && !BATCH), "flip-incremental variant: one row tile, column split");
     extern __shared__ __align__(16) unsigned char lds[];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -2195,8 +2194,11 @@ template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE>
 static hipError_t launch_mfma_m(const SweepArgs& a, size_t lds, hipStream_t st)
 {
     // accept/reject variants exist for MT = 1, CBW = 2 only
-    if constexpr (MT == 1 && CBW == 2)
-        if (a.mh) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, true>(a, lds, st);
+    if constexpr (MT == 1 && CBW == 2) {
+        if constexpr (GROUP && !JLDS)
+            if (a.mh && a.inc) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, true, true>(a, lds, st);
+        if (a.mh && !a.inc) return launch_mfma_t<PATH, MT, CBW, GROUP, JLDS, TRACE, true>(a, lds, st);
+    }
     if (a.mh) return hipErrorInvalidValue;
     // flip-incremental variants: one row tile, column split, J streamed
     if constexpr (MT == 1 && GROUP && !JLDS)
@@ -2252,18 +2254,19 @@ static const void* group_kernel(int jlds, int trace)
                  : reinterpret_cast<const void*>(k_sweep_mfma<PATH, MT, CBW, true, false, false, false, MH>);
 }
 
-template <int PATH, int CBW>
+template <int PATH, int CBW, bool MH = false>
 static const void* group_kernel_inc(int trace)
 {
-    return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, true, false, false, true>)
-                 : reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, false, false, false, true>);
+    return trace ? reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, true, false, MH, true>)
+                 : reinterpret_cast<const void*>(k_sweep_mfma<PATH, 1, CBW, true, false, false, false, MH, true>);
 }
 
 template <int PATH>
 static const void* group_kernel_p(int mt, int cbw, int jlds, int trace, int mh, int inc)
 {
     if (inc) {
-        if (mh || mt != 1 || jlds) return nullptr;
+        if (mt != 1 || jlds) return nullptr;
+        if (mh) return cbw == 2 ? group_kernel_inc<PATH, 2, true>(trace) : nullptr;
         return cbw == 1 ? group_kernel_inc<PATH, 1>(trace) : group_kernel_inc<PATH, 2>(trace);
     }
     if (mh) return (mt == 1 && cbw == 2) ? group_kernel<PATH, 1, 2, true>(jlds, trace) : nullptr;

@@ -70,7 +70,7 @@ struct phia_problem {
     // anneal
     bool started = false, has_run = false, trace = false;
     bool one_block_kernel = false;  // restrict geometries to k_sweep_mfma (server table launches)
-    int inc_mode = 1;               // flip-incremental field update where a variant exists
+    int inc_mode = -1;              // flip-incremental update: -1 default, 0 off, 1 on where a variant exists
     int inc_mode_geo = -1;          // inc_mode when the current state and geometry were set up
     int64_t* dincstat = nullptr;    // [4] flip-incremental step counters of the current anneal
     int32_t R = 0;

@@ -284,10 +284,13 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
     a.G = G;
     a.j_lds = j_lds;
     a.mh = p->mh;
-    // flip-incremental field update where it has a variant: int8, one row
-    // tile, column split with J streamed, no accept/reject, own launch
-    a.inc = (p->inc_mode && p->path != PHIA_PATH_FP32 && mt == 1 && G > 1 && !j_lds && !p->mh &&
-             !p->one_block_kernel && ncb <= 64 * kWaves)
+    // flip-incremental field update where it has a variant: int8 or BF16
+    // hi/lo, one row tile, column split with J streamed, own launch
+    // (by default not with the accept/reject step: rejections return whole
+    // replicas to their trajectory start, so few steps qualify)
+    const bool want = p->inc_mode == 1 || (p->inc_mode < 0 && !p->mh);
+    a.inc = (want && p->path != PHIA_PATH_FP32 && mt == 1 && G > 1 && !j_lds && !p->one_block_kernel &&
+             ncb <= 64 * kWaves)
                 ? 1
                 : 0;
     size_t lds = sweep_mfma_lds_bytes(p->path, mt, a);
@@ -1267,7 +1270,7 @@ phia_status phia_set_incremental(phia_problem* p, int32_t on)
     clear_error();
     phia_status st = check_usable(p);
     if (st != PHIA_OK) return st;
-    if (on != 0 && on != 1) return fail(PHIA_EINVAL, "incremental must be 0 or 1 (got %d)", on);
+    if (on < -1 || on > 1) return fail(PHIA_EINVAL, "incremental must be -1, 0 or 1 (got %d)", on);
     p->inc_mode = on;
     return PHIA_OK;
 }

@@ -207,8 +207,10 @@ class Problem:
         _check(lib().phia_set_trace(self._p, 1 if enable else 0))
 
     def set_incremental(self, on=True):
-        """Flip-incremental J.s update where the sweep has it (identical results)."""
-        _check(lib().phia_set_incremental(self._p, 1 if on else 0))
+        """Flip-incremental J.s update where the sweep has it (identical
+        results): True, False, or None for the default (on, except with the
+        accept/reject step)."""
+        _check(lib().phia_set_incremental(self._p, -1 if on is None else 1 if on else 0))
 
     def incremental_stats(self):
         """(incremental steps, full-product steps, k blocks of the incremental

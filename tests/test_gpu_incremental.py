@@ -35,8 +35,9 @@ def int_units(J, h, f):
     return (np.rint(J * 2**f).astype(np.int32), np.rint(h * 2**f).astype(np.int32))
 
 
-def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=None, path="i8"):
-    say(f"case N={J.shape[0]} path={path} geometry={geometry} inc={inc} R={R} T={T} chunk={chunk} trace={trace}")
+def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=None, path="i8", mh=None):
+    say(f"case N={J.shape[0]} path={path} geometry={geometry} inc={inc} R={R} T={T} chunk={chunk} trace={trace} "
+        f"mh={mh}")
     os.environ["PHIA_GEOMETRY"] = geometry
     try:
         p = P.Problem(J, h, frac_bits=f, path=path)
@@ -44,9 +45,9 @@ def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=Non
         if trace:
             p.set_trace(True)
         if chunk is None:
-            p.anneal(R, T, 0.2, 1.0, beta0=b0, beta1=b1, refresh_L=L, seed=seed)
+            p.anneal(R, T, 0.2, 1.0, beta0=b0, beta1=b1, refresh_L=L, seed=seed, mh=mh)
         else:
-            p.start(R, T, 0.2, 1.0, beta0=b0, beta1=b1, refresh_L=L, seed=seed)
+            p.start(R, T, 0.2, 1.0, beta0=b0, beta1=b1, refresh_L=L, seed=seed, mh=mh)
             for k in range(chunk, T + chunk, chunk):
                 p.run(min(k, T))
             p.sync()
@@ -55,13 +56,16 @@ def run(P, J, h, f, geometry, inc, R, T, b0, b1, L, seed, trace=False, chunk=Non
     E, S, K = p.replica_best()
     x, v, _ = p.get_state()
     out = dict(E=E, S=S, K=K, x=x, v=v, info=p.info(), stats=p.incremental_stats(),
-               trace=p.trace(T) if trace else None)
+               trace=p.trace(T) if trace else None, mhc=p.replica_mh() if mh is not None else None)
     p.close()
     say("  info", out["info"]["group"], out["info"]["incremental"], "stats", out["stats"])
     return out
 
 
 def same(a, b):
+    if a["mhc"] is not None:
+        for u, w in zip(a["mhc"], b["mhc"]):
+            assert np.array_equal(u, w), "accept/reject counts"
     for key in ("E", "S", "K", "x", "v", "trace"):
         if a[key] is None:
             continue
@@ -71,11 +75,13 @@ def same(a, b):
         assert np.array_equal(u, w), key
 
 
-def oracle_check(O, dev, J, h, f, T, b0, b1, L, seed, rows, trace=False):
+def oracle_check(O, dev, J, h, f, T, b0, b1, L, seed, rows, trace=False, mh=None):
     Ji, hi = int_units(J, h, f)
     betas = O.beta_linear(b0, b1, T)
     for r in rows:
-        o = O.anneal(Ji, hi, f, 1, betas, 0.2, 1.0, L, seed, r0=r, trace=trace)
+        o = O.anneal(Ji, hi, f, 1, betas, 0.2, 1.0, L, seed, r0=r, trace=trace, mh=mh)
+        if mh is not None:
+            assert (dev["mhc"][0][r], dev["mhc"][1][r]) == (o.acc[0], o.dec[0]), f"accept/reject replica {r}"
         assert np.array_equal(dev["x"][r].view(np.uint32), o.x[0].view(np.uint32)), f"x replica {r}"
         assert np.array_equal(dev["v"][r].view(np.uint32), o.v[0].view(np.uint32)), f"v replica {r}"
         assert dev["E"][r] == o.bestE[0] and dev["K"][r] == o.bestStep[0], f"record replica {r}"
@@ -176,3 +182,25 @@ def test_incremental_several_blocks_per_group(P, O):
     n_inc, n_full, _ = on["stats"]
     assert n_inc + n_full == (R // 16) * T and n_inc > 0
     oracle_check(O, on, J, h, 5, T, b0, b1, L, seed, rows=(0, 64, 79))
+
+
+@pytest.mark.parametrize("path", sorted(PATHS))
+def test_incremental_with_accept_reject(P, O, path):
+    """The accept/reject step returns the rejected replicas to their
+    trajectory start, a change of many signs at once; the incremental update
+    (asked for explicitly: the default leaves it off with this step) sees it
+    like any other change.  Adaptive beta multiplier, ragged R."""
+    f, bits = PATHS[path]
+    J, h = inst.sk_gauss_fixed(300, 5, frac_bits=f, bits=bits)
+    R, T, b0, b1, L, seed, mh = 40, 300, 0.05 * 2.0 ** (f - 5), 3.0 * 2.0 ** (f - 5), 20, 3, (1.05, 0.95)
+    on = run(P, J, h, f, "1,4,0,2", True, R, T, b0, b1, L, seed, path=path, mh=mh, trace=True)
+    off = run(P, J, h, f, "1,4,0,2", False, R, T, b0, b1, L, seed, path=path, mh=mh, trace=True)
+    dflt = run(P, J, h, f, "1,4,0,2", None, R, T, b0, b1, L, seed, path=path, mh=mh, trace=True)
+    assert on["info"]["incremental"] == 1 and off["info"]["incremental"] == 0
+    assert dflt["info"]["incremental"] == 0, "the default leaves it off with the accept/reject step"
+    same(on, off)
+    same(on, dflt)
+    n_inc, n_full, _ = on["stats"]
+    assert n_inc > 0 and n_full > 0
+    assert on["mhc"][1].max() > 0, "decisions were taken"
+    oracle_check(O, on, J, h, f, T, b0, b1, L, seed, rows=(0, 39), trace=True, mh=mh)
