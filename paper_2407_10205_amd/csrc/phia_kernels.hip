@@ -146,6 +146,45 @@ __device__ __forceinline__ long long wave_sum16_i64(long long v)
 
 // Momentum draws happen once every L steps; a real call keeps the unrolled
 // sweep loops from holding many Philox states live at once.
+// Block-shared momentum draws.  One Philox block of the momentum stream,
+// (replica, columns 8 c8 .. 8 c8 + 7), yields the draws of those 8 columns;
+// each pair of its words gives two of them by Box-Muller exactly as
+// dev_gauss computes them (g[0] = cos draw, g[1] = sin draw).
+__device__ __forceinline__ void gauss_pair(uint64_t word, float& gc, float& gs)
+{
+    const float ua = dev_uniform(static_cast<uint32_t>(word));
+    const float ub = dev_uniform(static_cast<uint32_t>(word >> 32));
+    const float rho = sqrtf(-2.0f * dev_ln_unit(ua));
+    float c, sn;
+    dev_sincos_2pi(ub, c, sn);
+    gc = rho * c;
+    gs = rho * sn;
+}
+
+// Draws 4 half .. 4 half + 3 of the block (pairs 2 half and 2 half + 1).
+__device__ __forceinline__ void gauss_block_half(uint64_t seed, uint64_t replica, uint64_t round, uint64_t c8, int half,
+                                                 float (&g)[4])
+{
+    const u64x4 o = dev_philox(c8, round, replica, kTagV, seed, 0);
+    gauss_pair(half ? o.w[2] : o.w[0], g[0], g[1]);
+    gauss_pair(half ? o.w[3] : o.w[1], g[2], g[3]);
+}
+
+// All 8 draws of the block, g[i & 7] = draw i.
+__device__ __forceinline__ void gauss_block(uint64_t seed, uint64_t replica, uint64_t round, uint64_t c8,
+                                            float (&g)[8])
+{
+    const u64x4 o = dev_philox(c8, round, replica, kTagV, seed, 0);
+#pragma unroll
+    for (int p = 0; p < 4; ++p) gauss_pair(o.w[p], g[2 * p], g[2 * p + 1]);
+}
+
+// Value v of lane `src` (all lanes of the wave active).
+__device__ __forceinline__ float lane_read(int src, float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src * 4, __builtin_bit_cast(int, v)));
+}
+
 __device__ __attribute__((noinline)) float gauss_v(uint64_t seed, uint64_t replica, uint64_t round, int i)
 {
     return dev_gauss(seed, kTagV, replica, round, static_cast<uint64_t>(i));
@@ -1074,18 +1113,49 @@ k_sweep_mfma(SweepArgs args)
                                 }
                             }
                     }
-                    // Momentum refresh: one Gaussian per owned element, drawn in
-                    // a rolled loop (one inlined generator) and moved into the
-                    // register-resident v afterwards.
+                    // Momentum refresh: one Gaussian per owned element, moved
+                    // into the register-resident v afterwards.  The wave's
+                    // elements (16 replicas x 16 columns per tile and column
+                    // block) fill 32 MT CBW Philox blocks of 8 columns each.
+                    // In the column-split sweep with two tiles or column
+                    // blocks per wave that is one block per lane: every block
+                    // is generated once and each element reads its draw from
+                    // the lane that made it.  Elsewhere (where the extra
+                    // registers would cost occupancy) a rolled loop draws per
+                    // element.
                     float vn[NE];
+                    if constexpr (GROUP && !BATCH && MT * CBW == 2) {
+                        // lane L: tile/column block u = L >> 5, replica row
+                        // (L >> 1) & 15, 8-column half L & 1 (all 8 draws)
+                        const int u = lane >> 5, mtl = u / CBW, cwl = u % CBW;
+                        float g[8];
+                        gauss_block(a.seed, a.r_base + rb0 + mtl * 16 + ((lane >> 1) & 15), round,
+                                    static_cast<uint64_t>(cb0 + wave + kWaves * cwl) * 2 + (lane & 1), g);
+                        const int q = lr & 7;
+#pragma unroll
+                        for (int e = 0; e < NE; ++e) {
+                            const int mt = e / (CBW * 4), cw = (e >> 2) % CBW, j = e & 3;
+                            const int src = (mt * CBW + cw) * 32 + 2 * (4 * lg + j) + (lr >> 3);
+                            float t = 0.0f;
+#pragma unroll
+                            for (int r = 0; r < 8; ++r) {
+                                const float tr = lane_read(src, g[r]);
+                                t = q == r ? tr : t;
+                            }
+                            const int c = wave + kWaves * cw;
+                            const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+                            vn[e] = (c < cbs && gr < a.R && (cb0 + c) * 16 + lr < N) ? t : 0.0f;
+                        }
+                    } else {
 #pragma unroll 1
-                    for (int e = 0; e < NE; ++e) {
-                        const int mt = e / (CBW * 4), cw = (e >> 2) % CBW, j = e & 3;
-                        const int c = wave + kWaves * cw;
-                        const int cl = (cb0 + c) * 16 + lr;
-                        const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
-                        const bool ok = c < cbs && gr < a.R && cl < N;
-                        vn[e] = ok ? dev_gauss(a.seed, kTagV, a.r_base + gr, round, cl) : 0.0f;
+                        for (int e = 0; e < NE; ++e) {
+                            const int mt = e / (CBW * 4), cw = (e >> 2) % CBW, j = e & 3;
+                            const int c = wave + kWaves * cw;
+                            const int cl = (cb0 + c) * 16 + lr;
+                            const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
+                            const bool ok = c < cbs && gr < a.R && cl < N;
+                            vn[e] = ok ? dev_gauss(a.seed, kTagV, a.r_base + gr, round, cl) : 0.0f;
+                        }
                     }
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
@@ -1777,16 +1847,25 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         uint64_t round = static_cast<uint64_t>(ref0 / a.L);
         uint64_t w[NU];
 
-        // Momentum refresh of the owned elements (draws of `round`).
+        // Momentum refresh of the owned elements (draws of `round`).  The
+        // wave's 256 draws (16 replicas x 16 columns) fill 32 Philox blocks
+        // (replica, 8-column half of the column block): lanes 2b and 2b + 1
+        // both generate block b = 2 rr + half and transform two of its four
+        // pairs each, and every element reads its draw from the lane that
+        // made it: element (replica 4 lg + j, column lr) sits in lane
+        // 4 (4 lg + j) + 2 (lr >> 3) + ((lr >> 2) & 1), slot lr & 3.
         auto refresh = [&]() {
-#pragma unroll 1
+            float g[4];
+            const int rr = lane >> 2, hb = (lane >> 1) & 1, hp = lane & 1;
+            gauss_block_half(a.seed, a.r_base + tb0 + rr, round, static_cast<uint64_t>(cblk) * 2 + hb, hp, g);
+            const int q = lr & 3;
+#pragma unroll
             for (int j = 0; j < 4; ++j) {
-                const int64_t gr = tb0 + 4 * lg + j;
-                const float g = (creal && gr < a.R) ? gauss_v(a.seed, a.r_base + gr, round, col) : 0.0f;
-                if (j == 0) v[0] = g;
-                else if (j == 1) v[1] = g;
-                else if (j == 2) v[2] = g;
-                else v[3] = g;
+                const int src = 4 * (4 * lg + j) + 2 * (lr >> 3) + ((lr >> 2) & 1);
+                const float t0 = lane_read(src, g[0]), t1 = lane_read(src, g[1]);
+                const float t2 = lane_read(src, g[2]), t3 = lane_read(src, g[3]);
+                const float t = q == 0 ? t0 : q == 1 ? t1 : q == 2 ? t2 : t3;
+                v[j] = (creal && tb0 + 4 * lg + j < a.R) ? t : 0.0f;
             }
         };
         auto signs4 = [&]() {
