@@ -1117,14 +1117,14 @@ k_sweep_mfma(SweepArgs args)
                     // into the register-resident v afterwards.  The wave's
                     // elements (16 replicas x 16 columns per tile and column
                     // block) fill 32 MT CBW Philox blocks of 8 columns each.
-                    // In the column-split sweep with two tiles or column
-                    // blocks per wave that is one block per lane: every block
-                    // is generated once and each element reads its draw from
-                    // the lane that made it.  Elsewhere (where the extra
+                    // In the column-split sweep (also its table launches)
+                    // with two tiles or column blocks per wave that is one
+                    // block per lane: every block is generated once and each
+                    // element reads its draw from the lane that made it.  Elsewhere (where the extra
                     // registers would cost occupancy) a rolled loop draws per
                     // element.
                     float vn[NE];
-                    if constexpr (GROUP && !BATCH && MT * CBW == 2) {
+                    if constexpr (GROUP && MT * CBW == 2) {
                         // lane L: tile/column block u = L >> 5, replica row
                         // (L >> 1) & 15, 8-column half L & 1 (all 8 draws)
                         const int u = lane >> 5, mtl = u / CBW, cwl = u % CBW;
