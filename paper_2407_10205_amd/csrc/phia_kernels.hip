@@ -1338,13 +1338,22 @@ k_sweep_mfma(SweepArgs args)
                 const int64_t* prev = sB + (par ^ 1) * RB;
                 int64_t* next = sB + par * RB;
                 const bool writer = (wave == 0 && lr == 0);
+                int64_t Ev[MT][4], Bv[MT][4];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) {  // all reads before any write
+                        const int row = mt * 16 + 4 * lg + j;
+                        Ev[mt][j] = -(tot[row] / 2);
+                        Bv[mt][j] = prev[row];
+                    }
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
                         const int row = mt * 16 + 4 * lg + j;
-                        const int64_t E = -(tot[row] / 2);
-                        const int64_t B = prev[row];
+                        const int64_t E = Ev[mt][j];
+                        const int64_t B = Bv[mt][j];
                         const bool imp = E < B;
                         if (writer) {
                             next[row] = imp ? E : B;
