@@ -148,8 +148,9 @@ __device__ __forceinline__ long long wave_sum16_i64(long long v)
 // sweep loops from holding many Philox states live at once.
 // Block-shared momentum draws.  One Philox block of the momentum stream,
 // (replica, columns 8 c8 .. 8 c8 + 7), yields the draws of those 8 columns;
-// each pair of its words gives two of them by Box-Muller exactly as
-// dev_gauss computes them (g[0] = cos draw, g[1] = sin draw).
+// each of its four 64-bit words gives two of them by Box-Muller exactly as
+// dev_gauss computes them (gc: the cosine draw of the even column, gs: the
+// sine draw of the odd one).
 __device__ __forceinline__ void gauss_pair(uint64_t word, float& gc, float& gs)
 {
     const float ua = dev_uniform(static_cast<uint32_t>(word));
