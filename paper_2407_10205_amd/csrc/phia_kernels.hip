@@ -530,8 +530,7 @@ __host__ __device__ inline uint32_t cb_bytes(int path, int Np)
 
 // inc: LDS of the flip-incremental field update (the changed column blocks
 // as a bit mask [ceil(Np/1024)] uint64 and one list of changed column blocks
-// per wave [kWaves][inc_list_len(Np)] uint16, which also stages that wave's
-// sign ballots).
+// per wave [kWaves][inc_list_len(Np)] uint16, at least 64 entries).
 __host__ __device__ inline uint32_t inc_list_len(int Np)
 {
     const uint32_t ncb = static_cast<uint32_t>(Np) / 16u;
@@ -858,7 +857,6 @@ k_sweep_mfma(SweepArgs args)
     constexpr int ESZ = (PATH == kPathI8) ? 1 : 2;
     constexpr int NE = MT * CBW * 4;  // owned elements per lane
     static_assert(NE <= 32, "previous-sign mask holds 32 elements");
-    static_assert(kWaves * NE * 8 <= 16 * MT * 80, "ballot staging fits in one S buffer");
     static_assert(!INC || (MT == 1 && GROUP && !BATCH), "flip-incremental variant: one row tile, column split");
     extern __shared__ __align__(16) unsigned char lds[];
 
@@ -1221,18 +1219,15 @@ k_sweep_mfma(SweepArgs args)
                 uint64_t* Pb = a.pbuf + gslot * static_cast<size_t>(G) * RB * 2;
                 if (!last) {
                     // One 16-bit sign word per (replica, 16-column block): the
-                    // wave's MT*CBW*4 ballots go through LDS so that each lane
-                    // stores one word with a single unbranched instruction.  The
-                    // staging area is the start of S[par], which the gather
-                    // below overwrites only after the next workgroup barrier.
-                    // With INC the previous step's S[par] may still be read by
-                    // another wave's incremental product, so the ballots go
-                    // through this wave's own list area instead.
+                    // wave's MT*CBW*4 ballots are wave-uniform, and each
+                    // publishing lane selects its own with a short select
+                    // chain, so every lane stores one word with a single
+                    // unbranched instruction (no staging, no per-ballot branch).
                     // With INC every word also carries, in bit 16, whether any
                     // sign of its column block changed in any replica of the
                     // block since step k-1 (pm holds those signs).
-                    uint64_t* sW = INC ? reinterpret_cast<uint64_t*>(sLw)
-                                       : reinterpret_cast<uint64_t*>(S) + wave * (MT * CBW * 4);
+                    constexpr int NB = MT * CBW * 4;
+                    uint64_t bal[NB];
                     uint32_t lchg = 0;  // INC: bit cw set when one of this lane's signs of block cw changed
 #pragma unroll
                     for (int mt = 0; mt < MT; ++mt)
@@ -1241,8 +1236,7 @@ k_sweep_mfma(SweepArgs args)
 #pragma unroll
                             for (int j = 0; j < 4; ++j) {
                                 const bool pos = x[mt][cw][j] >= 0.0f;
-                                const uint64_t b = __ballot(pos);
-                                if (lane == 0) sW[(mt * CBW + cw) * 4 + j] = b;
+                                bal[(mt * CBW + cw) * 4 + j] = __ballot(pos);
                                 if (INC) {
                                     const uint32_t was = (pm >> ((mt * CBW + cw) * 4 + j)) & 1u;
                                     lchg |= ((pos ? 1u : 0u) ^ was) << cw;
@@ -1254,15 +1248,16 @@ k_sweep_mfma(SweepArgs args)
                         for (int cw = 0; cw < CBW; ++cw)
                             chg |= (__ballot((lchg >> cw) & 1u) != 0 ? 1u : 0u) << cw;
                     }
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                     // lane -> (ballot bi = lane / 4, row group g = lane % 4)
-                    constexpr int NW = MT * CBW * 4 * 4;
+                    constexpr int NW = NB * 4;
                     if (lane < NW) {
                         const int bi = lane >> 2, g = lane & 3;
                         const int mt = bi / (CBW * 4), cw = (bi >> 2) % CBW, j = bi & 3;
                         const int c = wave + kWaves * cw;
-                        const uint64_t w = ((sW[bi] >> (16 * g)) & 0xffffu) |
+                        uint64_t b = bal[0];
+#pragma unroll
+                        for (int t = 1; t < NB; ++t) b = bi == t ? bal[t] : b;
+                        const uint64_t w = ((b >> (16 * g)) & 0xffffu) |
                                            (INC ? static_cast<uint64_t>((chg >> cw) & 1u) << 16 : 0u);
                         const int row = mt * 16 + 4 * g + j;
                         if (c < cbs)
