@@ -213,6 +213,17 @@ __device__ __forceinline__ float kick(float x, float v, int I, float ck, float e
     return __builtin_fmaf(eps, g, v);
 }
 
+// Sum over the 16 lanes of a DPP row (lanes sharing lane / 16), result in
+// every lane of the row.  All 64 lanes must be active.
+__device__ __forceinline__ int row_sum16_dpp(int v)
+{
+    v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
+    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
+    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true);          // row_mirror (every lane has a source)
+    return v;
+}
+
 __device__ __forceinline__ int wave_sum16(int v)
 {
     // sum over the 16 lanes that share lane / 16
@@ -1453,6 +1464,7 @@ k_sweep_mfma(SweepArgs args)
                 kick_all(std::integral_constant<int, 1>{});
             else
                 kick_all(std::integral_constant<int, 0>{});
+            int psum[MT][4];  // row sums over the 16 columns of each row group
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -1464,11 +1476,16 @@ k_sweep_mfma(SweepArgs args)
                         const int sg = (x[mt][cw][j] >= 0.0f) ? 1 : -1;
                         if (col[cw] < N) part += sg * (I[mt][cw][j] + hreg[cw]);
                     }
-                    part = wave_sum16(part);
-                    if (lr == 0)
-                        atomicAdd(reinterpret_cast<unsigned long long*>(sP + r3 * RB + mt * 16 + 4 * lg + j),
-                                  static_cast<unsigned long long>(static_cast<int64_t>(part)));
+                    psum[mt][j] = row_sum16_dpp(part);
                 }
+            // Lane lr < 4 MT of each row group adds row (lr >> 2) 16 + 4 lg + (lr & 3).
+            if (lr < 4 * MT) {
+                int v = psum[0][0];
+#pragma unroll
+                for (int t = 1; t < 4 * MT; ++t) v = lr == t ? psum[t >> 2][t & 3] : v;
+                atomicAdd(reinterpret_cast<unsigned long long*>(sP + r3 * RB + (lr >> 2) * 16 + 4 * lg + (lr & 3)),
+                          static_cast<unsigned long long>(static_cast<int64_t>(v)));
+            }
             r3 = r3n;
         }
         if (aborted) return;
@@ -1578,16 +1595,6 @@ __host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, boo
     return p;
 }
 
-// Sum over the 16 lanes of a DPP row (lanes sharing lane / 16), result in
-// every lane of the row.  All 64 lanes must be active.
-__device__ __forceinline__ int row_sum16_dpp(int v)
-{
-    v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
-    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true);          // row_mirror (every lane has a source)
-    return v;
-}
 
 // Gather mapping: thread t reads the words of replica row t / 32, column
 // blocks t % 32 + 32 u, u < NU; a column block past the end reads the last
