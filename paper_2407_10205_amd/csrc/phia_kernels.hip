@@ -1338,13 +1338,12 @@ k_sweep_mfma(SweepArgs args)
 
             // Records of step k-1 (App. B, Table 3, state 5).  Every lane that
             // holds a row takes the same decision from the previous record
-            // (parity buffer par^1); lane 0 of each row group in wave 0 writes
-            // the new record into buffer par.
+            // (parity buffer par^1); in wave 0 one lane per row writes the new
+            // record into buffer par.
             if (s > 0) {
                 const int64_t* tot = GROUP ? sE + par * RB : sP + r3p * RB;
                 const int64_t* prev = sB + (par ^ 1) * RB;
                 int64_t* next = sB + par * RB;
-                const bool writer = (wave == 0 && lr == 0);
                 int64_t Ev[MT][4], Bv[MT][4];
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
@@ -1354,27 +1353,65 @@ k_sweep_mfma(SweepArgs args)
                         Ev[mt][j] = -(tot[row] / 2);
                         Bv[mt][j] = prev[row];
                     }
+                if constexpr (GROUP) {
+                    uint32_t impm = 0;  // bit mt 4 + j: row mt 16 + 4 lg + j improved
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                    for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const int row = mt * 16 + 4 * lg + j;
-                        const int64_t E = Ev[mt][j];
-                        const int64_t B = Bv[mt][j];
-                        const bool imp = E < B;
-                        if (writer) {
-                            next[row] = imp ? E : B;
-                            if (imp) sK[row] = k - 1;
+                        for (int j = 0; j < 4; ++j) {
+                            const bool imp = Ev[mt][j] < Bv[mt][j];
+                            impm |= (imp ? 1u : 0u) << (mt * 4 + j);
+                            // replace this row's bits of the record by the signs of step k-1
+                            uint32_t rowmask = 0;
+#pragma unroll
+                            for (int cw = 0; cw < CBW; ++cw) rowmask |= 1u << ((mt * CBW + cw) * 4 + j);
+                            if (imp) bestbits = (bestbits & ~rowmask) | (pm & rowmask);
                         }
-                        if (TRACE && member == 0 && writer && rval[mt][j])
-                            a.etrace[(rb0 + row) * a.T + (k - 1)] = E;
-                        if (mh && last && member == 0 && writer && rval[mt][j]) a.mhE[(rb0 + row) * 2 + 1] = E;
-                        // replace this row's bits of the record by the signs of step k-1
-                        uint32_t rowmask = 0;
+                    // lane lr < 4 MT of each row group of wave 0 writes row
+                    // (lr >> 2) 16 + 4 lg + (lr & 3): one masked block of stores
+                    if (wave == 0 && lr < 4 * MT) {
+                        const int t = lr, row = (t >> 2) * 16 + 4 * lg + (t & 3);
+                        int64_t E = Ev[0][0], B = Bv[0][0];
+                        bool rv = rval[0][0];
 #pragma unroll
-                        for (int cw = 0; cw < CBW; ++cw) rowmask |= 1u << ((mt * CBW + cw) * 4 + j);
-                        if (imp) bestbits = (bestbits & ~rowmask) | (pm & rowmask);
+                        for (int u = 1; u < 4 * MT; ++u) {
+                            E = t == u ? Ev[u >> 2][u & 3] : E;
+                            B = t == u ? Bv[u >> 2][u & 3] : B;
+                            rv = t == u ? rval[u >> 2][u & 3] : rv;
+                        }
+                        const bool imp = (impm >> t) & 1u;
+                        next[row] = imp ? E : B;
+                        if (imp) sK[row] = k - 1;
+                        if (TRACE && member == 0 && rv) a.etrace[(rb0 + row) * a.T + (k - 1)] = E;
+                        if (mh && last && member == 0 && rv) a.mhE[(rb0 + row) * 2 + 1] = E;
                     }
+                } else {
+                    // one workgroup per replica block: lane 0 of each row group
+                    // writes its rows one by one (fewer registers, so two
+                    // workgroups share a CU)
+                    const bool writer = (wave == 0 && lr == 0);
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const int row = mt * 16 + 4 * lg + j;
+                            const int64_t E = Ev[mt][j];
+                            const int64_t B = Bv[mt][j];
+                            const bool imp = E < B;
+                            if (writer) {
+                                next[row] = imp ? E : B;
+                                if (imp) sK[row] = k - 1;
+                            }
+                            if (TRACE && member == 0 && writer && rval[mt][j])
+                                a.etrace[(rb0 + row) * a.T + (k - 1)] = E;
+                            if (mh && last && member == 0 && writer && rval[mt][j])
+                                a.mhE[(rb0 + row) * 2 + 1] = E;
+                            uint32_t rowmask = 0;
+#pragma unroll
+                            for (int cw = 0; cw < CBW; ++cw) rowmask |= 1u << ((mt * CBW + cw) * 4 + j);
+                            if (imp) bestbits = (bestbits & ~rowmask) | (pm & rowmask);
+                        }
+                }
             }
             if (last) break;
             if (tid < RB) sP[r3n * RB + tid] = 0;
