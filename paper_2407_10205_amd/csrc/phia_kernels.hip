@@ -1129,23 +1129,29 @@ k_sweep_mfma(SweepArgs args)
                     // block) fill 32 MT CBW Philox blocks of 8 columns each.
                     // In the column-split sweep (also its table launches)
                     // with two tiles or column blocks per wave that is one
-                    // block per lane: every block is generated once and each
-                    // element reads its draw from the lane that made it.  Elsewhere (where the extra
+                    // block per lane (two passes of that with the four column
+                    // blocks per wave of the int8 batch sweep): every block is
+                    // generated once and each element reads its draw from the
+                    // lane that made it.  Elsewhere (where the extra
                     // registers would cost occupancy) a rolled loop draws per
                     // element.
                     float vn[NE];
-                    if constexpr (GROUP && MT * CBW == 2) {
-                        // lane L: tile/column block u = L >> 5, replica row
-                        // (L >> 1) & 15, 8-column half L & 1 (all 8 draws)
-                        const int u = lane >> 5, mtl = u / CBW, cwl = u % CBW;
+                    if constexpr ((GROUP && MT * CBW == 2) ||
+                                  (PATH == kPathI8 && BATCH && !GROUP && !MH && MT == 1 && CBW == 4)) {
+                        // pass h covers tiles/column blocks u = 2 h, 2 h + 1;
+                        // lane L: u = 2 h + (L >> 5), replica row (L >> 1) & 15,
+                        // 8-column half L & 1 (all 8 draws)
+                        const int q = lr & 7;
+#pragma unroll
+                        for (int h = 0; h < MT * CBW / 2; ++h) {
+                        const int u = 2 * h + (lane >> 5), mtl = u / CBW, cwl = u % CBW;
                         float g[8];
                         gauss_block(a.seed, a.r_base + rb0 + mtl * 16 + ((lane >> 1) & 15), round,
                                     static_cast<uint64_t>(cb0 + wave + kWaves * cwl) * 2 + (lane & 1), g);
-                        const int q = lr & 7;
 #pragma unroll
-                        for (int e = 0; e < NE; ++e) {
+                        for (int e = 8 * h; e < 8 * h + 8; ++e) {
                             const int mt = e / (CBW * 4), cw = (e >> 2) % CBW, j = e & 3;
-                            const int src = (mt * CBW + cw) * 32 + 2 * (4 * lg + j) + (lr >> 3);
+                            const int src = ((mt * CBW + cw) & 1) * 32 + 2 * (4 * lg + j) + (lr >> 3);
                             float t = 0.0f;
 #pragma unroll
                             for (int r = 0; r < 8; ++r) {
@@ -1155,6 +1161,7 @@ k_sweep_mfma(SweepArgs args)
                             const int c = wave + kWaves * cw;
                             const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
                             vn[e] = (c < cbs && gr < a.R && (cb0 + c) * 16 + lr < N) ? t : 0.0f;
+                        }
                         }
                     } else {
 #pragma unroll 1
