@@ -22,6 +22,13 @@ class _MhC(C.Structure):
                 ("dec", C.c_void_p), ("trace", C.c_void_p)]
 
 
+def use_library(path):
+    """Load the oracle from `path` (a copy built for the host CPU) from now on."""
+    global _lib, _LIB_PATH
+    _lib = None
+    _LIB_PATH = path
+
+
 def _load():
     global _lib
     if _lib is not None:

@@ -241,6 +241,51 @@ def test_best_tracking_matches_trace_and_eq2(O):
         assert O.energy(J, h, run.bestS[r]) == run.bestE[r]
 
 
+# -------------------------------------------------- final argmin -----
+I64MAX = np.iinfo(np.int64).max
+
+
+@pytest.mark.parametrize("bestE,want", [
+    ([5], 0),                                   # one replica
+    ([I64MAX], 0),                              # one replica without a record
+    ([I64MAX, I64MAX, I64MAX], 0),              # no replica has a record: the first
+    ([I64MAX, -3, I64MAX], 1),                  # records beat the empty rows
+    ([-7, -9, -9, -8, -9], 1),                  # three-way tie: the lowest index
+    ([4, 3, 2, 1, 0, -1], 5),                   # minimum in the last row
+    ([-(2**62), 2**62, -(2**62) + 1], 0),       # full int64 range, no overflow
+    ([0, -1, I64MAX, -1, -2, -2], 4),           # tie after the first minimum
+])
+def test_argmin_hand_cases(O, bestE, want):
+    """Final choice of the reported configuration (App. B, Table 3, state 5:
+    the best result so far; ties over replicas take the lowest index): hand
+    cases covering ties, rows that never recorded an energy and R = 1."""
+    assert O.argmin(np.array(bestE, np.int64)) == want
+
+
+def test_argmin_matches_numpy_first_occurrence(O):
+    """numpy.argmin returns the first occurrence of the minimum: on random
+    arrays with many ties it must agree with the oracle everywhere."""
+    rs = np.random.default_rng(11)
+    for R in (1, 2, 3, 63, 64, 65, 255, 256, 257, 1000, 4096):
+        for _ in range(20):
+            E = rs.integers(-4, 3, size=R).astype(np.int64)
+            E[rs.random(R) < 0.1] = I64MAX
+            assert O.argmin(E) == int(np.argmin(E)), (R, E)
+
+
+def test_argmin_of_an_anneal_reports_a_ground_state(O):
+    """SK N = 16 after an anneal: many replicas tie at the exhaustive ground
+    energy, and the chosen one is the first of them."""
+    J, h = _c1()
+    Eg, _ = O.bruteforce(J, h)
+    betas = O.beta_linear(0.1, 3.0, 1000)
+    run = O.anneal(J, h, 0, 64, betas, 0.2, 1.0, 50, 1234, threads=4)
+    r = O.argmin(run.bestE)
+    ties = np.nonzero(run.bestE == Eg)[0]
+    assert ties.size > 1 and r == ties[0]
+    assert O.energy(J, h, run.bestS[r]) == Eg
+
+
 def test_harmonic_closed_form(O):
     """J = h = 0: each coordinate follows (x, v) <- (x + eps v, v - eps (x + eps v)),
     i.e. powers of [[1, eps], [-eps, 1 - eps^2]] (A7 with grad H = x)."""
