@@ -220,6 +220,28 @@ phia_status phia_set_incremental(phia_problem* p, int32_t on);
  * PHIA_ESTATE before any phia_anneal_start. */
 phia_status phia_incremental_stats(phia_problem* p, int64_t* out);
 
+/* Test hooks of the column-split exchange (diagnostic; results do not depend
+ * on them).  Workgroups that split one replica block's columns swap their
+ * spins every step through tagged words; the tag is a sequence number that
+ * runs on across launches and restarts (with the words cleared) before it
+ * would wrap: 24 bits in the interleaved sweep (sweep_kernel 1), 32 bits in
+ * the one-block-per-workgroup sweep.
+ *
+ * phia_set_exchange_seq sets the sequence number of the next launch of the
+ * current anneal, so that a test can start next to the wrap.  seq must not
+ * exceed 2^24 - 2 (interleaved) or 2^32 - 2.  PHIA_ESTATE before
+ * phia_anneal_start or when the geometry has no exchange (group 1);
+ * PHIA_EINVAL when seq is out of range.
+ *
+ * phia_set_wait_limit sets how many times a kernel polls one exchange word
+ * before it gives up (default 2^21).  A wait that gives up raises the
+ * device error word, every workgroup leaves the sweep at its next check,
+ * and phia_sync then returns PHIA_EDEVICE and poisons the handle.  A small
+ * limit lets a test take that path from the host without a real fault.
+ * Takes effect at the next launch. */
+phia_status phia_set_exchange_seq(phia_problem* p, uint32_t seq);
+phia_status phia_set_wait_limit(phia_problem* p, uint32_t polls);
+
 /* Autotuner of the launch geometry of the matrix-core sweep (replicas per
  * workgroup block, workgroups sharing one block's columns, coupling slice in
  * LDS or streamed): every feasible geometry for `replicas` replicas runs

@@ -192,10 +192,17 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
     }
     std::vector<SweepArgs> tab;
     std::vector<size_t> offs;
+    hipError_t e;
     for (const Launch& L : launches) {
         offs.push_back(tab.size());
         for (int i : L.members) {
             phia_problem* p = probs[i];
+            // 32-bit tags: restart the sequence (cleared words) before it would wrap
+            const uint64_t iters = static_cast<uint64_t>((p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups);
+            if (static_cast<uint64_t>(p->seq) + iters * static_cast<uint64_t>(k_end[i] - p->k + 1) > 0xfffffffeull) {
+                if ((e = clear_exchange(p)) != hipSuccess) return hip_fail(p, e, "exchange reset");
+                p->seq = 0;
+            }
             SweepArgs a = sweep_args(p);
             a.inc = 0;  // table launches carry no flip-incremental variant
             a.k0 = p->k;
@@ -211,7 +218,6 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
                 }
         }
     }
-    hipError_t e;
     if (!tab.empty()) {
         if (tab.size() > cap) {
             if (dtab) (void)hipFree(dtab);

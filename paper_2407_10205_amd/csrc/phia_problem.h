@@ -41,6 +41,7 @@ void kick_factors(const ::phia_problem* p, int64_t steps, const phia_schedule* s
 phia_status setup_state(::phia_problem* p, int32_t replicas, int64_t steps, const phia_schedule* s, uint64_t seed,
                         const std::vector<float>& ctab, bool& reuse, bool sync_first);
 void free_state(::phia_problem* p);
+hipError_t clear_exchange(::phia_problem* p);
 phia_status setup_mh_geometry(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
 phia_status launch_batch_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
@@ -99,6 +100,7 @@ struct phia_problem {
     uint64_t* dxbits = nullptr;
     uint64_t* dpbuf = nullptr;
     uint32_t seq = 0;
+    uint32_t spin_limit = phia::kSpinLimit;  // polls before a kernel's bounded wait gives up
     int32_t best_r = -1;
     size_t state_bytes = 0;
     phia::Geometry geo;

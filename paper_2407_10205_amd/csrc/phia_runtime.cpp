@@ -504,6 +504,7 @@ SweepArgs sweep_args(const phia_problem* p)
     a.pbuf = p->dpbuf;
     a.seq_base = p->seq;
     a.err = p->derr;
+    a.spin_limit = p->spin_limit;
     a.mh = p->mh;
     a.mh_up = p->mh_up;
     a.mh_down = p->mh_down;
@@ -909,6 +910,31 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     return PHIA_OK;
 }
 
+}  // extern "C"
+
+namespace phia {
+
+// Zero the exchange words of the current geometry (their tags restart at 1).
+hipError_t clear_exchange(phia_problem* p)
+{
+    hipError_t e = hipSuccess;
+    const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * (p->Np / 16) * sizeof(uint64_t);
+    if (p->dxbits) e = hipMemsetAsync(p->dxbits, 0, xb, p->st);
+    if (e == hipSuccess && p->dpbuf) {
+        const size_t pb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * 2 * sizeof(uint64_t);
+        e = hipMemsetAsync(p->dpbuf, 0, pb, p->st);
+    }
+    if (e == hipSuccess && p->dmhbuf) {
+        const size_t mb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * 4 * sizeof(uint64_t);
+        e = hipMemsetAsync(p->dmhbuf, 0, mb, p->st);
+    }
+    return e;
+}
+
+}  // namespace phia
+
+extern "C" {
+
 phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
 {
     clear_error();
@@ -935,8 +961,7 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
             const int64_t kk = std::min(k_end, k + chunk);
             const int64_t use = iters * (kk - k + 1);
             if (static_cast<int64_t>(p->seq) + use > tag_room) {
-                const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * (p->Np / 16) * sizeof(uint64_t);
-                if ((e = hipMemsetAsync(p->dxbits, 0, xb, p->st)) != hipSuccess) break;
+                if ((e = clear_exchange(p)) != hipSuccess) break;
                 p->seq = 0;
             }
             a.k0 = k;
@@ -947,11 +972,19 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
             k = kk;
         }
     } else {
-        e = launch_sweep_mfma(p->path, p->geo.mt, p->geo.cbw, a, p->geo.lds, p->st);
         if (p->geo.G > 1) {
-            const int iters = (p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups;
-            p->seq += static_cast<uint32_t>(iters) * static_cast<uint32_t>(k_end - p->k + 1);
+            // 32-bit tags: the sequence restarts (with cleared words) before
+            // it would wrap, so a word never carries a tag of a later step.
+            const uint64_t iters = static_cast<uint64_t>((p->geo.nblocks + p->geo.ngroups - 1) / p->geo.ngroups);
+            const uint64_t use = iters * static_cast<uint64_t>(k_end - p->k + 1);
+            if (static_cast<uint64_t>(p->seq) + use > 0xfffffffeull) {
+                if ((e = clear_exchange(p)) != hipSuccess) return hip_fail(p, e, "exchange reset");
+                p->seq = 0;
+                a.seq_base = 0;
+            }
+            p->seq += static_cast<uint32_t>(use);
         }
+        e = launch_sweep_mfma(p->path, p->geo.mt, p->geo.cbw, a, p->geo.lds, p->st);
     }
     if (e != hipSuccess) return hip_fail(p, e, "sweep launch");
     p->k = k_end;
@@ -1272,6 +1305,28 @@ phia_status phia_set_incremental(phia_problem* p, int32_t on)
     if (st != PHIA_OK) return st;
     if (on < -1 || on > 1) return fail(PHIA_EINVAL, "incremental must be -1, 0 or 1 (got %d)", on);
     p->inc_mode = on;
+    return PHIA_OK;
+}
+
+phia_status phia_set_exchange_seq(phia_problem* p, uint32_t seq)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (!p->started) return fail(PHIA_ESTATE, "phia_anneal_start has not been called");
+    if (p->geo.G < 2) return fail(PHIA_ESTATE, "the current geometry has no exchange between workgroups");
+    const uint32_t room = p->geo.kind >= 1 ? (1u << 24) - 2u : 0xfffffffeu;
+    if (seq > room) return fail(PHIA_EINVAL, "seq = %u beyond the tag range", seq);
+    p->seq = seq;
+    return PHIA_OK;
+}
+
+phia_status phia_set_wait_limit(phia_problem* p, uint32_t polls)
+{
+    clear_error();
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    p->spin_limit = polls;
     return PHIA_OK;
 }
 

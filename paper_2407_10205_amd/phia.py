@@ -27,7 +27,8 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
 # Every symbol declared in include/phia.h.
 EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_replica_mh", "phia_get_state",
-           "phia_set_state", "phia_get_info", "phia_set_incremental", "phia_incremental_stats", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
+           "phia_set_state", "phia_get_info", "phia_set_incremental", "phia_incremental_stats",
+           "phia_set_exchange_seq", "phia_set_wait_limit", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
            "phia_batch_run", "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
            "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
            "phia_destroy", "phia_last_error", "phia_version")
@@ -93,6 +94,8 @@ def _declare(lib):
         "phia_set_trace": [P, I32],
         "phia_set_incremental": [P, I32],
         "phia_incremental_stats": [P, P],
+        "phia_set_exchange_seq": [P, C.c_uint32],
+        "phia_set_wait_limit": [P, C.c_uint32],
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
         "phia_batch_run": [P, I32, P, P, P, P],
@@ -218,6 +221,14 @@ class Problem:
         out = (C.c_int64 * 3)()
         _check(lib().phia_incremental_stats(self._p, out))
         return tuple(int(v) for v in out)
+
+    def set_exchange_seq(self, seq):
+        """Test hook: sequence number of the next column-split launch."""
+        _check(lib().phia_set_exchange_seq(self._p, int(seq)))
+
+    def set_wait_limit(self, polls):
+        """Test hook: polls of one exchange word before a kernel gives up."""
+        _check(lib().phia_set_wait_limit(self._p, int(polls)))
 
     def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
               deriv="tanh", mh=None):

@@ -108,6 +108,104 @@ def test_c1_sk16_parity(P, O, path):
 
 
 @pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo"])
+def test_final_argmin_matches_oracle(P, O, path):
+    """Final choice (App. B, Table 3, state 5; ties over replicas take the
+    lowest index): SK N = 16 with most of its 64 replicas at the exhaustive
+    ground energy, and the ragged fixed-point case.  phia_best_exact's
+    (energy, replica) and phia_best's spins equal the oracle's argmin over
+    its per-replica records and that replica's best state."""
+    J, h = inst.sk_pm1(16, 0)
+    cases = [(J, h, 0, 64, 1000, 0.2, 1.0, 0.1, 3.0, 50, 1234)]
+    J2, h2 = inst.sk_gauss_fixed(77, 3, frac_bits=5, bits=8)
+    cases.append((J2, h2, 5, 37, 301, 0.15, 1.5, 0.05, 2.0, 37, 99))
+    for J, h, f, R, T, eps, gamma, b0, b1, L, seed in cases:
+        dev, runs = run_both(P, O, J, h, f, path, R, T, eps, gamma, b0, b1, L, seed, trace=False)
+        oE = np.array([runs[r].bestE[0] for r in range(R)], np.int64)
+        r_star = O.argmin(oE)
+        E_units, f_dev, r_dev = dev["best_exact"]
+        say("argmin", path, J.shape[0], "oracle", r_star, oE[r_star], "device", r_dev, E_units,
+            "ties", int(np.sum(oE == oE[r_star])))
+        assert (E_units, r_dev, f_dev) == (int(oE[r_star]), r_star, f)
+        e, s = dev["best"]
+        assert e == oE[r_star] * 2.0**-f
+        assert np.array_equal(s, runs[r_star].bestS[0])
+
+
+def test_final_argmin_many_ties_across_threads(P, O):
+    """4096 replicas of SK N = 16: ties at the ground energy spread over every
+    thread slot of the device reduction; the device picks the oracle's
+    lowest-index replica, whose state it returns."""
+    J, h = inst.sk_pm1(16, 0)
+    R, T = 4096, 300
+    p = P.Problem(J, h, path="i8")
+    p.anneal(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=50, seed=31)
+    E_units, _, r_dev = p.best_exact()
+    e, s = p.best()
+    Ed, Sd, _ = p.replica_best()
+    p.close()
+    Ji, hi = int_units(J, h, 0)
+    o = O.anneal(Ji, hi, 0, R, O.beta_linear(0.1, 3.0, T), 0.2, 1.0, 50, 31, threads=8)
+    assert np.array_equal(Ed, o.bestE) and np.array_equal(Sd, o.bestS)
+    r_star = O.argmin(o.bestE)
+    say("ties", int(np.sum(o.bestE == o.bestE[r_star])), "r*", r_star)
+    assert np.sum(o.bestE == o.bestE[r_star]) > 100
+    assert (E_units, r_dev) == (int(o.bestE[r_star]), r_star)
+    assert np.array_equal(s, o.bestS[r_star])
+
+
+def _betas_table(T):
+    """A non-linear inverse-temperature table: geometric rise, a plateau and
+    a drop (App. B, Table 3, state 4 leaves the temperature rule open)."""
+    k = np.arange(T, dtype=np.float64)
+    b = 0.05 * np.power(1.02, k)
+    b = np.minimum(b, 2.5)
+    b[T // 2: T // 2 + 7] = 0.3
+    return b.astype(np.float32)
+
+
+@pytest.mark.parametrize("path,geometry", [("fp32", None), ("i8", None), ("bf16hilo", None), ("i8", "1,3,1"),
+                                           ("i8", "pp,3")])
+def test_explicit_beta_table(P, O, path, geometry):
+    """An explicit, non-linear beta table (phia_schedule.betas) is used step
+    by step exactly as the oracle uses it: every replica bit-identical, on
+    every sweep kernel (plain FP32, one block per workgroup, column split,
+    interleaved column split)."""
+    import os
+    J, h = inst.sk_gauss_fixed(150, 5, frac_bits=5, bits=8)
+    R, T, L, seed = 45, 211, 23, 71
+    betas = _betas_table(T)
+    say(f"betas path={path} geometry={geometry}")
+    if geometry:
+        os.environ["PHIA_GEOMETRY"] = geometry
+    try:
+        p = P.Problem(J, h, frac_bits=5, path=path)
+        p.set_trace(geometry is None or not geometry.startswith("pp"))
+        p.anneal(R, T, 0.2, 1.0, betas=betas, refresh_L=L, seed=seed)
+    finally:
+        os.environ.pop("PHIA_GEOMETRY", None)
+    info = p.info()
+    say("geometry", info)
+    if geometry == "pp,3":
+        assert info["sweep_kernel"] == 1
+    elif geometry:
+        assert info["group"] == 3 and info["sweep_kernel"] == 0
+    E, S, K = p.replica_best()
+    x, v, _ = p.get_state()
+    tr = p.trace(T) if (geometry is None or not geometry.startswith("pp")) else None
+    p.close()
+    Ji, hi = int_units(J, h, 5)
+    o = O.anneal(Ji, hi, 5, R, betas, 0.2, 1.0, L, seed, trace=True, threads=8)
+    assert np.array_equal(x.view(np.uint32), o.x.view(np.uint32))
+    assert np.array_equal(v.view(np.uint32), o.v.view(np.uint32))
+    assert np.array_equal(E, o.bestE) and np.array_equal(K, o.bestStep) and np.array_equal(S, o.bestS)
+    if tr is not None:
+        assert np.array_equal(tr, o.Etrace)
+    # the linear table it replaces gives a different run
+    lin = O.anneal(Ji, hi, 5, 2, O.beta_linear(float(betas[0]), float(betas[-1]), T), 0.2, 1.0, L, seed)
+    assert not np.array_equal(lin.x, o.x[:2])
+
+
+@pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo"])
 def test_ragged_fixed_point_parity(P, O, path):
     """Ragged N (not a multiple of 16 or 64), ragged R, fractional couplings
     and fields on the 2^-5 grid, momentum refresh period not dividing T."""
@@ -657,9 +755,12 @@ def test_batch_full_size_sampled(P, O):
         Ji, hi = J.astype(np.int32), h.astype(np.int32)
         E, S, K = probs[i].replica_best()
         x, v, _ = probs[i].get_state()
-        for r in (0, 31):
+        for r in (0, 13, 16, 31):
             o = O.anneal(Ji, hi, 0, 1, betas, 0.2, 1.0, 25, 5000 + i, r0=r)
-            assert E[r] == o.bestE[0] and np.array_equal(x[r].view(np.uint32), o.x[0].view(np.uint32)), (i, r)
+            assert E[r] == o.bestE[0] and K[r] == o.bestStep[0], (i, r)
+            assert np.array_equal(S[r], o.bestS[0]), (i, r)
+            assert np.array_equal(x[r].view(np.uint32), o.x[0].view(np.uint32)), (i, r)
+            assert np.array_equal(v[r].view(np.uint32), o.v[0].view(np.uint32)), (i, r)
     for i in range(0, len(probs), 97):
         e, s = probs[i].best()
         J, h = insts[i]
