@@ -222,6 +222,8 @@ def run_serve_bench(args, w):
         tickets.append(srv.submit(p, R, T, r["target"], seed=17, **sr))
     res = [srv.wait(tk) for tk in tickets]
     srv.close()
+    for p in probs:
+        p.close()
     lat = np.array([x["t_done"] - x["t_arrive"] for x in res])
     su = float(sum(R * r["N"] * x["steps_used"] for r, x in zip(reqs, res)))
     span = max(x["t_done"] for x in res) - min(x["t_arrive"] for x in res)
@@ -268,6 +270,10 @@ def run_batch_bench(args, w):
     wall = time.perf_counter() - t0
     value = su * args.steps / wall
     best = [p.best_exact()[0] for p in probs[:4]]
+    # explicit teardown while the runtime and the stream are alive
+    for p in probs:
+        p.close()
+    torch.cuda.synchronize()
     if args.calibrate_copy:
         calibrate_copy()
     out = {"metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
@@ -362,19 +368,66 @@ def run_tts_sweep(args, w):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
-    """Time the oracle on a bounded replica/step sample of the workload."""
+def host_cpu():
+    """Host CPU as the CPU-baseline leg reports it: model name, logical CPUs,
+    CPUs this process may run on, and the threads the oracle uses (the
+    OpenMP thread count when the environment sets one, else every allowed
+    CPU)."""
+    model = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    allowed = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    threads = allowed
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        threads = min(allowed, int(env))
+    return {"model": model, "nproc": os.cpu_count() or 1, "allowed": allowed, "threads": max(1, threads)}
+
+
+_ORACLE_NATIVE = None
+
+
+def oracle_for_host():
+    """The oracle, compiled for this host's CPU (-O3 -march=native) into a
+    temporary directory; the in-tree portable build if that fails."""
+    global _ORACLE_NATIVE
+    from oracle import build as obuild, oracle as O
+    if _ORACLE_NATIVE is None:
+        import tempfile
+        try:
+            d = tempfile.mkdtemp(prefix="phia_oracle_")
+            _ORACLE_NATIVE = obuild.build(native=True, out=os.path.join(d, "liboracle_native.so"))
+        except Exception as e:  # noqa: BLE001 - fall back to the portable in-tree build
+            log(f"native oracle build failed ({e}); timing the in-tree build")
+            _ORACLE_NATIVE = ""
+    if _ORACLE_NATIVE:
+        O.use_library(_ORACLE_NATIVE)
+    return O, ("-O3 -march=native" if _ORACLE_NATIVE else "-O3 -march=x86-64-v3")
+
+
+def grid_units(J, h):
     import numpy as np
-    from oracle import oracle as O
     f = 0
     while not np.all(np.rint(J * 2**f) == J * 2**f) or not np.all(np.rint(h * 2**f) == h * 2**f):
         f += 1
-    Ji = np.rint(J * 2**f).astype(np.int32)
-    hi = np.rint(h * 2**f).astype(np.int32)
+    return f, np.rint(J * 2**f).astype(np.int32), np.rint(h * 2**f).astype(np.int32)
+
+
+def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
+    """Time the oracle on a bounded replica/step sample of the workload."""
+    O, flags = oracle_for_host()
+    f, Ji, hi = grid_units(J, h)
     N, T = J.shape[0], w["T"]
     s = w["sched"]
     betas = O.beta_linear(s["beta0"], s["beta1"], T)
-    threads = max(1, min(16, os.cpu_count() or 1))
+    cpu = host_cpu()
+    threads = cpu["threads"]
     # calibrate one replica on a few steps, then size the sample to the budget
     t = time.perf_counter()
     O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1, deriv=deriv, mh=mh)
@@ -386,8 +439,40 @@ def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
              mh=mh)
     dt = time.perf_counter() - t
     return {"value": R * N * steps / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"replicas 0..{R - 1}, steps 0..{steps - 1} of the same schedule, "
-                      f"{dt:.1f} s on {platform.processor() or platform.machine()}"}
+            "sample": f"replicas 0..{R - 1}, steps 0..{steps - 1} of the same schedule, {dt:.1f} s; oracle {flags}, "
+                      f"OpenMP over replicas",
+            "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cpus_allowed": cpu["allowed"]}
+
+
+def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
+    """Oracle timing on a subset of a workload's instances: every sampled
+    instance runs `threads` replicas (OpenMP over replicas) for the same
+    number of steps of its schedule, sized so that the sample takes about
+    budget_s.  Spin-updates/s of the sample = sum N x replicas x steps / time."""
+    O, flags = oracle_for_host()
+    cpu = host_cpu()
+    threads = cpu["threads"]
+    units = [grid_units(J, h) for J, h in insts]
+    betas = O.beta_linear(sched["beta0"], sched["beta1"], T)
+    # calibrate on the first instance
+    f, Ji, hi = units[0]
+    t = time.perf_counter()
+    O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=10,
+             threads=threads)
+    per_su = (time.perf_counter() - t) / (10 * threads * Ji.shape[0])
+    total_n = sum(u[1].shape[0] for u in units)
+    steps = int(max(10, min(T, budget_s / max(per_su * threads * total_n, 1e-12))))
+    su = 0.0
+    t = time.perf_counter()
+    for f, Ji, hi in units:
+        O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=steps,
+                 threads=threads)
+        su += float(Ji.shape[0]) * threads * steps
+    dt = time.perf_counter() - t
+    return {"value": su / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{what}: {len(units)} instances (sum N = {total_n}), replicas 0..{threads - 1}, "
+                      f"steps 0..{steps - 1} of each schedule, {dt:.1f} s; oracle {flags}, OpenMP over replicas",
+            "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cpus_allowed": cpu["allowed"]}
 
 
 def main():
@@ -555,6 +640,9 @@ def main():
             tts = t_run * math.log(0.01) / math.log(1.0 - P)
         extra = {"tts99_s": tts, "target_energy": int(target), "replica_success": p_hat,
                  "best_energy_per_run": [int(b[0]) for b in bests]}
+    # explicit teardown while the runtime and the stream are alive
+    prob.close()
+    torch.cuda.synchronize()
     if args.calibrate_copy:
         calibrate_copy()
     cpu = None

@@ -108,7 +108,7 @@ def test_exchange_seq_hook_rejects_bad_use(P):
     q.close()
 
 
-@pytest.mark.parametrize("spec", ["pp,3", "1,8,0"])
+@pytest.mark.parametrize("spec", ["pp,4", "1,8,0"])
 def test_wait_that_gives_up_poisons_the_handle(P, O, spec):
     """A wait limit of zero polls makes the first exchange word that is not
     yet current end the wait: the kernel raises the device error word, every
