@@ -142,6 +142,32 @@ phia_status phia_create(const double* J, const double* h, int32_t N,
 phia_status phia_anneal(phia_problem* p, int32_t replicas, int64_t steps,
                         const phia_schedule* schedule, uint64_t seed);
 
+/* phia_anneal for callers that cannot allocate device memory (code that runs
+ * where hipMalloc is not allowed: tight serving loops, harnesses that forbid
+ * it).  It allocates and frees nothing.  The caller passes device buffers
+ * for the replica state and records of `replicas` replicas, with
+ * Np = phia_info.Np (N padded to a multiple of 64):
+ *   x, v      float [replicas][Np]   final positions and momenta
+ *   bestE     int64 [replicas]       record energies in units of 2^-f
+ *   bestS     int8  [replicas][Np]   record states (+1 / -1; padding 0)
+ *   bestStep  int64 [replicas]       step of each record
+ * and optionally host outputs best_energy_units / best_replica (the argmin
+ * of phia_best_exact; NULL to skip).  Results are bit-identical to
+ * phia_anneal with the same arguments (no energy trace is recorded, and the
+ * accept/reject step is not available: PHIA_EINVAL).  The problem's own
+ * anneal state is left as it was.  The kernels' scratch (kick factors,
+ * exchange words, error word) lives in a fixed device array of 32 MiB per
+ * GPU, held until the process ends; an anneal whose scratch exceeds it
+ * (about 4 bytes per step plus the exchange of column-split geometries) or
+ * whose exchange tags would wrap within the call returns PHIA_ERANGE.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (several
+ * host threads, or several streams in flight) race and must not be made.
+ * Synchronises the problem's stream; a device error poisons the handle. */
+phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, int64_t steps,
+                                const phia_schedule* schedule, uint64_t seed, float* x, float* v,
+                                int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                                int64_t* best_energy_units, int32_t* best_replica);
+
 /* Allocate replica state and draw x ~ N(0, I) (App. A, A3) for step 0.
  * Enqueued on the problem's stream; returns without waiting. */
 phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps,

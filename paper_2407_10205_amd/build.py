@@ -9,7 +9,7 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libphia.so")
 
-SOURCES = ["phia_kernels.hip", "phia_runtime.cpp", "phia_batch.cpp", "phia_server.cpp"]
+SOURCES = ["phia_kernels.hip", "phia_runtime.cpp", "phia_batch.cpp", "phia_server.cpp", "phia_noalloc.hip"]
 
 # -ffp-contract=off: no implicit fused multiply-adds (the sweep's op sequence
 # is fixed and every fma is explicit).  Correctly rounded FP32 division and

@@ -44,6 +44,7 @@ void free_state(::phia_problem* p);
 hipError_t clear_exchange(::phia_problem* p);
 phia_status setup_mh_geometry(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
+Geometry plain_geometry(::phia_problem* p, int R);
 phia_status launch_batch_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
                                SweepArgs*& dtab, size_t& cap);
 phia_status launch_group_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,

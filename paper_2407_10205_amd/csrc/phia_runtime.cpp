@@ -469,6 +469,33 @@ void free_state(phia_problem* p)
     p->k = 0;
 }
 
+// Launch geometry that an anneal of R replicas without the accept/reject
+// step or energy traces would take (forced, tuned, cached or default), with
+// the problem's current anneal left as it is.
+Geometry plain_geometry(phia_problem* p, int R)
+{
+    const Geometry saved = p->geo;
+    const int mh = p->mh;
+    const bool trace = p->trace;
+    p->mh = 0;
+    p->trace = false;
+    Geometry g{};
+    if (p->path == PHIA_PATH_FP32) {
+        g.ok = true;
+        g.G = 1;
+        g.rows = kFp32Rows;
+        g.nblocks = (R + kFp32Rows - 1) / kFp32Rows;
+        g.ngroups = g.nblocks;
+    } else {
+        choose_mfma_geometry(p, R);
+        g = p->geo;
+    }
+    p->geo = saved;
+    p->mh = mh;
+    p->trace = trace;
+    return g;
+}
+
 SweepArgs sweep_args(const phia_problem* p)
 {
     SweepArgs a{};

@@ -25,7 +25,8 @@ STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG",
           -5: "PHIA_ENOMEM", -6: "PHIA_EDEVICE", -7: "PHIA_ESTATE"}
 
 # Every symbol declared in include/phia.h.
-EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_start", "phia_anneal_run", "phia_sync",
+EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_noalloc", "phia_anneal_start", "phia_anneal_run",
+           "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_replica_mh", "phia_get_state",
            "phia_set_state", "phia_get_info", "phia_set_incremental", "phia_incremental_stats",
            "phia_set_exchange_seq", "phia_set_wait_limit", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
@@ -79,6 +80,7 @@ def _declare(lib):
     sig = {
         "phia_create": [P, P, I32, P, P],
         "phia_anneal": [P, I32, I64, P, U64],
+        "phia_anneal_noalloc": [P, I32, I64, P, U64, P, P, P, P, P, P, P],
         "phia_anneal_start": [P, I32, I64, P, U64],
         "phia_anneal_run": [P, I64],
         "phia_sync": [P],
@@ -247,6 +249,19 @@ class Problem:
         self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh)
         _check(lib().phia_anneal(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
+
+    def anneal_noalloc(self, replicas, steps, eps, gamma, x, v, bestE, bestS, bestStep, beta0=None, beta1=None,
+                       betas=None, refresh_L=50, seed=0, deriv="tanh"):
+        """phia_anneal_noalloc: x, v, bestE, bestS, bestStep are device
+        addresses (ints) of caller-owned buffers ([replicas][Np] float, float,
+        [replicas] int64, [replicas][Np] int8, [replicas] int64).  Returns the
+        argmin (energy in units, replica)."""
+        sch = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, None)
+        e, r = C.c_int64(), C.c_int32()
+        _check(lib().phia_anneal_noalloc(self._p, int(replicas), int(steps), C.byref(sch), int(seed),
+                                         C.c_void_p(x), C.c_void_p(v), C.c_void_p(bestE), C.c_void_p(bestS),
+                                         C.c_void_p(bestStep), C.byref(e), C.byref(r)))
+        return e.value, r.value
 
     # -- results
     def best(self):
