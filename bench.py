@@ -76,7 +76,10 @@ WORKLOADS = {
 }
 
 
-KERNEL_SRC = os.path.join(ROOT, "paper_2407_10205_amd", "csrc", "phia_kernels.hip")
+CSRC = os.path.join(ROOT, "paper_2407_10205_amd", "csrc")
+# sources whose hash identifies each profiled kernel's code
+KERNEL_SRCS = {"k_batch_fp4": ["phia_batch_kernel.hip", "phia_devsweep.h", "phia_devmath.h"]}
+DEFAULT_SRCS = ["phia_kernels.hip", "phia_devsweep.h", "phia_devmath.h"]
 PROFILES = os.path.join(ROOT, "profiles")
 COPY_BYTES = 256 << 20  # plain device copy used to calibrate the byte counters
 
@@ -85,9 +88,12 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+def kernel_sha(kernel=None):
+    h = hashlib.sha256()
+    for name in KERNEL_SRCS.get(kernel, DEFAULT_SRCS):
+        with open(os.path.join(CSRC, name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_file(kernel, workload_name):
@@ -102,7 +108,7 @@ def recorded_traffic(kernel, workload_name, workload, geometry):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_sha") != kernel_sha() or t.get("workload") != workload or t.get("geometry") != geometry:
+    if t.get("kernel_sha") != kernel_sha(kernel) or t.get("workload") != workload or t.get("geometry") != geometry:
         return None
     return t.get("bytes_per_launch")
 
@@ -125,13 +131,14 @@ def _rows(pattern):
     return out
 
 
-def summarize_profiles(root, workload):
+def summarize_profiles(root, workload, kernel="k_sweep"):
     """Turn rocprofv3 outputs under root (stats/, fetch/, write/) into the
     traffic summary: per-dispatch FETCH_SIZE and WRITE_SIZE of the sweep
     kernel, each scaled by the same counter on the calibration copy."""
     stats = _rows(os.path.join(root, "stats", "**", "*kernel_stats.csv"))
-    res = {"workload": workload, "kernel_sha": kernel_sha(), "copy_bytes": COPY_BYTES}
-    sweeps = [row for row in stats if "k_sweep" in row.get("Name", "")]
+    res = {"workload": workload, "kernel": kernel, "kernel_sha": kernel_sha(kernel if kernel in KERNEL_SRCS else None),
+           "copy_bytes": COPY_BYTES}
+    sweeps = [row for row in stats if kernel in row.get("Name", "")]
     if sweeps:
         top = max(sweeps, key=lambda r: float(r.get("TotalDurationNs", 0)))
         res["kernel_stats"] = {k: top[k] for k in ("Name", "Calls", "AverageNs", "MinNs", "MaxNs", "Percentage")
@@ -143,7 +150,7 @@ def summarize_profiles(root, workload):
         for row in rows:
             name = row.get("Kernel_Name", row.get("Kernel-Name", ""))
             val = float(row.get("Counter_Value", row.get("Counter-Value", "nan")))
-            if "k_sweep" in name:
+            if kernel in name:
                 sweep.append(val)
             elif "copy" in name.lower() or "elementwise" in name.lower():
                 copy.append(val)
@@ -242,7 +249,10 @@ def run_serve_bench(args, w):
 
 
 def run_batch_bench(args, w):
-    """Throughput of the batched sweep: one step = the whole batch."""
+    """Throughput of the batched sweep: one step = one anneal of the whole
+    batch.  The batch plan (replica state, work tables, the instantiated
+    graph) is built once, untimed; every step launches it with new seeds, and
+    HIP events on its stream time the launches."""
     import numpy as np
     import torch
     from paper_2407_10205_amd import phia
@@ -253,39 +263,57 @@ def run_batch_bench(args, w):
     probs = [phia.Problem(J, h, path="i8", stream=stream.cuda_stream) for J, h in insts]
     n = len(probs)
     R, T, s = w["R"], w["T"], w["sched"]
-    reps, steps = [R] * n, [T] * n
-    scheds = [s] * n
     su = float(sum(p.N for p in probs)) * R * T
-
-    def one(seed0):
-        phia.batch_run(probs, reps, steps, scheds, [seed0 + i for i in range(n)])
+    t = time.perf_counter()
+    plan = phia.Batch(probs, [R] * n, [T] * n, [s] * n)
+    log(f"batch plan built in {time.perf_counter() - t:.1f} s")
+    kinds = [p.info()["sweep_kernel"] for p in probs]
 
     for i in range(args.warmup):
-        one(900_000 * (i + 1))
+        plan.launch([900_000 * (i + 1) + j for j in range(n)])
+        plan.sync()
     torch.cuda.synchronize()
+    events = []
     t0 = time.perf_counter()
     for i in range(args.steps):
-        one(1_000_000 * (i + 1))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.launch([1_000_000 * (i + 1) + j for j in range(n)])
+        e1.record(stream)
+        events.append((e0, e1))
+    plan.sync()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     value = su * args.steps / wall
+    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     best = [p.best_exact()[0] for p in probs[:4]]
     # explicit teardown while the runtime and the stream are alive
+    plan.close()
     for p in probs:
         p.close()
     torch.cuda.synchronize()
     if args.calibrate_copy:
         calibrate_copy()
+    achieved = su * OPS_PER_SPIN_UPDATE / (kern_ms / 1000)
+    kernel = "k_batch_fp4" if all(k == 3 for k in kinds) else "k_batch_fp4 + k_sweep_mfma (batch)"
+    cpu = None
+    if not args.no_cpu:
+        stride = max(1, n // 64)
+        sample = insts[::stride + 1] if stride > 1 else insts
+        cpu = cpu_baseline_instances(sample, R, T, s, args.cpu_seconds,
+                                     f"instances 0, {stride + 1}, {2 * (stride + 1)}, ... of the batch")
     out = {"metric": "spin-updates/s", "value": value, "unit": "spin-updates/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": 1000 * wall / args.steps, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "fp8xfp4" if kernel == "k_batch_fp4" else "i8",
+           "data": "synthetic",
            "config": {"workload": w["desc"], "instances": n, "replicas": R, "hmc_steps": T, "path": "i8",
-                      "schedule": s, "spin_updates_per_step": su},
-           "roofline": {"bound": "alu", "achieved": su * OPS_PER_SPIN_UPDATE / (wall / args.steps),
-                        "peak": VALU_OPS_PEAK, "unit": "ops/s",
-                        "frac": su * OPS_PER_SPIN_UPDATE / (wall / args.steps) / VALU_OPS_PEAK, "traffic": None,
-                        "kernel": "k_sweep_mfma (batch)"},
-           "cpu_baseline": None, "best_energy_first4": [int(b) for b in best]}
+                      "operands": "FP8 spins x FP4 couplings (exact for integer couplings in the FP4 set)",
+                      "schedule": s, "spin_updates_per_step": su, "sweep_kernel": kernel},
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_OPS_PEAK, "unit": "ops/s",
+                        "frac": achieved / VALU_OPS_PEAK,
+                        "traffic": recorded_traffic("k_batch_fp4", "batch4096", w["desc"], None),
+                        "kernel": kernel, "kernel_ms": kern_ms, "ops_per_spin_update": OPS_PER_SPIN_UPDATE},
+           "cpu_baseline": cpu, "best_energy_first4": [int(b) for b in best]}
     print(json.dumps(out), flush=True)
 
 
@@ -480,7 +508,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5, help="timed complete anneals")
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="maxcut800", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="batch4096", choices=sorted(WORKLOADS))
     ap.add_argument("--path", default=None, choices=["i8", "bf16hilo", "fp32", "auto"],
                     help="coupling path (default: the workload's, int8 unless stated)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -491,6 +519,8 @@ def main():
                     help="also run a plain 256 MiB device copy (byte-counter calibration)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise rocprofv3 outputs in DIR/{stats,fetch,write} and exit")
+    ap.add_argument("--profile-kernel", default=None,
+                    help="kernel name (substring) the summary covers (default: the workload's sweep kernel)")
     ap.add_argument("--geometry-out", metavar="FILE", help="write the launch geometry used to FILE")
     ap.add_argument("--deriv", default="tanh", choices=["tanh", "poly2"],
                     help="derivative factor of the kick: sech^2 (Eq. 8) or the FPGA's quadratic (POLY2 mode)")
@@ -504,7 +534,8 @@ def main():
     ap.add_argument("--chunk", type=int, default=250, help="serving workload: steps per scheduling round")
     args = ap.parse_args()
     if args.summarize_profiles:
-        res = summarize_profiles(args.summarize_profiles, WORKLOADS[args.workload]["desc"])
+        kern = args.profile_kernel or ("k_batch_fp4" if args.workload == "batch4096" else "k_sweep")
+        res = summarize_profiles(args.summarize_profiles, WORKLOADS[args.workload]["desc"], kern)
         geo = os.path.join(args.summarize_profiles, "geometry.json")
         if os.path.exists(geo):
             with open(geo) as f:

@@ -310,6 +310,33 @@ phia_status phia_eval_fmath(int32_t kind, const float* in, const uint64_t* in64,
 phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,
                            const int64_t* steps, const phia_schedule* scheds, const uint64_t* seeds);
 
+/* A reusable batch plan: phia_batch_run split into its parts, so that the
+ * set-up (replica state of every problem, work tables, the captured and
+ * instantiated HIP graph) happens once and the anneal of all problems can be
+ * launched many times.  phia_batch_create takes the same arguments as
+ * phia_batch_run without the seeds; the plan then holds the problems' replica
+ * state: phia_anneal_start, phia_anneal_run, phia_set_state, phia_autotune and
+ * phia_server_submit on them return PHIA_ESTATE until phia_batch_destroy
+ * (reading results stays allowed and waits for the batch).  Instances whose
+ * integer couplings are all FP4 values (0, +-1, +-2, +-3, +-4, +-6), with
+ * N <= 512 and no accept/reject step, run in one persistent kernel that
+ * takes 32-replica work items from a queue, largest first; the others run in
+ * one kernel per bucket of similar instances after it.
+ *
+ * phia_batch_launch enqueues one whole anneal of every problem with
+ * seeds[i] (host array of count seeds) on the plan's stream (problem 0's
+ * stream, or a private one when that is the null stream) and returns without
+ * waiting; results are bit-identical to phia_anneal of each problem with its
+ * seed.  phia_batch_sync waits for the last launch.  phia_batch_destroy waits
+ * and releases the plan (not the problems).  Destroying a member problem
+ * first makes later launches return PHIA_ESTATE. */
+typedef struct phia_batch phia_batch;
+phia_status phia_batch_create(phia_problem* const* probs, int32_t count, const int32_t* replicas,
+                              const int64_t* steps, const phia_schedule* scheds, phia_batch** out);
+phia_status phia_batch_launch(phia_batch* b, const uint64_t* seeds);
+phia_status phia_batch_sync(phia_batch* b);
+void phia_batch_destroy(phia_batch* b);
+
 /* ---------------------------------------------------------------- serving --
  * A server anneals submitted problems with continuous batching on one GPU.
  * Requests are admitted in arrival order when a slot is free and their

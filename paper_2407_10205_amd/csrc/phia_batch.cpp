@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <map>
+#include <new>
 #include <tuple>
 #include <vector>
 
@@ -252,17 +253,111 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
 
 }  // namespace phia
 
-extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas,
-                                      const int64_t* steps, const phia_schedule* scheds, const uint64_t* seeds)
+// ----------------------------------------------------------- batch plan --
+// A batch plan owns the replica state of its problems and one instantiated
+// HIP graph that runs every problem's whole anneal: a reset of the work
+// queue, the persistent sweep over the instances it holds (couplings that are
+// all FP4 integers, N <= 512, no accept/reject step), then, for the other
+// instances, an init kernel and one sweep kernel per bucket of similar
+// instances.  Seeds live in device memory and are refreshed before each
+// launch, so the graph is built once and launched many times.
+struct phia_batch {
+    int dev = 0;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    std::vector<phia_problem*> probs;
+    std::vector<int64_t> steps;
+    // persistent sweep
+    BatchInst* dinst = nullptr;
+    BatchItem* ditems = nullptr;
+    int nitems = 0;
+    int* dqueue = nullptr;
+    size_t fp4_lds = 0;
+    int n_fp4 = 0;
+    // one-item-per-workgroup sweep of the remaining instances
+    SweepArgs* dtab = nullptr;
+    // seeds: pinned host staging copy and device array
+    uint64_t* hseeds = nullptr;
+    uint64_t* dseeds = nullptr;
+    hipEvent_t seed_ev = nullptr;
+    bool seed_pending = false;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool launched = false;
+    bool broken = false;  // a member problem was destroyed
+};
+
+namespace phia {
+
+// Wait for the batch's work (results of its problems are read after it).
+hipError_t batch_wait(phia_batch* b)
+{
+    if (!b || !b->launched) return hipSuccess;
+    hipError_t e = hipStreamSynchronize(b->st);
+    if (e == hipSuccess) b->launched = false;
+    return e;
+}
+
+// A member problem is being destroyed: wait for the batch and drop it.
+void batch_forget(phia_batch* b, phia_problem* p)
+{
+    if (!b) return;
+    (void)batch_wait(b);
+    for (phia_problem*& q : b->probs)
+        if (q == p) q = nullptr;
+    b->broken = true;
+}
+
+}  // namespace phia
+
+namespace {
+
+// Instances the persistent sweep takes: int8 path with FP4 operand
+// couplings, N <= 512, no accept/reject step, row energies within int32.
+bool fp4_batchable(const phia_problem* p)
+{
+    return p->path == PHIA_PATH_I8 && p->dJ4 && p->Np <= kBatchFp4MaxNp && !p->mh &&
+           2 * p->maxrow * static_cast<int64_t>(p->N) < (int64_t(1) << 31);
+}
+
+void release(phia_batch* b)
+{
+    if (!b) return;
+    (void)hipSetDevice(b->dev);
+    if (b->launched && b->st) (void)hipStreamSynchronize(b->st);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->dinst) (void)hipFree(b->dinst);
+    if (b->ditems) (void)hipFree(b->ditems);
+    if (b->dqueue) (void)hipFree(b->dqueue);
+    if (b->dtab) (void)hipFree(b->dtab);
+    if (b->dseeds) (void)hipFree(b->dseeds);
+    if (b->hseeds) (void)hipHostFree(b->hseeds);
+    if (b->seed_ev) (void)hipEventDestroy(b->seed_ev);
+    for (phia_problem* p : b->probs)
+        if (p && p->batch == b) p->batch = nullptr;
+    if (b->own_stream && b->st) (void)hipStreamDestroy(b->st);
+    delete b;
+}
+
+}  // namespace
+
+extern "C" {
+
+phia_status phia_batch_create(phia_problem* const* probs, int32_t count, const int32_t* replicas,
+                              const int64_t* steps, const phia_schedule* scheds, phia_batch** out)
 {
     clear_error();
-    if (!probs || !replicas || !steps || !scheds || !seeds) return fail(PHIA_EINVAL, "null argument");
+    if (!out) return fail(PHIA_EINVAL, "out is null");
+    *out = nullptr;
+    if (!probs || !replicas || !steps || !scheds) return fail(PHIA_EINVAL, "null argument");
     if (count < 1 || count > (1 << 22)) return fail(PHIA_EINVAL, "count = %d out of range", count);
     const int dev = probs[0] ? probs[0]->dev : 0;
     for (int i = 0; i < count; ++i) {
         phia_problem* p = probs[i];
         phia_status st = check_usable(p);
         if (st != PHIA_OK) return st;
+        if (p->batch) return fail(PHIA_ESTATE, "problem %d already belongs to a batch", i);
         if (p->dev != dev) return fail(PHIA_EINVAL, "problem %d is on another device", i);
         if (p->path == PHIA_PATH_FP32) return fail(PHIA_EINVAL, "problem %d uses the FP32 path; batches run I8/BF16HILO", i);
         if (p->Np > kBatchMaxNp) return fail(PHIA_ERANGE, "problem %d: N = %d exceeds %d for batches", i, p->N, kBatchMaxNp);
@@ -279,39 +374,86 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
     if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
     if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(nullptr, e, "synchronise");
 
+    phia_batch* b = new (std::nothrow) phia_batch();
+    if (!b) return fail(PHIA_ENOMEM, "host allocation failed");
+    b->dev = dev;
+    b->probs.assign(probs, probs + count);
+    b->steps.assign(steps, steps + count);
     // Stream capture needs a stream other than the null stream.
-    hipStream_t st = probs[0]->st;
-    bool own_stream = false;
-    if (!st) {
-        if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+    b->st = probs[0]->st;
+    if (!b->st) {
+        if ((e = hipStreamCreateWithFlags(&b->st, hipStreamNonBlocking)) != hipSuccess) {
+            delete b;
             return hip_fail(nullptr, e, "stream creation");
-        own_stream = true;
+        }
+        b->own_stream = true;
     }
-    std::vector<hipStream_t> saved(static_cast<size_t>(count));
-    for (int i = 0; i < count; ++i) {
-        saved[i] = probs[i]->st;
-        probs[i]->st = st;
-    }
-    auto restore = [&]() {
-        for (int i = 0; i < count; ++i) probs[i]->st = saved[i];
-        if (own_stream) (void)hipStreamDestroy(st);
+    auto bail = [&](phia_status st_) {
+        release(b);
+        return st_;
     };
+    if ((e = hipMalloc(&b->dseeds, sizeof(uint64_t) * count)) != hipSuccess ||
+        (e = hipHostMalloc(&b->hseeds, sizeof(uint64_t) * count, hipHostMallocDefault)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&b->seed_ev, hipEventDisableTiming)) != hipSuccess)
+        return bail(fail(PHIA_ENOMEM, "seed buffers: %s", hipGetErrorString(e)));
+    for (int i = 0; i < count; ++i) b->hseeds[i] = 0;
 
-    // Replica state and schedules (host tables stay alive until the final sync).
+    // Replica state and schedules of every problem (host tables kept until
+    // the device has copied them).
     std::vector<std::vector<float>> ctabs(static_cast<size_t>(count));
-    std::vector<SweepArgs> init_tab(static_cast<size_t>(count));
+    std::vector<BatchInst> insts;
+    std::vector<BatchItem> items;
+    std::vector<int64_t> item_cost;
+    std::vector<SweepArgs> init_tab;
     std::map<std::tuple<int, int, int, int>, Bucket> buckets;
-    phia_status st_ = PHIA_OK;
-    for (int i = 0; i < count && st_ == PHIA_OK; ++i) {
+    for (int i = 0; i < count; ++i) {
         phia_problem* p = probs[i];
         kick_factors(p, steps[i], &scheds[i], ctabs[i]);
         bool reuse = false;
-        st_ = setup_state(p, replicas[i], steps[i], &scheds[i], seeds[i], ctabs[i], reuse, false);
-        if (st_ != PHIA_OK) break;
+        phia_status st_ = setup_state(p, replicas[i], steps[i], &scheds[i], 0, ctabs[i], reuse, false);
+        if (st_ != PHIA_OK) return bail(st_);
+        p->batch = b;
         p->geo = Geometry{};
         p->geo.ok = true;
-        p->geo.mt = 1;
         p->geo.G = 1;
+        p->geo.j_lds = 1;
+        if (fp4_batchable(p)) {
+            p->geo.kind = 3;
+            p->geo.mt = 2;
+            p->geo.rows = kBatchRows;
+            p->geo.nblocks = (replicas[i] + kBatchRows - 1) / kBatchRows;
+            p->geo.ngroups = p->geo.nblocks;
+            BatchInst a{};
+            a.J4 = static_cast<const unsigned char*>(p->dJ4);
+            a.h = p->dh;
+            a.ctab = p->dctab;
+            a.seed = b->dseeds + i;
+            a.x = p->dx;
+            a.v = p->dv;
+            a.bestE = p->dbestE;
+            a.bestS = p->dbestS;
+            a.bestStep = p->dbestStep;
+            a.k0 = 0;
+            a.k1 = steps[i];
+            a.L = p->L;
+            a.eps = p->eps;
+            a.gamma = p->gamma;
+            a.N = p->N;
+            a.Np = p->Np;
+            a.R = replicas[i];
+            a.deriv = p->deriv;
+            a.init = 1;
+            const bool dbl = batch_fp4_lds_bytes(p->Np, true) <= static_cast<size_t>(kLdsMax);
+            b->fp4_lds = std::max(b->fp4_lds, batch_fp4_lds_bytes(p->Np, dbl));
+            for (int blk = 0; blk < p->geo.nblocks; ++blk) {
+                items.push_back(BatchItem{static_cast<int32_t>(insts.size()), blk});
+                const int rows = std::min(kBatchRows, replicas[i] - blk * kBatchRows);
+                item_cost.push_back(static_cast<int64_t>(p->Np) * steps[i] * (rows > 16 ? 2 : 1));
+            }
+            insts.push_back(a);
+            continue;
+        }
+        p->geo.mt = 1;
         p->geo.rows = 16;
         p->geo.nblocks = (replicas[i] + 15) / 16;
         p->geo.ngroups = p->geo.nblocks;
@@ -320,7 +462,7 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         const int jl = sweep_batch_lds_bytes(p->path, p->Np, 1, p->mh) <= static_cast<size_t>(kLdsMax) ? 1 : 0;
         p->geo.cbw = cbw;
         p->geo.j_lds = jl;
-        if ((st_ = setup_mh_geometry(p)) != PHIA_OK) break;
+        if ((st_ = setup_mh_geometry(p)) != PHIA_OK) return bail(st_);
         SweepArgs a = sweep_args(p);
         a.inc = 0;  // table launches carry no flip-incremental variant
         a.J = p->dJ;
@@ -331,90 +473,162 @@ extern "C" phia_status phia_batch_run(phia_problem* const* probs, int32_t count,
         a.ncb = ncb;
         a.rows = 16;
         a.j_lds = jl;
-        init_tab[static_cast<size_t>(i)] = a;
-        Bucket& b = buckets[std::make_tuple(p->path, cbw, jl, p->mh)];
-        b.path = p->path;
-        b.cbw = cbw;
-        b.jl = jl;
-        b.mh = p->mh;
-        b.lds = std::max(b.lds, sweep_batch_lds_bytes(p->path, p->Np, jl, p->mh));
+        a.seedp = b->dseeds + i;
+        init_tab.push_back(a);
+        Bucket& bk = buckets[std::make_tuple(p->path, cbw, jl, p->mh)];
+        bk.path = p->path;
+        bk.cbw = cbw;
+        bk.jl = jl;
+        bk.mh = p->mh;
+        bk.lds = std::max(bk.lds, sweep_batch_lds_bytes(p->path, p->Np, jl, p->mh));
         for (int blk = 0; blk < p->geo.nblocks; ++blk) {
             SweepArgs it = a;
             it.block = blk;
             it.nblocks = blk + 1;
             it.ngroups = 1;
-            b.items.push_back(it);
+            bk.items.push_back(it);
         }
     }
-    if (st_ != PHIA_OK) {
-        restore();
-        return st_;
+    b->n_fp4 = static_cast<int>(insts.size());
+    // Persistent sweep items: costliest first, so that the queue's tail holds
+    // the shortest items.
+    {
+        std::vector<size_t> ord(items.size());
+        for (size_t t = 0; t < ord.size(); ++t) ord[t] = t;
+        std::stable_sort(ord.begin(), ord.end(), [&](size_t u, size_t w) { return item_cost[u] > item_cost[w]; });
+        std::vector<BatchItem> sorted;
+        sorted.reserve(items.size());
+        for (size_t t : ord) sorted.push_back(items[t]);
+        items.swap(sorted);
     }
-    size_t total_items = 0;
-    for (auto& kv : buckets) {
-        order_items(kv.second.items);
-        total_items += kv.second.items.size();
+    b->nitems = static_cast<int>(items.size());
+    if (!items.empty()) {
+        if ((e = hipMalloc(&b->dinst, sizeof(BatchInst) * insts.size())) != hipSuccess ||
+            (e = hipMalloc(&b->ditems, sizeof(BatchItem) * items.size())) != hipSuccess ||
+            (e = hipMalloc(&b->dqueue, 256)) != hipSuccess)
+            return bail(fail(PHIA_ENOMEM, "work table allocation failed"));
+        if ((e = hipMemcpy(b->dinst, insts.data(), sizeof(BatchInst) * insts.size(), hipMemcpyHostToDevice)) !=
+                hipSuccess ||
+            (e = hipMemcpy(b->ditems, items.data(), sizeof(BatchItem) * items.size(), hipMemcpyHostToDevice)) !=
+                hipSuccess)
+            return bail(hip_fail(nullptr, e, "work table upload"));
     }
-    // One device table: the init entries, then every bucket's items.
+    // One device table for the remaining instances: init entries, then every
+    // bucket's items.
     std::vector<SweepArgs> host_tab(init_tab);
     std::vector<size_t> offs;
     for (auto& kv : buckets) {
+        order_items(kv.second.items);
         offs.push_back(host_tab.size());
         host_tab.insert(host_tab.end(), kv.second.items.begin(), kv.second.items.end());
     }
-    SweepArgs* dtab = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    if ((e = hipMalloc(&dtab, sizeof(SweepArgs) * host_tab.size())) != hipSuccess) {
-        restore();
-        return fail(PHIA_ENOMEM, "work table allocation failed");
+    if (!host_tab.empty()) {
+        if ((e = hipMalloc(&b->dtab, sizeof(SweepArgs) * host_tab.size())) != hipSuccess)
+            return bail(fail(PHIA_ENOMEM, "work table allocation failed"));
+        if ((e = hipMemcpy(b->dtab, host_tab.data(), sizeof(SweepArgs) * host_tab.size(), hipMemcpyHostToDevice)) !=
+            hipSuccess)
+            return bail(hip_fail(nullptr, e, "work table upload"));
+        for (auto& kv : buckets)
+            if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, kv.second.lds)) != hipSuccess)
+                return bail(hip_fail(nullptr, e, "kernel attributes"));
     }
-    auto cleanup = [&]() {
-        if (exec) (void)hipGraphExecDestroy(exec);
-        if (graph) (void)hipGraphDestroy(graph);
-        (void)hipFree(dtab);
-        restore();
-    };
-    if ((e = hipMemcpyAsync(dtab, host_tab.data(), sizeof(SweepArgs) * host_tab.size(), hipMemcpyHostToDevice,
-                            st)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
-        cleanup();
-        return hip_fail(nullptr, e, "work table upload");
+    if (b->nitems > 0 && batch_fp4_grid(b->fp4_lds) < 1)
+        return bail(fail(PHIA_EDEVICE, "the persistent batch sweep does not fit the device"));
+    // schedules and state set-up above ran on the problems' streams
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return bail(hip_fail(nullptr, e, "state set-up"));
+
+    if ((e = hipStreamBeginCapture(b->st, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return bail(hip_fail(nullptr, e, "graph capture"));
+    hipError_t le = hipSuccess;
+    if (b->nitems > 0) {
+        le = launch_batch_queue_reset(b->dqueue, b->st);
+        if (le == hipSuccess) le = launch_batch_fp4(b->dinst, b->ditems, b->nitems, b->dqueue, b->fp4_lds, b->st);
     }
-    for (auto& kv : buckets)
-        if ((e = prepare_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, kv.second.lds)) != hipSuccess) {
-            cleanup();
-            return hip_fail(nullptr, e, "kernel attributes");
-        }
-    if ((e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal)) != hipSuccess) {
-        cleanup();
-        return hip_fail(nullptr, e, "graph capture");
-    }
-    hipError_t le = launch_init_batch(dtab, count, st);
+    if (le == hipSuccess && !init_tab.empty()) le = launch_init_batch(b->dtab, static_cast<int>(init_tab.size()), b->st);
     size_t bi = 0;
     for (auto& kv : buckets) {
         if (le == hipSuccess)
-            le = launch_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, dtab + offs[bi],
-                                    static_cast<int>(kv.second.items.size()), kv.second.lds, st);
+            le = launch_sweep_batch(kv.second.path, kv.second.cbw, kv.second.mh, b->dtab + offs[bi],
+                                    static_cast<int>(kv.second.items.size()), kv.second.lds, b->st);
         ++bi;
     }
-    e = hipStreamEndCapture(st, &graph);
-    if (le != hipSuccess || e != hipSuccess) {
-        cleanup();
-        return hip_fail(nullptr, le != hipSuccess ? le : e, "graph capture of the batch");
-    }
-    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess ||
-        (e = hipGraphLaunch(exec, st)) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess) {
-        for (int i = 0; i < count; ++i) probs[i]->poisoned = true;
-        cleanup();
-        return hip_fail(nullptr, e, "batch graph");
-    }
-    cleanup();
+    e = hipStreamEndCapture(b->st, &b->graph);
+    if (le != hipSuccess || e != hipSuccess)
+        return bail(hip_fail(nullptr, le != hipSuccess ? le : e, "graph capture of the batch"));
+    if ((e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0)) != hipSuccess)
+        return bail(hip_fail(nullptr, e, "graph instantiation"));
     for (int i = 0; i < count; ++i) {
-        probs[i]->k = steps[i];
-        probs[i]->started = true;
-        probs[i]->has_run = true;
+        probs[i]->k = 0;
+        probs[i]->started = false;
+        probs[i]->has_run = false;
     }
-    (void)total_items;
+    *out = b;
     return PHIA_OK;
 }
+
+phia_status phia_batch_launch(phia_batch* b, const uint64_t* seeds)
+{
+    clear_error();
+    if (!b || !seeds) return fail(PHIA_EINVAL, "null argument");
+    hipError_t e = hipSetDevice(b->dev);
+    if (e != hipSuccess) return hip_fail(nullptr, e, "hipSetDevice");
+    if (b->broken) return fail(PHIA_ESTATE, "a problem of the batch has been destroyed");
+    for (phia_problem* p : b->probs)
+        if (p->poisoned) return fail(PHIA_EDEVICE, "a problem of the batch is poisoned");
+    // the staging copy of the previous launch has been read before it is rewritten
+    if (b->seed_pending && (e = hipEventSynchronize(b->seed_ev)) != hipSuccess)
+        return hip_fail(nullptr, e, "seed staging");
+    const size_t n = b->probs.size();
+    for (size_t i = 0; i < n; ++i) b->hseeds[i] = seeds[i];
+    if ((e = hipMemcpyAsync(b->dseeds, b->hseeds, sizeof(uint64_t) * n, hipMemcpyHostToDevice, b->st)) !=
+            hipSuccess ||
+        (e = hipEventRecord(b->seed_ev, b->st)) != hipSuccess)
+        return hip_fail(nullptr, e, "seed upload");
+    b->seed_pending = true;
+    if ((e = hipGraphLaunch(b->exec, b->st)) != hipSuccess) {
+        for (phia_problem* p : b->probs) p->poisoned = true;
+        return hip_fail(nullptr, e, "batch graph launch");
+    }
+    b->launched = true;
+    for (size_t i = 0; i < n; ++i) {
+        phia_problem* p = b->probs[i];
+        p->seed = seeds[i];
+        p->k = b->steps[i];
+        p->started = true;
+        p->has_run = true;
+    }
+    return PHIA_OK;
+}
+
+phia_status phia_batch_sync(phia_batch* b)
+{
+    clear_error();
+    if (!b) return fail(PHIA_EINVAL, "null argument");
+    hipError_t e = hipSetDevice(b->dev);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->st);
+    if (e != hipSuccess) {
+        for (phia_problem* p : b->probs)
+            if (p) p->poisoned = true;
+        return hip_fail(nullptr, e, "batch");
+    }
+    b->launched = false;
+    return PHIA_OK;
+}
+
+void phia_batch_destroy(phia_batch* b) { release(b); }
+
+phia_status phia_batch_run(phia_problem* const* probs, int32_t count, const int32_t* replicas, const int64_t* steps,
+                           const phia_schedule* scheds, const uint64_t* seeds)
+{
+    clear_error();
+    if (!seeds) return fail(PHIA_EINVAL, "null argument");
+    phia_batch* b = nullptr;
+    phia_status st = phia_batch_create(probs, count, replicas, steps, scheds, &b);
+    if (st != PHIA_OK) return st;
+    st = phia_batch_launch(b, seeds);
+    if (st == PHIA_OK) st = phia_batch_sync(b);
+    release(b);
+    return st;
+}
+
+}  // extern "C"

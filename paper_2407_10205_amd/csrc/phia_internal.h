@@ -67,6 +67,7 @@ struct SweepArgs {
     uint64_t* mhbuf;            // [2][ngroups][G][rows][4] tagged 32-bit halves of (energy, kinetic) partials
     // batch mode: the launch argument points at one entry per workgroup
     const SweepArgs* table;     // work items (device), or null
+    const uint64_t* seedp;      // batch mode: the item's seed in device memory (replaces seed), or null
     int32_t block;              // replica block (group) of this work item
     int32_t member;             // group member of this work item (table launches of the group sweep)
 };
@@ -98,6 +99,40 @@ int max_coresident_pp(int ncb, int fp4, size_t lds_bytes);
 // batch mode: 16-replica work items, one workgroup each, up to 512 columns
 constexpr int kBatchMaxNp = kWaves * 4 * 16;
 hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st);
+
+// Persistent batched sweep (k_batch_fp4): every workgroup takes 32-replica
+// work items from a queue until it is empty.  One entry per instance.
+struct BatchInst {
+    const unsigned char* J4;    // FP4 fragments [Np/16][ceil(Np/128)][64][16] (k order of the interleaved sweep)
+    const int32_t* h;           // [Np] fields in sigma units, zero padded
+    const float* ctab;          // [T] c_k
+    const uint64_t* seed;       // the instance's seed (device)
+    float* x;                   // [R][Np]
+    float* v;                   // [R][Np]
+    int64_t* bestE;             // [R]
+    int8_t* bestS;              // [R][Np]
+    int64_t* bestStep;          // [R]
+    int64_t k0, k1;             // steps [k0, k1) of this launch
+    int64_t L;                  // momentum refresh period
+    float eps, gamma;
+    int32_t N, Np, R;
+    int32_t deriv;              // 0: sech^2, 1: POLY2
+    int32_t init;               // 1: draw x ~ N(0, I), v = 0 and reset the records first (k0 = 0)
+    int32_t pad_;
+};
+struct BatchItem {
+    int32_t inst;               // index into the instance table
+    int32_t block;              // 32-replica block of that instance
+};
+constexpr int kBatchRows = 32;           // replicas per work item
+constexpr int kBatchFp4MaxNp = 512;      // columns of the persistent sweep (8 waves x 4 column blocks)
+// LDS the persistent sweep needs for an instance of Np columns (J slice and
+// spins double-buffered, or single-buffered when double does not fit).
+size_t batch_fp4_lds_bytes(int Np, bool double_buffered);
+hipError_t launch_batch_fp4(const BatchInst* insts, const BatchItem* items, int nitems, int* queue, size_t lds,
+                            hipStream_t st);
+hipError_t launch_batch_queue_reset(int* queue, hipStream_t st);
+int batch_fp4_grid(size_t lds);
 size_t sweep_batch_lds_bytes(int path, int Np, int j_lds, int mh);
 hipError_t prepare_sweep_batch(int path, int cbw, int mh, size_t lds_bytes);
 hipError_t launch_sweep_batch(int path, int cbw, int mh, const SweepArgs* dtable, int nitems, size_t lds_bytes,

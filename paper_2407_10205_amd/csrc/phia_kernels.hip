@@ -47,13 +47,10 @@
 #include <type_traits>
 
 #include "phia_devmath.h"
+#include "phia_devsweep.h"
 #include "phia_internal.h"
 
 namespace phia {
-
-typedef int v4i __attribute__((ext_vector_type(4)));
-typedef float v4f __attribute__((ext_vector_type(4)));
-typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 
 // ------------------------------------------------------------------ init --
 __global__ void __launch_bounds__(256) k_init(SweepArgs a)
@@ -144,103 +141,6 @@ __device__ __forceinline__ long long wave_sum16_i64(long long v)
     return v;
 }
 
-// Momentum draws happen once every L steps; a real call keeps the unrolled
-// sweep loops from holding many Philox states live at once.
-// Block-shared momentum draws.  One Philox block of the momentum stream,
-// (replica, columns 8 c8 .. 8 c8 + 7), yields the draws of those 8 columns;
-// each of its four 64-bit words gives two of them by Box-Muller exactly as
-// dev_gauss computes them (gc: the cosine draw of the even column, gs: the
-// sine draw of the odd one).
-__device__ __forceinline__ void gauss_pair(uint64_t word, float& gc, float& gs)
-{
-    const float ua = dev_uniform(static_cast<uint32_t>(word));
-    const float ub = dev_uniform(static_cast<uint32_t>(word >> 32));
-    const float rho = sqrtf(-2.0f * dev_ln_unit(ua));
-    float c, sn;
-    dev_sincos_2pi(ub, c, sn);
-    gc = rho * c;
-    gs = rho * sn;
-}
-
-// Draws 4 half .. 4 half + 3 of the block (pairs 2 half and 2 half + 1).
-__device__ __forceinline__ void gauss_block_half(uint64_t seed, uint64_t replica, uint64_t round, uint64_t c8, int half,
-                                                 float (&g)[4])
-{
-    const u64x4 o = dev_philox(c8, round, replica, kTagV, seed, 0);
-    gauss_pair(half ? o.w[2] : o.w[0], g[0], g[1]);
-    gauss_pair(half ? o.w[3] : o.w[1], g[2], g[3]);
-}
-
-// All 8 draws of the block, g[i & 7] = draw i.
-__device__ __forceinline__ void gauss_block(uint64_t seed, uint64_t replica, uint64_t round, uint64_t c8,
-                                            float (&g)[8])
-{
-    const u64x4 o = dev_philox(c8, round, replica, kTagV, seed, 0);
-#pragma unroll
-    for (int p = 0; p < 4; ++p) gauss_pair(o.w[p], g[2 * p], g[2 * p + 1]);
-}
-
-// Value v of lane `src` (all lanes of the wave active).
-__device__ __forceinline__ float lane_read(int src, float v)
-{
-    return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute(src * 4, __builtin_bit_cast(int, v)));
-}
-
-__device__ __attribute__((noinline)) float gauss_v(uint64_t seed, uint64_t replica, uint64_t round, int i)
-{
-    return dev_gauss(seed, kTagV, replica, round, static_cast<uint64_t>(i));
-}
-
-// DERIV 0: sech^2 (Eq. 8); 1: the POLY2 quadratic.  Callers branch on the
-// (uniform) mode outside their element loops so that the elements of a lane
-// interleave.
-template <int DERIV>
-__device__ __forceinline__ float kick_t(float x, float v, int I, float ck, float eps, float gamma)
-{
-    const float u = gamma * x;
-    const float d = DERIV ? dev_poly2(u) : dev_sech2(u);
-    const float p = ck * d;
-    const float g = __builtin_fmaf(p, static_cast<float>(I), -x);
-    return __builtin_fmaf(eps, g, v);
-}
-
-__device__ __forceinline__ float kick(float x, float v, int I, float ck, float eps, float gamma, int deriv)
-{
-    const float u = gamma * x;
-    const float d = deriv ? dev_poly2(u) : dev_sech2(u);
-    const float p = ck * d;
-    const float g = __builtin_fmaf(p, static_cast<float>(I), -x);
-    return __builtin_fmaf(eps, g, v);
-}
-
-// Sum over the 16 lanes of a DPP row (lanes sharing lane / 16), result in
-// every lane of the row.  All 64 lanes must be active.
-__device__ __forceinline__ int row_sum16_dpp(int v)
-{
-    v += __builtin_amdgcn_update_dpp(0, v, 0xb1, 0xf, 0xf, false);   // quad_perm [1,0,3,2]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x4e, 0xf, 0xf, false);   // quad_perm [2,3,0,1]
-    v += __builtin_amdgcn_update_dpp(0, v, 0x141, 0xf, 0xf, false);  // row_half_mirror
-    v += __builtin_amdgcn_mov_dpp(v, 0x140, 0xf, 0xf, true);          // row_mirror (every lane has a source)
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum16(int v)
-{
-    // sum over the 16 lanes that share lane / 16
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    v += __shfl_xor(v, 8, 64);
-    return v;
-}
-
-__device__ __forceinline__ int wave_sum64(int v)
-{
-    v = wave_sum16(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
-}
 
 // --------------------------------------------------------- FP32 sweep --
 // Thread t owns columns i = t + 256 c (c < CPT) of kFp32Rows replicas.
@@ -863,7 +763,8 @@ template <int PATH, int MT, int CBW, bool GROUP, bool JLDS, bool TRACE, bool BAT
 __global__ void __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(CBW == 1 && MT == 1 ? 4 : 2)))
 k_sweep_mfma(SweepArgs args)
 {
-    const SweepArgs a = BATCH ? args.table[blockIdx.x] : args;
+    SweepArgs a = BATCH ? args.table[blockIdx.x] : args;
+    if (BATCH && a.seedp) a.seed = *a.seedp;
     const bool jl = BATCH ? (a.j_lds != 0) : JLDS;
     constexpr int RB = 16 * MT;
     constexpr int ESZ = (PATH == kPathI8) ? 1 : 2;
@@ -1746,8 +1647,6 @@ __device__ __forceinline__ void unpack_signs_fp4(uint32_t w, unsigned char* dst)
     *reinterpret_cast<uint2*>(dst) = uint2{fp4_byte(w & 0xffu), fp4_byte((w >> 8) & 0xffu)};
 }
 
-typedef int v8i __attribute__((ext_vector_type(8)));
-
 // S . J^T for one 16x16 tile with FP4 operands and FP32 accumulation
 // (v_mfma_scale_f32_16x16x128_f8f6f4, scales 1.0): every product and partial
 // sum is an integer below 2^24, so the result is exact.  Even and odd k
@@ -2184,7 +2083,8 @@ int max_coresident_pp(int ncb, int fp4, size_t lds)
 // One workgroup per instance: x ~ N(0, I), v = 0, records reset.
 __global__ void __launch_bounds__(256) k_init_batch(const SweepArgs* table)
 {
-    const SweepArgs& a = table[blockIdx.x];
+    SweepArgs a = table[blockIdx.x];
+    if (a.seedp) a.seed = *a.seedp;
     const int64_t total = static_cast<int64_t>(a.R) * a.Np;
     for (int64_t idx = threadIdx.x; idx < total; idx += blockDim.x) {
         const int64_t r = idx / a.Np;

@@ -12,7 +12,8 @@ namespace phia {
 // Launch geometry of the MFMA sweep (see k_sweep_mfma).
 struct Geometry {
     bool ok = false;
-    int kind = 0;      // 0: k_sweep_mfma; k_sweep_pp (interleaved sub-blocks) with 1: int8, 2: FP4 operands
+    int kind = 0;      // 0: k_sweep_mfma; k_sweep_pp (interleaved sub-blocks) with 1: int8, 2: FP4 operands;
+                       // 3: persistent batch sweep (k_batch_fp4)
     int mt = 1;        // 16-replica row tiles per workgroup
     int cbw = 2;       // max 16-column blocks per wave
     int G = 1;         // workgroups splitting the columns of one replica block
@@ -52,6 +53,12 @@ phia_status launch_group_chunk(::phia_problem* const* probs, int count, const in
 }  // namespace phia
 
 struct phia_problem;
+struct phia_batch;
+namespace phia {
+hipError_t batch_wait(::phia_batch* b);
+void batch_forget(::phia_batch* b, ::phia_problem* p);
+phia_status check_owned(const ::phia_problem* p);
+}  // namespace phia
 struct phia_problem {
     int dev = 0;
     hipStream_t st = nullptr;
@@ -107,4 +114,5 @@ struct phia_problem {
     phia::Geometry geo;
     phia::Geometry tuned;  // autotuned geometry for tuned_R replicas
     int32_t tuned_R = 0;
+    struct phia_batch* batch = nullptr;  // batch plan that holds the replica state, or null
 };

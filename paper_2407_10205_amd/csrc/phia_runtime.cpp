@@ -553,6 +553,15 @@ phia_status check_usable(const phia_problem* p)
     return PHIA_OK;
 }
 
+// Calls that change a problem's anneal: not while a batch plan holds its state.
+phia_status check_owned(const phia_problem* p)
+{
+    phia_status st = check_usable(p);
+    if (st != PHIA_OK) return st;
+    if (p->batch) return fail(PHIA_ESTATE, "the problem belongs to a batch plan (phia_batch_destroy releases it)");
+    return PHIA_OK;
+}
+
 }  // namespace phia
 
 // =================================================================== ABI ==
@@ -706,6 +715,7 @@ void phia_destroy(phia_problem* p)
 {
     if (!p) return;
     (void)hipSetDevice(p->dev);
+    if (p->batch) batch_forget(p->batch, p);
     if (!p->poisoned && p->st) (void)hipStreamSynchronize(p->st);
     if (!p->poisoned && !p->st) (void)hipDeviceSynchronize();
     free_state(p);
@@ -879,7 +889,7 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
                               uint64_t seed)
 {
     clear_error();
-    phia_status st = check_usable(p);
+    phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if ((st = check_schedule(replicas, steps, s)) != PHIA_OK) return st;
     std::vector<float> ctab;
@@ -965,7 +975,7 @@ extern "C" {
 phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
 {
     clear_error();
-    phia_status st = check_usable(p);
+    phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if (!p->started) return fail(PHIA_ESTATE, "phia_anneal_start has not been called");
     if (k_end < p->k || k_end > p->T) return fail(PHIA_EINVAL, "k_end = %lld outside [%lld, %lld]", (long long)k_end,
@@ -1051,6 +1061,10 @@ static phia_status need_results(phia_problem* p)
     phia_status st = check_usable(p);
     if (st != PHIA_OK) return st;
     if (!p->started || !p->has_run) return fail(PHIA_ESTATE, "no anneal steps have run");
+    if (p->batch) {
+        hipError_t e = batch_wait(p->batch);
+        if (e != hipSuccess) return hip_fail(p, e, "batch");
+    }
     return phia_sync(p);
 }
 
@@ -1170,6 +1184,10 @@ phia_status phia_get_state(phia_problem* p, float* x, float* v, int64_t* k)
     phia_status st = check_usable(p);
     if (st != PHIA_OK) return st;
     if (!p->started) return fail(PHIA_ESTATE, "no anneal started");
+    if (p->batch) {
+        hipError_t eb = batch_wait(p->batch);
+        if (eb != hipSuccess) return hip_fail(p, eb, "batch");
+    }
     st = phia_sync(p);
     if (st != PHIA_OK) return st;
     const size_t pitch = sizeof(float) * p->Np, w = sizeof(float) * p->N;
@@ -1185,7 +1203,7 @@ phia_status phia_get_state(phia_problem* p, float* x, float* v, int64_t* k)
 phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int64_t k)
 {
     clear_error();
-    phia_status st = check_usable(p);
+    phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if (!p->started) return fail(PHIA_ESTATE, "no anneal started");
     if (!x || !v) return fail(PHIA_EINVAL, "x and v are required");
@@ -1218,7 +1236,7 @@ phia_status phia_set_state(phia_problem* p, const float* x, const float* v, int6
 phia_status phia_autotune(phia_problem* p, int32_t replicas, int64_t probe_steps, double* best_us)
 {
     clear_error();
-    phia_status st = check_usable(p);
+    phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if (replicas < 1 || replicas > (1 << 20)) return fail(PHIA_EINVAL, "replicas = %d outside [1, 2^20]", replicas);
     if (probe_steps < 10 || probe_steps > 100000) return fail(PHIA_EINVAL, "probe_steps outside [10, 100000]");

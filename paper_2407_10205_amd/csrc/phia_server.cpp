@@ -297,7 +297,7 @@ phia_status phia_server_submit(phia_server* s, phia_problem* p, int32_t replicas
 {
     clear_error();
     if (!s || !ticket) return fail(PHIA_EINVAL, "null argument");
-    phia_status st = check_usable(p);
+    phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if ((st = check_schedule(replicas, max_steps, sched)) != PHIA_OK) return st;
     if (p->dev != s->dev) return fail(PHIA_EINVAL, "problem is on another device");

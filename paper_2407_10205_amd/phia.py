@@ -30,7 +30,8 @@ EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_noalloc", "phia_anneal_sta
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_replica_mh", "phia_get_state",
            "phia_set_state", "phia_get_info", "phia_set_incremental", "phia_incremental_stats",
            "phia_set_exchange_seq", "phia_set_wait_limit", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
-           "phia_batch_run", "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
+           "phia_batch_run", "phia_batch_create", "phia_batch_launch", "phia_batch_sync", "phia_batch_destroy",
+           "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
            "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
            "phia_destroy", "phia_last_error", "phia_version")
 
@@ -101,6 +102,9 @@ def _declare(lib):
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
         "phia_batch_run": [P, I32, P, P, P, P],
+        "phia_batch_create": [P, I32, P, P, P, P],
+        "phia_batch_launch": [P, P],
+        "phia_batch_sync": [P],
         "phia_server_create": [C.c_size_t, I32, I32, I32, P],
         "phia_server_submit": [P, P, I32, I64, I64, P, U64, P],
         "phia_server_poll": [P, U64, P],
@@ -117,6 +121,8 @@ def _declare(lib):
     lib.phia_destroy.restype = None
     lib.phia_server_destroy.argtypes = [P]
     lib.phia_server_destroy.restype = None
+    lib.phia_batch_destroy.argtypes = [P]
+    lib.phia_batch_destroy.restype = None
     lib.phia_last_error.restype = C.c_char_p
     lib.phia_version.restype = C.c_char_p
 
@@ -324,6 +330,63 @@ class Problem:
         d = {f: getattr(i, f) for f, _ in Info._fields_}
         d["path_name"] = PATH_NAMES.get(d["path"], "?")
         return d
+
+
+def _schedules(steps, schedules):
+    n = len(schedules)
+    scheds = (Schedule * n)()
+    keep = []
+    for i, sc in enumerate(schedules):
+        one = make_schedule(int(steps[i]), sc["eps"], sc["gamma"], sc.get("beta0"), sc.get("beta1"),
+                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"), sc.get("mh"))
+        keep.append(one)
+        C.memmove(C.byref(scheds, i * C.sizeof(Schedule)), C.byref(one), C.sizeof(Schedule))
+    return scheds, keep
+
+
+class Batch:
+    """A reusable batch plan (phia_batch_create): set up once, then launch
+    the anneal of every problem many times with new seeds."""
+
+    def __init__(self, problems, replicas, steps, schedules):
+        n = len(problems)
+        self.problems = list(problems)
+        arr = (C.c_void_p * n)(*[p._p for p in problems])
+        self._reps = np.ascontiguousarray(replicas, dtype=np.int32)
+        stp = np.ascontiguousarray(steps, dtype=np.int64)
+        scheds, keep = _schedules(stp, schedules)
+        b = C.c_void_p()
+        _check(lib().phia_batch_create(arr, n, _ptr(self._reps), _ptr(stp), C.cast(scheds, C.c_void_p),
+                                       C.byref(b)))
+        del keep
+        self._b = b
+        for p, r in zip(problems, self._reps):
+            p.R = int(r)
+
+    def launch(self, seeds):
+        """Enqueue one anneal of every problem (returns without waiting)."""
+        sd = np.ascontiguousarray(seeds, dtype=np.uint64)
+        _check(lib().phia_batch_launch(self._b, _ptr(sd)))
+
+    def sync(self):
+        _check(lib().phia_batch_sync(self._b))
+
+    def close(self):
+        if getattr(self, "_b", None):
+            lib().phia_batch_destroy(self._b)
+            self._b = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
 
 
 def batch_run(problems, replicas, steps, schedules, seeds):

@@ -557,6 +557,63 @@ def test_batch_matches_single_runs_and_oracle(P, O):
         p.close()
 
 
+def test_batch_plan_relaunch_and_ownership(P, O):
+    """A batch plan built once and launched twice with different seeds: every
+    instance bit-identical to annealing it alone with that seed, on the
+    persistent FP4 sweep (every k-block count 1-4, workgroups with idle
+    waves, single-buffered spins at Np = 512, partial 32-replica blocks)
+    and on the one-item-per-workgroup sweep (8-bit couplings) in the same
+    graph.  While the plan exists its problems refuse to anneal alone."""
+    specs = [("sk", 40, 32), ("reg3", 100, 45), ("sk", 200, 16), ("reg3", 330, 64), ("sk", 450, 33),
+             ("reg3", 470, 32), ("fixed", 150, 20), ("sk", 17, 5)]
+    insts, probs = [], []
+    for i, (kind, N, R) in enumerate(specs):
+        if kind == "sk":
+            J, h = inst.sk_pm1(N, 60 + i)
+        elif kind == "reg3":
+            J, h = inst.regular3_pm1(N, 60 + i)
+        else:
+            J, h = inst.sk_gauss_fixed(N, 60 + i, frac_bits=5, bits=8)
+        insts.append((J, h))
+        probs.append(P.Problem(J, h, path="i8"))
+    reps = [R for _, _, R in specs]
+    T = 150
+    sched = [dict(eps=0.2, gamma=1.0, beta0=0.05, beta1=2.0 + i, refresh_L=23, deriv="poly2" if i == 3 else "tanh")
+             for i in range(len(specs))]
+    plan = P.Batch(probs, reps, [T] * len(specs), sched)
+    kinds = [p.info()["sweep_kernel"] for p in probs]
+    say("sweep kernels", kinds)
+    assert kinds[:6] == [3] * 6 and kinds[6] == 0
+    with pytest.raises(P.PhiaError) as e:
+        probs[0].anneal(8, 10, 0.2, 1.0, beta0=0.1, beta1=1.0)
+    assert e.value.code == -7
+    for launch in range(2):
+        seeds = [1000 * launch + 7 * i + 3 for i in range(len(specs))]
+        plan.launch(seeds)
+        plan.sync()
+        for i, p in enumerate(probs):
+            got = p.replica_best() + p.get_state()[:2]
+            J, h = insts[i]
+            q = P.Problem(J, h, path="i8")
+            sc = sched[i]
+            q.anneal(reps[i], T, sc["eps"], sc["gamma"], beta0=sc["beta0"], beta1=sc["beta1"],
+                     refresh_L=sc["refresh_L"], seed=seeds[i], deriv=sc["deriv"])
+            ref = q.replica_best() + q.get_state()[:2]
+            q.close()
+            for u, w in zip(ref, got):
+                assert np.array_equal(u, w), (launch, specs[i])
+        # one replica of the largest instance against the oracle
+        J, h = insts[5]
+        o = O.anneal(J.astype(np.int32), h.astype(np.int32), 0, 1, O.beta_linear(0.05, 7.0, T), 0.2, 1.0, 23,
+                     seeds[5], r0=31)
+        E, S, K = probs[5].replica_best()
+        assert E[31] == o.bestE[0] and K[31] == o.bestStep[0] and np.array_equal(S[31], o.bestS[0])
+    plan.close()
+    probs[0].anneal(8, 10, 0.2, 1.0, beta0=0.1, beta1=1.0)  # released by the plan
+    for p in probs:
+        p.close()
+
+
 def _serve_specs():
     out = []
     for i, (N, dense, R, T) in enumerate([(40, False, 32, 900), (120, True, 16, 1200), (300, False, 20, 700),
