@@ -482,14 +482,15 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
     threads = cpu["threads"]
     units = [grid_units(J, h) for J, h in insts]
     betas = O.beta_linear(sched["beta0"], sched["beta1"], T)
-    # calibrate on the first instance
-    f, Ji, hi = units[0]
+    # calibrate on the whole sample with a few steps, then size the run to the budget
+    calib = 16
     t = time.perf_counter()
-    O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=10,
-             threads=threads)
-    per_su = (time.perf_counter() - t) / (10 * threads * Ji.shape[0])
+    for f, Ji, hi in units:
+        O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=calib,
+                 threads=threads)
+    per_step = (time.perf_counter() - t) / calib
     total_n = sum(u[1].shape[0] for u in units)
-    steps = int(max(10, min(T, budget_s / max(per_su * threads * total_n, 1e-12))))
+    steps = int(max(calib, min(T, budget_s / max(per_step, 1e-12))))
     su = 0.0
     t = time.perf_counter()
     for f, Ji, hi in units:
