@@ -65,6 +65,12 @@ WORKLOADS = {
                            "sk_ising, sk_uniform, spin_model; fractional ones on the 2^-6 grid); 256 replicas x "
                            "max(1000, 10 N) steps per run; target: exhaustive ground state for N <= 20, else the "
                            "best energy of a 20x longer run"),
+    "maxcut256": dict(gen="er_maxcut", args=dict(N=256, p=0.06, seed=0, signed=True), R=4, T=10000,
+                      sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
+                      desc="maxcut ER G(256,0.06) w=+-1, h=0, few replicas (default 4) x 1e4 steps"),
+    "reg3_4000": dict(gen="regular3_pm1", args=dict(N=4000, seed=0), R=64, T=10000, path="auto",
+                      sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
+                      desc="random 3-regular N=4000 J=+-1, h in {-1,0,1}, 64 replicas x 1e4 steps"),
     "sk2000": dict(gen="sk_gauss_fixed", args=dict(N=2000, seed=0, frac_bits=5, bits=8), R=512, T=20000,
                    sched=dict(eps=0.2, gamma=1.0, beta0=0.02, beta1=0.6, refresh_L=25),
                    desc="SK N=2000 J~N(0,1) 8-bit fixed point (2^-5), h in [-1,1], 512 replicas x 2e4 steps"),
@@ -78,7 +84,8 @@ WORKLOADS = {
 
 CSRC = os.path.join(ROOT, "paper_2407_10205_amd", "csrc")
 # sources whose hash identifies each profiled kernel's code
-KERNEL_SRCS = {"k_batch_fp4": ["phia_batch_kernel.hip", "phia_devsweep.h", "phia_devmath.h"]}
+KERNEL_SRCS = {"k_batch_fp4": ["phia_batch_kernel.hip", "phia_devsweep.h", "phia_devmath.h"],
+               "k_sweep_valu": ["phia_valu_kernel.hip", "phia_devsweep.h", "phia_devmath.h"]}
 DEFAULT_SRCS = ["phia_kernels.hip", "phia_devsweep.h", "phia_devmath.h"]
 PROFILES = os.path.join(ROOT, "profiles")
 COPY_BYTES = 256 << 20  # plain device copy used to calibrate the byte counters
@@ -510,7 +517,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5, help="timed complete anneals")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="batch4096", choices=sorted(WORKLOADS))
-    ap.add_argument("--path", default=None, choices=["i8", "bf16hilo", "fp32", "auto"],
+    ap.add_argument("--replicas", type=int, default=None, help="replica count (default: the workload's)")
+    ap.add_argument("--path", default=None, choices=["i8", "bf16hilo", "fp32", "ell", "auto"],
                     help="coupling path (default: the workload's, int8 unless stated)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu", action="store_true")
@@ -567,7 +575,7 @@ def main():
         run_tts_sweep(args, w)
         return
     J, h = make_instance(w)
-    N, R, T, s = J.shape[0], w["R"], w["T"], w["sched"]
+    N, R, T, s = J.shape[0], args.replicas or w["R"], w["T"], w["sched"]
     if args.path is None:
         args.path = w.get("path", "i8")
     stream = torch.cuda.Stream()
@@ -637,9 +645,11 @@ def main():
                                      "incremental")}
     # counter summaries are kept per kernel and per workload variant
     profile_key = (args.workload + ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "") +
-                   ("_full" if args.no_incremental else ""))
-    kernel = ("k_sweep_fp32" if info["path_name"] == "fp32" else
+                   ("_full" if args.no_incremental else "") + (f"_r{R}" if args.replicas else ""))
+    kernel = ("k_sweep_valu" if info["sweep_kernel"] == 4 else
               "k_sweep_pp" if info["sweep_kernel"] >= 1 else "k_sweep_mfma")
+    if info["sweep_kernel"] == 4:
+        mfma_ops = 0.0  # J.s on the vector ALUs
     if args.geometry_out:
         with open(args.geometry_out, "w") as f:
             json.dump(geometry, f)

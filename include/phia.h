@@ -50,10 +50,16 @@ typedef enum {
 /* Arithmetic used for the quasi-gradient J.s (Eq. 6).  Every path computes the
  * same exact integer field, so results are identical across paths. */
 typedef enum {
-    PHIA_PATH_AUTO = 0,     /* I8 if |J| <= 127 units, else BF16HILO, else FP32      */
+    PHIA_PATH_AUTO = 0,     /* I8 if |J| <= 127 units, else BF16HILO, else FP32; ELL
+                               for sparse rows with 512 < Np <= 4096 (at most Np/192
+                               nonzeros in every row)                                */
     PHIA_PATH_FP32 = 1,     /* FP32 couplings, VALU dot products (plain sweep)       */
-    PHIA_PATH_I8 = 2,       /* int8 couplings, int8 MFMA with int32 accumulation     */
-    PHIA_PATH_BF16HILO = 3  /* J = 256 hi + lo, two BF16 MFMA planes, FP32 accumulate */
+    PHIA_PATH_I8 = 2,       /* int8 couplings, int8 MFMA with int32 accumulation;
+                               with few replicas the VALU int8 dot-product sweep
+                               (see phia_anneal_start)                              */
+    PHIA_PATH_BF16HILO = 3, /* J = 256 hi + lo, two BF16 MFMA planes, FP32 accumulate */
+    PHIA_PATH_ELL = 4       /* sparse rows: D (index, coupling) slots per row, spin
+                               gathers on the VALUs; |J| <= 32767 units, N <= 4096 */
 } phia_path;
 
 typedef struct {
@@ -109,10 +115,13 @@ typedef struct {
     int32_t replicas;       /* R of the current anneal (0 if none)                   */
     int32_t rows_per_block; /* replicas per workgroup block                          */
     int32_t j_in_lds;       /* 1: each workgroup's coupling slice resides in LDS     */
-    int32_t sweep_kernel;   /* 0: one replica block per workgroup; 1: two 16-replica
-                               sub-blocks per workgroup whose steps alternate, so
-                               the column-split exchange of one overlaps the
-                               other's compute                                      */
+    int32_t sweep_kernel;   /* 0: one replica block per workgroup; 1 (int8 operands)
+                               and 2 (FP4 operands): two 16-replica sub-blocks per
+                               workgroup whose steps alternate, so the column-split
+                               exchange of one overlaps the other's compute; 3: the
+                               persistent batch sweep (phia_batch_*); 4: the VALU
+                               sweep, all columns of rows_per_block replicas per
+                               workgroup (FP32 and ELL paths, I8 with few replicas) */
     int64_t steps;          /* T of the current anneal                               */
     int64_t step;           /* next step to run                                      */
     int64_t max_abs_J;      /* max |J| in units                                      */
@@ -130,7 +139,7 @@ typedef struct {
  * [1, 16384] (else PHIA_EINVAL), and within what the resolved path's sweep
  * holds (else PHIA_ERANGE): N <= 5056 on I8 (4992 for metropolis
  * schedules, which then fail at phia_anneal_start), N <= 2496 on BF16HILO,
- * N <= 4096 on FP32.  opt may be NULL (frac_bits = -1, quantize = 0, AUTO,
+ * N <= 4096 on FP32 and ELL (ELL also needs |J| <= 32767 units).  opt may be NULL (frac_bits = -1, quantize = 0, AUTO,
  * device 0, null stream).  On success *out owns device copies of J and h. */
 phia_status phia_create(const double* J, const double* h, int32_t N,
                         const phia_options* opt, phia_problem** out);
@@ -168,8 +177,20 @@ phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, int64_t steps
                                 int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                                 int64_t* best_energy_units, int32_t* best_replica);
 
+/* Largest replica count for which an anneal on the I8 path takes the VALU
+ * int8 dot-product sweep by default, for padded size Np (0: never).  Below it
+ * J.s is a matrix-vector product per replica and the sweep is bound by the
+ * stream of J, which 16-row matrix-core tiles would mostly pad; the value is
+ * the crossover measured against the matrix-core sweeps on MI355X. */
+int32_t phia_valu_crossover(int32_t Np);
+
 /* Allocate replica state and draw x ~ N(0, I) (App. A, A3) for step 0.
- * Enqueued on the problem's stream; returns without waiting. */
+ * Enqueued on the problem's stream; returns without waiting.  The sweep's
+ * launch geometry is fixed here from (path, Np, replicas): on the I8 path,
+ * anneals of few replicas (replicas <= phia_valu_crossover(Np), no
+ * accept/reject step) run the VALU int8 dot-product sweep, where J.s is a
+ * matrix-vector product per replica; larger ones the matrix-core sweeps.
+ * A tuned or cached geometry (phia_autotune) takes precedence. */
 phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps,
                               const phia_schedule* schedule, uint64_t seed);
 

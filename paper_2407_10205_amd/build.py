@@ -17,8 +17,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libphia.so")
 OBJDIR = os.path.join(PKG, "_build")
 
-SOURCES = ["phia_kernels.hip", "phia_batch_kernel.hip", "phia_runtime.cpp", "phia_batch.cpp", "phia_server.cpp",
-           "phia_noalloc.hip"]
+SOURCES = ["phia_kernels.hip", "phia_batch_kernel.hip", "phia_valu_kernel.hip", "phia_runtime.cpp", "phia_batch.cpp",
+           "phia_server.cpp", "phia_noalloc.hip"]
 
 # -ffp-contract=off: no implicit fused multiply-adds (the sweep's op sequence
 # is fixed and every fma is explicit).  Correctly rounded FP32 division and

@@ -359,7 +359,9 @@ phia_status phia_batch_create(phia_problem* const* probs, int32_t count, const i
         if (st != PHIA_OK) return st;
         if (p->batch) return fail(PHIA_ESTATE, "problem %d already belongs to a batch", i);
         if (p->dev != dev) return fail(PHIA_EINVAL, "problem %d is on another device", i);
-        if (p->path == PHIA_PATH_FP32) return fail(PHIA_EINVAL, "problem %d uses the FP32 path; batches run I8/BF16HILO", i);
+        if (p->path != PHIA_PATH_I8 && p->path != PHIA_PATH_BF16HILO)
+            return fail(PHIA_EINVAL, "problem %d uses the %s path; batches run I8/BF16HILO", i,
+                        p->path == PHIA_PATH_FP32 ? "FP32" : "ELL");
         if (p->Np > kBatchMaxNp) return fail(PHIA_ERANGE, "problem %d: N = %d exceeds %d for batches", i, p->N, kBatchMaxNp);
         if ((st = check_schedule(replicas[i], steps[i], &scheds[i])) != PHIA_OK) return st;
         if (steps[i] >= (int64_t(1) << 31)) return fail(PHIA_EINVAL, "problem %d: too many steps", i);

@@ -1,6 +1,7 @@
 // Device helpers shared by the sweep kernels of the PHIA library (gfx950):
 // block-shared Box-Muller draws of the momentum stream, the kick of one
-// element (Eq. 5, Eq. 7-8, App. A A7), and wave reductions.
+// element (Eq. 5, Eq. 7-8, App. A A7), wave reductions, and the pieces of the
+// accept/reject step.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -109,6 +110,57 @@ __device__ __forceinline__ int wave_sum64(int v)
     v = wave_sum16(v);
     v += __shfl_xor(v, 16, 64);
     v += __shfl_xor(v, 32, 64);
+    return v;
+}
+
+// Accept/reject at the end of every trajectory of L steps (App. A: H(x, v) =
+// beta E(sgn x) + x.x/2 + v.v/2; Table 3, state 4: acceptance and temperature).
+constexpr uint32_t kTagMH = 2;
+
+// x^2 + v^2 on the grid 2^-24, capped at 2^46 grid units: the squares are exact
+// in double and their sum rounds once, so sums over a replica are exact int64
+// and independent of the order of summation.
+__device__ __forceinline__ long long kin_units(float x, float v)
+{
+    const double t = (static_cast<double>(x) * static_cast<double>(x) +
+                      static_cast<double>(v) * static_cast<double>(v)) * 0x1p24;
+    return t < 0x1p46 ? static_cast<long long>(__builtin_rint(t)) : (1ll << 46);
+}
+
+// Outcome of trajectory `traj` of stream replica rs: 1 accepted, 0 rejected,
+// -1 taken without a decision (start energy Es not known: the first
+// trajectory starts from the initial draw).  Ee: energy at its end, dq: change
+// of the kinetic units over all columns, beta: inverse temperature of its last
+// step, lam: the replica's beta multiplier.  Accept iff ln u < -dH with
+// dH = beta lam sigma (Ee - Es) + dq 2^-25 in double and u the first uniform
+// of the stream's accept/reject counter (0, traj, rs, tag 2).
+__device__ __forceinline__ int mh_outcome(uint64_t seed, uint64_t rs, int64_t traj, int64_t Es, int64_t Ee,
+                                          int64_t dq, float beta, float lam, float sigma)
+{
+    if (Es == INT64_MIN) return -1;
+    const double bl = static_cast<double>(beta) * static_cast<double>(lam);
+    const double dE = static_cast<double>(Ee - Es);
+    const double dQ = static_cast<double>(dq) * 0x1p-25;
+    const double dH = __builtin_fma(bl * static_cast<double>(sigma), dE, dQ);
+    const u64x4 o = dev_philox(0, static_cast<uint64_t>(traj), rs, kTagMH, seed, 0);
+    const float lnu = dev_ln_unit(dev_uniform(static_cast<uint32_t>(o.w[0])));
+    return (static_cast<double>(lnu) < -dH) ? 1 : 0;
+}
+
+// beta multiplier after an outcome, clamped to [2^-10, 2^10].
+__device__ __forceinline__ float mh_lambda(float lam, int outcome, float up, float down)
+{
+    if (outcome < 0) return lam;
+    const float l = lam * (outcome ? up : down);
+    return fminf(fmaxf(l, 0x1p-10f), 0x1p10f);
+}
+
+__device__ __forceinline__ long long wave_sum16_i64(long long v)
+{
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    v += __shfl_xor(v, 8, 64);
     return v;
 }
 

@@ -24,6 +24,7 @@ struct SweepArgs {
     const float* ctab;          // [T] c_k = (beta_k * gamma) * sigma
     float eps, gamma;
     int32_t deriv;              // 0: sech^2 (Eq. 8), 1: POLY2 quadratic
+    int32_t ell_d;              // ELL slots per row (ELL path)
     int64_t L;                  // momentum refresh period
     uint64_t seed;
     int64_t k0, k1;             // steps [k0, k1) of this launch
@@ -74,6 +75,8 @@ struct SweepArgs {
 
 // Layout of packed couplings.
 //  FP32: float [Np][Np] row-major.
+//  ELL:  int32 [D][Np]: slot d of row i is (J_ij << 16) | j for the d-th
+//        nonzero J_ij of row i (ascending j), zero for unused slots.
 //  I8:   fragment-major int8: [Np/16 col blocks][Np/64 k blocks][64 lanes][16],
 //        lane l holds J[cb*16 + l%16][kb*64 + 16*(l/16) + t], t < 16.
 //  BF16: [Np/16][Np/32 k chunks][2 planes hi, lo][64 lanes][8 bf16],
@@ -81,7 +84,12 @@ struct SweepArgs {
 //        with J = 256 hi + lo, lo in [-128, 127].
 
 hipError_t launch_init(const SweepArgs& a, hipStream_t st);
-hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st);
+// VALU sweeps (k_sweep_valu): RB replicas and all columns per workgroup.
+enum ValuForm : int { kValuFp32 = 0, kValuDot8 = 1, kValuEll = 2 };
+constexpr int kValuMaxNp = 4096;  // 16 columns per thread
+size_t valu_lds_bytes(int form, int rb, int Np);
+bool valu_variant(int form, int rb, int mh);  // a compiled (form, rows, accept/reject) combination
+hipError_t launch_sweep_valu(int form, int rb, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_mfma(int path, int mt, int cbw, const SweepArgs& a, size_t lds_bytes, hipStream_t st);
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a);
 hipError_t launch_argmin(const int64_t* bestE, int32_t R, int64_t* out2, hipStream_t st);

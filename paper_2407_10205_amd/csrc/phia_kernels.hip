@@ -17,8 +17,6 @@
 // Kernels:
 //   k_init         x ~ N(0, I) (App. A, A3), records and accept/reject
 //                  state reset.
-//   k_sweep_fp32   plain sweep: FP32 couplings, VALU dot products, one
-//                  workgroup owns kFp32Rows replicas for the whole launch.
 //   k_sweep_mfma   J.s on matrix cores: int8 x int8 -> int32
 //                  (v_mfma_i32_16x16x64_i8) or two BF16 planes J = 256 hi + lo
 //                  with FP32 accumulation (v_mfma_f32_16x16x32_bf16).  A
@@ -87,338 +85,6 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t st)
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_init, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a);
     return hipGetLastError();
-}
-
-// ------------------------------------------------------- shared helpers --
-// Accept/reject at the end of every trajectory of L steps (App. A: H(x, v) =
-// beta E(sgn x) + x.x/2 + v.v/2; Table 3, state 4: acceptance and temperature).
-constexpr uint32_t kTagMH = 2;
-
-// x^2 + v^2 on the grid 2^-24, capped at 2^46 grid units: the squares are exact
-// in double and their sum rounds once, so sums over a replica are exact int64
-// and independent of the order of summation.
-__device__ __forceinline__ long long kin_units(float x, float v)
-{
-    const double t = (static_cast<double>(x) * static_cast<double>(x) +
-                      static_cast<double>(v) * static_cast<double>(v)) * 0x1p24;
-    return t < 0x1p46 ? static_cast<long long>(__builtin_rint(t)) : (1ll << 46);
-}
-
-// Outcome of trajectory `traj` of stream replica rs: 1 accepted, 0 rejected,
-// -1 taken without a decision (start energy Es not known: the first
-// trajectory starts from the initial draw).  Ee: energy at its end, dq: change
-// of the kinetic units over all columns, beta: inverse temperature of its last
-// step, lam: the replica's beta multiplier.  Accept iff ln u < -dH with
-// dH = beta lam sigma (Ee - Es) + dq 2^-25 in double and u the first uniform
-// of the stream's accept/reject counter (0, traj, rs, tag 2).
-__device__ __forceinline__ int mh_outcome(uint64_t seed, uint64_t rs, int64_t traj, int64_t Es, int64_t Ee,
-                                          int64_t dq, float beta, float lam, float sigma)
-{
-    if (Es == INT64_MIN) return -1;
-    const double bl = static_cast<double>(beta) * static_cast<double>(lam);
-    const double dE = static_cast<double>(Ee - Es);
-    const double dQ = static_cast<double>(dq) * 0x1p-25;
-    const double dH = __builtin_fma(bl * static_cast<double>(sigma), dE, dQ);
-    const u64x4 o = dev_philox(0, static_cast<uint64_t>(traj), rs, kTagMH, seed, 0);
-    const float lnu = dev_ln_unit(dev_uniform(static_cast<uint32_t>(o.w[0])));
-    return (static_cast<double>(lnu) < -dH) ? 1 : 0;
-}
-
-// beta multiplier after an outcome, clamped to [2^-10, 2^10].
-__device__ __forceinline__ float mh_lambda(float lam, int outcome, float up, float down)
-{
-    if (outcome < 0) return lam;
-    const float l = lam * (outcome ? up : down);
-    return fminf(fmaxf(l, 0x1p-10f), 0x1p10f);
-}
-
-__device__ __forceinline__ long long wave_sum16_i64(long long v)
-{
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    v += __shfl_xor(v, 4, 64);
-    v += __shfl_xor(v, 8, 64);
-    return v;
-}
-
-
-// --------------------------------------------------------- FP32 sweep --
-// Thread t owns columns i = t + 256 c (c < CPT) of kFp32Rows replicas.
-template <int CPT, bool MH>
-__global__ void __launch_bounds__(256) k_sweep_fp32(SweepArgs a)
-{
-    constexpr int RB = kFp32Rows;
-    extern __shared__ __align__(16) float sS[];  // [RB][Np] spins as +-1.0f
-    __shared__ int64_t sPart[RB][4];
-    __shared__ int64_t sBest[RB];
-    __shared__ int sImp[RB];
-    // accept/reject bookkeeping (used only when a.mh)
-    __shared__ int64_t mEs[RB], mQ0[RB], mEl[RB];
-    __shared__ long long mPart[RB][4];
-    __shared__ float mLam[RB];
-    __shared__ int mOut[RB], mAcc[RB], mDec[RB];
-    constexpr bool mh = MH;
-
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int Np = a.Np, N = a.N;
-    const int64_t rb0 = static_cast<int64_t>(blockIdx.x) * RB;
-    const float* __restrict__ J = static_cast<const float*>(a.J);
-
-    float x[RB][CPT], v[RB][CPT];
-    int hc[CPT];
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int i = tid + 256 * c;
-        hc[c] = (i < Np) ? a.h[i] : 0;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            const bool ok = (rb0 + r < a.R) && (i < Np);
-            x[r][c] = ok ? a.x[(rb0 + r) * Np + i] : 0.0f;
-            v[r][c] = ok ? a.v[(rb0 + r) * Np + i] : 0.0f;
-        }
-    }
-    int64_t bstep = -1;
-    if (tid < RB) {
-        const bool ok = rb0 + tid < a.R;
-        sBest[tid] = ok ? a.bestE[rb0 + tid] : INT64_MAX;
-        bstep = ok ? a.bestStep[rb0 + tid] : -1;
-        if (mh) {
-            const int64_t gq = rb0 + tid;
-            mEs[tid] = ok ? a.mhE[gq * 2] : INT64_MIN;
-            mEl[tid] = ok ? a.mhE[gq * 2 + 1] : 0;
-            mQ0[tid] = ok ? a.mhQ[gq] : 0;
-            mLam[tid] = ok ? a.lam[gq] : 1.0f;
-            mAcc[tid] = ok ? a.mhc[gq * 2] : 0;
-            mDec[tid] = ok ? a.mhc[gq * 2 + 1] : 0;
-        }
-    }
-    __syncthreads();
-    float lamr[RB];
-#pragma unroll
-    for (int r = 0; r < RB; ++r) lamr[r] = mh ? mLam[r] : 1.0f;
-    // kinetic units of this thread's elements of row r, summed into mPart[r][wave]
-    auto kin_rows = [&]() {
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            long long q = 0;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) q += kin_units(x[r][c], v[r][c]);
-            q = wave_sum16_i64(q);
-            q += __shfl_xor(q, 16, 64);
-            q += __shfl_xor(q, 32, 64);
-            if (lane == 0) mPart[r][wave] = q;
-        }
-    };
-
-    for (int64_t k = a.k0; k < a.k1; ++k) {
-        if (k % a.L == 0) {
-            if (mh && k > 0) {
-                // End of trajectory k / L - 1 (energy of step k - 1 in mEl): one
-                // decision per replica; a rejected end point returns x to the
-                // trajectory's start.
-                kin_rows();
-                __syncthreads();
-                if (tid < RB) {
-                    const int64_t gq = rb0 + tid;
-                    int out = 1;
-                    if (gq < a.R) {
-                        const int64_t qe = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
-                        out = mh_outcome(a.seed, static_cast<uint64_t>(a.r_base + gq), k / a.L - 1, mEs[tid],
-                                         mEl[tid], qe - mQ0[tid], a.btab[k - 1], mLam[tid], a.sigma);
-                        if (out != 0) mEs[tid] = mEl[tid];
-                        mLam[tid] = mh_lambda(mLam[tid], out, a.mh_up, a.mh_down);
-                        if (out >= 0) {
-                            mAcc[tid] += out;
-                            mDec[tid] += 1;
-                        }
-                    }
-                    mOut[tid] = out;
-                }
-                __syncthreads();
-#pragma unroll
-                for (int r = 0; r < RB; ++r) {
-                    lamr[r] = mLam[r];
-                    if (mOut[r] == 0 && rb0 + r < a.R)
-#pragma unroll
-                        for (int c = 0; c < CPT; ++c) {
-                            const int i = tid + 256 * c;
-                            if (i < Np) x[r][c] = a.x0[(rb0 + r) * Np + i];
-                        }
-                }
-            }
-            const uint64_t rnd = static_cast<uint64_t>(k / a.L);
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int i = tid + 256 * c;
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    v[r][c] = (i < N && rb0 + r < a.R) ? gauss_v(a.seed, a.r_base + rb0 + r, rnd, i) : 0.0f;
-            }
-            if (mh) {
-                // Start of a trajectory: x snapshot and kinetic units (summed
-                // into mQ0 after the next barrier).
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    const int i = tid + 256 * c;
-#pragma unroll
-                    for (int r = 0; r < RB; ++r)
-                        if (rb0 + r < a.R && i < Np) a.x0[(rb0 + r) * Np + i] = x[r][c];
-                }
-                kin_rows();
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int i = tid + 256 * c;
-#pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                x[r][c] = __builtin_fmaf(a.eps, v[r][c], x[r][c]);
-                if (i < Np) sS[r * Np + i] = (x[r][c] >= 0.0f) ? 1.0f : -1.0f;
-            }
-        }
-        __syncthreads();
-
-        float acc[RB][CPT];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c)
-#pragma unroll
-            for (int r = 0; r < RB; ++r) acc[r][c] = 0.0f;
-        // Eight rows of J in flight per thread before their multiply-adds.
-        int j = 0;
-        for (; j + 8 <= N; j += 8) {
-            float jv[8][CPT];
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    const int i = tid + 256 * c;
-                    jv[u][c] = (i < Np) ? J[static_cast<int64_t>(j + u) * Np + i] : 0.0f;
-                }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                float sj[RB];
-#pragma unroll
-                for (int r = 0; r < RB; ++r) sj[r] = sS[r * Np + j + u];
-#pragma unroll
-                for (int c = 0; c < CPT; ++c)
-#pragma unroll
-                    for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv[u][c], sj[r], acc[r][c]);
-            }
-        }
-        for (; j < N; ++j) {
-            float sj[RB];
-#pragma unroll
-            for (int r = 0; r < RB; ++r) sj[r] = sS[r * Np + j];
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int i = tid + 256 * c;
-                const float jv = (i < Np) ? J[static_cast<int64_t>(j) * Np + i] : 0.0f;
-#pragma unroll
-                for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv, sj[r], acc[r][c]);
-            }
-        }
-
-        int I[RB][CPT];
-        int part[RB];
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            part[r] = 0;
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                const int i = tid + 256 * c;
-                I[r][c] = static_cast<int>(acc[r][c]) + hc[c];
-                const int s = (x[r][c] >= 0.0f) ? 1 : -1;
-                if (i < N) part[r] += s * (I[r][c] + hc[c]);
-            }
-            const int ws = wave_sum64(part[r]);
-            if (lane == 0) sPart[r][wave] = ws;
-        }
-        __syncthreads();
-        if (tid < RB) {
-            const int64_t tot = sPart[tid][0] + sPart[tid][1] + sPart[tid][2] + sPart[tid][3];
-            const int64_t E = -(tot / 2);
-            if (mh) {
-                mEl[tid] = E;
-                if (k % a.L == 0) mQ0[tid] = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
-            }
-            const bool ok = rb0 + tid < a.R;
-            if (ok && a.etrace) a.etrace[(rb0 + tid) * a.T + k] = E;
-            const int imp = ok && (E < sBest[tid]);
-            if (imp) {
-                sBest[tid] = E;
-                bstep = k;
-            }
-            sImp[tid] = imp;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            if (sImp[r]) {
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) {
-                    const int i = tid + 256 * c;
-                    if (i < N) a.bestS[(rb0 + r) * Np + i] = (x[r][c] >= 0.0f) ? 1 : -1;
-                }
-            }
-        }
-        const float ck = a.ctab[k];
-#pragma unroll
-        for (int c = 0; c < CPT; ++c)
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-                v[r][c] = kick(x[r][c], v[r][c], I[r][c], ck * lamr[r], a.eps, a.gamma, a.deriv);
-    }
-
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int i = tid + 256 * c;
-#pragma unroll
-        for (int r = 0; r < RB; ++r) {
-            if (rb0 + r < a.R && i < Np) {
-                a.x[(rb0 + r) * Np + i] = x[r][c];
-                a.v[(rb0 + r) * Np + i] = v[r][c];
-            }
-        }
-    }
-    if (tid < RB && rb0 + tid < a.R) {
-        a.bestE[rb0 + tid] = sBest[tid];
-        a.bestStep[rb0 + tid] = bstep;
-        if (mh) {
-            const int64_t gq = rb0 + tid;
-            a.mhE[gq * 2] = mEs[tid];
-            a.mhE[gq * 2 + 1] = mEl[tid];
-            a.mhQ[gq] = mQ0[tid];
-            a.lam[gq] = mLam[tid];
-            a.mhc[gq * 2] = mAcc[tid];
-            a.mhc[gq * 2 + 1] = mDec[tid];
-        }
-    }
-}
-
-template <bool MH>
-static hipError_t launch_fp32_t(const SweepArgs& a, hipStream_t st)
-{
-    const int cpt = (a.Np + 255) / 256;
-    const unsigned blocks = static_cast<unsigned>((a.R + kFp32Rows - 1) / kFp32Rows);
-    const size_t lds = sizeof(float) * static_cast<size_t>(kFp32Rows) * a.Np;
-    if (cpt <= 1)
-        hipLaunchKernelGGL((k_sweep_fp32<1, MH>), dim3(blocks), dim3(256), lds, st, a);
-    else if (cpt <= 2)
-        hipLaunchKernelGGL((k_sweep_fp32<2, MH>), dim3(blocks), dim3(256), lds, st, a);
-    else if (cpt <= 4)
-        hipLaunchKernelGGL((k_sweep_fp32<4, MH>), dim3(blocks), dim3(256), lds, st, a);
-    else if (cpt <= 8)
-        hipLaunchKernelGGL((k_sweep_fp32<8, MH>), dim3(blocks), dim3(256), lds, st, a);
-    else if (cpt <= 16)
-        hipLaunchKernelGGL((k_sweep_fp32<16, MH>), dim3(blocks), dim3(256), lds, st, a);
-    else
-        return hipErrorInvalidValue;
-    return hipGetLastError();
-}
-
-hipError_t launch_sweep_fp32(const SweepArgs& a, hipStream_t st)
-{
-    return a.mh ? launch_fp32_t<true>(a, st) : launch_fp32_t<false>(a, st);
 }
 
 // --------------------------------------------------------- MFMA sweep --

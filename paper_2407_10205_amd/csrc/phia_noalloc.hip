@@ -93,7 +93,7 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
 
     const Geometry g = plain_geometry(p, replicas);
     if (!g.ok) return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
-    const bool group = p->path != PHIA_PATH_FP32 && g.G > 1;
+    const bool group = g.kind != 4 && g.G > 1;
     const size_t ncb = static_cast<size_t>(p->Np / 16);
     const size_t xb = group ? 2 * static_cast<size_t>(g.ngroups) * g.rows * ncb * sizeof(uint64_t) : 0;
     const size_t pb = group ? 2 * static_cast<size_t>(g.ngroups) * g.G * g.rows * 2 * sizeof(uint64_t) : 0;
@@ -173,8 +173,9 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
     a.k1 = steps;
 
     if ((e = launch_init(a, stream)) != hipSuccess) return hip_fail(p, e, "init kernel launch");
-    if (p->path == PHIA_PATH_FP32) {
-        e = launch_sweep_fp32(a, stream);
+    if (g.kind == 4) {
+        e = launch_sweep_valu(p->path == PHIA_PATH_FP32 ? kValuFp32 : p->path == PHIA_PATH_ELL ? kValuEll : kValuDot8,
+                              g.rows, a, stream);
     } else if (g.kind >= 1) {
         // launches of at most 2^22 steps, sequence numbers running on
         uint32_t seq = 0;

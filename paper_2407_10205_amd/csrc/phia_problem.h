@@ -13,12 +13,12 @@ namespace phia {
 struct Geometry {
     bool ok = false;
     int kind = 0;      // 0: k_sweep_mfma; k_sweep_pp (interleaved sub-blocks) with 1: int8, 2: FP4 operands;
-                       // 3: persistent batch sweep (k_batch_fp4)
+                       // 3: persistent batch sweep (k_batch_fp4); 4: VALU sweep (k_sweep_valu)
     int mt = 1;        // 16-replica row tiles per workgroup
     int cbw = 2;       // max 16-column blocks per wave
     int G = 1;         // workgroups splitting the columns of one replica block
     int j_lds = 1;     // J slice resident in LDS
-    int rows = 16;     // replicas per block
+    int rows = 16;     // replicas per block (kind 4: per workgroup)
     int nblocks = 0;   // replica blocks
     int ngroups = 0;   // groups running concurrently
     int xcd_map = 0;   // group members share blockIdx % 8 (one XCD)
@@ -43,6 +43,7 @@ phia_status setup_state(::phia_problem* p, int32_t replicas, int64_t steps, cons
                         const std::vector<float>& ctab, bool& reuse, bool sync_first);
 void free_state(::phia_problem* p);
 hipError_t clear_exchange(::phia_problem* p);
+int valu_crossover(int Np);
 phia_status setup_mh_geometry(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
 Geometry plain_geometry(::phia_problem* p, int R);
@@ -66,6 +67,7 @@ struct phia_problem {
     bool exact = true;
     int64_t maxabsJ = 0;
     int64_t maxrow = 0;  // max_i (sum_j |J_ij| + |h_i|) in units
+    int ell_d = 0;       // ELL slots per row (ELL path)
     bool poisoned = false;
     // instance
     void* dJ = nullptr;

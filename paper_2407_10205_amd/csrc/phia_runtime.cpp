@@ -171,6 +171,30 @@ static void pack_i8(const std::vector<int32_t>& Ji, int N, int Np, std::vector<i
             }
 }
 
+// ELL: [D][Np] int32, D = the largest number of nonzeros in a row (at least
+// 1); slot d of row i holds (J_ij << 16) | j for the d-th nonzero of row i in
+// ascending j, zero past the row's last nonzero (coupling 0: no effect).
+static void pack_ell(const std::vector<int32_t>& Ji, int N, int Np, std::vector<int32_t>& out, int& D)
+{
+    D = 1;
+    for (int i = 0; i < N; ++i) {
+        int d = 0;
+        for (int j = 0; j < N; ++j) d += Ji[static_cast<size_t>(i) * N + j] != 0;
+        D = std::max(D, d);
+    }
+    out.assign(static_cast<size_t>(D) * Np, 0);
+    for (int i = 0; i < N; ++i) {
+        int d = 0;
+        for (int j = 0; j < N; ++j) {
+            const int32_t v = Ji[static_cast<size_t>(i) * N + j];
+            if (v == 0) continue;
+            out[static_cast<size_t>(d) * Np + i] =
+                static_cast<int32_t>((static_cast<uint32_t>(v) << 16) | static_cast<uint32_t>(j));
+            ++d;
+        }
+    }
+}
+
 static uint16_t bf16_of_int(int v)
 {
     // |v| <= 256: exact in bfloat16 (8 significant bits).
@@ -203,11 +227,24 @@ static void pack_bf16(const std::vector<int32_t>& Ji, int N, int Np, std::vector
 
 // ------------------------------------------------------- kernel geometry --
 // ------------------------------------------------------- tuning cache --
-// One line per tuned shape: "phia-tune4 path Np R kind mt cbw G jlds xcd us_per_step".
+// One line per tuned shape: "phia-tune4 path Np R kind mt cbw G jlds xcd us_per_step"
+// (kind 4, the VALU sweep: replicas per workgroup in place of mt).
 static const char* tune_cache_path() { return std::getenv("PHIA_TUNE_CACHE"); }
+
+static const char* path_name(int path)
+{
+    switch (path) {
+    case PHIA_PATH_FP32: return "FP32";
+    case PHIA_PATH_I8: return "int8";
+    case PHIA_PATH_BF16HILO: return "BF16 hi/lo";
+    case PHIA_PATH_ELL: return "ELL";
+    default: return "?";
+    }
+}
 
 static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g, int xcd = -1);
 static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd = -1);
+static bool make_geometry_valu(phia_problem* p, int R, int rb, Geometry& g);
 
 static bool lookup_tune_cache(phia_problem* p, int R)
 {
@@ -223,8 +260,9 @@ static bool lookup_tune_cache(phia_problem* p, int R)
     while (std::fscanf(f, "%31s %d %d %d %d %d %d %d %d %d %lf", tag, &pa, &np, &r, &kind, &mt, &cbw, &G, &jl, &xcd,
                        &us) == 11) {
         if (std::strcmp(tag, "phia-tune4") == 0 && pa == p->path && np == p->Np && r == R &&
-            (kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g, xcd)
-                       : make_geometry(p, R, mt, cbw, G, jl, g, xcd))) {
+            (kind == 4   ? make_geometry_valu(p, R, mt, g)
+             : kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g, xcd)
+                         : make_geometry(p, R, mt, cbw, G, jl, g, xcd))) {
             p->geo = g;
             found = true;
         }
@@ -239,7 +277,8 @@ static void append_tune_cache(const phia_problem* p, int R, const Geometry& g, d
     if (!path) return;
     FILE* f = std::fopen(path, "a");
     if (!f) return;
-    std::fprintf(f, "phia-tune4 %d %d %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.kind, g.mt, g.cbw, g.G,
+    std::fprintf(f, "phia-tune4 %d %d %d %d %d %d %d %d %d %.3f\n", p->path, p->Np, R, g.kind,
+                 g.kind == 4 ? g.rows : g.mt, g.cbw, g.G,
                  g.j_lds, g.xcd_map, us);
     std::fclose(f);
 }
@@ -274,6 +313,7 @@ static bool pick_xcd(const phia_problem* p, int G, int ngroups, int j_lds, int x
 static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g, int xcd)
 {
     const int Np = p->Np, ncb = Np / 16;
+    if (p->path != PHIA_PATH_I8 && p->path != PHIA_PATH_BF16HILO) return false;
     if (mt < 1 || mt > 2 || cbw < 1 || cbw > kCbwMax || G < 1 || G > ncb) return false;
     if (p->mh && (mt != 1 || cbw != 2)) return false;  // accept/reject variants: one row tile, two column blocks
     const int cbs_max = (ncb + G - 1) / G;
@@ -358,10 +398,84 @@ static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g
     return true;
 }
 
+// Replica counts that take the VALU sweeps by default.
+constexpr int kValuTuneMaxR = 64;  // the autotuner also times the int8 VALU sweep up to here
+
+// Largest replica count for which an int8 anneal takes the VALU dot-product
+// sweep (measured crossover against the matrix-core sweeps on MI355X).
+// Up to Np = 320 one workgroup per replica finishes a step sooner than the
+// matrix-core sweeps (about 0.9 against 1.2 us at Np = 64, 1.5 against 2.5 us
+// at Np = 256) until the replicas outnumber what the CUs run at once; from
+// Np = 384 the column-split matrix-core sweeps win at every replica count.
+// PHIA_VALU_CROSSOVER=n replaces the rule (tuning experiments; 0: never).
+int valu_crossover(int Np)
+{
+    if (const char* env = std::getenv("PHIA_VALU_CROSSOVER")) return std::atoi(env);
+    if (Np <= 64) return 1024;
+    if (Np <= 256) return 512;
+    if (Np <= 320) return 256;
+    return 0;
+}
+
+// Replicas per workgroup of the int8 VALU sweep and of the ELL sweep.
+static int valu_rows(int R) { return R > 1024 ? 2 : 1; }
+static int ell_rows(int) { return 1; }
+
+// VALU sweep (k_sweep_valu): rb replicas and all columns per workgroup; the
+// form follows the path (FP32, ELL, or the int8 dot products of the I8 path).
+static int valu_form(const phia_problem* p)
+{
+    return p->path == PHIA_PATH_FP32 ? kValuFp32 : p->path == PHIA_PATH_ELL ? kValuEll : kValuDot8;
+}
+
+static bool make_geometry_valu(phia_problem* p, int R, int rb, Geometry& g)
+{
+    const int form = valu_form(p);
+    if (p->Np > kValuMaxNp || !valu_variant(form, rb, p->mh)) return false;
+    // the int8 form: own launches only (served and batched problems run the
+    // matrix-core table kernels)
+    if (form == kValuDot8 && (p->path != PHIA_PATH_I8 || p->one_block_kernel)) return false;
+    g = Geometry{};
+    g.ok = true;
+    g.kind = 4;
+    g.mt = 1;
+    g.cbw = 1;
+    g.G = 1;
+    g.j_lds = 0;
+    g.rows = rb;
+    g.nblocks = (R + rb - 1) / rb;
+    g.ngroups = g.nblocks;
+    g.xcd_map = 0;
+    g.lds = valu_lds_bytes(form, rb, p->Np);
+    g.mh = p->mh;
+    return true;
+}
+
+}  // namespace phia
+
+extern "C" int32_t phia_valu_crossover(int32_t Np)
+{
+    return phia::valu_crossover(Np);
+}
+
+namespace phia {
+
 // Every feasible geometry for R replicas (group sizes up to 64 workgroups).
 static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
 {
     std::vector<Geometry> out;
+    if (p->path == PHIA_PATH_FP32 || p->path == PHIA_PATH_ELL) {
+        for (int rb : {1, 2, 4}) {
+            Geometry g;
+            if (make_geometry_valu(p, R, rb, g)) out.push_back(g);
+        }
+        return out;
+    }
+    if (p->path == PHIA_PATH_I8 && R <= kValuTuneMaxR)
+        for (int rb : {1, 2}) {
+            Geometry g;
+            if (make_geometry_valu(p, R, rb, g)) out.push_back(g);
+        }
     const int ncb = p->Np / 16;
     int last_cbs = -1;
     for (int G = 1; G <= std::min(ncb, 64); ++G) {
@@ -389,12 +503,17 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
 // then the fewest owned elements per workgroup, then J in LDS.
 // PHIA_GEOMETRY="mt,G,jlds[,cbw[,xcd]]" or "pp,G[,xcd]" / "pp4,G[,xcd]" forces
 // one candidate (tuning experiments).
-static void choose_mfma_geometry(phia_problem* p, int R)
+static void choose_geometry(phia_problem* p, int R)
 {
     p->geo.ok = false;
     int f_mt = 0, f_G = 0, f_j = -1, f_c = kCbwMax;
     if (const char* env = std::getenv("PHIA_GEOMETRY")) {
         int f_x = -1;
+        if (std::sscanf(env, "valu,%d", &f_G) == 1) {
+            Geometry g;
+            if (make_geometry_valu(p, R, f_G, g)) p->geo = g;
+            return;
+        }
         if (std::sscanf(env, "pp,%d,%d", &f_G, &f_x) >= 1 || std::sscanf(env, "pp4,%d,%d", &f_G, &f_x) >= 1) {
             Geometry g;
             if (make_geometry_pp(p, R, f_G, std::strncmp(env, "pp4", 3) == 0, g, f_x)) p->geo = g;
@@ -421,16 +540,24 @@ static void choose_mfma_geometry(phia_problem* p, int R)
         }
     }
     if (lookup_tune_cache(p, R)) return;
+    if (p->path == PHIA_PATH_FP32 || p->path == PHIA_PATH_ELL) {
+        make_geometry_valu(p, R, p->path == PHIA_PATH_FP32 ? kFp32Rows : ell_rows(R), p->geo);
+        return;
+    }
+    // Few replicas on the int8 path: the VALU dot-product sweep.
+    if (p->path == PHIA_PATH_I8 && R <= valu_crossover(p->Np) && make_geometry_valu(p, R, valu_rows(R), p->geo))
+        return;
     // Fewest passes over the replica blocks first; among those a geometry
     // without column split, else the interleaved kernel with the smallest
     // group, else the fewest owned elements per workgroup, then J in LDS.
     const std::vector<Geometry> cands = candidate_geometries(p, R);
     int min_iters = 1 << 30;
-    for (const Geometry& g : cands) min_iters = std::min(min_iters, (g.nblocks + g.ngroups - 1) / g.ngroups);
+    for (const Geometry& g : cands)
+        if (g.kind != 4) min_iters = std::min(min_iters, (g.nblocks + g.ngroups - 1) / g.ngroups);
     double best = 0;
     for (const Geometry& g : cands) {
         const int iters = (g.nblocks + g.ngroups - 1) / g.ngroups;
-        if (iters != min_iters) continue;
+        if (iters != min_iters || g.kind == 4) continue;  // the VALU sweep: by the crossover rule or tuning only
         const int cbs_max = (p->Np / 16 + g.G - 1) / g.G;
         const double elems = static_cast<double>(g.rows) * cbs_max * 16;
         double cost = g.kind >= 1 ? 1e6 + 2 * g.G - (g.kind == 2 ? 1 : 0)
@@ -479,17 +606,8 @@ Geometry plain_geometry(phia_problem* p, int R)
     const bool trace = p->trace;
     p->mh = 0;
     p->trace = false;
-    Geometry g{};
-    if (p->path == PHIA_PATH_FP32) {
-        g.ok = true;
-        g.G = 1;
-        g.rows = kFp32Rows;
-        g.nblocks = (R + kFp32Rows - 1) / kFp32Rows;
-        g.ngroups = g.nblocks;
-    } else {
-        choose_mfma_geometry(p, R);
-        g = p->geo;
-    }
+    choose_geometry(p, R);
+    const Geometry g = p->geo;
     p->geo = saved;
     p->mh = mh;
     p->trace = trace;
@@ -503,6 +621,7 @@ SweepArgs sweep_args(const phia_problem* p)
     a.Np = p->Np;
     a.h = p->dh;
     a.J = p->geo.kind == 2 ? p->dJ4 : p->dJ;
+    a.ell_d = p->ell_d;
     a.ctab = p->dctab;
     a.eps = p->eps;
     a.gamma = p->gamma;
@@ -580,7 +699,7 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     if (N < 1 || N > 16384) return fail(PHIA_EINVAL, "N = %d outside [1, 16384]", N);
     phia_options o{-1, 0, PHIA_PATH_AUTO, 0, nullptr};
     if (opt) o = *opt;
-    if (o.path < PHIA_PATH_AUTO || o.path > PHIA_PATH_BF16HILO) return fail(PHIA_EINVAL, "unknown path %d", o.path);
+    if (o.path < PHIA_PATH_AUTO || o.path > PHIA_PATH_ELL) return fail(PHIA_EINVAL, "unknown path %d", o.path);
 
     std::vector<int32_t> Ji, hi;
     int f = 0;
@@ -589,15 +708,19 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     if (st != PHIA_OK) return st;
 
     int64_t maxJ = 0, minJ = 0, maxrow = 0;
+    int maxdeg = 0;  // most nonzero couplings in a row
     for (int i = 0; i < N; ++i) {
         int64_t row = std::llabs(hi[i]);
+        int deg = 0;
         for (int j = 0; j < N; ++j) {
             const int64_t v = Ji[static_cast<size_t>(i) * N + j];
             maxJ = std::max(maxJ, v);
             minJ = std::min(minJ, v);
             row += std::llabs(v);
+            deg += v != 0;
         }
         maxrow = std::max(maxrow, row);
+        maxdeg = std::max(maxdeg, deg);
     }
     const int64_t maxabs = std::max(maxJ, -minJ);
     if (maxrow >= (int64_t(1) << 31)) return fail(PHIA_ERANGE, "sum_j |J_ij| + |h_i| does not fit int32");
@@ -606,9 +729,19 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     const bool bf_ok = maxabs <= 32767;
     const bool f32_ok = maxrow < (int64_t(1) << 24);
     if (path == PHIA_PATH_AUTO) path = i8_ok ? PHIA_PATH_I8 : bf_ok ? PHIA_PATH_BF16HILO : PHIA_PATH_FP32;
+    {
+        // Sparse rows beyond the batch sweep's sizes: ELL when the densest
+        // row has at most Np / 192 nonzeros (measured on MI355X: 3-regular
+        // rows take 2.1 against 3.7 us per step at N = 1000 and 8.5 against
+        // 13.8 us at N = 4000; ELL loses from about Np / 100 nonzeros).
+        const int Np = (N + 63) / 64 * 64;
+        if (o.path == PHIA_PATH_AUTO && bf_ok && Np > kBatchFp4MaxNp && Np <= kValuMaxNp && maxdeg <= Np / 192)
+            path = PHIA_PATH_ELL;
+    }
     if (path == PHIA_PATH_I8 && !i8_ok) return fail(PHIA_ERANGE, "couplings outside int8 for the I8 path");
     if (path == PHIA_PATH_BF16HILO && !bf_ok) return fail(PHIA_ERANGE, "couplings outside 16 bits for BF16HILO");
     if (path == PHIA_PATH_FP32 && !f32_ok) return fail(PHIA_ERANGE, "row sums exceed 2^24 for the FP32 path");
+    if (path == PHIA_PATH_ELL && !bf_ok) return fail(PHIA_ERANGE, "couplings outside 16 bits for the ELL path");
     {
         // Largest instance each sweep holds: the FP32 sweep keeps up to 16
         // columns per thread (Np <= 4096); the matrix-core sweeps stage two
@@ -616,8 +749,8 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
         // slice needs 32 Np bytes per operand byte there.
         const int Np = (N + 63) / 64 * 64;
         bool fits;
-        if (path == PHIA_PATH_FP32) {
-            fits = Np <= 4096;
+        if (path == PHIA_PATH_FP32 || path == PHIA_PATH_ELL) {
+            fits = Np <= kValuMaxNp;
         } else {
             SweepArgs a{};
             a.Np = Np;
@@ -627,8 +760,8 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
             fits = sweep_mfma_lds_bytes(path, 1, a) <= static_cast<size_t>(kLdsMax);
         }
         if (!fits)
-            return fail(PHIA_ERANGE, "N = %d is beyond the %s sweep (N <= 5056 int8, 2496 BF16 hi/lo, 4096 FP32)", N,
-                        path == PHIA_PATH_FP32 ? "FP32" : path == PHIA_PATH_I8 ? "int8" : "BF16 hi/lo");
+            return fail(PHIA_ERANGE, "N = %d is beyond the %s sweep (N <= 5056 int8, 2496 BF16 hi/lo, 4096 FP32/ELL)",
+                        N, path_name(path));
     }
 
     int ndev = 0;
@@ -657,6 +790,7 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     std::vector<int8_t> j8;
     std::vector<uint8_t> j4;
     std::vector<uint16_t> jb;
+    std::vector<int32_t> jell;
     const void* jsrc = nullptr;
     if (path == PHIA_PATH_FP32) {
         jf.assign(static_cast<size_t>(Np) * Np, 0.0f);
@@ -665,6 +799,10 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
                 jf[static_cast<size_t>(i) * Np + j] = static_cast<float>(Ji[static_cast<size_t>(i) * N + j]);
         jbytes = jf.size() * sizeof(float);
         jsrc = jf.data();
+    } else if (path == PHIA_PATH_ELL) {
+        pack_ell(Ji, N, Np, jell, p->ell_d);
+        jbytes = jell.size() * sizeof(int32_t);
+        jsrc = jell.data();
     } else if (path == PHIA_PATH_I8) {
         pack_i8(Ji, N, Np, j8);
         jbytes = j8.size();
@@ -910,32 +1048,24 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
         return PHIA_OK;
     }
     p->geo = Geometry{};
-    if (p->path == PHIA_PATH_FP32) {
-        p->geo.ok = true;
-        p->geo.G = 1;
-        p->geo.rows = kFp32Rows;
-        p->geo.nblocks = (replicas + kFp32Rows - 1) / kFp32Rows;
-        p->geo.ngroups = p->geo.nblocks;
-    } else {
-        choose_mfma_geometry(p, replicas);
-        if (!p->geo.ok) {
+    choose_geometry(p, replicas);
+    if (!p->geo.ok) {
+        free_state(p);
+        return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
+    }
+    if (p->geo.G > 1) {
+        // Tagged exchange words start at zero; tags start at 1.
+        const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * (p->Np / 16) * sizeof(uint64_t);
+        const size_t pb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * 2 * sizeof(uint64_t);
+        if ((e = dalloc(reinterpret_cast<void**>(&p->dxbits), xb, cnt)) != hipSuccess ||
+            (e = dalloc(reinterpret_cast<void**>(&p->dpbuf), pb, cnt)) != hipSuccess) {
             free_state(p);
-            return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
+            return fail(PHIA_ENOMEM, "exchange buffer allocation failed");
         }
-        if (p->geo.G > 1) {
-            // Tagged exchange words start at zero; tags start at 1.
-            const size_t xb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.rows * (p->Np / 16) * sizeof(uint64_t);
-            const size_t pb = 2 * static_cast<size_t>(p->geo.ngroups) * p->geo.G * p->geo.rows * 2 * sizeof(uint64_t);
-            if ((e = dalloc(reinterpret_cast<void**>(&p->dxbits), xb, cnt)) != hipSuccess ||
-                (e = dalloc(reinterpret_cast<void**>(&p->dpbuf), pb, cnt)) != hipSuccess) {
-                free_state(p);
-                return fail(PHIA_ENOMEM, "exchange buffer allocation failed");
-            }
-            if ((e = hipMemsetAsync(p->dxbits, 0, xb, p->st)) != hipSuccess ||
-                (e = hipMemsetAsync(p->dpbuf, 0, pb, p->st)) != hipSuccess)
-                return hip_fail(p, e, "exchange buffer reset");
-            p->seq = 0;
-        }
+        if ((e = hipMemsetAsync(p->dxbits, 0, xb, p->st)) != hipSuccess ||
+            (e = hipMemsetAsync(p->dpbuf, 0, pb, p->st)) != hipSuccess)
+            return hip_fail(p, e, "exchange buffer reset");
+        p->seq = 0;
     }
     if ((st = setup_mh_geometry(p)) != PHIA_OK) {
         free_state(p);
@@ -986,8 +1116,8 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
     SweepArgs a = sweep_args(p);
     a.k0 = p->k;
     a.k1 = k_end;
-    if (p->path == PHIA_PATH_FP32) {
-        e = launch_sweep_fp32(a, p->st);
+    if (p->geo.kind == 4) {
+        e = launch_sweep_valu(valu_form(p), p->geo.rows, a, p->st);
     } else if (p->geo.kind >= 1) {
         // 24-bit tags: launches of at most `chunk` steps, and the sequence
         // restarts (with cleared words) before it would wrap.
@@ -1242,6 +1372,7 @@ phia_status phia_autotune(phia_problem* p, int32_t replicas, int64_t probe_steps
     if (probe_steps < 10 || probe_steps > 100000) return fail(PHIA_EINVAL, "probe_steps outside [10, 100000]");
     if (best_us) *best_us = 0.0;
     if (p->path == PHIA_PATH_FP32) return PHIA_OK;  // one launch shape only
+    if (p->path == PHIA_PATH_ELL && p->mh) return PHIA_OK;
     std::vector<Geometry> cands = candidate_geometries(p, replicas);
     if (cands.empty()) return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
     // Candidates that need more passes over the replica blocks than twice

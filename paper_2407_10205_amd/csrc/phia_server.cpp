@@ -121,10 +121,11 @@ void round_once(phia_server* s, std::vector<Request*>& run)
     for (Request* r : run) {
         phia_problem* p = r->p;
         const int64_t k_end = std::min(p->k + s->chunk, p->T);
-        if (p->Np <= kBatchMaxNp && p->path != PHIA_PATH_FP32) {
+        const bool mfma = p->path == PHIA_PATH_I8 || p->path == PHIA_PATH_BF16HILO;
+        if (p->Np <= kBatchMaxNp && mfma) {
             small.push_back(p);
             small_end.push_back(k_end);
-        } else if (p->path != PHIA_PATH_FP32 && p->geo.kind == 0 && p->geo.G > 1) {
+        } else if (mfma && p->geo.kind == 0 && p->geo.G > 1) {
             split.push_back(p);
             split_end.push_back(k_end);
         } else if (k_end > p->k) {
@@ -134,7 +135,7 @@ void round_once(phia_server* s, std::vector<Request*>& run)
     if (!small.empty() && launch_batch_chunk(small.data(), static_cast<int>(small.size()), small_end.data(), s->st,
                                              s->dtab, s->dtab_cap) != PHIA_OK)
         for (Request* r : run)
-            if (r->p->Np <= kBatchMaxNp) r->failed = true;
+            if (std::find(small.begin(), small.end(), r->p) != small.end()) r->failed = true;
     // Column-split instances: several per cooperative launch.
     if (!split.empty() && launch_group_chunk(split.data(), static_cast<int>(split.size()), split_end.data(), s->st,
                                              s->gtab, s->gtab_cap) != PHIA_OK)

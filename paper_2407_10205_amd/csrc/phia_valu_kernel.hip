@@ -1,0 +1,454 @@
+// VALU sweeps of the PHIA library for gfx950 (k_sweep_valu).
+//
+// A workgroup of 256 threads owns RB replicas and all of their columns for
+// the whole launch: thread t keeps x and v of columns i = t + 256 c (c < CPT)
+// of every replica in registers, the spins of the current step go to LDS,
+// and J.s + h (Eq. 6) runs on the vector ALUs in one of three forms:
+//
+//   FORM 0 (FP32 path): FP32 couplings [Np][Np] row-major, one FMA per
+//          coupling against spins stored as +-1.0f.  The plain sweep.
+//   FORM 1 (int8 couplings, few replicas): the int8 fragment layout of the
+//          matrix-core sweeps, read by rows: thread i takes the 16-byte runs
+//          J[i][16 q .. 16 q + 15] (the lanes of a wave read 256-byte runs)
+//          and v_dot4 multiplies four couplings by four int8 spins at once.
+//          With few replicas J.s is a matrix-vector product per step: every
+//          coupling byte is used RB times, so the stream of J from L2/HBM
+//          bounds it and padding 16-row matrix tiles buys nothing.
+//   FORM 2 (ELL path): sparse couplings as D slots per row, [D][Np] words
+//          (column index in the low 16 bits, the integer coupling in the
+//          high 16), padding slots zero; each slot gathers one spin byte from
+//          LDS.  Work per step is proportional to the nonzeros, not N^2.
+//
+// Every product and sum is an exact integer, so all forms give the same
+// field, and the step (refresh, drift, readout, J.s + h, exact energy,
+// records, kick; Sec. 2.1, App. A A7, Table 3) is the one of the other
+// sweeps bit for bit.  MH adds the accept/reject step of App. A (Table 3,
+// state 4) at the end of every trajectory.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <type_traits>
+
+#include "phia_devmath.h"
+#include "phia_devsweep.h"
+#include "phia_internal.h"
+
+namespace phia {
+
+namespace {
+
+constexpr int kVT = 256;  // threads per workgroup
+
+// J.s of this thread's columns for every replica of the block (FORM 1):
+// fragments [Np/16][Np/64][64][16], lane l of fragment (cb, kb) holding
+// J[16 cb + l % 16][64 kb + 16 (l / 16) + t].
+template <int CPT, int RB>
+__device__ __forceinline__ void dot_i8(const int8_t* __restrict__ J8, const int8_t* sS8, int Np, int tid,
+                                       int (&acc)[RB][CPT])
+{
+    const int nkb = Np / 64;
+    for (int kb = 0; kb < nkb; ++kb) {
+        v4i s[RB][4];
+#pragma unroll
+        for (int r = 0; r < RB; ++r)
+#pragma unroll
+            for (int g = 0; g < 4; ++g) s[r][g] = *reinterpret_cast<const v4i*>(sS8 + r * Np + kb * 64 + 16 * g);
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + kVT * c;
+            if (i >= Np) continue;
+            const v4i* src = reinterpret_cast<const v4i*>(
+                J8 + ((static_cast<size_t>(i >> 4) * nkb + kb) * 64 + (i & 15)) * 16);
+            v4i w[4];
+#pragma unroll
+            for (int g = 0; g < 4; ++g) w[g] = src[16 * g];
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int g = 0; g < 4; ++g)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) acc[r][c] = __builtin_amdgcn_sdot4(w[g][t], s[r][g][t], acc[r][c], false);
+        }
+    }
+}
+
+// J.s by ELL gathers (FORM 2): slot d of row i is E[d Np + i].
+template <int CPT, int RB>
+__device__ __forceinline__ void dot_ell(const int32_t* __restrict__ E, const int8_t* sS8, int Np, int D, int tid,
+                                        int (&acc)[RB][CPT])
+{
+    int d = 0;
+    for (; d + 4 <= D; d += 4) {
+        int32_t w[4][CPT];
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + kVT * c;
+                w[u][c] = (i < Np) ? E[static_cast<size_t>(d + u) * Np + i] : 0;
+            }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int j = w[u][c] & 0xffff, val = w[u][c] >> 16;
+#pragma unroll
+                for (int r = 0; r < RB; ++r) acc[r][c] += val * static_cast<int>(sS8[r * Np + j]);
+            }
+    }
+    for (; d < D; ++d)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + kVT * c;
+            const int32_t w = (i < Np) ? E[static_cast<size_t>(d) * Np + i] : 0;
+            const int j = w & 0xffff, val = w >> 16;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r][c] += val * static_cast<int>(sS8[r * Np + j]);
+        }
+}
+
+// J.s by FP32 multiply-adds (FORM 0), eight rows of J in flight per thread.
+template <int CPT, int RB>
+__device__ __forceinline__ void dot_f32(const float* __restrict__ J, const float* sSf, int N, int Np, int tid,
+                                        int (&I)[RB][CPT])
+{
+    float acc[RB][CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+#pragma unroll
+        for (int r = 0; r < RB; ++r) acc[r][c] = 0.0f;
+    int j = 0;
+    for (; j + 8 <= N; j += 8) {
+        float jv[8][CPT];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + kVT * c;
+                jv[u][c] = (i < Np) ? J[static_cast<int64_t>(j + u) * Np + i] : 0.0f;
+            }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            float sj[RB];
+#pragma unroll
+            for (int r = 0; r < RB; ++r) sj[r] = sSf[r * Np + j + u];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv[u][c], sj[r], acc[r][c]);
+        }
+    }
+    for (; j < N; ++j) {
+        float sj[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) sj[r] = sSf[r * Np + j];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + kVT * c;
+            const float jv = (i < Np) ? J[static_cast<int64_t>(j) * Np + i] : 0.0f;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv, sj[r], acc[r][c]);
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) I[r][c] = static_cast<int>(acc[r][c]);
+}
+
+}  // namespace
+
+template <int FORM, int CPT, int RB, bool MH>
+__global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
+{
+    // spins of the current step: [RB][Np] +-1.0f (FORM 0) or +-1 int8
+    extern __shared__ __align__(16) unsigned char sRaw[];
+    float* sSf = reinterpret_cast<float*>(sRaw);
+    int8_t* sS8 = reinterpret_cast<int8_t*>(sRaw);
+    __shared__ int64_t sPart[RB][4];
+    __shared__ int64_t sBest[RB];
+    __shared__ int sImp[RB];
+    // accept/reject bookkeeping (MH only)
+    __shared__ int64_t mEs[RB], mQ0[RB], mEl[RB];
+    __shared__ long long mPart[RB][4];
+    __shared__ float mLam[RB];
+    __shared__ int mOut[RB], mAcc[RB], mDec[RB];
+    constexpr bool mh = MH;
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int Np = a.Np, N = a.N;
+    const int64_t rb0 = static_cast<int64_t>(blockIdx.x) * RB;
+
+    float x[RB][CPT], v[RB][CPT];
+    int hc[CPT];
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int i = tid + kVT * c;
+        hc[c] = (i < Np) ? a.h[i] : 0;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            const bool ok = (rb0 + r < a.R) && (i < Np);
+            x[r][c] = ok ? a.x[(rb0 + r) * Np + i] : 0.0f;
+            v[r][c] = ok ? a.v[(rb0 + r) * Np + i] : 0.0f;
+        }
+    }
+    int64_t bstep = -1;
+    if (tid < RB) {
+        const bool ok = rb0 + tid < a.R;
+        sBest[tid] = ok ? a.bestE[rb0 + tid] : INT64_MAX;
+        bstep = ok ? a.bestStep[rb0 + tid] : -1;
+        if (mh) {
+            const int64_t gq = rb0 + tid;
+            mEs[tid] = ok ? a.mhE[gq * 2] : INT64_MIN;
+            mEl[tid] = ok ? a.mhE[gq * 2 + 1] : 0;
+            mQ0[tid] = ok ? a.mhQ[gq] : 0;
+            mLam[tid] = ok ? a.lam[gq] : 1.0f;
+            mAcc[tid] = ok ? a.mhc[gq * 2] : 0;
+            mDec[tid] = ok ? a.mhc[gq * 2 + 1] : 0;
+        }
+    }
+    __syncthreads();
+    float lamr[RB];
+#pragma unroll
+    for (int r = 0; r < RB; ++r) lamr[r] = mh ? mLam[r] : 1.0f;
+    // kinetic units of this thread's elements of row r, summed into mPart[r][wave]
+    auto kin_rows = [&]() {
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            long long q = 0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) q += kin_units(x[r][c], v[r][c]);
+            q = wave_sum16_i64(q);
+            q += __shfl_xor(q, 16, 64);
+            q += __shfl_xor(q, 32, 64);
+            if (lane == 0) mPart[r][wave] = q;
+        }
+    };
+
+    for (int64_t k = a.k0; k < a.k1; ++k) {
+        if (k % a.L == 0) {
+            if (mh && k > 0) {
+                // End of trajectory k / L - 1 (energy of step k - 1 in mEl): one
+                // decision per replica; a rejected end point returns x to the
+                // trajectory's start.
+                kin_rows();
+                __syncthreads();
+                if (tid < RB) {
+                    const int64_t gq = rb0 + tid;
+                    int out = 1;
+                    if (gq < a.R) {
+                        const int64_t qe = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
+                        out = mh_outcome(a.seed, static_cast<uint64_t>(a.r_base + gq), k / a.L - 1, mEs[tid],
+                                         mEl[tid], qe - mQ0[tid], a.btab[k - 1], mLam[tid], a.sigma);
+                        if (out != 0) mEs[tid] = mEl[tid];
+                        mLam[tid] = mh_lambda(mLam[tid], out, a.mh_up, a.mh_down);
+                        if (out >= 0) {
+                            mAcc[tid] += out;
+                            mDec[tid] += 1;
+                        }
+                    }
+                    mOut[tid] = out;
+                }
+                __syncthreads();
+#pragma unroll
+                for (int r = 0; r < RB; ++r) {
+                    lamr[r] = mLam[r];
+                    if (mOut[r] == 0 && rb0 + r < a.R)
+#pragma unroll
+                        for (int c = 0; c < CPT; ++c) {
+                            const int i = tid + kVT * c;
+                            if (i < Np) x[r][c] = a.x0[(rb0 + r) * Np + i];
+                        }
+                }
+            }
+            const uint64_t rnd = static_cast<uint64_t>(k / a.L);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + kVT * c;
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    v[r][c] = (i < N && rb0 + r < a.R) ? gauss_v(a.seed, a.r_base + rb0 + r, rnd, i) : 0.0f;
+            }
+            if (mh) {
+                // Start of a trajectory: x snapshot and kinetic units (summed
+                // into mQ0 after the next barrier).
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int i = tid + kVT * c;
+#pragma unroll
+                    for (int r = 0; r < RB; ++r)
+                        if (rb0 + r < a.R && i < Np) a.x0[(rb0 + r) * Np + i] = x[r][c];
+                }
+                kin_rows();
+            }
+        }
+        // Drift and readout; padded columns keep x = 0 and read +1, which
+        // meets only zero couplings.
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + kVT * c;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                x[r][c] = __builtin_fmaf(a.eps, v[r][c], x[r][c]);
+                const bool pos = x[r][c] >= 0.0f;
+                if (i < Np) {
+                    if (FORM == 0)
+                        sSf[r * Np + i] = pos ? 1.0f : -1.0f;
+                    else
+                        sS8[r * Np + i] = pos ? 1 : -1;
+                }
+            }
+        }
+        __syncthreads();
+
+        int I[RB][CPT];
+        if constexpr (FORM == 0) {
+            dot_f32<CPT, RB>(static_cast<const float*>(a.J), sSf, N, Np, tid, I);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) I[r][c] = 0;
+            if constexpr (FORM == 1)
+                dot_i8<CPT, RB>(static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
+            else
+                dot_ell<CPT, RB>(static_cast<const int32_t*>(a.J), sS8, Np, a.ell_d, tid, I);
+        }
+
+        // Field, and the row energy partials s (I + h) of step k.
+        int part[RB];
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            part[r] = 0;
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                const int i = tid + kVT * c;
+                I[r][c] += hc[c];
+                const int s = (x[r][c] >= 0.0f) ? 1 : -1;
+                if (i < N) part[r] += s * (I[r][c] + hc[c]);
+            }
+            const int ws = wave_sum64(part[r]);
+            if (lane == 0) sPart[r][wave] = ws;
+        }
+        __syncthreads();
+        if (tid < RB) {
+            const int64_t tot = sPart[tid][0] + sPart[tid][1] + sPart[tid][2] + sPart[tid][3];
+            const int64_t E = -(tot / 2);
+            if (mh) {
+                mEl[tid] = E;
+                if (k % a.L == 0) mQ0[tid] = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
+            }
+            const bool ok = rb0 + tid < a.R;
+            if (ok && a.etrace) a.etrace[(rb0 + tid) * a.T + k] = E;
+            const int imp = ok && (E < sBest[tid]);
+            if (imp) {
+                sBest[tid] = E;
+                bstep = k;
+            }
+            sImp[tid] = imp;
+        }
+        __syncthreads();
+        // Records (Table 3, state 5): the spins of an improved replica.
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (sImp[r]) {
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) {
+                    const int i = tid + kVT * c;
+                    if (i < N) a.bestS[(rb0 + r) * Np + i] = (x[r][c] >= 0.0f) ? 1 : -1;
+                }
+            }
+        }
+        // Kick (mode branch outside the element loops).
+        const float ck = a.ctab[k];
+        auto kick_all = [&](auto mode) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    v[r][c] = kick_t<decltype(mode)::value>(x[r][c], v[r][c], I[r][c], ck * lamr[r], a.eps, a.gamma);
+        };
+        if (a.deriv)
+            kick_all(std::integral_constant<int, 1>{});
+        else
+            kick_all(std::integral_constant<int, 0>{});
+    }
+
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int i = tid + kVT * c;
+#pragma unroll
+        for (int r = 0; r < RB; ++r) {
+            if (rb0 + r < a.R && i < Np) {
+                a.x[(rb0 + r) * Np + i] = x[r][c];
+                a.v[(rb0 + r) * Np + i] = v[r][c];
+            }
+        }
+    }
+    if (tid < RB && rb0 + tid < a.R) {
+        a.bestE[rb0 + tid] = sBest[tid];
+        a.bestStep[rb0 + tid] = bstep;
+        if (mh) {
+            const int64_t gq = rb0 + tid;
+            a.mhE[gq * 2] = mEs[tid];
+            a.mhE[gq * 2 + 1] = mEl[tid];
+            a.mhQ[gq] = mQ0[tid];
+            a.lam[gq] = mLam[tid];
+            a.mhc[gq * 2] = mAcc[tid];
+            a.mhc[gq * 2 + 1] = mDec[tid];
+        }
+    }
+}
+
+namespace {
+
+template <int FORM, int RB, bool MH>
+hipError_t launch_valu_t(const SweepArgs& a, hipStream_t st)
+{
+    const int cpt = (a.Np + kVT - 1) / kVT;
+    const unsigned blocks = static_cast<unsigned>((a.R + RB - 1) / RB);
+    const size_t lds = valu_lds_bytes(FORM, RB, a.Np);
+    if (cpt <= 1)
+        hipLaunchKernelGGL((k_sweep_valu<FORM, 1, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
+    else if (cpt <= 2)
+        hipLaunchKernelGGL((k_sweep_valu<FORM, 2, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
+    else if (cpt <= 4)
+        hipLaunchKernelGGL((k_sweep_valu<FORM, 4, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
+    else if (cpt <= 8)
+        hipLaunchKernelGGL((k_sweep_valu<FORM, 8, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
+    else if (cpt <= 16)
+        hipLaunchKernelGGL((k_sweep_valu<FORM, 16, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t valu_lds_bytes(int form, int rb, int Np)
+{
+    return static_cast<size_t>(rb) * Np * (form == kValuFp32 ? sizeof(float) : 1);
+}
+
+bool valu_variant(int form, int rb, int mh)
+{
+    switch (form) {
+    case kValuFp32: return rb == kFp32Rows;
+    case kValuDot8: return (rb == 1 || rb == 2) && !mh;
+    case kValuEll: return rb == 1 || rb == 4;
+    default: return false;
+    }
+}
+
+hipError_t launch_sweep_valu(int form, int rb, const SweepArgs& a, hipStream_t st)
+{
+    if (!valu_variant(form, rb, a.mh) || a.Np > kValuMaxNp) return hipErrorInvalidValue;
+    if (form == kValuFp32) return a.mh ? launch_valu_t<kValuFp32, kFp32Rows, true>(a, st)
+                                       : launch_valu_t<kValuFp32, kFp32Rows, false>(a, st);
+    if (form == kValuDot8) return rb == 1 ? launch_valu_t<kValuDot8, 1, false>(a, st)
+                                          : launch_valu_t<kValuDot8, 2, false>(a, st);
+    if (rb == 1) return a.mh ? launch_valu_t<kValuEll, 1, true>(a, st) : launch_valu_t<kValuEll, 1, false>(a, st);
+    return a.mh ? launch_valu_t<kValuEll, 4, true>(a, st) : launch_valu_t<kValuEll, 4, false>(a, st);
+}
+
+}  // namespace phia

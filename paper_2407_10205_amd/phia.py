@@ -19,7 +19,7 @@ except Exception:  # pragma: no cover - torch is part of the image
 _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_PKG, "libphia.so")
 
-PATHS = {"auto": 0, "fp32": 1, "i8": 2, "bf16hilo": 3}
+PATHS = {"auto": 0, "fp32": 1, "i8": 2, "bf16hilo": 3, "ell": 4}
 PATH_NAMES = {v: k for k, v in PATHS.items()}
 STATUS = {0: "PHIA_OK", -1: "PHIA_EINVAL", -2: "PHIA_ENOTSYM", -3: "PHIA_EDIAG", -4: "PHIA_ERANGE",
           -5: "PHIA_ENOMEM", -6: "PHIA_EDEVICE", -7: "PHIA_ESTATE"}
@@ -33,7 +33,7 @@ EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_noalloc", "phia_anneal_sta
            "phia_batch_run", "phia_batch_create", "phia_batch_launch", "phia_batch_sync", "phia_batch_destroy",
            "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
            "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
-           "phia_destroy", "phia_last_error", "phia_version")
+           "phia_valu_crossover", "phia_destroy", "phia_last_error", "phia_version")
 
 REQ_QUEUED, REQ_RUNNING, REQ_DONE, REQ_CANCELLED, REQ_FAILED = 0, 1, 2, 3, -1
 
@@ -125,6 +125,8 @@ def _declare(lib):
     lib.phia_batch_destroy.restype = None
     lib.phia_last_error.restype = C.c_char_p
     lib.phia_version.restype = C.c_char_p
+    lib.phia_valu_crossover.argtypes = [I32]
+    lib.phia_valu_crossover.restype = C.c_int32
 
 
 _lib = None
@@ -411,6 +413,11 @@ def batch_run(problems, replicas, steps, schedules, seeds):
     for p, r in zip(problems, reps):
         p.R = int(r)
     del keep
+
+
+def valu_crossover(Np):
+    """Largest replica count for which an I8 anneal takes the VALU sweep (phia_valu_crossover)."""
+    return int(lib().phia_valu_crossover(int(Np)))
 
 
 def server_footprint(problem, replicas, max_steps):

@@ -61,6 +61,9 @@ def test_validation_codes(phia):
     assert _code(phia, off) == -4                        # no grid f <= 15 holds 0.3
     big = np.array([[0, 200.0], [200.0, 0]])
     assert _code(phia, big, path="i8") == -4             # outside int8
+    wide = np.array([[0, 40000.0], [40000.0, 0]])
+    assert _code(phia, wide, path="ell") == -4           # outside the 16 bits of an ELL slot
+    assert _code(phia, big, path=5) == -1                # unknown path
     assert _code(phia, np.array([[0, np.nan], [np.nan, 0]])) == -1
     assert _code(phia, np.zeros((2, 2)), frac_bits=16) == -1
 
@@ -81,7 +84,7 @@ def test_null_and_size_arguments(phia):
     L.phia_destroy(None)
 
 
-@pytest.mark.parametrize("path,N", [("i8", 5056), ("bf16hilo", 2496), ("fp32", 4096)])
+@pytest.mark.parametrize("path,N", [("i8", 5056), ("bf16hilo", 2496), ("fp32", 4096), ("ell", 4096)])
 def test_size_limits_per_path(phia, path, N):
     """Each path's largest instance passes the size check (on a machine
     without a GPU it then fails for want of a device); one spin more is

@@ -85,7 +85,7 @@ def assert_parity(dev, runs):
 RAGGED = dict(eps=0.3, gamma=1.0, beta0=0.2, beta1=3.0, refresh_L=23)
 
 
-@pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo"])
+@pytest.mark.parametrize("path", ["fp32", "i8", "bf16hilo", "ell"])
 def test_mh_parity_paths(P, O, path):
     """Ragged N, R and refresh period, fixed-point couplings on the 2^-5 grid,
     lam driven by the outcomes (1.25 up, 0.8 down): every replica matches."""
