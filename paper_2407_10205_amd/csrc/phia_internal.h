@@ -87,9 +87,11 @@ hipError_t launch_init(const SweepArgs& a, hipStream_t st);
 // VALU sweeps (k_sweep_valu): RB replicas and all columns per workgroup.
 enum ValuForm : int { kValuFp32 = 0, kValuDot8 = 1, kValuEll = 2 };
 constexpr int kValuMaxNp = 4096;  // 16 columns per thread
-size_t valu_lds_bytes(int form, int rb, int Np);
-bool valu_variant(int form, int rb, int mh);  // a compiled (form, rows, accept/reject) combination
-hipError_t launch_sweep_valu(int form, int rb, const SweepArgs& a, hipStream_t st);
+// LDS offset of the couplings of the int8 form when they reside in LDS.
+__host__ __device__ inline size_t valu_jl_offset(int rb, int Np) { return (static_cast<size_t>(rb) * Np + 15) & ~size_t(15); }
+size_t valu_lds_bytes(int form, int rb, int Np, bool jl);
+bool valu_variant(int form, int rb, int mh, bool jl);  // a compiled (form, rows, accept/reject, J in LDS) combination
+hipError_t launch_sweep_valu(int form, int rb, bool jl, const SweepArgs& a, hipStream_t st);
 hipError_t launch_sweep_mfma(int path, int mt, int cbw, const SweepArgs& a, size_t lds_bytes, hipStream_t st);
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a);
 hipError_t launch_argmin(const int64_t* bestE, int32_t R, int64_t* out2, hipStream_t st);

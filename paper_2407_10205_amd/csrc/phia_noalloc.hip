@@ -175,7 +175,7 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
     if ((e = launch_init(a, stream)) != hipSuccess) return hip_fail(p, e, "init kernel launch");
     if (g.kind == 4) {
         e = launch_sweep_valu(p->path == PHIA_PATH_FP32 ? kValuFp32 : p->path == PHIA_PATH_ELL ? kValuEll : kValuDot8,
-                              g.rows, a, stream);
+                              g.rows, g.j_lds != 0, a, stream);
     } else if (g.kind >= 1) {
         // launches of at most 2^22 steps, sequence numbers running on
         uint32_t seq = 0;

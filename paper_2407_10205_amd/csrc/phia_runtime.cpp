@@ -403,17 +403,19 @@ constexpr int kValuTuneMaxR = 64;  // the autotuner also times the int8 VALU swe
 
 // Largest replica count for which an int8 anneal takes the VALU dot-product
 // sweep (measured crossover against the matrix-core sweeps on MI355X).
-// Up to Np = 320 one workgroup per replica finishes a step sooner than the
-// matrix-core sweeps (about 0.9 against 1.2 us at Np = 64, 1.5 against 2.5 us
-// at Np = 256) until the replicas outnumber what the CUs run at once; from
-// Np = 384 the column-split matrix-core sweeps win at every replica count.
-// PHIA_VALU_CROSSOVER=n replaces the rule (tuning experiments; 0: never).
+// While J fits in LDS (Np <= 384) one workgroup per replica finishes a step
+// sooner than the matrix-core sweeps (0.94 against 1.21 us at Np = 64, 1.3
+// against 2.6 us at Np = 256, 2.05 against 2.77 us at Np = 384) until the
+// replicas outnumber the workgroups the CUs hold at once (J of 64 KiB: two
+// per CU, above 80 KiB: one); beyond Np = 384 the column-split matrix-core
+// sweeps win at every replica count.  PHIA_VALU_CROSSOVER=n replaces the
+// rule (tuning experiments; 0: never).
 int valu_crossover(int Np)
 {
     if (const char* env = std::getenv("PHIA_VALU_CROSSOVER")) return std::atoi(env);
     if (Np <= 64) return 1024;
     if (Np <= 256) return 512;
-    if (Np <= 320) return 256;
+    if (Np <= 384) return 256;
     return 0;
 }
 
@@ -431,7 +433,9 @@ static int valu_form(const phia_problem* p)
 static bool make_geometry_valu(phia_problem* p, int R, int rb, Geometry& g)
 {
     const int form = valu_form(p);
-    if (p->Np > kValuMaxNp || !valu_variant(form, rb, p->mh)) return false;
+    // the int8 couplings live in LDS when they fit next to the spins
+    const bool jl = form == kValuDot8 && valu_lds_bytes(form, rb, p->Np, true) <= static_cast<size_t>(kLdsMax);
+    if (p->Np > kValuMaxNp || !valu_variant(form, rb, p->mh, jl)) return false;
     // the int8 form: own launches only (served and batched problems run the
     // matrix-core table kernels)
     if (form == kValuDot8 && (p->path != PHIA_PATH_I8 || p->one_block_kernel)) return false;
@@ -441,12 +445,12 @@ static bool make_geometry_valu(phia_problem* p, int R, int rb, Geometry& g)
     g.mt = 1;
     g.cbw = 1;
     g.G = 1;
-    g.j_lds = 0;
+    g.j_lds = jl ? 1 : 0;
     g.rows = rb;
     g.nblocks = (R + rb - 1) / rb;
     g.ngroups = g.nblocks;
     g.xcd_map = 0;
-    g.lds = valu_lds_bytes(form, rb, p->Np);
+    g.lds = valu_lds_bytes(form, rb, p->Np, jl);
     g.mh = p->mh;
     return true;
 }
@@ -1117,7 +1121,7 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
     a.k0 = p->k;
     a.k1 = k_end;
     if (p->geo.kind == 4) {
-        e = launch_sweep_valu(valu_form(p), p->geo.rows, a, p->st);
+        e = launch_sweep_valu(valu_form(p), p->geo.rows, p->geo.j_lds != 0, a, p->st);
     } else if (p->geo.kind >= 1) {
         // 24-bit tags: launches of at most `chunk` steps, and the sequence
         // restarts (with cleared words) before it would wrap.

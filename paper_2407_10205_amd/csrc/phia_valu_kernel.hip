@@ -11,9 +11,9 @@
 //          matrix-core sweeps, read by rows: thread i takes the 16-byte runs
 //          J[i][16 q .. 16 q + 15] (the lanes of a wave read 256-byte runs)
 //          and v_dot4 multiplies four couplings by four int8 spins at once.
-//          With few replicas J.s is a matrix-vector product per step: every
-//          coupling byte is used RB times, so the stream of J from L2/HBM
-//          bounds it and padding 16-row matrix tiles buys nothing.
+//          With few replicas J.s is a matrix-vector product per step and a
+//          step is bound by its latency: J sits in LDS when it fits (Np <=
+//          384), so no step waits on L2, and no 16-row matrix tile is padded.
 //   FORM 2 (ELL path): sparse couplings as D slots per row, [D][Np] words
 //          (column index in the low 16 bits, the integer coupling in the
 //          high 16), padding slots zero; each slot gathers one spin byte from
@@ -158,13 +158,16 @@ __device__ __forceinline__ void dot_f32(const float* __restrict__ J, const float
 
 }  // namespace
 
-template <int FORM, int CPT, int RB, bool MH>
+// JL (FORM 1): the int8 couplings are copied to LDS once per launch, after
+// the spins, and every step reads them there.
+template <int FORM, int CPT, int RB, bool MH, bool JL>
 __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
 {
     // spins of the current step: [RB][Np] +-1.0f (FORM 0) or +-1 int8
     extern __shared__ __align__(16) unsigned char sRaw[];
     float* sSf = reinterpret_cast<float*>(sRaw);
     int8_t* sS8 = reinterpret_cast<int8_t*>(sRaw);
+    int8_t* sJ8 = reinterpret_cast<int8_t*>(sRaw + valu_jl_offset(RB, a.Np));
     __shared__ int64_t sPart[RB][4];
     __shared__ int64_t sBest[RB];
     __shared__ int sImp[RB];
@@ -191,6 +194,12 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
             x[r][c] = ok ? a.x[(rb0 + r) * Np + i] : 0.0f;
             v[r][c] = ok ? a.v[(rb0 + r) * Np + i] : 0.0f;
         }
+    }
+    if constexpr (JL) {
+        const uint4* src = static_cast<const uint4*>(a.J);
+        uint4* dst = reinterpret_cast<uint4*>(sJ8);
+        const int n16 = Np * Np / 16;
+        for (int u = tid; u < n16; u += kVT) dst[u] = src[u];
     }
     int64_t bstep = -1;
     if (tid < RB) {
@@ -310,7 +319,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) I[r][c] = 0;
             if constexpr (FORM == 1)
-                dot_i8<CPT, RB>(static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
+                dot_i8<CPT, RB>(JL ? sJ8 : static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
             else
                 dot_ell<CPT, RB>(static_cast<const int32_t*>(a.J), sS8, Np, a.ell_d, tid, I);
         }
@@ -402,53 +411,71 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
 
 namespace {
 
-template <int FORM, int RB, bool MH>
+template <int FORM, int CPT, int RB, bool MH, bool JL>
+hipError_t launch_valu_cpt(const SweepArgs& a, size_t lds, hipStream_t st)
+{
+    const auto kern = k_sweep_valu<FORM, CPT, RB, MH, JL>;
+    // dynamic LDS above the default limit must be allowed per kernel
+    if (lds > 64 * 1024) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    const unsigned blocks = static_cast<unsigned>((a.R + RB - 1) / RB);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kVT), lds, st, a);
+    return hipGetLastError();
+}
+
+template <int FORM, int RB, bool MH, bool JL>
 hipError_t launch_valu_t(const SweepArgs& a, hipStream_t st)
 {
     const int cpt = (a.Np + kVT - 1) / kVT;
-    const unsigned blocks = static_cast<unsigned>((a.R + RB - 1) / RB);
-    const size_t lds = valu_lds_bytes(FORM, RB, a.Np);
-    if (cpt <= 1)
-        hipLaunchKernelGGL((k_sweep_valu<FORM, 1, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
-    else if (cpt <= 2)
-        hipLaunchKernelGGL((k_sweep_valu<FORM, 2, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
-    else if (cpt <= 4)
-        hipLaunchKernelGGL((k_sweep_valu<FORM, 4, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
-    else if (cpt <= 8)
-        hipLaunchKernelGGL((k_sweep_valu<FORM, 8, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
-    else if (cpt <= 16)
-        hipLaunchKernelGGL((k_sweep_valu<FORM, 16, RB, MH>), dim3(blocks), dim3(kVT), lds, st, a);
-    else
+    const size_t lds = valu_lds_bytes(FORM, RB, a.Np, JL);
+    if (cpt <= 1) return launch_valu_cpt<FORM, 1, RB, MH, JL>(a, lds, st);
+    if (cpt <= 2) return launch_valu_cpt<FORM, 2, RB, MH, JL>(a, lds, st);
+    if constexpr (JL) {
+        return hipErrorInvalidValue;  // J in LDS: Np <= 384
+    } else {
+        if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL>(a, lds, st);
+        if (cpt <= 8) return launch_valu_cpt<FORM, 8, RB, MH, JL>(a, lds, st);
+        if (cpt <= 16) return launch_valu_cpt<FORM, 16, RB, MH, JL>(a, lds, st);
         return hipErrorInvalidValue;
-    return hipGetLastError();
+    }
 }
 
 }  // namespace
 
-size_t valu_lds_bytes(int form, int rb, int Np)
+size_t valu_lds_bytes(int form, int rb, int Np, bool jl)
 {
-    return static_cast<size_t>(rb) * Np * (form == kValuFp32 ? sizeof(float) : 1);
+    const size_t spins = static_cast<size_t>(rb) * Np * (form == kValuFp32 ? sizeof(float) : 1);
+    return jl ? valu_jl_offset(rb, Np) + static_cast<size_t>(Np) * Np : spins;
 }
 
-bool valu_variant(int form, int rb, int mh)
+bool valu_variant(int form, int rb, int mh, bool jl)
 {
     switch (form) {
-    case kValuFp32: return rb == kFp32Rows;
+    case kValuFp32: return rb == kFp32Rows && !jl;
     case kValuDot8: return (rb == 1 || rb == 2) && !mh;
-    case kValuEll: return rb == 1 || rb == 4;
+    case kValuEll: return (rb == 1 || rb == 4) && !jl;
     default: return false;
     }
 }
 
-hipError_t launch_sweep_valu(int form, int rb, const SweepArgs& a, hipStream_t st)
+hipError_t launch_sweep_valu(int form, int rb, bool jl, const SweepArgs& a, hipStream_t st)
 {
-    if (!valu_variant(form, rb, a.mh) || a.Np > kValuMaxNp) return hipErrorInvalidValue;
-    if (form == kValuFp32) return a.mh ? launch_valu_t<kValuFp32, kFp32Rows, true>(a, st)
-                                       : launch_valu_t<kValuFp32, kFp32Rows, false>(a, st);
-    if (form == kValuDot8) return rb == 1 ? launch_valu_t<kValuDot8, 1, false>(a, st)
-                                          : launch_valu_t<kValuDot8, 2, false>(a, st);
-    if (rb == 1) return a.mh ? launch_valu_t<kValuEll, 1, true>(a, st) : launch_valu_t<kValuEll, 1, false>(a, st);
-    return a.mh ? launch_valu_t<kValuEll, 4, true>(a, st) : launch_valu_t<kValuEll, 4, false>(a, st);
+    if (!valu_variant(form, rb, a.mh, jl) || a.Np > kValuMaxNp) return hipErrorInvalidValue;
+    if (jl && valu_lds_bytes(form, rb, a.Np, true) > static_cast<size_t>(kLdsMax)) return hipErrorInvalidValue;
+    if (form == kValuFp32) return a.mh ? launch_valu_t<kValuFp32, kFp32Rows, true, false>(a, st)
+                                       : launch_valu_t<kValuFp32, kFp32Rows, false, false>(a, st);
+    if (form == kValuDot8) {
+        if (jl) return rb == 1 ? launch_valu_t<kValuDot8, 1, false, true>(a, st)
+                               : launch_valu_t<kValuDot8, 2, false, true>(a, st);
+        return rb == 1 ? launch_valu_t<kValuDot8, 1, false, false>(a, st)
+                       : launch_valu_t<kValuDot8, 2, false, false>(a, st);
+    }
+    if (rb == 1) return a.mh ? launch_valu_t<kValuEll, 1, true, false>(a, st)
+                             : launch_valu_t<kValuEll, 1, false, false>(a, st);
+    return a.mh ? launch_valu_t<kValuEll, 4, true, false>(a, st) : launch_valu_t<kValuEll, 4, false, false>(a, st);
 }
 
 }  // namespace phia
