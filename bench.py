@@ -62,9 +62,10 @@ WORKLOADS = {
     "tts_sweep": dict(gen="tts_sweep", args=dict(sizes=(8, 16, 32, 64, 128, 256, 512, 1024), seed=0), R=256,
                       T=1000, sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
                       desc="time to target versus N for the Table 2 families (maxcut_dense, maxcut_d3, sk_bool, "
-                           "sk_ising, sk_uniform, spin_model; fractional ones on the 2^-6 grid); 256 replicas x "
-                           "max(1000, 10 N) steps per run; target: exhaustive ground state for N <= 20, else the "
-                           "best energy of a 20x longer run"),
+                           "sk_ising, sk_uniform, nae_3_sat, spin_model; fractional ones on the 2^-6 grid); 10 "
+                           "instances per point, 256 replicas x max(1000, 10 N) steps per run; target: the planted "
+                           "energy (nae_3_sat), the exhaustive ground state for N <= 20, else the best energy of a "
+                           "20x longer run; median TTS over the instances"),
     "maxcut256": dict(gen="er_maxcut", args=dict(N=256, p=0.06, seed=0, signed=True), R=4, T=10000,
                       sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
                       desc="maxcut ER G(256,0.06) w=+-1, h=0, few replicas (default 4) x 1e4 steps"),
@@ -354,7 +355,9 @@ def ground_energy_exhaustive(Ji, hi):
 
 def run_tts_sweep(args, w):
     """Time to target of one anneal (R replicas in parallel) for each Table 2
-    family and size.  One JSON line with every point."""
+    family and size, over several instances per point (the median TTS over
+    the instances, as Sec. 3.2 reports per problem type).  One JSON line
+    with every point."""
     import numpy as np
     import torch
     from paper_2407_10205_amd import instances as inst, phia
@@ -363,42 +366,53 @@ def run_tts_sweep(args, w):
     stream = torch.cuda.Stream()
     points = []
     t_all = time.perf_counter()
+    sizes = w["args"]["sizes"] if not args.tts_sizes else tuple(int(t) for t in args.tts_sizes.split(","))
     for fam in inst.TABLE2_FAMILIES:
-        for n in w["args"]["sizes"]:
+        for n in sizes:
             N = n + (n % 2 if fam == "maxcut_d3" else 0)
             T = max(w["T"], 10 * N)
-            J, h = inst.table2_family(fam, N, w["args"]["seed"] + n)
-            prob = phia.Problem(J, h, stream=stream.cuda_stream)
-            f = prob.info()["frac_bits"]
-            if N <= 20:
-                Ji = np.rint(J * 2 ** f).astype(np.int32)
-                hi = np.rint(h * 2 ** f).astype(np.int32)
-                target, how = ground_energy_exhaustive(Ji, hi), "exhaustive"
-            else:
-                prob.anneal(R, 20 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
-                            refresh_L=s["refresh_L"], seed=777)
-                target, how = int(prob.best_exact()[0]), "best of a 20x longer run"
-            prob.anneal(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"], refresh_L=s["refresh_L"],
-                        seed=1)  # warm-up
-            torch.cuda.synchronize()
-            reps, succ = 3, []
-            t0 = time.perf_counter()
-            for i in range(reps):
+            per = []
+            for k in range(args.tts_instances):
+                seed = w["args"]["seed"] + 1000 * k + n
+                if fam == "nae_3_sat":
+                    J, h, M, _, _ = inst.nae_3_sat(N, seed)
+                else:
+                    J, h = inst.table2_family(fam, N, seed)
+                prob = phia.Problem(J, h, stream=stream.cuda_stream)
+                f = prob.info()["frac_bits"]
+                if fam == "nae_3_sat":
+                    target, how = -M, "planted (every clause NAE-satisfied)"
+                elif N <= 20:
+                    Ji = np.rint(J * 2 ** f).astype(np.int32)
+                    hi = np.rint(h * 2 ** f).astype(np.int32)
+                    target, how = ground_energy_exhaustive(Ji, hi), "exhaustive"
+                else:
+                    prob.anneal(R, 20 * T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
+                                refresh_L=s["refresh_L"], seed=777)
+                    target, how = int(prob.best_exact()[0]), "best of a 20x longer run"
+                if k == 0:  # warm-up of this shape
+                    prob.anneal(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
+                                refresh_L=s["refresh_L"], seed=1)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
                 prob.anneal(R, T, s["eps"], s["gamma"], beta0=s["beta0"], beta1=s["beta1"],
-                            refresh_L=s["refresh_L"], seed=100 + i)
+                            refresh_L=s["refresh_L"], seed=100 + k)
                 E, _, _ = prob.replica_best()
-                succ.append(float(np.mean(E <= target)))
-            t_run = (time.perf_counter() - t0) / reps
-            info = prob.info()
-            prob.close()
-            p_hat = float(np.mean(succ))
-            pt = {"family": fam, "N": N, "steps": T, "path": info["path_name"], "frac_bits": f, "sweep_kernel": info["sweep_kernel"],
-                  "group": info["group"], "target_units": target, "target": how, "replica_success": p_hat,
-                  "t_run_s": t_run, "tts99_s": tts99(t_run, p_hat, R)}
+                t_run = time.perf_counter() - t0
+                info = prob.info()
+                prob.close()
+                p_hat = float(np.mean(E <= target))
+                per.append(dict(t_run=t_run, p=p_hat, tts=tts99(t_run, p_hat, R)))
+            tts = [q["tts"] for q in per]
+            pt = {"family": fam, "N": N, "steps": T, "instances": len(per), "path": info["path_name"],
+                  "frac_bits": f, "sweep_kernel": info["sweep_kernel"], "group": info["group"], "target": how,
+                  "tts99_median_s": float(np.median(tts)), "solved_instances": int(sum(q["p"] > 0 for q in per)),
+                  "replica_success_mean": float(np.mean([q["p"] for q in per])),
+                  "t_run_median_s": float(np.median([q["t_run"] for q in per]))}
             points.append(pt)
             log(json.dumps(pt))
     out = {"metric": "tts99_s", "unit": "s", "n_gpus": 1, "higher_is_better": False, "data": "synthetic",
-           "config": {"workload": w["desc"], "replicas": R, "schedule": s},
+           "config": {"workload": w["desc"], "replicas": R, "schedule": s, "instances_per_point": args.tts_instances},
            "points": points, "wall_s": time.perf_counter() - t_all}
     print(json.dumps(out), flush=True)
 
@@ -538,6 +552,8 @@ def main():
                          "multiply beta by UP after an acceptance, DOWN after a rejection (1,1: fixed schedule)")
     ap.add_argument("--no-incremental", action="store_true",
                     help="recompute J.s in full every step (default: flip-incremental update where the sweep has it)")
+    ap.add_argument("--tts-instances", type=int, default=10, help="tts_sweep: instances per (family, N)")
+    ap.add_argument("--tts-sizes", default=None, help="tts_sweep: comma-separated sizes (default: the workload's)")
     ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
     ap.add_argument("--chunk", type=int, default=250, help="serving workload: steps per scheduling round")

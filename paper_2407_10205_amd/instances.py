@@ -104,6 +104,49 @@ def regular3_graph(N, seed):
     return np.abs(J)
 
 
+def nae_3_sat(N, seed, alpha=2.0, planted=True):
+    """NAE-3-SAT as an Ising instance (clause-to-triangle reduction).
+
+    Clause k holds three distinct variables v with literal signs t (literal
+    value t s_v).  It is not-all-equal satisfied iff its literals are not
+    all equal; the sum of its three pairwise literal products is then -1,
+    else +3.  With J_ij = -(sum of t_i t_j over the clauses that contain the
+    pair i, j) and h = 0, Eq. 2 gives E(s) = sum over clauses of that pair
+    sum, so E >= -M for M clauses, with equality exactly when every clause
+    is NAE-satisfied.  Couplings are small integers (pairs shared by several
+    clauses add up), the coefficient set of the family in Table 2.
+
+    M = round(alpha N) clauses on uniformly drawn variable triples with fair
+    literal signs; planted=True keeps a clause only if a hidden uniform
+    assignment z NAE-satisfies it, so E(z) = -M is the ground energy.
+    Returns (J, h, M, z, clauses) with clauses an [M][3][2] array of
+    (variable, sign).
+    """
+    if N < 3:
+        raise ValueError("NAE-3-SAT needs at least three variables")
+    g = rng(seed)
+    z = g.choice([-1, 1], size=N)
+    M = max(1, int(round(alpha * N)))
+    clauses = []
+    while len(clauses) < M:
+        v = g.choice(N, size=3, replace=False)
+        t = g.choice([-1, 1], size=3)
+        lit = t * z[v]
+        if planted and lit[0] == lit[1] == lit[2]:
+            continue
+        clauses.append(np.stack([v, t], axis=1))
+    C = np.array(clauses, dtype=np.int64)
+    J = np.zeros((N, N))
+    for cl in C:
+        for a in range(3):
+            for b in range(a + 1, 3):
+                i, j = cl[a, 0], cl[b, 0]
+                w = float(cl[a, 1] * cl[b, 1])
+                J[i, j] -= w
+                J[j, i] -= w
+    return J, np.zeros(N), M, z.astype(np.float64), C
+
+
 # Table 2 families.  The table lists the problem's coefficients; as for the
 # max-cut rows (graph weights w, Ising couplings J = -w), every family enters
 # Eq. 2 with couplings -w, so that all of them are frustrated.
@@ -127,10 +170,13 @@ def table2_family(name, N, seed, frac_bits=6):
     if name == "spin_model":            # w_ij, h_i uniform on [-1, 1]
         J, h = uniform_fixed(N, seed, frac_bits=frac_bits)
         return -J, h
+    if name == "nae_3_sat":             # planted NAE-3-SAT, 2 N clauses (reduction above: already E = pair sums)
+        J, h, _, _, _ = nae_3_sat(N, seed)
+        return J, h
     raise ValueError(f"unknown family {name}")
 
 
-TABLE2_FAMILIES = ("maxcut_dense", "maxcut_d3", "sk_bool", "sk_ising", "sk_uniform", "spin_model")
+TABLE2_FAMILIES = ("maxcut_dense", "maxcut_d3", "sk_bool", "sk_ising", "sk_uniform", "nae_3_sat", "spin_model")
 
 
 def random_field_pm1(N, seed):

@@ -26,8 +26,49 @@ def test_table2_families(name):
     if name == "spin_model":
         assert np.all(np.abs(off) <= 1) and np.all(np.abs(h) <= 1)
         assert np.all(off * 64 == np.rint(off * 64)) and np.all(h * 64 == np.rint(h * 64))
+    if name == "nae_3_sat":
+        assert np.all(off == np.rint(off)) and np.any(off != 0)
     if name != "spin_model":
         assert np.all(h == 0)
+
+
+def _clause_energy(C, s):
+    """Sum over clauses of 3 (literals all equal) or -1 (not all equal),
+    counted clause by clause from the literal values."""
+    E = 0
+    for cl in C:
+        lit = cl[:, 1] * s[cl[:, 0]]
+        E += 3 if lit[0] == lit[1] == lit[2] else -1
+    return E
+
+
+def test_nae_3_sat_reduction_pins(O):
+    """NAE-3-SAT through the clause-to-triangle reduction: Eq. 2 of the
+    instance equals the clause count formula (3 per all-equal clause, -1
+    per NAE-satisfied one) on random states; planted instances (N <= 16,
+    2 N clauses) have exhaustive ground energy -M, reached by the hidden
+    assignment; the four sign patterns of one variable triple that together
+    exclude all eight assignments leave one clause violated (ground 0)."""
+    rs = np.random.default_rng(0)
+    for N, seed in ((6, 1), (9, 2), (12, 3), (16, 4)):
+        J, h, M, z, C = inst.nae_3_sat(N, seed)
+        Ji, hi = J.astype(np.int32), h.astype(np.int32)
+        for _ in range(20):
+            s = rs.choice([-1, 1], size=N).astype(np.int8)
+            assert O.energy(Ji, hi, s) == _clause_energy(C, s)
+        Eg, sg = O.bruteforce(Ji, hi)
+        assert Eg == -M
+        assert O.energy(Ji, hi, z.astype(np.int8)) == -M
+        assert _clause_energy(C, sg) == -M
+    C = np.array([[[0, 1], [1, 1], [2, 1]], [[0, 1], [1, 1], [2, -1]],
+                  [[0, 1], [1, -1], [2, 1]], [[0, -1], [1, 1], [2, 1]]])
+    J = np.zeros((3, 3), np.int32)
+    for cl in C:
+        for a in range(3):
+            for b in range(a + 1, 3):
+                J[cl[a, 0], cl[b, 0]] -= cl[a, 1] * cl[b, 1]
+                J[cl[b, 0], cl[a, 0]] -= cl[a, 1] * cl[b, 1]
+    assert O.bruteforce(J, np.zeros(3, np.int32))[0] == 0
 
 
 def test_bench_exhaustive_ground_energy_matches_oracle(O):
