@@ -68,6 +68,9 @@ def _load():
     lib.oracle_anneal.restype = C.c_int
     lib.oracle_anneal_mh.argtypes = lib.oracle_anneal.argtypes + [C.POINTER(_MhC)]
     lib.oracle_anneal_mh.restype = C.c_int
+    a = list(lib.oracle_anneal.argtypes)
+    lib.oracle_anneal_ex.argtypes = a[:15] + [C.c_int] + a[15:] + [C.POINTER(_MhC)]
+    lib.oracle_anneal_ex.restype = C.c_int
     lib.oracle_argmin.argtypes = [C.c_int, P]
     lib.oracle_argmin.restype = C.c_int
     _lib = lib
@@ -192,15 +195,16 @@ class Run:
 
 
 def anneal(J, h, frac_bits, R, betas, eps, gamma, L, seed, k0=0, k1=None, r0=0,
-           run=None, trace=False, threads=1, deriv="tanh", mh=None):
+           run=None, trace=False, threads=1, deriv="tanh", mh=None, ikick=False):
     """Run steps k0 <= k < k1 (default: all of betas) of the sweep.
 
     With run=None a fresh anneal starts (k0 must be 0); otherwise the given
     Run is continued in place.  deriv: "tanh" (Eq. 8) or "poly2" (the
     quadratic of the POLY2 mode).  mh: None, or (up, down) to accept or reject
     every trajectory of L steps and scale beta by up / down after each
-    outcome (trace=True also records the outcomes in run.mhtrace).  Returns
-    the Run.
+    outcome (trace=True also records the outcomes in run.mhtrace).  ikick:
+    the initial-kick variant (Table 3, state 2; not with mh).  Returns the
+    Run.
     """
     N, J, h = _ij(J, h)
     betas = np.ascontiguousarray(betas, dtype=np.float32)
@@ -215,7 +219,11 @@ def anneal(J, h, frac_bits, R, betas, eps, gamma, L, seed, k0=0, k1=None, r0=0,
             {"tanh": 0, "poly2": 1}[deriv],
             _p(run.x), _p(run.v), _p(run.bestE), _p(run.bestS),
             _p(run.bestStep), _p(run.Etrace), int(threads))
-    if mh is None:
+    if ikick:
+        if mh is not None:
+            raise ValueError("the initial kick is not combined with the accept/reject step")
+        rc = _load().oracle_anneal_ex(*args[:15], 1, *args[15:], None)
+    elif mh is None:
         rc = _load().oracle_anneal(*args)
     else:
         L = int(L)

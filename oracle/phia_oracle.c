@@ -381,9 +381,21 @@ static void metropolis(const mh_ctx* m, int N, float sigma, int64_t rr, int64_t 
     if (m->trace && traj >= m->m_first) m->trace[traj - m->m_first] = outcome;
 }
 
+/* Momentum update of A7's second line at the current x with step size h_eps:
+ * v <- v + h_eps (c sech^2(gamma x) I - x), c = beta gamma sigma (times lam). */
+static void kick(int N, float c, float h_eps, float gamma, int deriv, const float* x, const int32_t* I, float* v)
+{
+    for (int i = 0; i < N; ++i) {
+        float d = deriv ? oracle_poly2(gamma * x[i]) : oracle_sech2(gamma * x[i]);
+        float p = c * d;
+        float g = fmaf(p, (float)I[i], -x[i]);
+        v[i] = fmaf(h_eps, g, v[i]);
+    }
+}
+
 static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
                        int64_t rr, int64_t k0, int64_t k1, const float* betas,
-                       float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
+                       float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv, int ikick,
                        float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                        int64_t* Etrace, int8_t* s, int32_t* I, const mh_ctx* mh, int64_t* Elast)
 {
@@ -414,6 +426,15 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
                 memcpy(mh->x0, x, sizeof(float) * (size_t)N);
                 *mh->Qstart = kinetic_sum(N, x, v);
             }
+            /* Table 3, state 2 (initial-kick variant): the trajectory's first
+             * momentum update is half a kick at its start point, with the field
+             * of the current spins and this step's beta; the drift-kick steps
+             * that follow then form a leapfrog (velocities at half steps). */
+            if (ikick) {
+                for (int i = 0; i < N; ++i) s[i] = (x[i] >= 0.0f) ? 1 : -1;
+                oracle_local_field(N, J, h, s, I);
+                kick(N, (betas[k] * gamma) * sigma, 0.5f * eps, gamma, deriv, x, I, v);
+            }
         }
         /* A7, first line: drift with the current momentum. */
         for (int i = 0; i < N; ++i) x[i] = fmaf(eps, v[i], x[i]);
@@ -438,23 +459,20 @@ static void anneal_one(int N, const int32_t* J, const int32_t* h, float sigma,
          * (POLY2 mode: the quadratic in place of sech^2). */
         float c = (betas[k] * gamma) * sigma;
         if (mh) c = c * *mh->lam;
-        for (int i = 0; i < N; ++i) {
-            float d = deriv ? oracle_poly2(gamma * x[i]) : oracle_sech2(gamma * x[i]);
-            float p = c * d;
-            float g = fmaf(p, (float)I[i], -x[i]);
-            v[i] = fmaf(eps, g, v[i]);
-        }
+        kick(N, c, eps, gamma, deriv, x, I, v);
     }
 }
 
-int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
+int oracle_anneal_ex(int N, const int32_t* J, const int32_t* h, int frac_bits,
                      int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
-                     float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
+                     float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv, int ikick,
                      float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                      int64_t* Etrace, int threads, const oracle_mh* mh)
 {
     if (N < 1 || R < 0 || k0 < 0 || k1 < k0 || L < 1 || frac_bits < 0 || frac_bits > 30) return -1;
     if (deriv != 0 && deriv != 1) return -1;
+    if (ikick != 0 && ikick != 1) return -1;
+    if (ikick && mh && mh->enable) return -1;
     if (init && k0 != 0) return -1;
     if (mh && !mh->enable) mh = NULL;
     if (mh && (!mh->x0 || !mh->Estart || !mh->Qstart || !mh->Elast || !mh->lam || !mh->acc || !mh->dec))
@@ -497,7 +515,7 @@ int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
                 Elast = mh->Elast + r;
                 pc = &ctx;
             }
-            anneal_one(N, J, h, sigma, r0 + r, k0, k1, betas, eps, gamma, L, seed, init, deriv,
+            anneal_one(N, J, h, sigma, r0 + r, k0, k1, betas, eps, gamma, L, seed, init, deriv, ikick,
                        x + (int64_t)r * N, v + (int64_t)r * N, bestE + r,
                        bestS + (int64_t)r * N, bestStep + r,
                        Etrace ? Etrace + (int64_t)r * (k1 - k0) : NULL, s, I, pc, Elast);
@@ -508,13 +526,23 @@ int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
     return fail ? -1 : 0;
 }
 
+int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
+                     int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
+                     float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
+                     float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                     int64_t* Etrace, int threads, const oracle_mh* mh)
+{
+    return oracle_anneal_ex(N, J, h, frac_bits, R, r0, k0, k1, betas, eps, gamma, L, seed, init, deriv, 0,
+                            x, v, bestE, bestS, bestStep, Etrace, threads, mh);
+}
+
 int oracle_anneal(int N, const int32_t* J, const int32_t* h, int frac_bits,
                   int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
                   float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv,
                   float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                   int64_t* Etrace, int threads)
 {
-    return oracle_anneal_mh(N, J, h, frac_bits, R, r0, k0, k1, betas, eps, gamma, L, seed, init, deriv,
+    return oracle_anneal_ex(N, J, h, frac_bits, R, r0, k0, k1, betas, eps, gamma, L, seed, init, deriv, 0,
                             x, v, bestE, bestS, bestStep, Etrace, threads, NULL);
 }
 

@@ -93,6 +93,17 @@ int oracle_anneal_mh(int N, const int32_t* J, const int32_t* h, int frac_bits,
                      float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
                      int64_t* Etrace, int threads, const oracle_mh* mh);
 
+/* Both of the above, plus ikick = 1: the initial-kick variant of Table 3,
+ * state 2 -- after every momentum draw, half a kick (step eps / 2) at the
+ * current x with the field of its spins and the step's beta, so that the
+ * drift-kick steps of each trajectory form a leapfrog.  ikick with an
+ * enabled accept/reject step is rejected (-1). */
+int oracle_anneal_ex(int N, const int32_t* J, const int32_t* h, int frac_bits,
+                     int R, int64_t r0, int64_t k0, int64_t k1, const float* betas,
+                     float eps, float gamma, int64_t L, uint64_t seed, int init, int deriv, int ikick,
+                     float* x, float* v, int64_t* bestE, int8_t* bestS, int64_t* bestStep,
+                     int64_t* Etrace, int threads, const oracle_mh* mh);
+
 /* Lowest best energy over R replicas; ties take the lowest replica index. */
 int oracle_argmin(int R, const int64_t* bestE);
 

@@ -310,6 +310,65 @@ def test_harmonic_closed_form(O):
     assert np.max(np.abs(run.v - vr) / scale) < 1e-4
 
 
+def _leapfrog_closed_form(x0, v0, eps, n, center=0.0):
+    """Stormer-Verlet leapfrog for x'' = center - x started with a half kick:
+    x_n = c + (x0 - c) cos(n t) + (eps v0 / sin t) sin(n t), cos t = 1 - eps^2 / 2
+    (x_1 = x0 + eps (v0 + eps (c - x0) / 2) fixes the sine coefficient)."""
+    t = math.acos(1.0 - eps * eps / 2.0)
+    return center + (x0 - center) * np.cos(n * t) + (eps * v0 / math.sin(t)) * np.sin(n * t)
+
+
+def _ikick_draws(O, seed, R, N, rnd):
+    return np.array([[O.gauss(seed, 1, r, rnd, i) for i in range(N)] for r in range(R)], np.float64)
+
+
+def test_initial_kick_is_a_leapfrog_harmonic(O):
+    """Initial-kick variant (Table 3, state 2), J = h = 0: one trajectory
+    from the drawn x0 and momentum v0 follows the leapfrog closed form for
+    every step count, and the returned momentum is the half-step one,
+    (x_{n+1} - x_n) / eps.  Without the half kick (A7 alone) the same run
+    misses the closed form."""
+    N, R, eps, seed = 4, 3, 0.2, 17
+    J = np.zeros((N, N), np.int32)
+    h = np.zeros(N, np.int32)
+    x0 = np.array([[O.gauss(seed, 0, r, 0, i) for i in range(N)] for r in range(R)], np.float64)
+    v0 = _ikick_draws(O, seed, R, N, 0)
+    for T in (1, 2, 7, 50):
+        betas = np.full(T, 1.0, np.float32)
+        run = O.anneal(J, h, 0, R, betas, eps, 1.0, 10**9, seed, ikick=True)
+        xr = _leapfrog_closed_form(x0, v0, eps, T)
+        vr = (_leapfrog_closed_form(x0, v0, eps, T + 1) - xr) / eps
+        assert np.max(np.abs(run.x - xr)) < 2e-5 * T, T
+        assert np.max(np.abs(run.v - vr)) < 2e-5 * T, T
+    plain = O.anneal(J, h, 0, R, np.full(50, 1.0, np.float32), eps, 1.0, 10**9, seed)
+    assert np.max(np.abs(plain.x - _leapfrog_closed_form(x0, v0, eps, 50))) > 1e-2
+
+
+def test_initial_kick_every_trajectory_and_field_term(O):
+    """The half kick opens every trajectory of L steps (fresh momentum of
+    round m, chained closed forms), and it carries the field: with J = 0,
+    h = 1 unit, c = beta gamma sigma = 1 (beta = 2^20, gamma = 2^-20, where
+    sech^2 = 1 in FP32) the force is 1 - x, a leapfrog about x = 1."""
+    N, R, eps, seed, L, T = 3, 2, 0.25, 5, 20, 60
+    J = np.zeros((N, N), np.int32)
+    for hv, center, beta, gamma in ((0, 0.0, 1.0, 1.0), (1, 1.0, 2.0**20, 2.0**-20)):
+        h = np.full(N, hv, np.int32)
+        betas = np.full(T, beta, np.float32)
+        run = O.anneal(J, h, 0, R, betas, eps, gamma, L, seed, ikick=True)
+        x = np.array([[O.gauss(seed, 0, r, 0, i) for i in range(N)] for r in range(R)], np.float64)
+        for m in range(T // L):
+            v = _ikick_draws(O, seed, R, N, m)
+            x_end = _leapfrog_closed_form(x, v, eps, L, center)
+            v_end = (_leapfrog_closed_form(x, v, eps, L + 1, center) - x_end) / eps
+            x = x_end
+        assert np.max(np.abs(run.x - x)) < 1e-5, hv
+        assert np.max(np.abs(run.v - v_end)) < 1e-5, hv
+        plain = O.anneal(J, h, 0, R, betas, eps, gamma, L, seed)
+        assert np.max(np.abs(plain.x - x)) > 1e-2, hv
+    with pytest.raises(ValueError):
+        O.anneal(J, h, 0, 1, betas, eps, gamma, L, seed, ikick=True, mh=(1.0, 1.0))
+
+
 def test_decoupled_spins_conserve_surrogate_energy(O):
     """J = 0, h != 0, constant beta: the kick is the gradient of
     U(x) = -beta sigma h tanh(gamma x) + x^2/2 (Eq. 5 with Eq. 7-8), so the
