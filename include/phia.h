@@ -104,6 +104,14 @@ typedef struct {
     int32_t metropolis;     /* 0: no accept/reject step; 1: accept or reject every
                                trajectory of refresh_L steps                          */
     float mh_up, mh_down;   /* > 0, finite: factors of the beta multiplier            */
+    int32_t initial_kick;   /* 0: A7 as written; 1: the initial-kick variant of
+                               Table 3 state 2 -- after every momentum draw, half a
+                               kick (step eps/2) at the current x with the field of
+                               its spins and the step's beta, so that each
+                               trajectory's drift-kick steps form a leapfrog.  Runs
+                               on the VALU sweep (FP32, I8 and ELL paths; else
+                               PHIA_ERANGE at phia_anneal_start), not with
+                               metropolis, not in batches or the server (EINVAL)  */
 } phia_schedule;
 
 typedef struct {

@@ -364,6 +364,7 @@ phia_status phia_batch_create(phia_problem* const* probs, int32_t count, const i
                         p->path == PHIA_PATH_FP32 ? "FP32" : "ELL");
         if (p->Np > kBatchMaxNp) return fail(PHIA_ERANGE, "problem %d: N = %d exceeds %d for batches", i, p->N, kBatchMaxNp);
         if ((st = check_schedule(replicas[i], steps[i], &scheds[i])) != PHIA_OK) return st;
+        if (scheds[i].initial_kick) return fail(PHIA_EINVAL, "schedule %d: batches run without the initial kick", i);
         if (steps[i] >= (int64_t(1) << 31)) return fail(PHIA_EINVAL, "problem %d: too many steps", i);
     }
     {

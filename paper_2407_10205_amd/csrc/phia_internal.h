@@ -25,6 +25,7 @@ struct SweepArgs {
     float eps, gamma;
     int32_t deriv;              // 0: sech^2 (Eq. 8), 1: POLY2 quadratic
     int32_t ell_d;              // ELL slots per row (ELL path)
+    int32_t ikick;              // 1: half a kick after every momentum draw (VALU sweep only)
     int64_t L;                  // momentum refresh period
     uint64_t seed;
     int64_t k0, k1;             // steps [k0, k1) of this launch

@@ -91,7 +91,7 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
     unsigned char* base = nullptr;
     if ((e = scratch_address(p->dev, &base)) != hipSuccess) return hip_fail(nullptr, e, "scratch address");
 
-    const Geometry g = plain_geometry(p, replicas);
+    const Geometry g = plain_geometry(p, replicas, s->initial_kick ? 1 : 0);
     if (!g.ok) return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
     const bool group = g.kind != 4 && g.G > 1;
     const size_t ncb = static_cast<size_t>(p->Np / 16);
@@ -138,6 +138,7 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
     a.gamma = s->gamma;
     a.L = s->refresh_L;
     a.deriv = s->deriv_mode;
+    a.ikick = s->initial_kick ? 1 : 0;
     a.seed = seed;
     a.R = replicas;
     a.r_base = 0;

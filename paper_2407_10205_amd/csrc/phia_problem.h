@@ -46,7 +46,7 @@ hipError_t clear_exchange(::phia_problem* p);
 int valu_crossover(int Np);
 phia_status setup_mh_geometry(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
-Geometry plain_geometry(::phia_problem* p, int R);
+Geometry plain_geometry(::phia_problem* p, int R, int ikick = 0);
 phia_status launch_batch_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
                                SweepArgs*& dtab, size_t& cap);
 phia_status launch_group_chunk(::phia_problem* const* probs, int count, const int64_t* k_end, hipStream_t st,
@@ -88,6 +88,7 @@ struct phia_problem {
     int64_t T = 0, k = 0, L = 1;
     float eps = 0.f, gamma = 0.f;
     int deriv = 0;  // phia_deriv of the current anneal
+    int ikick = 0;  // initial-kick variant of the current anneal
     // accept/reject step of the current anneal
     int mh = 0;
     float mh_up = 1.f, mh_down = 1.f;

@@ -510,6 +510,14 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
 static void choose_geometry(phia_problem* p, int R)
 {
     p->geo.ok = false;
+    if (p->ikick) {
+        // the initial kick is a variant of the VALU sweep only
+        int rb = p->path == PHIA_PATH_FP32 ? kFp32Rows : p->path == PHIA_PATH_ELL ? ell_rows(R) : valu_rows(R);
+        if (const char* env = std::getenv("PHIA_GEOMETRY")) (void)std::sscanf(env, "valu,%d", &rb);
+        if (p->path == PHIA_PATH_FP32 || p->path == PHIA_PATH_ELL || p->path == PHIA_PATH_I8)
+            make_geometry_valu(p, R, rb, p->geo);
+        return;
+    }
     int f_mt = 0, f_G = 0, f_j = -1, f_c = kCbwMax;
     if (const char* env = std::getenv("PHIA_GEOMETRY")) {
         int f_x = -1;
@@ -603,17 +611,19 @@ void free_state(phia_problem* p)
 // Launch geometry that an anneal of R replicas without the accept/reject
 // step or energy traces would take (forced, tuned, cached or default), with
 // the problem's current anneal left as it is.
-Geometry plain_geometry(phia_problem* p, int R)
+Geometry plain_geometry(phia_problem* p, int R, int ikick)
 {
     const Geometry saved = p->geo;
-    const int mh = p->mh;
+    const int mh = p->mh, ik = p->ikick;
     const bool trace = p->trace;
     p->mh = 0;
+    p->ikick = ikick;
     p->trace = false;
     choose_geometry(p, R);
     const Geometry g = p->geo;
     p->geo = saved;
     p->mh = mh;
+    p->ikick = ik;
     p->trace = trace;
     return g;
 }
@@ -626,6 +636,7 @@ SweepArgs sweep_args(const phia_problem* p)
     a.h = p->dh;
     a.J = p->geo.kind == 2 ? p->dJ4 : p->dJ;
     a.ell_d = p->ell_d;
+    a.ikick = p->ikick;
     a.ctab = p->dctab;
     a.eps = p->eps;
     a.gamma = p->gamma;
@@ -897,6 +908,9 @@ phia_status check_schedule(int32_t replicas, int64_t steps, const phia_schedule*
     if (s->metropolis != 0 && s->metropolis != 1) return fail(PHIA_EINVAL, "metropolis = %d is neither 0 nor 1", s->metropolis);
     if (s->metropolis && !(std::isfinite(s->mh_up) && std::isfinite(s->mh_down) && s->mh_up > 0.0f && s->mh_down > 0.0f))
         return fail(PHIA_EINVAL, "mh_up and mh_down must be positive and finite");
+    if (s->initial_kick != 0 && s->initial_kick != 1)
+        return fail(PHIA_EINVAL, "initial_kick = %d is neither 0 nor 1", s->initial_kick);
+    if (s->initial_kick && s->metropolis) return fail(PHIA_EINVAL, "the initial kick is not combined with metropolis");
     return PHIA_OK;
 }
 
@@ -960,8 +974,9 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
         if (e != hipSuccess) return hip_fail(p, e, "synchronise before re-allocation");
     }
     const int mh = s->metropolis ? 1 : 0;
+    const int ikick = s->initial_kick ? 1 : 0;
     reuse = p->dx && p->R == replicas && p->T == steps && p->trace == (p->detrace != nullptr) && p->mh == mh &&
-            p->inc_mode_geo == p->inc_mode;
+            p->ikick == ikick && p->inc_mode_geo == p->inc_mode;
     if (!reuse) free_state(p);
     p->inc_mode_geo = p->inc_mode;
     p->R = replicas;
@@ -972,6 +987,7 @@ phia_status setup_state(phia_problem* p, int32_t replicas, int64_t steps, const 
     p->L = s->refresh_L;
     p->deriv = s->deriv_mode;
     p->mh = mh;
+    p->ikick = ikick;
     p->mh_up = mh ? s->mh_up : 1.0f;
     p->mh_down = mh ? s->mh_down : 1.0f;
     p->seed = seed;
@@ -1055,6 +1071,7 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     choose_geometry(p, replicas);
     if (!p->geo.ok) {
         free_state(p);
+        if (p->ikick) return fail(PHIA_ERANGE, "the initial kick runs on the VALU sweep (FP32, I8 and ELL paths)");
         return fail(PHIA_ERANGE, "no kernel geometry fits N = %d on this device", p->N);
     }
     if (p->geo.G > 1) {

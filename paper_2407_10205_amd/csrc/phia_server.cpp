@@ -301,6 +301,7 @@ phia_status phia_server_submit(phia_server* s, phia_problem* p, int32_t replicas
     phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if ((st = check_schedule(replicas, max_steps, sched)) != PHIA_OK) return st;
+    if (sched->initial_kick) return fail(PHIA_EINVAL, "served requests run without the initial kick");
     if (p->dev != s->dev) return fail(PHIA_EINVAL, "problem is on another device");
     Request* r = new (std::nothrow) Request();
     if (!r) return fail(PHIA_ENOMEM, "host allocation failed");

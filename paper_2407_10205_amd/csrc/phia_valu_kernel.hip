@@ -23,7 +23,8 @@
 // field, and the step (refresh, drift, readout, J.s + h, exact energy,
 // records, kick; Sec. 2.1, App. A A7, Table 3) is the one of the other
 // sweeps bit for bit.  MH adds the accept/reject step of App. A (Table 3,
-// state 4) at the end of every trajectory.
+// state 4) at the end of every trajectory; a.ikick the initial-kick variant
+// of Table 3, state 2 (half a kick after every momentum draw).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -234,6 +235,54 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
         }
     };
 
+    // J.s of the spins in LDS (no field yet)
+    auto js = [&](int (&I)[RB][CPT]) {
+        if constexpr (FORM == 0) {
+            dot_f32<CPT, RB>(static_cast<const float*>(a.J), sSf, N, Np, tid, I);
+        } else {
+#pragma unroll
+            for (int r = 0; r < RB; ++r)
+#pragma unroll
+                for (int c = 0; c < CPT; ++c) I[r][c] = 0;
+            if constexpr (FORM == 1)
+                dot_i8<CPT, RB>(JL ? sJ8 : static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
+            else
+                dot_ell<CPT, RB>(static_cast<const int32_t*>(a.J), sS8, Np, a.ell_d, tid, I);
+        }
+    };
+    // spins of the current x into LDS
+    auto put_spins = [&]() {
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int i = tid + kVT * c;
+#pragma unroll
+            for (int r = 0; r < RB; ++r) {
+                const bool pos = x[r][c] >= 0.0f;
+                if (i < Np) {
+                    if (FORM == 0)
+                        sSf[r * Np + i] = pos ? 1.0f : -1.0f;
+                    else
+                        sS8[r * Np + i] = pos ? 1 : -1;
+                }
+            }
+        }
+    };
+    // Kick of every element by step size he with the field I (mode branch
+    // outside the element loops).
+    auto kick_all = [&](const int (&I)[RB][CPT], float ck, float he) {
+        auto body = [&](auto mode) {
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+                    v[r][c] = kick_t<decltype(mode)::value>(x[r][c], v[r][c], I[r][c], ck * lamr[r], he, a.gamma);
+        };
+        if (a.deriv)
+            body(std::integral_constant<int, 1>{});
+        else
+            body(std::integral_constant<int, 0>{});
+    };
+
     for (int64_t k = a.k0; k < a.k1; ++k) {
         if (k % a.L == 0) {
             if (mh && k > 0) {
@@ -290,39 +339,33 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
                 }
                 kin_rows();
             }
+            if (a.ikick) {
+                // Table 3, state 2 (initial-kick variant): the trajectory's
+                // first momentum update is half a kick at its start point,
+                // with the field of the current spins and this step's beta.
+                put_spins();
+                __syncthreads();
+                int Ih[RB][CPT];
+                js(Ih);
+#pragma unroll
+                for (int r = 0; r < RB; ++r)
+#pragma unroll
+                    for (int c = 0; c < CPT; ++c) Ih[r][c] += hc[c];
+                kick_all(Ih, a.ctab[k], 0.5f * a.eps);
+                __syncthreads();  // the spins are read before the drift rewrites them
+            }
         }
         // Drift and readout; padded columns keep x = 0 and read +1, which
         // meets only zero couplings.
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int i = tid + kVT * c;
+        for (int c = 0; c < CPT; ++c)
 #pragma unroll
-            for (int r = 0; r < RB; ++r) {
-                x[r][c] = __builtin_fmaf(a.eps, v[r][c], x[r][c]);
-                const bool pos = x[r][c] >= 0.0f;
-                if (i < Np) {
-                    if (FORM == 0)
-                        sSf[r * Np + i] = pos ? 1.0f : -1.0f;
-                    else
-                        sS8[r * Np + i] = pos ? 1 : -1;
-                }
-            }
-        }
+            for (int r = 0; r < RB; ++r) x[r][c] = __builtin_fmaf(a.eps, v[r][c], x[r][c]);
+        put_spins();
         __syncthreads();
 
         int I[RB][CPT];
-        if constexpr (FORM == 0) {
-            dot_f32<CPT, RB>(static_cast<const float*>(a.J), sSf, N, Np, tid, I);
-        } else {
-#pragma unroll
-            for (int r = 0; r < RB; ++r)
-#pragma unroll
-                for (int c = 0; c < CPT; ++c) I[r][c] = 0;
-            if constexpr (FORM == 1)
-                dot_i8<CPT, RB>(JL ? sJ8 : static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
-            else
-                dot_ell<CPT, RB>(static_cast<const int32_t*>(a.J), sS8, Np, a.ell_d, tid, I);
-        }
+        js(I);
 
         // Field, and the row energy partials s (I + h) of step k.
         int part[RB];
@@ -368,19 +411,8 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
                 }
             }
         }
-        // Kick (mode branch outside the element loops).
-        const float ck = a.ctab[k];
-        auto kick_all = [&](auto mode) {
-#pragma unroll
-            for (int c = 0; c < CPT; ++c)
-#pragma unroll
-                for (int r = 0; r < RB; ++r)
-                    v[r][c] = kick_t<decltype(mode)::value>(x[r][c], v[r][c], I[r][c], ck * lamr[r], a.eps, a.gamma);
-        };
-        if (a.deriv)
-            kick_all(std::integral_constant<int, 1>{});
-        else
-            kick_all(std::integral_constant<int, 0>{});
+        // Kick (A7, second line).
+        kick_all(I, a.ctab[k], a.eps);
     }
 
 #pragma unroll

@@ -52,7 +52,8 @@ class Options(C.Structure):
 class Schedule(C.Structure):
     _fields_ = [("beta0", C.c_float), ("beta1", C.c_float), ("betas", C.c_void_p),
                 ("eps", C.c_float), ("gamma", C.c_float), ("refresh_L", C.c_int64), ("deriv_mode", C.c_int32),
-                ("metropolis", C.c_int32), ("mh_up", C.c_float), ("mh_down", C.c_float)]
+                ("metropolis", C.c_int32), ("mh_up", C.c_float), ("mh_down", C.c_float),
+                ("initial_kick", C.c_int32)]
 
 
 DERIV = {"tanh": 0, "poly2": 1}
@@ -153,12 +154,15 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
 
 
-def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, deriv="tanh", mh=None):
+def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, deriv="tanh", mh=None,
+                  ikick=False):
     """Build a Schedule; keeps a reference to the betas array on the object.
     deriv: "tanh" (Eq. 8) or "poly2" (the FPGA's quadratic).  mh: None, or
     (up, down) to accept or reject every trajectory of refresh_L steps and
-    multiply beta by up / down after each outcome ((1, 1): fixed schedule)."""
+    multiply beta by up / down after each outcome ((1, 1): fixed schedule).
+    ikick: the initial-kick variant (half a kick after every momentum draw)."""
     s = Schedule()
+    s.initial_kick = 1 if ikick else 0
     s.eps = eps
     s.gamma = gamma
     s.refresh_L = int(refresh_L)
@@ -241,8 +245,8 @@ class Problem:
         _check(lib().phia_set_wait_limit(self._p, int(polls)))
 
     def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
-              deriv="tanh", mh=None):
-        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh)
+              deriv="tanh", mh=None, ikick=False):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh, ikick)
         _check(lib().phia_anneal_start(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
 
@@ -253,18 +257,18 @@ class Problem:
         _check(lib().phia_sync(self._p))
 
     def anneal(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
-               deriv="tanh", mh=None):
-        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh)
+               deriv="tanh", mh=None, ikick=False):
+        self._sched = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, mh, ikick)
         _check(lib().phia_anneal(self._p, int(replicas), int(steps), C.byref(self._sched), int(seed)))
         self.R = int(replicas)
 
     def anneal_noalloc(self, replicas, steps, eps, gamma, x, v, bestE, bestS, bestStep, beta0=None, beta1=None,
-                       betas=None, refresh_L=50, seed=0, deriv="tanh"):
+                       betas=None, refresh_L=50, seed=0, deriv="tanh", ikick=False):
         """phia_anneal_noalloc: x, v, bestE, bestS, bestStep are device
         addresses (ints) of caller-owned buffers ([replicas][Np] float, float,
         [replicas] int64, [replicas][Np] int8, [replicas] int64).  Returns the
         argmin (energy in units, replica)."""
-        sch = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, None)
+        sch = make_schedule(steps, eps, gamma, beta0, beta1, betas, refresh_L, deriv, None, ikick)
         e, r = C.c_int64(), C.c_int32()
         _check(lib().phia_anneal_noalloc(self._p, int(replicas), int(steps), C.byref(sch), int(seed),
                                          C.c_void_p(x), C.c_void_p(v), C.c_void_p(bestE), C.c_void_p(bestS),
@@ -340,7 +344,8 @@ def _schedules(steps, schedules):
     keep = []
     for i, sc in enumerate(schedules):
         one = make_schedule(int(steps[i]), sc["eps"], sc["gamma"], sc.get("beta0"), sc.get("beta1"),
-                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"), sc.get("mh"))
+                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"), sc.get("mh"),
+                            sc.get("ikick", False))
         keep.append(one)
         C.memmove(C.byref(scheds, i * C.sizeof(Schedule)), C.byref(one), C.sizeof(Schedule))
     return scheds, keep
@@ -406,7 +411,8 @@ def batch_run(problems, replicas, steps, schedules, seeds):
     keep = []
     for i, sc in enumerate(schedules):
         one = make_schedule(int(stp[i]), sc["eps"], sc["gamma"], sc.get("beta0"), sc.get("beta1"),
-                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"), sc.get("mh"))
+                            sc.get("betas"), sc.get("refresh_L", 50), sc.get("deriv", "tanh"), sc.get("mh"),
+                            sc.get("ikick", False))
         keep.append(one)
         C.memmove(C.byref(scheds, i * C.sizeof(Schedule)), C.byref(one), C.sizeof(Schedule))
     _check(lib().phia_batch_run(arr, n, _ptr(reps), _ptr(stp), C.cast(scheds, C.c_void_p), _ptr(sd)))

@@ -219,3 +219,96 @@ def test_i8_valu_chunked_and_noalloc(P):
     assert same_E and same_x
     a.close()
     b.close()
+
+
+# ------------------------------------------------- initial kick ----
+def run_ikick(P, O, J, h, f, path, R, T, seed, L, geometry=None, chunks=(), deriv="tanh", rows=None):
+    say(f"ikick N={J.shape[0]} R={R} T={T} L={L} path={path} geometry={geometry} chunks={chunks}")
+    prob = P.Problem(J, h, frac_bits=f, path=path)
+    prob.set_trace(True)
+    with Forced(geometry):
+        prob.start(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=L, seed=seed, deriv=deriv, ikick=True)
+    for k in tuple(chunks) + (T,):
+        prob.run(k)
+    prob.sync()
+    E, S, K = prob.replica_best()
+    x, v, _ = prob.get_state()
+    dev = dict(E=E, S=S, K=K, x=x, v=v, info=prob.info(), trace=prob.trace(T))
+    prob.close()
+    Ji, hi = int_units(J, h, f)
+    betas = O.beta_linear(0.1, 3.0, T)
+    runs = {r: O.anneal(Ji, hi, f, 1, betas, 0.2, 1.0, L, seed, r0=r, trace=True, deriv=deriv, ikick=True)
+            for r in (range(R) if rows is None else rows)}
+    return dev, runs
+
+
+@pytest.mark.parametrize("path,geometry", [("fp32", None), ("i8", "valu,1"), ("i8", "valu,2"), ("ell", None)])
+def test_initial_kick_parity(P, O, path, geometry):
+    """Initial-kick variant (Table 3, state 2) on every VALU form: ragged
+    N = 150 fixed-point couplings for FP32 and int8, a 3-regular graph for
+    ELL; refresh period 23 that does not divide T = 201."""
+    if path == "ell":
+        J, h = inst.regular3_pm1(150, 9)
+        f = 0
+    else:
+        J, h = inst.sk_gauss_fixed(150, 4, frac_bits=5, bits=8)
+        f = 5
+    dev, runs = run_ikick(P, O, J, h, f, path, 7, 201, 21, 23, geometry=geometry)
+    assert dev["info"]["sweep_kernel"] == 4
+    assert_parity(dev, runs)
+    # the variant changes the trajectories
+    o0 = O.anneal(*int_units(J, h, f), f, 1, O.beta_linear(0.1, 3.0, 201), 0.2, 1.0, 23, 21, r0=0)
+    assert not np.array_equal(o0.x[0], runs[0].x[0])
+
+
+def test_initial_kick_chunked_poly2_and_large_n(P, O):
+    """Launch boundaries inside and at trajectory starts leave the results
+    unchanged (the half kick recomputes its field); POLY2 factor; the int8
+    form with J streamed (N = 600, no LDS copy) sampled."""
+    J, h = inst.er_maxcut(200, 0.05, 6, signed=True)
+    dev, runs = run_ikick(P, O, J, h, 0, "i8", 5, 120, 3, 20, chunks=(20, 33, 40, 100), deriv="poly2")
+    assert_parity(dev, runs)
+    J, h = inst.er_maxcut(600, 0.05, 7, signed=True)
+    dev, runs = run_ikick(P, O, J, h, 0, "i8", 3, 60, 4, 25, rows=[2])
+    assert dev["info"]["j_in_lds"] == 0
+    assert_parity(dev, runs)
+
+
+def test_initial_kick_noalloc_and_refusals(P):
+    """phia_anneal_noalloc with the initial kick equals phia_anneal; BF16
+    hi/lo (no VALU form) refuses it with PHIA_ERANGE, metropolis with
+    PHIA_EINVAL, and batch plans refuse it."""
+    import torch
+    J, h = inst.er_maxcut(130, 0.1, 8, signed=True)
+    R, T = 4, 90
+    a = P.Problem(J, h, path="i8")
+    a.anneal(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=30, seed=2, ikick=True)
+    E0, S0, K0 = a.replica_best()
+    x0, _, _ = a.get_state()
+    Np = a.info()["Np"]
+    d = torch.device("cuda:0")
+    bufs = [torch.empty(R, Np, dtype=torch.float32, device=d), torch.empty(R, Np, dtype=torch.float32, device=d),
+            torch.empty(R, dtype=torch.int64, device=d), torch.empty(R, Np, dtype=torch.int8, device=d),
+            torch.empty(R, dtype=torch.int64, device=d)]
+    a.anneal_noalloc(R, T, 0.2, 1.0, *(b.data_ptr() for b in bufs), beta0=0.1, beta1=3.0, refresh_L=30, seed=2,
+                     ikick=True)
+    torch.cuda.synchronize()
+    same = (np.array_equal(bufs[2].cpu().numpy(), E0) and
+            np.array_equal(bufs[0].cpu().numpy()[:, :x0.shape[1]].view(np.uint32), x0.view(np.uint32)))
+    assert same
+    with pytest.raises(P.PhiaError) as e:
+        a.start(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=30, seed=2, ikick=True, mh=(1.0, 1.0))
+    assert e.value.code == -1
+    a.close()
+    b = P.Problem(J * 300 / 128, h, path="bf16hilo", frac_bits=7, quantize=True)
+    with pytest.raises(P.PhiaError) as e:
+        b.start(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=30, seed=2, ikick=True)
+    assert e.value.code == -4
+    b.close()
+    c = P.Problem(J, h, path="i8")
+    c.start(R, T, 0.2, 1.0, beta0=0.1, beta1=3.0, refresh_L=30, seed=2)
+    c.sync()
+    with pytest.raises(P.PhiaError) as e:
+        P.Batch([c], [R], [T], [dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=30, ikick=True)])
+    assert e.value.code == -1
+    c.close()
