@@ -56,9 +56,10 @@ WORKLOADS = {
                            "3-regular +-1 with h in {-1,0,1}; 32 replicas x 5000 steps each, one graph launch"),
     "serve": dict(gen="serve", args=dict(rate=200.0, nmin=100, nmax=4000, seed=0), R=64, T=20000,
                   sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
-                  desc="serving: Poisson arrivals at 200 req/s, planted frustrated-loop instances, N log-uniform "
-                       "in [100,4000], half dense / half sparse, half integer / half fixed point (2^-4); 64 replicas, "
-                       "stop at the planted energy or 2e4 steps; beta in units of each instance's grid"),
+                  desc="serving: Poisson arrivals at 200 req/s, planted frustrated-loop instances (a pool of 120), "
+                       "N log-uniform in [100,4000], half dense / half sparse, each served as integers, as J 3/16 "
+                       "(2^-4 grid, int8) and as J 129/256 (2^-8 grid, BF16 hi/lo); 64 replicas, stop at the "
+                       "planted energy or 2e4 steps; beta divided by the coupling scale"),
     "tts_sweep": dict(gen="tts_sweep", args=dict(sizes=(8, 16, 32, 64, 128, 256, 512, 1024), seed=0), R=256,
                       T=1000, sched=dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25),
                       desc="time to target versus N for the Table 2 families (maxcut_dense, maxcut_d3, sk_bool, "
@@ -194,47 +195,65 @@ def make_batch(count, nmin, nmax, seed):
     return out
 
 
-def make_requests(count, rate, nmin, nmax, seed):
-    """Arrival times and planted instances of the serving workload."""
+# Precision variants of a served instance: (multiplier of the integer
+# couplings, fraction bits).  Positive scaling keeps the planted ground state;
+# 3/16 stays within int8 on the 2^-4 grid, 129/256 needs 16 bits (BF16 hi/lo).
+SERVE_VARIANTS = ((1, 0), (3, 4), (129, 8))
+
+
+def make_requests(count, rate, nmin, nmax, seed, pool=120):
+    """Arrival times and planted instances of the serving workload.  `pool`
+    distinct planted instances (sizes log-uniform, dense and sparse
+    alternating) are served in every precision variant; request i takes pool
+    entry i mod pool, variant (i // pool) mod 3 and its own seed."""
     import numpy as np
     from paper_2407_10205_amd import instances as inst
     g = inst.rng(seed)
     gaps = g.exponential(1.0 / rate, size=count)
-    sizes = np.rint(np.exp(g.uniform(np.log(nmin), np.log(nmax), size=count))).astype(int)
+    arrive = np.cumsum(gaps)
+    npool = min(pool, count)
+    sizes = np.rint(np.exp(g.uniform(np.log(nmin), np.log(nmax), size=npool))).astype(int)
+    base = []
+    for k in range(npool):
+        J, h, E, t = inst.planted_loops(int(sizes[k]), 20_000 + k, alpha=0.4, dense=(k % 2 == 1))
+        base.append((J, h, E, k % 2 == 1))
     reqs = []
     for i in range(count):
-        dense = i % 2 == 1
-        fixed = (i // 2) % 2 == 1
-        J, h, E, t = inst.planted_loops(int(sizes[i]), 20_000 + i, alpha=0.4, dense=dense)
-        f = 0
-        if fixed:  # the same instance held in fixed point: J / 16 on the 2^-4 grid
-            J, f = J / 16.0, 4
-        reqs.append(dict(arrive=float(np.cumsum(gaps)[i]), J=J, h=h, target=E, frac_bits=f, N=int(sizes[i]),
-                         dense=dense))
+        J, h, E, dense = base[i % npool]
+        mult, f = SERVE_VARIANTS[(i // npool) % len(SERVE_VARIANTS)]
+        if mult > 127 and dense and J.shape[0] > 2496:
+            mult, f = SERVE_VARIANTS[1]  # BF16 hi/lo holds N <= 2496 (sparse ones take ELL)
+        reqs.append(dict(arrive=float(arrive[i]), J0=J, h=h, target=E * mult, frac_bits=f,
+                         scale=mult / 2.0 ** f, N=J.shape[0], dense=dense, pool=i % npool, seed=17 + i))
     return reqs
 
 
 def run_serve_bench(args, w):
-    """Latency and throughput of the continuous-batching server."""
+    """Latency and throughput of the continuous-batching server.  Problems
+    defer their coupling upload to admission, so the server's memory budget
+    bounds everything the requests hold on the device."""
     import numpy as np
     from paper_2407_10205_amd import phia
     t = time.perf_counter()
     reqs = make_requests(args.requests, **w["args"])
-    probs = [phia.Problem(r["J"], r["h"], frac_bits=r["frac_bits"], path="i8") for r in reqs]
+    probs = [phia.Problem(r["J0"] * r["scale"], r["h"], frac_bits=r["frac_bits"], path="auto", defer_upload=True)
+             for r in reqs]
+    paths = [p.info()["path_name"] for p in probs]
     log(f"prepared {len(reqs)} requests in {time.perf_counter() - t:.1f} s")
     R, T, s = w["R"], w["T"], w["sched"]
-    srv = phia.Server(200 << 30, max_slots=args.slots, chunk_steps=args.chunk)
+    budget = int(args.serve_budget_gib * (1 << 30))
+    srv = phia.Server(budget, max_slots=args.slots, chunk_steps=args.chunk)
     tickets = []
     t0 = time.perf_counter()
     for r, p in zip(reqs, probs):
         delay = r["arrive"] - (time.perf_counter() - t0)
         if delay > 0:
             time.sleep(delay)
-        # beta in units of the instance's grid (beta 2^f): the fixed-point copy of
-        # an instance then anneals exactly as the integer one (power-of-two
-        # scaling), so success probabilities are matched across the mix
-        sr = dict(s, beta0=s["beta0"] * 2.0 ** r["frac_bits"], beta1=s["beta1"] * 2.0 ** r["frac_bits"])
-        tickets.append(srv.submit(p, R, T, r["target"], seed=17, **sr))
+        # beta divided by the couplings' scale: every variant of an instance
+        # then anneals the same real-valued dynamics, so success probabilities
+        # are matched across the mix
+        sr = dict(s, beta0=s["beta0"] / r["scale"], beta1=s["beta1"] / r["scale"])
+        tickets.append(srv.submit(p, R, T, r["target"], seed=r["seed"], **sr))
     res = [srv.wait(tk) for tk in tickets]
     srv.close()
     for p in probs:
@@ -243,16 +262,33 @@ def run_serve_bench(args, w):
     su = float(sum(R * r["N"] * x["steps_used"] for r, x in zip(reqs, res)))
     span = max(x["t_done"] for x in res) - min(x["t_arrive"] for x in res)
     ok = np.array([x["success"] for x in res], bool)
+    achieved = su * OPS_PER_SPIN_UPDATE / span
+    by_path = {pa: int(sum(1 for q in paths if q == pa)) for pa in sorted(set(paths))}
+    cpu = None
+    if not args.no_cpu:
+        # the oracle on every 10th pool instance, each variant's integer form
+        sample = [(reqs[k]["J0"], reqs[k]["h"]) for k in range(0, min(len(reqs), 120), 10)]
+        cpu = cpu_baseline_instances(sample, R, T, s, args.cpu_seconds, "serving pool")
     out = {"metric": "spin-updates/s", "value": su / span, "unit": "spin-updates/s", "n_gpus": 1,
            "steps": len(reqs), "warmup": 0, "ms_per_step": 1000 * span / len(reqs), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "i8", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None, "dtype": "mixed (i8, bf16 hi/lo, ell)", "data": "synthetic",
            "config": {"workload": w["desc"], "requests": len(reqs), "replicas": R, "max_steps": T,
-                      "slots": args.slots, "chunk_steps": args.chunk, "offered_rate_per_s": w["args"]["rate"]},
+                      "slots": args.slots, "chunk_steps": args.chunk, "offered_rate_per_s": w["args"]["rate"],
+                      "budget_bytes": budget, "paths": by_path, "variants": [list(v) for v in SERVE_VARIANTS]},
            "latency_p50_s": float(np.percentile(lat, 50)), "latency_p99_s": float(np.percentile(lat, 99)),
            "latency_p50_success_s": float(np.percentile(lat[ok], 50)) if ok.any() else None,
            "latency_p99_success_s": float(np.percentile(lat[ok], 99)) if ok.any() else None,
-           "success_rate": float(ok.mean()), "mean_steps_used": float(np.mean([x["steps_used"] for x in res])),
-           "roofline": None, "cpu_baseline": None}
+           "success_rate": float(ok.mean()),
+           "success_rate_by_variant": [float(ok[[k for k in range(len(reqs)) if reqs[k]["frac_bits"] == f]].mean())
+                                       for _, f in SERVE_VARIANTS],
+           "mean_steps_used": float(np.mean([x["steps_used"] for x in res])),
+           "roofline": {"bound": "alu", "achieved": achieved, "peak": VALU_OPS_PEAK, "unit": "ops/s",
+                        "frac": achieved / VALU_OPS_PEAK, "traffic": None,
+                        "kernel": "whole server (batched small, column-split and VALU sweeps)",
+                        "ops_per_spin_update": OPS_PER_SPIN_UPDATE,
+                        "note": "spin-updates of all requests x 33 over the wall-clock span from the first arrival "
+                                "to the last completion (idle gaps between arrivals included)"},
+           "cpu_baseline": cpu}
     print(json.dumps(out), flush=True)
 
 
@@ -554,7 +590,8 @@ def main():
                     help="recompute J.s in full every step (default: flip-incremental update where the sweep has it)")
     ap.add_argument("--tts-instances", type=int, default=10, help="tts_sweep: instances per (family, N)")
     ap.add_argument("--tts-sizes", default=None, help="tts_sweep: comma-separated sizes (default: the workload's)")
-    ap.add_argument("--requests", type=int, default=60, help="serving workload: number of requests")
+    ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serving workload: device memory budget")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
     ap.add_argument("--chunk", type=int, default=250, help="serving workload: steps per scheduling round")
     args = ap.parse_args()

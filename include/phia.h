@@ -68,6 +68,10 @@ typedef struct {
     int32_t path;       /* phia_path                                                     */
     int32_t device;     /* HIP device ordinal                                            */
     void* stream;       /* hipStream_t for all work of this problem; NULL = null stream  */
+    int32_t defer_upload; /* 0: J and h go to the device in phia_create; 1: they stay in
+                           host memory until the first anneal (or batch plan) needs
+                           them, and a served request that ends releases them again,
+                           so queued requests hold no device memory                 */
 } phia_options;
 
 /* Annealing schedule.  The inverse temperature of step k is betas[k] when

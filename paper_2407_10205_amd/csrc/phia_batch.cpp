@@ -316,7 +316,7 @@ namespace {
 // couplings, N <= 512, no accept/reject step, row energies within int32.
 bool fp4_batchable(const phia_problem* p)
 {
-    return p->path == PHIA_PATH_I8 && p->dJ4 && p->Np <= kBatchFp4MaxNp && !p->mh &&
+    return p->path == PHIA_PATH_I8 && p->has_j4 && p->Np <= kBatchFp4MaxNp && !p->mh &&
            2 * p->maxrow * static_cast<int64_t>(p->N) < (int64_t(1) << 31);
 }
 
@@ -413,7 +413,8 @@ phia_status phia_batch_create(phia_problem* const* probs, int32_t count, const i
         phia_problem* p = probs[i];
         kick_factors(p, steps[i], &scheds[i], ctabs[i]);
         bool reuse = false;
-        phia_status st_ = setup_state(p, replicas[i], steps[i], &scheds[i], 0, ctabs[i], reuse, false);
+        phia_status st_ = make_resident(p);
+        if (st_ == PHIA_OK) st_ = setup_state(p, replicas[i], steps[i], &scheds[i], 0, ctabs[i], reuse, false);
         if (st_ != PHIA_OK) return bail(st_);
         p->batch = b;
         p->geo = Geometry{};

@@ -86,6 +86,7 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
     if ((st = check_schedule(replicas, steps, s)) != PHIA_OK) return st;
     if (s->metropolis) return fail(PHIA_EINVAL, "phia_anneal_noalloc runs without the accept/reject step");
     if (!x || !v || !bestE || !bestS || !bestStep) return fail(PHIA_EINVAL, "state and record buffers are required");
+    if (!p->dJ) return fail(PHIA_ESTATE, "the couplings are not resident (a deferred upload happens at an anneal)");
     hipError_t e = hipSetDevice(p->dev);
     if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
     unsigned char* base = nullptr;

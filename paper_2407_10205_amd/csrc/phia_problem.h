@@ -43,6 +43,8 @@ phia_status setup_state(::phia_problem* p, int32_t replicas, int64_t steps, cons
                         const std::vector<float>& ctab, bool& reuse, bool sync_first);
 void free_state(::phia_problem* p);
 hipError_t clear_exchange(::phia_problem* p);
+phia_status make_resident(::phia_problem* p);
+void release_resident(::phia_problem* p);
 int valu_crossover(int Np);
 phia_status setup_mh_geometry(::phia_problem* p);
 SweepArgs sweep_args(const ::phia_problem* p);
@@ -78,6 +80,14 @@ struct phia_problem {
     int32_t* derr = nullptr;
     int64_t* dscratch = nullptr;
     size_t base_bytes = 0;
+    // packed couplings and fields on the host (dropped once resident unless
+    // the upload is deferred), FP64 copies only for rounded input
+    std::vector<unsigned char> hJ, hJ4;
+    std::vector<int32_t> hh;
+    std::vector<double> hJ64, hh64;
+    bool has_j4 = false;    // the couplings have an FP4 operand copy
+    bool defer = false;     // uploaded at first use, released when a served request ends
+    size_t jres_bytes = 0;  // device bytes of those copies when resident
     // anneal
     bool started = false, has_run = false, trace = false;
     bool one_block_kernel = false;  // restrict geometries to k_sweep_mfma (server table launches)

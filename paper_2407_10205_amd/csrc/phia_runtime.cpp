@@ -373,7 +373,7 @@ static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g
     if (p->path != PHIA_PATH_I8 || p->trace || p->one_block_kernel || p->mh || G < 2 || G > ncb ||
         ncb > kPpMaxNcb)
         return false;
-    if (fp4 && !p->dJ4) return false;
+    if (fp4 && !p->has_j4) return false;
     if (p->maxrow >= kPpMaxRowSum || 2 * p->maxrow * p->N >= (int64_t(1) << 31)) return false;
     if ((ncb + G - 1) / G > kWaves) return false;
     const size_t lds = sweep_pp_lds_bytes(Np, G, fp4);
@@ -608,6 +608,56 @@ void free_state(phia_problem* p)
     p->k = 0;
 }
 
+// Device copies of the couplings and fields (uploaded synchronously from the
+// host copies), if they are not resident yet.
+phia_status make_resident(phia_problem* p)
+{
+    if (p->dJ) return PHIA_OK;
+    if (p->hJ.empty()) return fail(PHIA_ESTATE, "the couplings are neither resident nor kept on the host");
+    hipError_t e = hipSetDevice(p->dev);
+    if (e != hipSuccess) return hip_fail(p, e, "hipSetDevice");
+    size_t* cnt = &p->base_bytes;
+    if ((e = dalloc(reinterpret_cast<void**>(&p->dJ), p->hJ.size(), cnt)) != hipSuccess ||
+        (e = dalloc(reinterpret_cast<void**>(&p->dh), sizeof(int32_t) * p->hh.size(), cnt)) != hipSuccess ||
+        (p->has_j4 && (e = dalloc(reinterpret_cast<void**>(&p->dJ4), p->hJ4.size(), cnt)) != hipSuccess) ||
+        (!p->hJ64.empty() &&
+         ((e = dalloc(reinterpret_cast<void**>(&p->dJ64), sizeof(double) * p->hJ64.size(), cnt)) != hipSuccess ||
+          (e = dalloc(reinterpret_cast<void**>(&p->dh64), sizeof(double) * p->hh64.size(), cnt)) != hipSuccess))) {
+        release_resident(p);
+        return fail(PHIA_ENOMEM, "device allocation of the couplings failed: %s", hipGetErrorString(e));
+    }
+    if ((e = hipMemcpy(p->dJ, p->hJ.data(), p->hJ.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(p->dh, p->hh.data(), sizeof(int32_t) * p->hh.size(), hipMemcpyHostToDevice)) != hipSuccess ||
+        (p->has_j4 && (e = hipMemcpy(p->dJ4, p->hJ4.data(), p->hJ4.size(), hipMemcpyHostToDevice)) != hipSuccess) ||
+        (p->dJ64 &&
+         ((e = hipMemcpy(p->dJ64, p->hJ64.data(), sizeof(double) * p->hJ64.size(), hipMemcpyHostToDevice)) !=
+              hipSuccess ||
+          (e = hipMemcpy(p->dh64, p->hh64.data(), sizeof(double) * p->hh64.size(), hipMemcpyHostToDevice)) !=
+              hipSuccess))) {
+        release_resident(p);
+        return fail(PHIA_EDEVICE, "upload of the couplings failed: %s", hipGetErrorString(e));
+    }
+    return PHIA_OK;
+}
+
+// Free the device copies of the couplings (deferred problems only: the host
+// copies stay, and the next use uploads them again).
+void release_resident(phia_problem* p)
+{
+    size_t freed = 0;
+    if (p->dJ) freed += p->hJ.size();
+    if (p->dh) freed += sizeof(int32_t) * p->hh.size();
+    if (p->dJ4) freed += p->hJ4.size();
+    if (p->dJ64) freed += sizeof(double) * p->hJ64.size();
+    if (p->dh64) freed += sizeof(double) * p->hh64.size();
+    dfree(p->dJ);
+    dfree(p->dJ4);
+    dfree(p->dh);
+    dfree(p->dJ64);
+    dfree(p->dh64);
+    p->base_bytes -= std::min(freed, p->base_bytes);
+}
+
 // Launch geometry that an anneal of R replicas without the accept/reject
 // step or energy traces would take (forced, tuned, cached or default), with
 // the problem's current anneal left as it is.
@@ -712,9 +762,10 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     *out = nullptr;
     if (!J) return fail(PHIA_EINVAL, "J is null");
     if (N < 1 || N > 16384) return fail(PHIA_EINVAL, "N = %d outside [1, 16384]", N);
-    phia_options o{-1, 0, PHIA_PATH_AUTO, 0, nullptr};
+    phia_options o{-1, 0, PHIA_PATH_AUTO, 0, nullptr, 0};
     if (opt) o = *opt;
     if (o.path < PHIA_PATH_AUTO || o.path > PHIA_PATH_ELL) return fail(PHIA_EINVAL, "unknown path %d", o.path);
+    if (o.defer_upload != 0 && o.defer_upload != 1) return fail(PHIA_EINVAL, "defer_upload = %d", o.defer_upload);
 
     std::vector<int32_t> Ji, hi;
     int f = 0;
@@ -832,33 +883,41 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
         jbytes = jb.size() * sizeof(uint16_t);
         jsrc = jb.data();
     }
+    // Packed couplings on the host until they are made resident; the FP64
+    // copies of J and h only for rounded input (exact instances take their
+    // FP64 energy from the integer one).
+    p->hJ.assign(static_cast<const unsigned char*>(jsrc), static_cast<const unsigned char*>(jsrc) + jbytes);
+    p->hJ4 = std::move(j4);
+    p->has_j4 = !p->hJ4.empty();
+    p->hh = std::move(hpad);
+    if (!exact) {
+        p->hJ64.assign(J, J + static_cast<size_t>(N) * N);
+        p->hh64.assign(static_cast<size_t>(N), 0.0);
+        if (h) std::copy(h, h + N, p->hh64.begin());
+    }
+    p->jres_bytes = p->hJ.size() + p->hJ4.size() + sizeof(int32_t) * p->hh.size() +
+                    sizeof(double) * (p->hJ64.size() + p->hh64.size());
+    p->defer = o.defer_upload != 0;
     size_t* cnt = &p->base_bytes;
-    if ((e = dalloc(reinterpret_cast<void**>(&p->dJ), jbytes, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dh), sizeof(int32_t) * Np, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dJ64), sizeof(double) * N * static_cast<size_t>(N), cnt)) !=
-            hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dh64), sizeof(double) * N, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->derr), sizeof(int32_t) * 4, cnt)) != hipSuccess ||
+    if ((e = dalloc(reinterpret_cast<void**>(&p->derr), sizeof(int32_t) * 4, cnt)) != hipSuccess ||
         (e = dalloc(reinterpret_cast<void**>(&p->dscratch), 64, cnt)) != hipSuccess ||
-        (e = dalloc(reinterpret_cast<void**>(&p->dincstat), 4 * sizeof(int64_t), cnt)) != hipSuccess ||
-        (!j4.empty() && (e = dalloc(reinterpret_cast<void**>(&p->dJ4), j4.size(), cnt)) != hipSuccess)) {
+        (e = dalloc(reinterpret_cast<void**>(&p->dincstat), 4 * sizeof(int64_t), cnt)) != hipSuccess) {
         phia_destroy(p);
         return fail(PHIA_ENOMEM, "device allocation failed: %s", hipGetErrorString(e));
     }
-    if (!j4.empty() && (e = hipMemcpy(p->dJ4, j4.data(), j4.size(), hipMemcpyHostToDevice)) != hipSuccess) {
+    if ((e = hipMemset(p->derr, 0, sizeof(int32_t) * 4)) != hipSuccess) {
         phia_destroy(p);
-        return fail(PHIA_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+        return fail(PHIA_EDEVICE, "device set-up failed: %s", hipGetErrorString(e));
     }
-    std::vector<double> h64(static_cast<size_t>(N), 0.0);
-    if (h) std::copy(h, h + N, h64.begin());
-    if ((e = hipMemcpy(p->dJ, jsrc, jbytes, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->dh, hpad.data(), sizeof(int32_t) * Np, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemcpy(p->dJ64, J, sizeof(double) * N * static_cast<size_t>(N), hipMemcpyHostToDevice)) !=
-            hipSuccess ||
-        (e = hipMemcpy(p->dh64, h64.data(), sizeof(double) * N, hipMemcpyHostToDevice)) != hipSuccess ||
-        (e = hipMemset(p->derr, 0, sizeof(int32_t) * 4)) != hipSuccess) {
-        phia_destroy(p);
-        return fail(PHIA_EDEVICE, "upload failed: %s", hipGetErrorString(e));
+    if (!p->defer) {
+        if ((st = make_resident(p)) != PHIA_OK) {
+            phia_destroy(p);
+            return st;
+        }
+        // the host copies are not needed again
+        std::vector<unsigned char>().swap(p->hJ);
+        std::vector<unsigned char>().swap(p->hJ4);
+        std::vector<double>().swap(p->hJ64);
     }
     *out = p;
     return PHIA_OK;
@@ -1050,6 +1109,7 @@ phia_status phia_anneal_start(phia_problem* p, int32_t replicas, int64_t steps, 
     phia_status st = check_owned(p);
     if (st != PHIA_OK) return st;
     if ((st = check_schedule(replicas, steps, s)) != PHIA_OK) return st;
+    if ((st = make_resident(p)) != PHIA_OK) return st;
     std::vector<float> ctab;
     kick_factors(p, steps, s, ctab);
     bool reuse = false;
@@ -1245,6 +1305,12 @@ phia_status phia_best_f64(phia_problem* p, double* energy)
     int32_t f, r;
     phia_status st = phia_best_exact(p, &E, &f, &r);
     if (st != PHIA_OK) return st;
+    if (p->exact) {
+        // couplings and fields are exactly J_int 2^-f: the energy is too
+        *energy = std::ldexp(static_cast<double>(E), -f);
+        return PHIA_OK;
+    }
+    if ((st = make_resident(p)) != PHIA_OK) return st;
     double* dout = reinterpret_cast<double*>(p->dscratch) + 4;
     hipError_t e = launch_energy_f64(p->dJ64, p->dh64, p->N, p->dbestS + static_cast<size_t>(r) * p->Np, dout, p->st);
     if (e != hipSuccess) return hip_fail(p, e, "FP64 energy launch");

@@ -91,7 +91,8 @@ namespace {
 size_t footprint(const phia_problem* p, int32_t R, int64_t T, bool mh = false)
 {
     const size_t RN = static_cast<size_t>(R) * p->Np;
-    size_t b = p->base_bytes + RN * 9 + static_cast<size_t>(R) * 16 + static_cast<size_t>(T) * 4 +
+    // the couplings count whether or not they are resident yet
+    size_t b = p->jres_bytes + RN * 9 + static_cast<size_t>(R) * 16 + static_cast<size_t>(T) * 4 +
                2 * RN / 16 * 8 * 2 + 65536;
     // accept/reject: x snapshot, per-replica state, beta table, kinetic units per member
     if (mh) b += RN * 4 + static_cast<size_t>(R) * 32 + static_cast<size_t>(T) * 4 + RN / 16 * 8 * 2;
@@ -104,6 +105,7 @@ void finish(phia_server* s, Request* r, int32_t state)
     r->res.t_done = s->now();
     r->res.steps_used = r->p->k;
     if (r->started) free_state(r->p);
+    if (r->p->defer) release_resident(r->p);
     r->p->st = r->saved_stream;
     r->p->one_block_kernel = false;
     r->p->started = false;

@@ -46,7 +46,7 @@ class PhiaError(RuntimeError):
 
 class Options(C.Structure):
     _fields_ = [("frac_bits", C.c_int32), ("quantize", C.c_int32), ("path", C.c_int32),
-                ("device", C.c_int32), ("stream", C.c_void_p)]
+                ("device", C.c_int32), ("stream", C.c_void_p), ("defer_upload", C.c_int32)]
 
 
 class Schedule(C.Structure):
@@ -187,14 +187,15 @@ def make_schedule(steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh
 class Problem:
     """One Ising instance on the device (phia_problem)."""
 
-    def __init__(self, J, h=None, frac_bits=-1, quantize=False, path="auto", device=0, stream=None):
+    def __init__(self, J, h=None, frac_bits=-1, quantize=False, path="auto", device=0, stream=None,
+                 defer_upload=False):
         J = np.ascontiguousarray(J, dtype=np.float64)
         if J.ndim != 2 or J.shape[0] != J.shape[1]:
             raise ValueError("J must be square")
         self.N = J.shape[0]
         hh = None if h is None else np.ascontiguousarray(h, dtype=np.float64)
         o = Options(frac_bits, 1 if quantize else 0, PATHS[path] if isinstance(path, str) else int(path),
-                    device, C.c_void_p(stream) if stream else None)
+                    device, C.c_void_p(stream) if stream else None, 1 if defer_upload else 0)
         p = C.c_void_p()
         _check(lib().phia_create(_ptr(J), _ptr(hh), self.N, C.byref(o), C.byref(p)))
         self._p = p
