@@ -292,14 +292,17 @@ phia_status phia_incremental_stats(phia_problem* p, int64_t* out);
  * phia_anneal_start or when the geometry has no exchange (group 1);
  * PHIA_EINVAL when seq is out of range.
  *
- * phia_set_wait_limit sets how many times a kernel polls one exchange word
- * before it gives up (default 2^21).  A wait that gives up raises the
- * device error word, every workgroup leaves the sweep at its next check,
- * and phia_sync then returns PHIA_EDEVICE and poisons the handle.  A small
- * limit lets a test take that path from the host without a real fault.
- * Takes effect at the next launch. */
+ * A kernel polls one exchange word at most 2^21 times before it gives up;
+ * every 256th poll it also gives up if the device error word is raised.  A
+ * wait that gives up raises the word, every workgroup leaves the sweep at
+ * its next check, and phia_sync then returns PHIA_EDEVICE and poisons the
+ * handle.  phia_raise_error_word(p, 1) raises the word before every
+ * following launch, as if a workgroup had given up, so that a test takes
+ * that path from the host without a real fault (a launch whose waits are
+ * all short still completes its steps; the handle is poisoned either way);
+ * 0 turns it off. */
 phia_status phia_set_exchange_seq(phia_problem* p, uint32_t seq);
-phia_status phia_set_wait_limit(phia_problem* p, uint32_t polls);
+phia_status phia_raise_error_word(phia_problem* p, int32_t on);
 
 /* Autotuner of the launch geometry of the matrix-core sweep (replicas per
  * workgroup block, workgroups sharing one block's columns, coupling slice in

@@ -54,7 +54,6 @@ struct SweepArgs {
     uint64_t* pbuf;             // [2][ngroups][G][rows][2] (seq << 32) | 32-bit half of a partial energy
     uint32_t seq_base;          // sequence number before this launch (tags start at seq_base + 1)
     int32_t* err;               // device error word (1 = barrier timeout)
-    uint32_t spin_limit;        // polls of one exchange word before a wait gives up
     // accept/reject at the end of every trajectory of L steps (mh != 0)
     int32_t mh;
     float mh_up, mh_down;       // beta multiplier factors after an acceptance / a rejection

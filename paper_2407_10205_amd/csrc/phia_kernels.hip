@@ -135,18 +135,17 @@ __host__ __device__ inline LdsPlan lds_plan(int path, int mt, int Np, int cbs_ma
 }
 
 // Poll a tagged exchange word until its upper 32 bits equal seq.  Gives up
-// after `limit` polls (or when another workgroup has already given up),
+// after kSpinLimit polls (or when another workgroup has already given up),
 // raising the device error word and the workgroup's abort flag; the caller
 // then leaves the sweep, so every wave of the grid terminates.
-__device__ __forceinline__ uint64_t await_tag(const uint64_t* p, uint32_t seq, int32_t* err, int* abort_flag,
-                                              uint32_t limit)
+__device__ __forceinline__ uint64_t await_tag(const uint64_t* p, uint32_t seq, int32_t* err, int* abort_flag)
 {
     uint32_t polls = 0;
     for (;;) {
         const uint64_t w = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (static_cast<uint32_t>(w >> 32) == seq) return w;
         ++polls;
-        if (polls > limit ||
+        if (polls > kSpinLimit ||
             ((polls & 255u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             *abort_flag = 1;
@@ -640,7 +639,7 @@ k_sweep_mfma(SweepArgs args)
 #pragma unroll
                                 for (int u = 0; u < 4; ++u)
                                     if (static_cast<uint32_t>(w[u] >> 32) != mseq)
-                                        w[u] = await_tag(src + u, mseq, a.err, sAbort, a.spin_limit);
+                                        w[u] = await_tag(src + u, mseq, a.err, sAbort);
                                 const uint64_t e = (w[0] & 0xffffffffu) | ((w[1] & 0xffffffffu) << 32);
                                 const uint64_t d = (w[2] & 0xffffffffu) | ((w[3] & 0xffffffffu) << 32);
                                 atomicAdd(reinterpret_cast<unsigned long long*>(mTE + q % RB),
@@ -877,7 +876,7 @@ k_sweep_mfma(SweepArgs args)
                         const int q = base + u * kThreads + tid;
                         if (q >= nw) continue;
                         uint64_t w = wv[u];
-                        if (static_cast<uint32_t>(w >> 32) != seq) w = await_tag(X + q, seq, a.err, sAbort, a.spin_limit);
+                        if (static_cast<uint32_t>(w >> 32) != seq) w = await_tag(X + q, seq, a.err, sAbort);
                         const int row = q / a.ncb, cb = q - row * a.ncb;
                         unpack_signs<ESZ>(static_cast<uint32_t>(w) & 0xffffu, S + row * srow + cb * 16 * ESZ);
                         if (INC && q < a.ncb) chg_cb = ((w >> 16) & 1u) != 0;
@@ -895,8 +894,8 @@ k_sweep_mfma(SweepArgs args)
                         const uint64_t* src = Pb + static_cast<size_t>(q) * 2;
                         uint64_t lo = __hip_atomic_load(src, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                         uint64_t hi = __hip_atomic_load(src + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        if (static_cast<uint32_t>(lo >> 32) != seq) lo = await_tag(src, seq, a.err, sAbort, a.spin_limit);
-                        if (static_cast<uint32_t>(hi >> 32) != seq) hi = await_tag(src + 1, seq, a.err, sAbort, a.spin_limit);
+                        if (static_cast<uint32_t>(lo >> 32) != seq) lo = await_tag(src, seq, a.err, sAbort);
+                        if (static_cast<uint32_t>(hi >> 32) != seq) hi = await_tag(src + 1, seq, a.err, sAbort);
                         const uint64_t e = (lo & 0xffffffffu) | ((hi & 0xffffffffu) << 32);
                         atomicAdd(reinterpret_cast<unsigned long long*>(sE + par * RB + (q % RB)),
                                   static_cast<unsigned long long>(e));
@@ -1230,18 +1229,18 @@ __device__ __forceinline__ uint32_t pp_stale(uint32_t tag, const uint64_t (&w)[N
 }
 
 // Re-read the words that still carry an older tag until all are current.
-// The loop is uniform over the wave.  Returns false after `limit` polls
+// The loop is uniform over the wave.  Returns false after kSpinLimit polls
 // or once another workgroup has raised the device error word (then this
 // one raises it too).
 template <int NU>
 __device__ __forceinline__ bool pp_complete(const uint64_t* Xs, const int (&off)[NU], uint32_t tag, uint64_t (&w)[NU],
-                                            int32_t* err, uint32_t limit)
+                                            int32_t* err)
 {
     uint32_t stale = pp_stale<NU>(tag, w);
     uint32_t polls = 0;
     while (__any(stale != 0)) {
         ++polls;
-        if (polls > limit ||
+        if (polls > kSpinLimit ||
             ((polls & 255u) == 0 && __hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)) {
             __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return false;
@@ -1507,7 +1506,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             if (q < nsteps) ck_next = a.ctab[a.k0 + q];
             const uint64_t* X = xs(seq);
             pp_issue<NU>(X, goff, w);
-            const bool ok = pp_complete<NU>(X, goff, seq & 0xffffffu, w, a.err, a.spin_limit);
+            const bool ok = pp_complete<NU>(X, goff, seq & 0xffffffu, w, a.err);
             int psum = 0;
 #pragma unroll
             for (int u = 0; u < NU; ++u) {

@@ -121,7 +121,7 @@ struct phia_problem {
     uint64_t* dxbits = nullptr;
     uint64_t* dpbuf = nullptr;
     uint32_t seq = 0;
-    uint32_t spin_limit = phia::kSpinLimit;  // polls before a kernel's bounded wait gives up
+    bool give_up = false;  // test hook: the device error word is raised before every sweep launch
     int32_t best_r = -1;
     size_t state_bytes = 0;
     phia::Geometry geo;

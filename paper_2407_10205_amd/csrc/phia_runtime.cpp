@@ -715,7 +715,6 @@ SweepArgs sweep_args(const phia_problem* p)
     a.pbuf = p->dpbuf;
     a.seq_base = p->seq;
     a.err = p->derr;
-    a.spin_limit = p->spin_limit;
     a.mh = p->mh;
     a.mh_up = p->mh_up;
     a.mh_down = p->mh_down;
@@ -1197,6 +1196,10 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
     SweepArgs a = sweep_args(p);
     a.k0 = p->k;
     a.k1 = k_end;
+    // test hook: the error word raised before the launch, as if another
+    // workgroup had given up
+    if (p->give_up && (e = hipMemsetAsync(p->derr, 0x02, 1, p->st)) != hipSuccess)
+        return hip_fail(p, e, "error word");
     if (p->geo.kind == 4) {
         e = launch_sweep_valu(valu_form(p), p->geo.rows, p->geo.j_lds != 0, a, p->st);
     } else if (p->geo.kind >= 1) {
@@ -1584,12 +1587,12 @@ phia_status phia_set_exchange_seq(phia_problem* p, uint32_t seq)
     return PHIA_OK;
 }
 
-phia_status phia_set_wait_limit(phia_problem* p, uint32_t polls)
+phia_status phia_raise_error_word(phia_problem* p, int32_t on)
 {
     clear_error();
     phia_status st = check_usable(p);
     if (st != PHIA_OK) return st;
-    p->spin_limit = polls;
+    p->give_up = on != 0;
     return PHIA_OK;
 }
 

@@ -29,7 +29,7 @@ EXPORTS = ("phia_create", "phia_anneal", "phia_anneal_noalloc", "phia_anneal_sta
            "phia_sync",
            "phia_best", "phia_best_exact", "phia_best_f64", "phia_replica_best", "phia_replica_mh", "phia_get_state",
            "phia_set_state", "phia_get_info", "phia_set_incremental", "phia_incremental_stats",
-           "phia_set_exchange_seq", "phia_set_wait_limit", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
+           "phia_set_exchange_seq", "phia_raise_error_word", "phia_autotune", "phia_set_trace", "phia_get_trace", "phia_eval_fmath",
            "phia_batch_run", "phia_batch_create", "phia_batch_launch", "phia_batch_sync", "phia_batch_destroy",
            "phia_server_create", "phia_server_submit", "phia_server_footprint", "phia_server_poll",
            "phia_server_wait", "phia_server_spins", "phia_server_cancel", "phia_server_destroy",
@@ -99,7 +99,7 @@ def _declare(lib):
         "phia_set_incremental": [P, I32],
         "phia_incremental_stats": [P, P],
         "phia_set_exchange_seq": [P, C.c_uint32],
-        "phia_set_wait_limit": [P, C.c_uint32],
+        "phia_raise_error_word": [P, I32],
         "phia_get_trace": [P, P],
         "phia_eval_fmath": [I32, P, P, P, I64, I32],
         "phia_batch_run": [P, I32, P, P, P, P],
@@ -241,9 +241,9 @@ class Problem:
         """Test hook: sequence number of the next column-split launch."""
         _check(lib().phia_set_exchange_seq(self._p, int(seq)))
 
-    def set_wait_limit(self, polls):
-        """Test hook: polls of one exchange word before a kernel gives up."""
-        _check(lib().phia_set_wait_limit(self._p, int(polls)))
+    def raise_error_word(self, on=True):
+        """Test hook: raise the device error word before every following launch."""
+        _check(lib().phia_raise_error_word(self._p, 1 if on else 0))
 
     def start(self, replicas, steps, eps, gamma, beta0=None, beta1=None, betas=None, refresh_L=50, seed=0,
               deriv="tanh", mh=None, ikick=False):

@@ -110,18 +110,18 @@ def test_exchange_seq_hook_rejects_bad_use(P):
 
 @pytest.mark.parametrize("spec", ["pp,4", "1,8,0"])
 def test_wait_that_gives_up_poisons_the_handle(P, O, spec):
-    """A wait limit of zero polls makes the first exchange word that is not
-    yet current end the wait: the kernel raises the device error word, every
-    workgroup leaves the sweep, phia_sync reports PHIA_EDEVICE and every
+    """The device error word raised from the host before a launch, as if a
+    workgroup's bounded wait had given up: the kernels leave the sweep at
+    their next check (or finish), phia_sync reports PHIA_EDEVICE and every
     later call on the handle does too.  A fresh problem then runs normally."""
     J, h = inst.er_maxcut(400, 0.05, 2)
     R, T = 1024, 300
-    say("wait limit 0", spec)
+    say("error word raised", spec)
     with _Geometry(spec):
         p = P.Problem(J, h, path="i8")
         p.start(R, T, 0.2, 1.0, seed=3, **SCHED)
     assert p.info()["group"] > 1
-    p.set_wait_limit(0)
+    p.raise_error_word()
     p.run(T)
     with pytest.raises(P.PhiaError) as e:
         p.sync()
