@@ -313,11 +313,13 @@ void batch_forget(phia_batch* b, phia_problem* p)
 namespace {
 
 // Instances the persistent sweep takes: int8 path with FP4 operand
-// couplings, N <= 512, no accept/reject step, row energies within int32.
+// couplings, N <= 512, no accept/reject step, and every row energy sum (and
+// partial sum) below 2^24 in magnitude, so that the sweep's FP32 sums are
+// exact: |sum_i s_i (I_i + h_i)| <= N (maxrow + max |h|) <= 2 maxrow N.
 bool fp4_batchable(const phia_problem* p)
 {
     return p->path == PHIA_PATH_I8 && p->has_j4 && p->Np <= kBatchFp4MaxNp && !p->mh &&
-           2 * p->maxrow * static_cast<int64_t>(p->N) < (int64_t(1) << 31);
+           2 * p->maxrow * static_cast<int64_t>(p->N) < (int64_t(1) << 24);
 }
 
 void release(phia_batch* b)

@@ -17,8 +17,10 @@
 // (+1 = 0x38, -1 = 0xB8) in the k order of the FP4 fragments, and J.s runs
 // on v_mfma_scale_f32_16x16x128_f8f6f4 (FP8 spins x FP4 couplings, FP32
 // accumulation, scales 1): every product and partial sum is an integer
-// below 2^24, so the field is exact.  Row energies are summed by DPP within
-// a wave and by LDS atomics over the waves; the records of step k are taken
+// below 2^24, so the field is exact, and it stays in FP32 for the kick and
+// the energy terms (their sums are integers below 2^24 too: host-checked).
+// Row energies are summed by DPP within a wave and by LDS atomics over the
+// waves; the records of step k are taken
 // in step k + 1 after the step's only barrier.  x is drawn here when an item
 // starts a fresh anneal (no separate init kernel).
 #include <hip/hip_runtime.h>
@@ -77,7 +79,7 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
     constexpr uint32_t srow = NKB * 128u + 16u;
     constexpr uint32_t sb = kBatchRows * srow;
     const uint32_t jb = static_cast<uint32_t>(a.Np / 16) * NKB * 1024u;
-    int32_t* sE = reinterpret_cast<int32_t*>(lds);  // [3][32] row energy sums of steps k mod 3
+    float* sE = reinterpret_cast<float*>(lds);  // [3][32] row energy sums of steps k mod 3 (exact integers)
     unsigned char* sJ = lds + kFixedLds;
     unsigned char* sS = lds + kFixedLds + jb;       // [dbuf ? 2 : 1][32][srow] FP8 spins
     const int nsteps = static_cast<int>(a.k1 - a.k0);
@@ -93,13 +95,16 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
         const int Np = a.Np, N = a.N;
         const int64_t rb0 = static_cast<int64_t>(blk) * kBatchRows;
         const uint64_t seed = *a.seed;
-        int col[NCW], hreg[NCW];
+        int col[NCW];
+        float hf[NCW], h2f[NCW];
         bool creal[NCW];
 #pragma unroll
         for (int cw = 0; cw < NCW; ++cw) {
             col[cw] = (wave + kBW * cw) * 16 + lr;
             creal[cw] = col[cw] < N;
-            hreg[cw] = a.h[col[cw]];
+            const int hv = a.h[col[cw]];
+            hf[cw] = static_cast<float>(hv);
+            h2f[cw] = static_cast<float>(2 * hv);
         }
         // rows of this lane: rb0 + mt 16 + 4 lg + j; bit mt 4 + j set when < R
         uint32_t rmask = 0;
@@ -109,7 +114,8 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
             for (int j = 0; j < 4; ++j)
                 rmask |= (rb0 + mt * 16 + 4 * lg + j < a.R ? 1u : 0u) << (mt * 4 + j);
         float x[MT][NCW][4], v[MT][NCW][4];
-        int32_t bE[MT][4], bK[MT][4];
+        float bE[MT][4];    // record energy (+inf: none yet)
+        int32_t bK[MT][4];
         uint32_t bestbits = 0;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -118,11 +124,11 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
                 const bool ok = (rmask >> (mt * 4 + j)) & 1u;
                 const int64_t gr = rb0 + mt * 16 + 4 * lg + j;
                 if (a.init) {
-                    bE[mt][j] = INT32_MAX;
+                    bE[mt][j] = __builtin_inff();
                     bK[mt][j] = -1;
                 } else {
                     const int64_t b = ok ? a.bestE[gr] : INT64_MAX;
-                    bE[mt][j] = b > INT32_MAX ? INT32_MAX : static_cast<int32_t>(b);
+                    bE[mt][j] = b == INT64_MAX ? __builtin_inff() : static_cast<float>(b);
                     bK[mt][j] = ok ? static_cast<int32_t>(a.bestStep[gr]) : -1;
                 }
 #pragma unroll
@@ -217,11 +223,11 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
             if (s > 0) {
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
-                    const int4 t4 = *reinterpret_cast<const int4*>(sE + r3p * 32 + mt * 16 + 4 * lg);
-                    const int32_t tot[4] = {t4.x, t4.y, t4.z, t4.w};
+                    const float4 t4 = *reinterpret_cast<const float4*>(sE + r3p * 32 + mt * 16 + 4 * lg);
+                    const float tot[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const int32_t E = -(tot[j] >> 1);  // the sum is even
+                        const float E = -0.5f * tot[j];  // the sum is even: exact
                         const bool imp = E < bE[mt][j];
                         bE[mt][j] = imp ? E : bE[mt][j];
                         bK[mt][j] = imp ? static_cast<int32_t>(k - 1) : bK[mt][j];
@@ -233,7 +239,7 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
                 }
             }
             if (last) break;
-            if (wave == 0 && lane < 32) sE[r3n * 32 + lane] = 0;  // read two steps ago
+            if (wave == 0 && lane < 32) sE[r3n * 32 + lane] = 0.0f;  // read two steps ago
             const float ck = a.ctab[k];
 
             // J.s on matrix cores: FP8 spins x FP4 couplings over the k blocks.
@@ -273,13 +279,13 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
                     __builtin_amdgcn_sched_barrier(0);
                 }
             }
-            int I[MT][NCW][4];
+            float I[MT][NCW][4];  // field J s + h, an exact integer in FP32
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int cw = 0; cw < NCW; ++cw)
 #pragma unroll
-                    for (int j = 0; j < 4; ++j) I[mt][cw][j] = static_cast<int>(acc[mt][cw][j]) + hreg[cw];
+                    for (int j = 0; j < 4; ++j) I[mt][cw][j] = acc[mt][cw][j] + hf[cw];
 
             // Kick (mode branch outside the element loops).
             auto kick_all = [&](auto mode) {
@@ -289,8 +295,8 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
                     for (int cw = 0; cw < NCW; ++cw)
 #pragma unroll
                         for (int j = 0; j < 4; ++j)
-                            v[mt][cw][j] = kick_t<decltype(mode)::value>(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j],
-                                                                        ck, eps, gamma);
+                            v[mt][cw][j] = kick_tf<decltype(mode)::value>(x[mt][cw][j], v[mt][cw][j], I[mt][cw][j],
+                                                                         ck, eps, gamma);
             };
             if (a.deriv)
                 kick_all(std::integral_constant<int, 1>{});
@@ -299,22 +305,22 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
 
             // Row energy partials s (I + h) of step k (padded columns have
             // zero couplings and field, so I + h = 0 there).
-            int psum[MT][4];
+            float psum[MT][4];
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    int part = 0;
+                    float part = 0.0f;
 #pragma unroll
                     for (int cw = 0; cw < NCW; ++cw) {
-                        const int ih = I[mt][cw][j] + hreg[cw];
+                        const float ih = acc[mt][cw][j] + h2f[cw];
                         part += (x[mt][cw][j] >= 0.0f) ? ih : -ih;
                     }
-                    psum[mt][j] = row_sum16_dpp(part);
+                    psum[mt][j] = row_sum16_dpp_f(part);
                 }
             // lane lr < 8 of each row group adds row (lr >> 2) 16 + 4 lg + (lr & 3)
             if (lr < 4 * MT) {
-                int t = psum[0][0];
+                float t = psum[0][0];
 #pragma unroll
                 for (int u = 1; u < 4 * MT; ++u) t = lr == u ? psum[u >> 2][u & 3] : t;
                 atomicAdd(sE + r3 * 32 + (lr >> 2) * 16 + 4 * lg + (lr & 3), t);
@@ -337,7 +343,7 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
                     if (creal[cw]) a.bestS[idx] = ((bestbits >> ((mt * NCW + cw) * 4 + j)) & 1u) ? 1 : -1;
                 }
                 if (wave == 0 && lr == 0) {
-                    a.bestE[gr] = bE[mt][j] == INT32_MAX ? INT64_MAX : static_cast<int64_t>(bE[mt][j]);
+                    a.bestE[gr] = bE[mt][j] == __builtin_inff() ? INT64_MAX : static_cast<int64_t>(bE[mt][j]);
                     a.bestStep[gr] = bK[mt][j];
                 }
             }

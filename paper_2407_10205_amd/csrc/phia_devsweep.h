@@ -75,6 +75,41 @@ __device__ __forceinline__ float kick_t(float x, float v, int I, float ck, float
     return __builtin_fmaf(eps, g, v);
 }
 
+// The same kick with the field already in FP32 (If == (float)I exactly:
+// integer fields below 2^24 in magnitude).
+template <int DERIV>
+__device__ __forceinline__ float kick_tf(float x, float v, float If, float ck, float eps, float gamma)
+{
+    const float u = gamma * x;
+    const float d = DERIV ? dev_poly2(u) : dev_sech2(u);
+    const float p = ck * d;
+    const float g = __builtin_fmaf(p, If, -x);
+    return __builtin_fmaf(eps, g, v);
+}
+
+// row_sum16_dpp for FP32 values that are integers below 2^24 in magnitude
+// (every partial sum is then exact, so the order does not matter).
+__device__ __forceinline__ float dpp_f_b1(float a)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, a), 0xb1, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_f_4e(float a)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, a), 0x4e, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float dpp_f_141(float a)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, a), 0x141, 0xf, 0xf, false));
+}
+__device__ __forceinline__ float row_sum16_dpp_f(float v)
+{
+    v += dpp_f_b1(v);   // quad_perm [1,0,3,2]
+    v += dpp_f_4e(v);   // quad_perm [2,3,0,1]
+    v += dpp_f_141(v);  // row_half_mirror
+    v += __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x140, 0xf, 0xf, true));
+    return v;
+}
+
 __device__ __forceinline__ float kick(float x, float v, int I, float ck, float eps, float gamma, int deriv)
 {
     const float u = gamma * x;
