@@ -146,15 +146,34 @@ void oracle_sincos_2pi(float u, float* c, float* s)
  * sech^2 = (4t) y^2.  No division. */
 float oracle_sech2(float u)
 {
+    /* sech^2 u = 4t / (1 + t)^2 with t = e^{-2|u|}.  t4 = 4t comes from the
+     * exponential above with every Taylor coefficient times 4 (an exact
+     * power-of-two scaling of each Horner step) and the scale applied by
+     * ldexp; -2|u| is clamped at -80, so t4 stays a normal number and
+     * sech^2 u = sech^2 40 for |u| >= 40.  1/q, q = 1 + t in [1, 2]: the
+     * quadratic (32 q^2 - 144 q + 210)/99, whose relative error 1 - q y
+     * is T3(2q - 3)/99 (at most 1/99), then two Newton steps. */
     float a = fabsf(u);
-    float t = oracle_exp_nonpos(-(a + a));
-    float q = 1.0f + t;
-    float y = fmaf(-(8.0f / 17.0f), q, 24.0f / 17.0f);
-    for (int it = 0; it < 3; ++it) {
-        float e = fmaf(-q, y, 1.0f);
-        y = fmaf(y, e, y);
+    float y = fmaxf(-(a + a), -80.0f);
+    float kf = rintf(y * O_LOG2E);
+    float r = fmaf(-kf, O_LN2_HI, y);
+    r = fmaf(-kf, O_LN2_LO, r);
+    float p = 4.0f / 5040.0f;
+    p = fmaf(p, r, 4.0f / 720.0f);
+    p = fmaf(p, r, 4.0f / 120.0f);
+    p = fmaf(p, r, 4.0f / 24.0f);
+    p = fmaf(p, r, 4.0f / 6.0f);
+    p = fmaf(p, r, 2.0f);
+    p = fmaf(p, r, 4.0f);
+    p = fmaf(p, r, 4.0f);
+    float t4 = ldexpf(p, (int)kf);
+    float q = fmaf(t4, 0.25f, 1.0f);
+    float z = fmaf(fmaf(32.0f / 99.0f, q, -144.0f / 99.0f), q, 210.0f / 99.0f);
+    for (int it = 0; it < 2; ++it) {
+        float e = fmaf(-q, z, 1.0f);
+        z = fmaf(z, e, z);
     }
-    return (4.0f * t) * (y * y);
+    return t4 * (z * z);
 }
 
 /* POLY2 derivative mode: the FPGA replaces Eq. 8's sech^2 by a quadratic

@@ -95,7 +95,10 @@ def test_sech2_within_6ulp_and_even(O):
         assert got == float(O.sech2(-u))
     assert worst <= 6.0
     assert float(O.sech2(0.0)) == 1.0
-    assert float(O.sech2(41.0)) == 0.0
+    # -2|u| is clamped at -80: a constant tail of 4 e^-80 (1 + O(e^-80))
+    tail = float(O.sech2(40.0))
+    assert abs(tail - 4.0 * math.exp(-80.0)) <= 4 * ulp32(tail)
+    assert float(O.sech2(41.0)) == tail and float(O.sech2(-1e4)) == tail
 
 
 def test_gauss_is_standard_normal(O):
