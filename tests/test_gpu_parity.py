@@ -78,7 +78,8 @@ def test_fmath_bit_exact(P, O):
     got = P.eval_fmath(2, us)
     ref = np.array([O.sincos_2pi(u) for u in us], np.float32)
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
-    xs = np.concatenate([rs.normal(0, 3, 30000), [0.0, -0.0, 40.0, 41.0]]).astype(np.float32)
+    xs = np.concatenate([rs.normal(0, 3, 30000), [0.0, -0.0, 40.0, 41.0], np.linspace(-90, 90, 721),
+                         rs.normal(0, 0.01, 2000)]).astype(np.float32)
     got = P.eval_fmath(3, xs)
     ref = np.array([O.sech2(x) for x in xs], np.float32)
     assert np.array_equal(got.view(np.uint32), ref.view(np.uint32))
