@@ -33,10 +33,14 @@ VALU_OPS_PEAK = CUS * 64 * CLOCK_HZ          # 64 FP32/INT32 lanes per CU per cl
 INT8_MFMA_PEAK = 5.0e15                      # dense int8 ops/s
 BF16_MFMA_PEAK = 2.5e15
 FP4_MFMA_PEAK = 10.1e15
-# Arithmetic operations of one spin-update in the sweep specification (TANH
-# mode): drift 1, readout 1, field add 1, energy term 3, kick 27 (gamma x,
-# 2|u|, e^y 17, sech^2 assembly 3 with the division counted once, c*d,
-# int->float, two fma).  The 16-column MFMA output is exactly the field.
+# Arithmetic operations of one spin-update, the fixed yardstick of every
+# roofline fraction here (TANH mode): drift 1, readout 1, field add 1, energy
+# term 3, kick 27 (gamma x, 2|u|, e^y 17, sech^2 assembly 3 with the
+# reciprocal counted once, c*d, int->float, two fma), as the sweep
+# specification was first written.  Later sequences compute the same
+# quantities with fewer instructions (the sech^2 now takes 24); the count is
+# kept so that fractions stay comparable.  The 16-column MFMA output is
+# exactly the field.
 OPS_PER_SPIN_UPDATE = 33
 # POLY2 mode: the kick is gamma x, u*u, one fma, max, c*d, int->float and two
 # fma (8 instead of 27).
