@@ -1198,7 +1198,7 @@ __host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, boo
     else
         p.s_off = nkb_regs > 0 ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
     p.s_bytes = 16u * (fp4 ? pp_srow_fp4(nkb_regs) : pp_srow(Np, nkb_regs));
-    p.e_off = p.s_off + 2u * p.s_bytes;  // [2][16] energy sums of the previous step
+    p.e_off = p.s_off + 2u * p.s_bytes;  // [2][16] energies of the previous step
     p.b_off = p.e_off + 2u * 16u * 8u;   // [2 sub-blocks][2 parities][16] best energies
     p.k_off = p.b_off + 4u * 16u * 8u;   // [2][16] step of the best energy
     p.misc_off = p.k_off + 2u * 16u * 8u;
@@ -1254,69 +1254,70 @@ __device__ __forceinline__ bool pp_complete(const uint64_t* Xs, const int (&off)
     return true;
 }
 
-// A wave that owns a column block stores the words of its 16 replica rows:
-// lane (lr, lg) with lr < 4 stores row 4 lg + lr (at dst), taking the spins
-// from ballot lr and the row's partial energy p_lr (each p_j is present in
-// every lane of its DPP row).
-__device__ __forceinline__ void pp_publish(uint64_t* dst, int lr, int lg, const float (&x)[4], int p0, int p1, int p2,
-                                           int p3, uint32_t tag)
-{
-    const uint64_t b0 = __ballot(x[0] >= 0.0f), b1 = __ballot(x[1] >= 0.0f);
-    const uint64_t b2 = __ballot(x[2] >= 0.0f), b3 = __ballot(x[3] >= 0.0f);
-    const bool odd = (lr & 1) != 0, high = (lr & 2) != 0;
-    const uint64_t b = high ? (odd ? b3 : b2) : (odd ? b1 : b0);
-    const int pe = high ? (odd ? p3 : p2) : (odd ? p1 : p0);
-    const uint64_t word = (static_cast<uint64_t>(tag) << 40) |
-                          (static_cast<uint64_t>(static_cast<uint32_t>(pe) & 0xffffffu) << 16) |
-                          ((b >> (16 * lg)) & 0xffffu);
-    if (lr < 4) __hip_atomic_store(dst, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// I = S . J^T + h for one 16x16 tile, J fragments in VGPRs.  The S
-// operands of kPpDepth k blocks are in flight ahead of the products; k blocks
-// at or past nkb read S padding against zero J fragments and add nothing.
+// The products below run transposed, D = J_slice . S^T: the J fragments are
+// the A operand and the spins the B operand (both MFMA operands take row
+// lane % 16 and k chunk lane / 16, so the same registers serve either
+// side).  Lane (lr, lg) then receives replica lr, columns 4 lg .. 4 lg + 3 of
+// the wave's column block: a lane holds one replica, which makes its
+// records, its partial energy and its share of the published spins local.
 constexpr int kPpDepth = 4;
 
+// J fragments in VGPRs.  The S operands of kPpDepth k blocks are in flight
+// ahead of the products; k blocks at or past the packed ones read S padding
+// against zero J fragments and add nothing.
 template <int NKB>
-__device__ __forceinline__ void quasi_gradient_regj(const unsigned char* S, uint32_t srow, const v4i (&jr)[NKB],
-                                                    int nkb, int lr, int lg, int h, int (&I)[4])
+__device__ __forceinline__ v4i quasi_gradient_regj(const unsigned char* S, uint32_t srow, const v4i (&jr)[NKB], int lr,
+                                                   int lg)
 {
-    (void)nkb;
     const unsigned char* row = S + lr * srow + 16 * lg;
-    v4i A[kPpDepth];
+    v4i B[kPpDepth];
 #pragma unroll
-    for (int d = 0; d < kPpDepth && d < NKB; ++d) A[d] = *reinterpret_cast<const v4i*>(row + d * 64);
+    for (int d = 0; d < kPpDepth && d < NKB; ++d) B[d] = *reinterpret_cast<const v4i*>(row + d * 64);
     v4i acc = v4i{0, 0, 0, 0};
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
-        const v4i cur = A[kb % kPpDepth];
-        if (kb + kPpDepth < NKB) A[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
-        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(cur, jr[kb], acc, 0, 0, 0);
+        const v4i cur = B[kb % kPpDepth];
+        if (kb + kPpDepth < NKB) B[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(jr[kb], cur, acc, 0, 0, 0);
     }
-#pragma unroll
-    for (int j = 0; j < 4; ++j) I[j] = acc[j] + h;
+    return acc;
 }
 
-// Expand one 16-bit sign word into 16 FP4 (E2M1) spins, +1.0 = 0x2 and
-// -1.0 = 0xA, 8 bytes: within each byte of spin bits the nibbles hold spins
-// 0 4 1 5 2 6 3 7 (the packed J uses the same order along k).
+// The wave's column block of J in LDS (fragment-major, nkb blocks of
+// 1 KiB), one k block in flight ahead of the product.
+__device__ __forceinline__ v4i quasi_gradient_ldsj(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
+                                                   int nkb, int lane, int lr, int lg)
+{
+    const unsigned char* row = S + lr * srow + 16 * lg;
+    const unsigned char* jl = Jw + lane * 16;
+    v4i sn = *reinterpret_cast<const v4i*>(row), jn = *reinterpret_cast<const v4i*>(jl);
+    v4i acc = v4i{0, 0, 0, 0};
+    for (int kb = 0; kb < nkb; ++kb) {
+        const v4i s = sn, j = jn;
+        if (kb + 1 < nkb) {
+            sn = *reinterpret_cast<const v4i*>(row + (kb + 1) * 64);
+            jn = *reinterpret_cast<const v4i*>(jl + (kb + 1) * 1024);
+        }
+        acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(j, s, acc, 0, 0, 0);
+    }
+    return acc;
+}
+
+// One byte of sign bits as 8 FP4 (E2M1) spins, +1.0 = 0x2 and -1.0 = 0xA:
+// the nibbles hold spins 0 4 1 5 2 6 3 7 (the packed J uses the same order
+// along k).  The 24-bit multiplies keep the expansion at full VALU rate (the
+// compiler would otherwise fold the nibble shift into a 32-bit multiply).
 __device__ __forceinline__ uint32_t fp4_byte(uint32_t b)
 {
-    const uint32_t lo = ((b & 0xfu) * 0x00204081u) & 0x01010101u;  // bit i -> bit 8 i
-    const uint32_t hi = ((b >> 4) * 0x00204081u) & 0x01010101u;
-    return 0xaaaaaaaau - 8u * (lo | (hi << 4));
-}
-
-__device__ __forceinline__ void unpack_signs_fp4(uint32_t w, unsigned char* dst)
-{
-    *reinterpret_cast<uint2*>(dst) = uint2{fp4_byte(w & 0xffu), fp4_byte((w >> 8) & 0xffu)};
+    const uint32_t lo = __umul24(b & 0xfu, 0x00204081u) & 0x01010101u;  // bit i -> bit 8 i
+    const uint32_t hi = __umul24(b >> 4, 0x00204081u) & 0x01010101u;
+    return 0xaaaaaaaau ^ ((lo | (hi << 4)) << 3);  // clears bit 3 of the nibbles of -1 spins
 }
 
 // S . J^T for one 16x16 tile with FP4 operands and FP32 accumulation
 // (v_mfma_scale_f32_16x16x128_f8f6f4, scales 1.0): every product and partial
 // sum is an integer below 2^24, so the result is exact.  Even and odd k
-// blocks go to two accumulators (two independent MFMA chains); the caller
-// converts the sum after other work, while the products run.
+// blocks go to two accumulators (two independent MFMA chains).
 // Jw: the wave's column block of the LDS J slice, NKB blocks of 1 KiB.
 template <int NKB>
 __device__ __forceinline__ v4f quasi_gradient_fp4(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
@@ -1327,16 +1328,16 @@ __device__ __forceinline__ v4f quasi_gradient_fp4(const unsigned char* S, uint32
     v4i A[kPpDepth], B[kPpDepth];
 #pragma unroll
     for (int d = 0; d < kPpDepth && d < NKB; ++d) {
-        A[d] = *reinterpret_cast<const v4i*>(row + d * 64);
-        B[d] = *reinterpret_cast<const v4i*>(jl + d * 1024);
+        A[d] = *reinterpret_cast<const v4i*>(jl + d * 1024);
+        B[d] = *reinterpret_cast<const v4i*>(row + d * 64);
     }
     v4f acc0 = v4f{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
         const v4i ca = A[kb % kPpDepth], cb = B[kb % kPpDepth];
         if (kb + kPpDepth < NKB) {
-            A[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
-            B[kb % kPpDepth] = *reinterpret_cast<const v4i*>(jl + (kb + kPpDepth) * 1024);
+            A[kb % kPpDepth] = *reinterpret_cast<const v4i*>(jl + (kb + kPpDepth) * 1024);
+            B[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
         }
         const v8i a8 = v8i{ca[0], ca[1], ca[2], ca[3], 0, 0, 0, 0};
         const v8i b8 = v8i{cb[0], cb[1], cb[2], cb[3], 0, 0, 0, 0};
@@ -1348,12 +1349,33 @@ __device__ __forceinline__ v4f quasi_gradient_fp4(const unsigned char* S, uint32
     return acc0 + acc1;
 }
 
+// Sum over the four lanes l, l ^ 16, l ^ 32, l ^ 48 (the lanes of one replica
+// in the transposed products), in each of them.  The gfx950 lane swaps
+// exchange rows 2i + 1 of the first operand with rows 2i of the second
+// (permlane16), then the upper half of the first with the lower half of the
+// second (permlane32); applied to two copies of v, the two outputs add up to
+// v[l] + v[partner] in every lane.  VALU only: no LDS round trip queued
+// behind the other waves' operand reads.  Written in assembly so that the
+// two copies stay two registers (the compiler may otherwise take one output
+// for the other); the nop covers the VALU-write-to-permlane-read hazard.
+// The whole wave must be active.
+__device__ __forceinline__ uint32_t replica_sum_u(uint32_t v)
+{
+    uint32_t a = v, b = v;
+    asm volatile("s_nop 1\n\tv_permlane16_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+    v = a + b;
+    a = v;
+    b = v;
+    asm volatile("s_nop 1\n\tv_permlane32_swap_b32 %0, %1" : "+v"(a), "+v"(b));
+    return a + b;
+}
+
 // Sixteen waves: team 0 (waves 0-7) owns sub-block 0, team 1 (waves 8-15)
 // sub-block 1; wave w of a team owns column block cb0 + w.  Each team
 // alternates between gathering its sub-block's spins (and the previous
-// step's partial energies) and computing one step of it; the teams are one
-// phase apart, so in every phase one team computes while the other waits
-// for the exchange, and a workgroup barrier closes each phase.
+// step's energies) and computing one step of it; the teams are one phase
+// apart, so in every phase one team computes while the other waits for the
+// exchange, and a workgroup barrier closes each phase.
 constexpr int kPpWaves = 16;
 constexpr int kPpThreads = 64 * kPpWaves;
 
@@ -1363,7 +1385,8 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     static_assert(!FP4 || NKB > 0, "FP4 operands need the unrolled k loop");
     constexpr bool JREG = NKB > 0 && !FP4;  // int8 J fragments in VGPRs
     extern __shared__ __align__(16) unsigned char lds[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: team and column block in SGPRs
     const int team = wave >> 3, tw = wave & 7, tt = tid & 511;
     const int lr = lane & 15, lg = lane >> 4;
     const int Np = a.Np, N = a.N, ncb = a.ncb, G = a.G;
@@ -1393,7 +1416,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
     const bool cval = tw < cbs;  // this wave owns a column block
     const int cblk = cb0 + tw;
-    const int col = cblk * 16 + lr;
+    const int col0 = cblk * 16 + 4 * lg;  // the lane's columns col0 .. col0 + 3 (of replica lr)
     // J of the wave's column block: VGPR fragments, or the member's slice in
     // LDS (FP4: NKB blocks per column block, zero past the packed ones).
     v4i jr[JREG ? NKB : 1];
@@ -1422,8 +1445,15 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     }
     if (tid == 0) *sAbort = 0;
 
-    const int hreg1[1] = {cval ? a.h[col] : 0};
-    const bool creal = cval && col < N;
+    // Fields of the lane's columns in FP32 (|h| < 2^18, exact), and which of
+    // them are real (col < N; padded columns have zero couplings and field).
+    float hf[4];
+    uint32_t creal = 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        hf[j] = cval ? static_cast<float>(a.h[col0 + j]) : 0.0f;
+        if (cval && col0 + j < N) creal |= 1u << j;
+    }
     const int grow = tt >> 5, gc0 = tt & 31;
     const float eps = a.eps, gamma = a.gamma;
     const int nsteps = static_cast<int>(a.k1 - a.k0);
@@ -1433,7 +1463,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     int goff[NU];  // gather: word indices of this thread
 #pragma unroll
     for (int u = 0; u < NU; ++u) goff[u] = grow * ncb + min(gc0 + 32 * u, ncb - 1);
-    const int poff = (4 * lg + (lr & 3)) * ncb + cblk;  // publication: word of row 4 lg + lr (lanes lr < 4)
+    const int poff = lr * ncb + cblk;  // publication: the word of replica row lr (lanes lg == 0)
     int iter = 0;
 
     for (int blk = group; blk < a.nblocks; blk += a.ngroups, ++iter) {
@@ -1452,15 +1482,22 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             sBall[(sb * 2 + 1) * 16 + r] = b32;
             sKall[q] = ok ? a.bestStep[rb0 + q] : -1;
         }
+        const int64_t gr = tb0 + lr;  // the lane's replica
+        const bool rok = cval && gr < a.R;
         float x[4], v[4];
         uint32_t bestbits = 0, pm = 0;
+        if (rok) {
+            const float4 xx = *reinterpret_cast<const float4*>(a.x + gr * Np + col0);
+            const float4 vv = *reinterpret_cast<const float4*>(a.v + gr * Np + col0);
+            const uint32_t bs = *reinterpret_cast<const uint32_t*>(a.bestS + gr * Np + col0);
+            x[0] = xx.x, x[1] = xx.y, x[2] = xx.z, x[3] = xx.w;
+            v[0] = vv.x, v[1] = vv.y, v[2] = vv.z, v[3] = vv.w;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t gr = tb0 + 4 * lg + j;
-            const bool ok = cval && gr < a.R;
-            x[j] = ok ? a.x[gr * Np + col] : 0.0f;
-            v[j] = ok ? a.v[gr * Np + col] : 0.0f;
-            if (ok && creal && a.bestS[gr * Np + col] > 0) bestbits |= 1u << j;
+            for (int j = 0; j < 4; ++j)
+                if (((creal >> j) & 1u) && static_cast<int8_t>((bs >> (8 * j)) & 0xffu) > 0) bestbits |= 1u << j;
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x[j] = v[j] = 0.0f;
         }
 
         const uint32_t seq0 = a.seq_base + static_cast<uint32_t>(iter) * seq_stride + 1u;
@@ -1468,26 +1505,15 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         uint64_t round = static_cast<uint64_t>(ref0 / a.L);
         uint64_t w[NU];
 
-        // Momentum refresh of the owned elements (draws of `round`).  The
-        // wave's 256 draws (16 replicas x 16 columns) fill 32 Philox blocks
-        // (replica, 8-column half of the column block): lanes 2b and 2b + 1
-        // both generate block b = 2 rr + half and transform two of its four
-        // pairs each, and every element reads its draw from the lane that
-        // made it: element (replica 4 lg + j, column lr) sits in lane
-        // 4 (4 lg + j) + 2 (lr >> 3) + ((lr >> 2) & 1), slot lr & 3.
+        // Momentum refresh of the lane's four elements (draws of `round`):
+        // columns 4 lg .. 4 lg + 3 of the column block are the half lg & 1 of
+        // the Philox block of (replica, 8-column group 2 cblk + (lg >> 1)),
+        // so every lane draws its own elements.
         auto refresh = [&]() {
             float g[4];
-            const int rr = lane >> 2, hb = (lane >> 1) & 1, hp = lane & 1;
-            gauss_block_half(a.seed, a.r_base + tb0 + rr, round, static_cast<uint64_t>(cblk) * 2 + hb, hp, g);
-            const int q = lr & 3;
+            gauss_block_half(a.seed, a.r_base + gr, round, static_cast<uint64_t>(cblk) * 2 + (lg >> 1), lg & 1, g);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int src = 4 * (4 * lg + j) + 2 * (lr >> 3) + ((lr >> 2) & 1);
-                const float t0 = lane_read(src, g[0]), t1 = lane_read(src, g[1]);
-                const float t2 = lane_read(src, g[2]), t3 = lane_read(src, g[3]);
-                const float t = q == 0 ? t0 : q == 1 ? t1 : q == 2 ? t2 : t3;
-                v[j] = (creal && tb0 + 4 * lg + j < a.R) ? t : 0.0f;
-            }
+            for (int j = 0; j < 4; ++j) v[j] = (((creal >> j) & 1u) && gr < a.R) ? g[j] : 0.0f;
         };
         auto signs4 = [&]() {
             uint32_t m = 0;
@@ -1496,10 +1522,19 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                 if (x[j] >= 0.0f) m |= 1u << j;
             return m;
         };
+        // Word of replica lr: the 16 spins of the column block gathered from
+        // the four lanes of the replica, and the partial energy qi.  Called
+        // with the whole wave active.
+        auto publish = [&](uint64_t* X, int qi, uint32_t tag) {
+            const uint32_t m = replica_sum_u(signs4() << (4 * lg));  // disjoint bits: the sum is the OR
+            const uint64_t word = (static_cast<uint64_t>(tag) << 40) |
+                                  (static_cast<uint64_t>(static_cast<uint32_t>(qi) & 0xffffffu) << 16) | m;
+            if (lg == 0) __hip_atomic_store(X + poff, word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        };
 
         // Publication q: spins of step k0 + q and partial energies of step
         // k0 + q - 1 of this team's sub-block; read into S (q < nsteps) and
-        // the row energy sums (q > 0).  Returns false when the wait gave up.
+        // the energies (q > 0).  Returns false when the wait gave up.
         float ck_next = 0.0f;  // c_k of the next compute phase, loaded with its gather
         auto gather = [&](int q) {
             const uint32_t seq = seq0 + static_cast<uint32_t>(q);
@@ -1512,88 +1547,84 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             for (int u = 0; u < NU; ++u) {
                 const int c = gc0 + 32 * u;
                 if (c < ncb) {
+                    const uint32_t lo = static_cast<uint32_t>(w[u]);
                     if (q < nsteps) {
                         if (FP4)
-                            unpack_signs_fp4(static_cast<uint32_t>(w[u]), S + grow * srow + c * 8);
+                            *reinterpret_cast<uint2*>(S + grow * srow + c * 8) =
+                                uint2{fp4_byte(lo & 0xffu), fp4_byte((lo >> 8) & 0xffu)};
                         else
-                            unpack_signs<1>(static_cast<uint32_t>(w[u]) & 0xffffu, S + grow * srow + c * 16);
+                            unpack_signs<1>(lo & 0xffffu, S + grow * srow + c * 16);
                     }
                     psum += static_cast<int32_t>(static_cast<uint32_t>(w[u] >> 16) << 8) >> 8;
                 }
             }
             if (q > 0) {
                 // Row total over the 32 lanes of the replica row: DPP row
-                // sums, then row r - 1 added into rows 1 and 3.
+                // sums, then row r - 1 added into rows 1 and 3.  The total
+                // is even (J symmetric, h counted twice); its negative half
+                // is the energy (Eq. 2).
                 int t = row_sum16_dpp(psum);
                 t += __builtin_amdgcn_update_dpp(0, t, 0x142, 0xa, 0xf, false);  // row_bcast:15
-                if (gc0 == 31) sEt[grow] = t;
+                if (gc0 == 31) sEt[grow] = -(t >> 1);
             }
             return ok;
         };
 
-        // Records of step k0 + s - 1, then (s < nsteps) step k0 + s and its
-        // publication s + 1.
+        // Step k0 + s and its publication s + 1 (s < nsteps), then the
+        // records of step k0 + s - 1.
         auto compute = [&](int s) {
             const int64_t k = a.k0 + s;
             const bool closing = (s == nsteps);
             const float ck = ck_next;
-            int I[1][1][4] = {};
             v4f facc = v4f{0.0f, 0.0f, 0.0f, 0.0f};
+            v4i iacc = v4i{0, 0, 0, 0};
             if (!closing && cval) {
                 if (FP4)
                     facc = quasi_gradient_fp4<(NKB > 0 ? NKB : 1)>(S, srow, sJ + static_cast<size_t>(tw) * NKB * 1024u,
                                                                  lane, lr, lg);
                 else if (JREG)
-                    quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, nkb, lr, lg, hreg1[0], I[0][0]);
+                    iacc = quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, lr, lg);
                 else
-                    quasi_gradient<kPathI8, 1, 1, 1>(S, srow, sJ + static_cast<size_t>(tw) * cbb, 0, Np, lane, lr,
-                                                     lg, hreg1, I);
+                    iacc = quasi_gradient_ldsj(S, srow, sJ + static_cast<size_t>(tw) * cbb, nkb, lane, lr, lg);
             }
-            if (s > 0) {  // App. B, Table 3, state 5
-                const int par = static_cast<int>(k & 1);
-                const int32_t* prev = sB + (par ^ 1) * 16;
-                int32_t* next = sB + par * 16;
-                int32_t Ev[4], Bv[4];
-#pragma unroll
-                for (int j = 0; j < 4; ++j) {  // all reads before any write
-                    Ev[j] = -(sEt[4 * lg + j] >> 1);  // the sum is even (J symmetric, h counted twice)
-                    Bv[j] = prev[4 * lg + j];
-                }
-                uint32_t impm = 0;
-#pragma unroll
-                for (int j = 0; j < 4; ++j)
-                    if (Ev[j] < Bv[j]) impm |= 1u << j;
-                bestbits = (bestbits & ~impm) | (pm & impm);
-                if (tw == 0 && lr == 0) {
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) {
-                        const bool imp = (impm >> j) & 1u;
-                        next[4 * lg + j] = imp ? Ev[j] : Bv[j];
-                        if (imp) sK[4 * lg + j] = k - 1;
+            // The records of step k - 1 wait until after the publication:
+            // the next gather of every member waits on the words, nothing
+            // waits on the records within the phase.
+            const uint32_t pm_prev = pm;
+            auto records = [&]() {
+                if (s > 0) {  // App. B, Table 3, state 5: the records of replica lr
+                    const int par = static_cast<int>(k & 1);
+                    const int32_t Ev = sEt[lr], Bv = sB[(par ^ 1) * 16 + lr];
+                    const bool imp = Ev < Bv;
+                    if (imp) bestbits = pm_prev;
+                    if (tw == 0 && lg == 0) {
+                        sB[par * 16 + lr] = imp ? Ev : Bv;
+                        if (imp) sK[lr] = k - 1;
                     }
                 }
+            };
+            if (closing || !cval) {
+                records();
+                return;
             }
-            if (FP4 && !closing && cval) {
-#pragma unroll
-                for (int j = 0; j < 4; ++j) I[0][0][j] = static_cast<int>(facc[j]) + hreg1[0];
-            }
-            if (closing || !cval) return;
-            int part[4];
+            // I = J s + h and s (I + h) in FP32: integers below 2^24 (host
+            // check), so every sum is exact.
+            float If[4], q = 0.0f;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
-                // padded columns (col >= N) have zero couplings and field: I + h = 0
-                const int ih = I[0][0][j] + hreg1[0];
-                part[j] = (x[j] >= 0.0f) ? ih : -ih;
+                const float f = FP4 ? facc[j] : static_cast<float>(iacc[j]);
+                If[j] = f + hf[j];
+                const float e = If[j] + hf[j];
+                q += (x[j] >= 0.0f) ? e : -e;
             }
+            const int qi = static_cast<int>(replica_sum_u(static_cast<uint32_t>(static_cast<int>(q))));
             if (a.deriv) {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) v[j] = kick_t<1>(x[j], v[j], I[0][0][j], ck, eps, gamma);
+                for (int j = 0; j < 4; ++j) v[j] = kick_tf<1>(x[j], v[j], If[j], ck, eps, gamma);
             } else {
 #pragma unroll
-                for (int j = 0; j < 4; ++j) v[j] = kick_t<0>(x[j], v[j], I[0][0][j], ck, eps, gamma);
+                for (int j = 0; j < 4; ++j) v[j] = kick_tf<0>(x[j], v[j], If[j], ck, eps, gamma);
             }
-            const int p0 = row_sum16_dpp(part[0]), p1 = row_sum16_dpp(part[1]);
-            const int p2 = row_sum16_dpp(part[2]), p3 = row_sum16_dpp(part[3]);
             pm = signs4();
             if (s + 1 < nsteps) {
                 if (k + 1 == next_ref) refresh();
@@ -1601,7 +1632,8 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                 for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(eps, v[j], x[j]);
             }
             const uint32_t seq = seq0 + static_cast<uint32_t>(s) + 1u;
-            pp_publish(xs(seq) + poff, lr, lg, x, p0, p1, p2, p3, seq & 0xffffffu);
+            publish(xs(seq), qi, seq & 0xffffffu);
+            records();
         };
 
         // Publication 0: the drift of step k0.
@@ -1614,7 +1646,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             }
 #pragma unroll
             for (int j = 0; j < 4; ++j) x[j] = __builtin_fmaf(eps, v[j], x[j]);
-            if (cval) pp_publish(xs(seq0) + poff, lr, lg, x, 0, 0, 0, 0, seq0 & 0xffffffu);
+            if (cval) publish(xs(seq0), 0, seq0 & 0xffffffu);
         }
         __syncthreads();  // records initialised
         if (team == 0 && !gather(0)) *sAbort = 1;
@@ -1645,13 +1677,12 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         }
         if (aborted) return;
 
+        if (rok) {
+            *reinterpret_cast<float4*>(a.x + gr * Np + col0) = float4{x[0], x[1], x[2], x[3]};
+            *reinterpret_cast<float4*>(a.v + gr * Np + col0) = float4{v[0], v[1], v[2], v[3]};
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int64_t gr = tb0 + 4 * lg + j;
-            if (!cval || gr >= a.R) continue;
-            a.x[gr * Np + col] = x[j];
-            a.v[gr * Np + col] = v[j];
-            if (creal) a.bestS[gr * Np + col] = ((bestbits >> j) & 1u) ? 1 : -1;
+            for (int j = 0; j < 4; ++j)
+                if ((creal >> j) & 1u) a.bestS[gr * Np + col0 + j] = ((bestbits >> j) & 1u) ? 1 : -1;
         }
         __syncthreads();
         if (member == 0) {
