@@ -1187,16 +1187,14 @@ __host__ __device__ inline uint32_t pp_srow(int Np, int nkb_regs)
 __host__ __device__ inline uint32_t pp_srow_fp4(int nkb_regs) { return 64u * nkb_regs + 16u; }
 
 // LDS of the interleaved sweep.  int8 operands: J slice in LDS unless
-// nkb_regs > 0 (VGPR fragments).  FP4 operands: J slice always in LDS,
-// nkb_regs blocks of 1 KiB per column block (zero past the packed ones).
+// nkb_regs > 0 (VGPR fragments).  FP4 operands: J always in VGPRs (nkb_regs
+// fragments per wave, zero past the packed ones), so LDS holds the spins
+// and the records only.
 __host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, bool fp4 = false)
 {
     PpPlan p;
     p.j_off = 0;
-    if (fp4)
-        p.s_off = static_cast<uint32_t>(cbs_max) * static_cast<uint32_t>(nkb_regs) * 1024u;
-    else
-        p.s_off = nkb_regs > 0 ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
+    p.s_off = (fp4 || nkb_regs > 0) ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
     p.s_bytes = 16u * (fp4 ? pp_srow_fp4(nkb_regs) : pp_srow(Np, nkb_regs));
     p.e_off = p.s_off + 2u * p.s_bytes;  // [2][16] energies of the previous step
     p.b_off = p.e_off + 2u * 16u * 8u;   // [2 sub-blocks][2 parities][16] best energies
@@ -1314,31 +1312,25 @@ __device__ __forceinline__ uint32_t fp4_byte(uint32_t b)
     return 0xaaaaaaaau ^ ((lo | (hi << 4)) << 3);  // clears bit 3 of the nibbles of -1 spins
 }
 
-// S . J^T for one 16x16 tile with FP4 operands and FP32 accumulation
+// The product with FP4 operands and FP32 accumulation
 // (v_mfma_scale_f32_16x16x128_f8f6f4, scales 1.0): every product and partial
-// sum is an integer below 2^24, so the result is exact.  Even and odd k
-// blocks go to two accumulators (two independent MFMA chains).
-// Jw: the wave's column block of the LDS J slice, NKB blocks of 1 KiB.
+// sum is an integer below 2^24, so the result is exact.  J fragments in
+// VGPRs (NKB blocks of 128 k positions; zero past the packed ones), the S
+// operands of kPpDepth k blocks in flight ahead of the products; even and
+// odd k blocks go to two accumulators (two independent MFMA chains).
 template <int NKB>
-__device__ __forceinline__ v4f quasi_gradient_fp4(const unsigned char* S, uint32_t srow, const unsigned char* Jw,
-                                                  int lane, int lr, int lg)
+__device__ __forceinline__ v4f quasi_gradient_fp4(const unsigned char* S, uint32_t srow, const v4i (&jr)[NKB], int lr,
+                                                  int lg)
 {
     const unsigned char* row = S + lr * srow + 16 * lg;
-    const unsigned char* jl = Jw + lane * 16;
-    v4i A[kPpDepth], B[kPpDepth];
+    v4i B[kPpDepth];
 #pragma unroll
-    for (int d = 0; d < kPpDepth && d < NKB; ++d) {
-        A[d] = *reinterpret_cast<const v4i*>(jl + d * 1024);
-        B[d] = *reinterpret_cast<const v4i*>(row + d * 64);
-    }
+    for (int d = 0; d < kPpDepth && d < NKB; ++d) B[d] = *reinterpret_cast<const v4i*>(row + d * 64);
     v4f acc0 = v4f{0.0f, 0.0f, 0.0f, 0.0f}, acc1 = v4f{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
     for (int kb = 0; kb < NKB; ++kb) {
-        const v4i ca = A[kb % kPpDepth], cb = B[kb % kPpDepth];
-        if (kb + kPpDepth < NKB) {
-            A[kb % kPpDepth] = *reinterpret_cast<const v4i*>(jl + (kb + kPpDepth) * 1024);
-            B[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
-        }
+        const v4i ca = jr[kb], cb = B[kb % kPpDepth];
+        if (kb + kPpDepth < NKB) B[kb % kPpDepth] = *reinterpret_cast<const v4i*>(row + (kb + kPpDepth) * 64);
         const v8i a8 = v8i{ca[0], ca[1], ca[2], ca[3], 0, 0, 0, 0};
         const v8i b8 = v8i{cb[0], cb[1], cb[2], cb[3], 0, 0, 0, 0};
         if (kb & 1)
@@ -1383,7 +1375,7 @@ template <int NU, int NKB, bool FP4 = false>
 __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sweep_pp(SweepArgs a)
 {
     static_assert(!FP4 || NKB > 0, "FP4 operands need the unrolled k loop");
-    constexpr bool JREG = NKB > 0 && !FP4;  // int8 J fragments in VGPRs
+    constexpr bool JREG = NKB > 0;  // J fragments in VGPRs (always for FP4)
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x, lane = tid & 63;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: team and column block in SGPRs
@@ -1417,8 +1409,9 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     const bool cval = tw < cbs;  // this wave owns a column block
     const int cblk = cb0 + tw;
     const int col0 = cblk * 16 + 4 * lg;  // the lane's columns col0 .. col0 + 3 (of replica lr)
-    // J of the wave's column block: VGPR fragments, or the member's slice in
-    // LDS (FP4: NKB blocks per column block, zero past the packed ones).
+    // J of the wave's column block: VGPR fragments (fragment-major, nkb
+    // packed blocks of 1 KiB per column block, zero past them), or the
+    // member's int8 slice in LDS.
     v4i jr[JREG ? NKB : 1];
     if (JREG) {
         const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb;
@@ -1426,16 +1419,6 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         for (int kb = 0; kb < (JREG ? NKB : 1); ++kb)
             jr[kb] = (cval && kb < nkb) ? *reinterpret_cast<const v4i*>(Jw + kb * 1024 + lane * 16)
                                         : v4i{0, 0, 0, 0};
-    } else if (FP4) {
-        const uint32_t per_cb = static_cast<uint32_t>(NKB) * 64u;  // 16-byte vectors per column block
-        const uint4* src = reinterpret_cast<const uint4*>(a.J);
-        uint4* dst = reinterpret_cast<uint4*>(sJ);
-        for (uint32_t q = tid; q < static_cast<uint32_t>(cbs) * per_cb; q += kPpThreads) {
-            const uint32_t c = q / per_cb, kb = (q % per_cb) / 64u, l = q % 64u;
-            dst[q] = kb < static_cast<uint32_t>(nkb)
-                         ? src[(static_cast<size_t>(cb0 + c) * nkb + kb) * 64u + l]
-                         : uint4{0u, 0u, 0u, 0u};
-        }
     } else {
         const uint32_t nvec = static_cast<uint32_t>(cbs) * cbb / 16u;
         const uint4* src = reinterpret_cast<const uint4*>(static_cast<const unsigned char*>(a.J) +
@@ -1580,8 +1563,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
             v4i iacc = v4i{0, 0, 0, 0};
             if (!closing && cval) {
                 if (FP4)
-                    facc = quasi_gradient_fp4<(NKB > 0 ? NKB : 1)>(S, srow, sJ + static_cast<size_t>(tw) * NKB * 1024u,
-                                                                 lane, lr, lg);
+                    facc = quasi_gradient_fp4<(JREG ? NKB : 1)>(S, srow, jr, lr, lg);
                 else if (JREG)
                     iacc = quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, lr, lg);
                 else
