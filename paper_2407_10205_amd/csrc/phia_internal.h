@@ -103,9 +103,9 @@ int max_coresident_mfma(int path, int mt, int cbw, int jlds, int trace, int mh, 
 // interleaved group sweep: int8 J, two 16-replica sub-blocks per workgroup
 constexpr int kPpMaxNcb = 256;            // Np <= 4096
 constexpr int64_t kPpMaxRowSum = 1 << 18;  // 32 * max_i(sum_j |J_ij| + |h_i|) < 2^23
-size_t sweep_pp_lds_bytes(int Np, int G, int fp4);
-hipError_t launch_sweep_pp(const SweepArgs& a, int fp4, size_t lds_bytes, hipStream_t st);
-int max_coresident_pp(int ncb, int fp4, size_t lds_bytes);
+size_t sweep_pp_lds_bytes(int Np, int G, int fp4, int jg);
+hipError_t launch_sweep_pp(const SweepArgs& a, int fp4, int jg, size_t lds_bytes, hipStream_t st);
+int max_coresident_pp(int ncb, int fp4, int jg, size_t lds_bytes);
 // batch mode: 16-replica work items, one workgroup each, up to 512 columns
 constexpr int kBatchMaxNp = kWaves * 4 * 16;
 hipError_t launch_init_batch(const SweepArgs* dtable, int count, hipStream_t st);

@@ -1187,14 +1187,15 @@ __host__ __device__ inline uint32_t pp_srow(int Np, int nkb_regs)
 __host__ __device__ inline uint32_t pp_srow_fp4(int nkb_regs) { return 64u * nkb_regs + 16u; }
 
 // LDS of the interleaved sweep.  int8 operands: J slice in LDS unless
-// nkb_regs > 0 (VGPR fragments).  FP4 operands: J always in VGPRs (nkb_regs
-// fragments per wave, zero past the packed ones), so LDS holds the spins
-// and the records only.
-__host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, bool fp4 = false)
+// nkb_regs > 0 (VGPR fragments) or jg (J streamed from global memory, the
+// L2 of the member's XCD).  FP4 operands: J always in VGPRs (nkb_regs
+// fragments per wave, zero past the packed ones).  Without a J slice LDS
+// holds the spins and the records only.
+__host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, bool fp4 = false, bool jg = false)
 {
     PpPlan p;
     p.j_off = 0;
-    p.s_off = (fp4 || nkb_regs > 0) ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
+    p.s_off = (fp4 || nkb_regs > 0 || jg) ? 0u : static_cast<uint32_t>(cbs_max) * cb_bytes(kPathI8, Np);
     p.s_bytes = 16u * (fp4 ? pp_srow_fp4(nkb_regs) : pp_srow(Np, nkb_regs));
     p.e_off = p.s_off + 2u * p.s_bytes;  // [2][16] energies of the previous step
     p.b_off = p.e_off + 2u * 16u * 8u;   // [2 sub-blocks][2 parities][16] best energies
@@ -1301,6 +1302,58 @@ __device__ __forceinline__ v4i quasi_gradient_ldsj(const unsigned char* S, uint3
     return acc;
 }
 
+// The wave's column block of J read from global memory (fragment-major, nkb
+// blocks of 1 KiB, served by L2 after the first pass): D fragments in
+// flight ahead of the products keep the L2-to-CU fill busy.  The steady
+// state loads unconditionally (a conditionally written fragment makes the
+// compiler wait for every load at the join); the last fewer than 2 D blocks
+// come from the ring and, if needed, one more batch.
+constexpr int kPpJgDepth = 4;
+
+template <int D>
+__device__ __forceinline__ v4i quasi_gradient_gj(const unsigned char* S, uint32_t srow, const unsigned char* Jg,
+                                                 int nkb, int lane, int lr, int lg)
+{
+    const unsigned char* row = S + lr * srow + 16 * lg;
+    const unsigned char* jl = Jg + lane * 16;
+    v4i jb[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) jb[d] = *reinterpret_cast<const v4i*>(jl + min(d, nkb - 1) * 1024);
+    v4i acc = v4i{0, 0, 0, 0};
+    int kb = 0;
+    for (; kb + 2 * D <= nkb; kb += D) {
+#pragma unroll
+        for (int d = 0; d < D; ++d) {
+            // consume the fragment, then reload its registers (no copy at the
+            // loop edge, so the loads stay in flight across iterations)
+            const v4i sv = *reinterpret_cast<const v4i*>(row + (kb + d) * 64);
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(jb[d], sv, acc, 0, 0, 0);
+            jb[d] = *reinterpret_cast<const v4i*>(jl + (kb + D + d) * 1024);
+        }
+    }
+    if (kb + D < nkb) {  // blocks kb + D .. nkb - 1 (fewer than D)
+        v4i jc[D];
+#pragma unroll
+        for (int d = 0; d < D; ++d) jc[d] = *reinterpret_cast<const v4i*>(jl + min(kb + D + d, nkb - 1) * 1024);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(jb[d], *reinterpret_cast<const v4i*>(row + (kb + d) * 64),
+                                                        acc, 0, 0, 0);
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (kb + D + d < nkb)
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                    jc[d], *reinterpret_cast<const v4i*>(row + (kb + D + d) * 64), acc, 0, 0, 0);
+    } else {
+#pragma unroll
+        for (int d = 0; d < D; ++d)
+            if (kb + d < nkb)
+                acc = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                    jb[d], *reinterpret_cast<const v4i*>(row + (kb + d) * 64), acc, 0, 0, 0);
+    }
+    return acc;
+}
+
 // One byte of sign bits as 8 FP4 (E2M1) spins, +1.0 = 0x2 and -1.0 = 0xA:
 // the nibbles hold spins 0 4 1 5 2 6 3 7 (the packed J uses the same order
 // along k).  The 24-bit multiplies keep the expansion at full VALU rate (the
@@ -1371,10 +1424,11 @@ __device__ __forceinline__ uint32_t replica_sum_u(uint32_t v)
 constexpr int kPpWaves = 16;
 constexpr int kPpThreads = 64 * kPpWaves;
 
-template <int NU, int NKB, bool FP4 = false>
+template <int NU, int NKB, bool FP4 = false, bool JG = false>
 __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu(4))) k_sweep_pp(SweepArgs a)
 {
     static_assert(!FP4 || NKB > 0, "FP4 operands need the unrolled k loop");
+    static_assert(!JG || (NKB == 0 && !FP4), "streamed J: int8 operands, runtime k loop");
     constexpr bool JREG = NKB > 0;  // J fragments in VGPRs (always for FP4)
     extern __shared__ __align__(16) unsigned char lds[];
     const int tid = threadIdx.x, lane = tid & 63;
@@ -1392,7 +1446,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
         group = blockIdx.x / G;
     }
     const int cb0 = member * ncb / G, cb1 = (member + 1) * ncb / G, cbs = cb1 - cb0;
-    const PpPlan P = pp_plan(Np, (ncb + G - 1) / G, NKB, FP4);
+    const PpPlan P = pp_plan(Np, (ncb + G - 1) / G, NKB, FP4, JG);
     const uint32_t srow = FP4 ? pp_srow_fp4(NKB) : pp_srow(Np, NKB);
     const int nkb = FP4 ? (Np + 127) / 128 : Np / 64;  // packed k blocks
     const uint32_t cbb = FP4 ? static_cast<uint32_t>(nkb) * 1024u : cb_bytes(kPathI8, Np);
@@ -1410,10 +1464,11 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     const int cblk = cb0 + tw;
     const int col0 = cblk * 16 + 4 * lg;  // the lane's columns col0 .. col0 + 3 (of replica lr)
     // J of the wave's column block: VGPR fragments (fragment-major, nkb
-    // packed blocks of 1 KiB per column block, zero past them), or the
-    // member's int8 slice in LDS.
+    // packed blocks of 1 KiB per column block, zero past them), the member's
+    // int8 slice in LDS, or (JG) read from global memory at every product.
     v4i jr[JREG ? NKB : 1];
-    if (JREG) {
+    if (JG) {
+    } else if (JREG) {
         const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb;
 #pragma unroll
         for (int kb = 0; kb < (JREG ? NKB : 1); ++kb)
@@ -1566,6 +1621,10 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                     facc = quasi_gradient_fp4<(JREG ? NKB : 1)>(S, srow, jr, lr, lg);
                 else if (JREG)
                     iacc = quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, lr, lg);
+                else if (JG)
+                    iacc = quasi_gradient_gj<kPpJgDepth>(
+                        S, srow, static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb, nkb, lane,
+                        lr, lg);
                 else
                     iacc = quasi_gradient_ldsj(S, srow, sJ + static_cast<size_t>(tw) * cbb, nkb, lane, lr, lg);
             }
@@ -1698,14 +1757,15 @@ static int pp_nkb4(int Np)
     return nkb <= 8 ? (nkb + 1) / 2 * 2 : 0;
 }
 
-size_t sweep_pp_lds_bytes(int Np, int G, int fp4)
+size_t sweep_pp_lds_bytes(int Np, int G, int fp4, int jg)
 {
     const int ncb = Np / 16;
     if (fp4) return pp_plan(Np, (ncb + G - 1) / G, pp_nkb4(Np), true).total;
+    if (jg) return pp_plan(Np, (ncb + G - 1) / G, 0, false, true).total;
     return pp_plan(Np, (ncb + G - 1) / G, pp_nkb_regs(Np)).total;
 }
 
-static const void* pp_kernel(int ncb, int fp4)
+static const void* pp_kernel(int ncb, int fp4, int jg)
 {
     const int Np = 16 * ncb;
     if (fp4) {
@@ -1716,6 +1776,12 @@ static const void* pp_kernel(int ncb, int fp4)
         case 8: return reinterpret_cast<const void*>(k_sweep_pp<2, 8, true>);
         default: return nullptr;
         }
+    }
+    if (jg) {  // Np <= 2048: wider gathers would spill the J ring
+        if (ncb <= 32) return reinterpret_cast<const void*>(k_sweep_pp<1, 0, false, true>);
+        if (ncb <= 64) return reinterpret_cast<const void*>(k_sweep_pp<2, 0, false, true>);
+        if (ncb <= 128) return reinterpret_cast<const void*>(k_sweep_pp<4, 0, false, true>);
+        return nullptr;
     }
     switch (pp_nkb_regs(Np)) {
     case 2: return reinterpret_cast<const void*>(k_sweep_pp<1, 2>);
@@ -1728,10 +1794,10 @@ static const void* pp_kernel(int ncb, int fp4)
     return reinterpret_cast<const void*>(k_sweep_pp<8, 0>);
 }
 
-hipError_t launch_sweep_pp(const SweepArgs& a, int fp4, size_t lds, hipStream_t st)
+hipError_t launch_sweep_pp(const SweepArgs& a, int fp4, int jg, size_t lds, hipStream_t st)
 {
     if (a.ncb < 1 || a.ncb > kPpMaxNcb) return hipErrorInvalidValue;
-    const void* kern = pp_kernel(a.ncb, fp4);
+    const void* kern = pp_kernel(a.ncb, fp4, jg);
     if (!kern) return hipErrorInvalidValue;
     hipError_t e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
     if (e != hipSuccess) return e;
@@ -1743,14 +1809,14 @@ hipError_t launch_sweep_pp(const SweepArgs& a, int fp4, size_t lds, hipStream_t 
     return hipGetLastError();
 }
 
-int max_coresident_pp(int ncb, int fp4, size_t lds)
+int max_coresident_pp(int ncb, int fp4, int jg, size_t lds)
 {
     int dev = 0, cus = 0, per = 0;
     if (ncb < 1 || ncb > kPpMaxNcb) return 0;
-    if (!pp_kernel(ncb, fp4)) return 0;
+    const void* f = pp_kernel(ncb, fp4, jg);
+    if (!f) return 0;
     if (hipGetDevice(&dev) != hipSuccess) return 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-    const void* f = pp_kernel(ncb, fp4);
     if (hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds)) != hipSuccess)
         return 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, f, kPpThreads, lds) != hipSuccess) return 0;

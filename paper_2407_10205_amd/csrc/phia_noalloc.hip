@@ -186,7 +186,7 @@ extern "C" phia_status phia_anneal_noalloc(phia_problem* p, int32_t replicas, in
             a.k0 = k;
             a.k1 = kk;
             a.seq_base = seq;
-            e = launch_sweep_pp(a, g.kind == 2, g.lds, stream);
+            e = launch_sweep_pp(a, g.kind == 2, g.kind == 1 && !g.j_lds, g.lds, stream);
             seq += static_cast<uint32_t>(iters * (kk - k + 1));
             k = kk;
         }

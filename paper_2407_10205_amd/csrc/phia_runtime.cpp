@@ -243,7 +243,7 @@ static const char* path_name(int path)
 }
 
 static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_lds, Geometry& g, int xcd = -1);
-static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd = -1);
+static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd = -1, int jg = 0);
 static bool make_geometry_valu(phia_problem* p, int R, int rb, Geometry& g);
 
 static bool lookup_tune_cache(phia_problem* p, int R)
@@ -261,7 +261,7 @@ static bool lookup_tune_cache(phia_problem* p, int R)
                        &us) == 11) {
         if (std::strcmp(tag, "phia-tune4") == 0 && pa == p->path && np == p->Np && r == R &&
             (kind == 4   ? make_geometry_valu(p, R, mt, g)
-             : kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g, xcd)
+             : kind >= 1 ? make_geometry_pp(p, R, G, kind == 2, g, xcd, kind == 1 && jl == 0)
                          : make_geometry(p, R, mt, cbw, G, jl, g, xcd))) {
             p->geo = g;
             found = true;
@@ -366,19 +366,20 @@ static bool make_geometry(phia_problem* p, int R, int mt, int cbw, int G, int j_
 // Interleaved group sweep (k_sweep_pp): int8 path, blocks of 32 replicas as
 // two 16-replica sub-blocks on two wave teams, G >= 2 workgroups per block
 // with one column block per wave; MFMA operands int8 or (fp4 = 1, couplings
-// that are all FP4 integers) FP4.  False if it does not apply.
-static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd)
+// that are all FP4 integers) FP4; jg = 1: int8 J streamed from global memory
+// instead of held per member (j_lds = 0).  False if it does not apply.
+static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g, int xcd, int jg)
 {
     const int Np = p->Np, ncb = Np / 16;
     if (p->path != PHIA_PATH_I8 || p->trace || p->one_block_kernel || p->mh || G < 2 || G > ncb ||
         ncb > kPpMaxNcb)
         return false;
-    if (fp4 && !p->has_j4) return false;
+    if (fp4 && (!p->has_j4 || jg)) return false;
     if (p->maxrow >= kPpMaxRowSum || 2 * p->maxrow * p->N >= (int64_t(1) << 31)) return false;
     if ((ncb + G - 1) / G > kWaves) return false;
-    const size_t lds = sweep_pp_lds_bytes(Np, G, fp4);
+    const size_t lds = sweep_pp_lds_bytes(Np, G, fp4, jg);
     if (lds > static_cast<size_t>(kLdsMax)) return false;
-    const int maxwg = max_coresident_pp(ncb, fp4, lds);
+    const int maxwg = max_coresident_pp(ncb, fp4, jg, lds);
     if (maxwg < G) return false;
     const int nblocks = (R + 31) / 32;
     int ngroups = std::min(nblocks, maxwg / G);
@@ -389,11 +390,11 @@ static bool make_geometry_pp(phia_problem* p, int R, int G, int fp4, Geometry& g
     g.mt = 2;
     g.cbw = 1;
     g.G = G;
-    g.j_lds = 1;
+    g.j_lds = jg ? 0 : 1;
     g.rows = 32;
     g.nblocks = nblocks;
     g.ngroups = ngroups;
-    if (!pick_xcd(p, G, ngroups, 1, xcd, g.xcd_map)) return false;
+    if (!pick_xcd(p, G, ngroups, jg ? 0 : 1, xcd, g.xcd_map)) return false;
     g.lds = lds;
     return true;
 }
@@ -499,13 +500,22 @@ static std::vector<Geometry> candidate_geometries(phia_problem* p, int R)
             Geometry g;
             if (make_geometry_pp(p, R, G, fp4, g)) out.push_back(g);
         }
+        {
+            // interleaved with J streamed from global memory, both placements
+            Geometry g, h;
+            if (make_geometry_pp(p, R, G, 0, g, -1, 1)) {
+                out.push_back(g);
+                if (make_geometry_pp(p, R, G, 0, h, 1 - g.xcd_map, 1)) out.push_back(h);
+            }
+        }
     }
     return out;
 }
 
 // Default geometry without tuning: fewest passes over the replica blocks,
 // then the fewest owned elements per workgroup, then J in LDS.
-// PHIA_GEOMETRY="mt,G,jlds[,cbw[,xcd]]" or "pp,G[,xcd]" / "pp4,G[,xcd]" forces
+// PHIA_GEOMETRY="mt,G,jlds[,cbw[,xcd]]" or "pp,G[,xcd]" / "pp4,G[,xcd]" /
+// "ppg,G[,xcd]" (interleaved, int8 J streamed from global memory) forces
 // one candidate (tuning experiments).
 static void choose_geometry(phia_problem* p, int R)
 {
@@ -526,9 +536,11 @@ static void choose_geometry(phia_problem* p, int R)
             if (make_geometry_valu(p, R, f_G, g)) p->geo = g;
             return;
         }
-        if (std::sscanf(env, "pp,%d,%d", &f_G, &f_x) >= 1 || std::sscanf(env, "pp4,%d,%d", &f_G, &f_x) >= 1) {
+        if (std::sscanf(env, "pp,%d,%d", &f_G, &f_x) >= 1 || std::sscanf(env, "pp4,%d,%d", &f_G, &f_x) >= 1 ||
+            std::sscanf(env, "ppg,%d,%d", &f_G, &f_x) >= 1) {
             Geometry g;
-            if (make_geometry_pp(p, R, f_G, std::strncmp(env, "pp4", 3) == 0, g, f_x)) p->geo = g;
+            if (make_geometry_pp(p, R, f_G, std::strncmp(env, "pp4", 3) == 0, g, f_x, std::strncmp(env, "ppg", 3) == 0))
+                p->geo = g;
             return;
         }
         if (std::sscanf(env, "%d,%d,%d,%d,%d", &f_mt, &f_G, &f_j, &f_c, &f_x) >= 3) {
@@ -572,7 +584,7 @@ static void choose_geometry(phia_problem* p, int R)
         if (iters != min_iters || g.kind == 4) continue;  // the VALU sweep: by the crossover rule or tuning only
         const int cbs_max = (p->Np / 16 + g.G - 1) / g.G;
         const double elems = static_cast<double>(g.rows) * cbs_max * 16;
-        double cost = g.kind >= 1 ? 1e6 + 2 * g.G - (g.kind == 2 ? 1 : 0)
+        double cost = g.kind >= 1 ? 1e6 + 2 * g.G - (g.kind == 2 ? 1 : 0) + (g.j_lds ? 0 : 0.5)
                                   : (g.G > 1 ? 2e6 : 0.0) + elems * 2 + (g.j_lds ? 0 : 1);
         // Served requests share cooperative launches: the fewest workgroups.
         if (p->one_block_kernel) cost = static_cast<double>(g.nblocks) * g.G * 4 + (g.j_lds ? 0 : 1) + g.mt;
@@ -1218,7 +1230,7 @@ phia_status phia_anneal_run(phia_problem* p, int64_t k_end)
             a.k0 = k;
             a.k1 = kk;
             a.seq_base = p->seq;
-            e = launch_sweep_pp(a, p->geo.kind == 2, p->geo.lds, p->st);
+            e = launch_sweep_pp(a, p->geo.kind == 2, p->geo.kind == 1 && !p->geo.j_lds, p->geo.lds, p->st);
             p->seq += static_cast<uint32_t>(use);
             k = kk;
         }

@@ -384,6 +384,33 @@ def test_interleaved_group_sweep_full_parity(P, O):
     assert_parity(dev, runs)
 
 
+def test_interleaved_streamed_j_full_parity(P, O):
+    """Interleaved sweep with the int8 J read from global memory at every
+    product (no slice per member): the ragged case bit-identical to the
+    oracle, and a run split into uneven chunks, in the other XCD placement,
+    bit-identical to the one-launch run."""
+    J, h = inst.sk_gauss_fixed(150, 5, frac_bits=5, bits=8)
+    with _Geometry("ppg,3"):
+        dev, runs = run_both(P, O, J, h, 5, "i8", 45, 137, 0.2, 1.0, 0.05, 1.5, 23, 71, trace=False)
+    say("geometry", dev["info"])
+    assert dev["info"]["sweep_kernel"] == 1 and dev["info"]["group"] == 3 and dev["info"]["j_in_lds"] == 0
+    assert_parity(dev, runs)
+    with _Geometry("ppg,4,0"):
+        p = P.Problem(J, h, frac_bits=5, path="i8")
+        p.start(45, 137, 0.2, 1.0, beta0=0.05, beta1=1.5, refresh_L=23, seed=71)
+        for k in (1, 40, 96, 137):  # end steps of uneven chunks
+            p.run(k)
+        p.sync()
+        info = p.info()
+        E, S, K = p.replica_best()
+        x, v, _ = p.get_state()
+        p.close()
+    assert info["j_in_lds"] == 0 and info["group"] == 4
+    assert np.array_equal(E, dev["E"]) and np.array_equal(K, dev["K"]) and np.array_equal(S, dev["S"])
+    assert np.array_equal(x.view(np.uint32), dev["x"].view(np.uint32))
+    assert np.array_equal(v.view(np.uint32), dev["v"].view(np.uint32))
+
+
 def test_interleaved_geometries_and_chunks_identical(P, O):
     """Group sizes, several passes over the replica blocks per launch
     (R = 4096 on a 320-spin instance) and runs split into uneven chunks all
@@ -756,7 +783,8 @@ def test_largest_instance_per_path(P, O, path, N, R, T):
 
 
 # -------------------------------------- the other workloads at full size ----
-@pytest.mark.parametrize("path,geometry", [("i8", None), ("i8", "1,8,0,2"), ("bf16hilo", None)])
+@pytest.mark.parametrize("path,geometry", [("i8", None), ("i8", "1,8,0,2"), ("i8", "ppg,16,0"), ("i8", "ppg,16,1"),
+                                           ("bf16hilo", None)])
 def test_sk2000_full_shape_sampled(P, O, path, geometry):
     """Dense SK N = 2000 on the 2^-5 grid (8-bit couplings), 512 replicas:
     the full instance and replica count (short run), in the default launch
@@ -775,8 +803,11 @@ def test_sk2000_full_shape_sampled(P, O, path, geometry):
         os.environ.pop("PHIA_GEOMETRY", None)
     E, S, K = p.replica_best()
     x, v, _ = p.get_state()
-    say("geometry", p.info())
+    info = p.info()
+    say("geometry", info)
     p.close()
+    if geometry and geometry.startswith("ppg"):
+        assert info["sweep_kernel"] == 1 and info["j_in_lds"] == 0 and info["group"] == 16
     Ji, hi = int_units(J, h, 5)
     betas = O.beta_linear(0.1, 3.0, T)
     for r in (0, 255, 511):
