@@ -1173,7 +1173,7 @@ k_sweep_mfma(SweepArgs args)
 // parity seq & 1: a slot is rewritten two publications later, after every
 // member has read it.
 struct PpPlan {
-    uint32_t j_off, s_off, s_bytes, e_off, b_off, k_off, misc_off, total;
+    uint32_t j_off, s_off, s_bytes, e_off, b_off, k_off, misc_off, part_off, total;
 };
 
 // S row stride: Np bytes, or 64 NKB bytes when the MFMA loop reads NKB
@@ -1201,7 +1201,8 @@ __host__ __device__ inline PpPlan pp_plan(int Np, int cbs_max, int nkb_regs, boo
     p.b_off = p.e_off + 2u * 16u * 8u;   // [2 sub-blocks][2 parities][16] best energies
     p.k_off = p.b_off + 4u * 16u * 8u;   // [2][16] step of the best energy
     p.misc_off = p.k_off + 2u * 16u * 8u;
-    p.total = p.misc_off + 16u;
+    p.part_off = p.misc_off + 16u;  // jg: [8 waves][64 lanes] partial products of the gathering team
+    p.total = p.part_off + (jg ? static_cast<uint32_t>(kWaves) * 64u * 16u : 0u);
     return p;
 }
 
@@ -1460,6 +1461,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     int64_t* sKall = reinterpret_cast<int64_t*>(lds + P.k_off);
     int64_t* sK = sKall + team * 16;
     int* sAbort = reinterpret_cast<int*>(lds + P.misc_off);
+    v4i* sPart = reinterpret_cast<v4i*>(lds + P.part_off);
     const bool cval = tw < cbs;  // this wave owns a column block
     const int cblk = cb0 + tw;
     const int col0 = cblk * 16 + 4 * lg;  // the lane's columns col0 .. col0 + 3 (of replica lr)
@@ -1467,9 +1469,9 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
     // packed blocks of 1 KiB per column block, zero past them), the member's
     // int8 slice in LDS, or (JG) read from global memory at every product.
     v4i jr[JREG ? NKB : 1];
+    const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb;
     if (JG) {
     } else if (JREG) {
-        const unsigned char* Jw = static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb;
 #pragma unroll
         for (int kb = 0; kb < (JREG ? NKB : 1); ++kb)
             jr[kb] = (cval && kb < nkb) ? *reinterpret_cast<const v4i*>(Jw + kb * 1024 + lane * 16)
@@ -1610,7 +1612,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
 
         // Step k0 + s and its publication s + 1 (s < nsteps), then the
         // records of step k0 + s - 1.
-        auto compute = [&](int s) {
+        auto compute = [&](int s, v4i jg_acc) {
             const int64_t k = a.k0 + s;
             const bool closing = (s == nsteps);
             const float ck = ck_next;
@@ -1622,9 +1624,7 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                 else if (JREG)
                     iacc = quasi_gradient_regj<(JREG ? NKB : 1)>(S, srow, jr, lr, lg);
                 else if (JG)
-                    iacc = quasi_gradient_gj<kPpJgDepth>(
-                        S, srow, static_cast<const unsigned char*>(a.J) + static_cast<size_t>(cblk) * cbb, nkb, lane,
-                        lr, lg);
+                    iacc = jg_acc;  // computed by both teams before the mid-phase barrier
                 else
                     iacc = quasi_gradient_ldsj(S, srow, sJ + static_cast<size_t>(tw) * cbb, nkb, lane, lr, lg);
             }
@@ -1702,9 +1702,31 @@ __global__ void __launch_bounds__(kPpThreads) __attribute__((amdgpu_waves_per_eu
                 break;
             }
             const int abort_flag = *sAbort;  // consumed one phase later
+            v4i jg_acc = v4i{0, 0, 0, 0};
+            if (JG) {
+                // The product of the computing team's step, split between the
+                // teams: the computing team takes k blocks [0, kh), the
+                // gathering team [kh, nkb) of the same column block and
+                // sub-block (its spins are in LDS since the previous phase),
+                // handing its partial over through LDS.  Twice the J fragments
+                // in flight per CU; the gathering team polls for its words
+                // after the barrier.
+                const int cteam = ph & 1, sc = (ph - cteam) >> 1;
+                const int kh = (nkb + 1) >> 1;
+                if (sc < nsteps && cval) {
+                    const unsigned char* Sc = lds + P.s_off + cteam * P.s_bytes;
+                    if (team == cteam)
+                        jg_acc = quasi_gradient_gj<kPpJgDepth>(Sc, srow, Jw, kh, lane, lr, lg);
+                    else if (nkb > kh)
+                        sPart[tw * 64 + lane] = quasi_gradient_gj<kPpJgDepth>(Sc + kh * 64, srow, Jw + kh * 1024,
+                                                                              nkb - kh, lane, lr, lg);
+                }
+                __syncthreads();
+                if (team == cteam && sc < nsteps && cval && nkb > kh) jg_acc += sPart[tw * 64 + lane];
+            }
             if (team == (ph & 1)) {
                 const int s = (ph - team) >> 1;
-                compute(s);
+                compute(s, jg_acc);
                 if (s + 1 < nsteps && a.k0 + s + 1 == next_ref) {
                     next_ref += a.L;
                     ++round;
