@@ -703,7 +703,8 @@ def main():
     geometry = {k: info[k] for k in ("group", "rows_per_block", "j_in_lds", "sweep_kernel", "group_on_one_xcd",
                                      "incremental")}
     # counter summaries are kept per kernel and per workload variant
-    profile_key = (args.workload + ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "") +
+    profile_key = (args.workload + (f"_{args.path}" if args.path != w.get("path", "i8") else "") +
+                   ("_poly2" if args.deriv == "poly2" else "") + ("_mh" if mh is not None else "") +
                    ("_full" if args.no_incremental else "") + (f"_r{R}" if args.replicas else ""))
     kernel = ("k_sweep_valu" if info["sweep_kernel"] == 4 else
               "k_sweep_pp" if info["sweep_kernel"] >= 1 else "k_sweep_mfma")
