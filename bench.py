@@ -346,7 +346,7 @@ def run_batch_bench(args, w):
     kernel = "k_batch_fp4" if all(k == 3 for k in kinds) else "k_batch_fp4 + k_sweep_mfma (batch)"
     cpu = None
     if not args.no_cpu:
-        stride = max(1, n // 64)
+        stride = max(1, n // 256)
         sample = insts[::stride + 1] if stride > 1 else insts
         cpu = cpu_baseline_instances(sample, R, T, s, args.cpu_seconds,
                                      f"instances 0, {stride + 1}, {2 * (stride + 1)}, ... of the batch")
@@ -521,8 +521,10 @@ def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
     t = time.perf_counter()
     O.anneal(Ji, hi, f, 1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=20, threads=1, deriv=deriv, mh=mh)
     per_step = (time.perf_counter() - t) / 20
-    R = threads
     steps = int(max(20, min(T, budget_s / max(per_step, 1e-9))))
+    # more replicas (groups of `threads`, up to the workload's) until the
+    # sample fills the budget
+    R = min(max(w["R"], threads), threads * max(1, int(budget_s / max(steps * per_step, 1e-9))))
     t = time.perf_counter()
     O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads, deriv=deriv,
              mh=mh)

@@ -221,21 +221,33 @@ __device__ __attribute__((noinline)) void batch_item(const BatchInst& a, int blk
             // Records of step k - 1 (App. B, Table 3, state 5): every lane that
             // holds a row takes the same decision.
             if (s > 0) {
+                float E[MT][4];
+                uint32_t impm = 0;
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt) {
                     const float4 t4 = *reinterpret_cast<const float4*>(sE + r3p * 32 + mt * 16 + 4 * lg);
                     const float tot[4] = {t4.x, t4.y, t4.z, t4.w};
 #pragma unroll
                     for (int j = 0; j < 4; ++j) {
-                        const float E = -0.5f * tot[j];  // the sum is even: exact
-                        const bool imp = E < bE[mt][j];
-                        bE[mt][j] = imp ? E : bE[mt][j];
-                        bK[mt][j] = imp ? static_cast<int32_t>(k - 1) : bK[mt][j];
-                        uint32_t rowmask = 0;
-#pragma unroll
-                        for (int cw = 0; cw < NCW; ++cw) rowmask |= 1u << ((mt * NCW + cw) * 4 + j);
-                        bestbits = imp ? ((bestbits & ~rowmask) | (pprev & rowmask)) : bestbits;
+                        E[mt][j] = -0.5f * tot[j];  // the sum is even: exact
+                        if (E[mt][j] < bE[mt][j]) impm |= 1u << (mt * 4 + j);
                     }
+                }
+                // Late in an anneal few steps improve a record: the updates
+                // run only when some row of the wave improved (uniform branch).
+                if (__any(impm != 0)) {
+#pragma unroll
+                    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                        for (int j = 0; j < 4; ++j) {
+                            const bool imp = (impm >> (mt * 4 + j)) & 1u;
+                            bE[mt][j] = imp ? E[mt][j] : bE[mt][j];
+                            bK[mt][j] = imp ? static_cast<int32_t>(k - 1) : bK[mt][j];
+                            uint32_t rowmask = 0;
+#pragma unroll
+                            for (int cw = 0; cw < NCW; ++cw) rowmask |= 1u << ((mt * NCW + cw) * 4 + j);
+                            bestbits = imp ? ((bestbits & ~rowmask) | (pprev & rowmask)) : bestbits;
+                        }
                 }
             }
             if (last) break;
