@@ -1156,9 +1156,11 @@ k_sweep_mfma(SweepArgs args)
 // owns column block cb0 + w of both sub-blocks), Np / 16 <= 32 * NU,
 // 32 * max_i(sum_j |J_ij| + |h_i|) < 2^23 (a 16-column partial energy fits 24
 // bits) and 2 N max_i(...) < 2^31 (a row's energy sum fits int32).  With
-// NKB > 0 (Np <= 64 NKB) a wave keeps its column block of J in VGPRs as NKB
-// MFMA operand fragments for the whole launch; with NKB = 0 the member's J
-// slice sits in LDS.
+// NKB > 0 (FP4 operands: NKB blocks of 128 k positions; int8: Np <= 64 NKB)
+// a wave keeps its column block of J in VGPRs as NKB MFMA operand fragments
+// for the whole launch; with NKB = 0 the member's int8 J slice sits in LDS,
+// or (JG) each product reads it from global memory and both teams share the
+// product of the computing one.
 //
 // Exchange word of (sub-block, replica row, column block), 64 bits:
 //   [63:40] low 24 bits of the publication's sequence number (tag)
