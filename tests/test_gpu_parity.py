@@ -862,7 +862,10 @@ def test_serving_full_stream_energies(P, O):
     """The serving workload's 60 requests (N log-uniform in [100, 4000], dense
     and sparse, integer and fixed point): every result's energy is the Eq. 2
     energy of the state it returns, success means reaching the planted
-    energy, and no result lies below the planted ground state."""
+    energy, and no result lies below the planted ground state.  The three
+    smallest requests are also replayed on the oracle for the steps they
+    used: the served record (lowest energy over the replicas, lowest replica
+    on ties, and its spins) is the oracle's (App. B, Table 3, state 5)."""
     import time
     g = inst.rng(0)
     n = 60
@@ -881,7 +884,9 @@ def test_serving_full_stream_energies(P, O):
         t = srv.submit(p, 64, 20000, E, seed=900 + i, **sched)
         reqs.append((p, t, J, h, E, f))
     say("submitted", n)
-    for p, t, J, h, E, f in reqs:
+    smallest = set(np.argsort(sizes, kind="stable")[:3].tolist())
+    betas = O.beta_linear(sched["beta0"], sched["beta1"], 20000)
+    for i, (p, t, J, h, E, f) in enumerate(reqs):
         r = srv.wait(t, 300.0)
         assert r["state"] == P.REQ_DONE, r
         s = srv.spins(t)
@@ -890,6 +895,13 @@ def test_serving_full_stream_energies(P, O):
         e = O.energy(Ji, hi, s)
         assert e == r["energy_units"]
         assert e >= E and r["success"] == (e <= E)
+        if i in smallest:
+            o = O.anneal(Ji, hi, f, 64, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 900 + i,
+                         k1=int(r["steps_used"]), threads=8)
+            rs = int(np.argmin(o.bestE))  # first index of the minimum
+            say("replayed request", i, "N", J.shape[0], "steps", r["steps_used"], "replica", rs)
+            assert o.bestE[rs] == r["energy_units"] and rs == r["replica"], (i, rs, r)
+            assert np.array_equal(o.bestS[rs], s), i
     srv.close()
     for p, *_ in reqs:
         p.close()
