@@ -545,15 +545,23 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
     threads = cpu["threads"]
     units = [grid_units(J, h) for J, h in insts]
     betas = O.beta_linear(sched["beta0"], sched["beta1"], T)
-    # calibrate on the whole sample with a few steps, then size the run to the budget
+    # calibrate on the whole sample at two step counts (each call also has a fixed cost: set-up,
+    # initial kick, thread start), then size the run to the budget
     calib = 16
-    t = time.perf_counter()
-    for f, Ji, hi in units:
-        O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=calib,
-                 threads=threads)
-    per_step = (time.perf_counter() - t) / calib
+
+    def run_all(k):
+        t = time.perf_counter()
+        for f, Ji, hi in units:
+            O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=k,
+                     threads=threads)
+        return time.perf_counter() - t
+
+    t1 = run_all(calib)
+    t2 = run_all(4 * calib)
+    per_step = max((t2 - t1) / (3 * calib), 1e-12)
+    fixed = max(t1 - calib * per_step, 0.0)
     total_n = sum(u[1].shape[0] for u in units)
-    steps = int(max(calib, min(T, budget_s / max(per_step, 1e-12))))
+    steps = int(max(calib, min(T, (budget_s - fixed) / per_step)))
     su = 0.0
     t = time.perf_counter()
     for f, Ji, hi in units:
