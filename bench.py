@@ -529,9 +529,17 @@ def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
     O.anneal(Ji, hi, f, R, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps, threads=threads, deriv=deriv,
              mh=mh)
     dt = time.perf_counter() - t
+    # a fifth of the budget on one thread
+    steps1 = int(max(20, min(T, budget_s / 5 / max(per_step, 1e-9))))
+    R1 = max(1, min(w["R"], int(budget_s / 5 / max(steps1 * per_step, 1e-9))))
+    t = time.perf_counter()
+    O.anneal(Ji, hi, f, R1, betas, s["eps"], s["gamma"], s["refresh_L"], 7, k1=steps1, threads=1, deriv=deriv, mh=mh)
+    dt1 = time.perf_counter() - t
     return {"value": R * N * steps / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"replicas 0..{R - 1}, steps 0..{steps - 1} of the same schedule, {dt:.1f} s; oracle {flags}, "
                       f"OpenMP over replicas",
+            "single_thread": {"value": R1 * N * steps1 / dt1, "unit": "spin-updates/s",
+                              "sample": f"replicas 0..{R1 - 1}, steps 0..{steps1 - 1}, one thread, {dt1:.1f} s"},
             "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cpus_allowed": cpu["allowed"]}
 
 
@@ -539,39 +547,43 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
     """Oracle timing on a subset of a workload's instances: every sampled
     instance runs `threads` replicas (OpenMP over replicas) for the same
     number of steps of its schedule, sized so that the sample takes about
-    budget_s.  Spin-updates/s of the sample = sum N x replicas x steps / time."""
+    budget_s.  Spin-updates/s of the sample = sum N x replicas x steps / time.
+    A shorter run of one replica per instance on one thread gives the
+    single-thread rate."""
     O, flags = oracle_for_host()
     cpu = host_cpu()
     threads = cpu["threads"]
     units = [grid_units(J, h) for J, h in insts]
     betas = O.beta_linear(sched["beta0"], sched["beta1"], T)
-    # calibrate on the whole sample at two step counts (each call also has a fixed cost: set-up,
-    # initial kick, thread start), then size the run to the budget
-    calib = 16
+    total_n = sum(u[1].shape[0] for u in units)
 
-    def run_all(k):
+    def run_all(k, reps, nthr):
         t = time.perf_counter()
         for f, Ji, hi in units:
-            O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=k,
-                     threads=threads)
+            O.anneal(Ji, hi, f, reps, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=k,
+                     threads=nthr)
         return time.perf_counter() - t
 
-    t1 = run_all(calib)
-    t2 = run_all(4 * calib)
-    per_step = max((t2 - t1) / (3 * calib), 1e-12)
-    fixed = max(t1 - calib * per_step, 0.0)
-    total_n = sum(u[1].shape[0] for u in units)
-    steps = int(max(calib, min(T, (budget_s - fixed) / per_step)))
-    su = 0.0
-    t = time.perf_counter()
-    for f, Ji, hi in units:
-        O.anneal(Ji, hi, f, threads, betas, sched["eps"], sched["gamma"], sched["refresh_L"], 7, k1=steps,
-                 threads=threads)
-        su += float(Ji.shape[0]) * threads * steps
-    dt = time.perf_counter() - t
-    return {"value": su / dt, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
+    def sample(reps, nthr, budget):
+        # calibrate on the whole sample at two step counts (each call also has a fixed cost:
+        # set-up, initial kick, thread start), then size the run to the budget
+        calib = 16
+        t1 = run_all(calib, reps, nthr)
+        t2 = run_all(4 * calib, reps, nthr)
+        per_step = max((t2 - t1) / (3 * calib), 1e-12)
+        fixed = max(t1 - calib * per_step, 0.0)
+        steps = int(max(calib, min(T, (budget - fixed) / per_step)))
+        dt = run_all(steps, reps, nthr)
+        return total_n * reps * steps / dt, steps, dt
+
+    value, steps, dt = sample(threads, threads, budget_s)
+    v1, steps1, dt1 = sample(1, 1, budget_s / 5)
+    return {"value": value, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{what}: {len(units)} instances (sum N = {total_n}), replicas 0..{threads - 1}, "
                       f"steps 0..{steps - 1} of each schedule, {dt:.1f} s; oracle {flags}, OpenMP over replicas",
+            "single_thread": {"value": v1, "unit": "spin-updates/s",
+                              "sample": f"the same instances, replica 0, steps 0..{steps1 - 1}, one thread, "
+                                        f"{dt1:.1f} s"},
             "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cpus_allowed": cpu["allowed"]}
 
 
