@@ -545,9 +545,9 @@ def cpu_baseline(J, h, w, budget_s, deriv="tanh", mh=None):
 
 def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
     """Oracle timing on a subset of a workload's instances: every sampled
-    instance runs `threads` replicas (OpenMP over replicas) for the same
-    number of steps of its schedule, sized so that the sample takes about
-    budget_s.  Spin-updates/s of the sample = sum N x replicas x steps / time.
+    instance runs `threads` replicas (OpenMP over replicas; more, up to R,
+    when the whole schedule fits) for the same number of steps of its
+    schedule, sized so that the sample takes about budget_s.  Spin-updates/s of the sample = sum N x replicas x steps / time.
     A shorter run of one replica per instance on one thread gives the
     single-thread rate."""
     O, flags = oracle_for_host()
@@ -566,24 +566,27 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
 
     def sample(reps, nthr, budget):
         # calibrate on the whole sample at two step counts (each call also has a fixed cost:
-        # set-up, initial kick, thread start), then size the run to the budget
+        # set-up, initial kick, thread start), then size the run to the budget: steps first,
+        # then, when the whole schedule fits, more replicas (multiples of `reps`, at most R)
         calib = 16
         t1 = run_all(calib, reps, nthr)
         t2 = run_all(4 * calib, reps, nthr)
         per_step = max((t2 - t1) / (3 * calib), 1e-12)
         fixed = max(t1 - calib * per_step, 0.0)
         steps = int(max(calib, min(T, (budget - fixed) / per_step)))
+        if steps >= T:
+            reps = max(reps, min(max(R, reps), reps * int((budget - fixed) / (T * per_step))))
         dt = run_all(steps, reps, nthr)
-        return total_n * reps * steps / dt, steps, dt
+        return total_n * reps * steps / dt, reps, steps, dt
 
-    value, steps, dt = sample(threads, threads, budget_s)
-    v1, steps1, dt1 = sample(1, 1, budget_s / 5)
+    value, reps, steps, dt = sample(threads, threads, budget_s)
+    v1, reps1, steps1, dt1 = sample(1, 1, budget_s / 5)
     return {"value": value, "unit": "spin-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{what}: {len(units)} instances (sum N = {total_n}), replicas 0..{threads - 1}, "
+            "sample": f"{what}: {len(units)} instances (sum N = {total_n}), replicas 0..{reps - 1}, "
                       f"steps 0..{steps - 1} of each schedule, {dt:.1f} s; oracle {flags}, OpenMP over replicas",
             "single_thread": {"value": v1, "unit": "spin-updates/s",
-                              "sample": f"the same instances, replica 0, steps 0..{steps1 - 1}, one thread, "
-                                        f"{dt1:.1f} s"},
+                              "sample": f"the same instances, replicas 0..{reps1 - 1}, steps 0..{steps1 - 1}, "
+                                        f"one thread, {dt1:.1f} s"},
             "cpu_model": cpu["model"], "nproc": cpu["nproc"], "cpus_allowed": cpu["allowed"]}
 
 
