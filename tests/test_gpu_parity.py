@@ -411,6 +411,19 @@ def test_interleaved_streamed_j_full_parity(P, O):
     assert np.array_equal(v.view(np.uint32), dev["v"].view(np.uint32))
 
 
+def test_interleaved_streamed_j_split_parity(P, O):
+    """Streamed J at the size it is built for (N = 1990, G = 16: 32 k blocks
+    per column block, 16 streamed by each team through the fragment ring and
+    its tail): ragged columns and a partly filled second sub-block,
+    bit-identical to the oracle."""
+    J, h = inst.sk_gauss_fixed(1990, 7, frac_bits=5, bits=8)
+    with _Geometry("ppg,16"):
+        dev, runs = run_both(P, O, J, h, 5, "i8", 20, 40, 0.2, 1.0, 0.05, 1.5, 13, 73, trace=False)
+    say("geometry", dev["info"])
+    assert dev["info"]["sweep_kernel"] == 1 and dev["info"]["group"] == 16 and dev["info"]["j_in_lds"] == 0
+    assert_parity(dev, runs)
+
+
 def test_interleaved_geometries_and_chunks_identical(P, O):
     """Group sizes, several passes over the replica blocks per launch
     (R = 4096 on a 320-spin instance) and runs split into uneven chunks all
