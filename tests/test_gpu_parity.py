@@ -598,6 +598,55 @@ def test_batch_matches_single_runs_and_oracle(P, O):
         p.close()
 
 
+def test_batch_fp4_edge_sizes(P, O):
+    """The persistent FP4 batch kernel at its edges: a single spin with a
+    field, N = 2, one column block (only wave 0 owns columns), 32 / 33 spins
+    around a column-block boundary, 511 and the largest N = 512; one replica,
+    a full 32-replica item, and 33 replicas (a second item with one real
+    row).  Bit-identical to single runs, and to the oracle on the last
+    replica of each instance."""
+    specs = [(1, 1, 60), (2, 32, 45), (16, 33, 50), (32, 7, 40), (33, 32, 41), (511, 33, 23), (512, 1, 30)]
+    insts, probs, reps, steps, scheds, seeds = [], [], [], [], [], []
+    for i, (N, R, T) in enumerate(specs):
+        J, h = inst.sk_pm1(N, 40 + i)
+        h = np.asarray(h, np.float64).copy()
+        h[: min(N, 3)] = [1.0, -1.0, 1.0][: min(N, 3)]  # non-zero fields, incl. the single spin's
+        insts.append((J, h))
+        probs.append(P.Problem(J, h, path="i8"))
+        reps.append(R)
+        steps.append(T)
+        scheds.append(dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=2.5, refresh_L=7 + i,
+                           deriv="poly2" if i % 3 == 2 else "tanh"))
+        seeds.append(500 + i)
+    plan = P.Batch(probs, reps, steps, scheds)
+    kinds = [p.info()["sweep_kernel"] for p in probs]
+    say("batch edge sizes, sweep kernels", kinds)
+    assert kinds == [3] * len(specs)
+    plan.launch(seeds)
+    plan.sync()
+    for i, p in enumerate(probs):
+        got = p.replica_best() + p.get_state()[:2]
+        J, h = insts[i]
+        sc = scheds[i]
+        q = P.Problem(J, h, path="i8")
+        q.anneal(reps[i], steps[i], sc["eps"], sc["gamma"], beta0=sc["beta0"], beta1=sc["beta1"],
+                 refresh_L=sc["refresh_L"], seed=seeds[i], deriv=sc["deriv"])
+        ref = q.replica_best() + q.get_state()[:2]
+        q.close()
+        for u, w in zip(ref, got):
+            assert np.array_equal(u, w), specs[i]
+        Ji, hi = int_units(J, h, 0)
+        o = O.anneal(Ji, hi, 0, 1, O.beta_linear(sc["beta0"], sc["beta1"], steps[i]), sc["eps"], sc["gamma"],
+                     sc["refresh_L"], seeds[i], r0=reps[i] - 1, deriv=sc["deriv"])
+        assert got[0][-1] == o.bestE[0] and got[2][-1] == o.bestStep[0], specs[i]
+        assert np.array_equal(got[1][-1], o.bestS[0]), specs[i]
+        assert np.array_equal(got[3][-1].view(np.uint32), o.x[0].view(np.uint32)), specs[i]
+        assert np.array_equal(got[4][-1].view(np.uint32), o.v[0].view(np.uint32)), specs[i]
+    plan.close()
+    for p in probs:
+        p.close()
+
+
 def test_batch_plan_relaunch_and_ownership(P, O):
     """A batch plan built once and launched twice with different seeds: every
     instance bit-identical to annealing it alone with that seed, on the
