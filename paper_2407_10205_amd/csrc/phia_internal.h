@@ -86,7 +86,7 @@ struct SweepArgs {
 hipError_t launch_init(const SweepArgs& a, hipStream_t st);
 // VALU sweeps (k_sweep_valu): RB replicas and all columns per workgroup.
 enum ValuForm : int { kValuFp32 = 0, kValuDot8 = 1, kValuEll = 2 };
-constexpr int kValuMaxNp = 4096;  // 16 columns per thread
+constexpr int kValuMaxNp = 4096;  // 16 columns per thread at 256 threads, 4 at 1024
 // LDS offset of the couplings of the int8 form when they reside in LDS.
 __host__ __device__ inline size_t valu_jl_offset(int rb, int Np) { return (static_cast<size_t>(rb) * Np + 15) & ~size_t(15); }
 size_t valu_lds_bytes(int form, int rb, int Np, bool jl);

@@ -1,9 +1,10 @@
 // VALU sweeps of the PHIA library for gfx950 (k_sweep_valu).
 //
-// A workgroup of 256 threads owns RB replicas and all of their columns for
-// the whole launch: thread t keeps x and v of columns i = t + 256 c (c < CPT)
-// of every replica in registers, the spins of the current step go to LDS,
-// and J.s + h (Eq. 6) runs on the vector ALUs in one of three forms:
+// A workgroup of VT threads (256; 1024 for FORM 0) owns RB replicas and all
+// of their columns for the whole launch: thread t keeps x and v of columns
+// i = t + VT c (c < CPT) of every replica in registers, the spins of the
+// current step go to LDS, and J.s + h (Eq. 6) runs on the vector ALUs in one
+// of three forms:
 //
 //   FORM 0 (FP32 path): FP32 couplings [Np][Np] row-major, one FMA per
 //          coupling against spins stored as +-1.0f.  The plain sweep.
@@ -38,12 +39,16 @@ namespace phia {
 
 namespace {
 
-constexpr int kVT = 256;  // threads per workgroup
+constexpr int kVT = 256;  // threads per workgroup of the int8 and ELL forms
+// The FP32 form takes 1024 threads (one column each up to Np = 1024): its
+// product is one FMA per coupling and replica, issue-bound, and four waves
+// per SIMD hide the L2 latency of its coupling rows.
+constexpr int valu_threads(int form) { return form == kValuFp32 ? 1024 : kVT; }
 
 // J.s of this thread's columns for every replica of the block (FORM 1):
 // fragments [Np/16][Np/64][64][16], lane l of fragment (cb, kb) holding
 // J[16 cb + l % 16][64 kb + 16 (l / 16) + t].
-template <int CPT, int RB>
+template <int CPT, int RB, int VT>
 __device__ __forceinline__ void dot_i8(const int8_t* __restrict__ J8, const int8_t* sS8, int Np, int tid,
                                        int (&acc)[RB][CPT])
 {
@@ -56,7 +61,7 @@ __device__ __forceinline__ void dot_i8(const int8_t* __restrict__ J8, const int8
             for (int g = 0; g < 4; ++g) s[r][g] = *reinterpret_cast<const v4i*>(sS8 + r * Np + kb * 64 + 16 * g);
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int i = tid + kVT * c;
+            const int i = tid + VT * c;
             if (i >= Np) continue;
             const v4i* src = reinterpret_cast<const v4i*>(
                 J8 + ((static_cast<size_t>(i >> 4) * nkb + kb) * 64 + (i & 15)) * 16);
@@ -74,7 +79,7 @@ __device__ __forceinline__ void dot_i8(const int8_t* __restrict__ J8, const int8
 }
 
 // J.s by ELL gathers (FORM 2): slot d of row i is E[d Np + i].
-template <int CPT, int RB>
+template <int CPT, int RB, int VT>
 __device__ __forceinline__ void dot_ell(const int32_t* __restrict__ E, const int8_t* sS8, int Np, int D, int tid,
                                         int (&acc)[RB][CPT])
 {
@@ -85,7 +90,7 @@ __device__ __forceinline__ void dot_ell(const int32_t* __restrict__ E, const int
         for (int u = 0; u < 4; ++u)
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-                const int i = tid + kVT * c;
+                const int i = tid + VT * c;
                 w[u][c] = (i < Np) ? E[static_cast<size_t>(d + u) * Np + i] : 0;
             }
 #pragma unroll
@@ -100,7 +105,7 @@ __device__ __forceinline__ void dot_ell(const int32_t* __restrict__ E, const int
     for (; d < D; ++d)
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int i = tid + kVT * c;
+            const int i = tid + VT * c;
             const int32_t w = (i < Np) ? E[static_cast<size_t>(d) * Np + i] : 0;
             const int j = w & 0xffff, val = w >> 16;
 #pragma unroll
@@ -109,7 +114,7 @@ __device__ __forceinline__ void dot_ell(const int32_t* __restrict__ E, const int
 }
 
 // J.s by FP32 multiply-adds (FORM 0), eight rows of J in flight per thread.
-template <int CPT, int RB>
+template <int CPT, int RB, int VT>
 __device__ __forceinline__ void dot_f32(const float* __restrict__ J, const float* sSf, int N, int Np, int tid,
                                         int (&I)[RB][CPT])
 {
@@ -125,7 +130,7 @@ __device__ __forceinline__ void dot_f32(const float* __restrict__ J, const float
         for (int u = 0; u < 8; ++u)
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-                const int i = tid + kVT * c;
+                const int i = tid + VT * c;
                 jv[u][c] = (i < Np) ? J[static_cast<int64_t>(j + u) * Np + i] : 0.0f;
             }
 #pragma unroll
@@ -145,7 +150,7 @@ __device__ __forceinline__ void dot_f32(const float* __restrict__ J, const float
         for (int r = 0; r < RB; ++r) sj[r] = sSf[r * Np + j];
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int i = tid + kVT * c;
+            const int i = tid + VT * c;
             const float jv = (i < Np) ? J[static_cast<int64_t>(j) * Np + i] : 0.0f;
 #pragma unroll
             for (int r = 0; r < RB; ++r) acc[r][c] = __builtin_fmaf(jv, sj[r], acc[r][c]);
@@ -161,20 +166,20 @@ __device__ __forceinline__ void dot_f32(const float* __restrict__ J, const float
 
 // JL (FORM 1): the int8 couplings are copied to LDS once per launch, after
 // the spins, and every step reads them there.
-template <int FORM, int CPT, int RB, bool MH, bool JL>
-__global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
+template <int FORM, int CPT, int RB, bool MH, bool JL, int VT>
+__global__ void __launch_bounds__(VT) k_sweep_valu(SweepArgs a)
 {
     // spins of the current step: [RB][Np] +-1.0f (FORM 0) or +-1 int8
     extern __shared__ __align__(16) unsigned char sRaw[];
     float* sSf = reinterpret_cast<float*>(sRaw);
     int8_t* sS8 = reinterpret_cast<int8_t*>(sRaw);
     int8_t* sJ8 = reinterpret_cast<int8_t*>(sRaw + valu_jl_offset(RB, a.Np));
-    __shared__ int64_t sPart[RB][4];
+    __shared__ int64_t sPart[RB][VT / 64];
     __shared__ int64_t sBest[RB];
     __shared__ int sImp[RB];
     // accept/reject bookkeeping (MH only)
     __shared__ int64_t mEs[RB], mQ0[RB], mEl[RB];
-    __shared__ long long mPart[RB][4];
+    __shared__ long long mPart[RB][VT / 64];
     __shared__ float mLam[RB];
     __shared__ int mOut[RB], mAcc[RB], mDec[RB];
     constexpr bool mh = MH;
@@ -187,7 +192,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
     int hc[CPT];
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const int i = tid + kVT * c;
+        const int i = tid + VT * c;
         hc[c] = (i < Np) ? a.h[i] : 0;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
@@ -200,7 +205,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
         const uint4* src = static_cast<const uint4*>(a.J);
         uint4* dst = reinterpret_cast<uint4*>(sJ8);
         const int n16 = Np * Np / 16;
-        for (int u = tid; u < n16; u += kVT) dst[u] = src[u];
+        for (int u = tid; u < n16; u += VT) dst[u] = src[u];
     }
     int64_t bstep = -1;
     if (tid < RB) {
@@ -238,23 +243,23 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
     // J.s of the spins in LDS (no field yet)
     auto js = [&](int (&I)[RB][CPT]) {
         if constexpr (FORM == 0) {
-            dot_f32<CPT, RB>(static_cast<const float*>(a.J), sSf, N, Np, tid, I);
+            dot_f32<CPT, RB, VT>(static_cast<const float*>(a.J), sSf, N, Np, tid, I);
         } else {
 #pragma unroll
             for (int r = 0; r < RB; ++r)
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) I[r][c] = 0;
             if constexpr (FORM == 1)
-                dot_i8<CPT, RB>(JL ? sJ8 : static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
+                dot_i8<CPT, RB, VT>(JL ? sJ8 : static_cast<const int8_t*>(a.J), sS8, Np, tid, I);
             else
-                dot_ell<CPT, RB>(static_cast<const int32_t*>(a.J), sS8, Np, a.ell_d, tid, I);
+                dot_ell<CPT, RB, VT>(static_cast<const int32_t*>(a.J), sS8, Np, a.ell_d, tid, I);
         }
     };
     // spins of the current x into LDS
     auto put_spins = [&]() {
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
-            const int i = tid + kVT * c;
+            const int i = tid + VT * c;
 #pragma unroll
             for (int r = 0; r < RB; ++r) {
                 const bool pos = x[r][c] >= 0.0f;
@@ -295,7 +300,9 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
                     const int64_t gq = rb0 + tid;
                     int out = 1;
                     if (gq < a.R) {
-                        const int64_t qe = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
+                        int64_t qe = 0;
+#pragma unroll
+                        for (int w = 0; w < VT / 64; ++w) qe += mPart[tid][w];
                         out = mh_outcome(a.seed, static_cast<uint64_t>(a.r_base + gq), k / a.L - 1, mEs[tid],
                                          mEl[tid], qe - mQ0[tid], a.btab[k - 1], mLam[tid], a.sigma);
                         if (out != 0) mEs[tid] = mEl[tid];
@@ -314,7 +321,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
                     if (mOut[r] == 0 && rb0 + r < a.R)
 #pragma unroll
                         for (int c = 0; c < CPT; ++c) {
-                            const int i = tid + kVT * c;
+                            const int i = tid + VT * c;
                             if (i < Np) x[r][c] = a.x0[(rb0 + r) * Np + i];
                         }
                 }
@@ -322,7 +329,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
             const uint64_t rnd = static_cast<uint64_t>(k / a.L);
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-                const int i = tid + kVT * c;
+                const int i = tid + VT * c;
 #pragma unroll
                 for (int r = 0; r < RB; ++r)
                     v[r][c] = (i < N && rb0 + r < a.R) ? gauss_v(a.seed, a.r_base + rb0 + r, rnd, i) : 0.0f;
@@ -332,7 +339,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
                 // into mQ0 after the next barrier).
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
-                    const int i = tid + kVT * c;
+                    const int i = tid + VT * c;
 #pragma unroll
                     for (int r = 0; r < RB; ++r)
                         if (rb0 + r < a.R && i < Np) a.x0[(rb0 + r) * Np + i] = x[r][c];
@@ -374,7 +381,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
             part[r] = 0;
 #pragma unroll
             for (int c = 0; c < CPT; ++c) {
-                const int i = tid + kVT * c;
+                const int i = tid + VT * c;
                 I[r][c] += hc[c];
                 const int s = (x[r][c] >= 0.0f) ? 1 : -1;
                 if (i < N) part[r] += s * (I[r][c] + hc[c]);
@@ -384,11 +391,18 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
         }
         __syncthreads();
         if (tid < RB) {
-            const int64_t tot = sPart[tid][0] + sPart[tid][1] + sPart[tid][2] + sPart[tid][3];
+            int64_t tot = 0;
+#pragma unroll
+            for (int w = 0; w < VT / 64; ++w) tot += sPart[tid][w];
             const int64_t E = -(tot / 2);
             if (mh) {
                 mEl[tid] = E;
-                if (k % a.L == 0) mQ0[tid] = mPart[tid][0] + mPart[tid][1] + mPart[tid][2] + mPart[tid][3];
+                if (k % a.L == 0) {
+                    int64_t q0 = 0;
+#pragma unroll
+                    for (int w = 0; w < VT / 64; ++w) q0 += mPart[tid][w];
+                    mQ0[tid] = q0;
+                }
             }
             const bool ok = rb0 + tid < a.R;
             if (ok && a.etrace) a.etrace[(rb0 + tid) * a.T + k] = E;
@@ -406,7 +420,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
             if (sImp[r]) {
 #pragma unroll
                 for (int c = 0; c < CPT; ++c) {
-                    const int i = tid + kVT * c;
+                    const int i = tid + VT * c;
                     if (i < N) a.bestS[(rb0 + r) * Np + i] = (x[r][c] >= 0.0f) ? 1 : -1;
                 }
             }
@@ -417,7 +431,7 @@ __global__ void __launch_bounds__(kVT) k_sweep_valu(SweepArgs a)
 
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
-        const int i = tid + kVT * c;
+        const int i = tid + VT * c;
 #pragma unroll
         for (int r = 0; r < RB; ++r) {
             if (rb0 + r < a.R && i < Np) {
@@ -446,7 +460,8 @@ namespace {
 template <int FORM, int CPT, int RB, bool MH, bool JL>
 hipError_t launch_valu_cpt(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    const auto kern = k_sweep_valu<FORM, CPT, RB, MH, JL>;
+    constexpr int VT = valu_threads(FORM);
+    const auto kern = k_sweep_valu<FORM, CPT, RB, MH, JL, VT>;
     // dynamic LDS above the default limit must be allowed per kernel
     if (lds > 64 * 1024) {
         const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kern),
@@ -454,19 +469,23 @@ hipError_t launch_valu_cpt(const SweepArgs& a, size_t lds, hipStream_t st)
         if (e != hipSuccess) return e;
     }
     const unsigned blocks = static_cast<unsigned>((a.R + RB - 1) / RB);
-    hipLaunchKernelGGL(kern, dim3(blocks), dim3(kVT), lds, st, a);
+    hipLaunchKernelGGL(kern, dim3(blocks), dim3(VT), lds, st, a);
     return hipGetLastError();
 }
 
 template <int FORM, int RB, bool MH, bool JL>
 hipError_t launch_valu_t(const SweepArgs& a, hipStream_t st)
 {
-    const int cpt = (a.Np + kVT - 1) / kVT;
+    constexpr int VT = valu_threads(FORM);
+    const int cpt = (a.Np + VT - 1) / VT;
     const size_t lds = valu_lds_bytes(FORM, RB, a.Np, JL);
     if (cpt <= 1) return launch_valu_cpt<FORM, 1, RB, MH, JL>(a, lds, st);
     if (cpt <= 2) return launch_valu_cpt<FORM, 2, RB, MH, JL>(a, lds, st);
     if constexpr (JL) {
         return hipErrorInvalidValue;  // J in LDS: Np <= 384
+    } else if constexpr (VT > kVT) {
+        if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL>(a, lds, st);
+        return hipErrorInvalidValue;  // Np <= 4096
     } else {
         if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL>(a, lds, st);
         if (cpt <= 8) return launch_valu_cpt<FORM, 8, RB, MH, JL>(a, lds, st);
