@@ -575,7 +575,7 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
         fixed = max(t1 - calib * per_step, 0.0)
         steps = int(max(calib, min(T, (budget - fixed) / per_step)))
         if steps >= T:
-            reps = max(reps, min(max(R, reps), reps * int((budget - fixed) / (T * per_step))))
+            reps = max(reps, min(max(R, reps), reps * int(round((budget - fixed) / (T * per_step)))))
         dt = run_all(steps, reps, nthr)
         return total_n * reps * steps / dt, reps, steps, dt
 
