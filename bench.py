@@ -547,9 +547,9 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
     """Oracle timing on a subset of a workload's instances: every sampled
     instance runs `threads` replicas (OpenMP over replicas; more, up to R,
     when the whole schedule fits) for the same number of steps of its
-    schedule, sized so that the sample takes about budget_s.  Spin-updates/s of the sample = sum N x replicas x steps / time.
-    A shorter run of one replica per instance on one thread gives the
-    single-thread rate."""
+    schedule, sized so that the sample takes about budget_s.  Spin-updates/s
+    of the sample = sum N x replicas x steps / time.  A shorter run of one
+    replica per instance on one thread gives the single-thread rate."""
     O, flags = oracle_for_host()
     cpu = host_cpu()
     threads = cpu["threads"]
