@@ -5,10 +5,12 @@
 // fits the memory budget next to the requests already running; its replica
 // state then stays resident until it retires.  The service thread runs
 // scheduling rounds: each round advances every running request by one chunk
-// of steps -- all running instances with N <= 512 in one batched launch
-// (16-replica work items), larger ones each in their own column-split
-// launch, all on one stream -- then reads every request's best energy with
-// one synchronisation.  A request retires when its best energy reaches its
+// of steps -- the column-split instances packed into one cooperative launch
+// that has the device to itself (its workgroups wait for each other), then
+// all running instances with N <= 512 in one batched launch on the service
+// stream, overlapped with the VALU sweeps (ELL, FP32, few replicas), whose
+// own launches go round-robin to three more streams -- then reads every
+// request's best energy with one synchronisation.  A request retires when its best energy reaches its
 // target or its step budget is used up; its result (energy, replica, steps,
 // best state, timestamps) is kept for the caller and its device state is
 // released, which may admit waiting requests at the next round.  Requests
@@ -27,6 +29,7 @@
 #include <thread>
 #include <tuple>
 #include <unordered_map>
+#include <utility>
 #include <vector>
 
 #include "phia.h"
@@ -70,6 +73,10 @@ struct phia_server {
     int64_t chunk = 1000;
     int dev = 0;
     hipStream_t st = nullptr;
+    static constexpr int kAux = 3;  // streams for the VALU sweeps' own launches (default priority)
+    hipStream_t aux[kAux] = {};
+    hipEvent_t ev_split = nullptr;      // the cooperative launch of a round has ended
+    hipEvent_t ev_aux[kAux] = {};       // an auxiliary stream's launches of a round have ended
     int64_t* host_res = nullptr;  // pinned: [2 * max_slots] (energy, replica)
     SweepArgs* dtab = nullptr;  // work table of the batched small instances
     size_t dtab_cap = 0;
@@ -119,6 +126,7 @@ void round_once(phia_server* s, std::vector<Request*>& run)
     const int n = static_cast<int>(run.size());
     std::vector<phia_problem*> small, split;
     std::vector<int64_t> small_end, split_end;
+    std::vector<std::pair<Request*, int64_t>> solo;  // VALU sweeps (normal launches of their own)
     hipError_t e = hipSuccess;
     for (Request* r : run) {
         phia_problem* p = r->p;
@@ -131,18 +139,44 @@ void round_once(phia_server* s, std::vector<Request*>& run)
             split.push_back(p);
             split_end.push_back(k_end);
         } else if (k_end > p->k) {
-            if (phia_anneal_run(p, k_end) != PHIA_OK) r->failed = true;
+            if (p->geo.kind == 4)
+                solo.push_back({r, k_end});
+            else if (phia_anneal_run(p, k_end) != PHIA_OK)
+                r->failed = true;
         }
     }
-    if (!small.empty() && launch_batch_chunk(small.data(), static_cast<int>(small.size()), small_end.data(), s->st,
-                                             s->dtab, s->dtab_cap) != PHIA_OK)
-        for (Request* r : run)
-            if (std::find(small.begin(), small.end(), r->p) != small.end()) r->failed = true;
-    // Column-split instances: several per cooperative launch.
+    // Column-split instances: several per cooperative launch, with nothing
+    // else on the device (the launches below wait for it).
     if (!split.empty() && launch_group_chunk(split.data(), static_cast<int>(split.size()), split_end.data(), s->st,
                                              s->gtab, s->gtab_cap) != PHIA_OK)
         for (Request* r : run)
             if (std::find(split.begin(), split.end(), r->p) != split.end()) r->failed = true;
+    // The VALU sweeps' launches on the auxiliary streams, after it.
+    const int na = std::min<int>(phia_server::kAux, static_cast<int>(solo.size()));
+    bool aux_ok = na == 0 || hipEventRecord(s->ev_split, s->st) == hipSuccess;
+    for (int k = 0; aux_ok && k < na; ++k) aux_ok = hipStreamWaitEvent(s->aux[k], s->ev_split, 0) == hipSuccess;
+    for (size_t i = 0; i < solo.size(); ++i) {
+        Request* r = solo[i].first;
+        if (!aux_ok) {
+            r->failed = true;
+            continue;
+        }
+        r->p->st = s->aux[i % na];
+        if (phia_anneal_run(r->p, solo[i].second) != PHIA_OK) r->failed = true;
+        r->p->st = s->st;
+    }
+    // The batched small instances on the service stream, beside them.
+    if (!small.empty() && launch_batch_chunk(small.data(), static_cast<int>(small.size()), small_end.data(), s->st,
+                                             s->dtab, s->dtab_cap) != PHIA_OK)
+        for (Request* r : run)
+            if (std::find(small.begin(), small.end(), r->p) != small.end()) r->failed = true;
+    // The service stream waits for the auxiliary ones before the argmins.
+    for (int k = 0; k < na; ++k)
+        if (hipEventRecord(s->ev_aux[k], s->aux[k]) != hipSuccess ||
+            hipStreamWaitEvent(s->st, s->ev_aux[k], 0) != hipSuccess) {
+            for (auto& q : solo) q.first->failed = true;
+            break;
+        }
     for (int i = 0; i < n; ++i) {
         phia_problem* p = run[i]->p;
         if ((e = launch_argmin(p->dbestE, p->R, p->dscratch, s->st)) != hipSuccess ||
@@ -150,7 +184,12 @@ void round_once(phia_server* s, std::vector<Request*>& run)
                                 s->st)) != hipSuccess)
             run[i]->failed = true;
     }
-    if ((e = hipStreamSynchronize(s->st)) != hipSuccess) {
+    e = hipStreamSynchronize(s->st);
+    for (int k = 0; k < na; ++k) {  // complete already, unless an event call above failed
+        const hipError_t ek = hipStreamSynchronize(s->aux[k]);
+        if (e == hipSuccess) e = ek;
+    }
+    if (e != hipSuccess) {
         for (Request* r : run) {
             r->failed = true;
             r->p->poisoned = true;
@@ -169,6 +208,16 @@ void round_once(phia_server* s, std::vector<Request*>& run)
         r->energy = s->host_res[2 * i];
         r->replica = static_cast<int32_t>(s->host_res[2 * i + 1]);
     }
+}
+
+void release_streams(phia_server* s)
+{
+    if (s->st) (void)hipStreamDestroy(s->st);
+    for (int k = 0; k < phia_server::kAux; ++k) {
+        if (s->aux[k]) (void)hipStreamDestroy(s->aux[k]);
+        if (s->ev_aux[k]) (void)hipEventDestroy(s->ev_aux[k]);
+    }
+    if (s->ev_split) (void)hipEventDestroy(s->ev_split);
 }
 
 void service(phia_server* s)
@@ -282,10 +331,16 @@ phia_status phia_server_create(size_t hbm_budget, int32_t max_slots, int32_t chu
     s->chunk = chunk_steps;
     s->dev = device;
     s->t0 = std::chrono::steady_clock::now();
-    if ((e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking)) != hipSuccess ||
-        (e = hipHostMalloc(reinterpret_cast<void**>(&s->host_res), sizeof(int64_t) * 2 * max_slots)) !=
-            hipSuccess) {
-        if (s->st) (void)hipStreamDestroy(s->st);
+    e = hipStreamCreateWithFlags(&s->st, hipStreamNonBlocking);
+    for (int k = 0; e == hipSuccess && k < phia_server::kAux; ++k) {
+        e = hipStreamCreateWithFlags(&s->aux[k], hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_aux[k], hipEventDisableTiming);
+    }
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_split, hipEventDisableTiming);
+    if (e == hipSuccess)
+        e = hipHostMalloc(reinterpret_cast<void**>(&s->host_res), sizeof(int64_t) * 2 * max_slots);
+    if (e != hipSuccess) {
+        release_streams(s);
         delete s;
         return hip_fail(nullptr, e, "server resources");
     }
@@ -424,7 +479,7 @@ void phia_server_destroy(phia_server* s)
     if (s->dtab) (void)hipFree(s->dtab);
     if (s->gtab) (void)hipFree(s->gtab);
     if (s->host_res) (void)hipHostFree(s->host_res);
-    if (s->st) (void)hipStreamDestroy(s->st);
+    release_streams(s);
     delete s;
 }
 

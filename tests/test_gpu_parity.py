@@ -756,6 +756,58 @@ def test_server_result_same_alone_and_in_mix(P, O):
         p.close()
 
 
+def test_server_valu_requests_overlap_same_alone_and_in_mix(P, O):
+    """Requests on the VALU sweeps (ELL, FP32) run their own launches on the
+    server's auxiliary streams, overlapped with each other and with the
+    batched small instances, after the round's cooperative column-split
+    launch: five of them (more than the three streams) in a mix with a
+    batched and a column-split request give the same results as each request
+    served alone."""
+    specs = [  # (N, dense, path, R, T, seed)
+        (700, False, "ell", 32, 600, 1), (300, True, "fp32", 16, 500, 2), (200, False, "ell", 24, 700, 3),
+        (500, False, "ell", 16, 450, 4), (90, True, "fp32", 8, 800, 5), (40, False, "i8", 32, 600, 6),
+        (700, False, "i8", 32, 500, 7),
+    ]
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    inst_list = []
+    for N, dense, path, R, T, seed in specs:
+        J, h, E, _ = inst.planted_loops(N, 300 + seed, alpha=0.4, dense=dense)
+        inst_list.append((J, h, E))
+
+    def serve(idx, slots):
+        srv = P.Server(1 << 36, max_slots=slots, chunk_steps=90)
+        probs, tickets = [], []
+        for i in idx:
+            J, h, E = inst_list[i]
+            N, dense, path, R, T, seed = specs[i]
+            p = P.Problem(J, h, path=path)
+            probs.append(p)
+            tickets.append(srv.submit(p, R, T, E, seed=seed, **sched))
+        res = [srv.wait(t, 120.0) for t in tickets]
+        spins = [srv.spins(t) for t in tickets]
+        kinds = [p.info()["sweep_kernel"] for p in probs]
+        srv.close()
+        for p in probs:
+            p.close()
+        return res, spins, kinds
+
+    alone = [serve([i], 1) for i in range(len(specs))]
+    mix, mix_spins, kinds = serve(list(range(len(specs))), 8)
+    say("sweep kernels", kinds)
+    assert sum(k == 4 for k in kinds) == 5
+    for i in range(len(specs)):
+        r1, s1 = alone[i][0][0], alone[i][1][0]
+        r2, s2 = mix[i], mix_spins[i]
+        say("request", i, specs[i][2], r1, r2)
+        assert r1["state"] == P.REQ_DONE and r2["state"] == P.REQ_DONE
+        for key in ("success", "energy_units", "replica", "steps_used"):
+            assert r1[key] == r2[key], (i, key)
+        assert np.array_equal(s1, s2), i
+        J, h, E = inst_list[i]
+        assert O.energy(J.astype(np.int32), h.astype(np.int32), s2) == r2["energy_units"]
+        assert r2["energy_units"] >= E and r2["success"] == (r2["energy_units"] <= E)
+
+
 def test_server_column_split_requests_share_launches(P, O):
     """Large requests (column-split geometries) of several sizes and replica
     counts run together, several per cooperative launch; with an unreachable
