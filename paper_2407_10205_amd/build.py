@@ -18,7 +18,7 @@ LIB = os.path.join(PKG, "libphia.so")
 OBJDIR = os.path.join(PKG, "_build")
 
 SOURCES = ["phia_kernels.hip", "phia_batch_kernel.hip", "phia_valu_kernel.hip", "phia_runtime.cpp", "phia_batch.cpp",
-           "phia_server.cpp", "phia_noalloc.hip"]
+           "phia_server.cpp", "phia_server_kernels.hip", "phia_noalloc.hip"]
 
 # -ffp-contract=off: no implicit fused multiply-adds (the sweep's op sequence
 # is fixed and every fma is explicit).  Correctly rounded FP32 division and

@@ -95,6 +95,10 @@ hipError_t launch_sweep_valu(int form, int rb, bool jl, const SweepArgs& a, hipS
 hipError_t launch_sweep_mfma(int path, int mt, int cbw, const SweepArgs& a, size_t lds_bytes, hipStream_t st);
 size_t sweep_mfma_lds_bytes(int path, int mt, const SweepArgs& a);
 hipError_t launch_argmin(const int64_t* bestE, int32_t R, int64_t* out2, hipStream_t st);
+// n problems' argmins in one launch (phia_server_kernels.hip): pairs[2 j], pairs[2 j + 1] =
+// (energy, replica) of problem j, errs[j] = *err[j] (0 for a null err[j]).
+hipError_t launch_argmin_many(const int64_t* const* bestE, const int32_t* R, const int32_t* const* err, int n,
+                              int64_t* pairs, int32_t* errs, hipStream_t st);
 hipError_t launch_energy_f64(const double* J, const double* h, int32_t N, const int8_t* s,
                              double* out, hipStream_t st);
 hipError_t launch_fmath_eval(int kind, const float* in, const uint64_t* in64, float* out, int64_t n,

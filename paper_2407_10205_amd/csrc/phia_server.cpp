@@ -77,7 +77,8 @@ struct phia_server {
     hipStream_t aux[kAux] = {};
     hipEvent_t ev_split = nullptr;      // the cooperative launch of a round has ended
     hipEvent_t ev_aux[kAux] = {};       // an auxiliary stream's launches of a round have ended
-    int64_t* host_res = nullptr;  // pinned: [2 * max_slots] (energy, replica)
+    int64_t* host_res = nullptr;  // pinned: [2 n] (energy, replica) of a round's n requests, then [n] int32 error words
+    int64_t* dev_res = nullptr;   // the same on the device, written by one batched argmin per round
     SweepArgs* dtab = nullptr;  // work table of the batched small instances
     size_t dtab_cap = 0;
     SweepArgs* gtab = nullptr;  // work table of the column-split instances
@@ -177,13 +178,23 @@ void round_once(phia_server* s, std::vector<Request*>& run)
             for (auto& q : solo) q.first->failed = true;
             break;
         }
+    // Every request's best (energy, replica) and error word: one launch, one copy.
+    std::vector<const int64_t*> best(n);
+    std::vector<const int32_t*> errw(n);
+    std::vector<int32_t> reps(n);
     for (int i = 0; i < n; ++i) {
-        phia_problem* p = run[i]->p;
-        if ((e = launch_argmin(p->dbestE, p->R, p->dscratch, s->st)) != hipSuccess ||
-            (e = hipMemcpyAsync(s->host_res + 2 * i, p->dscratch, 2 * sizeof(int64_t), hipMemcpyDeviceToHost,
-                                s->st)) != hipSuccess)
-            run[i]->failed = true;
+        const phia_problem* p = run[i]->p;
+        best[i] = p->dbestE;
+        reps[i] = p->R;
+        errw[i] = p->geo.G > 1 ? p->derr : nullptr;
     }
+    int32_t* dev_err = reinterpret_cast<int32_t*>(s->dev_res + 2 * n);
+    const size_t res_bytes = sizeof(int64_t) * 2 * n + sizeof(int32_t) * n;
+    if (n > 0 && ((e = launch_argmin_many(best.data(), reps.data(), errw.data(), n, s->dev_res, dev_err, s->st)) !=
+                      hipSuccess ||
+                  (e = hipMemcpyAsync(s->host_res, s->dev_res, res_bytes, hipMemcpyDeviceToHost, s->st)) !=
+                      hipSuccess))
+        for (Request* r : run) r->failed = true;
     e = hipStreamSynchronize(s->st);
     for (int k = 0; k < na; ++k) {  // complete already, unless an event call above failed
         const hipError_t ek = hipStreamSynchronize(s->aux[k]);
@@ -196,11 +207,11 @@ void round_once(phia_server* s, std::vector<Request*>& run)
         }
         return;
     }
+    const int32_t* host_err = reinterpret_cast<const int32_t*>(s->host_res + 2 * n);
     for (int i = 0; i < n; ++i) {
         Request* r = run[i];
         if (r->failed) continue;
-        int32_t err = 0;
-        if (r->p->geo.G > 1 && hipMemcpy(&err, r->p->derr, sizeof err, hipMemcpyDeviceToHost) == hipSuccess && err) {
+        if (host_err[i] != 0) {
             r->failed = true;
             r->p->poisoned = true;
             continue;
@@ -337,9 +348,11 @@ phia_status phia_server_create(size_t hbm_budget, int32_t max_slots, int32_t chu
         if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_aux[k], hipEventDisableTiming);
     }
     if (e == hipSuccess) e = hipEventCreateWithFlags(&s->ev_split, hipEventDisableTiming);
-    if (e == hipSuccess)
-        e = hipHostMalloc(reinterpret_cast<void**>(&s->host_res), sizeof(int64_t) * 2 * max_slots);
+    const size_t res_bytes = sizeof(int64_t) * 2 * max_slots + sizeof(int32_t) * max_slots;
+    if (e == hipSuccess) e = hipHostMalloc(reinterpret_cast<void**>(&s->host_res), res_bytes);
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(&s->dev_res), res_bytes);
     if (e != hipSuccess) {
+        if (s->host_res) (void)hipHostFree(s->host_res);
         release_streams(s);
         delete s;
         return hip_fail(nullptr, e, "server resources");
@@ -479,6 +492,7 @@ void phia_server_destroy(phia_server* s)
     if (s->dtab) (void)hipFree(s->dtab);
     if (s->gtab) (void)hipFree(s->gtab);
     if (s->host_res) (void)hipHostFree(s->host_res);
+    if (s->dev_res) (void)hipFree(s->dev_res);
     release_streams(s);
     delete s;
 }
