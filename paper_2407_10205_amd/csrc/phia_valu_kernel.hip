@@ -1,10 +1,10 @@
 // VALU sweeps of the PHIA library for gfx950 (k_sweep_valu).
 //
-// A workgroup of VT threads (256; 1024 for FORM 0) owns RB replicas and all
-// of their columns for the whole launch: thread t keeps x and v of columns
-// i = t + VT c (c < CPT) of every replica in registers, the spins of the
-// current step go to LDS, and J.s + h (Eq. 6) runs on the vector ALUs in one
-// of three forms:
+// A workgroup of VT threads (256; 1024 for FORM 0 above Np = 256) owns RB
+// replicas and all of their columns for the whole launch: thread t keeps x
+// and v of columns i = t + VT c (c < CPT) of every replica in registers, the
+// spins of the current step go to LDS, and J.s + h (Eq. 6) runs on the vector
+// ALUs in one of three forms:
 //
 //   FORM 0 (FP32 path): FP32 couplings [Np][Np] row-major, one FMA per
 //          coupling against spins stored as +-1.0f.  The plain sweep.
@@ -40,10 +40,11 @@ namespace phia {
 namespace {
 
 constexpr int kVT = 256;  // threads per workgroup of the int8 and ELL forms
-// The FP32 form takes 1024 threads (one column each up to Np = 1024): its
-// product is one FMA per coupling and replica, issue-bound, and four waves
-// per SIMD hide the L2 latency of its coupling rows.
-constexpr int valu_threads(int form) { return form == kValuFp32 ? 1024 : kVT; }
+// The FP32 form takes 1024 threads above Np = 256 (one column each up to
+// Np = 1024): its product is one FMA per coupling and replica, issue-bound,
+// and four waves per SIMD hide the L2 latency of its coupling rows.  Up to
+// Np = 256 one column per thread needs only 256.
+constexpr int kVtFp32 = 1024;
 
 // J.s of this thread's columns for every replica of the block (FORM 1):
 // fragments [Np/16][Np/64][64][16], lane l of fragment (cb, kb) holding
@@ -457,10 +458,9 @@ __global__ void __launch_bounds__(VT) k_sweep_valu(SweepArgs a)
 
 namespace {
 
-template <int FORM, int CPT, int RB, bool MH, bool JL>
+template <int FORM, int CPT, int RB, bool MH, bool JL, int VT = kVT>
 hipError_t launch_valu_cpt(const SweepArgs& a, size_t lds, hipStream_t st)
 {
-    constexpr int VT = valu_threads(FORM);
     const auto kern = k_sweep_valu<FORM, CPT, RB, MH, JL, VT>;
     // dynamic LDS above the default limit must be allowed per kernel
     if (lds > 64 * 1024) {
@@ -476,16 +476,20 @@ hipError_t launch_valu_cpt(const SweepArgs& a, size_t lds, hipStream_t st)
 template <int FORM, int RB, bool MH, bool JL>
 hipError_t launch_valu_t(const SweepArgs& a, hipStream_t st)
 {
-    constexpr int VT = valu_threads(FORM);
-    const int cpt = (a.Np + VT - 1) / VT;
     const size_t lds = valu_lds_bytes(FORM, RB, a.Np, JL);
+    if constexpr (FORM == kValuFp32) {
+        if (a.Np <= kVT) return launch_valu_cpt<FORM, 1, RB, MH, JL>(a, lds, st);
+        const int cpt = (a.Np + kVtFp32 - 1) / kVtFp32;
+        if (cpt <= 1) return launch_valu_cpt<FORM, 1, RB, MH, JL, kVtFp32>(a, lds, st);
+        if (cpt <= 2) return launch_valu_cpt<FORM, 2, RB, MH, JL, kVtFp32>(a, lds, st);
+        if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL, kVtFp32>(a, lds, st);
+        return hipErrorInvalidValue;  // Np <= 4096
+    }
+    const int cpt = (a.Np + kVT - 1) / kVT;
     if (cpt <= 1) return launch_valu_cpt<FORM, 1, RB, MH, JL>(a, lds, st);
     if (cpt <= 2) return launch_valu_cpt<FORM, 2, RB, MH, JL>(a, lds, st);
     if constexpr (JL) {
         return hipErrorInvalidValue;  // J in LDS: Np <= 384
-    } else if constexpr (VT > kVT) {
-        if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL>(a, lds, st);
-        return hipErrorInvalidValue;  // Np <= 4096
     } else {
         if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL>(a, lds, st);
         if (cpt <= 8) return launch_valu_cpt<FORM, 8, RB, MH, JL>(a, lds, st);
