@@ -51,7 +51,7 @@ typedef enum {
  * same exact integer field, so results are identical across paths. */
 typedef enum {
     PHIA_PATH_AUTO = 0,     /* I8 if |J| <= 127 units, else BF16HILO, else FP32; ELL
-                               for sparse rows with 512 < Np <= 4096 (at most Np/192
+                               for sparse rows with 512 < Np <= 4096 (at most Np/64
                                nonzeros in every row)                                */
     PHIA_PATH_FP32 = 1,     /* FP32 couplings, VALU dot products (plain sweep)       */
     PHIA_PATH_I8 = 2,       /* int8 couplings, int8 MFMA with int32 accumulation;

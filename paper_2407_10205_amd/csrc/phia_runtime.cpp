@@ -422,7 +422,10 @@ int valu_crossover(int Np)
 
 // Replicas per workgroup of the int8 VALU sweep and of the ELL sweep.
 static int valu_rows(int R) { return R > 1024 ? 2 : 1; }
-static int ell_rows(int) { return 1; }
+// ELL: one replica per workgroup, four from 1024 replicas (3-regular N = 512
+// with 1024 replicas: 3.1 against 5.7 us per step; 64 replicas at N = 4000:
+// 7.9 against 3.4 us)
+static int ell_rows(int R) { return R >= 1024 ? 4 : 1; }
 
 // VALU sweep (k_sweep_valu): rb replicas and all columns per workgroup; the
 // form follows the path (FP32, ELL, or the int8 dot products of the I8 path).
@@ -814,11 +817,13 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     if (path == PHIA_PATH_AUTO) path = i8_ok ? PHIA_PATH_I8 : bf_ok ? PHIA_PATH_BF16HILO : PHIA_PATH_FP32;
     {
         // Sparse rows beyond the batch sweep's sizes: ELL when the densest
-        // row has at most Np / 192 nonzeros (measured on MI355X: 3-regular
-        // rows take 2.1 against 3.7 us per step at N = 1000 and 8.5 against
-        // 13.8 us at N = 4000; ELL loses from about Np / 100 nonzeros).
+        // row has at most Np / 64 nonzeros (measured on MI355X, 16 and 256
+        // replicas: ELL ties the int8 matrix cores at 16-18 nonzeros for
+        // N = 1000, 32-41 for N = 2000, 52 and more for N = 4000; 3-regular
+        // rows take 1.6 against 2.5 us per step at N = 1000 and 3.4 against
+        // 14 us at N = 4000).
         const int Np = (N + 63) / 64 * 64;
-        if (o.path == PHIA_PATH_AUTO && bf_ok && Np > kBatchFp4MaxNp && Np <= kValuMaxNp && maxdeg <= Np / 192)
+        if (o.path == PHIA_PATH_AUTO && bf_ok && Np > kBatchFp4MaxNp && Np <= kValuMaxNp && maxdeg <= Np / 64)
             path = PHIA_PATH_ELL;
     }
     if (path == PHIA_PATH_I8 && !i8_ok) return fail(PHIA_ERANGE, "couplings outside int8 for the I8 path");

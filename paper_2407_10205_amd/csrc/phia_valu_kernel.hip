@@ -1,10 +1,10 @@
 // VALU sweeps of the PHIA library for gfx950 (k_sweep_valu).
 //
-// A workgroup of VT threads (256; 1024 for FORM 0 above Np = 256) owns RB
-// replicas and all of their columns for the whole launch: thread t keeps x
-// and v of columns i = t + VT c (c < CPT) of every replica in registers, the
-// spins of the current step go to LDS, and J.s + h (Eq. 6) runs on the vector
-// ALUs in one of three forms:
+// A workgroup of VT threads (256; 1024 for FORMs 0 and 2 above Np = 256)
+// owns RB replicas and all of their columns for the whole launch: thread t
+// keeps x and v of columns i = t + VT c (c < CPT) of every replica in
+// registers, the spins of the current step go to LDS, and J.s + h (Eq. 6)
+// runs on the vector ALUs in one of three forms:
 //
 //   FORM 0 (FP32 path): FP32 couplings [Np][Np] row-major, one FMA per
 //          coupling against spins stored as +-1.0f.  The plain sweep.
@@ -40,11 +40,12 @@ namespace phia {
 namespace {
 
 constexpr int kVT = 256;  // threads per workgroup of the int8 and ELL forms
-// The FP32 form takes 1024 threads above Np = 256 (one column each up to
-// Np = 1024): its product is one FMA per coupling and replica, issue-bound,
-// and four waves per SIMD hide the L2 latency of its coupling rows.  Up to
-// Np = 256 one column per thread needs only 256.
-constexpr int kVtFp32 = 1024;
+// The FP32 and ELL forms take 1024 threads above Np = 256 (one column each
+// up to Np = 1024): four waves per SIMD hide the latency of their coupling
+// rows (L2) and spin gathers (LDS), where one wave per SIMD with up to 16
+// columns per thread waits on them.  Up to Np = 256 one column per thread
+// needs only 256.
+constexpr int kVtWide = 1024;
 
 // J.s of this thread's columns for every replica of the block (FORM 1):
 // fragments [Np/16][Np/64][64][16], lane l of fragment (cb, kb) holding
@@ -477,12 +478,12 @@ template <int FORM, int RB, bool MH, bool JL>
 hipError_t launch_valu_t(const SweepArgs& a, hipStream_t st)
 {
     const size_t lds = valu_lds_bytes(FORM, RB, a.Np, JL);
-    if constexpr (FORM == kValuFp32) {
+    if constexpr (FORM == kValuFp32 || FORM == kValuEll) {
         if (a.Np <= kVT) return launch_valu_cpt<FORM, 1, RB, MH, JL>(a, lds, st);
-        const int cpt = (a.Np + kVtFp32 - 1) / kVtFp32;
-        if (cpt <= 1) return launch_valu_cpt<FORM, 1, RB, MH, JL, kVtFp32>(a, lds, st);
-        if (cpt <= 2) return launch_valu_cpt<FORM, 2, RB, MH, JL, kVtFp32>(a, lds, st);
-        if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL, kVtFp32>(a, lds, st);
+        const int cpt = (a.Np + kVtWide - 1) / kVtWide;
+        if (cpt <= 1) return launch_valu_cpt<FORM, 1, RB, MH, JL, kVtWide>(a, lds, st);
+        if (cpt <= 2) return launch_valu_cpt<FORM, 2, RB, MH, JL, kVtWide>(a, lds, st);
+        if (cpt <= 4) return launch_valu_cpt<FORM, 4, RB, MH, JL, kVtWide>(a, lds, st);
         return hipErrorInvalidValue;  // Np <= 4096
     }
     const int cpt = (a.Np + kVT - 1) / kVT;
