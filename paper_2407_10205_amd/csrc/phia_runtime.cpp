@@ -831,8 +831,8 @@ phia_status phia_create(const double* J, const double* h, int32_t N, const phia_
     if (path == PHIA_PATH_FP32 && !f32_ok) return fail(PHIA_ERANGE, "row sums exceed 2^24 for the FP32 path");
     if (path == PHIA_PATH_ELL && !bf_ok) return fail(PHIA_ERANGE, "couplings outside 16 bits for the ELL path");
     {
-        // Largest instance each sweep holds: the FP32 sweep keeps up to 16
-        // columns per thread (Np <= 4096); the matrix-core sweeps stage two
+        // Largest instance each sweep holds: the FP32 and ELL sweeps keep up
+        // to 4 columns per thread of 1024 (Np <= 4096); the matrix-core sweeps stage two
         // spin rows of every replica in LDS, so even the thinnest column
         // slice needs 32 Np bytes per operand byte there.
         const int Np = (N + 63) / 64 * 64;
