@@ -90,3 +90,28 @@ def test_tts99_definition():
     assert bench.tts99(2.0, 0.5, 100) == 2.0
     p = 1 - (1 - 0.001) ** 64
     assert abs(bench.tts99(1.0, 0.001, 64) - math.log(0.01) / math.log(1 - p)) < 1e-12
+
+
+def test_cpu_baseline_fields():
+    """The benchmark's CPU leg (the oracle timed on the host) reports the
+    fields its result line carries: a positive rate, the thread count it
+    used, kind "oracle", the sample it timed, the single-thread rate and the
+    host CPU; the sample grows its replica count (up to the workload's) when
+    the whole schedule fits the budget."""
+    import bench
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    insts = [inst.sk_pm1(24, 1), inst.regular3_pm1(30, 2)]
+    r = bench.cpu_baseline_instances(insts, 64, 40, sched, 0.5, "two instances")
+    cores = bench.host_cpu()["threads"]
+    assert r["kind"] == "oracle" and r["unit"] == "spin-updates/s" and r["cores"] == cores
+    assert r["value"] > 0 and r["single_thread"]["value"] > 0
+    assert "steps 0..39" in r["sample"] and "two instances" in r["sample"]
+    reps = int(r["sample"].split("replicas 0..")[1].split(",")[0]) + 1
+    assert reps >= cores and reps % cores == 0 and reps <= max(64, cores)
+    for key in ("cpu_model", "nproc", "cpus_allowed"):
+        assert key in r
+    J, h = inst.sk_pm1(20, 3)
+    w = dict(R=8, T=30, sched=dict(sched))
+    r = bench.cpu_baseline(J, h, w, 0.3)
+    assert r["kind"] == "oracle" and r["value"] > 0 and r["single_thread"]["value"] > 0
+    assert "steps 0..29" in r["sample"] and r["cores"] == cores
