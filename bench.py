@@ -624,7 +624,7 @@ def main():
     ap.add_argument("--requests", type=int, default=1000, help="serving workload: number of requests")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="serving workload: device memory budget")
     ap.add_argument("--slots", type=int, default=64, help="serving workload: concurrent requests")
-    ap.add_argument("--chunk", type=int, default=250, help="serving workload: steps per scheduling round")
+    ap.add_argument("--chunk", type=int, default=100, help="serving workload: steps per scheduling round")
     args = ap.parse_args()
     if args.summarize_profiles:
         kern = args.profile_kernel or ("k_batch_fp4" if args.workload == "batch4096" else "k_sweep")
