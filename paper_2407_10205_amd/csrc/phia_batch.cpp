@@ -233,6 +233,11 @@ phia_status launch_group_chunk(phia_problem* const* probs, int count, const int6
     }
     for (size_t li = 0; li < launches.size(); ++li) {
         const Launch& L = launches[li];
+        // test hook, as in phia_anneal_run: the error word raised before the
+        // launch, as if another workgroup had given up
+        for (int i : L.members)
+            if (probs[i]->give_up && (e = hipMemsetAsync(probs[i]->derr, 0x02, 1, st)) != hipSuccess)
+                return hip_fail(probs[i], e, "error word");
         if ((e = launch_sweep_group_table(L.path, L.mt, L.cbw, L.mh, dtab + offs[li], L.nwg, L.lds, st)) !=
             hipSuccess)
             return hip_fail(nullptr, e, "group table launch");

@@ -142,3 +142,53 @@ def test_wait_that_gives_up_poisons_the_handle(P, O, spec):
     o = O.anneal(J.astype(np.int32), h.astype(np.int32), 0, 1, O.beta_linear(SCHED["beta0"], SCHED["beta1"], 40),
                  0.2, 1.0, SCHED["refresh_L"], 3, r0=63)
     assert E[63] == o.bestE[0] and np.array_equal(S[63], o.bestS[0])
+
+
+def test_served_request_whose_wait_gives_up_fails_alone(P, O):
+    """A served column-split request whose device error word is raised from
+    the host (as if one of its workgroups' bounded waits had given up) runs in
+    the same cooperative table launch as another column-split request: the
+    round's batched read-out reports its error word, the request ends
+    FAILED, and the other requests (one column-split, one batched) give the
+    same results as when served without it."""
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    specs = []
+    for i, (N, dense, R, T) in enumerate([(700, False, 32, 400), (650, False, 32, 400), (60, True, 32, 400)]):
+        J, h, E, _ = inst.planted_loops(N, 400 + i, alpha=0.4, dense=dense)
+        specs.append((J, h, E, R, T, 30 + i))
+
+    def serve(raise_first):
+        srv = P.Server(1 << 36, max_slots=8, chunk_steps=100)
+        probs, tickets = [], []
+        for k, (J, h, E, R, T, seed) in enumerate(specs):
+            if k == 0 and not raise_first:
+                continue
+            p = P.Problem(J, h, path="i8")
+            if k == 0:
+                p.raise_error_word()
+            probs.append(p)
+            tickets.append(srv.submit(p, R, T, E, seed=seed, **sched))
+        res = [srv.wait(t, 120.0) for t in tickets]
+        spins = [srv.spins(t) if r["state"] == P.REQ_DONE else None for t, r in zip(tickets, res)]
+        kinds = []
+        for p in probs:  # the failed request's problem is poisoned
+            try:
+                i = p.info()
+                kinds.append((i["sweep_kernel"], i["group"]))
+            except P.PhiaError as e:
+                kinds.append(e.code)
+        srv.close()
+        for p in probs:
+            p.close()
+        return res, spins, kinds
+
+    res, spins, kinds = serve(True)
+    say("raised", res[0], "geometries", kinds)
+    # only column-split requests carry an error word into the read-out
+    assert res[0]["state"] == P.REQ_FAILED and kinds[1][0] == 0 and kinds[1][1] > 1
+    ref, ref_spins, _ = serve(False)
+    for r1, s1, r2, s2 in zip(res[1:], spins[1:], ref, ref_spins):
+        assert r1["state"] == P.REQ_DONE and r2["state"] == P.REQ_DONE
+        for key in ("success", "energy_units", "replica", "steps_used"):
+            assert r1[key] == r2[key], key
+        assert np.array_equal(s1, s2)
