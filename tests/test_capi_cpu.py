@@ -94,3 +94,25 @@ def test_size_limits_per_path(phia, path, N):
     assert _code(phia, J, path=path) == -4
     code = _code(phia, J[:N, :N].copy(), path=path)
     assert code != -4
+
+
+def test_product_and_oracle_share_no_code():
+    """The HIP path and the CPU oracle are independent: no source of the
+    package (kernels, runtime, binding) refers to the oracle, and the oracle
+    includes no header of the package nor imports its binding."""
+    pkg = os.path.join(ROOT, "paper_2407_10205_amd")
+    for d, _, files in os.walk(pkg):
+        if "_build" in d or "__pycache__" in d:
+            continue
+        for f in files:
+            if f.endswith((".py", ".hip", ".cpp", ".h")):
+                assert "oracle" not in open(os.path.join(d, f)).read().lower(), os.path.join(d, f)
+    assert "oracle" not in open(HEADER).read().lower()
+    odir = os.path.join(ROOT, "oracle")
+    for f in os.listdir(odir):
+        if f.endswith((".c", ".h")):
+            incs = re.findall(r'#include\s+[<"]([^>"]+)[>"]', open(os.path.join(odir, f)).read())
+            assert all(i in ("phia_oracle.h", "math.h", "stdlib.h", "string.h", "stdint.h", "omp.h") for i in incs), (f, incs)
+        if f.endswith(".py"):
+            src = open(os.path.join(odir, f)).read()
+            assert "paper_2407_10205_amd" not in src and "libphia" not in src, f
