@@ -100,6 +100,26 @@ def test_mh_parity_paths(P, O, path):
     assert 0 < dev["acc"].sum() < dev["dec"].sum()
 
 
+@pytest.mark.parametrize("path", ["fp32", "ell"])
+def test_mh_wide_workgroups(P, O, path):
+    """The accept/reject step in the 1024-thread FP32 and ELL workgroups
+    (Np = 640): the kinetic sums over 16 waves, a ragged replica count,
+    every replica against the oracle."""
+    if path == "fp32":
+        J, h = inst.sk_gauss_fixed(600, 4, frac_bits=5, bits=8)
+        f = 5
+    else:
+        J, h = inst.regular3_pm1(600, 4)
+        f = 0
+    R, T, seed, mh = 9, 151, 17, (1.25, 0.8)
+    say(f"mh wide path={path} N=600 R={R} T={T}")
+    dev = device_run(P, J, h, f, path, R, T, RAGGED, seed, mh)
+    assert dev["info"]["path_name"] == path and dev["info"]["sweep_kernel"] == 4
+    runs = oracle_rows(O, J, h, f, T, RAGGED, seed, mh, range(R))
+    assert_parity(dev, runs)
+    assert np.all(dev["dec"] == 5)  # k = 23, ..., 138; the first trajectory is taken undecided
+
+
 def test_mh_off_by_default_and_counts_rejected(P, O):
     J, h = inst.sk_pm1(16, 0)
     p = P.Problem(J, h, path="i8")

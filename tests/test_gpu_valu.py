@@ -113,6 +113,34 @@ def test_ell_largest_n_sampled(P, O):
     assert_parity(dev, runs)
 
 
+@pytest.mark.parametrize("path,kind,N,R,geometry", [
+    ("fp32", "fixed", 700, 7, None), ("fp32", "fixed", 1500, 5, None), ("ell", "reg3", 700, 5, "valu,1"),
+    ("ell", "reg3", 1500, 6, "valu,4"), ("ell", "er16", 1100, 3, None)])
+def test_wide_workgroup_forms_parity(P, O, path, kind, N, R, geometry):
+    """The FP32 and ELL forms in 1024-thread workgroups (Np > 256): one and
+    two columns per thread, ragged replica blocks of four, and uneven 16-bit
+    ELL rows with the POLY2 factor; every replica bit-identical to the
+    oracle."""
+    deriv, f = "tanh", 0
+    if kind == "fixed":
+        J, h = inst.sk_gauss_fixed(N, 11, frac_bits=5, bits=8)
+        f = 5
+    elif kind == "reg3":
+        J, h = inst.regular3_pm1(N, 12)
+    else:
+        rs = np.random.default_rng(13)
+        A = np.triu((rs.random((N, N)) < 0.01) * rs.integers(-2**14, 2**14, (N, N)), 1)
+        J = (A + A.T).astype(np.float64) / 2**9
+        h = rs.integers(-300, 300, N).astype(np.float64) / 2**9
+        f, deriv = 9, "poly2"
+    dev, runs = run_both(P, O, J, h, f, path, R, 61, 21, geometry=geometry, deriv=deriv,
+                         b0=0.01 if f == 9 else 0.1, b1=0.3 if f == 9 else 3.0)
+    assert dev["info"]["path_name"] == path and dev["info"]["sweep_kernel"] == 4
+    if geometry:
+        assert dev["info"]["rows_per_block"] == int(geometry.split(",")[1])
+    assert_parity(dev, runs)
+
+
 def test_ell_matches_other_paths(P):
     """Same instance, same seed: ELL, int8 and FP32 give identical results."""
     J, h = inst.er_maxcut(300, 0.06, 4, signed=True)
