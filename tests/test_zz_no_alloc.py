@@ -68,7 +68,7 @@ def _same(a, b, what):
     assert a["best"] == b["best"], what
 
 
-@pytest.mark.parametrize("path,geometry", [("i8", None), ("fp32", None), ("bf16hilo", None), ("i8", "pp,3"),
+@pytest.mark.parametrize("path,geometry", [("i8", None), ("fp32", None), ("ell", None), ("bf16hilo", None), ("i8", "pp,3"),
                                            ("i8", "pp4,3"), ("i8", "ppg,3"), ("i8", "1,3,1"), ("i8", "1,4,0")])
 def test_noalloc_equals_anneal_twice(P, path, geometry):
     """Two calls in a row, the second with fewer replicas and steps, each
