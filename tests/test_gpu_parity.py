@@ -384,6 +384,44 @@ def test_interleaved_group_sweep_full_parity(P, O):
     assert_parity(dev, runs)
 
 
+@pytest.mark.parametrize("path,geometry", [("i8", None), ("i8", "pp,3"), ("i8", "pp4,3"), ("i8", "ppg,3"),
+                                           ("i8", "1,3,1"), ("fp32", None), ("ell", None), ("bf16hilo", None)])
+def test_refresh_period_extremes(P, O, path, geometry):
+    """The momentum refresh at its extremes: a fresh draw at every step
+    (L = 1) and a single draw at step 0 (L > T), on every sweep kernel;
+    ragged N and R, every replica bit-identical to the oracle."""
+    J, h = inst.sk_pm1(150, 9)
+    T = 40
+    import contextlib
+    for L in (1, T + 5):
+        with _Geometry(geometry) if geometry else contextlib.nullcontext():
+            dev, runs = run_both(P, O, J, h, 0, path, 19, T, 0.2, 1.0, 0.1, 2.0, L, 60 + L,
+                                 trace=not (geometry or "").startswith("pp"))  # no traces in the interleaved sweep
+        say("geometry", path, geometry, L, dev["info"]["sweep_kernel"], dev["info"]["group"])
+        if geometry:
+            assert dev["info"]["group"] == int(geometry.split(",")[1])
+        assert_parity(dev, runs)
+    # the persistent batch kernel, against single runs
+    if path == "i8" and geometry is None:
+        probs = [P.Problem(J, h, path="i8") for _ in range(2)]
+        scheds = [dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=2.0, refresh_L=L) for L in (1, T + 5)]
+        plan = P.Batch(probs, [19, 19], [T, T], scheds)
+        assert [p.info()["sweep_kernel"] for p in probs] == [3, 3]
+        plan.launch([71, 72])
+        plan.sync()
+        for p, sc, seed in zip(probs, scheds, (71, 72)):
+            got = p.replica_best() + p.get_state()[:2]
+            q = P.Problem(J, h, path="i8")
+            q.anneal(19, T, 0.2, 1.0, beta0=0.1, beta1=2.0, refresh_L=sc["refresh_L"], seed=seed)
+            ref = q.replica_best() + q.get_state()[:2]
+            q.close()
+            for u, w in zip(ref, got):
+                assert np.array_equal(u, w), sc
+        plan.close()
+        for p in probs:
+            p.close()
+
+
 def test_interleaved_streamed_j_full_parity(P, O):
     """Interleaved sweep with the int8 J read from global memory at every
     product (no slice per member): the ragged case bit-identical to the
