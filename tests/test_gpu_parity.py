@@ -388,16 +388,17 @@ def test_interleaved_group_sweep_full_parity(P, O):
                                            ("i8", "1,3,1"), ("fp32", None), ("ell", None), ("bf16hilo", None)])
 def test_refresh_period_extremes(P, O, path, geometry):
     """The momentum refresh at its extremes: a fresh draw at every step
-    (L = 1) and a single draw at step 0 (L > T), on every sweep kernel;
-    ragged N and R, every replica bit-identical to the oracle."""
+    (L = 1) and a single draw at step 0 (L > T), and the shortest anneals
+    (one step, whose linear schedule is beta0 alone, and two), on every sweep
+    kernel; ragged N and R, every replica bit-identical to the oracle."""
     J, h = inst.sk_pm1(150, 9)
     T = 40
     import contextlib
-    for L in (1, T + 5):
+    for TT, L in ((T, 1), (T, T + 5), (1, 25), (2, 1)):
         with _Geometry(geometry) if geometry else contextlib.nullcontext():
-            dev, runs = run_both(P, O, J, h, 0, path, 19, T, 0.2, 1.0, 0.1, 2.0, L, 60 + L,
+            dev, runs = run_both(P, O, J, h, 0, path, 19, TT, 0.2, 1.0, 0.1, 2.0, L, 60 + L + TT,
                                  trace=not (geometry or "").startswith("pp"))  # no traces in the interleaved sweep
-        say("geometry", path, geometry, L, dev["info"]["sweep_kernel"], dev["info"]["group"])
+        say("geometry", path, geometry, TT, L, dev["info"]["sweep_kernel"], dev["info"]["group"])
         if geometry:
             assert dev["info"]["group"] == int(geometry.split(",")[1])
         assert_parity(dev, runs)
