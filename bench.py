@@ -570,8 +570,8 @@ def cpu_baseline_instances(insts, R, T, sched, budget_s, what):
         # then, when the whole schedule fits, more replicas (multiples of `reps`, at most R)
         calib = 16
         t1 = run_all(calib, reps, nthr)
-        t2 = run_all(4 * calib, reps, nthr)
-        per_step = max((t2 - t1) / (3 * calib), 1e-12)
+        t2 = run_all(16 * calib, reps, nthr)
+        per_step = max((t2 - t1) / (15 * calib), 1e-12)
         fixed = max(t1 - calib * per_step, 0.0)
         steps = int(max(calib, min(T, (budget - fixed) / per_step)))
         if steps >= T:
