@@ -847,6 +847,42 @@ def test_server_valu_requests_overlap_same_alone_and_in_mix(P, O):
         assert r2["energy_units"] >= E and r2["success"] == (r2["energy_units"] <= E)
 
 
+def test_server_read_out_of_more_than_64_requests(P, O):
+    """80 requests running at once (100 slots): the round's batched argmin
+    takes them in launches of 64 and 16; every result's energy is the Eq. 2
+    energy of the state it returns, and sampled requests equal the same
+    request served alone."""
+    sched = dict(eps=0.2, gamma=1.0, beta0=0.1, beta1=3.0, refresh_L=25)
+    specs = []
+    for i in range(80):
+        J, h = inst.sk_pm1(20 + (i % 7), 500 + i)
+        specs.append((J, h, 8 + (i % 3), 600, 900 + i))
+
+    def serve(idx, slots):
+        srv = P.Server(1 << 36, max_slots=slots, chunk_steps=60)
+        probs = [P.Problem(specs[i][0], specs[i][1], path="i8") for i in idx]
+        tickets = []  # submitted together, so that the requests' ten rounds overlap
+        for i, p in zip(idx, probs):
+            J, h, R, T, seed = specs[i]
+            tickets.append(srv.submit(p, R, T, -10**9, seed=seed, **sched))  # unreachable target: full budget
+        res = [srv.wait(t, 120.0) for t in tickets]
+        spins = [srv.spins(t) for t in tickets]
+        srv.close()
+        for p in probs:
+            p.close()
+        return res, spins
+
+    res, spins = serve(range(80), 100)
+    for (J, h, R, T, seed), r, sp in zip(specs, res, spins):
+        assert r["state"] == P.REQ_DONE and r["steps_used"] == T and not r["success"]
+        assert O.energy(J.astype(np.int32), h.astype(np.int32), sp) == r["energy_units"]
+    for i in (0, 63, 64, 79):
+        (r1,), (s1,) = serve([i], 1)
+        for key in ("energy_units", "replica", "steps_used"):
+            assert r1[key] == res[i][key], (i, key)
+        assert np.array_equal(s1, spins[i]), i
+
+
 def test_server_column_split_requests_share_launches(P, O):
     """Large requests (column-split geometries) of several sizes and replica
     counts run together, several per cooperative launch; with an unreachable
